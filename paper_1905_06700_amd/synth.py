@@ -1,0 +1,206 @@
+"""Seeded synthetic single-photon lidar scenes.
+
+This module only simulates data: photon arrival times are drawn from a
+continuous impulse response and binned, background photons are uniform over
+the histogram, and every count is Poisson (the observation model of the
+paper's Results, "Observation model").  It contains none of the
+reconstruction's arithmetic and is shared by the GPU tests, the oracle tests
+and the benchmark, which all take their inputs from here.
+
+Seeds: numpy PCG64 with seed = 1905067000 + 1000 * config + scene.  Draw
+order inside a scene: geometry, then reflectivities, then photons.
+
+Scenes stand in for the paper's two datasets (a 141 x 141 x 4613 raster scan
+of a head at 40 m and 32 x 32 x 153 array video at 320 m), which are not
+available; shapes, photon levels and signal-to-background ratios follow the
+paper's descriptions.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from math import erf, sqrt
+
+import numpy as np
+
+SEED_BASE = 1905067000
+
+
+def seed_of(config: int, scene: int = 0) -> int:
+    return SEED_BASE + 1000 * config + scene
+
+
+# --------------------------------------------------------------------------
+# impulse responses (binned probabilities of a continuous arrival jitter)
+# --------------------------------------------------------------------------
+
+def _norm_cdf(x):
+    x = np.asarray(x, dtype=np.float64)
+    return 0.5 * (1.0 + np.vectorize(erf)(x / sqrt(2.0)))
+
+
+@dataclass
+class IRF:
+    """Binned impulse response: probs[k] = P(round(X) = lags[k]) for the jitter X;
+    origin = argmax index.  A surface at depth d (bins) puts its photons at
+    round(d - lags[origin] + X)."""
+    lags: np.ndarray
+    probs: np.ndarray
+    kind: str
+    sigma: float
+    tau: float = 0.0
+
+    @property
+    def origin(self) -> int:
+        return int(np.argmax(self.probs))
+
+    @property
+    def shift(self) -> int:
+        return int(self.lags[self.origin])
+
+    def draw(self, rng: np.random.Generator, n: int) -> np.ndarray:
+        x = rng.normal(0.0, self.sigma, n)
+        if self.tau > 0:
+            x = x + rng.exponential(self.tau, n)
+        return x
+
+
+def gaussian_irf(sigma: float, half: int) -> IRF:
+    lags = np.arange(-half, half + 1)
+    probs = _norm_cdf((lags + 0.5) / sigma) - _norm_cdf((lags - 0.5) / sigma)
+    return IRF(lags, probs, "gaussian", sigma)
+
+
+def exgauss_irf(sigma: float, tau: float, lo: int, hi: int) -> IRF:
+    """Gaussian(0, sigma) convolved with an exponential tail of mean tau."""
+    lags = np.arange(lo, hi + 1)
+
+    def cdf(x):
+        x = np.asarray(x, dtype=np.float64)
+        lam = 1.0 / tau
+        return _norm_cdf(x / sigma) - np.exp(-lam * x + 0.5 * (lam * sigma) ** 2) * \
+            _norm_cdf(x / sigma - lam * sigma)
+
+    probs = cdf(lags + 0.5) - cdf(lags - 0.5)
+    return IRF(lags, np.maximum(probs, 0.0), "exgauss", sigma, tau)
+
+
+# --------------------------------------------------------------------------
+# scenes
+# --------------------------------------------------------------------------
+
+@dataclass
+class Scene:
+    Z: np.ndarray            # uint16 [rows, cols, T]
+    irf: IRF
+    T: int
+    depth: np.ndarray        # float64 [S, rows, cols], true depth in bins (nan = absent)
+    intensity: np.ndarray    # float64 [S, rows, cols], expected signal photons
+    background: float        # expected background photons per bin
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def rows(self):
+        return self.Z.shape[0]
+
+    @property
+    def cols(self):
+        return self.Z.shape[1]
+
+
+def render(rng, irf: IRF, T: int, depth, intensity, b: float, gain=None) -> np.ndarray:
+    """Poisson photon counts for surfaces (depth, intensity) [S, rows, cols] on a
+    uniform background b per bin.  Photons outside [0, T) are lost."""
+    S, rows, cols = depth.shape
+    npix = rows * cols
+    g = np.ones(npix) if gain is None else np.asarray(gain, dtype=np.float64).reshape(-1)
+    pix_all, bin_all = [], []
+    for s in range(S):
+        d = depth[s].reshape(-1)
+        lam = np.where(np.isfinite(d), intensity[s].reshape(-1), 0.0) * g
+        n = rng.poisson(lam)
+        pix = np.repeat(np.arange(npix), n)
+        x = irf.draw(rng, pix.size)
+        tb = np.floor(d[pix] - irf.shift + x + 0.5).astype(np.int64)
+        keep = (tb >= 0) & (tb < T)
+        pix_all.append(pix[keep])
+        bin_all.append(tb[keep])
+    nb = rng.poisson(b * T * g)
+    pix = np.repeat(np.arange(npix), nb)
+    pix_all.append(pix)
+    bin_all.append(rng.integers(0, T, pix.size))
+    pix = np.concatenate(pix_all)
+    tb = np.concatenate(bin_all)
+    counts = np.bincount(pix * T + tb, minlength=npix * T)
+    assert counts.max(initial=0) < 65535, "count overflow for uint16 histograms"
+    return counts.astype(np.uint16).reshape(rows, cols, T)
+
+
+def _blur_circular(field_, sigma):
+    rows, cols = field_.shape
+    fy = np.fft.fftfreq(rows)[:, None]
+    fx = np.fft.fftfreq(cols)[None, :]
+    H = np.exp(-2.0 * (np.pi * sigma) ** 2 * (fx ** 2 + fy ** 2))
+    return np.real(np.fft.ifft2(np.fft.fft2(field_) * H))
+
+
+def plane_scene(scene: int = 0, rows: int = 32, cols: int = 32, T: int = 300,
+                signal: float = 10.0, bkg_photons: float = 1.0, theta=None) -> Scene:
+    """Config 1: one tilted plane with depths spanning bins 50..250, Gaussian
+    IRF sigma 1.5 bins, mean `signal` photons/pixel, reflectivity U[0.5, 1],
+    `bkg_photons` background photons per pixel."""
+    rng = np.random.default_rng(seed_of(1, scene))
+    irf = gaussian_irf(1.5, 9)
+    th = rng.uniform(0.0, np.pi / 2) if theta is None else float(theta)
+    i, j = np.mgrid[0:rows, 0:cols].astype(np.float64)
+    u = j * np.cos(th) + i * np.sin(th)
+    span = u.max() - u.min()
+    d = 50.0 + 200.0 * (u - u.min()) / (span if span > 0 else 1.0)
+    rho = rng.uniform(0.5, 1.0, (rows, cols))
+    r = rho * signal / 0.75
+    b = bkg_photons / T
+    Z = render(rng, irf, T, d[None], r[None], b)
+    return Scene(Z, irf, T, d[None], r[None], b,
+                 dict(config=1, dz=0.1, p_xy=1.0, mean_signal=signal, r_min=0.2 * signal,
+                      r_init=0, k_init=3))
+
+
+def head_scene(scene: int = 0, rows: int = 141, cols: int = 141, T: int = 4613,
+               signal: float = 5.0, sbr: float = 0.1) -> Scene:
+    """Config 2 (the paper's raster-scan shape, 141 x 141 x 4613): a smooth bumpy
+    back surface and a foreground occluder 200 bins nearer over 30% of the
+    pixels (a thresholded smooth random field), ex-Gaussian IRF (sigma 3 bins,
+    exponential tail 10 bins), mean `signal` photons/pixel at the given SBR."""
+    rng = np.random.default_rng(seed_of(2, scene))
+    irf = exgauss_irf(3.0, 10.0, -18, 118)
+    i, j = np.mgrid[0:rows, 0:cols].astype(np.float64)
+    ci = (rows - 1) / 2.0
+    d_bg = (T / 2.0 - 6.5) + 100.0 * np.sin(2 * np.pi * i / 47) * np.sin(2 * np.pi * j / 47) \
+        + 2.0 * (i - ci)
+    noise = rng.normal(0.0, 1.0, (rows, cols))
+    sm = _blur_circular(noise, 6.0)
+    n_occ = int(round(0.3 * rows * cols))
+    order = np.argsort(sm.reshape(-1), kind="stable")[::-1]
+    M = np.zeros(rows * cols)
+    M[order[:n_occ]] = 1.0
+    M = M.reshape(rows, cols)
+    d_fg = d_bg - 200.0
+    rho_bg = rng.uniform(0.5, 1.0, (rows, cols))
+    rho_fg = rng.uniform(0.5, 1.0, (rows, cols))
+    a = signal / 0.75
+    r_bg = a * rho_bg * (1.0 - 0.5 * M)
+    r_fg = a * rho_fg * 0.5 * M
+    depth = np.stack([np.where(M > 0, d_fg, np.nan), d_bg])
+    inten = np.stack([np.where(M > 0, r_fg, 0.0), r_bg])
+    b = signal / sbr / T
+    Z = render(rng, irf, T, depth, inten, b)
+    return Scene(Z, irf, T, depth, inten, b,
+                 dict(config=2, dz=0.05, p_xy=1.0, mean_signal=signal, r_min=0.2 * signal,
+                      r_init=0, k_init=3, occluder=M))
+
+
+def random_gain(rng_seed: int, rows: int, cols: int, dead_frac: float = 0.02) -> np.ndarray:
+    """Per-pixel detector gain in [0.5, 1.5] with a fraction of dead (0) pixels."""
+    rng = np.random.default_rng(rng_seed)
+    g = rng.uniform(0.5, 1.5, (rows, cols))
+    g[rng.random((rows, cols)) < dead_frac] = 0.0
+    return g
