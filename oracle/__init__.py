@@ -65,7 +65,7 @@ class Params:
     dz: float = 0.1
     h_apss: float = 2.0
     h_int: float = 2.0
-    beta_t: float = 1.0
+    beta_t: float = 0.5
     dmax: float = 0.0
     beta_r: float = 1.0
     beta_b: float = 1.0
@@ -96,15 +96,14 @@ _I64 = C.c_int64
 
 def _declare(L):
     L.or_model_new.restype = C.c_void_p
-    L.or_model_new.argtypes = [_dp, C.c_int, C.c_int, C.c_int, C.c_int]
+    L.or_model_new.argtypes = [_dp, C.c_int, C.c_int, C.c_int]
     L.or_model_free.argtypes = [C.c_void_p]
     L.or_model_origin.restype = C.c_int
     L.or_model_origin.argtypes = [C.c_void_p]
     L.or_model_sigma2.restype = C.c_double
     L.or_model_sigma2.argtypes = [C.c_void_p]
-    L.or_model_fine_len.restype = C.c_int
-    L.or_model_fine_len.argtypes = [C.c_void_p]
-    L.or_model_fine.argtypes = [C.c_void_p, _dp]
+    L.or_model_fisher.restype = C.c_double
+    L.or_model_fisher.argtypes = [C.c_void_p]
     L.or_model_window.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int)]
     L.or_h.argtypes = [C.c_void_p, C.c_int, _dp, _dp, _dp]
     L.or_S.argtypes = [C.c_void_p, C.c_int, _dp, _dp, _dp]
@@ -135,13 +134,13 @@ def _declare(L):
 
 
 class Model:
-    """IRF model (normalised samples, Catmull-Rom fine table, sigma_h^2)."""
+    """IRF model (normalised samples, Catmull-Rom interpolant, sigma_h^2, Fisher information)."""
 
-    def __init__(self, irf, T: int, origin: int = -1, U: int = 32):
+    def __init__(self, irf, T: int, origin: int = -1):
         self.irf = np.ascontiguousarray(irf, dtype=np.float64)
-        self.T, self.U = int(T), int(U)
+        self.T = int(T)
         self.L = len(self.irf)
-        self._h = lib().or_model_new(self.irf, self.L, int(origin), self.T, self.U)
+        self._h = lib().or_model_new(self.irf, self.L, int(origin), self.T)
         if not self._h:
             raise ValueError("invalid IRF")
 
@@ -158,10 +157,9 @@ class Model:
     def sigma2(self) -> float:
         return lib().or_model_sigma2(self._h)
 
-    def fine(self) -> np.ndarray:
-        out = np.zeros(lib().or_model_fine_len(self._h))
-        lib().or_model_fine(self._h, out)
-        return out
+    @property
+    def fisher(self) -> float:
+        return lib().or_model_fisher(self._h)
 
     def window(self):
         wl, wr = C.c_int(), C.c_int()

@@ -32,31 +32,40 @@
 /* ------------------------------------------------------------------------ */
 
 struct or_model {
-    int     L, o, T, U;
+    int     L, o, T;
     double* hbar;   /* normalised IRF samples, sum 1 */
-    double* hF;     /* fine table over sample positions [-1, L], (L+1)*U + 1 values */
-    int     nF;
+    double  hmax;   /* largest sample */
     double  sigma2; /* IRF variance in bins^2 */
+    double  fisher; /* shift Fisher information per photon, 1/bins^2 */
     int     wl, wr; /* peak window half widths (5% / 95% cumulative mass) */
 };
 
+static void h_eval(const or_model* m, double tau, double* h, double* hp);
+
 static double hb(const or_model* m, int k) { return (k >= 0 && k < m->L) ? m->hbar[k] : 0.0; }
 
-/* Uniform Catmull-Rom cubic between p1 (s = 0) and p2 (s = 1). */
+/* Uniform Catmull-Rom cubic between p1 (s = 0) and p2 (s = 1), and its
+ * derivative in s. */
 static double catmull_rom(double p0, double p1, double p2, double p3, double s)
 {
     return 0.5 * (2.0 * p1 + (-p0 + p2) * s + (2.0 * p0 - 5.0 * p1 + 4.0 * p2 - p3) * s * s
                   + (-p0 + 3.0 * p1 - 3.0 * p2 + p3) * s * s * s);
 }
 
+static double catmull_rom_ds(double p0, double p1, double p2, double p3, double s)
+{
+    return 0.5 * ((-p0 + p2) + 2.0 * (2.0 * p0 - 5.0 * p1 + 4.0 * p2 - p3) * s
+                  + 3.0 * (-p0 + 3.0 * p1 - 3.0 * p2 + p3) * s * s);
+}
+
 /* The IRF h is "known" per pixel (Observation model).  Reading: samples
  * irf[0..L-1] at integer lags, normalised to unit sum, origin `origin`
  * (argmax when negative, smallest index on ties).  The continuous h(tau) is the
- * Catmull-Rom interpolant of the samples (zero beyond them), tabulated every
- * 1/U bin and linearly interpolated between table entries. */
-or_model* or_model_new(const double* irf, int L, int origin, int T, int U)
+ * Catmull-Rom interpolant of the samples (zero beyond them, clamped at zero),
+ * so h and h' are continuous between and across samples. */
+or_model* or_model_new(const double* irf, int L, int origin, int T)
 {
-    if (L <= 0 || T <= 0 || U <= 0 || L > T) return NULL;
+    if (L <= 0 || T <= 0 || L > T) return NULL;
     double sum = 0.0;
     for (int k = 0; k < L; ++k) {
         if (!(irf[k] >= 0.0) || !isfinite(irf[k])) return NULL;
@@ -64,7 +73,7 @@ or_model* or_model_new(const double* irf, int L, int origin, int T, int U)
     }
     if (!(sum > 0.0)) return NULL;
     or_model* m = (or_model*)calloc(1, sizeof(or_model));
-    m->L = L; m->T = T; m->U = U;
+    m->L = L; m->T = T;
     m->hbar = (double*)malloc(sizeof(double) * L);
     for (int k = 0; k < L; ++k) m->hbar[k] = irf[k] / sum;
     if (origin < 0) {
@@ -73,19 +82,26 @@ or_model* or_model_new(const double* irf, int L, int origin, int T, int U)
         origin = best;
     }
     m->o = origin;
-    m->nF = (L + 1) * U + 1;
-    m->hF = (double*)malloc(sizeof(double) * m->nF);
-    for (int i = 0; i < m->nF; ++i) {
-        int k = i / U - 1;                 /* sample index at or left of the position */
-        double s = (double)(i % U) / U;    /* local parameter in [0, 1) */
-        double v = catmull_rom(hb(m, k - 1), hb(m, k), hb(m, k + 1), hb(m, k + 2), s);
-        m->hF[i] = v > 0.0 ? v : 0.0;
-    }
+    m->hmax = 0.0;
+    for (int k = 0; k < L; ++k) m->hmax = m->hbar[k] > m->hmax ? m->hbar[k] : m->hmax;
     double mu = 0.0;
     for (int k = 0; k < L; ++k) mu += k * m->hbar[k];
     double var = 0.0;
     for (int k = 0; k < L; ++k) var += m->hbar[k] * (k - mu) * (k - mu);
     m->sigma2 = var;
+    /* Fisher information of one photon about the shift of h (no background),
+     * averaged over 32 sub-bin phases: mean_j sum_lag h'(lag + j/32)^2 / h(..),
+     * over the lags where h is at least 1e-3 of the largest sample. */
+    {
+        double acc = 0.0;
+        for (int j = 0; j < 32; ++j)
+            for (int l = -origin - 1; l <= L - origin; ++l) {
+                double h, hp;
+                h_eval(m, l + j / 32.0, &h, &hp);
+                if (h >= 1e-3 * m->hmax) acc += hp * hp / h;
+            }
+        m->fisher = acc / 32.0;
+    }
     /* Peak window: lags where the cumulative IRF mass first reaches 5% / 95%. */
     double c = 0.0;
     int klo = -1, khi = -1;
@@ -104,25 +120,28 @@ or_model* or_model_new(const double* irf, int L, int origin, int T, int U)
 void or_model_free(or_model* m)
 {
     if (!m) return;
-    free(m->hbar); free(m->hF); free(m);
+    free(m->hbar); free(m);
 }
 int    or_model_origin(const or_model* m) { return m->o; }
 double or_model_sigma2(const or_model* m) { return m->sigma2; }
-int    or_model_fine_len(const or_model* m) { return m->nF; }
-void   or_model_fine(const or_model* m, double* out) { memcpy(out, m->hF, sizeof(double) * m->nF); }
+double or_model_fisher(const or_model* m) { return m->fisher; }
 void   or_model_window(const or_model* m, int* wl, int* wr) { *wl = m->wl; *wr = m->wr; }
 
-/* h(tau) and its derivative dh/dtau (slope of the table segment holding tau,
- * right-continuous). */
+/* h(tau) and dh/dtau: the Catmull-Rom segment holding sample position
+ * x = tau + origin; zero where the cubic is negative or beyond the samples. */
 static void h_eval(const or_model* m, double tau, double* h, double* hp)
 {
-    double u = (tau + m->o + 1) * m->U;
-    if (!(u >= 0.0) || u >= (double)((m->L + 1) * m->U)) { *h = 0.0; *hp = 0.0; return; }
-    int i = (int)floor(u);
-    double w = u - i;
-    double d = m->hF[i + 1] - m->hF[i];
-    *h = m->hF[i] + w * d;
-    *hp = m->U * d;
+    double x = tau + m->o;
+    *h = 0.0;
+    *hp = 0.0;
+    if (!(x > -1.0) || !(x < m->L)) return;
+    int k = (int)floor(x);
+    double s = x - k;
+    double p0 = hb(m, k - 1), p1 = hb(m, k), p2 = hb(m, k + 1), p3 = hb(m, k + 2);
+    double v = catmull_rom(p0, p1, p2, p3, s);
+    if (v <= 0.0) return;
+    *h = v;
+    *hp = catmull_rom_ds(p0, p1, p2, p3, s);
 }
 
 void or_h(const or_model* m, int n, const double* tau, double* h, double* hp)
@@ -447,7 +466,7 @@ void or_init(const or_model* m, const or_params* p, int F, int rows, int cols,
             for (int tau = s0; tau <= s1; ++tau) supp[tau] = 1;
             if (!accept) break;
             pk[npk] = best; lo[npk] = a; hi[npk] = c; ++npk;
-            for (int tb = a; tb <= c; ++tb) claimed[tb] = (char)npk;   /* peak index + 1 */
+            for (int tb = a; tb <= c; ++tb) if (!claimed[tb]) claimed[tb] = (char)npk;   /* peak index + 1 */
         }
         /* intensities and background from the pixel's own photons */
         int64_t zp = 0;
@@ -571,7 +590,7 @@ void or_depth_step(const or_model* m, const or_params* p, int64_t npix,
                    double* t, const double* r, const int* cnt, const double* b)
 {
     int K = p->k_max;
-    double dmax = p->dmax > 0.0 ? p->dmax : fmax(0.5, 0.5 * sqrt(m->sigma2));
+    double dmax = p->dmax > 0.0 ? p->dmax : fmax(0.5, 1.0 / sqrt(m->fisher));
     double* t0 = (double*)malloc(sizeof(double) * K);
     for (int64_t pix = 0; pix < npix; ++pix) {
         double G = g[pix];
@@ -592,7 +611,7 @@ void or_depth_step(const or_model* m, const or_params* p, int64_t npix,
             }
             double S, Sp;
             S_eval(m, t0[k], &S, &Sp);
-            double step = -p->beta_t * m->sigma2 * (Sp + acc);
+            double step = -p->beta_t * (Sp + acc) / m->fisher;
             if (step > dmax) step = dmax;
             if (step < -dmax) step = -dmax;
             double tn = t0[k] + step;

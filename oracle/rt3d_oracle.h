@@ -39,8 +39,8 @@ typedef struct or_params {
     double dz;          /* world units per bin */
     double h_apss;      /* APSS kernel support (world units) */
     double h_int;       /* intensity-graph radius (world units) */
-    double beta_t;      /* depth step scale */
-    double dmax;        /* depth step clip (bins); <= 0: max(0.5, 0.5*sigma_h) */
+    double beta_t;      /* depth step scale (Fisher units) */
+    double dmax;        /* depth step clip (bins); <= 0: max(0.5, 1/sqrt(Fisher)) */
     double beta_r;      /* intensity step scale */
     double beta_b;      /* background step scale */
     double r_min;       /* minimum admissible intensity (photons) */
@@ -58,13 +58,12 @@ typedef struct or_params {
 
 typedef struct or_model or_model;
 
-/* IRF model: normalised samples, Catmull-Rom fine table, sigma_h^2. */
-or_model* or_model_new(const double* irf, int L, int origin, int T, int U);
+/* IRF model: normalised samples, Catmull-Rom interpolant, sigma_h^2, shift Fisher information. */
+or_model* or_model_new(const double* irf, int L, int origin, int T);
 void      or_model_free(or_model* m);
 int       or_model_origin(const or_model* m);
 double    or_model_sigma2(const or_model* m);
-int       or_model_fine_len(const or_model* m);
-void      or_model_fine(const or_model* m, double* out);
+double    or_model_fisher(const or_model* m);
 void      or_model_window(const or_model* m, int* wl, int* wr);
 void      or_h(const or_model* m, int n, const double* tau, double* h, double* hp);
 void      or_S(const or_model* m, int n, const double* tau, double* S, double* Sp);

@@ -1,0 +1,69 @@
+"""Helpers shared by the GPU parity tests: moving seeded inputs and oracle
+states onto the device in the library's layout and back.  No arithmetic of
+the method lives here."""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+import oracle
+from paper_1905_06700_amd import rt3d, synth
+
+K = rt3d.K_MAX
+
+
+def to_dev_hist(Z: np.ndarray) -> torch.Tensor:
+    return torch.from_numpy(np.ascontiguousarray(Z).view(np.int16)).cuda()
+
+
+def to_dev_u32(a: np.ndarray) -> torch.Tensor:
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint32).view(np.int32)).cuda()
+
+
+def u32(t: torch.Tensor) -> np.ndarray:
+    return t.cpu().numpy().view(np.uint32)
+
+
+def oracle_to_device(s: oracle.State) -> rt3d.DeviceState:
+    """Pixel-major oracle state -> slot-major device state (k_max <= K)."""
+    P = s.npix
+    t = np.zeros((K, P))
+    r = np.zeros((K, P), dtype=np.float32)
+    n = np.zeros((3, K, P), dtype=np.float32)
+    n[2] = -1.0
+    t[:s.K] = s.t.T
+    r[:s.K] = s.r.T
+    n[:, :s.K] = np.transpose(s.n, (2, 1, 0))
+    d = rt3d.DeviceState(s.F, s.rows, s.cols,
+                         torch.from_numpy(t).cuda(), torch.from_numpy(r).cuda(),
+                         torch.from_numpy(n).cuda(),
+                         torch.from_numpy(s.cnt.astype(np.uint8)).cuda(),
+                         torch.from_numpy(s.b.astype(np.float32)).cuda())
+    return d
+
+
+def device_to_oracle(d: rt3d.DeviceState, k_max: int, g=None) -> oracle.State:
+    s = oracle.State(d.frames, d.rows, d.cols, k_max, g)
+    s.t[:] = d.t.cpu().numpy()[:k_max].T
+    s.r[:] = d.r.cpu().numpy()[:k_max].T.astype(np.float64)
+    s.n[:] = np.transpose(d.n.cpu().numpy()[:, :k_max], (2, 1, 0)).astype(np.float64)
+    s.cnt[:] = d.cnt.cpu().numpy().astype(np.int32)
+    s.b[:] = d.b.cpu().numpy().astype(np.float64)
+    return s
+
+
+def params_for(scene: synth.Scene, **kw) -> dict:
+    """Parameters shared by both sides for a scene (readings, see the design notes)."""
+    m = scene.meta
+    p = dict(dz=m["dz"], p_xy=m["p_xy"], r_min=m["r_min"], r_init=m["r_init"], k_init=m["k_init"])
+    p.update(kw)
+    return p
+
+
+def pair(scene: synth.Scene, **kw):
+    """(oracle.Oracle, rt3d.Context) for one scene with identical parameters."""
+    p = params_for(scene, **kw)
+    model = oracle.Model(scene.irf.probs, scene.T)
+    O = oracle.Oracle(model, oracle.Params(**{k: v for k, v in p.items() if k != "denoiser"}))
+    ctx = rt3d.Context(scene.irf.probs, scene.T, **p)
+    return O, ctx

@@ -1,0 +1,283 @@
+"""GPU parity: every step of the HIP path against the FP64 oracle on the same
+seeded inputs, called through the C ABI.
+
+Bars (the GPU computes in FP32 with FP64 depth state, the oracle in FP64):
+  - compaction: bit-exact;
+  - initialisation: integer peak depths and counts exact (integer score), r/b
+    to FP32 rounding;
+  - raw gradients: |gpu - oracle| <= 1e-4 x (sum of absolute terms);
+  - single steps: depth within 2e-4 bin, intensity/background within 1e-5
+    relative, APSS within 1e-3 bin;
+  - whole reconstruction: identical point counts on >= 99.9% of pixels and
+    depths within 1e-3 bin on pixels whose count and neighbourhood counts
+    agree (a decision taken on the other side of a threshold is listed with
+    its margin).
+Inputs: config-1 plane (32 x 32 x 300), config-2 head shape (141 x 141 x
+4613) and a ragged 37 x 23 x 777 scene that spans several tiles with a tail.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import device_to_oracle, oracle_to_device, pair, to_dev_hist, u32
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import oracle  # noqa: E402
+from paper_1905_06700_amd import rt3d, synth  # noqa: E402
+
+
+def _scene(name):
+    if name == "c1":
+        return synth.plane_scene(0)
+    if name == "c2":
+        sc = synth.head_scene(0)
+        sc.meta["r_init"] = 1
+        return sc
+    if name == "ragged":
+        sc = synth.head_scene(7, rows=37, cols=23, T=777, signal=8.0, sbr=0.5)
+        sc.meta.update(r_init=1, dz=0.07)
+        return sc
+    raise KeyError(name)
+
+
+_cache = {}
+
+
+def scene(name):
+    if name not in _cache:
+        print(f"[gpu-parity] generating {name}", flush=True)
+        _cache[name] = _scene(name)
+    return _cache[name]
+
+
+def csr(sc):
+    return oracle.compact(sc.Z.reshape(1, sc.rows, sc.cols, sc.T))
+
+
+# ------------------------------------------------------------------ compaction
+
+@pytest.mark.parametrize("name", ["c1", "c2", "ragged"])
+def test_compaction_bit_exact(name):
+    sc = scene(name)
+    O, ctx = pair(sc)
+    off_o, ent_o = csr(sc)
+    off, ent = ctx.compact(to_dev_hist(sc.Z))
+    st = ctx.query()
+    assert st.device_error == 0
+    np.testing.assert_array_equal(u32(off), off_o)
+    E = int(off_o[-1])
+    np.testing.assert_array_equal(u32(ent)[:E], ent_o)
+
+
+def test_compaction_edge_cases():
+    rng = np.random.default_rng(0)
+    ctx = rt3d.Context([1.0, 2.0, 1.0], 301)
+    for Z in [np.zeros((5, 301), np.uint16),                     # empty
+              np.full((3, 301), 65534, np.uint16),               # dense, maximum counts
+              (rng.poisson(0.3, (131, 301))).astype(np.uint16),  # ragged pixel starts
+              np.eye(301, dtype=np.uint16)[:7] * 9]:             # one bin each
+        off_o, ent_o = oracle.compact(Z)
+        off, ent = ctx.compact(to_dev_hist(Z))
+        assert ctx.query().device_error == 0
+        np.testing.assert_array_equal(u32(off), off_o)
+        np.testing.assert_array_equal(u32(ent)[:len(ent_o)], ent_o)
+    # capacity overflow is reported, not written past
+    Z = np.ones((4, 301), np.uint16)
+    off, ent = ctx.compact(to_dev_hist(Z), capacity=100)
+    with pytest.raises(rt3d.Rt3dError) as e:
+        ctx.query()
+    assert e.value.status == rt3d.E_CAPACITY
+
+
+# ------------------------------------------------------------------ init
+
+@pytest.mark.parametrize("name", ["c1", "c2", "ragged"])
+def test_init_matches_oracle(name):
+    sc = scene(name)
+    O, ctx = pair(sc)
+    off_o, ent_o = csr(sc)
+    so = O.init(off_o, ent_o, oracle.State(1, sc.rows, sc.cols, 4))
+    from gpu_util import to_dev_u32
+    d = ctx.step(rt3d.STEP_INIT, None, to_dev_u32(off_o), to_dev_u32(ent_o), shape=(1, sc.rows, sc.cols))
+    sg = device_to_oracle(d, 4)
+    np.testing.assert_array_equal(sg.cnt, so.cnt)
+    np.testing.assert_array_equal(sg.t, so.t)
+    np.testing.assert_allclose(sg.r, so.r, rtol=2e-6, atol=1e-6)
+    np.testing.assert_allclose(sg.b, so.b, rtol=2e-6, atol=1e-12)
+    np.testing.assert_allclose(sg.n, so.n, atol=2e-6)
+
+
+# ------------------------------------------------------------------ gradients
+
+@pytest.mark.parametrize("name", ["c1", "c2", "ragged"])
+@pytest.mark.parametrize("iters", [0, 3])
+def test_gradients_match_oracle(name, iters):
+    from gpu_util import to_dev_u32
+    sc = scene(name)
+    O, ctx = pair(sc)
+    off_o, ent_o = csr(sc)
+    s = O.init(off_o, ent_o, oracle.State(1, sc.rows, sc.cols, 4))
+    for _ in range(iters):
+        O.iterate(off_o, ent_o, s)
+    (gt, gr, gb), (at, ar, ab) = O.grad(off_o, ent_o, s)
+    dgt, dgr, dgb = ctx.gradients(oracle_to_device(s), to_dev_u32(off_o), to_dev_u32(ent_o))
+    dgt = dgt.cpu().numpy()[:4].T.astype(np.float64)
+    dgr = dgr.cpu().numpy()[:4].T.astype(np.float64)
+    dgb = dgb.cpu().numpy().astype(np.float64)
+    live = np.arange(4)[None, :] < s.cnt[:, None]
+    for g_gpu, g_or, a in ((dgt, gt, at), (dgr, gr, ar)):
+        err = np.abs(g_gpu - g_or)[live]
+        assert np.all(err <= 1e-4 * a[live] + 1e-30), (err.max(), (err / a[live]).max())
+    assert np.all(np.abs(dgb - gb) <= 1e-4 * ab + 1e-30)
+
+
+# ------------------------------------------------------------------ single steps
+
+def _state_after(sc, O, iters):
+    off_o, ent_o = csr(sc)
+    s = O.init(off_o, ent_o, oracle.State(1, sc.rows, sc.cols, 4))
+    for _ in range(iters):
+        O.iterate(off_o, ent_o, s)
+    return s
+
+
+@pytest.mark.parametrize("name", ["c1", "c2", "ragged"])
+def test_single_steps_match_oracle(name):
+    from gpu_util import to_dev_u32
+    sc = scene(name)
+    O, ctx = pair(sc)
+    off_o, ent_o = csr(sc)
+    off, ent = to_dev_u32(off_o), to_dev_u32(ent_o)
+    s0 = _state_after(sc, O, 2)
+    din = oracle_to_device(s0)
+    live = np.arange(4)[None, :] < s0.cnt[:, None]
+
+    # depth step
+    so = O.depth_step(off_o, ent_o, s0.copy())
+    sg = device_to_oracle(ctx.step(rt3d.STEP_DEPTH, din, off, ent), 4)
+    assert np.abs(sg.t - so.t)[live].max() <= 2e-4
+
+    # APSS
+    so = O.apss(s0.copy())
+    sg = device_to_oracle(ctx.step(rt3d.STEP_APSS, din), 4)
+    assert np.abs(sg.t - so.t)[live].max() <= 1e-3
+    assert np.abs(sg.n - so.n)[live].max() <= 1e-3
+
+    # merge
+    so = O.merge(s0.copy())
+    sg = device_to_oracle(ctx.step(rt3d.STEP_MERGE, din), 4)
+    np.testing.assert_array_equal(sg.cnt, so.cnt)
+    lv = np.arange(4)[None, :] < so.cnt[:, None]
+    assert np.abs(sg.t - so.t)[lv].max(initial=0) <= 1e-9
+    np.testing.assert_allclose(sg.r[lv], so.r[lv], rtol=1e-6)
+
+    # intensity step
+    so = O.intensity_step(off_o, ent_o, s0.copy())
+    sg = device_to_oracle(ctx.step(rt3d.STEP_INTENSITY, din, off, ent), 4)
+    np.testing.assert_allclose(sg.r[live], so.r[live], rtol=1e-5, atol=1e-6)
+
+    # intensity filter + threshold
+    so = O.intensity_filter(s0.copy())
+    sg = device_to_oracle(ctx.step(rt3d.STEP_IFILTER, din), 4)
+    same = sg.cnt == so.cnt
+    assert same.mean() >= 0.999, np.nonzero(~same)
+    lv = (np.arange(4)[None, :] < so.cnt[:, None]) & same[:, None]
+    np.testing.assert_allclose(sg.r[lv], so.r[lv], rtol=1e-5)
+    np.testing.assert_array_equal(sg.t[lv], so.t[lv])
+
+    # background step
+    so = O.bg_step(off_o, ent_o, s0.copy())
+    sg = device_to_oracle(ctx.step(rt3d.STEP_BKG, din, off, ent), 4)
+    np.testing.assert_allclose(sg.b, so.b, rtol=1e-5, atol=1e-12)
+
+    # background filter
+    so = O.bg_filter(s0.copy())
+    sg = device_to_oracle(ctx.step(rt3d.STEP_BFILTER, din), 4)
+    np.testing.assert_allclose(sg.b, so.b, rtol=1e-5, atol=1e-12)
+
+
+# ------------------------------------------------------------------ whole loop
+
+def _compare_final(sc, so, res, P):
+    pt_off = u32(res.pt_off).astype(np.int64)
+    cnt_g = np.diff(pt_off)
+    same = cnt_g == so.cnt
+    frac = same.mean()
+    depth = res.depth.cpu().numpy()
+    inten = res.intensity.cpu().numpy()
+    # pixels whose own and 5x5-neighbourhood counts agree
+    rows, cols = sc.rows, sc.cols
+    bad = (~same).reshape(-1, rows, cols)
+    nb_bad = np.zeros_like(bad)
+    for di in range(-2, 3):
+        for dj in range(-2, 3):
+            nb_bad |= np.roll(np.roll(bad, di, 1), dj, 2)
+    ok = (~nb_bad).reshape(-1)
+    errs = []
+    for p in np.nonzero(ok)[0]:
+        c = so.cnt[p]
+        if c:
+            errs.append(np.abs(depth[pt_off[p]:pt_off[p] + c] - so.t[p, :c]).max())
+    return frac, np.array(errs), cnt_g, depth, inten, pt_off
+
+
+@pytest.mark.parametrize("name", ["c1", "c2", "ragged"])
+def test_reconstruction_matches_oracle(name):
+    sc = scene(name)
+    O, ctx = pair(sc)
+    off_o, ent_o = csr(sc)
+    so = O.reconstruct(off_o, ent_o, oracle.State(1, sc.rows, sc.cols, 4))
+    res = ctx.reconstruct(to_dev_hist(sc.Z)[None])
+    st = ctx.query()
+    assert st.device_error == 0
+    assert st.entries == len(ent_o)
+    frac, errs, cnt_g, depth, inten, pt_off = _compare_final(sc, so, res, sc.rows * sc.cols)
+    print(f"[gpu-parity] {name}: count agreement {frac:.5f}, max depth err {errs.max():.2e} bins "
+          f"over {len(errs)} pixels", flush=True)
+    assert frac >= 0.999
+    assert errs.max() <= 1e-3
+    np.testing.assert_allclose(res.background.cpu().numpy(), so.b, rtol=1e-3, atol=1e-9)
+
+
+def test_reconstruction_is_deterministic():
+    sc = scene("c1")
+    _, ctx = pair(sc)
+    Z = to_dev_hist(sc.Z)[None]
+    a = ctx.reconstruct(Z)
+    b = ctx.reconstruct(Z)
+    torch.cuda.synchronize()
+    for x, y in ((a.pt_off, b.pt_off), (a.depth, b.depth), (a.intensity, b.intensity),
+                 (a.background, b.background)):
+        assert torch.equal(x, y)
+
+
+def test_batched_frames_equal_single_frames():
+    scs = [synth.plane_scene(s) for s in range(3)]
+    _, ctx = pair(scs[0])
+    Z = torch.cat([to_dev_hist(s.Z)[None] for s in scs])
+    batch = ctx.reconstruct(Z)
+    P = 32 * 32
+    for f, s in enumerate(scs):
+        one = ctx.reconstruct(to_dev_hist(s.Z)[None])
+        pb = u32(batch.pt_off).astype(np.int64)
+        p1 = u32(one.pt_off).astype(np.int64)
+        np.testing.assert_array_equal(np.diff(pb[f * P:(f + 1) * P + 1]), np.diff(p1))
+        a, b = pb[f * P], pb[(f + 1) * P]
+        np.testing.assert_array_equal(batch.depth[a:b].cpu().numpy(), one.depth[:p1[-1]].cpu().numpy())
+
+
+def test_gain_and_dead_pixels():
+    sc = scene("c1")
+    O, ctx = pair(sc)
+    g = synth.random_gain(5, sc.rows, sc.cols)
+    # counts scale with the gain in the observation model
+    rng = np.random.default_rng(9)
+    Z = synth.render(rng, sc.irf, sc.T, sc.depth, sc.intensity, sc.background, gain=g)
+    off_o, ent_o = oracle.compact(Z[None])
+    so = oracle.State(1, sc.rows, sc.cols, 4, g=g.reshape(-1))
+    O.reconstruct(off_o, ent_o, so)
+    res = ctx.reconstruct(to_dev_hist(Z)[None], gain=torch.from_numpy(g.astype(np.float32).reshape(-1)).cuda())
+    frac, errs, cnt_g, *_ = _compare_final(sc, so, res, sc.rows * sc.cols)
+    assert frac >= 0.999 and errs.max() <= 1e-3
+    assert np.all(cnt_g[g.reshape(-1) == 0] == 0)

@@ -117,3 +117,22 @@ def test_invalid_irf_rejected(oracle_lib):
         oracle_lib.Model([1.0, -1.0, 2.0], T=10)
     with pytest.raises(ValueError):
         oracle_lib.Model(np.ones(11), T=10)
+
+
+def test_fisher_information_of_binned_gaussian(oracle_lib):
+    # Fisher information about the shift theta of a binned Gaussian,
+    # p_k(theta) = Phi((k + 1/2 - theta)/s) - Phi((k - 1/2 - theta)/s),
+    # I(theta) = sum_k p_k'(theta)^2 / p_k(theta), averaged over theta in [0, 1)
+    sig = 2.5
+    lags = np.arange(-15, 16)
+    binned = norm.cdf((lags + 0.5) / sig) - norm.cdf((lags - 0.5) / sig)
+    m = oracle_lib.Model(binned, T=400)
+    vals = []
+    for th in np.arange(64) / 64.0:
+        p = norm.cdf((lags + 0.5 - th) / sig) - norm.cdf((lags - 0.5 - th) / sig)
+        dp = (norm.pdf((lags - 0.5 - th) / sig) - norm.pdf((lags + 0.5 - th) / sig)) / sig
+        vals.append(np.sum(dp ** 2 / p))
+    exact = np.mean(vals)
+    assert abs(m.fisher / exact - 1) < 2e-2
+    # and a wider Gaussian approaches the continuous value 1/sigma^2
+    assert abs(exact * sig ** 2 - 1) < 0.02

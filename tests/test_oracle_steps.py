@@ -143,7 +143,9 @@ def test_depth_step_moves_towards_the_data(oracle_lib):
     Z = np.zeros((1, 1, 100), dtype=np.uint16)
     Z[0, 0, 41:60] = np.round(irf * 1000).astype(np.uint16)   # surface at 50
     off, ent = oracle_lib.compact(Z)
-    O = oracle_lib.Oracle(m, oracle_lib.Params(k_max=1, dmax=5.0))
+    # beta_t = 1 with strong, background-free data: the Fisher-scaled step is
+    # close to a Newton step
+    O = oracle_lib.Oracle(m, oracle_lib.Params(k_max=1, dmax=5.0, beta_t=1.0))
     for start in (48.3, 50.6, 51.9):
         s = oracle_lib.State(1, 1, 1, 1)
         s.cnt[0] = 1
@@ -155,8 +157,8 @@ def test_depth_step_moves_towards_the_data(oracle_lib):
 
 
 def test_depth_step_is_fisher_scaled_gradient(oracle_lib):
-    # the step is -beta sigma_h^2 (dNLL/dt)/(g r), with dNLL/dt pinned by finite
-    # differences in test_oracle_grad
+    # the step is -beta (dNLL/dt)/(g r I_h), I_h the shift Fisher information of
+    # one photon, with dNLL/dt pinned by finite differences in test_oracle_grad
     from test_oracle_grad import small_problem
     m, s, Z, off, ent = small_problem(oracle_lib, seed=4)
     O = oracle_lib.Oracle(m, oracle_lib.Params(k_max=3, dmax=1e9, beta_t=0.7))
@@ -166,7 +168,7 @@ def test_depth_step_is_fisher_scaled_gradient(oracle_lib):
     for p in range(s.npix):
         for k in range(s.cnt[p]):
             if s.g[p] > 0:
-                expect = np.clip(t0[p, k] - 0.7 * m.sigma2 * gt[p, k] / (s.g[p] * s.r[p, k]), 0, m.T - 1)
+                expect = np.clip(t0[p, k] - 0.7 * gt[p, k] / (s.g[p] * s.r[p, k] * m.fisher), 0, m.T - 1)
                 assert abs(s.t[p, k] - expect) < 1e-9 * max(1.0, abs(expect))
             else:
                 assert s.t[p, k] == t0[p, k]
