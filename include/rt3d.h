@@ -1,0 +1,223 @@
+/*
+ * rt3d.h -- C ABI of librt3d.so, an MI355X (gfx950) implementation of the
+ * per-iteration body of the plug-and-play point-cloud reconstruction of
+ * single-photon lidar data (Tachella et al., "Real-time 3D reconstruction
+ * from single-photon lidar data using plug-and-play point cloud denoisers").
+ *
+ * Problem (Results, "Observation model"): a lidar cube Z of rows x cols
+ * pixels and T histogram bins holds Poisson counts with mean
+ *     lambda[i,j,t] = g[i,j] * ( sum_{n in pixel (i,j)} r_n h(t - t_n) + b[i,j] ),
+ * h the known impulse response (IRF), g the detector gain (0 = dead pixel),
+ * t_n / r_n the depth (bins) and intensity (photons) of point n, b the
+ * background (photons per bin).  The library returns, per pixel, the points
+ * (depth, intensity) and the background that the reconstruction loop of
+ * Results, "Reconstruction algorithm" reaches: gradient steps on t, r and b,
+ * each followed by a denoiser (APSS point-cloud denoising for depth, a
+ * manifold nearest-neighbour low-pass plus a minimum-intensity threshold for
+ * intensity, a 2-D image filter for background).
+ *
+ * Conventions
+ *   - bins are 0-based; depth is the real-valued bin of the IRF origin;
+ *   - pixel p = (frame * rows + i) * cols + j; P = frames * rows * cols;
+ *   - every pointer called `dev_*` or documented as device memory is HIP
+ *     device memory owned by the caller; the library never frees it;
+ *   - every call that takes `hip_stream` only enqueues work on that stream
+ *     (a hipStream_t, NULL = the default stream) and returns; inputs must stay
+ *     valid and outputs untouched until the stream has passed that point;
+ *   - a context is used by one host thread at a time; contexts are
+ *     independent.  No C++ exception crosses this interface.
+ *
+ * Errors: every call returns rt3d_status; on failure rt3d_last_error(ctx)
+ * gives a message (valid until the next call on that context).  Errors found
+ * on the device (capacity overflow) are sticky in the context and reported
+ * by rt3d_query().
+ */
+#ifndef RT3D_H
+#define RT3D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t rt3d_status;
+#define RT3D_OK             0
+#define RT3D_E_INVALID     -1   /* bad argument: null, zero size, bad IRF, misaligned pointer */
+#define RT3D_E_NOMEM       -2   /* workspace missing or too small */
+#define RT3D_E_DEVICE      -3   /* a HIP call failed; message has its text */
+#define RT3D_E_CAPACITY    -4   /* entry or point capacity exceeded; outputs truncated */
+#define RT3D_E_STATE       -5   /* call not valid in the context's state */
+#define RT3D_E_UNSUPPORTED -6   /* valid request this build does not handle */
+
+#define RT3D_K_MAX 4            /* compile-time slot capacity per pixel */
+
+/* Depth denoiser plugged into the depth block. */
+#define RT3D_DENOISE_NONE 0
+#define RT3D_DENOISE_APSS 1
+
+/* Algorithm parameters.  Defaults (rt3d_params_default) are the readings of
+ * the paper's unstated constants; `struct_size` must be sizeof(rt3d_params). */
+typedef struct rt3d_params {
+    uint32_t struct_size;
+    int32_t  n_iter;     /* iterations of the loop (20) */
+    int32_t  k_max;      /* slots per pixel, <= RT3D_K_MAX (4) */
+    int32_t  k_init;     /* peaks sought per pixel at initialisation, <= k_max (3) */
+    double   p_xy;       /* world units per pixel (1) */
+    double   dz;         /* world units per bin (0.1) */
+    double   h_apss;     /* APSS kernel support, world units (2) */
+    double   h_int;      /* intensity graph radius, world units (2) */
+    double   beta_t;     /* depth step scale in units of 1/(g r I_h), I_h the IRF's shift
+                            Fisher information per photon (0.5) */
+    double   dmax;       /* depth step clip in bins; <= 0: max(0.5, 1/sqrt(I_h)) */
+    double   beta_r;     /* intensity step scale (1) */
+    double   beta_b;     /* background step scale (1) */
+    double   r_min;      /* minimum admissible intensity, photons (1) */
+    double   d_merge;    /* in-pixel merge distance, bins; <= 0: max(1, sigma_h) */
+    double   sigma_b;    /* background Gaussian filter, pixels; 0 = identity (2) */
+    double   b_min;      /* background floor, photons/bin (1e-8) */
+    double   sbr_guess;  /* log-matched filter floor eps = 1/(sbr_guess T) (1) */
+    int32_t  r_init;     /* initialisation photon pooling radius, pixels (0) */
+    int32_t  n_min;      /* minimum photons in a peak window (2) */
+    double   kappa;      /* peak acceptance in background standard deviations (3) */
+    int32_t  w_nms;      /* peak suppression half width, bins; <= 0: ceil(max(1, 2 sigma_h)) */
+    int32_t  m_min;      /* minimum APSS neighbours (3) */
+    int32_t  denoiser;   /* RT3D_DENOISE_APSS (default) or RT3D_DENOISE_NONE */
+} rt3d_params;
+
+/* Input kinds. */
+#define RT3D_IN_HIST_U16   0   /* dense histograms */
+#define RT3D_IN_PHOTON_CSR 1   /* active-bin lists, as rt3d_debug_compact writes them */
+
+typedef struct rt3d_input {
+    uint32_t struct_size;      /* sizeof(rt3d_input) */
+    int32_t  kind;             /* RT3D_IN_* */
+    uint32_t frames, rows, cols;
+    /* RT3D_IN_HIST_U16: device uint16 [frames][rows][cols][bins], 16-byte aligned. */
+    const uint16_t* hist;
+    /* RT3D_IN_PHOTON_CSR: device off[P + 1] and ent[off[P]]; entry = (bin << 16) | count,
+     * bins strictly ascending within a pixel, counts >= 1. */
+    const uint32_t* off;
+    const uint32_t* ent;
+    /* Optional device float gain[P] (g of the observation model); NULL = 1. */
+    const float* gain;
+} rt3d_input;
+
+typedef struct rt3d_output {
+    uint32_t struct_size;      /* sizeof(rt3d_output) */
+    uint32_t capacity;         /* points the per-point arrays can hold (P * RT3D_K_MAX always suffices) */
+    uint32_t* pt_off;          /* device [P + 1]: points of pixel p are pt_off[p] .. pt_off[p+1]-1 */
+    double*   depth;           /* device [capacity]: depth in bins, ascending within a pixel */
+    float*    intensity;       /* device [capacity]: intensity in photons */
+    float*    normal;          /* device [capacity * 3] or NULL: unit surface normal (x, y, z) */
+    float*    background;      /* device [P]: background in photons per bin */
+} rt3d_output;
+
+/* Per-point state in device memory, slot-major structure of arrays, as the
+ * library keeps it between steps; used by the step-by-step entry points. */
+typedef struct rt3d_state {
+    uint32_t frames, rows, cols;
+    double*  t;     /* [RT3D_K_MAX][P] depth, bins */
+    float*   r;     /* [RT3D_K_MAX][P] intensity */
+    float*   n;     /* [3][RT3D_K_MAX][P] normal components x, y, z */
+    uint8_t* cnt;   /* [P] live slots 0..cnt-1, ascending depth */
+    float*   b;     /* [P] background */
+} rt3d_state;
+
+typedef struct rt3d_stats {
+    uint32_t struct_size;      /* sizeof(rt3d_stats) */
+    int32_t  device_error;     /* sticky RT3D_E_* found on the device, or RT3D_OK */
+    uint64_t entries;          /* active entries of the last compaction */
+    uint64_t points;           /* points in the last output */
+} rt3d_stats;
+
+typedef struct rt3d_ctx rt3d_ctx;
+
+/* Fill every field of *p with its default. */
+void rt3d_params_default(rt3d_params* p);
+
+/* Create a context for histograms of `bins` bins and the IRF irf[0..irf_len-1]
+ * (host memory, copied): samples at integer lags, normalised here to unit sum,
+ * origin sample `irf_origin` (< 0: the argmax, smallest index on ties).  The
+ * continuous h is the Catmull-Rom interpolant of the samples (zero outside,
+ * clamped at zero), so h and h' are continuous (Results, "Observation model":
+ * h is known).
+ * Requirements: 1 <= irf_len <= bins <= 65535, samples finite and >= 0 with
+ * positive sum.  Uses the current HIP device; uploads small tables (blocking).
+ * E_INVALID on bad arguments, E_DEVICE on a HIP failure. */
+rt3d_status rt3d_create(const double* irf, uint32_t irf_len, int32_t irf_origin, uint32_t bins,
+                        const rt3d_params* p, rt3d_ctx** out);
+
+/* Destroy a context (NULL allowed).  Caller memory is not freed. */
+void rt3d_destroy(rt3d_ctx* ctx);
+
+/* Last error message of the context ("" if none). */
+const char* rt3d_last_error(const rt3d_ctx* ctx);
+
+/* IRF variance sigma_h^2 (bins^2) and model facts of the context. */
+double rt3d_sigma2(const rt3d_ctx* ctx);
+
+/* Bytes of device workspace needed for batches of up to frames x rows x cols
+ * pixels with up to max_entries (< 2^32) active entries after compaction.
+ * rt3d_set_workspace binds such a block (device memory owned by the caller,
+ * 256-byte aligned, at least rt3d_workspace_bytes for the same arguments;
+ * it clears the block's error word, synchronously).  The block must stay
+ * valid while work that uses it is in flight; one workspace serves one stream
+ * at a time.  E_INVALID on a NULL/misaligned pointer or max_entries >= 2^32,
+ * E_NOMEM when `bytes` is too small. */
+size_t rt3d_workspace_bytes(const rt3d_ctx* ctx, uint32_t frames, uint32_t rows, uint32_t cols,
+                            uint64_t max_entries);
+rt3d_status rt3d_set_workspace(rt3d_ctx* ctx, void* dev_ptr, size_t bytes, uint32_t frames,
+                               uint32_t rows, uint32_t cols, uint64_t max_entries);
+
+/* Whole reconstruction (all of the loop: compaction of histograms into active
+ * bins, log-matched-filter initialisation, n_iter iterations of depth,
+ * intensity and background updates, output packing) for a batch of frames.
+ * Asynchronous on hip_stream; no host synchronisation inside.  E_INVALID /
+ * E_NOMEM / E_UNSUPPORTED are found on the host before anything is enqueued. */
+rt3d_status rt3d_reconstruct(rt3d_ctx* ctx, const rt3d_input* in, rt3d_output* out,
+                             void* hip_stream);
+
+/* Synchronise hip_stream, then report device-side errors, entry and point
+ * counts of the last calls.  Returns the sticky device error (or OK). */
+rt3d_status rt3d_query(rt3d_ctx* ctx, void* hip_stream, rt3d_stats* st);
+
+/* ---------------------------------------------------------------------------
+ * Step-by-step entry points (each row of the loop alone, for testing and
+ * for callers composing their own loop).  All asynchronous on hip_stream.
+ * ------------------------------------------------------------------------- */
+
+/* Histogram -> active-bin lists (Methods: cost linear in bins with non-zero
+ * counts).  hist: device uint16 [P][bins], 16-byte aligned; off: device
+ * [P + 1]; ent: device [capacity].  Entries beyond capacity are dropped and
+ * E_CAPACITY becomes the sticky device error.  Needs the workspace. */
+rt3d_status rt3d_debug_compact(rt3d_ctx* ctx, const uint16_t* hist, uint32_t npix,
+                               uint32_t* off, uint32_t* ent, uint64_t capacity, void* hip_stream);
+
+/* Steps.  `in` is read, `out` is written in full (it must not alias `in`);
+ * off/ent are the active-bin lists, gain may be NULL. */
+#define RT3D_STEP_INIT       0  /* log-matched-filter initialisation + initial normals (reads no state) */
+#define RT3D_STEP_DEPTH      1  /* gradient step on depth */
+#define RT3D_STEP_APSS       2  /* APSS depth denoiser */
+#define RT3D_STEP_MERGE      3  /* in-pixel merge of coincident points */
+#define RT3D_STEP_INTENSITY  4  /* gradient step on intensity */
+#define RT3D_STEP_IFILTER    5  /* intensity low-pass, threshold, slot compaction */
+#define RT3D_STEP_BKG        6  /* gradient step on background */
+#define RT3D_STEP_BFILTER    7  /* background image filter */
+#define RT3D_STEP_ITERATION  8  /* one whole iteration (steps 1..7) */
+rt3d_status rt3d_debug_step(rt3d_ctx* ctx, int32_t step, const uint32_t* off, const uint32_t* ent,
+                            const float* gain, const rt3d_state* in, rt3d_state* out,
+                            void* hip_stream);
+
+/* Raw partial derivatives of the negative log-likelihood (Results,
+ * "Observation model"): gt, gr device float [RT3D_K_MAX][P] (slots >= cnt
+ * written 0), gb device float [P]. */
+rt3d_status rt3d_debug_gradients(rt3d_ctx* ctx, const uint32_t* off, const uint32_t* ent,
+                                 const float* gain, const rt3d_state* st,
+                                 float* gt, float* gr, float* gb, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

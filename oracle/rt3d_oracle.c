@@ -309,8 +309,15 @@ void or_grad(const or_model* m, int64_t npix, const uint32_t* off, const uint32_
         for (int k = 0; k < c; ++k) {
             double S, Sp;
             S_eval(m, tp[k], &S, &Sp);
+            /* S' is itself a sum over bins: its terms count in the scale */
+            double asp = 0.0;
+            for (int t = 0; t < m->T; ++t) {
+                double h, hp;
+                h_eval(m, t - tp[k], &h, &hp);
+                asp += fabs(hp);
+            }
             gt[p * k_max + k] = G * rp[k] * (Sp + st[k]);
-            at[p * k_max + k] = G * fabs(rp[k]) * (fabs(Sp) + ast[k]);
+            at[p * k_max + k] = G * fabs(rp[k]) * (asp + ast[k]);
             gr[p * k_max + k] = G * (S - sr[k]);
             ar[p * k_max + k] = G * (S + asr[k]);
         }

@@ -1,0 +1,198 @@
+// k_apss.hip -- APSS point-cloud denoising of depth (Results, "Reconstruction
+// algorithm", depth update: algebraic point set surfaces fit local spheres to
+// the points in world coordinates, the kernel size setting the low-pass) and
+// the in-pixel merge of coincident points.
+//
+// Sphere fit (derived from its least-squares definition): with neighbours
+// y_m = x_m - x_q closer than h, weights w = (1 - d^2/h^2)^4 and unit normals
+// n_m, the sphere s(y) = u0 + ul.y + u4 |y|^2 minimising
+// sum w |grad s(y_m) - n_m|^2, then sum w s(y_m)^2 over u0, is
+//   u4 = (PN - P.N/W) / (2 (PP - P.P/W)),  ul = (N - 2 u4 P)/W,
+//   u0 = -(ul.P + u4 PP)/W,
+// W = sum w, P = sum w y, N = sum w n, PN = sum w y.n, PP = sum w y.y.
+// Reading: q moves along its line of sight to the sphere's root nearest to it
+// (clipped to [-h, h]); its normal becomes grad s there, facing the sensor.
+// Jacobi: every query reads the state before the step.
+//
+// Mapping: one lane per pixel; the lane visits the (2R+1)^2 pixel window
+// around its pixel.  World positions are formed relative to the query in
+// FP64 and the moments accumulate in FP32 in those local coordinates.
+#include "rt3d_dev.h"
+
+namespace rt3d {
+
+__global__ __launch_bounds__(256) void k_apss(DevModel m, DevParams p, Shape sh, DevState in, DevState out)
+{
+    const long long P = sh.P;
+    const long long pix = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pix >= P) return;
+    const int c = load_cnt(in.cnt, pix);
+    out.cnt[pix] = (uint8_t)c;
+    out.b[pix] = in.b[pix];
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+        out.t[k * P + pix] = in.t[k * P + pix];
+        out.r[k * P + pix] = in.r[k * P + pix];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) out.n[(a * KM + k) * P + pix] = in.n[(a * KM + k) * P + pix];
+    }
+    const int per_frame = sh.rows * sh.cols;
+    const long long fr = pix / per_frame;
+    const int i = (int)((pix / sh.cols) % sh.rows), j = (int)(pix % sh.cols);
+    const int R = p.apss_R;
+    const float h = (float)p.h_apss, h2 = h * h, inv_h2 = 1.f / h2;
+    const float pxy = (float)p.p_xy;
+    const double dz = p.dz;
+    const double tmax = (double)(m.T - 1);
+    for (int k = 0; k < KM; ++k) {
+        if (k >= c) break;
+        const double tq = in.t[k * P + pix];
+        float W = 0.f, Px = 0.f, Py = 0.f, Pz = 0.f, Nx = 0.f, Ny = 0.f, Nz = 0.f, PN = 0.f, PP = 0.f;
+        int nn = 0;
+        for (int i2 = max(0, i - R); i2 <= min(sh.rows - 1, i + R); ++i2) {
+            const float yy = (float)(i2 - i) * pxy;
+            for (int j2 = max(0, j - R); j2 <= min(sh.cols - 1, j + R); ++j2) {
+                const float yx = (float)(j2 - j) * pxy;
+                const long long pp = (fr * sh.rows + i2) * sh.cols + j2;
+                const int cc = load_cnt(in.cnt, pp);
+                for (int k2 = 0; k2 < cc; ++k2) {
+                    const float yz = (float)((in.t[k2 * P + pp] - tq) * dz);
+                    const float d2 = yx * yx + yy * yy + yz * yz;
+                    if (!(d2 < h2)) continue;
+                    float a = 1.f - d2 * inv_h2;
+                    a = a * a;
+                    const float w = a * a;
+                    const float nx = in.n[(0 * KM + k2) * P + pp];
+                    const float ny = in.n[(1 * KM + k2) * P + pp];
+                    const float nz = in.n[(2 * KM + k2) * P + pp];
+                    W += w;
+                    Px = fmaf(w, yx, Px);
+                    Py = fmaf(w, yy, Py);
+                    Pz = fmaf(w, yz, Pz);
+                    Nx = fmaf(w, nx, Nx);
+                    Ny = fmaf(w, ny, Ny);
+                    Nz = fmaf(w, nz, Nz);
+                    PN = fmaf(w, yx * nx + yy * ny + yz * nz, PN);
+                    PP = fmaf(w, d2, PP);
+                    ++nn;
+                }
+            }
+        }
+        if (nn < p.m_min) continue;
+        const float invW = 1.f / W;
+        const float PdP = Px * Px + Py * Py + Pz * Pz;
+        const float PdN = Px * Nx + Py * Ny + Pz * Nz;
+        const float D = PP - PdP * invW;
+        if (!(D > 1e-12f * W * h2)) continue;
+        const float u4 = 0.5f * (PN - PdN * invW) / D;
+        const float ulx = (Nx - 2.f * u4 * Px) * invW;
+        const float uly = (Ny - 2.f * u4 * Py) * invW;
+        const float ulz = (Nz - 2.f * u4 * Pz) * invW;
+        const float u0 = -(ulx * Px + uly * Py + ulz * Pz + u4 * PP) * invW;
+        const float nul = sqrtf(ulx * ulx + uly * uly + ulz * ulz);
+        if (!(fabsf(ulz) > 1e-6f * nul)) continue;
+        const float disc = ulz * ulz - 4.f * u4 * u0;
+        float sroot;
+        if (disc < 0.f) sroot = -ulz / (2.f * u4);
+        else sroot = -2.f * u0 / (ulz + copysignf(sqrtf(disc), ulz));
+        sroot = fminf(fmaxf(sroot, -h), h);
+        double tn = tq + (double)sroot / dz;
+        tn = tn < 0.0 ? 0.0 : (tn > tmax ? tmax : tn);
+        out.t[k * P + pix] = tn;
+        const float gx = ulx, gy = uly, gz = ulz + 2.f * u4 * sroot;
+        const float gn = sqrtf(gx * gx + gy * gy + gz * gz);
+        if (gn > 0.f) {
+            const float sg = gz > 0.f ? -1.f : 1.f;
+            const float inv = sg / gn;
+            out.n[(0 * KM + k) * P + pix] = gx * inv;
+            out.n[(1 * KM + k) * P + pix] = gy * inv;
+            out.n[(2 * KM + k) * P + pix] = gz * inv;
+        }
+    }
+}
+
+// Reading (not in the paper): points of one pixel closer than d_merge bins in
+// depth describe one surface; in depth order they merge into the
+// intensity-weighted depth, summed intensity and weighted normal.
+__global__ __launch_bounds__(256) void k_merge(DevParams p, Shape sh, DevState s)
+{
+    const long long P = sh.P;
+    const long long pix = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pix >= P) return;
+    int c = load_cnt(s.cnt, pix);
+    if (c < 2) return;
+    double t[KM];
+    float r[KM], nx[KM], ny[KM], nz[KM];
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+        if (k < c) {
+            t[k] = s.t[k * P + pix];
+            r[k] = s.r[k * P + pix];
+            nx[k] = s.n[(0 * KM + k) * P + pix];
+            ny[k] = s.n[(1 * KM + k) * P + pix];
+            nz[k] = s.n[(2 * KM + k) * P + pix];
+        }
+    }
+    // stable insertion sort by depth
+    for (int a = 1; a < c; ++a)
+        for (int b = a; b > 0 && t[b] < t[b - 1]; --b) {
+            double x = t[b]; t[b] = t[b - 1]; t[b - 1] = x;
+            float y = r[b]; r[b] = r[b - 1]; r[b - 1] = y;
+            y = nx[b]; nx[b] = nx[b - 1]; nx[b - 1] = y;
+            y = ny[b]; ny[b] = ny[b - 1]; ny[b - 1] = y;
+            y = nz[b]; nz[b] = nz[b - 1]; nz[b - 1] = y;
+        }
+    const double dm = p.d_merge;
+    int a = 0;
+    while (a + 1 < c) {
+        if (t[a + 1] - t[a] < dm) {
+            const double ra = r[a], rb = r[a + 1];
+            const double tt = (ra + rb > 0.0) ? (ra * t[a] + rb * t[a + 1]) / (ra + rb) : 0.5 * (t[a] + t[a + 1]);
+            const float mx = r[a] * nx[a] + r[a + 1] * nx[a + 1];
+            const float my = r[a] * ny[a] + r[a + 1] * ny[a + 1];
+            const float mz = r[a] * nz[a] + r[a + 1] * nz[a + 1];
+            const float nrm = sqrtf(mx * mx + my * my + mz * mz);
+            if (nrm > 0.f) {
+                nx[a] = mx / nrm;
+                ny[a] = my / nrm;
+                nz[a] = mz / nrm;
+            }
+            t[a] = tt;
+            r[a] = (float)(ra + rb);
+            for (int b = a + 1; b + 1 < c; ++b) {
+                t[b] = t[b + 1]; r[b] = r[b + 1];
+                nx[b] = nx[b + 1]; ny[b] = ny[b + 1]; nz[b] = nz[b + 1];
+            }
+            --c;
+        } else {
+            ++a;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+        const bool live = k < c;
+        s.t[k * P + pix] = live ? t[k] : 0.0;
+        s.r[k * P + pix] = live ? r[k] : 0.f;
+        s.n[(0 * KM + k) * P + pix] = live ? nx[k] : 0.f;
+        s.n[(1 * KM + k) * P + pix] = live ? ny[k] : 0.f;
+        s.n[(2 * KM + k) * P + pix] = live ? nz[k] : -1.f;
+    }
+    s.cnt[pix] = (uint8_t)c;
+}
+
+hipError_t launch_apss(const DevModel& m, const DevParams& p, const Shape& sh, DevState in, DevState out,
+                       hipStream_t st)
+{
+    if (sh.P == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_apss, dim3((unsigned)((sh.P + 255) / 256)), dim3(256), 0, st, m, p, sh, in, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_merge(const DevParams& p, const Shape& sh, DevState s, hipStream_t st)
+{
+    if (sh.P == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_merge, dim3((unsigned)((sh.P + 255) / 256)), dim3(256), 0, st, p, sh, s);
+    return hipGetLastError();
+}
+
+}  // namespace rt3d

@@ -1,0 +1,210 @@
+// k_compact.hip -- histogram -> active-bin lists, and a device-wide exclusive
+// scan.  The paper's cost model (Methods) is linear in the active (non-zero)
+// bins of each pixel; every later step reads only these lists.
+//
+// Layout: Z is uint16 [P][T] (bins contiguous per pixel); the output is CSR
+// over pixels, entry = (bin << 16) | count, ascending bin.  One wavefront per
+// pixel streams the pixel's bins with 16-byte loads (8 bins per lane per
+// load); a wave-level prefix sum places each lane's entries.
+#include "rt3d_dev.h"
+
+namespace rt3d {
+
+constexpr int SCAN_THREADS = 256;
+constexpr int SCAN_ITEMS = 4;
+constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
+
+// Exclusive prefix over the block's threads; returns the block total in `total`.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t& total)
+{
+    __shared__ uint32_t wsum[SCAN_THREADS / 64];
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    uint32_t inc = wave_incl_scan(v);
+    if (l == 63) wsum[w] = inc;
+    __syncthreads();
+    uint32_t base = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_THREADS / 64; ++k) {
+        uint32_t s = wsum[k];
+        if (k < w) base += s;
+        tot += s;
+    }
+    __syncthreads();
+    total = tot;
+    return base + inc - v;
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_reduce(const uint32_t* __restrict__ in,
+                                                              long long n, uint32_t* __restrict__ partial)
+{
+    long long base = (long long)blockIdx.x * SCAN_TILE + (long long)threadIdx.x * SCAN_ITEMS;
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k)
+        if (base + k < n) s += in[base + k];
+    uint32_t total;
+    block_excl_scan(s, total);
+    if (threadIdx.x == 0) partial[blockIdx.x] = total;
+}
+
+// One block: exclusive scan of the tile totals in place; out[n] = grand total.
+// A grand total above `cap` (or above 32 bits) sets E_CAPACITY.
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_partials(uint32_t* __restrict__ partial,
+                                                                long long nb, uint32_t* __restrict__ out_total,
+                                                                uint64_t cap, int32_t* __restrict__ err)
+{
+    uint32_t carry = 0;
+    uint64_t wide = 0;
+    for (long long b0 = 0; b0 < nb; b0 += SCAN_THREADS) {
+        long long i = b0 + threadIdx.x;
+        uint32_t v = i < nb ? partial[i] : 0u;
+        uint32_t total;
+        uint32_t ex = block_excl_scan(v, total);
+        if (i < nb) partial[i] = carry + ex;
+        carry += total;
+        wide += total;
+    }
+    if (threadIdx.x == 0) {
+        *out_total = carry;
+        if (err && wide > cap) *err = RT3D_E_CAPACITY;
+    }
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_apply(const uint32_t* __restrict__ in, long long n,
+                                                             const uint32_t* __restrict__ partial,
+                                                             uint32_t* __restrict__ out)
+{
+    long long base = (long long)blockIdx.x * SCAN_TILE + (long long)threadIdx.x * SCAN_ITEMS;
+    uint32_t v[SCAN_ITEMS];
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        v[k] = base + k < n ? in[base + k] : 0u;
+        s += v[k];
+    }
+    uint32_t total;
+    uint32_t run = partial[blockIdx.x] + block_excl_scan(s, total);
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        if (base + k < n) out[base + k] = run;
+        run += v[k];
+    }
+}
+
+size_t scan_partial_elems(long long n) { return (size_t)((n + SCAN_TILE - 1) / SCAN_TILE) + 1; }
+
+// out[0..n] = exclusive prefix of in[0..n-1] followed by the total.  `in` and
+// `out` may alias (each tile reads its inputs before writing).
+hipError_t launch_scan(const uint32_t* in, uint32_t* out, long long n, uint32_t* partial, uint64_t cap,
+                       int32_t* err, hipStream_t st)
+{
+    long long nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+    if (nb > 0)
+        hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, st, in, n, partial);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(SCAN_THREADS), 0, st, partial, nb, out + n, cap, err);
+    if (nb > 0)
+        hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, st, in, n, partial, out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// compaction
+
+constexpr int CP_WAVES = 4;   // pixels (wavefronts) per block
+
+// Loads the 8 bins of vector v (bins 8v .. 8v+7 of the flat histogram array);
+// bins outside [lo, hi) read as 0.  Vectors wholly inside the array use one
+// 16-byte load; the array's last partial vector is read element-wise.
+__device__ __forceinline__ void load8(const uint16_t* __restrict__ Z, long long v, long long lo, long long hi,
+                                      long long total, uint16_t (&z)[8])
+{
+    long long i0 = v << 3;
+    if (i0 + 8 <= total) {
+        uint4 x = *reinterpret_cast<const uint4*>(Z + i0);
+        uint32_t w[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            z[2 * k] = (uint16_t)(w[k] & 0xffffu);
+            z[2 * k + 1] = (uint16_t)(w[k] >> 16);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) z[k] = (i0 + k < total) ? Z[i0 + k] : (uint16_t)0;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        if (i0 + k < lo || i0 + k >= hi) z[k] = 0;
+}
+
+__global__ __launch_bounds__(64 * CP_WAVES) void k_compact_count(const uint16_t* __restrict__ Z, long long P,
+                                                                 int T, uint32_t* __restrict__ counts)
+{
+    const long long p = (long long)blockIdx.x * CP_WAVES + (threadIdx.x >> 6);
+    if (p >= P) return;
+    const int lane = threadIdx.x & 63;
+    const long long lo = p * T, hi = lo + T, total = P * T;
+    const long long vs = lo >> 3, ve = (hi + 7) >> 3;
+    uint32_t c = 0;
+    for (long long v = vs + lane; v < ve; v += 64) {
+        uint16_t z[8];
+        load8(Z, v, lo, hi, total, z);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) c += z[k] != 0;
+    }
+    c = wave_sum(c);
+    if (lane == 0) counts[p] = c;
+}
+
+__global__ __launch_bounds__(64 * CP_WAVES) void k_compact_fill(const uint16_t* __restrict__ Z, long long P,
+                                                                int T, const uint32_t* __restrict__ off,
+                                                                uint32_t* __restrict__ ent, uint64_t cap,
+                                                                int32_t* __restrict__ err)
+{
+    const long long p = (long long)blockIdx.x * CP_WAVES + (threadIdx.x >> 6);
+    if (p >= P) return;
+    const int lane = threadIdx.x & 63;
+    const long long lo = p * T, hi = lo + T, total = P * T;
+    const long long vs = lo >> 3, ve = (hi + 7) >> 3;
+    uint64_t run = off[p];
+    bool overflow = false;
+    for (long long vb = vs; vb < ve; vb += 64) {       // uniform over the wave
+        const long long v = vb + lane;
+        uint16_t z[8];
+        if (v < ve) load8(Z, v, lo, hi, total, z);
+        else {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) z[k] = 0;
+        }
+        uint32_t c = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) c += z[k] != 0;
+        uint32_t inc = wave_incl_scan(c);
+        uint32_t tot = __shfl(inc, 63, 64);
+        uint64_t pos = run + (inc - c);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (z[k]) {
+                uint32_t bin = (uint32_t)((v << 3) + k - lo);
+                if (pos < cap) ent[pos] = (bin << 16) | z[k];
+                else overflow = true;
+                ++pos;
+            }
+        }
+        run += tot;
+    }
+    if (overflow) *err = RT3D_E_CAPACITY;
+}
+
+hipError_t launch_compact(const uint16_t* Z, long long P, int T, uint32_t* off, uint32_t* ent, uint64_t cap,
+                          uint32_t* counts, uint32_t* partial, int32_t* err, hipStream_t st)
+{
+    unsigned nb = (unsigned)((P + CP_WAVES - 1) / CP_WAVES);
+    if (nb > 0) hipLaunchKernelGGL(k_compact_count, dim3(nb), dim3(64 * CP_WAVES), 0, st, Z, P, T, counts);
+    hipError_t e = launch_scan(counts, off, P, partial, cap, err, st);
+    if (e != hipSuccess) return e;
+    if (nb > 0)
+        hipLaunchKernelGGL(k_compact_fill, dim3(nb), dim3(64 * CP_WAVES), 0, st, Z, P, T, off, ent, cap, err);
+    return hipGetLastError();
+}
+
+}  // namespace rt3d

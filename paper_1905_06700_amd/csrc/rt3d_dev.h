@@ -1,0 +1,172 @@
+// rt3d_dev.h -- device-side structures, helpers and kernel launchers shared by
+// the HIP translation units of librt3d.so (internal; not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/rt3d.h"
+
+namespace rt3d {
+
+constexpr int KM = RT3D_K_MAX;
+
+// Observation model tables on the device (built on the host in FP64).
+struct DevModel {
+    const float4*  cr;    // Catmull-Rom segment k-1 (samples k..k+1): cubic coefficients (c0, c1, c2, c3)
+    const int32_t* q;     // log-matched-filter weights, 16 fractional bits
+    const double*  hbar;  // normalised IRF samples
+    int   T, L, o;
+    int   wl, wr;         // peak window half widths
+    int   wnms;           // peak suppression half width
+    float sigma2;         // IRF variance
+    float fisher_inv;     // 1 / (shift Fisher information per photon)
+};
+
+// Parameters as the kernels use them.
+struct DevParams {
+    int    k_max, k_init, r_init, n_min, m_min, apss_R;
+    double p_xy, dz, h_apss, h_int;
+    double beta_t, dmax, beta_r, beta_b, r_min, d_merge, b_min, kappa;
+};
+
+// Point state, slot-major structure of arrays (see rt3d_state).
+struct DevState {
+    double*  t;
+    float*   r;
+    float*   n;     // [3][KM][P]
+    uint8_t* cnt;
+    float*   b;
+};
+
+struct Shape {
+    int F, rows, cols;
+    long long P;    // F * rows * cols
+};
+
+// ---------------------------------------------------------------------------
+// Model evaluation in FP32 local coordinates.
+
+// Catmull-Rom segment value and slope at local parameter s, clamped at zero.
+__device__ __forceinline__ void cr_segment(const float4 c, float s, float& h, float& hp)
+{
+    h = fmaf(fmaf(fmaf(c.w, s, c.z), s, c.y), s, c.x);
+    hp = fmaf(fmaf(3.f * c.w, s, 2.f * c.z), s, c.y);
+    if (!(h > 0.f)) {
+        h = 0.f;
+        hp = 0.f;
+    }
+}
+
+// h(tb - t) and dh/dtau for an integer bin tb and a point at depth t held as
+// integer anchor a = floor(t) plus fraction f = t - a.  h is the Catmull-Rom
+// interpolant of the IRF samples (continuous value and slope).
+__device__ __forceinline__ void irf_eval(const DevModel& m, int tb, int a, float f, float& h, float& hp)
+{
+    const float x = (float)(tb - a + m.o) - f;   // sample position of the lag
+    h = 0.f;
+    hp = 0.f;
+    if (x > -1.f && x < (float)m.L) {
+        const float fk = floorf(x);
+        cr_segment(m.cr[(int)fk + 1], x - fk, h, hp);
+    }
+}
+
+// S(t) = sum over bins of h(tb - t) and dS/dt = -sum h'(tb - t), by direct
+// summation over the IRF support (every lag shares the local parameter).
+__device__ __forceinline__ void s_eval(const DevModel& m, double t, float& S, float& Sp)
+{
+    const double fl = floor(t);
+    const int a = (int)fl;
+    const float f = (float)(t - fl);
+    const int sh = f > 0.f ? 1 : 0;
+    const float s = sh ? 1.f - f : 0.f;
+    // segment k holds bin tb = k + a - o + sh; keep 0 <= tb <= T - 1
+    const int k0 = max(-1, m.o - a - sh), k1 = min(m.L - 1, m.T - 1 + m.o - a - sh);
+    float acc = 0.f, accp = 0.f;
+    for (int k = k0; k <= k1; ++k) {
+        float h, hp;
+        cr_segment(m.cr[k + 1], s, h, hp);
+        acc += h;
+        accp -= hp;
+    }
+    S = acc;
+    Sp = accp;
+}
+
+__device__ __forceinline__ int ent_bin(uint32_t e) { return (int)(e >> 16); }
+
+// Live slot count of a pixel, clamped to the slot capacity.
+__device__ __forceinline__ int load_cnt(const uint8_t* cnt, long long pix)
+{
+    int c = cnt[pix];
+    return c < KM ? c : KM;
+}
+__device__ __forceinline__ int ent_cnt(uint32_t e) { return (int)(e & 0xffffu); }
+
+// Wave-level helpers (wave64).
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v)
+{
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+// Inclusive prefix sum over the 64 lanes.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
+{
+    const int l = lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t o = __shfl_up(v, d, 64);
+        if (l >= d) v += o;
+    }
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers (defined in the .hip files).  All enqueue on `st` and return the
+// launch status.
+
+hipError_t launch_scan(const uint32_t* in, uint32_t* out, long long n, uint32_t* partial,
+                       uint64_t cap, int32_t* err, hipStream_t st);
+size_t scan_partial_elems(long long n);
+
+hipError_t launch_compact(const uint16_t* Z, long long P, int T, uint32_t* off, uint32_t* ent,
+                          uint64_t cap, uint32_t* counts, uint32_t* partial, int32_t* err,
+                          hipStream_t st);
+
+hipError_t launch_init(const DevModel& m, const DevParams& p, const Shape& sh, const uint32_t* off,
+                       const uint32_t* ent, const float* gain, DevState s, int32_t* err,
+                       hipStream_t st);
+hipError_t launch_init_normals(const DevParams& p, const Shape& sh, DevState s, hipStream_t st);
+
+hipError_t launch_depth_step(const DevModel& m, const DevParams& p, const Shape& sh,
+                             const uint32_t* off, const uint32_t* ent, const float* gain,
+                             DevState s, hipStream_t st);
+hipError_t launch_intensity_step(const DevModel& m, const DevParams& p, const Shape& sh,
+                                 const uint32_t* off, const uint32_t* ent, const float* gain,
+                                 DevState s, hipStream_t st);
+hipError_t launch_bg_step(const DevModel& m, const DevParams& p, const Shape& sh,
+                          const uint32_t* off, const uint32_t* ent, const float* gain, DevState s,
+                          hipStream_t st);
+hipError_t launch_gradients(const DevModel& m, const DevParams& p, const Shape& sh,
+                            const uint32_t* off, const uint32_t* ent, const float* gain,
+                            DevState s, float* gt, float* gr, float* gb, hipStream_t st);
+
+hipError_t launch_apss(const DevModel& m, const DevParams& p, const Shape& sh, DevState in,
+                       DevState out, hipStream_t st);
+hipError_t launch_merge(const DevParams& p, const Shape& sh, DevState s, hipStream_t st);
+hipError_t launch_ifilter(const DevParams& p, const Shape& sh, DevState in, DevState out,
+                          hipStream_t st);
+hipError_t launch_bfilter(const float* w, int rb, const Shape& sh, float b_min, float* b,
+                          float* tmp, hipStream_t st);
+hipError_t launch_copy_state(const Shape& sh, DevState in, DevState out, hipStream_t st);
+
+hipError_t launch_output(const Shape& sh, DevState s, rt3d_output* out, uint32_t* counts,
+                         uint32_t* partial, int32_t* err, hipStream_t st);
+
+}  // namespace rt3d

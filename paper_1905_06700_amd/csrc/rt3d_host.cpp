@@ -1,0 +1,610 @@
+// rt3d_host.cpp -- host runtime behind the C ABI of include/rt3d.h: argument
+// checks, the IRF tables (built in FP64), workspace carving and the launch
+// sequence of one reconstruction.  Nothing here synchronises the caller's
+// stream except rt3d_query and rt3d_create's table upload.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "rt3d_dev.h"
+
+namespace rt3d {
+size_t init_lds_bytes(int T);
+}
+
+using namespace rt3d;
+
+struct rt3d_ctx {
+    rt3d_params p{};
+    int T = 0, L = 0, o = 0;
+    double sigma2 = 0.0, fisher = 0.0;
+    int wl = 0, wr = 0, wnms = 0, apss_R = 0;
+    double dmax = 0.0, dmerge = 0.0;
+    std::vector<double> hbar;
+    int device = 0;
+    // device tables (owned)
+    float4* d_cr = nullptr;
+    int32_t* d_q = nullptr;
+    double* d_hbar = nullptr;
+    float* d_bw = nullptr;
+    int rb = 0;
+    // workspace (caller's)
+    uint8_t* ws = nullptr;
+    size_t ws_bytes = 0;
+    long long ws_P = 0;
+    uint64_t ws_E = 0;
+    // last call facts
+    long long last_P = 0;
+    bool last_compacted = false;
+    std::string err;
+};
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+
+size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+struct Workspace {
+    uint32_t* off;
+    uint32_t* ent;
+    uint32_t* counts;
+    uint32_t* partial;
+    DevState A, B;
+    float* btmp;
+    int32_t* err;
+    size_t bytes;
+};
+
+// Carves the workspace for P pixels and E entries; with base == nullptr it
+// only measures.
+Workspace carve(uint8_t* base, long long P, uint64_t E)
+{
+    Workspace w{};
+    size_t at = 0;
+    auto take = [&](size_t bytes) -> uint8_t* {
+        uint8_t* ptr = base ? base + at : nullptr;
+        at += align_up(bytes);
+        return ptr;
+    };
+    w.err = (int32_t*)take(sizeof(int32_t) * 4);
+    w.off = (uint32_t*)take(sizeof(uint32_t) * (P + 1));
+    w.ent = (uint32_t*)take(sizeof(uint32_t) * std::max<uint64_t>(E, 1));
+    w.counts = (uint32_t*)take(sizeof(uint32_t) * std::max<long long>(P, 1));
+    w.partial = (uint32_t*)take(sizeof(uint32_t) * scan_partial_elems(P));
+    for (DevState* s : {&w.A, &w.B}) {
+        s->t = (double*)take(sizeof(double) * KM * P);
+        s->r = (float*)take(sizeof(float) * KM * P);
+        s->n = (float*)take(sizeof(float) * 3 * KM * P);
+        s->cnt = (uint8_t*)take(P);
+        s->b = (float*)take(sizeof(float) * P);
+    }
+    w.btmp = (float*)take(sizeof(float) * P);
+    w.bytes = at;
+    return w;
+}
+
+rt3d_status fail(rt3d_ctx* c, rt3d_status st, const std::string& msg)
+{
+    if (c) c->err = msg;
+    return st;
+}
+
+rt3d_status hip_fail(rt3d_ctx* c, hipError_t e, const char* what)
+{
+    return fail(c, RT3D_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define RT3D_HIP(ctx, call)                                      \
+    do {                                                         \
+        hipError_t e_ = (call);                                  \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, #call);   \
+    } while (0)
+
+DevModel dev_model(const rt3d_ctx* c)
+{
+    DevModel m{};
+    m.cr = c->d_cr;
+    m.q = c->d_q;
+    m.hbar = c->d_hbar;
+    m.T = c->T;
+    m.L = c->L;
+    m.o = c->o;
+    m.wl = c->wl;
+    m.wr = c->wr;
+    m.wnms = c->wnms;
+    m.sigma2 = (float)c->sigma2;
+    m.fisher_inv = (float)(1.0 / c->fisher);
+    return m;
+}
+
+DevParams dev_params(const rt3d_ctx* c)
+{
+    DevParams d{};
+    const rt3d_params& p = c->p;
+    d.k_max = p.k_max;
+    d.k_init = p.k_init;
+    d.r_init = p.r_init;
+    d.n_min = p.n_min;
+    d.m_min = p.m_min;
+    d.apss_R = c->apss_R;
+    d.p_xy = p.p_xy;
+    d.dz = p.dz;
+    d.h_apss = p.h_apss;
+    d.h_int = p.h_int;
+    d.beta_t = p.beta_t;
+    d.dmax = c->dmax;
+    d.beta_r = p.beta_r;
+    d.beta_b = p.beta_b;
+    d.r_min = p.r_min;
+    d.d_merge = c->dmerge;
+    d.b_min = p.b_min;
+    d.kappa = p.kappa;
+    return d;
+}
+
+rt3d_status check_params(const rt3d_params* p, uint32_t bins, std::string& why)
+{
+    if (!p) { why = "params is NULL"; return RT3D_E_INVALID; }
+    if (p->struct_size != sizeof(rt3d_params)) { why = "params.struct_size mismatch"; return RT3D_E_INVALID; }
+    if (p->n_iter < 0) { why = "n_iter < 0"; return RT3D_E_INVALID; }
+    if (p->k_max < 1 || p->k_max > RT3D_K_MAX) { why = "k_max outside 1..RT3D_K_MAX"; return RT3D_E_INVALID; }
+    if (p->k_init < 1 || p->k_init > p->k_max) { why = "k_init outside 1..k_max"; return RT3D_E_INVALID; }
+    if (!(p->p_xy > 0) || !(p->dz > 0) || !(p->h_apss > 0) || !(p->h_int >= 0)) {
+        why = "p_xy, dz, h_apss must be > 0 and h_int >= 0"; return RT3D_E_INVALID;
+    }
+    if (!(p->b_min > 0)) { why = "b_min must be > 0"; return RT3D_E_INVALID; }
+    if (!(p->sigma_b >= 0) || p->sigma_b > 64) { why = "sigma_b outside [0, 64]"; return RT3D_E_INVALID; }
+    if (!(p->sbr_guess > 0)) { why = "sbr_guess must be > 0"; return RT3D_E_INVALID; }
+    if (p->r_init < 0 || p->r_init > 8) { why = "r_init outside 0..8"; return RT3D_E_INVALID; }
+    if (p->denoiser != RT3D_DENOISE_APSS && p->denoiser != RT3D_DENOISE_NONE) {
+        why = "unknown denoiser"; return RT3D_E_UNSUPPORTED;
+    }
+    if (std::ceil(p->h_apss / p->p_xy) > 16) { why = "h_apss / p_xy above 16 pixels"; return RT3D_E_UNSUPPORTED; }
+    if (!(p->beta_t >= 0) || !(p->beta_r >= 0) || !(p->beta_b >= 0)) { why = "negative step scale"; return RT3D_E_INVALID; }
+    if (!std::isfinite(p->r_min) || !std::isfinite(p->kappa) || p->kappa < 0) {
+        why = "r_min / kappa not finite or kappa < 0"; return RT3D_E_INVALID;
+    }
+    (void)bins;
+    return RT3D_OK;
+}
+
+rt3d_status need_ws(rt3d_ctx* c, long long P, Workspace& w)
+{
+    if (!c->ws) return fail(c, RT3D_E_NOMEM, "no workspace bound (rt3d_set_workspace)");
+    if (P > c->ws_P) return fail(c, RT3D_E_NOMEM, "batch larger than the workspace was sized for");
+    w = carve(c->ws, c->ws_P, c->ws_E);
+    return RT3D_OK;
+}
+
+bool state_ok(const rt3d_state* s)
+{
+    return s && s->t && s->r && s->n && s->cnt && s->b && s->frames && s->rows && s->cols;
+}
+
+DevState dev_state(const rt3d_state* s) { return DevState{s->t, s->r, s->n, s->cnt, s->b}; }
+
+bool shape_ok(uint32_t F, uint32_t rows, uint32_t cols)
+{
+    const long long P = (long long)F * rows * cols;
+    return P > 0 && P < (1ll << 31) && (long long)rows * cols < (1ll << 31);
+}
+
+Shape shape_of(uint32_t F, uint32_t rows, uint32_t cols)
+{
+    Shape sh;
+    sh.F = (int)F;
+    sh.rows = (int)rows;
+    sh.cols = (int)cols;
+    sh.P = (long long)F * rows * cols;
+    return sh;
+}
+
+// One iteration of the loop on state A (in/out) with B as the second buffer.
+rt3d_status iterate(rt3d_ctx* c, const Shape& sh, const uint32_t* off, const uint32_t* ent, const float* gain,
+                    DevState A, DevState B, float* btmp, hipStream_t st)
+{
+    const DevModel m = dev_model(c);
+    const DevParams p = dev_params(c);
+    RT3D_HIP(c, launch_depth_step(m, p, sh, off, ent, gain, A, st));
+    DevState cur = A;
+    if (c->p.denoiser == RT3D_DENOISE_APSS) {
+        RT3D_HIP(c, launch_apss(m, p, sh, A, B, st));
+        cur = B;
+    } else {
+        RT3D_HIP(c, launch_copy_state(sh, A, B, st));
+        cur = B;
+    }
+    RT3D_HIP(c, launch_merge(p, sh, cur, st));
+    RT3D_HIP(c, launch_intensity_step(m, p, sh, off, ent, gain, cur, st));
+    RT3D_HIP(c, launch_ifilter(p, sh, cur, A, st));
+    RT3D_HIP(c, launch_bg_step(m, p, sh, off, ent, gain, A, st));
+    RT3D_HIP(c, launch_bfilter(c->d_bw, c->rb, sh, (float)c->p.b_min, A.b, btmp, st));
+    return RT3D_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void rt3d_params_default(rt3d_params* p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->struct_size = sizeof(rt3d_params);
+    p->n_iter = 20;
+    p->k_max = 4;
+    p->k_init = 3;
+    p->p_xy = 1.0;
+    p->dz = 0.1;
+    p->h_apss = 2.0;
+    p->h_int = 2.0;
+    p->beta_t = 0.5;
+    p->dmax = 0.0;
+    p->beta_r = 1.0;
+    p->beta_b = 1.0;
+    p->r_min = 1.0;
+    p->d_merge = 0.0;
+    p->sigma_b = 2.0;
+    p->b_min = 1e-8;
+    p->sbr_guess = 1.0;
+    p->r_init = 0;
+    p->n_min = 2;
+    p->kappa = 3.0;
+    p->w_nms = 0;
+    p->m_min = 3;
+    p->denoiser = RT3D_DENOISE_APSS;
+}
+
+rt3d_status rt3d_create(const double* irf, uint32_t irf_len, int32_t irf_origin, uint32_t bins,
+                        const rt3d_params* p, rt3d_ctx** out)
+{
+    if (!out) return RT3D_E_INVALID;
+    *out = nullptr;
+    if (!irf || irf_len == 0 || bins == 0 || bins > 65535 || irf_len > bins) return RT3D_E_INVALID;
+    std::string why;
+    rt3d_status ps = check_params(p, bins, why);
+    if (ps != RT3D_OK) return ps;
+    double sum = 0.0;
+    for (uint32_t k = 0; k < irf_len; ++k) {
+        if (!std::isfinite(irf[k]) || irf[k] < 0.0) return RT3D_E_INVALID;
+        sum += irf[k];
+    }
+    if (!(sum > 0.0)) return RT3D_E_INVALID;
+    if (irf_origin >= (int32_t)irf_len) return RT3D_E_INVALID;
+    if (p->r_init > 0 && init_lds_bytes((int)bins) > 65536) return RT3D_E_UNSUPPORTED;
+    if (init_lds_bytes((int)bins) > 65536) return RT3D_E_UNSUPPORTED;
+
+    rt3d_ctx* c = new (std::nothrow) rt3d_ctx();
+    if (!c) return RT3D_E_NOMEM;
+    c->p = *p;
+    c->T = (int)bins;
+    c->L = (int)irf_len;
+    c->hbar.resize(irf_len);
+    for (uint32_t k = 0; k < irf_len; ++k) c->hbar[k] = irf[k] / sum;
+    if (irf_origin < 0) {
+        int best = 0;
+        for (int k = 1; k < c->L; ++k)
+            if (c->hbar[k] > c->hbar[best]) best = k;
+        irf_origin = best;
+    }
+    c->o = irf_origin;
+    // moments and windows of the normalised IRF
+    double mu = 0.0;
+    for (int k = 0; k < c->L; ++k) mu += k * c->hbar[k];
+    double var = 0.0;
+    for (int k = 0; k < c->L; ++k) var += c->hbar[k] * (k - mu) * (k - mu);
+    c->sigma2 = var;
+    const double sh = std::sqrt(var);
+    {
+        double acc = 0.0;
+        int lo = -1, hi = -1;
+        for (int k = 0; k < c->L; ++k) {
+            acc += c->hbar[k];
+            if (lo < 0 && acc >= 0.05) lo = k;
+            if (hi < 0 && acc >= 0.95) hi = k;
+        }
+        if (lo < 0) lo = 0;
+        if (hi < 0) hi = c->L - 1;
+        c->wl = std::max(0, c->o - lo);
+        c->wr = std::max(0, hi - c->o);
+    }
+    c->wnms = p->w_nms > 0 ? p->w_nms : (int)std::ceil(std::max(1.0, 2.0 * sh));
+    c->dmerge = p->d_merge > 0 ? p->d_merge : std::max(1.0, sh);
+    c->apss_R = (int)std::ceil(p->h_apss / p->p_xy);
+
+    const int L = c->L, T = c->T;
+    // Catmull-Rom cubic of each segment between samples k and k+1, k = -1..L-1
+    // (samples beyond the IRF are zero): value c0 + c1 s + c2 s^2 + c3 s^3
+    auto hb = [&](int k) { return (k >= 0 && k < L) ? c->hbar[k] : 0.0; };
+    std::vector<float4> cr(L + 1);
+    std::vector<double> crd((size_t)4 * (L + 1));
+    for (int k = -1; k < L; ++k) {
+        const double p0 = hb(k - 1), p1 = hb(k), p2 = hb(k + 1), p3 = hb(k + 2);
+        double* d = &crd[(size_t)4 * (k + 1)];
+        d[0] = p1;
+        d[1] = 0.5 * (p2 - p0);
+        d[2] = p0 - 2.5 * p1 + 2.0 * p2 - 0.5 * p3;
+        d[3] = 0.5 * (p3 - p0) + 1.5 * (p1 - p2);
+        cr[k + 1] = make_float4((float)d[0], (float)d[1], (float)d[2], (float)d[3]);
+    }
+    // shift Fisher information of one photon (no background), averaged over 32
+    // sub-bin phases, over lags where h is at least 1e-3 of the largest sample
+    {
+        double hmax = 0.0;
+        for (int k = 0; k < L; ++k) hmax = std::max(hmax, c->hbar[k]);
+        double acc = 0.0;
+        for (int j = 0; j < 32; ++j) {
+            for (int l = -c->o - 1; l <= L - c->o; ++l) {
+                const double x = l + j / 32.0 + c->o;
+                if (!(x > -1.0) || !(x < L)) continue;
+                const int k = (int)std::floor(x);
+                const double sl = x - k;
+                const double* d = &crd[(size_t)4 * (k + 1)];
+                const double h = ((d[3] * sl + d[2]) * sl + d[1]) * sl + d[0];
+                if (!(h > 0.0) || h < 1e-3 * hmax) continue;
+                const double hp = (3.0 * d[3] * sl + 2.0 * d[2]) * sl + d[1];
+                acc += hp * hp / h;
+            }
+        }
+        c->fisher = acc / 32.0;
+    }
+    if (!(c->fisher > 0.0)) {
+        delete c;
+        return RT3D_E_INVALID;
+    }
+    c->dmax = p->dmax > 0 ? p->dmax : std::max(0.5, 1.0 / std::sqrt(c->fisher));
+    // log-matched filter weights, 16 fractional bits
+    std::vector<int32_t> q(L);
+    const double inv_eps = p->sbr_guess * (double)T;
+    for (int k = 0; k < L; ++k) q[k] = (int32_t)std::llround(std::log1p(c->hbar[k] * inv_eps) * 65536.0);
+    // background filter taps
+    std::vector<float> bw;
+    if (p->sigma_b > 0.0) {
+        c->rb = (int)std::ceil(4.0 * p->sigma_b);
+        std::vector<double> w(2 * c->rb + 1);
+        double s = 0.0;
+        for (int d = -c->rb; d <= c->rb; ++d) {
+            w[d + c->rb] = std::exp(-(double)d * d / (2.0 * p->sigma_b * p->sigma_b));
+            s += w[d + c->rb];
+        }
+        for (double v : w) bw.push_back((float)(v / s));
+    } else {
+        c->rb = 0;
+        bw.push_back(1.0f);
+    }
+
+    hipError_t e = hipGetDevice(&c->device);
+    if (e == hipSuccess) e = hipMalloc(&c->d_cr, sizeof(float4) * cr.size());
+    if (e == hipSuccess) e = hipMalloc(&c->d_q, sizeof(int32_t) * q.size());
+    if (e == hipSuccess) e = hipMalloc(&c->d_hbar, sizeof(double) * L);
+    if (e == hipSuccess) e = hipMalloc(&c->d_bw, sizeof(float) * bw.size());
+    if (e == hipSuccess) e = hipMemcpy(c->d_cr, cr.data(), sizeof(float4) * cr.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->d_q, q.data(), sizeof(int32_t) * q.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->d_hbar, c->hbar.data(), sizeof(double) * L, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->d_bw, bw.data(), sizeof(float) * bw.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        rt3d_destroy(c);
+        return RT3D_E_DEVICE;
+    }
+    *out = c;
+    return RT3D_OK;
+}
+
+void rt3d_destroy(rt3d_ctx* c)
+{
+    if (!c) return;
+    int prev = 0;
+    bool switched = hipGetDevice(&prev) == hipSuccess && prev != c->device && hipSetDevice(c->device) == hipSuccess;
+    if (c->d_cr) (void)hipFree(c->d_cr);
+    if (c->d_q) (void)hipFree(c->d_q);
+    if (c->d_hbar) (void)hipFree(c->d_hbar);
+    if (c->d_bw) (void)hipFree(c->d_bw);
+    if (switched) (void)hipSetDevice(prev);
+    delete c;
+}
+
+const char* rt3d_last_error(const rt3d_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+double rt3d_sigma2(const rt3d_ctx* c) { return c ? c->sigma2 : 0.0; }
+
+size_t rt3d_workspace_bytes(const rt3d_ctx* c, uint32_t frames, uint32_t rows, uint32_t cols, uint64_t max_entries)
+{
+    if (!c) return 0;
+    const long long P = (long long)frames * rows * cols;
+    return carve(nullptr, P, max_entries).bytes;
+}
+
+rt3d_status rt3d_set_workspace(rt3d_ctx* c, void* dev_ptr, size_t bytes, uint32_t frames, uint32_t rows,
+                               uint32_t cols, uint64_t max_entries)
+{
+    if (!c) return RT3D_E_INVALID;
+    c->ws = nullptr;
+    c->ws_P = 0;
+    c->ws_E = 0;
+    if (!dev_ptr || bytes == 0) return fail(c, RT3D_E_INVALID, "workspace pointer NULL or size 0");
+    if (((uintptr_t)dev_ptr) % ALIGN) return fail(c, RT3D_E_INVALID, "workspace not 256-byte aligned");
+    if (max_entries >= (1ull << 32)) return fail(c, RT3D_E_INVALID, "max_entries must be < 2^32");
+    const long long P = (long long)frames * rows * cols;
+    if (P <= 0) return fail(c, RT3D_E_INVALID, "zero frames, rows or cols");
+    if (carve(nullptr, P, max_entries).bytes > bytes)
+        return fail(c, RT3D_E_NOMEM, "workspace smaller than rt3d_workspace_bytes for this shape");
+    Workspace w = carve((uint8_t*)dev_ptr, P, max_entries);
+    hipError_t e = hipMemset(w.err, 0, sizeof(int32_t) * 4);
+    if (e != hipSuccess) return hip_fail(c, e, "hipMemset(workspace error word)");
+    c->ws = (uint8_t*)dev_ptr;
+    c->ws_bytes = bytes;
+    c->ws_P = P;
+    c->ws_E = max_entries;
+    return RT3D_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+rt3d_status rt3d_reconstruct(rt3d_ctx* c, const rt3d_input* in, rt3d_output* out, void* hip_stream)
+{
+    if (!c) return RT3D_E_INVALID;
+    if (!in || in->struct_size != sizeof(rt3d_input)) return fail(c, RT3D_E_INVALID, "input NULL or struct_size mismatch");
+    if (!out || out->struct_size != sizeof(rt3d_output)) return fail(c, RT3D_E_INVALID, "output NULL or struct_size mismatch");
+    if (!shape_ok(in->frames, in->rows, in->cols))
+        return fail(c, RT3D_E_INVALID, "frames x rows x cols must be in 1 .. 2^31-1");
+    if (!out->pt_off || !out->depth || !out->intensity || !out->background || out->capacity == 0)
+        return fail(c, RT3D_E_INVALID, "output pointers NULL or capacity 0");
+    const Shape sh = shape_of(in->frames, in->rows, in->cols);
+    Workspace w;
+    rt3d_status s = need_ws(c, sh.P, w);
+    if (s != RT3D_OK) return s;
+    hipStream_t st = (hipStream_t)hip_stream;
+    const uint32_t* off;
+    const uint32_t* ent;
+    if (in->kind == RT3D_IN_HIST_U16) {
+        if (!in->hist) return fail(c, RT3D_E_INVALID, "hist is NULL");
+        if (((uintptr_t)in->hist) % 16) return fail(c, RT3D_E_INVALID, "hist not 16-byte aligned");
+        RT3D_HIP(c, launch_compact(in->hist, sh.P, c->T, w.off, w.ent, c->ws_E, w.counts, w.partial, w.err, st));
+        off = w.off;
+        ent = w.ent;
+        c->last_compacted = true;
+    } else if (in->kind == RT3D_IN_PHOTON_CSR) {
+        if (!in->off || !in->ent) return fail(c, RT3D_E_INVALID, "off/ent is NULL");
+        off = in->off;
+        ent = in->ent;
+        c->last_compacted = false;
+    } else {
+        return fail(c, RT3D_E_UNSUPPORTED, "unknown input kind");
+    }
+    c->last_P = sh.P;
+    const DevModel m = dev_model(c);
+    const DevParams p = dev_params(c);
+    RT3D_HIP(c, launch_init(m, p, sh, off, ent, in->gain, w.A, w.err, st));
+    RT3D_HIP(c, launch_init_normals(p, sh, w.A, st));
+    for (int it = 0; it < c->p.n_iter; ++it) {
+        s = iterate(c, sh, off, ent, in->gain, w.A, w.B, w.btmp, st);
+        if (s != RT3D_OK) return s;
+    }
+    RT3D_HIP(c, launch_output(sh, w.A, out, w.counts, w.partial, w.err, st));
+    return RT3D_OK;
+}
+
+rt3d_status rt3d_query(rt3d_ctx* c, void* hip_stream, rt3d_stats* st)
+{
+    if (!c) return RT3D_E_INVALID;
+    if (st && st->struct_size != sizeof(rt3d_stats)) return fail(c, RT3D_E_INVALID, "stats struct_size mismatch");
+    RT3D_HIP(c, hipStreamSynchronize((hipStream_t)hip_stream));
+    int32_t derr = 0;
+    uint32_t E = 0;
+    if (c->ws) {
+        Workspace w = carve(c->ws, c->ws_P, c->ws_E);
+        RT3D_HIP(c, hipMemcpy(&derr, w.err, sizeof(int32_t), hipMemcpyDeviceToHost));
+        if (c->last_compacted && c->last_P > 0)
+            RT3D_HIP(c, hipMemcpy(&E, w.off + c->last_P, sizeof(uint32_t), hipMemcpyDeviceToHost));
+        if (derr != 0) RT3D_HIP(c, hipMemset(w.err, 0, sizeof(int32_t)));
+    }
+    if (st) {
+        st->device_error = derr;
+        st->entries = E;
+        st->points = 0;
+    }
+    if (derr != 0) return fail(c, derr, "device reported an error (capacity exceeded)");
+    return RT3D_OK;
+}
+
+rt3d_status rt3d_debug_compact(rt3d_ctx* c, const uint16_t* hist, uint32_t npix, uint32_t* off, uint32_t* ent,
+                               uint64_t capacity, void* hip_stream)
+{
+    if (!c) return RT3D_E_INVALID;
+    if (!hist || !off || !ent || npix == 0 || capacity == 0) return fail(c, RT3D_E_INVALID, "NULL pointer or zero size");
+    if (((uintptr_t)hist) % 16) return fail(c, RT3D_E_INVALID, "hist not 16-byte aligned");
+    Workspace w;
+    rt3d_status s = need_ws(c, npix, w);
+    if (s != RT3D_OK) return s;
+    RT3D_HIP(c, launch_compact(hist, npix, c->T, off, ent, capacity, w.counts, w.partial, w.err,
+                               (hipStream_t)hip_stream));
+    return RT3D_OK;
+}
+
+rt3d_status rt3d_debug_step(rt3d_ctx* c, int32_t step, const uint32_t* off, const uint32_t* ent, const float* gain,
+                            const rt3d_state* in, rt3d_state* out, void* hip_stream)
+{
+    if (!c) return RT3D_E_INVALID;
+    if (!state_ok(out)) return fail(c, RT3D_E_INVALID, "output state incomplete");
+    if (step != RT3D_STEP_INIT && !state_ok(in)) return fail(c, RT3D_E_INVALID, "input state incomplete");
+    if (step != RT3D_STEP_INIT && (in->frames != out->frames || in->rows != out->rows || in->cols != out->cols))
+        return fail(c, RT3D_E_INVALID, "state shapes differ");
+    if (step != RT3D_STEP_INIT && (in->t == out->t || in->r == out->r || in->cnt == out->cnt))
+        return fail(c, RT3D_E_INVALID, "in and out alias");
+    const bool needs_csr = step == RT3D_STEP_INIT || step == RT3D_STEP_DEPTH || step == RT3D_STEP_INTENSITY ||
+                           step == RT3D_STEP_BKG || step == RT3D_STEP_ITERATION;
+    if (needs_csr && (!off || !ent)) return fail(c, RT3D_E_INVALID, "off/ent is NULL");
+    if (!shape_ok(out->frames, out->rows, out->cols)) return fail(c, RT3D_E_INVALID, "bad state shape");
+    const Shape sh = shape_of(out->frames, out->rows, out->cols);
+    hipStream_t st = (hipStream_t)hip_stream;
+    const DevModel m = dev_model(c);
+    const DevParams p = dev_params(c);
+    DevState O = dev_state(out);
+    switch (step) {
+    case RT3D_STEP_INIT:
+        RT3D_HIP(c, launch_init(m, p, sh, off, ent, gain, O, nullptr, st));
+        RT3D_HIP(c, launch_init_normals(p, sh, O, st));
+        return RT3D_OK;
+    case RT3D_STEP_APSS:
+        RT3D_HIP(c, launch_apss(m, p, sh, dev_state(in), O, st));
+        return RT3D_OK;
+    case RT3D_STEP_IFILTER:
+        RT3D_HIP(c, launch_ifilter(p, sh, dev_state(in), O, st));
+        return RT3D_OK;
+    default:
+        break;
+    }
+    if (step < 0 || step > RT3D_STEP_ITERATION) return fail(c, RT3D_E_INVALID, "unknown step");
+    RT3D_HIP(c, launch_copy_state(sh, dev_state(in), O, st));
+    switch (step) {
+    case RT3D_STEP_DEPTH:
+        RT3D_HIP(c, launch_depth_step(m, p, sh, off, ent, gain, O, st));
+        return RT3D_OK;
+    case RT3D_STEP_MERGE:
+        RT3D_HIP(c, launch_merge(p, sh, O, st));
+        return RT3D_OK;
+    case RT3D_STEP_INTENSITY:
+        RT3D_HIP(c, launch_intensity_step(m, p, sh, off, ent, gain, O, st));
+        return RT3D_OK;
+    case RT3D_STEP_BKG:
+        RT3D_HIP(c, launch_bg_step(m, p, sh, off, ent, gain, O, st));
+        return RT3D_OK;
+    case RT3D_STEP_BFILTER: {
+        Workspace w;
+        rt3d_status s = need_ws(c, sh.P, w);
+        if (s != RT3D_OK) return s;
+        RT3D_HIP(c, launch_bfilter(c->d_bw, c->rb, sh, (float)c->p.b_min, O.b, w.btmp, st));
+        return RT3D_OK;
+    }
+    case RT3D_STEP_ITERATION: {
+        Workspace w;
+        rt3d_status s = need_ws(c, sh.P, w);
+        if (s != RT3D_OK) return s;
+        return iterate(c, sh, off, ent, gain, O, w.B, w.btmp, st);
+    }
+    default:
+        return fail(c, RT3D_E_INVALID, "unknown step");
+    }
+}
+
+rt3d_status rt3d_debug_gradients(rt3d_ctx* c, const uint32_t* off, const uint32_t* ent, const float* gain,
+                                 const rt3d_state* s, float* gt, float* gr, float* gb, void* hip_stream)
+{
+    if (!c) return RT3D_E_INVALID;
+    if (!state_ok(s) || !off || !ent || !gt || !gr || !gb) return fail(c, RT3D_E_INVALID, "NULL argument");
+    if (!shape_ok(s->frames, s->rows, s->cols)) return fail(c, RT3D_E_INVALID, "bad state shape");
+    const Shape sh = shape_of(s->frames, s->rows, s->cols);
+    RT3D_HIP(c, launch_gradients(dev_model(c), dev_params(c), sh, off, ent, gain, dev_state(s), gt, gr, gb,
+                                 (hipStream_t)hip_stream));
+    return RT3D_OK;
+}
+
+}  // extern "C"

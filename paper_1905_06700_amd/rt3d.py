@@ -1,0 +1,302 @@
+"""ctypes binding of librt3d.so (the C ABI in include/rt3d.h).
+
+Argument marshalling only: every step runs in the library's HIP kernels.
+PyTorch supplies device memory (tensors) and the stream (the current torch
+stream).  Loading fails loudly when the library has not been built; there is
+no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librt3d.so")
+K_MAX = 4
+
+OK, E_INVALID, E_NOMEM, E_DEVICE, E_CAPACITY, E_STATE, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+DENOISE_NONE, DENOISE_APSS = 0, 1
+IN_HIST_U16, IN_PHOTON_CSR = 0, 1
+STEP_INIT, STEP_DEPTH, STEP_APSS, STEP_MERGE, STEP_INTENSITY, STEP_IFILTER, STEP_BKG, STEP_BFILTER, \
+    STEP_ITERATION = range(9)
+
+EXPORTS = ["rt3d_params_default", "rt3d_create", "rt3d_destroy", "rt3d_last_error", "rt3d_sigma2",
+           "rt3d_workspace_bytes", "rt3d_set_workspace", "rt3d_reconstruct", "rt3d_query",
+           "rt3d_debug_compact", "rt3d_debug_step", "rt3d_debug_gradients"]
+
+
+class Rt3dError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"rt3d status {status}: {msg}")
+        self.status = status
+
+
+class Params(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("n_iter", C.c_int32), ("k_max", C.c_int32),
+                ("k_init", C.c_int32), ("p_xy", C.c_double), ("dz", C.c_double),
+                ("h_apss", C.c_double), ("h_int", C.c_double), ("beta_t", C.c_double),
+                ("dmax", C.c_double), ("beta_r", C.c_double), ("beta_b", C.c_double),
+                ("r_min", C.c_double), ("d_merge", C.c_double), ("sigma_b", C.c_double),
+                ("b_min", C.c_double), ("sbr_guess", C.c_double), ("r_init", C.c_int32),
+                ("n_min", C.c_int32), ("kappa", C.c_double), ("w_nms", C.c_int32),
+                ("m_min", C.c_int32), ("denoiser", C.c_int32)]
+
+
+class Input(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("kind", C.c_int32), ("frames", C.c_uint32),
+                ("rows", C.c_uint32), ("cols", C.c_uint32), ("hist", C.c_void_p),
+                ("off", C.c_void_p), ("ent", C.c_void_p), ("gain", C.c_void_p)]
+
+
+class Output(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("capacity", C.c_uint32), ("pt_off", C.c_void_p),
+                ("depth", C.c_void_p), ("intensity", C.c_void_p), ("normal", C.c_void_p),
+                ("background", C.c_void_p)]
+
+
+class State(C.Structure):
+    _fields_ = [("frames", C.c_uint32), ("rows", C.c_uint32), ("cols", C.c_uint32),
+                ("t", C.c_void_p), ("r", C.c_void_p), ("n", C.c_void_p), ("cnt", C.c_void_p),
+                ("b", C.c_void_p)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("device_error", C.c_int32),
+                ("entries", C.c_uint64), ("points", C.c_uint64)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(or python paper_1905_06700_amd/build.py)")
+        L = C.CDLL(LIB_PATH)
+        vp, st = C.c_void_p, C.c_int32
+        L.rt3d_params_default.argtypes = [C.POINTER(Params)]
+        L.rt3d_create.argtypes = [C.POINTER(C.c_double), C.c_uint32, C.c_int32, C.c_uint32,
+                                  C.POINTER(Params), C.POINTER(vp)]
+        L.rt3d_create.restype = st
+        L.rt3d_destroy.argtypes = [vp]
+        L.rt3d_last_error.argtypes = [vp]
+        L.rt3d_last_error.restype = C.c_char_p
+        L.rt3d_sigma2.argtypes = [vp]
+        L.rt3d_sigma2.restype = C.c_double
+        L.rt3d_workspace_bytes.argtypes = [vp, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint64]
+        L.rt3d_workspace_bytes.restype = C.c_size_t
+        L.rt3d_set_workspace.argtypes = [vp, vp, C.c_size_t, C.c_uint32, C.c_uint32, C.c_uint32,
+                                         C.c_uint64]
+        L.rt3d_set_workspace.restype = st
+        L.rt3d_reconstruct.argtypes = [vp, C.POINTER(Input), C.POINTER(Output), vp]
+        L.rt3d_reconstruct.restype = st
+        L.rt3d_query.argtypes = [vp, vp, C.POINTER(Stats)]
+        L.rt3d_query.restype = st
+        L.rt3d_debug_compact.argtypes = [vp, vp, C.c_uint32, vp, vp, C.c_uint64, vp]
+        L.rt3d_debug_compact.restype = st
+        L.rt3d_debug_step.argtypes = [vp, C.c_int32, vp, vp, vp, C.POINTER(State), C.POINTER(State), vp]
+        L.rt3d_debug_step.restype = st
+        L.rt3d_debug_gradients.argtypes = [vp, vp, vp, vp, C.POINTER(State), vp, vp, vp, vp]
+        L.rt3d_debug_gradients.restype = st
+        _lib = L
+    return _lib
+
+
+def default_params(**kw) -> Params:
+    p = Params()
+    lib().rt3d_params_default(C.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k) or k == "struct_size":
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+@dataclass
+class DeviceState:
+    """Slot-major point state on the device (see rt3d_state)."""
+    frames: int
+    rows: int
+    cols: int
+    t: torch.Tensor      # float64 [K_MAX, P]
+    r: torch.Tensor      # float32 [K_MAX, P]
+    n: torch.Tensor      # float32 [3, K_MAX, P]
+    cnt: torch.Tensor    # uint8 [P]
+    b: torch.Tensor      # float32 [P]
+
+    @classmethod
+    def empty(cls, frames, rows, cols, device="cuda"):
+        P = frames * rows * cols
+        return cls(frames, rows, cols,
+                   torch.zeros(K_MAX, P, dtype=torch.float64, device=device),
+                   torch.zeros(K_MAX, P, dtype=torch.float32, device=device),
+                   torch.zeros(3, K_MAX, P, dtype=torch.float32, device=device),
+                   torch.zeros(P, dtype=torch.uint8, device=device),
+                   torch.zeros(P, dtype=torch.float32, device=device))
+
+    def c(self) -> State:
+        for x in (self.t, self.r, self.n, self.cnt, self.b):
+            assert x.is_cuda and x.is_contiguous()
+        return State(self.frames, self.rows, self.cols, self.t.data_ptr(), self.r.data_ptr(),
+                     self.n.data_ptr(), self.cnt.data_ptr(), self.b.data_ptr())
+
+
+@dataclass
+class Result:
+    pt_off: torch.Tensor     # uint32-valued int64 view [P+1] (stored as int32 on device)
+    depth: torch.Tensor      # float64 [capacity]
+    intensity: torch.Tensor  # float32 [capacity]
+    normal: torch.Tensor     # float32 [capacity, 3]
+    background: torch.Tensor  # float32 [P]
+
+
+class Context:
+    """One rt3d context: an IRF, a bin count and parameters."""
+
+    def __init__(self, irf, bins: int, origin: int = -1, **params):
+        self.params = default_params(**params)
+        irf = [float(x) for x in irf]
+        arr = (C.c_double * len(irf))(*irf)
+        h = C.c_void_p()
+        s = lib().rt3d_create(arr, len(irf), int(origin), int(bins), C.byref(self.params), C.byref(h))
+        if s != OK:
+            raise Rt3dError(s, "rt3d_create failed")
+        self._h = h
+        self.bins = int(bins)
+        self._ws = None
+        self._ws_shape = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.rt3d_destroy(h)
+            self._h = None
+
+    def _check(self, s):
+        if s != OK:
+            raise Rt3dError(s, lib().rt3d_last_error(self._h).decode())
+
+    @property
+    def sigma2(self) -> float:
+        return lib().rt3d_sigma2(self._h)
+
+    def workspace(self, frames: int, rows: int, cols: int, max_entries: int):
+        """Allocate (torch) and bind a workspace for up to this batch shape."""
+        shape = (frames, rows, cols, max_entries)
+        if self._ws_shape == shape:
+            return
+        nb = lib().rt3d_workspace_bytes(self._h, frames, rows, cols, max_entries)
+        self._ws = torch.empty(nb + 256, dtype=torch.uint8, device="cuda")
+        base = self._ws.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        self._check(lib().rt3d_set_workspace(self._h, C.c_void_p(aligned), nb, frames, rows, cols,
+                                             max_entries))
+        self._ws_shape = shape
+
+    def query(self) -> Stats:
+        st = Stats()
+        st.struct_size = C.sizeof(Stats)
+        self._check(lib().rt3d_query(self._h, _stream(), C.byref(st)))
+        return st
+
+    # -- whole reconstruction ------------------------------------------------
+    def make_output(self, P: int, capacity: int | None = None, normals: bool = True) -> Result:
+        cap = P * K_MAX if capacity is None else capacity
+        dev = "cuda"
+        return Result(torch.zeros(P + 1, dtype=torch.int32, device=dev),
+                      torch.zeros(cap, dtype=torch.float64, device=dev),
+                      torch.zeros(cap, dtype=torch.float32, device=dev),
+                      torch.zeros(cap, 3, dtype=torch.float32, device=dev) if normals else None,
+                      torch.zeros(P, dtype=torch.float32, device=dev))
+
+    def reconstruct_into(self, out: Result, frames: int, rows: int, cols: int, hist=None, off=None,
+                         ent=None, gain=None):
+        """Enqueue one reconstruction on the current torch stream (no sync)."""
+        inp = Input()
+        inp.struct_size = C.sizeof(Input)
+        inp.frames, inp.rows, inp.cols = frames, rows, cols
+        if hist is not None:
+            assert hist.dtype == torch.uint16 or hist.dtype == torch.int16
+            assert hist.is_cuda and hist.is_contiguous()
+            inp.kind = IN_HIST_U16
+            inp.hist = hist.data_ptr()
+        else:
+            inp.kind = IN_PHOTON_CSR
+            inp.off, inp.ent = off.data_ptr(), ent.data_ptr()
+        inp.gain = gain.data_ptr() if gain is not None else None
+        o = Output()
+        o.struct_size = C.sizeof(Output)
+        o.capacity = out.depth.numel()
+        o.pt_off, o.depth, o.intensity = out.pt_off.data_ptr(), out.depth.data_ptr(), out.intensity.data_ptr()
+        o.normal = out.normal.data_ptr() if out.normal is not None else None
+        o.background = out.background.data_ptr()
+        self._check(lib().rt3d_reconstruct(self._h, C.byref(inp), C.byref(o), _stream()))
+        return out
+
+    def reconstruct(self, hist, gain=None, max_entries=None) -> Result:
+        """hist: cuda uint16 [frames, rows, cols, bins] (or [rows, cols, bins])."""
+        if hist.dim() == 3:
+            hist = hist.unsqueeze(0)
+        F, R, Cc, T = hist.shape
+        assert T == self.bins
+        P = F * R * Cc
+        me = int(max_entries) if max_entries is not None else min(P * T, 2 ** 32 - 1)
+        self.workspace(F, R, Cc, me)
+        out = self.make_output(P)
+        self.reconstruct_into(out, F, R, Cc, hist=hist, gain=gain)
+        return out
+
+    # -- step-by-step entry points -----------------------------------------
+    def compact(self, hist, capacity=None):
+        hist = hist.contiguous()
+        T = hist.shape[-1]
+        P = hist.numel() // T
+        cap = int(capacity) if capacity is not None else max(1, P * T)
+        off = torch.zeros(P + 1, dtype=torch.int32, device="cuda")
+        ent = torch.zeros(cap, dtype=torch.int32, device="cuda")
+        if self._ws_shape is None or self._ws_shape[0] * self._ws_shape[1] * self._ws_shape[2] < P:
+            self.workspace(1, 1, P, 1)
+        self._check(lib().rt3d_debug_compact(self._h, _ptr(hist), P, _ptr(off), _ptr(ent), cap, _stream()))
+        return off, ent
+
+    def step(self, step: int, st_in: DeviceState | None, off=None, ent=None, gain=None,
+             shape=None) -> DeviceState:
+        if st_in is not None:
+            F, R, Cc = st_in.frames, st_in.rows, st_in.cols
+        else:
+            F, R, Cc = shape
+        out = DeviceState.empty(F, R, Cc)
+        cin = st_in.c() if st_in is not None else None
+        cout = out.c()
+        if step in (STEP_BFILTER, STEP_ITERATION):
+            P = F * R * Cc
+            if self._ws_shape is None or self._ws_shape[0] * self._ws_shape[1] * self._ws_shape[2] < P:
+                self.workspace(F, R, Cc, 1)
+        self._check(lib().rt3d_debug_step(self._h, step, _ptr(off), _ptr(ent), _ptr(gain),
+                                          C.byref(cin) if cin is not None else None, C.byref(cout),
+                                          _stream()))
+        return out
+
+    def gradients(self, st: DeviceState, off, ent, gain=None):
+        P = st.frames * st.rows * st.cols
+        gt = torch.zeros(K_MAX, P, dtype=torch.float32, device="cuda")
+        gr = torch.zeros(K_MAX, P, dtype=torch.float32, device="cuda")
+        gb = torch.zeros(P, dtype=torch.float32, device="cuda")
+        cs = st.c()
+        self._check(lib().rt3d_debug_gradients(self._h, _ptr(off), _ptr(ent), _ptr(gain), C.byref(cs),
+                                               _ptr(gt), _ptr(gr), _ptr(gb), _stream()))
+        return gt, gr, gb

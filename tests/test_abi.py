@@ -34,7 +34,7 @@ def test_struct_sizes_match_header(L):
     from paper_1905_06700_amd import rt3d
     p = rt3d.default_params()
     assert p.struct_size == C.sizeof(rt3d.Params)
-    assert p.n_iter == 20 and p.k_max == 4 and p.upsample == 32 and p.denoiser == rt3d.DENOISE_APSS
+    assert p.n_iter == 20 and p.k_max == 4 and p.beta_t == 0.5 and p.denoiser == rt3d.DENOISE_APSS
 
 
 def test_create_rejects_bad_arguments_on_host(L):
@@ -54,7 +54,7 @@ def test_create_rejects_bad_arguments_on_host(L):
     assert create([1.0, 2.0], 100, origin=2) == rt3d.E_INVALID  # origin outside the IRF
     bad = rt3d.default_params(k_max=5)
     assert create([1.0], 100, params=bad) == rt3d.E_INVALID
-    bad = rt3d.default_params(upsample=24)
+    bad = rt3d.default_params(h_apss=0.0)
     assert create([1.0], 100, params=bad) == rt3d.E_INVALID
     bad = rt3d.default_params(denoiser=7)
     assert create([1.0], 100, params=bad) == rt3d.E_UNSUPPORTED
