@@ -183,6 +183,28 @@ rt3d_status rt3d_reconstruct(rt3d_ctx* ctx, const rt3d_input* in, rt3d_output* o
  * counts of the last calls.  Returns the sticky device error (or OK). */
 rt3d_status rt3d_query(rt3d_ctx* ctx, void* hip_stream, rt3d_stats* st);
 
+/* Kernel timing.  rt3d_profile(ctx, id) makes every later launch of kernel
+ * group `id` (RT3D_KERNEL_*) on any stream be bracketed by HIP events
+ * recorded on that stream; id < 0 switches timing off.  rt3d_profile_read
+ * waits for the recorded events, returns the summed milliseconds and the
+ * number of timed launches, and clears them.  The events are created once and
+ * reused (at most 4096 launches are kept between reads; later ones are not
+ * timed).  E_INVALID for an unknown id, E_DEVICE on a HIP failure. */
+#define RT3D_KERNEL_COMPACT   0   /* histogram -> active bins (count, scan, fill) */
+#define RT3D_KERNEL_INIT      1   /* log-matched-filter initialisation */
+#define RT3D_KERNEL_NORMALS   2   /* initial normals */
+#define RT3D_KERNEL_DEPTH     3   /* depth gradient step */
+#define RT3D_KERNEL_APSS      4   /* APSS */
+#define RT3D_KERNEL_MERGE     5   /* in-pixel merge */
+#define RT3D_KERNEL_INTENSITY 6   /* intensity gradient step */
+#define RT3D_KERNEL_IFILTER   7   /* intensity low-pass and threshold */
+#define RT3D_KERNEL_BKG       8   /* background gradient step */
+#define RT3D_KERNEL_BFILTER   9   /* background filter (row and column passes) */
+#define RT3D_KERNEL_OUTPUT   10   /* output packing (count, scan, pack) */
+#define RT3D_KERNEL_COUNT    11
+rt3d_status rt3d_profile(rt3d_ctx* ctx, int32_t id);
+rt3d_status rt3d_profile_read(rt3d_ctx* ctx, double* total_ms, uint64_t* launches);
+
 /* ---------------------------------------------------------------------------
  * Step-by-step entry points (each row of the loop alone, for testing and
  * for callers composing their own loop).  All asynchronous on hip_stream.

@@ -12,45 +12,95 @@
 // only.  Intensity = own photons in the claimed bins minus background over
 // the IRF mass there; background = own photons outside the claimed bins.
 //
-// Mapping: one wavefront per pixel.  The pooled photon list lives in LDS
-// (dense pooled histogram built with LDS integer atomics, then compacted in
-// bin order); each lane scores a contiguous run of tau with a two-pointer
-// sweep over the list, and the wave reduces (score, tau).
+// Mapping: one wavefront per pixel, four pixels per workgroup.  The argmax
+// over tau is an exact branch and bound over blocks of 64 consecutive tau
+// (one tau per lane): an upper bound of every block's best score,
+// sum over pooled photons of z * max q over the lags the block can see, is
+// scattered into LDS with 64-bit integer atomics; blocks are then scored
+// exactly in decreasing bound order until no remaining bound can beat (or tie
+// at a smaller tau) the best score found.  The bound only counts photons, so
+// it stays valid after photons are claimed.  Only a few blocks per pixel are
+// ever scored exactly, so the cost follows the active bins, not T.
 #include "rt3d_dev.h"
 
 namespace rt3d {
 
-struct Peak {
-    int t, a, c, w;   // depth, window [a, c], bins claimed
+// Accepted peaks of one pixel, held in registers (every index below is a
+// compile-time constant after unrolling, so nothing spills to scratch).
+struct Peaks {
+    int t[KM], a[KM], c[KM], w[KM];
+    int n;
+
+    // first accepted peak whose window [a, c] holds bin tb, or -1
+    __device__ __forceinline__ int owner(int tb) const
+    {
+        int ow = -1;
+#pragma unroll
+        for (int j = KM - 1; j >= 0; --j)
+            if (j < n && tb >= a[j] && tb <= c[j]) ow = j;
+        return ow;
+    }
+
+    __device__ __forceinline__ bool suppressed(int tau, int wnms) const
+    {
+        bool sup = false;
+#pragma unroll
+        for (int j = 0; j < KM; ++j)
+            if (j < n && abs(tau - t[j]) <= wnms) sup = true;
+        return sup;
+    }
+
+    __device__ __forceinline__ void push(int tt, int aa, int cc, int ww)
+    {
+#pragma unroll
+        for (int j = 0; j < KM; ++j)
+            if (j == n) {
+                t[j] = tt;
+                a[j] = aa;
+                c[j] = cc;
+                w[j] = ww;
+            }
+        ++n;
+    }
 };
 
-__device__ __forceinline__ int owner_of(int tb, const Peak* pk, int n)
+// Orders LDS traffic between the lanes of one wavefront.
+__device__ __forceinline__ void wave_sync()
 {
-    for (int j = 0; j < n; ++j)
-        if (tb >= pk[j].a && tb <= pk[j].c) return j;
-    return -1;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ int lower_bound_u16(const uint16_t* a, int n, int key)
+// max q[lo..hi] from the range-maximum table (lo <= hi, both in [0, L)).
+__device__ __forceinline__ int q_range_max(const DevModel& m, int lo, int hi)
 {
-    int lo = 0, hi = n;
-    while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        if ((int)a[mid] < key) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
+    const int len = hi - lo + 1;
+    const int l = 31 - __clz(len);
+    const int a = m.qst[l * m.L + lo], b = m.qst[l * m.L + hi - (1 << l) + 1];
+    return a > b ? a : b;
 }
 
-__global__ __launch_bounds__(64) void k_init(DevModel m, DevParams p, Shape sh, const uint32_t* __restrict__ off,
-                                             const uint32_t* __restrict__ ent, const float* __restrict__ gain,
-                                             DevState s)
+__device__ __forceinline__ int popc_ballot(bool x) { return __popcll(__ballot(x)); }
+
+constexpr int INIT_WAVES = 4;
+
+__global__ __launch_bounds__(64 * INIT_WAVES) void k_init(DevModel m, DevParams p, Shape sh,
+                                                          const uint32_t* __restrict__ off,
+                                                          const uint32_t* __restrict__ ent,
+                                                          const float* __restrict__ gain, DevState s)
 {
-    extern __shared__ uint32_t smem[];
-    const long long pix = blockIdx.x;
+    extern __shared__ unsigned long long smem64[];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const long long P = sh.P;
-    const int lane = threadIdx.x;
+    const long long pix = (long long)blockIdx.x * INIT_WAVES + wv;
+    if (pix >= P) return;                       // whole wavefront; no workgroup barriers below
     const int T = m.T, L = m.L, o = m.o;
+    const int nb = (T + 63) >> 6;
+    const int R = p.r_init, side = 2 * R + 1;
+    unsigned long long* ub = smem64 + (size_t)wv * (nb + side * side);
+    uint2* lists = reinterpret_cast<uint2*>(ub + nb);
+
     if (lane < KM) {
         s.t[lane * P + pix] = 0.0;
         s.r[lane * P + pix] = 0.f;
@@ -70,111 +120,123 @@ __global__ __launch_bounds__(64) void k_init(DevModel m, DevParams p, Shape sh, 
     const long long fr = pix / per_frame;
     const int i = (int)((pix / sh.cols) % sh.rows), j = (int)(pix % sh.cols);
 
-    uint32_t* lz = smem;                           // [T] pooled counts of the list
-    uint16_t* lt = (uint16_t*)(smem + T);          // [T] bins of the list
-    uint32_t* agg = smem + T + (T + 1) / 2;        // [T] dense pooled histogram
-    int nlist;
-    if (p.r_init > 0) {
-        for (int tb = lane; tb < T; tb += 64) agg[tb] = 0;
-        __syncthreads();
-        for (int i2 = i - p.r_init; i2 <= i + p.r_init; ++i2) {
-            if (i2 < 0 || i2 >= sh.rows) continue;
-            for (int j2 = j - p.r_init; j2 <= j + p.r_init; ++j2) {
-                if (j2 < 0 || j2 >= sh.cols) continue;
-                long long pp = (fr * sh.rows + i2) * sh.cols + j2;
-                for (uint32_t e = off[pp] + lane; e < off[pp + 1]; e += 64) {
-                    uint32_t v = ent[e];
-                    if (ent_bin(v) < T) atomicAdd(&agg[ent_bin(v)], (uint32_t)ent_cnt(v));
-                }
-            }
+    // pooled photon lists: the CSR ranges of the window's pixels
+    int npl = 0;
+    for (int i2 = i - R; i2 <= i + R; ++i2) {
+        if (i2 < 0 || i2 >= sh.rows) continue;
+        for (int j2 = j - R; j2 <= j + R; ++j2) {
+            if (j2 < 0 || j2 >= sh.cols) continue;
+            const long long pp = (fr * sh.rows + i2) * sh.cols + j2;
+            if (lane == 0) lists[npl] = make_uint2(off[pp], off[pp + 1]);
+            ++npl;
         }
-        __syncthreads();
-        // compact the dense histogram in bin order: lane l owns bins [l*C, (l+1)*C)
-        const int C = (T + 63) / 64;
-        const int b0 = lane * C, b1 = min(T, b0 + C);
-        uint32_t c = 0;
-        for (int tb = b0; tb < b1; ++tb) c += agg[tb] != 0;
-        uint32_t inc = wave_incl_scan(c);
-        nlist = __shfl(inc, 63, 64);
-        uint32_t pos = inc - c;
-        for (int tb = b0; tb < b1; ++tb) {
-            uint32_t z = agg[tb];
-            if (z) {
-                lt[pos] = (uint16_t)tb;
-                lz[pos] = z;
-                ++pos;
-            }
-        }
-        __syncthreads();
-    } else {
-        const uint32_t e0 = off[pix];
-        nlist = min((int)(off[pix + 1] - e0), T);
-        for (int e = lane; e < nlist; e += 64) {
-            uint32_t v = ent[e0 + e];
-            lt[e] = (uint16_t)ent_bin(v);
-            lz[e] = (uint32_t)ent_cnt(v);
-        }
-        __syncthreads();
     }
-    long long ntot = 0;
-    for (int e = lane; e < nlist; e += 64) ntot += lz[e];
-    ntot = wave_sum(ntot);
+    for (int b = lane; b < nb; b += 64) ub[b] = 0ull;
+    wave_sync();
 
-    Peak pk[KM];
-    int npk = 0;
-    const int C = (T + 63) / 64;
-    const int tau0 = lane * C, tau1 = min(T, tau0 + C);
+    // photon total and per-block score bounds
+    long long ntot = 0;
+    for (int l = 0; l < npl; ++l) {
+        const uint2 rg = lists[l];
+        for (uint32_t e = rg.x + lane; e < rg.y; e += 64) {
+            const uint32_t v = ent[e];
+            const int t = ent_bin(v), z = ent_cnt(v);
+            if (t >= T) continue;
+            ntot += z;
+            const int tlo = max(0, t + o - L + 1), thi = min(T - 1, t + o);
+            for (int b = tlo >> 6; b <= (thi >> 6); ++b) {
+                const int a0 = max(tlo, b << 6), a1 = min(thi, (b << 6) + 63);
+                const int qm = q_range_max(m, t - a1 + o, t - a0 + o);
+                atomicAdd(&ub[b], (unsigned long long)z * (unsigned long long)qm);
+            }
+        }
+    }
+    ntot = wave_sum(ntot);
+    wave_sync();
+
+    Peaks pk;
+    pk.n = 0;
+#pragma unroll
+    for (int j = 0; j < KM; ++j) pk.t[j] = pk.a[j] = pk.c[j] = pk.w[j] = 0;
     const double k2 = p.kappa * p.kappa;
     for (int it = 0; it < p.k_init; ++it) {
-        // lane-local best over its run of tau
-        long long bestv = -1;
+        long long best = -1;
         int bestt = 0x7fffffff;
-        if (tau0 < tau1) {
-            int lo = lower_bound_u16(lt, nlist, tau0 - o);
-            int hi = lo;
-            for (int tau = tau0; tau < tau1; ++tau) {
-                const int wlo = tau - o, whi = tau - o + L - 1;
-                while (lo < nlist && (int)lt[lo] < wlo) ++lo;
-                if (hi < lo) hi = lo;
-                while (hi < nlist && (int)lt[hi] <= whi) ++hi;
-                bool sup = false;
-                for (int q = 0; q < npk; ++q) sup |= abs(tau - pk[q].t) <= m.wnms;
-                if (sup) continue;
-                long long sc = 0;
-                for (int x = lo; x < hi; ++x) {
-                    int tb = lt[x];
-                    const int lag = tb - tau + o;
-                    if ((unsigned)lag >= (unsigned)L || owner_of(tb, pk, npk) >= 0) continue;
-                    sc += (long long)lz[x] * (long long)m.q[lag];
-                }
-                if (sc > bestv) {
-                    bestv = sc;
-                    bestt = tau;
+        uint32_t done = 0;                      // bit q: block lane + 64 q scored in this round
+        while (true) {
+            // unscored block with the largest bound (smallest index on ties)
+            unsigned long long bu = 0;
+            int bb = 0x7fffffff;
+            for (int q = 0; lane + 64 * q < nb; ++q) {
+                if ((done >> q) & 1u) continue;
+                const unsigned long long u = ub[lane + 64 * q];
+                if (bb == 0x7fffffff || u > bu) {
+                    bu = u;
+                    bb = lane + 64 * q;
                 }
             }
-        }
-        // wave argmax: larger score, then smaller tau
 #pragma unroll
-        for (int d = 32; d >= 1; d >>= 1) {
-            long long ov = __shfl_xor(bestv, d, 64);
-            int ot = __shfl_xor(bestt, d, 64);
-            if (ov > bestv || (ov == bestv && ot < bestt)) {
-                bestv = ov;
-                bestt = ot;
+            for (int d = 32; d >= 1; d >>= 1) {
+                const unsigned long long ou = __shfl_xor(bu, d, 64);
+                const int ob = __shfl_xor(bb, d, 64);
+                if (ob != 0x7fffffff && (bb == 0x7fffffff || ou > bu || (ou == bu && ob < bb))) {
+                    bu = ou;
+                    bb = ob;
+                }
+            }
+            if (bb == 0x7fffffff) break;
+            if ((long long)bu < best || ((long long)bu == best && (bb << 6) > bestt)) break;
+            if (lane == (bb & 63)) done |= 1u << (bb >> 6);
+            // exact scores of the block's 64 tau
+            const int tau = (bb << 6) + lane;
+            const int wlo = (bb << 6) - o, whi = (bb << 6) + 63 - o + L - 1;
+            long long sc = 0;
+            for (int l = 0; l < npl; ++l) {
+                const uint2 rg = lists[l];
+                int c0 = 0, c1 = 0;
+                for (uint32_t e0 = rg.x; e0 < rg.y; e0 += 64) {
+                    const uint32_t e = e0 + lane;
+                    const int t = e < rg.y ? ent_bin(ent[e]) : 0x7fffffff;
+                    c0 += popc_ballot(t < wlo);
+                    c1 += popc_ballot(t <= whi);
+                }
+                for (uint32_t x = rg.x + c0; x < rg.x + c1; ++x) {
+                    const uint32_t v = ent[x];
+                    const int tb = ent_bin(v);
+                    if (pk.owner(tb) >= 0) continue;
+                    const int lag = tb - tau + o;
+                    if ((unsigned)lag < (unsigned)L) sc += (long long)ent_cnt(v) * (long long)m.q[lag];
+                }
+            }
+            const bool valid = tau < T && !pk.suppressed(tau, m.wnms);
+            long long sv = valid ? sc : -1;
+            int st = valid ? tau : 0x7fffffff;
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) {
+                const long long ov = __shfl_xor(sv, d, 64);
+                const int ot = __shfl_xor(st, d, 64);
+                if (ov > sv || (ov == sv && ot < st)) {
+                    sv = ov;
+                    st = ot;
+                }
+            }
+            if (st != 0x7fffffff && (sv > best || (sv == best && st < bestt))) {
+                best = sv;
+                bestt = st;
             }
         }
-        if (bestt == 0x7fffffff) break;      // every tau suppressed
+        if (bestt == 0x7fffffff) break;          // every tau suppressed
         const int a = max(0, bestt - m.wl), c = min(T - 1, bestt + m.wr);
         int win = 0;
-        for (int tb = a + lane; tb <= c; tb += 64) win += owner_of(tb, pk, npk) < 0;
+        for (int tb = a + lane; tb <= c; tb += 64) win += pk.owner(tb) < 0;
         win = wave_sum(win);
         long long nwin = 0;
-        {
-            int x0 = lower_bound_u16(lt, nlist, a);
-            for (int x = x0 + lane; x < nlist; x += 64) {
-                int tb = lt[x];
-                if (tb > c) break;
-                if (owner_of(tb, pk, npk) < 0) nwin += lz[x];
+        for (int l = 0; l < npl; ++l) {
+            const uint2 rg = lists[l];
+            for (uint32_t e = rg.x + lane; e < rg.y; e += 64) {
+                const uint32_t v = ent[e];
+                const int tb = ent_bin(v);
+                if (tb >= a && tb <= c && pk.owner(tb) < 0) nwin += ent_cnt(v);
             }
         }
         nwin = wave_sum(nwin);
@@ -182,22 +244,19 @@ __global__ __launch_bounds__(64) void k_init(DevModel m, DevParams p, Shape sh, 
         const double d = (double)nwin - bw;
         const bool accept = win > 0 && nwin >= p.n_min && d >= 0.0 && d * d >= k2 * bw;
         if (!accept) break;
-        pk[npk].t = bestt;
-        pk[npk].a = a;
-        pk[npk].c = c;
-        pk[npk].w = win;
-        ++npk;
+        pk.push(bestt, a, c, win);
     }
+    const int npk = pk.n;
 
     // own photons: total and per claimed window
     const uint32_t e0 = off[pix], e1 = off[pix + 1];
     long long zp = 0;
     long long nown[KM] = {0, 0, 0, 0};
     for (uint32_t e = e0 + lane; e < e1; e += 64) {
-        uint32_t v = ent[e];
-        int z = ent_cnt(v);
+        const uint32_t v = ent[e];
+        const int z = ent_cnt(v);
         zp += z;
-        int ow = owner_of(ent_bin(v), pk, npk);
+        const int ow = pk.owner(ent_bin(v));
 #pragma unroll
         for (int k = 0; k < KM; ++k)
             if (ow == k) nown[k] += z;
@@ -209,45 +268,56 @@ __global__ __launch_bounds__(64) void k_init(DevModel m, DevParams p, Shape sh, 
         nown[k] = wave_sum(nown[k]);
         if (k < npk) {
             double hs = 0.0;
-            for (int tb = pk[k].a + lane; tb <= pk[k].c; tb += 64) {
-                int idx = tb - pk[k].t + o;
-                if (owner_of(tb, pk, npk) == k && idx >= 0 && idx < L) hs += m.hbar[idx];
+            for (int tb = pk.a[k] + lane; tb <= pk.c[k]; tb += 64) {
+                const int idx = tb - pk.t[k] + o;
+                if (pk.owner(tb) == k && idx >= 0 && idx < L) hs += m.hbar[idx];
             }
             H[k] = wave_sum(hs);
         }
     }
     if (lane != 0) return;
     long long sum_n = 0, sum_w = 0;
-    for (int k = 0; k < npk; ++k) {
-        sum_n += nown[k];
-        sum_w += pk[k].w;
-    }
+#pragma unroll
+    for (int k = 0; k < KM; ++k)
+        if (k < npk) {
+            sum_n += nown[k];
+            sum_w += pk.w[k];
+        }
     long long num = zp - sum_n;
     if (num < 0) num = 0;
     const long long den = (long long)T - sum_w;
+    // kept peaks, then ascending depth (distinct depths; a fixed sorting network)
     int kt[KM];
     float kr[KM];
-    int nk = 0;
-    for (int k = 0; k < npk; ++k) {
-        const long long w = pk[k].w;
-        const bool keep = den > 0 ? (nown[k] * den > num * w) : (nown[k] > 0);
-        if (!keep || !(H[k] > 0.0)) continue;
+    bool kk[KM];
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+        const long long w = pk.w[k];
+        const bool keep = k < npk && (den > 0 ? (nown[k] * den > num * w) : (nown[k] > 0)) && H[k] > 0.0;
         const double excess = den > 0 ? (double)nown[k] - (double)num * (double)w / (double)den
                                       : (double)nown[k];
-        kt[nk] = pk[k].t;
-        kr[nk] = (float)(excess / ((double)G * H[k]));
-        ++nk;
+        kk[k] = keep;
+        kt[k] = keep ? pk.t[k] : 0x7fffffff;
+        kr[k] = keep ? (float)(excess / ((double)G * H[k])) : 0.f;
     }
-    for (int x = 1; x < nk; ++x)
-        for (int y = x; y > 0 && kt[y] < kt[y - 1]; --y) {
-            int tt = kt[y]; kt[y] = kt[y - 1]; kt[y - 1] = tt;
-            float rr = kr[y]; kr[y] = kr[y - 1]; kr[y - 1] = rr;
-        }
+#pragma unroll
+    for (int x = 0; x < KM; ++x)
+#pragma unroll
+        for (int y = 0; y + 1 < KM - x; ++y)
+            if (kt[y + 1] < kt[y]) {
+                const int tt = kt[y]; kt[y] = kt[y + 1]; kt[y + 1] = tt;
+                const float rr = kr[y]; kr[y] = kr[y + 1]; kr[y + 1] = rr;
+            }
+    int nk = 0;
+#pragma unroll
+    for (int k = 0; k < KM; ++k) nk += kk[k] ? 1 : 0;
     if (nk > p.k_max) nk = p.k_max;
-    for (int k = 0; k < nk; ++k) {
-        s.t[k * P + pix] = (double)kt[k];
-        s.r[k * P + pix] = kr[k];
-    }
+#pragma unroll
+    for (int k = 0; k < KM; ++k)
+        if (k < nk) {
+            s.t[k * P + pix] = (double)kt[k];
+            s.r[k * P + pix] = kr[k];
+        }
     s.cnt[pix] = (uint8_t)nk;
     const double bown = den > 0 ? (double)num / (double)den : 0.0;
     const double b0 = bown / (double)G;
@@ -318,10 +388,12 @@ __global__ __launch_bounds__(256) void k_init_normals(DevParams p, Shape sh, Dev
     }
 }
 
-size_t init_lds_bytes(int T)
+// LDS bytes of one init workgroup: per wavefront, one 64-bit bound per block of
+// 64 tau and one CSR range per pooled pixel.
+size_t init_lds_bytes(int T, int r_init)
 {
-    // lz[T] + lt[T] (uint16, padded to words) + agg[T]
-    return sizeof(uint32_t) * ((size_t)T + (size_t)(T + 1) / 2 + (size_t)T);
+    const size_t nb = (size_t)(T + 63) / 64, side = 2 * (size_t)r_init + 1;
+    return INIT_WAVES * (nb + side * side) * sizeof(unsigned long long);
 }
 
 hipError_t launch_init(const DevModel& m, const DevParams& p, const Shape& sh, const uint32_t* off,
@@ -329,8 +401,9 @@ hipError_t launch_init(const DevModel& m, const DevParams& p, const Shape& sh, c
 {
     (void)err;
     if (sh.P == 0) return hipSuccess;
-    size_t lds = init_lds_bytes(m.T);
-    hipLaunchKernelGGL(k_init, dim3((unsigned)sh.P), dim3(64), lds, st, m, p, sh, off, ent, gain, s);
+    const size_t lds = init_lds_bytes(m.T, p.r_init);
+    const unsigned nblk = (unsigned)((sh.P + INIT_WAVES - 1) / INIT_WAVES);
+    hipLaunchKernelGGL(k_init, dim3(nblk), dim3(64 * INIT_WAVES), lds, st, m, p, sh, off, ent, gain, s);
     return hipGetLastError();
 }
 

@@ -68,8 +68,7 @@ __device__ __forceinline__ void accumulate(const DevModel& m, const PixPoints& q
         shp[k] = 0.f;
         ahp[k] = 0.f;
     }
-    for (uint32_t e = e0; e < e1; ++e) {
-        const uint32_t v = ent[e];
+    auto one = [&](uint32_t v) {
         const int tb = ent_bin(v);
         const float z = (float)ent_cnt(v);
         float h[KM], hp[KM];
@@ -93,7 +92,17 @@ __device__ __forceinline__ void accumulate(const DevModel& m, const PixPoints& q
                 if (ABS) ahp[k] = fmaf(zl, fabsf(hp[k]), ahp[k]);
             }
         }
+    };
+    // eight entries in flight per lane, then the tail
+    uint32_t e = e0;
+    for (; e + 8 <= e1; e += 8) {
+        uint32_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = ent[e + u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) one(v[u]);
     }
+    for (; e < e1; ++e) one(ent[e]);
 }
 
 __global__ __launch_bounds__(256) void k_depth_step(DevModel m, DevParams p, Shape sh,

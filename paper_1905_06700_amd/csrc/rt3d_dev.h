@@ -15,6 +15,7 @@ constexpr int KM = RT3D_K_MAX;
 struct DevModel {
     const float4*  cr;    // Catmull-Rom segment k-1 (samples k..k+1): cubic coefficients (c0, c1, c2, c3)
     const int32_t* q;     // log-matched-filter weights, 16 fractional bits
+    const int32_t* qst;   // range-maximum table of q: qst[l * L + k] = max q[k .. k + 2^l - 1]
     const double*  hbar;  // normalised IRF samples
     int   T, L, o;
     int   wl, wr;         // peak window half widths

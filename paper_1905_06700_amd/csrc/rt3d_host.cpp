@@ -14,7 +14,7 @@
 #include "rt3d_dev.h"
 
 namespace rt3d {
-size_t init_lds_bytes(int T);
+size_t init_lds_bytes(int T, int r_init);
 }
 
 using namespace rt3d;
@@ -30,6 +30,7 @@ struct rt3d_ctx {
     // device tables (owned)
     float4* d_cr = nullptr;
     int32_t* d_q = nullptr;
+    int32_t* d_qst = nullptr;
     double* d_hbar = nullptr;
     float* d_bw = nullptr;
     int rb = 0;
@@ -41,6 +42,10 @@ struct rt3d_ctx {
     // last call facts
     long long last_P = 0;
     bool last_compacted = false;
+    // kernel timing (rt3d_profile)
+    int prof_id = -1;
+    std::vector<hipEvent_t> prof_ev;   // start/end pairs
+    size_t prof_n = 0;                 // pairs recorded since the last read
     std::string err;
 };
 
@@ -100,6 +105,31 @@ rt3d_status hip_fail(rt3d_ctx* c, hipError_t e, const char* what)
     return fail(c, RT3D_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+constexpr size_t PROF_MAX = 4096;
+
+// Starts timing a launch of kernel group `id` when it is the profiled one.
+bool prof_begin(rt3d_ctx* c, int id, hipStream_t st, size_t& slot)
+{
+    if (c->prof_id != id || c->prof_n >= PROF_MAX) return false;
+    while (c->prof_ev.size() < 2 * (c->prof_n + 1)) {
+        hipEvent_t ev;
+        if (hipEventCreate(&ev) != hipSuccess) return false;
+        c->prof_ev.push_back(ev);
+    }
+    slot = c->prof_n++;
+    return hipEventRecord(c->prof_ev[2 * slot], st) == hipSuccess;
+}
+
+// Launch of kernel group `id`, timed when profiled.
+#define RT3D_LAUNCH(ctx, id, st, call)                                          \
+    do {                                                                        \
+        size_t slot_ = 0;                                                       \
+        const bool on_ = prof_begin(ctx, id, st, slot_);                        \
+        hipError_t e_ = (call);                                                 \
+        if (on_) (void)hipEventRecord((ctx)->prof_ev[2 * slot_ + 1], st);       \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, #call);                  \
+    } while (0)
+
 #define RT3D_HIP(ctx, call)                                      \
     do {                                                         \
         hipError_t e_ = (call);                                  \
@@ -111,6 +141,7 @@ DevModel dev_model(const rt3d_ctx* c)
     DevModel m{};
     m.cr = c->d_cr;
     m.q = c->d_q;
+    m.qst = c->d_qst;
     m.hbar = c->d_hbar;
     m.T = c->T;
     m.L = c->L;
@@ -211,20 +242,20 @@ rt3d_status iterate(rt3d_ctx* c, const Shape& sh, const uint32_t* off, const uin
 {
     const DevModel m = dev_model(c);
     const DevParams p = dev_params(c);
-    RT3D_HIP(c, launch_depth_step(m, p, sh, off, ent, gain, A, st));
+    RT3D_LAUNCH(c, RT3D_KERNEL_DEPTH, st, launch_depth_step(m, p, sh, off, ent, gain, A, st));
     DevState cur = A;
     if (c->p.denoiser == RT3D_DENOISE_APSS) {
-        RT3D_HIP(c, launch_apss(m, p, sh, A, B, st));
+        RT3D_LAUNCH(c, RT3D_KERNEL_APSS, st, launch_apss(m, p, sh, A, B, st));
         cur = B;
     } else {
         RT3D_HIP(c, launch_copy_state(sh, A, B, st));
         cur = B;
     }
-    RT3D_HIP(c, launch_merge(p, sh, cur, st));
-    RT3D_HIP(c, launch_intensity_step(m, p, sh, off, ent, gain, cur, st));
-    RT3D_HIP(c, launch_ifilter(p, sh, cur, A, st));
-    RT3D_HIP(c, launch_bg_step(m, p, sh, off, ent, gain, A, st));
-    RT3D_HIP(c, launch_bfilter(c->d_bw, c->rb, sh, (float)c->p.b_min, A.b, btmp, st));
+    RT3D_LAUNCH(c, RT3D_KERNEL_MERGE, st, launch_merge(p, sh, cur, st));
+    RT3D_LAUNCH(c, RT3D_KERNEL_INTENSITY, st, launch_intensity_step(m, p, sh, off, ent, gain, cur, st));
+    RT3D_LAUNCH(c, RT3D_KERNEL_IFILTER, st, launch_ifilter(p, sh, cur, A, st));
+    RT3D_LAUNCH(c, RT3D_KERNEL_BKG, st, launch_bg_step(m, p, sh, off, ent, gain, A, st));
+    RT3D_LAUNCH(c, RT3D_KERNEL_BFILTER, st, launch_bfilter(c->d_bw, c->rb, sh, (float)c->p.b_min, A.b, btmp, st));
     return RT3D_OK;
 }
 
@@ -277,8 +308,7 @@ rt3d_status rt3d_create(const double* irf, uint32_t irf_len, int32_t irf_origin,
     }
     if (!(sum > 0.0)) return RT3D_E_INVALID;
     if (irf_origin >= (int32_t)irf_len) return RT3D_E_INVALID;
-    if (p->r_init > 0 && init_lds_bytes((int)bins) > 65536) return RT3D_E_UNSUPPORTED;
-    if (init_lds_bytes((int)bins) > 65536) return RT3D_E_UNSUPPORTED;
+    if (init_lds_bytes((int)bins, p->r_init) > 65536) return RT3D_E_UNSUPPORTED;
 
     rt3d_ctx* c = new (std::nothrow) rt3d_ctx();
     if (!c) return RT3D_E_NOMEM;
@@ -363,6 +393,18 @@ rt3d_status rt3d_create(const double* irf, uint32_t irf_len, int32_t irf_origin,
     std::vector<int32_t> q(L);
     const double inv_eps = p->sbr_guess * (double)T;
     for (int k = 0; k < L; ++k) q[k] = (int32_t)std::llround(std::log1p(c->hbar[k] * inv_eps) * 65536.0);
+    // range-maximum table of q: level l holds max q[k .. k + 2^l - 1]
+    int nlev = 1;
+    while ((1 << nlev) <= L) ++nlev;
+    std::vector<int32_t> qst((size_t)nlev * L);
+    for (int k = 0; k < L; ++k) qst[k] = q[k];
+    for (int l = 1; l < nlev; ++l)
+        for (int k = 0; k < L; ++k) {
+            const int a = qst[(size_t)(l - 1) * L + k];
+            const int k2 = k + (1 << (l - 1));
+            const int b = k2 < L ? qst[(size_t)(l - 1) * L + k2] : a;
+            qst[(size_t)l * L + k] = std::max(a, b);
+        }
     // background filter taps
     std::vector<float> bw;
     if (p->sigma_b > 0.0) {
@@ -382,10 +424,12 @@ rt3d_status rt3d_create(const double* irf, uint32_t irf_len, int32_t irf_origin,
     hipError_t e = hipGetDevice(&c->device);
     if (e == hipSuccess) e = hipMalloc(&c->d_cr, sizeof(float4) * cr.size());
     if (e == hipSuccess) e = hipMalloc(&c->d_q, sizeof(int32_t) * q.size());
+    if (e == hipSuccess) e = hipMalloc(&c->d_qst, sizeof(int32_t) * qst.size());
     if (e == hipSuccess) e = hipMalloc(&c->d_hbar, sizeof(double) * L);
     if (e == hipSuccess) e = hipMalloc(&c->d_bw, sizeof(float) * bw.size());
     if (e == hipSuccess) e = hipMemcpy(c->d_cr, cr.data(), sizeof(float4) * cr.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->d_q, q.data(), sizeof(int32_t) * q.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->d_qst, qst.data(), sizeof(int32_t) * qst.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->d_hbar, c->hbar.data(), sizeof(double) * L, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->d_bw, bw.data(), sizeof(float) * bw.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
@@ -396,6 +440,30 @@ rt3d_status rt3d_create(const double* irf, uint32_t irf_len, int32_t irf_origin,
     return RT3D_OK;
 }
 
+rt3d_status rt3d_profile(rt3d_ctx* c, int32_t id)
+{
+    if (!c) return RT3D_E_INVALID;
+    if (id >= RT3D_KERNEL_COUNT) return fail(c, RT3D_E_INVALID, "unknown kernel id");
+    c->prof_id = id < 0 ? -1 : id;
+    return RT3D_OK;
+}
+
+rt3d_status rt3d_profile_read(rt3d_ctx* c, double* total_ms, uint64_t* launches)
+{
+    if (!c) return RT3D_E_INVALID;
+    double sum = 0.0;
+    for (size_t i = 0; i < c->prof_n; ++i) {
+        RT3D_HIP(c, hipEventSynchronize(c->prof_ev[2 * i + 1]));
+        float ms = 0.f;
+        RT3D_HIP(c, hipEventElapsedTime(&ms, c->prof_ev[2 * i], c->prof_ev[2 * i + 1]));
+        sum += ms;
+    }
+    if (total_ms) *total_ms = sum;
+    if (launches) *launches = c->prof_n;
+    c->prof_n = 0;
+    return RT3D_OK;
+}
+
 void rt3d_destroy(rt3d_ctx* c)
 {
     if (!c) return;
@@ -403,8 +471,10 @@ void rt3d_destroy(rt3d_ctx* c)
     bool switched = hipGetDevice(&prev) == hipSuccess && prev != c->device && hipSetDevice(c->device) == hipSuccess;
     if (c->d_cr) (void)hipFree(c->d_cr);
     if (c->d_q) (void)hipFree(c->d_q);
+    if (c->d_qst) (void)hipFree(c->d_qst);
     if (c->d_hbar) (void)hipFree(c->d_hbar);
     if (c->d_bw) (void)hipFree(c->d_bw);
+    for (hipEvent_t ev : c->prof_ev) (void)hipEventDestroy(ev);
     if (switched) (void)hipSetDevice(prev);
     delete c;
 }
@@ -467,7 +537,8 @@ rt3d_status rt3d_reconstruct(rt3d_ctx* c, const rt3d_input* in, rt3d_output* out
     if (in->kind == RT3D_IN_HIST_U16) {
         if (!in->hist) return fail(c, RT3D_E_INVALID, "hist is NULL");
         if (((uintptr_t)in->hist) % 16) return fail(c, RT3D_E_INVALID, "hist not 16-byte aligned");
-        RT3D_HIP(c, launch_compact(in->hist, sh.P, c->T, w.off, w.ent, c->ws_E, w.counts, w.partial, w.err, st));
+        RT3D_LAUNCH(c, RT3D_KERNEL_COMPACT, st,
+                    launch_compact(in->hist, sh.P, c->T, w.off, w.ent, c->ws_E, w.counts, w.partial, w.err, st));
         off = w.off;
         ent = w.ent;
         c->last_compacted = true;
@@ -482,13 +553,13 @@ rt3d_status rt3d_reconstruct(rt3d_ctx* c, const rt3d_input* in, rt3d_output* out
     c->last_P = sh.P;
     const DevModel m = dev_model(c);
     const DevParams p = dev_params(c);
-    RT3D_HIP(c, launch_init(m, p, sh, off, ent, in->gain, w.A, w.err, st));
-    RT3D_HIP(c, launch_init_normals(p, sh, w.A, st));
+    RT3D_LAUNCH(c, RT3D_KERNEL_INIT, st, launch_init(m, p, sh, off, ent, in->gain, w.A, w.err, st));
+    RT3D_LAUNCH(c, RT3D_KERNEL_NORMALS, st, launch_init_normals(p, sh, w.A, st));
     for (int it = 0; it < c->p.n_iter; ++it) {
         s = iterate(c, sh, off, ent, in->gain, w.A, w.B, w.btmp, st);
         if (s != RT3D_OK) return s;
     }
-    RT3D_HIP(c, launch_output(sh, w.A, out, w.counts, w.partial, w.err, st));
+    RT3D_LAUNCH(c, RT3D_KERNEL_OUTPUT, st, launch_output(sh, w.A, out, w.counts, w.partial, w.err, st));
     return RT3D_OK;
 }
 

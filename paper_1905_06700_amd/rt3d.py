@@ -25,7 +25,10 @@ STEP_INIT, STEP_DEPTH, STEP_APSS, STEP_MERGE, STEP_INTENSITY, STEP_IFILTER, STEP
 
 EXPORTS = ["rt3d_params_default", "rt3d_create", "rt3d_destroy", "rt3d_last_error", "rt3d_sigma2",
            "rt3d_workspace_bytes", "rt3d_set_workspace", "rt3d_reconstruct", "rt3d_query",
+           "rt3d_profile", "rt3d_profile_read",
            "rt3d_debug_compact", "rt3d_debug_step", "rt3d_debug_gradients"]
+KERNELS = ["compact", "init", "normals", "depth", "apss", "merge", "intensity", "ifilter", "bkg",
+           "bfilter", "output"]
 
 
 class Rt3dError(RuntimeError):
@@ -98,6 +101,10 @@ def lib():
         L.rt3d_reconstruct.restype = st
         L.rt3d_query.argtypes = [vp, vp, C.POINTER(Stats)]
         L.rt3d_query.restype = st
+        L.rt3d_profile.argtypes = [vp, C.c_int32]
+        L.rt3d_profile.restype = st
+        L.rt3d_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]
+        L.rt3d_profile_read.restype = st
         L.rt3d_debug_compact.argtypes = [vp, vp, C.c_uint32, vp, vp, C.c_uint64, vp]
         L.rt3d_debug_compact.restype = st
         L.rt3d_debug_step.argtypes = [vp, C.c_int32, vp, vp, vp, C.POINTER(State), C.POINTER(State), vp]
@@ -206,6 +213,17 @@ class Context:
         self._check(lib().rt3d_set_workspace(self._h, C.c_void_p(aligned), nb, frames, rows, cols,
                                              max_entries))
         self._ws_shape = shape
+
+    def profile(self, kernel: str | None):
+        """Time every later launch of one kernel group with HIP events (None = off)."""
+        kid = -1 if kernel is None else KERNELS.index(kernel)
+        self._check(lib().rt3d_profile(self._h, kid))
+
+    def profile_read(self):
+        """(total milliseconds, launches) of the timed kernel since the last read."""
+        ms, n = C.c_double(), C.c_uint64()
+        self._check(lib().rt3d_profile_read(self._h, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
 
     def query(self) -> Stats:
         st = Stats()

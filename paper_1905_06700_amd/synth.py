@@ -130,9 +130,11 @@ def render(rng, irf: IRF, T: int, depth, intensity, b: float, gain=None) -> np.n
     bin_all.append(rng.integers(0, T, pix.size))
     pix = np.concatenate(pix_all)
     tb = np.concatenate(bin_all)
-    counts = np.bincount(pix * T + tb, minlength=npix * T)
-    assert counts.max(initial=0) < 65535, "count overflow for uint16 histograms"
-    return counts.astype(np.uint16).reshape(rows, cols, T)
+    idx, cnt = np.unique(pix * T + tb, return_counts=True)
+    assert cnt.max(initial=0) < 65535, "count overflow for uint16 histograms"
+    Z = np.zeros(npix * T, dtype=np.uint16)
+    Z[idx] = cnt
+    return Z.reshape(rows, cols, T)
 
 
 def _blur_circular(field_, sigma):
