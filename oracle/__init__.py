@@ -197,6 +197,18 @@ def compact(Z: np.ndarray):
     return off, ent[:e].copy() if e else np.zeros(0, dtype=np.uint32)
 
 
+def compact_events(pix, bins, npix: int, T: int):
+    """Photon events (pixel, bin), any order -> the active-bin lists of their
+    histogram: the count of each (pixel, bin) is the number of events that name
+    it (the observation model's z), then `compact`.  Counts above 65535 do not
+    fit the entry format and raise."""
+    key = np.asarray(pix, dtype=np.int64) * T + np.asarray(bins, dtype=np.int64)
+    assert key.size == 0 or (key.min() >= 0 and key.max() < npix * T)
+    Z = np.bincount(key, minlength=npix * T)
+    assert Z.max(initial=0) <= 65535
+    return compact(Z.astype(np.uint16).reshape(npix, T))
+
+
 def _ent(ent):
     ent = np.ascontiguousarray(ent, dtype=np.uint32)
     return ent if ent.size else np.zeros(1, dtype=np.uint32)

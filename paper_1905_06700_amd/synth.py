@@ -200,6 +200,52 @@ def head_scene(scene: int = 0, rows: int = 141, cols: int = 141, T: int = 4613,
                       r_init=0, k_init=3, occluder=M))
 
 
+def layers_scene(scene: int = 0, rows: int = 256, cols: int = 256, T: int = 1024, signal: float = 2.0,
+                 sbr: float = 0.05, config: int = 4) -> Scene:
+    """Config 4 (learned-denoiser scenes): up to three piecewise-smooth depth
+    layers (base depths at 0.68 T, 0.44 T and 0.20 T): each a random plane
+    (tilt <= 0.5 bin/pixel) plus 40 x a unit-variance field blurred at 16 px
+    plus offsets U[-30, 30] on 8 Voronoi cells.  Layer 0 covers every pixel,
+    layer 1 half of them and layer 2 a fifth (thresholded smooth fields); a
+    front layer takes half of the signal left behind it.  Reflectivity
+    U[0.5, 1], mean `signal` photons/pixel, ex-Gaussian IRF of config 2."""
+    rng = np.random.default_rng(seed_of(config, scene))
+    irf = exgauss_irf(3.0, 10.0, -18, 118)
+    i, j = np.mgrid[0:rows, 0:cols].astype(np.float64)
+    depth = np.full((3, rows, cols), np.nan)
+    base = (0.68 * T, 0.44 * T, 0.20 * T)
+    fields = []
+    for s in range(3):
+        ti, tj = rng.uniform(-0.5, 0.5, 2)
+        f = _blur_circular(rng.normal(0, 1, (rows, cols)), 16.0)
+        f /= f.std() + 1e-12
+        cells = rng.uniform(0, 1, (8, 2)) * [rows, cols]
+        offs = rng.uniform(-30, 30, 8)
+        lab = np.argmin((i[..., None] - cells[:, 0]) ** 2 + (j[..., None] - cells[:, 1]) ** 2, axis=-1)
+        d = base[s] + ti * (i - rows / 2) + tj * (j - cols / 2) + 40.0 * f + offs[lab]
+        fields.append(np.clip(d, 20, T - 40))
+    pres = [np.ones((rows, cols), bool)]
+    for frac in (0.5, 0.8):
+        g = _blur_circular(rng.normal(0, 1, (rows, cols)), 8.0)
+        pres.append(g > np.quantile(g, frac))
+    for s in range(3):
+        depth[s] = np.where(pres[s], fields[s], np.nan)
+    rho = rng.uniform(0.5, 1.0, (3, rows, cols))
+    a = signal / 0.75
+    share = np.zeros((3, rows, cols))
+    left = np.ones((rows, cols))
+    for s in (2, 1, 0):                       # nearest layer first
+        take = np.where(pres[s], 0.5 * left if s > 0 else left, 0.0)
+        share[s] = take
+        left = left - take
+    inten = a * rho * share
+    b = signal / sbr / T
+    Z = render(rng, irf, T, depth, np.where(np.isfinite(depth), inten, 0.0), b)
+    return Scene(Z, irf, T, depth, inten, b,
+                 dict(config=config, dz=0.1, p_xy=1.0, mean_signal=signal, r_min=0.2 * signal,
+                      r_init=1, k_init=4))
+
+
 def random_gain(rng_seed: int, rows: int, cols: int, dead_frac: float = 0.02) -> np.ndarray:
     """Per-pixel detector gain in [0.5, 1.5] with a fraction of dead (0) pixels."""
     rng = np.random.default_rng(rng_seed)

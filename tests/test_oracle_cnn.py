@@ -1,0 +1,107 @@
+"""Pins of the learned-denoiser oracle (oracle/cnn.py).
+
+The convolution is pinned to torch's conv2d in float64 (a library routine
+with a different formulation: NCHW, OIHW), the backward pass to central
+finite differences of the loss, Adam to torch.optim.Adam, and the features
+and target matching to hand-built cases.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import cnn
+
+
+def test_conv3x3_equals_torch_conv2d():
+    rng = np.random.default_rng(0)
+    x = rng.normal(size=(2, 5, 7, 4))
+    W = rng.normal(size=(3, 3, 4, 6))
+    b = rng.normal(size=6)
+    y = cnn.conv3x3(x, W, b)
+    xt = torch.from_numpy(x).permute(0, 3, 1, 2)
+    wt = torch.from_numpy(W).permute(3, 2, 0, 1)          # [cout, cin, ky, kx]
+    yt = torch.nn.functional.conv2d(xt, wt, torch.from_numpy(b), padding=1).permute(0, 2, 3, 1)
+    np.testing.assert_allclose(y, yt.numpy(), rtol=1e-12, atol=1e-12)
+
+
+def test_backward_matches_finite_differences():
+    rng = np.random.default_rng(1)
+    F, H, W = 1, 5, 6
+    x = rng.normal(size=(F, H, W, 16))
+    w = cnn.he_init(3).astype(np.float64)
+    w += rng.normal(0, 0.05, w.shape)                     # non-zero biases, padding weights
+    target = rng.normal(size=(F, H, W, 3))
+    mask = rng.random((F, H, W, 3)) < 0.6
+    loss, g = cnn.loss_and_grad(x, w, target, mask)
+    idx = rng.choice(len(w), 60, replace=False)
+    eps = 1e-6
+    for i in idx:
+        wp, wm = w.copy(), w.copy()
+        wp[i] += eps
+        wm[i] -= eps
+        fd = (cnn.loss_and_grad(x, wp, target, mask)[0] - cnn.loss_and_grad(x, wm, target, mask)[0]) / (2 * eps)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(g[i])) + 1e-8, (i, fd, g[i])
+
+
+def test_adam_equals_torch():
+    rng = np.random.default_rng(2)
+    w0 = rng.normal(size=50)
+    wt = torch.tensor(w0.copy(), requires_grad=True)
+    opt = torch.optim.Adam([wt], lr=1e-2, betas=(0.9, 0.999), eps=1e-8)
+    w, m, v = w0.copy(), np.zeros(50), np.zeros(50)
+    for step in range(1, 6):
+        g = rng.normal(size=50)
+        opt.zero_grad()
+        wt.grad = torch.tensor(g)
+        opt.step()
+        w, m, v = cnn.adam(w, g, m, v, step, 1e-2)
+    np.testing.assert_allclose(w, wt.detach().numpy(), rtol=1e-12, atol=1e-14)
+
+
+def test_features_hand_cases():
+    F, H, W, K = 1, 3, 3, 4
+    t = np.zeros((9, K))
+    r = np.zeros((9, K))
+    cnt = np.ones(9, dtype=int)
+    t[:, 0] = 100.0
+    r[:, 0] = np.e - 1.0
+    t[4, 0] = 110.0                                   # centre sits 10 bins deeper
+    x = cnn.features(t, r, cnt, 2.0, F, H, W)
+    assert x.shape == (1, 3, 3, 16)
+    # the 5 x 5 window of any pixel of a 3 x 3 image holds all nine pixels
+    np.testing.assert_allclose(x[0, 1, 1, 0], (110.0 - 910.0 / 9) / 2.0)
+    np.testing.assert_allclose(x[0, 0, 0, 0], (100.0 - 910.0 / 9) / 2.0)
+    np.testing.assert_allclose(x[..., 1], 1.0)
+    np.testing.assert_allclose(x[..., 2], 1.0)
+    assert np.all(x[..., 3:] == 0)
+    # a four-point pixel still feeds its first three slots; large offsets clip at 8 sigma
+    cnt[0] = 4
+    t[0, :] = [1.0, 2.0, 3.0, 4.0]
+    x = cnn.features(t, r, cnt, 2.0, F, H, W)
+    assert x[0, 0, 0, 5] == 1.0 and x[0, 0, 0, 8] == 1.0
+    assert x[0, 0, 0, 0] == -8.0
+
+
+def test_target_matching():
+    t = np.array([[10.0, 50.0, 0, 0], [5.0, 0, 0, 0]])
+    cnt = np.array([2, 1])
+    truth = np.array([[11.0, np.nan], [48.0, 30.0]])      # [S, P]
+    tgt, msk = cnn.targets(t, cnt, truth, sigma_h=1.0)
+    assert msk.tolist() == [[True, True, False], [False, False, False]]
+    np.testing.assert_allclose(tgt[0, :2], [1.0, -2.0])
+
+
+def test_training_reduces_loss_on_a_toy():
+    rng = np.random.default_rng(4)
+    x = rng.normal(size=(1, 8, 8, 16))
+    x[..., 9:] = 0
+    target = np.tanh(x[..., :3])
+    mask = np.ones_like(target, dtype=bool)
+    w = cnn.he_init(0).astype(np.float64)
+    m = np.zeros_like(w)
+    v = np.zeros_like(w)
+    l0, _ = cnn.loss_and_grad(x, w, target, mask)
+    for step in range(1, 41):
+        loss, g = cnn.loss_and_grad(x, w, target, mask)
+        w, m, v = cnn.adam(w, g, m, v, step, 3e-3)
+    assert loss < 0.5 * l0

@@ -40,6 +40,32 @@ def test_compaction_empty(oracle_lib):
     assert ent.size == 0 and np.all(off == 0)
 
 
+def test_compaction_of_events_hand_case(oracle_lib):
+    # photons of 3 pixels x 5 bins: pixel 0 gets bin 3 twice and bin 1 once,
+    # pixel 1 nothing, pixel 2 bin 0 once -- in scrambled order
+    off, ent = oracle_lib.compact_events([0, 2, 0, 0], [3, 0, 1, 3], 3, 5)
+    np.testing.assert_array_equal(off, [0, 2, 2, 3])
+    np.testing.assert_array_equal(ent, [(1 << 16) | 1, (3 << 16) | 2, (0 << 16) | 1])
+
+
+def test_compaction_of_events_is_order_free_and_conserves_photons(oracle_lib):
+    rng = np.random.default_rng(3)
+    npix, T = 40, 97
+    pix = rng.integers(0, npix, 3000)
+    bins = rng.integers(0, T, 3000)
+    off, ent = oracle_lib.compact_events(pix, bins, npix, T)
+    perm = rng.permutation(pix.size)
+    off2, ent2 = oracle_lib.compact_events(pix[perm], bins[perm], npix, T)
+    np.testing.assert_array_equal(off, off2)
+    np.testing.assert_array_equal(ent, ent2)
+    assert int((ent & 0xFFFF).sum()) == pix.size
+    for p in range(npix):                       # per pixel: distinct bins ascending, counts by brute force
+        e = ent[off[p]:off[p + 1]]
+        mine = bins[pix == p]
+        np.testing.assert_array_equal(e >> 16, np.unique(mine))
+        np.testing.assert_array_equal(e & 0xFFFF, [(mine == b).sum() for b in np.unique(mine)])
+
+
 # ---------------------------------------------------------------- initialisation
 
 def gauss_model(oracle, T, sig=1.5, half=9):
