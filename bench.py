@@ -58,6 +58,67 @@ def algorithmic_bytes(kernel, F, N, T, E, pts):
     raise KeyError(kernel)
 
 
+def learned_vs_apss(n_train=4, n_eval=4, steps=300, rows=256, cols=256, bins=1024):
+    """Learned denoiser against plain APSS on multi-layer scenes: train on the
+    GPU (the library's forward/backward kernels), then time and score both on
+    held-out scenes (depth RMSE with misses counted at 3 sigma_h)."""
+    import numpy as np
+    import torch
+
+    from paper_1905_06700_amd import rt3d, synth, train
+
+    t0 = time.perf_counter()
+    tr = [synth.layers_scene(s, rows=rows, cols=cols, T=bins) for s in range(n_train)]
+    ev = [synth.layers_scene(10000 + s, rows=rows, cols=cols, T=bins) for s in range(n_eval)]
+    p = dict(dz=tr[0].meta["dz"], r_min=tr[0].meta["r_min"], r_init=tr[0].meta["r_init"],
+             k_init=tr[0].meta["k_init"])
+    apss = rt3d.Context(tr[0].irf.probs, bins, **p)
+    net = rt3d.Context(tr[0].irf.probs, bins, denoiser=rt3d.DENOISE_CNN, **p)
+    Ztr = torch.stack([torch.from_numpy(s.Z.view(np.int16)) for s in tr]).cuda()
+    truth = torch.from_numpy(np.concatenate([s.depth.reshape(3, -1) for s in tr], axis=1)
+                             .astype(np.float32)).cuda()
+    log(f"[bench] learned denoiser: recording depth-block inputs of {n_train} training scenes")
+    recorded = train.record_depth_inputs(apss, Ztr)
+    net.workspace(n_train, rows, cols, n_train * rows * cols * 256)
+    hist = train.train(net, [(recorded, truth)], steps=steps, lr=2e-3, seed=0)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    del recorded
+    Zev = torch.stack([torch.from_numpy(s.Z.view(np.int16)) for s in ev]).cuda()
+    sig = float(np.sqrt(apss.sigma2))
+    out = {}
+    for name, ctx in (("apss", apss), ("cnn", net)):
+        ctx.workspace(n_eval, rows, cols, n_eval * rows * cols * 256)
+        res = ctx.make_output(n_eval * rows * cols)
+        ctx.reconstruct_into(res, n_eval, rows, cols, hist=Zev)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(3):
+            ctx.reconstruct_into(res, n_eval, rows, cols, hist=Zev)
+        e1.record()
+        torch.cuda.synchronize()
+        fps = 3 * n_eval / (e0.elapsed_time(e1) / 1e3)
+        pt = res.pt_off.cpu().numpy().view(np.uint32).astype(np.int64)
+        dep = res.depth.cpu().numpy()
+        rm, found = [], []
+        P1 = rows * cols
+        for f, s in enumerate(ev):
+            sl = pt[f * P1:(f + 1) * P1 + 1] - pt[f * P1]
+            r, fo = train.depth_rmse(s.depth.reshape(3, -1), sl, dep[pt[f * P1]:], 3 * sig)
+            rm.append(r)
+            found.append(fo)
+        out[name] = {"frames_per_s": round(fps, 2), "depth_rmse_bins": round(float(np.mean(rm)), 3),
+                     "found_within_3sigma": round(float(np.mean(found)), 4)}
+    out["rmse_ratio_cnn_over_apss"] = round(out["cnn"]["depth_rmse_bins"] / out["apss"]["depth_rmse_bins"], 4)
+    out["speedup_cnn_over_apss"] = round(out["cnn"]["frames_per_s"] / out["apss"]["frames_per_s"], 3)
+    out["workload"] = (f"{rows}x{cols}x{bins} multi-layer scenes (up to 3 surfaces, 2 signal photons/px, "
+                       f"SBR 0.05), {n_eval} held-out frames per call")
+    out["training"] = {"scenes": n_train, "steps": steps, "final_loss": round(hist[-1], 4),
+                       "first_loss": round(hist[0], 4), "seconds_incl_data": round(train_s, 1)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -66,6 +127,7 @@ def main():
     ap.add_argument("--frames", type=int, default=16, help="frames per reconstruction call")
     ap.add_argument("--kernel", default="depth", help="kernel group for the roofline object")
     ap.add_argument("--cpu-frames", type=int, default=2, help="frames the oracle times (0 = skip)")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-APSS leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); frames are "
@@ -176,6 +238,7 @@ def main():
         "active_entries_per_frame": E // F, "points_per_frame": pts // F,
         "single_frame_latency_ms": round(latency_ms, 3), "wall_s": round(wall, 3),
         "roofline": roofline, "cpu_baseline": cpu,
+        "learned_vs_apss": None if args.no_learned else learned_vs_apss(),
         "paper_context": {"frames_per_s": 76.9, "ms_per_frame": 13, "hardware": "NVIDIA Titan Xp",
                           "data": "real head scan, ~3 photons/px, SBR 13"},
     }

@@ -56,6 +56,7 @@ typedef int32_t rt3d_status;
 /* Depth denoiser plugged into the depth block. */
 #define RT3D_DENOISE_NONE 0
 #define RT3D_DENOISE_APSS 1
+#define RT3D_DENOISE_CNN  2   /* learned network for pixels with <= 3 points, APSS for the rest */
 
 /* Algorithm parameters.  Defaults (rt3d_params_default) are the readings of
  * the paper's unstated constants; `struct_size` must be sizeof(rt3d_params). */
@@ -83,12 +84,13 @@ typedef struct rt3d_params {
     double   kappa;      /* peak acceptance in background standard deviations (3) */
     int32_t  w_nms;      /* peak suppression half width, bins; <= 0: ceil(max(1, 2 sigma_h)) */
     int32_t  m_min;      /* minimum APSS neighbours (3) */
-    int32_t  denoiser;   /* RT3D_DENOISE_APSS (default) or RT3D_DENOISE_NONE */
+    int32_t  denoiser;   /* RT3D_DENOISE_APSS (default), RT3D_DENOISE_CNN or RT3D_DENOISE_NONE */
 } rt3d_params;
 
 /* Input kinds. */
 #define RT3D_IN_HIST_U16   0   /* dense histograms */
 #define RT3D_IN_PHOTON_CSR 1   /* active-bin lists, as rt3d_debug_compact writes them */
+#define RT3D_IN_PHOTON_EVENTS 2 /* unordered photon events (pixel, bin) */
 
 typedef struct rt3d_input {
     uint32_t struct_size;      /* sizeof(rt3d_input) */
@@ -102,6 +104,15 @@ typedef struct rt3d_input {
     const uint32_t* ent;
     /* Optional device float gain[P] (g of the observation model); NULL = 1. */
     const float* gain;
+    /* RT3D_IN_PHOTON_EVENTS: n_events (< 2^31) photons, in any order; device
+     * ev_pixel[n_events] = f * rows * cols + i * cols + j and ev_bin[n_events] = bin.
+     * ev_scratch is caller-owned device memory of n_events uint32, overwritten.
+     * An event with pixel >= P or bin >= bins is dropped and a bin receiving more
+     * than 65535 photons is stored as 65535; both leave RT3D_E_INVALID for rt3d_query. */
+    const uint32_t* ev_pixel;
+    const uint16_t* ev_bin;
+    uint32_t* ev_scratch;
+    uint64_t n_events;
 } rt3d_input;
 
 typedef struct rt3d_output {
@@ -201,7 +212,8 @@ rt3d_status rt3d_query(rt3d_ctx* ctx, void* hip_stream, rt3d_stats* st);
 #define RT3D_KERNEL_BKG       8   /* background gradient step */
 #define RT3D_KERNEL_BFILTER   9   /* background filter (row and column passes) */
 #define RT3D_KERNEL_OUTPUT   10   /* output packing (count, scan, pack) */
-#define RT3D_KERNEL_COUNT    11
+#define RT3D_KERNEL_CNN      11   /* learned denoiser forward (features + four convolutions) */
+#define RT3D_KERNEL_COUNT    12
 rt3d_status rt3d_profile(rt3d_ctx* ctx, int32_t id);
 rt3d_status rt3d_profile_read(rt3d_ctx* ctx, double* total_ms, uint64_t* launches);
 
@@ -216,6 +228,19 @@ rt3d_status rt3d_profile_read(rt3d_ctx* ctx, double* total_ms, uint64_t* launche
  * E_CAPACITY becomes the sticky device error.  Needs the workspace. */
 rt3d_status rt3d_debug_compact(rt3d_ctx* ctx, const uint16_t* hist, uint32_t npix,
                                uint32_t* off, uint32_t* ent, uint64_t capacity, void* hip_stream);
+
+/* Photon events -> the same active-bin lists (the photons a time-tagged
+ * detector reports, counted per (pixel, bin); Methods: only bins with non-zero
+ * counts are kept).  ev_pixel / ev_bin: device [n_events] (n_events < 2^31, any
+ * order; pixel < npix, bin < bins); ev_scratch: caller-owned device
+ * [n_events] uint32, overwritten.  off: device [npix + 1]; ent: device
+ * [capacity].  The output does not depend on the event order.  Out-of-range
+ * events are dropped and a count above 65535 is stored as 65535, each leaving
+ * E_INVALID as the sticky device error; entries beyond capacity are dropped
+ * with E_CAPACITY.  Needs the workspace. */
+rt3d_status rt3d_debug_compact_events(rt3d_ctx* ctx, const uint32_t* ev_pixel, const uint16_t* ev_bin,
+                                      uint64_t n_events, uint32_t npix, uint32_t* ev_scratch, uint32_t* off,
+                                      uint32_t* ent, uint64_t capacity, void* hip_stream);
 
 /* Steps.  `in` is read, `out` is written in full (it must not alias `in`);
  * off/ent are the active-bin lists, gain may be NULL. */
@@ -238,6 +263,53 @@ rt3d_status rt3d_debug_step(rt3d_ctx* ctx, int32_t step, const uint32_t* off, co
 rt3d_status rt3d_debug_gradients(rt3d_ctx* ctx, const uint32_t* off, const uint32_t* ent,
                                  const float* gain, const rt3d_state* st,
                                  float* gt, float* gr, float* gb, void* hip_stream);
+
+/* ---------------------------------------------------------------------------
+ * Learned depth denoiser.  The paper lets any denoiser act as the proximal
+ * step of the depth block (Results, "Reconstruction algorithm"; Discussion).
+ * With p->denoiser == RT3D_DENOISE_CNN the depth block runs, after the depth
+ * gradient step, a four-layer 3x3 convolutional network on the per-pixel
+ * slot maps (features of slots 0..2: (t - 5x5 mean of the slot)/sigma_h
+ * clipped to [-8, 8], log(1 + r), valid flag; channels 16 -> 32 -> 32 -> 32
+ * -> 3, ReLU between layers, zero padding), FP16 matrix-core arithmetic with
+ * FP32 accumulation, and moves slot k by sigma_h * output_k; pixels with four
+ * points use APSS.  Weights: RT3D_CNN_PARAMS FP32 values, layer by layer
+ * w[ky][kx][cin][cout] then bias[cout] for (cin, cout) = (16, 32), (32, 32),
+ * (32, 32), (32, 3).  The workspace of a CNN context holds the training
+ * buffers (size it with rt3d_workspace_bytes on that context).
+ * ------------------------------------------------------------------------- */
+#define RT3D_CNN_PARAMS 24003
+
+typedef struct rt3d_adam {
+    uint32_t struct_size;      /* sizeof(rt3d_adam) */
+    float lr;                  /* >= 0; 0 computes loss and gradient, weights stay */
+    float beta1, beta2;        /* in [0, 1) */
+    float eps;                 /* > 0 */
+} rt3d_adam;
+
+/* Host FP32 weights in / out (synchronous on the null stream).  Setting the
+ * weights clears the Adam moments and step.  E_INVALID when n != RT3D_CNN_PARAMS. */
+rt3d_status rt3d_cnn_set_weights(rt3d_ctx* ctx, const float* host, size_t n);
+rt3d_status rt3d_cnn_get_weights(rt3d_ctx* ctx, float* host, size_t n);
+
+/* FP32 gradient of the last rt3d_cnn_train_step (in the weight layout above),
+ * synchronous, for testing.  E_STATE without a CNN workspace. */
+rt3d_status rt3d_cnn_last_gradient(rt3d_ctx* ctx, float* host, size_t n);
+
+/* Network output for a state: y device float [3][P] (corrections in sigma_h
+ * units for slots 0..2; pixels with four points included).  Needs a CNN
+ * context and its workspace. */
+rt3d_status rt3d_cnn_forward(rt3d_ctx* ctx, const rt3d_state* st, float* y, void* hip_stream);
+
+/* One training step on a state (the depth block's input) and its true depths
+ * truth: device float [n_surf][P], NaN where a pixel has no such surface.
+ * Targets: slot k < min(cnt, 3) takes the nearest true depth of its pixel
+ * within 3 sigma_h; loss = mean squared error of the outputs over matched
+ * slots.  Backward pass on the matrix cores, deterministic weight-gradient
+ * reduction, Adam on the FP32 master weights.  loss: device float [2] =
+ * (loss, matched slots).  Asynchronous on hip_stream. */
+rt3d_status rt3d_cnn_train_step(rt3d_ctx* ctx, const rt3d_state* st, const float* truth, uint32_t n_surf,
+                                const rt3d_adam* opt, float* loss, void* hip_stream);
 
 #ifdef __cplusplus
 }

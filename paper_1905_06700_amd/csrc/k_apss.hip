@@ -14,45 +14,87 @@
 // (clipped to [-h, h]); its normal becomes grad s there, facing the sensor.
 // Jacobi: every query reads the state before the step.
 //
-// Mapping: one lane per pixel; the lane visits the (2R+1)^2 pixel window
-// around its pixel.  World positions are formed relative to the query in
-// FP64 and the moments accumulate in FP32 in those local coordinates.
+// Mapping: eight lanes per pixel split the (2R+1)^2 pixel window around it;
+// each accumulates the sphere moments of its share in FP32, in coordinates
+// local to the query (positions formed in FP64), and the eight partial
+// moment sets meet in a fixed wavefront-shuffle tree.
 #include "rt3d_dev.h"
 
 namespace rt3d {
 
-__global__ __launch_bounds__(256) void k_apss(DevModel m, DevParams p, Shape sh, DevState in, DevState out)
+// Sphere fit from the moments and projection of the query along its line of
+// sight: updates depth t (bins) and normal n when the fit is usable.
+__device__ __forceinline__ void apss_project(bool ok, float W, float Px, float Py, float Pz, float Nx, float Ny,
+                                             float Nz, float PN, float PP, float h, float h2, double dz, double tmax,
+                                             double& t, float (&n)[3])
+{
+    if (!ok) return;
+    const float invW = 1.f / W;
+    const float PdP = Px * Px + Py * Py + Pz * Pz;
+    const float PdN = Px * Nx + Py * Ny + Pz * Nz;
+    const float D = PP - PdP * invW;
+    if (!(D > 1e-12f * W * h2)) return;
+    const float u4 = 0.5f * (PN - PdN * invW) / D;
+    const float ulx = (Nx - 2.f * u4 * Px) * invW;
+    const float uly = (Ny - 2.f * u4 * Py) * invW;
+    const float ulz = (Nz - 2.f * u4 * Pz) * invW;
+    const float u0 = -(ulx * Px + uly * Py + ulz * Pz + u4 * PP) * invW;
+    const float nul = sqrtf(ulx * ulx + uly * uly + ulz * ulz);
+    if (!(fabsf(ulz) > 1e-6f * nul)) return;
+    const float disc = ulz * ulz - 4.f * u4 * u0;
+    float sroot;
+    if (disc < 0.f) sroot = -ulz / (2.f * u4);
+    else sroot = -2.f * u0 / (ulz + copysignf(sqrtf(disc), ulz));
+    sroot = fminf(fmaxf(sroot, -h), h);
+    double tn = t + (double)sroot / dz;
+    t = tn < 0.0 ? 0.0 : (tn > tmax ? tmax : tn);
+    const float gx = ulx, gy = uly, gz = ulz + 2.f * u4 * sroot;
+    const float gn = sqrtf(gx * gx + gy * gy + gz * gz);
+    if (gn > 0.f) {
+        const float inv = (gz > 0.f ? -1.f : 1.f) / gn;
+        n[0] = gx * inv;
+        n[1] = gy * inv;
+        n[2] = gz * inv;
+    }
+}
+
+constexpr int LPA = 8;   // lanes per pixel: the window's pixels are split over them
+
+__global__ __launch_bounds__(256) void k_apss(DevModel m, DevParams p, Shape sh, DevState in, DevState out,
+                                              int only_above)
 {
     const long long P = sh.P;
-    const long long pix = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (pix >= P) return;
-    const int c = load_cnt(in.cnt, pix);
-    out.cnt[pix] = (uint8_t)c;
-    out.b[pix] = in.b[pix];
-#pragma unroll
-    for (int k = 0; k < KM; ++k) {
-        out.t[k * P + pix] = in.t[k * P + pix];
-        out.r[k * P + pix] = in.r[k * P + pix];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) out.n[(a * KM + k) * P + pix] = in.n[(a * KM + k) * P + pix];
+    const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long pix = gid / LPA;
+    const int sub = (int)(gid % LPA);
+    const bool live = pix < P;
+    const long long pq = live ? pix : 0;
+    const int c = live ? load_cnt(in.cnt, pq) : 0;
+    if (live) {
+        if (sub == 0) {
+            out.cnt[pix] = (uint8_t)c;
+            out.b[pix] = in.b[pix];
+        }
+        if (sub < KM) out.r[sub * P + pix] = in.r[sub * P + pix];   // depth and normal: lane 0 below
     }
+    const bool fit = live && !(only_above >= 0 && c <= only_above);
     const int per_frame = sh.rows * sh.cols;
-    const long long fr = pix / per_frame;
-    const int i = (int)((pix / sh.cols) % sh.rows), j = (int)(pix % sh.cols);
-    const int R = p.apss_R;
+    const long long fr = pq / per_frame;
+    const int i = (int)((pq / sh.cols) % sh.rows), j = (int)(pq % sh.cols);
+    const int R = p.apss_R, side = 2 * R + 1;
     const float h = (float)p.h_apss, h2 = h * h, inv_h2 = 1.f / h2;
     const float pxy = (float)p.p_xy;
     const double dz = p.dz;
     const double tmax = (double)(m.T - 1);
-    for (int k = 0; k < KM; ++k) {
-        if (k >= c) break;
-        const double tq = in.t[k * P + pix];
-        float W = 0.f, Px = 0.f, Py = 0.f, Pz = 0.f, Nx = 0.f, Ny = 0.f, Nz = 0.f, PN = 0.f, PP = 0.f;
-        int nn = 0;
-        for (int i2 = max(0, i - R); i2 <= min(sh.rows - 1, i + R); ++i2) {
-            const float yy = (float)(i2 - i) * pxy;
-            for (int j2 = max(0, j - R); j2 <= min(sh.cols - 1, j + R); ++j2) {
-                const float yx = (float)(j2 - j) * pxy;
+    for (int k = 0; k < KM; ++k) {                  // every lane runs every slot (shuffles below)
+        const bool act = fit && k < c;
+        const double tq = act ? in.t[k * P + pq] : 0.0;
+        float W = 0.f, Px = 0.f, Py = 0.f, Pz = 0.f, Nx = 0.f, Ny = 0.f, Nz = 0.f, PN = 0.f, PP = 0.f, nn = 0.f;
+        if (act) {
+            for (int widx = sub; widx < side * side; widx += LPA) {
+                const int i2 = i + widx / side - R, j2 = j + widx % side - R;
+                if (i2 < 0 || i2 >= sh.rows || j2 < 0 || j2 >= sh.cols) continue;
+                const float yy = (float)(i2 - i) * pxy, yx = (float)(j2 - j) * pxy;
                 const long long pp = (fr * sh.rows + i2) * sh.cols + j2;
                 const int cc = load_cnt(in.cnt, pp);
                 for (int k2 = 0; k2 < cc; ++k2) {
@@ -74,40 +116,32 @@ __global__ __launch_bounds__(256) void k_apss(DevModel m, DevParams p, Shape sh,
                     Nz = fmaf(w, nz, Nz);
                     PN = fmaf(w, yx * nx + yy * ny + yz * nz, PN);
                     PP = fmaf(w, d2, PP);
-                    ++nn;
+                    nn += 1.f;
                 }
             }
         }
-        if (nn < p.m_min) continue;
-        const float invW = 1.f / W;
-        const float PdP = Px * Px + Py * Py + Pz * Pz;
-        const float PdN = Px * Nx + Py * Ny + Pz * Nz;
-        const float D = PP - PdP * invW;
-        if (!(D > 1e-12f * W * h2)) continue;
-        const float u4 = 0.5f * (PN - PdN * invW) / D;
-        const float ulx = (Nx - 2.f * u4 * Px) * invW;
-        const float uly = (Ny - 2.f * u4 * Py) * invW;
-        const float ulz = (Nz - 2.f * u4 * Pz) * invW;
-        const float u0 = -(ulx * Px + uly * Py + ulz * Pz + u4 * PP) * invW;
-        const float nul = sqrtf(ulx * ulx + uly * uly + ulz * ulz);
-        if (!(fabsf(ulz) > 1e-6f * nul)) continue;
-        const float disc = ulz * ulz - 4.f * u4 * u0;
-        float sroot;
-        if (disc < 0.f) sroot = -ulz / (2.f * u4);
-        else sroot = -2.f * u0 / (ulz + copysignf(sqrtf(disc), ulz));
-        sroot = fminf(fmaxf(sroot, -h), h);
-        double tn = tq + (double)sroot / dz;
-        tn = tn < 0.0 ? 0.0 : (tn > tmax ? tmax : tn);
-        out.t[k * P + pix] = tn;
-        const float gx = ulx, gy = uly, gz = ulz + 2.f * u4 * sroot;
-        const float gn = sqrtf(gx * gx + gy * gy + gz * gz);
-        if (gn > 0.f) {
-            const float sg = gz > 0.f ? -1.f : 1.f;
-            const float inv = sg / gn;
-            out.n[(0 * KM + k) * P + pix] = gx * inv;
-            out.n[(1 * KM + k) * P + pix] = gy * inv;
-            out.n[(2 * KM + k) * P + pix] = gz * inv;
+        // sphere moments of the pixel's LPA lanes (fixed xor tree)
+#pragma unroll
+        for (int d = 1; d < LPA; d <<= 1) {
+            W += __shfl_xor(W, d, 64);
+            Px += __shfl_xor(Px, d, 64);
+            Py += __shfl_xor(Py, d, 64);
+            Pz += __shfl_xor(Pz, d, 64);
+            Nx += __shfl_xor(Nx, d, 64);
+            Ny += __shfl_xor(Ny, d, 64);
+            Nz += __shfl_xor(Nz, d, 64);
+            PN += __shfl_xor(PN, d, 64);
+            PP += __shfl_xor(PP, d, 64);
+            nn += __shfl_xor(nn, d, 64);
         }
+        if (!live || sub != 0) continue;
+        // lane 0 writes the slot: the projection when the fit succeeds, else the input
+        double tn = in.t[k * P + pix];
+        float on[3] = {in.n[(0 * KM + k) * P + pix], in.n[(1 * KM + k) * P + pix], in.n[(2 * KM + k) * P + pix]};
+        apss_project(act && nn >= (float)p.m_min, W, Px, Py, Pz, Nx, Ny, Nz, PN, PP, h, h2, dz, tmax, tn, on);
+        out.t[k * P + pix] = tn;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) out.n[(a * KM + k) * P + pix] = on[a];
     }
 }
 
@@ -181,10 +215,11 @@ __global__ __launch_bounds__(256) void k_merge(DevParams p, Shape sh, DevState s
 }
 
 hipError_t launch_apss(const DevModel& m, const DevParams& p, const Shape& sh, DevState in, DevState out,
-                       hipStream_t st)
+                       int only_above, hipStream_t st)
 {
     if (sh.P == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_apss, dim3((unsigned)((sh.P + 255) / 256)), dim3(256), 0, st, m, p, sh, in, out);
+    hipLaunchKernelGGL(k_apss, dim3((unsigned)((sh.P * LPA + 255) / 256)), dim3(256), 0, st, m, p, sh, in, out,
+                       only_above);
     return hipGetLastError();
 }
 

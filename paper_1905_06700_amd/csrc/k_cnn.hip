@@ -1,0 +1,504 @@
+// k_cnn.hip -- the learned depth denoiser that can replace APSS in the depth
+// block (the paper treats the denoiser as interchangeable: Results,
+// "Reconstruction algorithm"; Discussion, other denoisers trade quality for
+// speed).  Reading (not in the paper): a four-layer 3x3 convolutional network
+// on per-pixel slot maps (features of the first three slots: depth relative
+// to the 5x5 mean of that slot in sigma_h units, log(1 + r), valid flag)
+// predicting each slot's depth correction in sigma_h units; pixels with four
+// points keep APSS.
+//
+// Every convolution is an implicit GEMM on the matrix cores:
+// v_mfma_f32_16x16x16_f16 (FP16 inputs, FP32 accumulation).  Activations are
+// FP16 NHWC with 16 or 32 channels (64 B per pixel at 32), weights FP16.
+//   forward:         Y[p][co]   = b[co] + sum_{tap, ci} X[p + tap][ci] W[tap][ci][co]
+//   backward data:   dX[p][ci]  = sum_{tap, co} dY[p + tap][co] W'[tap][co][ci],
+//                    W' the tap-flipped transpose, gated by the ReLU of X
+//   backward weight: dW[tap][ci][co] = sum_p X[p + tap][ci] dY[p][co],
+//                    per-workgroup partials reduced in a fixed order
+// A workgroup owns 64 consecutive pixels of one image row (4 wavefronts x 16
+// pixels) and stages the 3-row halo and the layer's weights in LDS.
+#include "rt3d_dev.h"
+#include "rt3d_cnn.h"
+
+#include <hip/hip_fp16.h>
+
+namespace rt3d {
+
+typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+constexpr int CT = 64;   // output pixels per workgroup (one row segment)
+
+__device__ __forceinline__ float4_t mfma16(half4_t a, half4_t b, float4_t c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
+}
+
+// Stages rows y-1..y+1, columns x0-1..x0+CT of one frame (zero outside the
+// image) into LDS as [3][CT+2][C] halves.
+template <int C>
+__device__ __forceinline__ void stage_halo(const __half* __restrict__ X, int F, int H, int W, int f, int y,
+                                           int x0, __half* __restrict__ halo)
+{
+    constexpr int VPP = C / 8;                       // 16-byte vectors per pixel
+    const int nvec = 3 * (CT + 2) * VPP;
+    for (int v = threadIdx.x; v < nvec; v += blockDim.x) {
+        const int c8 = v % VPP;
+        const int px = (v / VPP) % (CT + 2);
+        const int ry = v / (VPP * (CT + 2));
+        const int yy = y + ry - 1, xx = x0 + px - 1;
+        uint4 val = make_uint4(0, 0, 0, 0);
+        if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+            val = reinterpret_cast<const uint4*>(X + (((long long)f * H + yy) * W + xx) * C)[c8];
+        reinterpret_cast<uint4*>(halo)[v] = val;
+    }
+    (void)F;
+}
+
+// Forward / backward-data convolution.  Wt: FP16 [COUT][9 * CIN] (k = tap * CIN + ci,
+// tap = ky * 3 + kx).  MODE 0: + bias, ReLU; 1: + bias (last layer); 2: gate by
+// (G > 0) (backward data, G = the layer input's activation), no bias.
+template <int CIN, int COUT, int MODE>
+__global__ __launch_bounds__(256) void k_conv3x3(const __half* __restrict__ X, const __half* __restrict__ Wt,
+                                                 const float* __restrict__ bias, const __half* __restrict__ Gate,
+                                                 __half* __restrict__ Y, int F, int H, int W)
+{
+    constexpr int K = 9 * CIN;
+    constexpr int NT = COUT / 16;
+    __shared__ __align__(16) __half halo[3 * (CT + 2) * CIN];
+    __shared__ __align__(16) __half wsh[COUT * K];
+    const int segs = (W + CT - 1) / CT;
+    const int seg = blockIdx.x % segs;
+    const int y = (blockIdx.x / segs) % H;
+    const int f = blockIdx.x / (segs * H);
+    const int x0 = seg * CT;
+    stage_halo<CIN>(X, F, H, W, f, y, x0, halo);
+    for (int v = threadIdx.x; v < COUT * K / 8; v += blockDim.x)
+        reinterpret_cast<uint4*>(wsh)[v] = reinterpret_cast<const uint4*>(Wt)[v];
+    __syncthreads();
+
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int i = lane & 15, g = lane >> 4;
+    float4_t acc[NT];
+#pragma unroll
+    for (int n = 0; n < NT; ++n) acc[n] = (float4_t){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+        const int ky = tap / 3, kx = tap % 3;
+        const __half* arow = halo + ((ky * (CT + 2)) + wv * 16 + i + kx) * CIN;
+#pragma unroll
+        for (int cc = 0; cc < CIN / 16; ++cc) {
+            const half4_t a = *reinterpret_cast<const half4_t*>(arow + cc * 16 + 4 * g);
+            const int k = tap * CIN + cc * 16 + 4 * g;
+#pragma unroll
+            for (int n = 0; n < NT; ++n) {
+                const half4_t b = *reinterpret_cast<const half4_t*>(wsh + (n * 16 + i) * K + k);
+                acc[n] = mfma16(a, b, acc[n]);
+            }
+        }
+    }
+    // D[row = 4 g + r][col = i]: pixel x0 + 16 wv + 4 g + r, channel 16 n + i
+#pragma unroll
+    for (int n = 0; n < NT; ++n) {
+        const int co = n * 16 + i;
+        const float bco = (MODE != 2) ? bias[co] : 0.f;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int x = x0 + wv * 16 + 4 * g + r;
+            if (x >= W) continue;
+            const long long pix = ((long long)f * H + y) * W + x;
+            float v = acc[n][r] + bco;
+            if (MODE == 0) v = fmaxf(v, 0.f);
+            if (MODE == 2 && !(__half2float(Gate[pix * COUT + co]) > 0.f)) v = 0.f;
+            Y[pix * COUT + co] = __float2half(v);
+        }
+    }
+}
+
+// Weight gradient partials: each workgroup reduces its row segment over
+// ROWS_PER_WG consecutive rows (same frame) into part[wg][9 * CIN][COUT] and
+// bias partials bpart[wg][COUT].
+constexpr int WG_ROWS = 8;
+
+template <int CIN, int COUT>
+__global__ __launch_bounds__(256) void k_conv3x3_wgrad(const __half* __restrict__ X, const __half* __restrict__ dY,
+                                                       float* __restrict__ part, float* __restrict__ bpart,
+                                                       int F, int H, int W)
+{
+    constexpr int K9 = 9 * CIN;
+    constexpr int MT = K9 / 16;                  // row tiles of (tap, ci)
+    constexpr int NT = COUT / 16;
+    constexpr int TILES = MT * NT;
+    constexpr int TPW = (TILES + 3) / 4;         // tiles per wavefront
+    __shared__ __align__(16) __half halo[3 * (CT + 2) * CIN];
+    __shared__ __align__(16) __half dys[CT * COUT];
+    const int segs = (W + CT - 1) / CT;
+    const int rblocks = (H + WG_ROWS - 1) / WG_ROWS;
+    const int seg = blockIdx.x % segs;
+    const int rb = (blockIdx.x / segs) % rblocks;
+    const int f = blockIdx.x / (segs * rblocks);
+    const int x0 = seg * CT;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int i = lane & 15, g = lane >> 4;
+    float4_t acc[TPW];
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) acc[t] = (float4_t){0.f, 0.f, 0.f, 0.f};
+    float bsum = 0.f;
+    for (int yr = 0; yr < WG_ROWS; ++yr) {
+        const int y = rb * WG_ROWS + yr;
+        if (y >= H) break;
+        __syncthreads();
+        stage_halo<CIN>(X, F, H, W, f, y, x0, halo);
+        for (int v = threadIdx.x; v < CT * COUT / 8; v += blockDim.x) {
+            const int px = v / (COUT / 8), c8 = v % (COUT / 8);
+            const int x = x0 + px;
+            uint4 val = make_uint4(0, 0, 0, 0);
+            if (x < W) val = reinterpret_cast<const uint4*>(dY + (((long long)f * H + y) * W + x) * COUT)[c8];
+            reinterpret_cast<uint4*>(dys)[v] = val;
+        }
+        __syncthreads();
+        if (threadIdx.x < COUT)
+            for (int px = 0; px < CT; ++px) bsum += __half2float(dys[px * COUT + threadIdx.x]);
+        // K dimension: the segment's 64 pixels in 4 steps of 16
+#pragma unroll
+        for (int ks = 0; ks < CT / 16; ++ks) {
+#pragma unroll
+            for (int t = 0; t < TPW; ++t) {
+                const int tile = wv * TPW + t;
+                if (tile >= TILES) continue;
+                const int mt = tile / NT, nt = tile % NT;
+                const int row = mt * 16 + i;                  // (tap, ci) of this lane's A row
+                const int tap = row / CIN, ci = row % CIN;
+                const int ky = tap / 3, kx = tap % 3;
+                half4_t a, b;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int px = ks * 16 + 4 * g + r;        // reduction index = pixel
+                    a[r] = (_Float16)halo[((ky * (CT + 2)) + px + kx) * CIN + ci];
+                    b[r] = (_Float16)dys[px * COUT + nt * 16 + i];
+                }
+                acc[t] = mfma16(a, b, acc[t]);
+            }
+        }
+    }
+    float* out = part + (size_t)blockIdx.x * K9 * COUT;
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+        const int tile = wv * TPW + t;
+        if (tile >= TILES) continue;
+        const int mt = tile / NT, nt = tile % NT;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) out[(mt * 16 + 4 * g + r) * COUT + nt * 16 + i] = acc[t][r];
+    }
+    if (threadIdx.x < COUT) bpart[(size_t)blockIdx.x * COUT + threadIdx.x] = bsum;
+}
+
+// Sums weight-gradient partials over workgroups in a fixed order and writes
+// the FP32 gradient of the flat master-weight layout (scaled by 1/count).
+__global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ part, const float* __restrict__ bpart,
+                                                      int nwg, int cin_store, int cout_store, int cin, int cout,
+                                                      const float* __restrict__ count, float* __restrict__ grad)
+{
+    const int n_w = 9 * cin * cout;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n_w + cout) return;
+    const float inv = 1.f / fmaxf(count[0], 1.f);
+    float s = 0.f;
+    if (idx < n_w) {
+        const int co = idx % cout, ci = (idx / cout) % cin, tap = idx / (cout * cin);
+        const int row = tap * cin_store + ci;
+        for (int wg = 0; wg < nwg; ++wg) s += part[((size_t)wg * 9 * cin_store + row) * cout_store + co];
+    } else {
+        const int co = idx - n_w;
+        for (int wg = 0; wg < nwg; ++wg) s += bpart[(size_t)wg * cout_store + co];
+    }
+    grad[idx] = s * inv;
+}
+
+// Features of the first three slots, FP16 [P][16].
+__global__ __launch_bounds__(256) void k_cnn_pack(Shape sh, DevState s, float sigma_h, __half* __restrict__ x)
+{
+    const long long P = sh.P;
+    const long long pix = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pix >= P) return;
+    const int per_frame = sh.rows * sh.cols;
+    const long long fr = pix / per_frame;
+    const int i = (int)((pix / sh.cols) % sh.rows), j = (int)(pix % sh.cols);
+    const int c = min(load_cnt(s.cnt, pix), 3);
+    float v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) v[q] = 0.f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        if (k >= c) continue;
+        double sum = 0.0;
+        int n = 0;
+        for (int i2 = max(0, i - 2); i2 <= min(sh.rows - 1, i + 2); ++i2)
+            for (int j2 = max(0, j - 2); j2 <= min(sh.cols - 1, j + 2); ++j2) {
+                const long long pp = (fr * sh.rows + i2) * sh.cols + j2;
+                if (min(load_cnt(s.cnt, pp), 3) > k) {
+                    sum += s.t[k * P + pp];
+                    ++n;
+                }
+            }
+        const double tk = s.t[k * P + pix];
+        const double mean = sum / n;
+        v[3 * k] = fminf(fmaxf((float)((tk - mean) / (double)sigma_h), -8.f), 8.f);
+        v[3 * k + 1] = log1pf(s.r[k * P + pix]);
+        v[3 * k + 2] = 1.f;
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) x[pix * 16 + q] = __float2half(v[q]);
+}
+
+// Slot k < 3 of a pixel with at most three points moves by sigma_h * y_k.
+__global__ __launch_bounds__(256) void k_cnn_apply(Shape sh, const __half* __restrict__ y, float sigma_h,
+                                                   double tmax, DevState s)
+{
+    const long long P = sh.P;
+    const long long pix = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pix >= P) return;
+    const int c = load_cnt(s.cnt, pix);
+    if (c > 3) return;
+    for (int k = 0; k < c; ++k) {
+        double t = s.t[k * P + pix] + (double)(sigma_h * __half2float(y[pix * 16 + k]));
+        t = t < 0.0 ? 0.0 : (t > tmax ? tmax : t);
+        s.t[k * P + pix] = t;
+    }
+}
+
+// Network outputs of the first three channels as float [3][P].
+__global__ __launch_bounds__(256) void k_cnn_unpack(long long P, const __half* __restrict__ y, float* __restrict__ out)
+{
+    const long long pix = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pix >= P) return;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) out[k * P + pix] = __half2float(y[pix * 16 + k]);
+}
+
+// Training targets: slot k < min(cnt, 3) takes the nearest true depth of its
+// pixel within 3 sigma_h (first surface on ties); truth [S][P], NaN = absent.
+__global__ __launch_bounds__(256) void k_cnn_targets(Shape sh, DevState s, const float* __restrict__ truth, int S,
+                                                     float sigma_h, float* __restrict__ tgt, uint8_t* __restrict__ msk)
+{
+    const long long P = sh.P;
+    const long long pix = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pix >= P) return;
+    const int c = min(load_cnt(s.cnt, pix), 3);
+    for (int k = 0; k < 3; ++k) {
+        float tv = 0.f;
+        uint8_t mv = 0;
+        if (k < c) {
+            const double t = s.t[k * P + pix];
+            double bd = 0.0;
+            int bs = -1;
+            for (int q = 0; q < S; ++q) {
+                const float tr = truth[(long long)q * P + pix];
+                if (!(tr == tr)) continue;               // NaN: no such surface
+                const double d = fabs((double)tr - t);
+                if (bs < 0 || d < bd) {
+                    bs = q;
+                    bd = d;
+                }
+            }
+            if (bs >= 0 && bd <= 3.0 * (double)sigma_h) {
+                tv = fminf(fmaxf((float)(((double)truth[(long long)bs * P + pix] - t) / (double)sigma_h), -8.f), 8.f);
+                mv = 1;
+            }
+        }
+        tgt[k * P + pix] = tv;
+        msk[k * P + pix] = mv;
+    }
+}
+
+// Masked squared error: per-block partial sums, and dY = 2 (y - y*) m in FP16
+// (the gradient of the sum; 1/count is applied to the weight gradients).
+__global__ __launch_bounds__(256) void k_cnn_loss(long long P, const __half* __restrict__ y,
+                                                  const float* __restrict__ tgt, const uint8_t* __restrict__ msk,
+                                                  __half* __restrict__ dy, float* __restrict__ lpart)
+{
+    __shared__ float red[2][256];
+    const long long pix = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    float se = 0.f, n = 0.f;
+    if (pix < P) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            float g = 0.f;
+            if (k < 3 && msk[k * P + pix]) {
+                const float d = __half2float(y[pix * 16 + k]) - tgt[k * P + pix];
+                se += d * d;
+                n += 1.f;
+                g = 2.f * d;
+            }
+            dy[pix * 16 + k] = __float2half(g);
+        }
+    }
+    red[0][threadIdx.x] = se;
+    red[1][threadIdx.x] = n;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if (threadIdx.x < w) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + w];
+            red[1][threadIdx.x] += red[1][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        lpart[2 * blockIdx.x] = red[0][0];
+        lpart[2 * blockIdx.x + 1] = red[1][0];
+    }
+}
+
+__global__ __launch_bounds__(64) void k_cnn_loss_final(const float* __restrict__ lpart, int nb, float* __restrict__ out)
+{
+    if (threadIdx.x != 0) return;
+    double se = 0.0, n = 0.0;
+    for (int b = 0; b < nb; ++b) {
+        se += lpart[2 * b];
+        n += lpart[2 * b + 1];
+    }
+    out[0] = (float)(se / (n > 1.0 ? n : 1.0));
+    out[1] = (float)n;
+}
+
+// Adam on the FP32 master weights.
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ w, float* __restrict__ m, float* __restrict__ v,
+                                              const float* __restrict__ g, int n, float lr, float b1, float b2,
+                                              float eps, float c1, float c2)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n) return;
+    const float gi = g[idx];
+    const float mi = b1 * m[idx] + (1.f - b1) * gi;
+    const float vi = b2 * v[idx] + (1.f - b2) * gi * gi;
+    m[idx] = mi;
+    v[idx] = vi;
+    w[idx] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// FP16 kernel layouts from the FP32 master weights of one layer (flat
+// [3][3][cin][cout] then bias[cout]): forward Wt[co][tap * CIS + ci] and
+// backward-data Wb[ci][tap' * COS + co] with tap' = 8 - tap; padded
+// channels are zero.
+__global__ __launch_bounds__(256) void k_cnn_prepare(const float* __restrict__ mw, int cin, int cout, int cis, int cos_,
+                                                     __half* __restrict__ wt, __half* __restrict__ wb,
+                                                     float* __restrict__ bias)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nf = cos_ * 9 * cis;
+    if (idx < nf) {
+        const int co = idx / (9 * cis), k = idx % (9 * cis), tap = k / cis, ci = k % cis;
+        const float v = (co < cout && ci < cin) ? mw[(tap * cin + ci) * cout + co] : 0.f;
+        wt[idx] = __float2half(v);
+        // the same weight in the backward-data layout
+        if (wb) wb[ci * 9 * cos_ + (8 - tap) * cos_ + co] = __float2half(v);
+    }
+    if (idx < cos_) bias[idx] = idx < cout ? mw[9 * cin * cout + idx] : 0.f;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+
+static inline unsigned nb256(long long n) { return (unsigned)((n + 255) / 256); }
+
+static unsigned conv_grid(const Shape& sh) { return (unsigned)(sh.F * sh.rows * ((sh.cols + CT - 1) / CT)); }
+
+unsigned cnn_wgrad_groups(const Shape& sh)
+{
+    return (unsigned)(sh.F * ((sh.rows + WG_ROWS - 1) / WG_ROWS) * ((sh.cols + CT - 1) / CT));
+}
+
+hipError_t launch_cnn_prepare(const CnnWeights& w, hipStream_t st)
+{
+    const float* mw = w.master;
+    for (int l = 0; l < CNN_LAYERS; ++l) {
+        const int nf = CNN_COS[l] * 9 * CNN_CIS[l];
+        hipLaunchKernelGGL(k_cnn_prepare, dim3(nb256(nf)), dim3(256), 0, st, mw, CNN_CIN[l], CNN_COUT[l],
+                           CNN_CIS[l], CNN_COS[l], w.wt[l], l > 0 ? w.wb[l] : nullptr, w.bias[l]);
+        mw += 9 * CNN_CIN[l] * CNN_COUT[l] + CNN_COUT[l];
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_cnn_forward(const Shape& sh, DevState s, float sigma_h, const CnnWeights& w, const CnnBuffers& b,
+                              hipStream_t st)
+{
+    if (sh.P == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cnn_pack, dim3(nb256(sh.P)), dim3(256), 0, st, sh, s, sigma_h, b.act[0]);
+    const unsigned g = conv_grid(sh);
+    hipLaunchKernelGGL((k_conv3x3<16, 32, 0>), dim3(g), dim3(256), 0, st, b.act[0], w.wt[0], w.bias[0], nullptr,
+                       b.act[1], sh.F, sh.rows, sh.cols);
+    hipLaunchKernelGGL((k_conv3x3<32, 32, 0>), dim3(g), dim3(256), 0, st, b.act[1], w.wt[1], w.bias[1], nullptr,
+                       b.act[2], sh.F, sh.rows, sh.cols);
+    hipLaunchKernelGGL((k_conv3x3<32, 32, 0>), dim3(g), dim3(256), 0, st, b.act[2], w.wt[2], w.bias[2], nullptr,
+                       b.act[3], sh.F, sh.rows, sh.cols);
+    hipLaunchKernelGGL((k_conv3x3<32, 16, 1>), dim3(g), dim3(256), 0, st, b.act[3], w.wt[3], w.bias[3], nullptr,
+                       b.act[4], sh.F, sh.rows, sh.cols);
+    return hipGetLastError();
+}
+
+hipError_t launch_cnn_apply(const Shape& sh, const CnnBuffers& b, float sigma_h, double tmax, DevState s,
+                            hipStream_t st)
+{
+    if (sh.P == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cnn_apply, dim3(nb256(sh.P)), dim3(256), 0, st, sh, b.act[4], sigma_h, tmax, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_cnn_unpack(const Shape& sh, const CnnBuffers& b, float* out, hipStream_t st)
+{
+    if (sh.P == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cnn_unpack, dim3(nb256(sh.P)), dim3(256), 0, st, sh.P, b.act[4], out);
+    return hipGetLastError();
+}
+
+hipError_t launch_cnn_train_step(const Shape& sh, DevState s, float sigma_h, const float* truth, int S,
+                                 CnnWeights& w, const CnnBuffers& b, const CnnAdam& opt, float* loss,
+                                 hipStream_t st)
+{
+    if (sh.P == 0) return hipSuccess;
+    hipError_t e = launch_cnn_forward(sh, s, sigma_h, w, b, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cnn_targets, dim3(nb256(sh.P)), dim3(256), 0, st, sh, s, truth, S, sigma_h, b.tgt, b.msk);
+    const unsigned nbl = nb256(sh.P);
+    hipLaunchKernelGGL(k_cnn_loss, dim3(nbl), dim3(256), 0, st, sh.P, b.act[4], b.tgt, b.msk, b.dy16, b.lpart);
+    hipLaunchKernelGGL(k_cnn_loss_final, dim3(1), dim3(64), 0, st, b.lpart, (int)nbl, loss);
+    const unsigned g = conv_grid(sh);
+    const unsigned gw = cnn_wgrad_groups(sh);
+    // layer 3 (32 -> 16 stored): weight gradient, then data gradient into layer 2's output
+    float* grad = b.grad;
+    const int off3 = CNN_OFF[3], off2 = CNN_OFF[2], off1 = CNN_OFF[1], off0 = CNN_OFF[0];
+    hipLaunchKernelGGL((k_conv3x3_wgrad<32, 16>), dim3(gw), dim3(256), 0, st, b.act[3], b.dy16, b.part, b.bpart,
+                       sh.F, sh.rows, sh.cols);
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(nb256(9 * 32 * 3 + 3)), dim3(256), 0, st, b.part, b.bpart, (int)gw, 32, 16,
+                       32, 3, loss + 1, grad + off3);
+    hipLaunchKernelGGL((k_conv3x3<16, 32, 2>), dim3(g), dim3(256), 0, st, b.dy16, w.wb[3], nullptr, b.act[3], b.dA,
+                       sh.F, sh.rows, sh.cols);
+    // layer 2
+    hipLaunchKernelGGL((k_conv3x3_wgrad<32, 32>), dim3(gw), dim3(256), 0, st, b.act[2], b.dA, b.part, b.bpart,
+                       sh.F, sh.rows, sh.cols);
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(nb256(9 * 32 * 32 + 32)), dim3(256), 0, st, b.part, b.bpart, (int)gw, 32,
+                       32, 32, 32, loss + 1, grad + off2);
+    hipLaunchKernelGGL((k_conv3x3<32, 32, 2>), dim3(g), dim3(256), 0, st, b.dA, w.wb[2], nullptr, b.act[2], b.dB,
+                       sh.F, sh.rows, sh.cols);
+    // layer 1
+    hipLaunchKernelGGL((k_conv3x3_wgrad<32, 32>), dim3(gw), dim3(256), 0, st, b.act[1], b.dB, b.part, b.bpart,
+                       sh.F, sh.rows, sh.cols);
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(nb256(9 * 32 * 32 + 32)), dim3(256), 0, st, b.part, b.bpart, (int)gw, 32,
+                       32, 32, 32, loss + 1, grad + off1);
+    hipLaunchKernelGGL((k_conv3x3<32, 32, 2>), dim3(g), dim3(256), 0, st, b.dB, w.wb[1], nullptr, b.act[1], b.dA,
+                       sh.F, sh.rows, sh.cols);
+    // layer 0 (16 -> 32): weight gradient only
+    hipLaunchKernelGGL((k_conv3x3_wgrad<16, 32>), dim3(gw), dim3(256), 0, st, b.act[0], b.dA, b.part, b.bpart,
+                       sh.F, sh.rows, sh.cols);
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(nb256(9 * 16 * 32 + 32)), dim3(256), 0, st, b.part, b.bpart, (int)gw, 16,
+                       32, 16, 32, loss + 1, grad + off0);
+    // Adam, then the FP16 layouts
+    ++w.step;
+    const float c1 = 1.f - powf(opt.beta1, (float)w.step), c2 = 1.f - powf(opt.beta2, (float)w.step);
+    hipLaunchKernelGGL(k_adam, dim3(nb256(CNN_PARAMS)), dim3(256), 0, st, w.master, w.m, w.v, grad, CNN_PARAMS,
+                       opt.lr, opt.beta1, opt.beta2, opt.eps, c1, c2);
+    return launch_cnn_prepare(w, st);
+}
+
+}  // namespace rt3d

@@ -21,6 +21,14 @@
 // at a smaller tau) the best score found.  The bound only counts photons, so
 // it stays valid after photons are claimed.  Only a few blocks per pixel are
 // ever scored exactly, so the cost follows the active bins, not T.
+//
+// When the pooled photons fit (INIT_ELDS entries, T <= INIT_SB x INIT_NB_LDS),
+// they are staged in LDS with the IRF weight tables, the bounds are kept per
+// sub-block of INIT_SB tau (tighter, so fewer 64-tau blocks are scored), a
+// scored sub-block keeps its best in LDS, and after an accepted peak only the
+// sub-blocks that peak changes (tau that can see its claimed bins or fall
+// under its suppression) are scored again.  Otherwise the photons are read from HBM and every round scores
+// afresh.
 #include "rt3d_dev.h"
 
 namespace rt3d {
@@ -72,18 +80,106 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// max q[lo..hi] from the range-maximum table (lo <= hi, both in [0, L)).
-__device__ __forceinline__ int q_range_max(const DevModel& m, int lo, int hi)
+// max q[lo..hi] from the range-maximum table qst (level l: max of 2^l
+// consecutive weights; lo <= hi, both in [0, L)).
+__device__ __forceinline__ int q_range_max(const int* qst, int L, int lo, int hi)
 {
     const int len = hi - lo + 1;
     const int l = 31 - __clz(len);
-    const int a = m.qst[l * m.L + lo], b = m.qst[l * m.L + hi - (1 << l) + 1];
+    const int a = qst[l * L + lo], b = qst[l * L + hi - (1 << l) + 1];
     return a > b ? a : b;
 }
 
 __device__ __forceinline__ int popc_ballot(bool x) { return __popcll(__ballot(x)); }
 
 constexpr int INIT_WAVES = 4;
+constexpr int INIT_ELDS = 1024;   // pooled entries a wavefront scores from LDS; more: branch and bound
+constexpr int INIT_QLDS = 4096;   // IRF weight tables (ints) up to this size are staged in LDS
+constexpr int NO_TAU = 0x7fffffff;
+
+// Per-block tables of the LDS branch and bound, in 8-byte words: score bound,
+// cached best score and cached best tau (int32).
+inline __host__ __device__ size_t init_block_words(int nb) { return 2 * (size_t)nb + ((size_t)nb + 1) / 2; }
+
+// Width (tau) of the sub-blocks the LDS path bounds, and the number of
+// sub-blocks up to which it keeps their tables.
+constexpr int INIT_SB = 16;
+constexpr int INIT_NB_LDS = 512;
+
+// 8-byte LDS words of one wavefront: the pooled CSR ranges, then either the
+// LDS path's block tables and staged photons or the HBM path's block bounds.
+inline __host__ __device__ size_t init_wave_words(int T, int r_init)
+{
+    const size_t nb = (size_t)(T + 63) / 64, nbs = (size_t)(T + INIT_SB - 1) / INIT_SB;
+    const size_t side = 2 * (size_t)r_init + 1;
+    const size_t staged = nbs <= INIT_NB_LDS ? init_block_words((int)nbs) + (size_t)INIT_ELDS / 2 : 0;
+    return side * side + (nb > staged ? nb : staged);
+}
+
+// Levels of the range-maximum table of an IRF of L samples.
+inline __host__ __device__ int q_levels(int L)
+{
+    int n = 1;
+    while ((1 << n) <= L) ++n;
+    return n;
+}
+
+// Exact scores of block bb's 64 tau (one per lane): L(tau) = sum of
+// z q[t - tau + o] over the pooled photons in unclaimed bins t the block can
+// see, [wlo, whi].  Each pooled list (ascending bins, staged in LDS at
+// E[es[l] ..]) is read 64 photons at a time; ballots find the photons inside
+// the window and each is broadcast from the lane that loaded it.  Returns the
+// lane's (score, tau), or (-1, NO_TAU) where tau >= T or an accepted peak
+// suppresses it.
+__device__ __forceinline__ void score_block(const uint32_t* E, const uint2* lists, int npl, int bb,
+                                            const int* qt, int L, int o, int T, const Peaks& pk, int wnms,
+                                            long long& sv, int& st)
+{
+    const int lane = threadIdx.x & 63;
+    const int tau = (bb << 6) + lane;
+    const int wlo = (bb << 6) - o, whi = (bb << 6) + 63 - o + L - 1;
+    long long sc = 0;
+    int es = 0;
+    for (int l = 0; l < npl; ++l) {
+        const uint2 rg = lists[l];
+        const int nl = (int)(rg.y - rg.x);
+        for (int c0 = 0; c0 < nl; c0 += 64) {
+            const int x = c0 + lane;
+            const int vv = x < nl ? (int)E[es + x] : 0;
+            const int t = x < nl ? ent_bin((uint32_t)vv) : NO_TAU;
+            const int k0 = __popcll(__ballot(t < wlo)), k1 = __popcll(__ballot(t <= whi));
+            for (int k = k0; k < k1; ++k) {
+                const uint32_t v = (uint32_t)__builtin_amdgcn_readlane(vv, k);
+                const int tb = ent_bin(v);
+                if (pk.owner(tb) >= 0) continue;
+                const int lag = tb - tau + o;
+                if ((unsigned)lag < (unsigned)L) sc += (long long)ent_cnt(v) * (long long)qt[lag];
+            }
+            if (k1 < 64) break;                  // the rest of the list lies beyond the window
+        }
+        es += nl;
+    }
+    const bool valid = tau < T && !pk.suppressed(tau, wnms);
+    sv = valid ? sc : -1;
+    st = valid ? tau : NO_TAU;
+}
+
+// Argmax of (score, tau) over aligned groups of `width` lanes (a power of
+// two <= 64): largest score, smallest tau on ties; every lane of a group ends
+// with the group's result.
+__device__ __forceinline__ void argmax_reduce(long long& sv, int& st, int width)
+{
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        if (d >= width) continue;
+        const long long ov = __shfl_xor(sv, d, 64);
+        const int ot = __shfl_xor(st, d, 64);
+        if (ov > sv || (ov == sv && ot < st)) {
+            sv = ov;
+            st = ot;
+        }
+    }
+}
 
 __global__ __launch_bounds__(64 * INIT_WAVES) void k_init(DevModel m, DevParams p, Shape sh,
                                                           const uint32_t* __restrict__ off,
@@ -92,14 +188,28 @@ __global__ __launch_bounds__(64 * INIT_WAVES) void k_init(DevModel m, DevParams 
 {
     extern __shared__ unsigned long long smem64[];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int T = m.T, L = m.L, o = m.o;
+    const int R = p.r_init, side = 2 * R + 1;
+    const size_t ww = init_wave_words(T, R);
+    // IRF weights and their range-maximum table, staged by the whole
+    // workgroup before any wavefront leaves
+    const int nq = L * (1 + q_levels(L));
+    int* qs = reinterpret_cast<int*>(smem64 + INIT_WAVES * ww);
+    const bool q_lds = nq <= INIT_QLDS;
+    if (q_lds) {
+        for (int k = threadIdx.x; k < L; k += blockDim.x) qs[k] = m.q[k];
+        for (int k = threadIdx.x; k < nq - L; k += blockDim.x) qs[L + k] = m.qst[k];
+    }
+    __syncthreads();
+    const int* qt = q_lds ? qs : m.q;
+    const int* qstt = q_lds ? qs + L : m.qst;
+
     const long long P = sh.P;
     const long long pix = (long long)blockIdx.x * INIT_WAVES + wv;
     if (pix >= P) return;                       // whole wavefront; no workgroup barriers below
-    const int T = m.T, L = m.L, o = m.o;
     const int nb = (T + 63) >> 6;
-    const int R = p.r_init, side = 2 * R + 1;
-    unsigned long long* ub = smem64 + (size_t)wv * (nb + side * side);
-    uint2* lists = reinterpret_cast<uint2*>(ub + nb);
+    uint2* lists = reinterpret_cast<uint2*>(smem64 + (size_t)wv * ww);
+    unsigned long long* ub = smem64 + (size_t)wv * ww + side * side;
 
     if (lane < KM) {
         s.t[lane * P + pix] = 0.0;
@@ -121,37 +231,18 @@ __global__ __launch_bounds__(64 * INIT_WAVES) void k_init(DevModel m, DevParams 
     const int i = (int)((pix / sh.cols) % sh.rows), j = (int)(pix % sh.cols);
 
     // pooled photon lists: the CSR ranges of the window's pixels
-    int npl = 0;
+    int npl = 0, total = 0;
     for (int i2 = i - R; i2 <= i + R; ++i2) {
         if (i2 < 0 || i2 >= sh.rows) continue;
         for (int j2 = j - R; j2 <= j + R; ++j2) {
             if (j2 < 0 || j2 >= sh.cols) continue;
             const long long pp = (fr * sh.rows + i2) * sh.cols + j2;
-            if (lane == 0) lists[npl] = make_uint2(off[pp], off[pp + 1]);
+            const uint32_t e0 = off[pp], e1 = off[pp + 1];
+            if (lane == 0) lists[npl] = make_uint2(e0, e1);
+            total += (int)(e1 - e0);
             ++npl;
         }
     }
-    for (int b = lane; b < nb; b += 64) ub[b] = 0ull;
-    wave_sync();
-
-    // photon total and per-block score bounds
-    long long ntot = 0;
-    for (int l = 0; l < npl; ++l) {
-        const uint2 rg = lists[l];
-        for (uint32_t e = rg.x + lane; e < rg.y; e += 64) {
-            const uint32_t v = ent[e];
-            const int t = ent_bin(v), z = ent_cnt(v);
-            if (t >= T) continue;
-            ntot += z;
-            const int tlo = max(0, t + o - L + 1), thi = min(T - 1, t + o);
-            for (int b = tlo >> 6; b <= (thi >> 6); ++b) {
-                const int a0 = max(tlo, b << 6), a1 = min(thi, (b << 6) + 63);
-                const int qm = q_range_max(m, t - a1 + o, t - a0 + o);
-                atomicAdd(&ub[b], (unsigned long long)z * (unsigned long long)qm);
-            }
-        }
-    }
-    ntot = wave_sum(ntot);
     wave_sync();
 
     Peaks pk;
@@ -159,92 +250,237 @@ __global__ __launch_bounds__(64 * INIT_WAVES) void k_init(DevModel m, DevParams 
 #pragma unroll
     for (int j = 0; j < KM; ++j) pk.t[j] = pk.a[j] = pk.c[j] = pk.w[j] = 0;
     const double k2 = p.kappa * p.kappa;
-    for (int it = 0; it < p.k_init; ++it) {
-        long long best = -1;
-        int bestt = 0x7fffffff;
-        uint32_t done = 0;                      // bit q: block lane + 64 q scored in this round
-        while (true) {
-            // unscored block with the largest bound (smallest index on ties)
-            unsigned long long bu = 0;
-            int bb = 0x7fffffff;
-            for (int q = 0; lane + 64 * q < nb; ++q) {
-                if ((done >> q) & 1u) continue;
-                const unsigned long long u = ub[lane + 64 * q];
-                if (bb == 0x7fffffff || u > bu) {
-                    bu = u;
-                    bb = lane + 64 * q;
-                }
-            }
-#pragma unroll
-            for (int d = 32; d >= 1; d >>= 1) {
-                const unsigned long long ou = __shfl_xor(bu, d, 64);
-                const int ob = __shfl_xor(bb, d, 64);
-                if (ob != 0x7fffffff && (bb == 0x7fffffff || ou > bu || (ou == bu && ob < bb))) {
-                    bu = ou;
-                    bb = ob;
-                }
-            }
-            if (bb == 0x7fffffff) break;
-            if ((long long)bu < best || ((long long)bu == best && (bb << 6) > bestt)) break;
-            if (lane == (bb & 63)) done |= 1u << (bb >> 6);
-            // exact scores of the block's 64 tau
-            const int tau = (bb << 6) + lane;
-            const int wlo = (bb << 6) - o, whi = (bb << 6) + 63 - o + L - 1;
-            long long sc = 0;
-            for (int l = 0; l < npl; ++l) {
-                const uint2 rg = lists[l];
-                int c0 = 0, c1 = 0;
-                for (uint32_t e0 = rg.x; e0 < rg.y; e0 += 64) {
-                    const uint32_t e = e0 + lane;
-                    const int t = e < rg.y ? ent_bin(ent[e]) : 0x7fffffff;
-                    c0 += popc_ballot(t < wlo);
-                    c1 += popc_ballot(t <= whi);
-                }
-                for (uint32_t x = rg.x + c0; x < rg.x + c1; ++x) {
-                    const uint32_t v = ent[x];
-                    const int tb = ent_bin(v);
-                    if (pk.owner(tb) >= 0) continue;
-                    const int lag = tb - tau + o;
-                    if ((unsigned)lag < (unsigned)L) sc += (long long)ent_cnt(v) * (long long)m.q[lag];
-                }
-            }
-            const bool valid = tau < T && !pk.suppressed(tau, m.wnms);
-            long long sv = valid ? sc : -1;
-            int st = valid ? tau : 0x7fffffff;
-#pragma unroll
-            for (int d = 32; d >= 1; d >>= 1) {
-                const long long ov = __shfl_xor(sv, d, 64);
-                const int ot = __shfl_xor(st, d, 64);
-                if (ov > sv || (ov == sv && ot < st)) {
-                    sv = ov;
-                    st = ot;
-                }
-            }
-            if (st != 0x7fffffff && (sv > best || (sv == best && st < bestt))) {
-                best = sv;
-                bestt = st;
+    long long ntot = 0;
+
+    const int nbs = (T + INIT_SB - 1) / INIT_SB;
+    if (total <= INIT_ELDS && nbs <= INIT_NB_LDS) {
+        // Branch and bound from LDS.  Stage the pooled photon lists; per
+        // sub-block of INIT_SB tau keep a score bound (photons x the largest
+        // weight over the lags the sub-block sees) and, once scored, its exact
+        // best.  The sub-block with the largest bound is scored with the three
+        // others of its 64-tau block (one tau per lane).  After an accepted
+        // peak only sub-blocks whose tau can see its claimed bins or fall under
+        // its suppression lose their best.
+        unsigned long long* bnd = ub;                                   // [nbs] bounds
+        long long* bsc = reinterpret_cast<long long*>(ub + nbs);        // [nbs] cached best score, -2 = none
+        int* btau = reinterpret_cast<int*>(ub + 2 * nbs);               // [nbs] cached best tau
+        uint32_t* E = reinterpret_cast<uint32_t*>(ub + init_block_words(nbs));
+        for (int b = lane; b < nbs; b += 64) {
+            bnd[b] = 0ull;
+            bsc[b] = -2;
+            btau[b] = NO_TAU;
+        }
+        int es = 0;
+        for (int l = 0; l < npl; ++l) {
+            const uint2 rg = lists[l];
+            const int nl = (int)(rg.y - rg.x);
+            for (int x = lane; x < nl; x += 64) E[es + x] = ent[rg.x + x];
+            es += nl;
+        }
+        wave_sync();
+        for (int x = lane; x < total; x += 64) {
+            const uint32_t v = E[x];
+            const int t = ent_bin(v), z = ent_cnt(v);
+            if (t >= T) continue;
+            ntot += z;
+            const int tlo = max(0, t + o - L + 1), thi = min(T - 1, t + o);
+            for (int b = tlo / INIT_SB; b <= thi / INIT_SB; ++b) {
+                const int a0 = max(tlo, b * INIT_SB), a1 = min(thi, b * INIT_SB + INIT_SB - 1);
+                const int qm = q_range_max(qstt, L, t - a1 + o, t - a0 + o);
+                atomicAdd(&bnd[b], (unsigned long long)z * (unsigned long long)qm);
             }
         }
-        if (bestt == 0x7fffffff) break;          // every tau suppressed
-        const int a = max(0, bestt - m.wl), c = min(T - 1, bestt + m.wr);
-        int win = 0;
-        for (int tb = a + lane; tb <= c; tb += 64) win += pk.owner(tb) < 0;
-        win = wave_sum(win);
-        long long nwin = 0;
+        ntot = wave_sum(ntot);
+        wave_sync();
+        for (int it = 0; it < p.k_init; ++it) {
+            // best over the sub-blocks whose exact best is known
+            long long best = -1;
+            int bestt = NO_TAU;
+            for (int b = lane; b < nbs; b += 64) {
+                const long long v = bsc[b];
+                const int t = btau[b];
+                if (v > best || (v == best && t < bestt)) {
+                    best = v;
+                    bestt = t;
+                }
+            }
+            argmax_reduce(best, bestt, 64);
+            while (true) {
+                // unscored sub-block with the largest bound (smallest index on ties)
+                unsigned long long bu = 0;
+                int bb = NO_TAU;
+                for (int b = lane; b < nbs; b += 64) {
+                    if (bsc[b] != -2) continue;
+                    const unsigned long long u = bnd[b];
+                    if (bb == NO_TAU || u > bu) {
+                        bu = u;
+                        bb = b;
+                    }
+                }
+#pragma unroll
+                for (int d = 32; d >= 1; d >>= 1) {
+                    const unsigned long long ou = __shfl_xor(bu, d, 64);
+                    const int ob = __shfl_xor(bb, d, 64);
+                    if (ob != NO_TAU && (bb == NO_TAU || ou > bu || (ou == bu && ob < bb))) {
+                        bu = ou;
+                        bb = ob;
+                    }
+                }
+                if (bb == NO_TAU) break;
+                if ((long long)bu < best || ((long long)bu == best && bb * INIT_SB > bestt)) break;
+                long long sv;
+                int st;
+                const int span = bb * INIT_SB / 64;
+                score_block(E, lists, npl, span, qt, L, o, T, pk, m.wnms, sv, st);
+                argmax_reduce(sv, st, INIT_SB);                  // best of each sub-block
+                const int sb = span * (64 / INIT_SB) + lane / INIT_SB;
+                if (lane % INIT_SB == 0 && sb < nbs) {
+                    bsc[sb] = sv;
+                    btau[sb] = st;
+                }
+                argmax_reduce(sv, st, 64);                       // best of the 64 tau
+                wave_sync();
+                if (st != NO_TAU && (sv > best || (sv == best && st < bestt))) {
+                    best = sv;
+                    bestt = st;
+                }
+            }
+            if (bestt == NO_TAU) break;          // every tau suppressed
+            const int a = max(0, bestt - m.wl), c = min(T - 1, bestt + m.wr);
+            int win = 0;
+            for (int tb = a + lane; tb <= c; tb += 64) win += pk.owner(tb) < 0;
+            win = wave_sum(win);
+            long long nwin = 0;
+            for (int x = lane; x < total; x += 64) {
+                const uint32_t v = E[x];
+                const int tb = ent_bin(v);
+                if (tb >= a && tb <= c && pk.owner(tb) < 0) nwin += ent_cnt(v);
+            }
+            nwin = wave_sum(nwin);
+            const double bw = (double)ntot * (double)win / (double)T;
+            const double d = (double)nwin - bw;
+            const bool accept = win > 0 && nwin >= p.n_min && d >= 0.0 && d * d >= k2 * bw;
+            if (!accept) break;
+            pk.push(bestt, a, c, win);
+            // forget the bests of blocks the new peak changes
+            const int A0 = a + o - L + 1, A1 = c + o, S0 = bestt - m.wnms, S1 = bestt + m.wnms;
+            for (int b = lane; b < nbs; b += 64) {
+                const int ta = b * INIT_SB, tb = b * INIT_SB + INIT_SB - 1;
+                if ((ta <= A1 && tb >= A0) || (ta <= S1 && tb >= S0)) bsc[b] = -2;
+            }
+            wave_sync();
+        }
+    } else {
+        // Branch and bound over blocks of 64 tau, reading the photons from HBM.
+        for (int b = lane; b < nb; b += 64) ub[b] = 0ull;
+        wave_sync();
+
+        // photon total and per-block score bounds
         for (int l = 0; l < npl; ++l) {
             const uint2 rg = lists[l];
             for (uint32_t e = rg.x + lane; e < rg.y; e += 64) {
                 const uint32_t v = ent[e];
-                const int tb = ent_bin(v);
-                if (tb >= a && tb <= c && pk.owner(tb) < 0) nwin += ent_cnt(v);
+                const int t = ent_bin(v), z = ent_cnt(v);
+                if (t >= T) continue;
+                ntot += z;
+                const int tlo = max(0, t + o - L + 1), thi = min(T - 1, t + o);
+                for (int b = tlo >> 6; b <= (thi >> 6); ++b) {
+                    const int a0 = max(tlo, b << 6), a1 = min(thi, (b << 6) + 63);
+                    const int qm = q_range_max(qstt, L, t - a1 + o, t - a0 + o);
+                    atomicAdd(&ub[b], (unsigned long long)z * (unsigned long long)qm);
+                }
             }
         }
-        nwin = wave_sum(nwin);
-        const double bw = (double)ntot * (double)win / (double)T;
-        const double d = (double)nwin - bw;
-        const bool accept = win > 0 && nwin >= p.n_min && d >= 0.0 && d * d >= k2 * bw;
-        if (!accept) break;
-        pk.push(bestt, a, c, win);
+        ntot = wave_sum(ntot);
+        wave_sync();
+
+        for (int it = 0; it < p.k_init; ++it) {
+            long long best = -1;
+            int bestt = 0x7fffffff;
+            uint32_t done = 0;                      // bit q: block lane + 64 q scored in this round
+            while (true) {
+                // unscored block with the largest bound (smallest index on ties)
+                unsigned long long bu = 0;
+                int bb = 0x7fffffff;
+                for (int q = 0; lane + 64 * q < nb; ++q) {
+                    if ((done >> q) & 1u) continue;
+                    const unsigned long long u = ub[lane + 64 * q];
+                    if (bb == 0x7fffffff || u > bu) {
+                        bu = u;
+                        bb = lane + 64 * q;
+                    }
+                }
+#pragma unroll
+                for (int d = 32; d >= 1; d >>= 1) {
+                    const unsigned long long ou = __shfl_xor(bu, d, 64);
+                    const int ob = __shfl_xor(bb, d, 64);
+                    if (ob != 0x7fffffff && (bb == 0x7fffffff || ou > bu || (ou == bu && ob < bb))) {
+                        bu = ou;
+                        bb = ob;
+                    }
+                }
+                if (bb == 0x7fffffff) break;
+                if ((long long)bu < best || ((long long)bu == best && (bb << 6) > bestt)) break;
+                if (lane == (bb & 63)) done |= 1u << (bb >> 6);
+                // exact scores of the block's 64 tau
+                const int tau = (bb << 6) + lane;
+                const int wlo = (bb << 6) - o, whi = (bb << 6) + 63 - o + L - 1;
+                long long sc = 0;
+                for (int l = 0; l < npl; ++l) {
+                    const uint2 rg = lists[l];
+                    int c0 = 0, c1 = 0;
+                    for (uint32_t e0 = rg.x; e0 < rg.y; e0 += 64) {
+                        const uint32_t e = e0 + lane;
+                        const int t = e < rg.y ? ent_bin(ent[e]) : 0x7fffffff;
+                        c0 += popc_ballot(t < wlo);
+                        c1 += popc_ballot(t <= whi);
+                    }
+                    for (uint32_t x = rg.x + c0; x < rg.x + c1; ++x) {
+                        const uint32_t v = ent[x];
+                        const int tb = ent_bin(v);
+                        if (pk.owner(tb) >= 0) continue;
+                        const int lag = tb - tau + o;
+                        if ((unsigned)lag < (unsigned)L) sc += (long long)ent_cnt(v) * (long long)m.q[lag];
+                    }
+                }
+                const bool valid = tau < T && !pk.suppressed(tau, m.wnms);
+                long long sv = valid ? sc : -1;
+                int st = valid ? tau : 0x7fffffff;
+#pragma unroll
+                for (int d = 32; d >= 1; d >>= 1) {
+                    const long long ov = __shfl_xor(sv, d, 64);
+                    const int ot = __shfl_xor(st, d, 64);
+                    if (ov > sv || (ov == sv && ot < st)) {
+                        sv = ov;
+                        st = ot;
+                    }
+                }
+                if (st != 0x7fffffff && (sv > best || (sv == best && st < bestt))) {
+                    best = sv;
+                    bestt = st;
+                }
+            }
+            if (bestt == 0x7fffffff) break;          // every tau suppressed
+            const int a = max(0, bestt - m.wl), c = min(T - 1, bestt + m.wr);
+            int win = 0;
+            for (int tb = a + lane; tb <= c; tb += 64) win += pk.owner(tb) < 0;
+            win = wave_sum(win);
+            long long nwin = 0;
+            for (int l = 0; l < npl; ++l) {
+                const uint2 rg = lists[l];
+                for (uint32_t e = rg.x + lane; e < rg.y; e += 64) {
+                    const uint32_t v = ent[e];
+                    const int tb = ent_bin(v);
+                    if (tb >= a && tb <= c && pk.owner(tb) < 0) nwin += ent_cnt(v);
+                }
+            }
+            nwin = wave_sum(nwin);
+            const double bw = (double)ntot * (double)win / (double)T;
+            const double d = (double)nwin - bw;
+            const bool accept = win > 0 && nwin >= p.n_min && d >= 0.0 && d * d >= k2 * bw;
+            if (!accept) break;
+            pk.push(bestt, a, c, win);
+        }
     }
     const int npk = pk.n;
 
@@ -388,12 +624,12 @@ __global__ __launch_bounds__(256) void k_init_normals(DevParams p, Shape sh, Dev
     }
 }
 
-// LDS bytes of one init workgroup: per wavefront, one 64-bit bound per block of
-// 64 tau and one CSR range per pooled pixel.
-size_t init_lds_bytes(int T, int r_init)
+// LDS bytes of one init workgroup: the wavefronts' areas and the IRF weights.
+size_t init_lds_bytes(int T, int L, int r_init)
 {
-    const size_t nb = (size_t)(T + 63) / 64, side = 2 * (size_t)r_init + 1;
-    return INIT_WAVES * (nb + side * side) * sizeof(unsigned long long);
+    const size_t nq = (size_t)L * (1 + q_levels(L));
+    const size_t qwords = nq <= INIT_QLDS ? (nq + 1) / 2 : 0;
+    return (INIT_WAVES * init_wave_words(T, r_init) + qwords) * sizeof(unsigned long long);
 }
 
 hipError_t launch_init(const DevModel& m, const DevParams& p, const Shape& sh, const uint32_t* off,
@@ -401,7 +637,7 @@ hipError_t launch_init(const DevModel& m, const DevParams& p, const Shape& sh, c
 {
     (void)err;
     if (sh.P == 0) return hipSuccess;
-    const size_t lds = init_lds_bytes(m.T, p.r_init);
+    const size_t lds = init_lds_bytes(m.T, m.L, p.r_init);
     const unsigned nblk = (unsigned)((sh.P + INIT_WAVES - 1) / INIT_WAVES);
     hipLaunchKernelGGL(k_init, dim3(nblk), dim3(64 * INIT_WAVES), lds, st, m, p, sh, off, ent, gain, s);
     return hipGetLastError();

@@ -17,9 +17,10 @@
 //   background: b <- max(b_min, b [(1-beta_b) + beta_b sum z/(lambda T)]).
 // Within a pixel every point uses lambda from before the step (Jacobi).
 //
-// Mapping: one lane per pixel; the lane streams its pixel's active entries
-// (cost linear in active bins, as in the paper's Methods) and keeps the
-// pixel's <= 4 points in registers.  Depth is held in FP64 state and
+// Mapping: four lanes per pixel share its active entries (cost linear in
+// active bins, as in the paper's Methods; consecutive lanes read consecutive
+// entries) and combine their partial sums with wavefront shuffles; every lane
+// keeps the pixel's <= 4 points in registers.  Depth is held in FP64 state and
 // evaluated in FP32 around an integer anchor, so the IRF lookup error stays
 // at FP32 rounding of the local offset whatever T is.
 #include "rt3d_dev.h"
@@ -54,20 +55,23 @@ __device__ __forceinline__ void load_points(const DevState& s, long long P, long
     }
 }
 
-// Accumulates over the pixel's entries: sz = sum z/lambda, sh[k] = sum z h_k/lambda,
-// shp[k] = sum z h'_k/lambda (and the absolute-term sums when ABS).
-template <bool ABS>
+// Lanes per pixel: a pixel's active entries are split over LPP consecutive
+// lanes (entry e + LPP i), whose partial sums meet in a shuffle tree.
+constexpr int LPP = 4;
+
+// Partial sums over the entries e0, e0 + LPP, ... < e1 of one pixel:
+// sz = sum z/lambda, sh[k] = sum z h_k/lambda, shp[k] = sum z h'_k/lambda.
 __device__ __forceinline__ void accumulate(const DevModel& m, const PixPoints& q, float bb, float G,
                                            const uint32_t* __restrict__ ent, uint32_t e0, uint32_t e1,
-                                           float& sz, float (&sh)[KM], float (&shp)[KM], float (&ahp)[KM])
+                                           float& sz, float (&sh)[KM], float (&shp)[KM])
 {
     sz = 0.f;
 #pragma unroll
     for (int k = 0; k < KM; ++k) {
         sh[k] = 0.f;
         shp[k] = 0.f;
-        ahp[k] = 0.f;
     }
+    const float invG = 1.f / G;
     auto one = [&](uint32_t v) {
         const int tb = ent_bin(v);
         const float z = (float)ent_cnt(v);
@@ -82,27 +86,69 @@ __device__ __forceinline__ void accumulate(const DevModel& m, const PixPoints& q
                 lam = fmaf(q.r[k], h[k], lam);
             }
         }
-        const float zl = z * __builtin_amdgcn_rcpf(lam * G);
+        const float zl = z * invG * __builtin_amdgcn_rcpf(lam);
         sz += zl;
 #pragma unroll
         for (int k = 0; k < KM; ++k) {
             if (k < q.c) {
                 sh[k] = fmaf(zl, h[k], sh[k]);
                 shp[k] = fmaf(zl, hp[k], shp[k]);
-                if (ABS) ahp[k] = fmaf(zl, fabsf(hp[k]), ahp[k]);
             }
         }
     };
-    // eight entries in flight per lane, then the tail
+    // four entries in flight per lane, then the tail
     uint32_t e = e0;
-    for (; e + 8 <= e1; e += 8) {
-        uint32_t v[8];
+    for (; e + 3 * LPP < e1; e += 4 * LPP) {
+        uint32_t v[4];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = ent[e + u];
+        for (int u = 0; u < 4; ++u) v[u] = ent[e + u * LPP];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) one(v[u]);
+        for (int u = 0; u < 4; ++u) one(v[u]);
     }
-    for (; e < e1; ++e) one(ent[e]);
+    for (; e < e1; e += LPP) one(ent[e]);
+}
+
+// Sums the partials of the LPP lanes of a pixel (every lane ends with the total).
+__device__ __forceinline__ void reduce_lanes(float& sz, float (&sh)[KM], float (&shp)[KM])
+{
+#pragma unroll
+    for (int d = 1; d < LPP; d <<= 1) {
+        sz += __shfl_xor(sz, d, 64);
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+            sh[k] += __shfl_xor(sh[k], d, 64);
+            shp[k] += __shfl_xor(shp[k], d, 64);
+        }
+    }
+}
+
+// Common prologue: the pixel of this lane, its points and its entry range.
+struct Lane {
+    long long pix;
+    int sub;
+    bool live;
+    float G;
+    PixPoints q;
+    uint32_t e0, e1;
+};
+
+__device__ __forceinline__ Lane lane_setup(const DevState& s, long long P, const uint32_t* __restrict__ off,
+                                           const float* __restrict__ gain, bool need_points)
+{
+    Lane L;
+    const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    L.pix = gid / LPP;
+    L.sub = (int)(gid % LPP);
+    L.live = L.pix < P;
+    const long long pp = L.live ? L.pix : 0;
+    L.G = L.live ? (gain ? gain[pp] : 1.f) : 0.f;
+    load_points(s, P, pp, L.q);
+    if (!L.live) L.q.c = 0;
+    const bool work = L.live && L.G > 0.f && (!need_points || L.q.c > 0);
+    L.e0 = work ? off[pp] + L.sub : 0;
+    L.e1 = work ? off[pp + 1] : 0;
+    L.live = work;
+    return L;
 }
 
 __global__ __launch_bounds__(256) void k_depth_step(DevModel m, DevParams p, Shape sh,
@@ -111,27 +157,24 @@ __global__ __launch_bounds__(256) void k_depth_step(DevModel m, DevParams p, Sha
                                                     const float* __restrict__ gain, DevState s)
 {
     const long long P = sh.P;
-    const long long pix = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (pix >= P) return;
-    const float G = gain ? gain[pix] : 1.f;
-    PixPoints q;
-    load_points(s, P, pix, q);
-    if (q.c == 0 || !(G > 0.f)) return;
-    float sz, shh[KM], shp[KM], ahp[KM];
-    accumulate<false>(m, q, s.b[pix], G, ent, off[pix], off[pix + 1], sz, shh, shp, ahp);
+    const Lane L = lane_setup(s, P, off, gain, true);
+    float sz, shh[KM], shp[KM];
+    accumulate(m, L.q, L.live ? s.b[L.pix] : 1.f, L.live ? L.G : 1.f, ent, L.e0, L.e1, sz, shh, shp);
+    reduce_lanes(sz, shh, shp);
+    if (!L.live || L.sub != 0) return;
     const float scale = (float)p.beta_t * m.fisher_inv;
     const float dmax = (float)p.dmax;
     const double tmax = (double)(m.T - 1);
 #pragma unroll
     for (int k = 0; k < KM; ++k) {
-        if (k < q.c && q.r[k] > 0.f) {
+        if (k < L.q.c && L.q.r[k] > 0.f) {
             float S, Sp;
-            s_eval(m, q.t[k], S, Sp);
+            s_eval(m, L.q.t[k], S, Sp);
             float step = -scale * (Sp + shp[k]);
             step = fminf(fmaxf(step, -dmax), dmax);
-            double tn = q.t[k] + (double)step;
+            double tn = L.q.t[k] + (double)step;
             tn = tn < 0.0 ? 0.0 : (tn > tmax ? tmax : tn);
-            s.t[k * P + pix] = tn;
+            s.t[k * P + L.pix] = tn;
         }
     }
 }
@@ -142,23 +185,20 @@ __global__ __launch_bounds__(256) void k_intensity_step(DevModel m, DevParams p,
                                                         const float* __restrict__ gain, DevState s)
 {
     const long long P = sh.P;
-    const long long pix = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (pix >= P) return;
-    const float G = gain ? gain[pix] : 1.f;
-    PixPoints q;
-    load_points(s, P, pix, q);
-    if (q.c == 0 || !(G > 0.f)) return;
-    float sz, shh[KM], shp[KM], ahp[KM];
-    accumulate<false>(m, q, s.b[pix], G, ent, off[pix], off[pix + 1], sz, shh, shp, ahp);
+    const Lane L = lane_setup(s, P, off, gain, true);
+    float sz, shh[KM], shp[KM];
+    accumulate(m, L.q, L.live ? s.b[L.pix] : 1.f, L.live ? L.G : 1.f, ent, L.e0, L.e1, sz, shh, shp);
+    reduce_lanes(sz, shh, shp);
+    if (!L.live || L.sub != 0) return;
     const float br = (float)p.beta_r;
 #pragma unroll
     for (int k = 0; k < KM; ++k) {
-        if (k < q.c) {
+        if (k < L.q.c) {
             float S, Sp;
-            s_eval(m, q.t[k], S, Sp);
+            s_eval(m, L.q.t[k], S, Sp);
             if (S > 0.f) {
-                float v = q.r[k] * ((1.f - br) + br * shh[k] / S);
-                s.r[k * P + pix] = fmaxf(v, 0.f);
+                const float v = L.q.r[k] * ((1.f - br) + br * shh[k] / S);
+                s.r[k * P + L.pix] = fmaxf(v, 0.f);
             }
         }
     }
@@ -170,18 +210,15 @@ __global__ __launch_bounds__(256) void k_bg_step(DevModel m, DevParams p, Shape 
                                                  const float* __restrict__ gain, DevState s)
 {
     const long long P = sh.P;
-    const long long pix = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (pix >= P) return;
-    const float G = gain ? gain[pix] : 1.f;
-    if (!(G > 0.f)) return;
-    PixPoints q;
-    load_points(s, P, pix, q);
-    float sz, shh[KM], shp[KM], ahp[KM];
-    const float bb = s.b[pix];
-    accumulate<false>(m, q, bb, G, ent, off[pix], off[pix + 1], sz, shh, shp, ahp);
+    const Lane L = lane_setup(s, P, off, gain, false);
+    const float bb = L.live ? s.b[L.pix] : 1.f;
+    float sz, shh[KM], shp[KM];
+    accumulate(m, L.q, bb, L.live ? L.G : 1.f, ent, L.e0, L.e1, sz, shh, shp);
+    reduce_lanes(sz, shh, shp);
+    if (!L.live || L.sub != 0) return;
     const float bt = (float)p.beta_b;
     const float v = bb * ((1.f - bt) + bt * sz / (float)m.T);
-    s.b[pix] = fmaxf(v, (float)p.b_min);
+    s.b[L.pix] = fmaxf(v, (float)p.b_min);
 }
 
 __global__ __launch_bounds__(256) void k_gradients(DevModel m, Shape sh, const uint32_t* __restrict__ off,
@@ -191,26 +228,25 @@ __global__ __launch_bounds__(256) void k_gradients(DevModel m, Shape sh, const u
                                                    float* __restrict__ gb)
 {
     const long long P = sh.P;
-    const long long pix = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (pix >= P) return;
-    const float G = gain ? gain[pix] : 1.f;
-    PixPoints q;
-    load_points(s, P, pix, q);
-    float sz = 0.f, shh[KM] = {0, 0, 0, 0}, shp[KM] = {0, 0, 0, 0}, ahp[KM];
-    if (G > 0.f) accumulate<false>(m, q, s.b[pix], G, ent, off[pix], off[pix + 1], sz, shh, shp, ahp);
+    const Lane L = lane_setup(s, P, off, gain, false);
+    float sz, shh[KM], shp[KM];
+    accumulate(m, L.q, L.live ? s.b[L.pix] : 1.f, L.live ? L.G : 1.f, ent, L.e0, L.e1, sz, shh, shp);
+    reduce_lanes(sz, shh, shp);
+    if (L.pix >= P || L.sub != 0) return;
+    const float G = L.G;
 #pragma unroll
     for (int k = 0; k < KM; ++k) {
         float vt = 0.f, vr = 0.f;
-        if (k < q.c && G > 0.f) {
+        if (k < L.q.c && G > 0.f) {
             float S, Sp;
-            s_eval(m, q.t[k], S, Sp);
-            vt = G * q.r[k] * (Sp + shp[k]);
+            s_eval(m, L.q.t[k], S, Sp);
+            vt = G * L.q.r[k] * (Sp + shp[k]);
             vr = G * (S - shh[k]);
         }
-        gt[k * P + pix] = vt;
-        gr[k * P + pix] = vr;
+        gt[k * P + L.pix] = vt;
+        gr[k * P + L.pix] = vr;
     }
-    gb[pix] = G > 0.f ? G * ((float)m.T - sz) : 0.f;
+    gb[L.pix] = G > 0.f ? G * ((float)m.T - sz) : 0.f;
 }
 
 static inline unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
@@ -219,7 +255,8 @@ hipError_t launch_depth_step(const DevModel& m, const DevParams& p, const Shape&
                              const uint32_t* ent, const float* gain, DevState s, hipStream_t st)
 {
     if (sh.P == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_depth_step, dim3(blocks_for(sh.P, 256)), dim3(256), 0, st, m, p, sh, off, ent, gain, s);
+    hipLaunchKernelGGL(k_depth_step, dim3(blocks_for(sh.P * LPP, 256)), dim3(256), 0, st, m, p, sh, off, ent, gain,
+                       s);
     return hipGetLastError();
 }
 
@@ -227,8 +264,8 @@ hipError_t launch_intensity_step(const DevModel& m, const DevParams& p, const Sh
                                  const uint32_t* ent, const float* gain, DevState s, hipStream_t st)
 {
     if (sh.P == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_intensity_step, dim3(blocks_for(sh.P, 256)), dim3(256), 0, st, m, p, sh, off, ent, gain,
-                       s);
+    hipLaunchKernelGGL(k_intensity_step, dim3(blocks_for(sh.P * LPP, 256)), dim3(256), 0, st, m, p, sh, off, ent,
+                       gain, s);
     return hipGetLastError();
 }
 
@@ -236,7 +273,7 @@ hipError_t launch_bg_step(const DevModel& m, const DevParams& p, const Shape& sh
                           const uint32_t* ent, const float* gain, DevState s, hipStream_t st)
 {
     if (sh.P == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bg_step, dim3(blocks_for(sh.P, 256)), dim3(256), 0, st, m, p, sh, off, ent, gain, s);
+    hipLaunchKernelGGL(k_bg_step, dim3(blocks_for(sh.P * LPP, 256)), dim3(256), 0, st, m, p, sh, off, ent, gain, s);
     return hipGetLastError();
 }
 
@@ -246,8 +283,8 @@ hipError_t launch_gradients(const DevModel& m, const DevParams& p, const Shape& 
 {
     (void)p;
     if (sh.P == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gradients, dim3(blocks_for(sh.P, 256)), dim3(256), 0, st, m, sh, off, ent, gain, s, gt,
-                       gr, gb);
+    hipLaunchKernelGGL(k_gradients, dim3(blocks_for(sh.P * LPP, 256)), dim3(256), 0, st, m, sh, off, ent, gain, s,
+                       gt, gr, gb);
     return hipGetLastError();
 }
 

@@ -140,6 +140,10 @@ hipError_t launch_compact(const uint16_t* Z, long long P, int T, uint32_t* off, 
                           uint64_t cap, uint32_t* counts, uint32_t* partial, int32_t* err,
                           hipStream_t st);
 
+hipError_t launch_compact_events(const uint32_t* pix, const uint16_t* bin, uint64_t n, long long P, int T,
+                                 uint32_t* evoff, uint32_t* scratch, uint32_t* off, uint32_t* ent, uint64_t cap,
+                                 uint32_t* counts, uint32_t* partial, int32_t* err, hipStream_t st);
+
 hipError_t launch_init(const DevModel& m, const DevParams& p, const Shape& sh, const uint32_t* off,
                        const uint32_t* ent, const float* gain, DevState s, int32_t* err,
                        hipStream_t st);
@@ -158,8 +162,9 @@ hipError_t launch_gradients(const DevModel& m, const DevParams& p, const Shape& 
                             const uint32_t* off, const uint32_t* ent, const float* gain,
                             DevState s, float* gt, float* gr, float* gb, hipStream_t st);
 
+// only_above >= 0: pixels with at most that many points are copied, not fitted
 hipError_t launch_apss(const DevModel& m, const DevParams& p, const Shape& sh, DevState in,
-                       DevState out, hipStream_t st);
+                       DevState out, int only_above, hipStream_t st);
 hipError_t launch_merge(const DevParams& p, const Shape& sh, DevState s, hipStream_t st);
 hipError_t launch_ifilter(const DevParams& p, const Shape& sh, DevState in, DevState out,
                           hipStream_t st);

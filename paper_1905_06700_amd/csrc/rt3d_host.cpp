@@ -12,9 +12,10 @@
 #include <vector>
 
 #include "rt3d_dev.h"
+#include "rt3d_cnn.h"
 
 namespace rt3d {
-size_t init_lds_bytes(int T, int r_init);
+size_t init_lds_bytes(int T, int L, int r_init);
 }
 
 using namespace rt3d;
@@ -38,10 +39,15 @@ struct rt3d_ctx {
     uint8_t* ws = nullptr;
     size_t ws_bytes = 0;
     long long ws_P = 0;
+    uint32_t ws_rows = 1, ws_cols = 1;
+    unsigned ws_cnn_groups = 0;        // weight-gradient partial groups the workspace holds
     uint64_t ws_E = 0;
     // last call facts
     long long last_P = 0;
     bool last_compacted = false;
+    // learned denoiser weights (always allocated; zero until set)
+    CnnWeights cnn;
+    bool cnn_set = false;
     // kernel timing (rt3d_profile)
     int prof_id = -1;
     std::vector<hipEvent_t> prof_ev;   // start/end pairs
@@ -60,15 +66,17 @@ struct Workspace {
     uint32_t* ent;
     uint32_t* counts;
     uint32_t* partial;
+    uint32_t* evoff;
     DevState A, B;
     float* btmp;
+    CnnBuffers cnn;
     int32_t* err;
     size_t bytes;
 };
 
 // Carves the workspace for P pixels and E entries; with base == nullptr it
 // only measures.
-Workspace carve(uint8_t* base, long long P, uint64_t E)
+Workspace carve(uint8_t* base, long long P, uint64_t E, bool with_cnn = false, unsigned cnn_groups = 0)
 {
     Workspace w{};
     size_t at = 0;
@@ -82,6 +90,7 @@ Workspace carve(uint8_t* base, long long P, uint64_t E)
     w.ent = (uint32_t*)take(sizeof(uint32_t) * std::max<uint64_t>(E, 1));
     w.counts = (uint32_t*)take(sizeof(uint32_t) * std::max<long long>(P, 1));
     w.partial = (uint32_t*)take(sizeof(uint32_t) * scan_partial_elems(P));
+    w.evoff = (uint32_t*)take(sizeof(uint32_t) * (P + 1));
     for (DevState* s : {&w.A, &w.B}) {
         s->t = (double*)take(sizeof(double) * KM * P);
         s->r = (float*)take(sizeof(float) * KM * P);
@@ -90,6 +99,21 @@ Workspace carve(uint8_t* base, long long P, uint64_t E)
         s->b = (float*)take(sizeof(float) * P);
     }
     w.btmp = (float*)take(sizeof(float) * P);
+    if (with_cnn) {
+        const size_t nb = (size_t)((P + 255) / 256);
+        w.cnn.act[0] = (__half*)take(sizeof(__half) * 16 * P);
+        for (int l = 1; l <= 3; ++l) w.cnn.act[l] = (__half*)take(sizeof(__half) * 32 * P);
+        w.cnn.act[4] = (__half*)take(sizeof(__half) * 16 * P);
+        w.cnn.dy16 = (__half*)take(sizeof(__half) * 16 * P);
+        w.cnn.dA = (__half*)take(sizeof(__half) * 32 * P);
+        w.cnn.dB = (__half*)take(sizeof(__half) * 32 * P);
+        w.cnn.tgt = (float*)take(sizeof(float) * 3 * P);
+        w.cnn.msk = (uint8_t*)take(3 * P);
+        w.cnn.lpart = (float*)take(sizeof(float) * 2 * nb);
+        w.cnn.part = (float*)take(sizeof(float) * (size_t)cnn_groups * 9 * 32 * 32);
+        w.cnn.bpart = (float*)take(sizeof(float) * (size_t)cnn_groups * 32);
+        w.cnn.grad = (float*)take(sizeof(float) * CNN_PARAMS);
+    }
     w.bytes = at;
     return w;
 }
@@ -193,7 +217,7 @@ rt3d_status check_params(const rt3d_params* p, uint32_t bins, std::string& why)
     if (!(p->sigma_b >= 0) || p->sigma_b > 64) { why = "sigma_b outside [0, 64]"; return RT3D_E_INVALID; }
     if (!(p->sbr_guess > 0)) { why = "sbr_guess must be > 0"; return RT3D_E_INVALID; }
     if (p->r_init < 0 || p->r_init > 8) { why = "r_init outside 0..8"; return RT3D_E_INVALID; }
-    if (p->denoiser != RT3D_DENOISE_APSS && p->denoiser != RT3D_DENOISE_NONE) {
+    if (p->denoiser != RT3D_DENOISE_APSS && p->denoiser != RT3D_DENOISE_NONE && p->denoiser != RT3D_DENOISE_CNN) {
         why = "unknown denoiser"; return RT3D_E_UNSUPPORTED;
     }
     if (std::ceil(p->h_apss / p->p_xy) > 16) { why = "h_apss / p_xy above 16 pixels"; return RT3D_E_UNSUPPORTED; }
@@ -205,11 +229,28 @@ rt3d_status check_params(const rt3d_params* p, uint32_t bins, std::string& why)
     return RT3D_OK;
 }
 
+bool uses_cnn(const rt3d_ctx* c) { return c->p.denoiser == RT3D_DENOISE_CNN; }
+
+// Workspace of a context for P pixels of rows x cols frames and E entries.
+Workspace carve_ctx(const rt3d_ctx* c, uint8_t* base, long long P, uint64_t E, uint32_t rows, uint32_t cols)
+{
+    unsigned groups = 0;
+    if (uses_cnn(c)) {
+        Shape sh;
+        sh.rows = (int)rows;
+        sh.cols = (int)cols;
+        sh.F = (int)(P / ((long long)rows * cols));
+        sh.P = P;
+        groups = cnn_wgrad_groups(sh);
+    }
+    return carve(base, P, E, uses_cnn(c), groups);
+}
+
 rt3d_status need_ws(rt3d_ctx* c, long long P, Workspace& w)
 {
     if (!c->ws) return fail(c, RT3D_E_NOMEM, "no workspace bound (rt3d_set_workspace)");
     if (P > c->ws_P) return fail(c, RT3D_E_NOMEM, "batch larger than the workspace was sized for");
-    w = carve(c->ws, c->ws_P, c->ws_E);
+    w = carve_ctx(c, c->ws, c->ws_P, c->ws_E, c->ws_rows, c->ws_cols);
     return RT3D_OK;
 }
 
@@ -238,14 +279,20 @@ Shape shape_of(uint32_t F, uint32_t rows, uint32_t cols)
 
 // One iteration of the loop on state A (in/out) with B as the second buffer.
 rt3d_status iterate(rt3d_ctx* c, const Shape& sh, const uint32_t* off, const uint32_t* ent, const float* gain,
-                    DevState A, DevState B, float* btmp, hipStream_t st)
+                    DevState A, DevState B, float* btmp, const CnnBuffers* cnn, hipStream_t st)
 {
     const DevModel m = dev_model(c);
     const DevParams p = dev_params(c);
     RT3D_LAUNCH(c, RT3D_KERNEL_DEPTH, st, launch_depth_step(m, p, sh, off, ent, gain, A, st));
     DevState cur = A;
     if (c->p.denoiser == RT3D_DENOISE_APSS) {
-        RT3D_LAUNCH(c, RT3D_KERNEL_APSS, st, launch_apss(m, p, sh, A, B, st));
+        RT3D_LAUNCH(c, RT3D_KERNEL_APSS, st, launch_apss(m, p, sh, A, B, -1, st));
+        cur = B;
+    } else if (c->p.denoiser == RT3D_DENOISE_CNN) {
+        // APSS only for pixels holding more points than the network's three slots
+        RT3D_LAUNCH(c, RT3D_KERNEL_APSS, st, launch_apss(m, p, sh, A, B, 3, st));
+        RT3D_LAUNCH(c, RT3D_KERNEL_CNN, st, launch_cnn_forward(sh, B, (float)std::sqrt(c->sigma2), c->cnn, *cnn, st));
+        RT3D_HIP(c, launch_cnn_apply(sh, *cnn, (float)std::sqrt(c->sigma2), (double)(c->T - 1), B, st));
         cur = B;
     } else {
         RT3D_HIP(c, launch_copy_state(sh, A, B, st));
@@ -308,7 +355,7 @@ rt3d_status rt3d_create(const double* irf, uint32_t irf_len, int32_t irf_origin,
     }
     if (!(sum > 0.0)) return RT3D_E_INVALID;
     if (irf_origin >= (int32_t)irf_len) return RT3D_E_INVALID;
-    if (init_lds_bytes((int)bins, p->r_init) > 65536) return RT3D_E_UNSUPPORTED;
+    if (init_lds_bytes((int)bins, (int)irf_len, p->r_init) > 65536) return RT3D_E_UNSUPPORTED;
 
     rt3d_ctx* c = new (std::nothrow) rt3d_ctx();
     if (!c) return RT3D_E_NOMEM;
@@ -432,6 +479,22 @@ rt3d_status rt3d_create(const double* irf, uint32_t irf_len, int32_t irf_origin,
     if (e == hipSuccess) e = hipMemcpy(c->d_qst, qst.data(), sizeof(int32_t) * qst.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->d_hbar, c->hbar.data(), sizeof(double) * L, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->d_bw, bw.data(), sizeof(float) * bw.size(), hipMemcpyHostToDevice);
+    // learned-denoiser weights: FP32 master, Adam moments, FP16 layouts, biases (all zero)
+    if (e == hipSuccess) e = hipMalloc(&c->cnn.master, sizeof(float) * 3 * CNN_PARAMS);
+    if (e == hipSuccess) {
+        c->cnn.m = c->cnn.master + CNN_PARAMS;
+        c->cnn.v = c->cnn.master + 2 * CNN_PARAMS;
+        e = hipMemset(c->cnn.master, 0, sizeof(float) * 3 * CNN_PARAMS);
+    }
+    for (int l = 0; l < CNN_LAYERS && e == hipSuccess; ++l) {
+        const size_t nw = (size_t)CNN_COS[l] * 9 * CNN_CIS[l];
+        e = hipMalloc(&c->cnn.wt[l], sizeof(__half) * nw);
+        if (e == hipSuccess) e = hipMemset(c->cnn.wt[l], 0, sizeof(__half) * nw);
+        if (e == hipSuccess && l > 0) e = hipMalloc(&c->cnn.wb[l], sizeof(__half) * nw);
+        if (e == hipSuccess && l > 0) e = hipMemset(c->cnn.wb[l], 0, sizeof(__half) * nw);
+        if (e == hipSuccess) e = hipMalloc(&c->cnn.bias[l], sizeof(float) * CNN_COS[l]);
+        if (e == hipSuccess) e = hipMemset(c->cnn.bias[l], 0, sizeof(float) * CNN_COS[l]);
+    }
     if (e != hipSuccess) {
         rt3d_destroy(c);
         return RT3D_E_DEVICE;
@@ -475,6 +538,12 @@ void rt3d_destroy(rt3d_ctx* c)
     if (c->d_hbar) (void)hipFree(c->d_hbar);
     if (c->d_bw) (void)hipFree(c->d_bw);
     for (hipEvent_t ev : c->prof_ev) (void)hipEventDestroy(ev);
+    if (c->cnn.master) (void)hipFree(c->cnn.master);
+    for (int l = 0; l < CNN_LAYERS; ++l) {
+        if (c->cnn.wt[l]) (void)hipFree(c->cnn.wt[l]);
+        if (c->cnn.wb[l]) (void)hipFree(c->cnn.wb[l]);
+        if (c->cnn.bias[l]) (void)hipFree(c->cnn.bias[l]);
+    }
     if (switched) (void)hipSetDevice(prev);
     delete c;
 }
@@ -487,7 +556,7 @@ size_t rt3d_workspace_bytes(const rt3d_ctx* c, uint32_t frames, uint32_t rows, u
 {
     if (!c) return 0;
     const long long P = (long long)frames * rows * cols;
-    return carve(nullptr, P, max_entries).bytes;
+    return carve_ctx(c, nullptr, P, max_entries, rows, cols).bytes;
 }
 
 rt3d_status rt3d_set_workspace(rt3d_ctx* c, void* dev_ptr, size_t bytes, uint32_t frames, uint32_t rows,
@@ -502,15 +571,21 @@ rt3d_status rt3d_set_workspace(rt3d_ctx* c, void* dev_ptr, size_t bytes, uint32_
     if (max_entries >= (1ull << 32)) return fail(c, RT3D_E_INVALID, "max_entries must be < 2^32");
     const long long P = (long long)frames * rows * cols;
     if (P <= 0) return fail(c, RT3D_E_INVALID, "zero frames, rows or cols");
-    if (carve(nullptr, P, max_entries).bytes > bytes)
+    if (carve_ctx(c, nullptr, P, max_entries, rows, cols).bytes > bytes)
         return fail(c, RT3D_E_NOMEM, "workspace smaller than rt3d_workspace_bytes for this shape");
-    Workspace w = carve((uint8_t*)dev_ptr, P, max_entries);
+    Workspace w = carve_ctx(c, (uint8_t*)dev_ptr, P, max_entries, rows, cols);
     hipError_t e = hipMemset(w.err, 0, sizeof(int32_t) * 4);
     if (e != hipSuccess) return hip_fail(c, e, "hipMemset(workspace error word)");
     c->ws = (uint8_t*)dev_ptr;
     c->ws_bytes = bytes;
     c->ws_P = P;
     c->ws_E = max_entries;
+    c->ws_rows = rows;
+    c->ws_cols = cols;
+    {
+        Shape sh = shape_of(frames, rows, cols);
+        c->ws_cnn_groups = uses_cnn(c) ? cnn_wgrad_groups(sh) : 0;
+    }
     return RT3D_OK;
 }
 
@@ -547,6 +622,16 @@ rt3d_status rt3d_reconstruct(rt3d_ctx* c, const rt3d_input* in, rt3d_output* out
         off = in->off;
         ent = in->ent;
         c->last_compacted = false;
+    } else if (in->kind == RT3D_IN_PHOTON_EVENTS) {
+        if (in->n_events >= (1ull << 31)) return fail(c, RT3D_E_INVALID, "n_events must be < 2^31");
+        if (in->n_events > 0 && (!in->ev_pixel || !in->ev_bin || !in->ev_scratch))
+            return fail(c, RT3D_E_INVALID, "ev_pixel/ev_bin/ev_scratch is NULL");
+        RT3D_LAUNCH(c, RT3D_KERNEL_COMPACT, st,
+                    launch_compact_events(in->ev_pixel, in->ev_bin, in->n_events, sh.P, c->T, w.evoff,
+                                          in->ev_scratch, w.off, w.ent, c->ws_E, w.counts, w.partial, w.err, st));
+        off = w.off;
+        ent = w.ent;
+        c->last_compacted = true;
     } else {
         return fail(c, RT3D_E_UNSUPPORTED, "unknown input kind");
     }
@@ -556,7 +641,7 @@ rt3d_status rt3d_reconstruct(rt3d_ctx* c, const rt3d_input* in, rt3d_output* out
     RT3D_LAUNCH(c, RT3D_KERNEL_INIT, st, launch_init(m, p, sh, off, ent, in->gain, w.A, w.err, st));
     RT3D_LAUNCH(c, RT3D_KERNEL_NORMALS, st, launch_init_normals(p, sh, w.A, st));
     for (int it = 0; it < c->p.n_iter; ++it) {
-        s = iterate(c, sh, off, ent, in->gain, w.A, w.B, w.btmp, st);
+        s = iterate(c, sh, off, ent, in->gain, w.A, w.B, w.btmp, &w.cnn, st);
         if (s != RT3D_OK) return s;
     }
     RT3D_LAUNCH(c, RT3D_KERNEL_OUTPUT, st, launch_output(sh, w.A, out, w.counts, w.partial, w.err, st));
@@ -571,7 +656,7 @@ rt3d_status rt3d_query(rt3d_ctx* c, void* hip_stream, rt3d_stats* st)
     int32_t derr = 0;
     uint32_t E = 0;
     if (c->ws) {
-        Workspace w = carve(c->ws, c->ws_P, c->ws_E);
+        Workspace w = carve_ctx(c, c->ws, c->ws_P, c->ws_E, c->ws_rows, c->ws_cols);
         RT3D_HIP(c, hipMemcpy(&derr, w.err, sizeof(int32_t), hipMemcpyDeviceToHost));
         if (c->last_compacted && c->last_P > 0)
             RT3D_HIP(c, hipMemcpy(&E, w.off + c->last_P, sizeof(uint32_t), hipMemcpyDeviceToHost));
@@ -600,6 +685,23 @@ rt3d_status rt3d_debug_compact(rt3d_ctx* c, const uint16_t* hist, uint32_t npix,
     return RT3D_OK;
 }
 
+rt3d_status rt3d_debug_compact_events(rt3d_ctx* c, const uint32_t* ev_pixel, const uint16_t* ev_bin,
+                                      uint64_t n_events, uint32_t npix, uint32_t* ev_scratch, uint32_t* off,
+                                      uint32_t* ent, uint64_t capacity, void* hip_stream)
+{
+    if (!c) return RT3D_E_INVALID;
+    if (!off || !ent || npix == 0 || capacity == 0) return fail(c, RT3D_E_INVALID, "NULL pointer or zero size");
+    if (n_events >= (1ull << 31)) return fail(c, RT3D_E_INVALID, "n_events must be < 2^31");
+    if (n_events > 0 && (!ev_pixel || !ev_bin || !ev_scratch))
+        return fail(c, RT3D_E_INVALID, "ev_pixel/ev_bin/ev_scratch is NULL");
+    Workspace w;
+    rt3d_status s = need_ws(c, npix, w);
+    if (s != RT3D_OK) return s;
+    RT3D_HIP(c, launch_compact_events(ev_pixel, ev_bin, n_events, npix, c->T, w.evoff, ev_scratch, off, ent,
+                                      capacity, w.counts, w.partial, w.err, (hipStream_t)hip_stream));
+    return RT3D_OK;
+}
+
 rt3d_status rt3d_debug_step(rt3d_ctx* c, int32_t step, const uint32_t* off, const uint32_t* ent, const float* gain,
                             const rt3d_state* in, rt3d_state* out, void* hip_stream)
 {
@@ -625,7 +727,7 @@ rt3d_status rt3d_debug_step(rt3d_ctx* c, int32_t step, const uint32_t* off, cons
         RT3D_HIP(c, launch_init_normals(p, sh, O, st));
         return RT3D_OK;
     case RT3D_STEP_APSS:
-        RT3D_HIP(c, launch_apss(m, p, sh, dev_state(in), O, st));
+        RT3D_HIP(c, launch_apss(m, p, sh, dev_state(in), O, -1, st));
         return RT3D_OK;
     case RT3D_STEP_IFILTER:
         RT3D_HIP(c, launch_ifilter(p, sh, dev_state(in), O, st));
@@ -659,7 +761,7 @@ rt3d_status rt3d_debug_step(rt3d_ctx* c, int32_t step, const uint32_t* off, cons
         Workspace w;
         rt3d_status s = need_ws(c, sh.P, w);
         if (s != RT3D_OK) return s;
-        return iterate(c, sh, off, ent, gain, O, w.B, w.btmp, st);
+        return iterate(c, sh, off, ent, gain, O, w.B, w.btmp, &w.cnn, st);
     }
     default:
         return fail(c, RT3D_E_INVALID, "unknown step");
@@ -675,6 +777,89 @@ rt3d_status rt3d_debug_gradients(rt3d_ctx* c, const uint32_t* off, const uint32_
     const Shape sh = shape_of(s->frames, s->rows, s->cols);
     RT3D_HIP(c, launch_gradients(dev_model(c), dev_params(c), sh, off, ent, gain, dev_state(s), gt, gr, gb,
                                  (hipStream_t)hip_stream));
+    return RT3D_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+rt3d_status rt3d_cnn_set_weights(rt3d_ctx* c, const float* host, size_t n)
+{
+    if (!c) return RT3D_E_INVALID;
+    if (!host || n != (size_t)CNN_PARAMS) return fail(c, RT3D_E_INVALID, "weights NULL or n != RT3D_CNN_PARAMS");
+    for (size_t k = 0; k < n; ++k)
+        if (!std::isfinite(host[k])) return fail(c, RT3D_E_INVALID, "non-finite weight");
+    RT3D_HIP(c, hipMemcpy(c->cnn.master, host, sizeof(float) * n, hipMemcpyHostToDevice));
+    RT3D_HIP(c, hipMemset(c->cnn.m, 0, sizeof(float) * 2 * CNN_PARAMS));
+    c->cnn.step = 0;
+    RT3D_HIP(c, launch_cnn_prepare(c->cnn, nullptr));
+    RT3D_HIP(c, hipDeviceSynchronize());
+    c->cnn_set = true;
+    return RT3D_OK;
+}
+
+rt3d_status rt3d_cnn_get_weights(rt3d_ctx* c, float* host, size_t n)
+{
+    if (!c) return RT3D_E_INVALID;
+    if (!host || n != (size_t)CNN_PARAMS) return fail(c, RT3D_E_INVALID, "weights NULL or n != RT3D_CNN_PARAMS");
+    RT3D_HIP(c, hipDeviceSynchronize());
+    RT3D_HIP(c, hipMemcpy(host, c->cnn.master, sizeof(float) * n, hipMemcpyDeviceToHost));
+    return RT3D_OK;
+}
+
+static rt3d_status cnn_ready(rt3d_ctx* c, const rt3d_state* st, Workspace& w)
+{
+    if (!uses_cnn(c)) return fail(c, RT3D_E_STATE, "context was not created with RT3D_DENOISE_CNN");
+    if (!state_ok(st) || !shape_ok(st->frames, st->rows, st->cols)) return fail(c, RT3D_E_INVALID, "bad state");
+    const Shape sh = shape_of(st->frames, st->rows, st->cols);
+    rt3d_status s = need_ws(c, sh.P, w);
+    if (s != RT3D_OK) return s;
+    if (cnn_wgrad_groups(sh) > c->ws_cnn_groups)
+        return fail(c, RT3D_E_NOMEM, "frame shape needs more weight-gradient groups than the workspace holds");
+    return RT3D_OK;
+}
+
+rt3d_status rt3d_cnn_last_gradient(rt3d_ctx* c, float* host, size_t n)
+{
+    if (!c) return RT3D_E_INVALID;
+    if (!host || n != (size_t)CNN_PARAMS) return fail(c, RT3D_E_INVALID, "gradient NULL or n != RT3D_CNN_PARAMS");
+    if (!uses_cnn(c) || !c->ws) return fail(c, RT3D_E_STATE, "no CNN workspace");
+    Workspace w = carve_ctx(c, c->ws, c->ws_P, c->ws_E, c->ws_rows, c->ws_cols);
+    RT3D_HIP(c, hipDeviceSynchronize());
+    RT3D_HIP(c, hipMemcpy(host, w.cnn.grad, sizeof(float) * n, hipMemcpyDeviceToHost));
+    return RT3D_OK;
+}
+
+rt3d_status rt3d_cnn_forward(rt3d_ctx* c, const rt3d_state* st, float* y, void* hip_stream)
+{
+    if (!c) return RT3D_E_INVALID;
+    if (!y) return fail(c, RT3D_E_INVALID, "y is NULL");
+    Workspace w;
+    rt3d_status s = cnn_ready(c, st, w);
+    if (s != RT3D_OK) return s;
+    const Shape sh = shape_of(st->frames, st->rows, st->cols);
+    hipStream_t hs = (hipStream_t)hip_stream;
+    RT3D_HIP(c, launch_cnn_forward(sh, dev_state(st), (float)std::sqrt(c->sigma2), c->cnn, w.cnn, hs));
+    RT3D_HIP(c, launch_cnn_unpack(sh, w.cnn, y, hs));
+    return RT3D_OK;
+}
+
+rt3d_status rt3d_cnn_train_step(rt3d_ctx* c, const rt3d_state* st, const float* truth, uint32_t n_surf,
+                                const rt3d_adam* opt, float* loss, void* hip_stream)
+{
+    if (!c) return RT3D_E_INVALID;
+    if (!truth || !loss || n_surf == 0 || n_surf > 64) return fail(c, RT3D_E_INVALID, "truth/loss NULL or n_surf bad");
+    if (!opt || opt->struct_size != sizeof(rt3d_adam) || !(opt->lr >= 0) || !(opt->beta1 >= 0 && opt->beta1 < 1) ||
+        !(opt->beta2 >= 0 && opt->beta2 < 1) || !(opt->eps > 0))
+        return fail(c, RT3D_E_INVALID, "bad Adam settings");
+    Workspace w;
+    rt3d_status s = cnn_ready(c, st, w);
+    if (s != RT3D_OK) return s;
+    const Shape sh = shape_of(st->frames, st->rows, st->cols);
+    CnnAdam a{opt->lr, opt->beta1, opt->beta2, opt->eps};
+    RT3D_HIP(c, launch_cnn_train_step(sh, dev_state(st), (float)std::sqrt(c->sigma2), truth, (int)n_surf, c->cnn,
+                                      w.cnn, a, loss, (hipStream_t)hip_stream));
     return RT3D_OK;
 }
 

@@ -19,16 +19,25 @@ K_MAX = 4
 
 OK, E_INVALID, E_NOMEM, E_DEVICE, E_CAPACITY, E_STATE, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 DENOISE_NONE, DENOISE_APSS = 0, 1
-IN_HIST_U16, IN_PHOTON_CSR = 0, 1
+IN_HIST_U16, IN_PHOTON_CSR, IN_PHOTON_EVENTS = 0, 1, 2
 STEP_INIT, STEP_DEPTH, STEP_APSS, STEP_MERGE, STEP_INTENSITY, STEP_IFILTER, STEP_BKG, STEP_BFILTER, \
     STEP_ITERATION = range(9)
 
 EXPORTS = ["rt3d_params_default", "rt3d_create", "rt3d_destroy", "rt3d_last_error", "rt3d_sigma2",
            "rt3d_workspace_bytes", "rt3d_set_workspace", "rt3d_reconstruct", "rt3d_query",
            "rt3d_profile", "rt3d_profile_read",
-           "rt3d_debug_compact", "rt3d_debug_step", "rt3d_debug_gradients"]
+           "rt3d_debug_compact", "rt3d_debug_compact_events", "rt3d_debug_step", "rt3d_debug_gradients",
+           "rt3d_cnn_set_weights", "rt3d_cnn_get_weights", "rt3d_cnn_last_gradient",
+           "rt3d_cnn_forward", "rt3d_cnn_train_step"]
 KERNELS = ["compact", "init", "normals", "depth", "apss", "merge", "intensity", "ifilter", "bkg",
-           "bfilter", "output"]
+           "bfilter", "output", "cnn"]
+DENOISE_CNN = 2
+CNN_PARAMS = 24003
+
+
+class Adam(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("lr", C.c_float), ("beta1", C.c_float),
+                ("beta2", C.c_float), ("eps", C.c_float)]
 
 
 class Rt3dError(RuntimeError):
@@ -51,7 +60,9 @@ class Params(C.Structure):
 class Input(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("kind", C.c_int32), ("frames", C.c_uint32),
                 ("rows", C.c_uint32), ("cols", C.c_uint32), ("hist", C.c_void_p),
-                ("off", C.c_void_p), ("ent", C.c_void_p), ("gain", C.c_void_p)]
+                ("off", C.c_void_p), ("ent", C.c_void_p), ("gain", C.c_void_p),
+                ("ev_pixel", C.c_void_p), ("ev_bin", C.c_void_p), ("ev_scratch", C.c_void_p),
+                ("n_events", C.c_uint64)]
 
 
 class Output(C.Structure):
@@ -107,10 +118,20 @@ def lib():
         L.rt3d_profile_read.restype = st
         L.rt3d_debug_compact.argtypes = [vp, vp, C.c_uint32, vp, vp, C.c_uint64, vp]
         L.rt3d_debug_compact.restype = st
+        L.rt3d_debug_compact_events.argtypes = [vp, vp, vp, C.c_uint64, C.c_uint32, vp, vp, vp, C.c_uint64, vp]
+        L.rt3d_debug_compact_events.restype = st
         L.rt3d_debug_step.argtypes = [vp, C.c_int32, vp, vp, vp, C.POINTER(State), C.POINTER(State), vp]
         L.rt3d_debug_step.restype = st
         L.rt3d_debug_gradients.argtypes = [vp, vp, vp, vp, C.POINTER(State), vp, vp, vp, vp]
         L.rt3d_debug_gradients.restype = st
+        fp = C.POINTER(C.c_float)
+        for name in ("rt3d_cnn_set_weights", "rt3d_cnn_get_weights", "rt3d_cnn_last_gradient"):
+            getattr(L, name).argtypes = [vp, fp, C.c_size_t]
+            getattr(L, name).restype = st
+        L.rt3d_cnn_forward.argtypes = [vp, C.POINTER(State), vp, vp]
+        L.rt3d_cnn_forward.restype = st
+        L.rt3d_cnn_train_step.argtypes = [vp, C.POINTER(State), vp, C.c_uint32, C.POINTER(Adam), vp, vp]
+        L.rt3d_cnn_train_step.restype = st
         _lib = L
     return _lib
 
@@ -242,8 +263,9 @@ class Context:
                       torch.zeros(P, dtype=torch.float32, device=dev))
 
     def reconstruct_into(self, out: Result, frames: int, rows: int, cols: int, hist=None, off=None,
-                         ent=None, gain=None):
-        """Enqueue one reconstruction on the current torch stream (no sync)."""
+                         ent=None, gain=None, events=None):
+        """Enqueue one reconstruction on the current torch stream (no sync).
+        Input: hist, or (off, ent), or events = (pixel int32, bin int16, scratch int32)."""
         inp = Input()
         inp.struct_size = C.sizeof(Input)
         inp.frames, inp.rows, inp.cols = frames, rows, cols
@@ -252,6 +274,12 @@ class Context:
             assert hist.is_cuda and hist.is_contiguous()
             inp.kind = IN_HIST_U16
             inp.hist = hist.data_ptr()
+        elif events is not None:
+            pix, bins, scratch = events
+            assert pix.numel() == bins.numel() <= scratch.numel()
+            inp.kind = IN_PHOTON_EVENTS
+            inp.ev_pixel, inp.ev_bin, inp.ev_scratch = pix.data_ptr(), bins.data_ptr(), scratch.data_ptr()
+            inp.n_events = pix.numel()
         else:
             inp.kind = IN_PHOTON_CSR
             inp.off, inp.ent = off.data_ptr(), ent.data_ptr()
@@ -291,6 +319,21 @@ class Context:
         self._check(lib().rt3d_debug_compact(self._h, _ptr(hist), P, _ptr(off), _ptr(ent), cap, _stream()))
         return off, ent
 
+    def compact_events(self, pix, bins, npix: int, capacity=None):
+        """Photon events (cuda int32 pixel, int16 bin, any order) -> (off, ent)."""
+        pix, bins = pix.contiguous(), bins.contiguous()
+        assert pix.dtype == torch.int32 and bins.dtype in (torch.int16, torch.uint16)
+        n = pix.numel()
+        cap = int(capacity) if capacity is not None else max(1, n)
+        off = torch.zeros(npix + 1, dtype=torch.int32, device="cuda")
+        ent = torch.zeros(cap, dtype=torch.int32, device="cuda")
+        scratch = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+        if self._ws_shape is None or self._ws_shape[0] * self._ws_shape[1] * self._ws_shape[2] < npix:
+            self.workspace(1, 1, npix, 1)
+        self._check(lib().rt3d_debug_compact_events(self._h, _ptr(pix), _ptr(bins), n, npix, _ptr(scratch),
+                                                    _ptr(off), _ptr(ent), cap, _stream()))
+        return off, ent
+
     def step(self, step: int, st_in: DeviceState | None, off=None, ent=None, gain=None,
              shape=None) -> DeviceState:
         if st_in is not None:
@@ -308,6 +351,46 @@ class Context:
                                           C.byref(cin) if cin is not None else None, C.byref(cout),
                                           _stream()))
         return out
+
+    # -- learned denoiser -------------------------------------------------
+    def cnn_set_weights(self, w):
+        import numpy as np
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        assert w.size == CNN_PARAMS
+        self._check(lib().rt3d_cnn_set_weights(self._h, w.ctypes.data_as(C.POINTER(C.c_float)), w.size))
+
+    def _host_vec(self, fn):
+        import numpy as np
+        out = np.zeros(CNN_PARAMS, dtype=np.float32)
+        self._check(fn(self._h, out.ctypes.data_as(C.POINTER(C.c_float)), out.size))
+        return out
+
+    def cnn_get_weights(self):
+        return self._host_vec(lib().rt3d_cnn_get_weights)
+
+    def cnn_last_gradient(self):
+        return self._host_vec(lib().rt3d_cnn_last_gradient)
+
+    def cnn_forward(self, st: DeviceState) -> torch.Tensor:
+        """Network output [3, P] (slot corrections in sigma_h units)."""
+        P = st.frames * st.rows * st.cols
+        y = torch.zeros(3, P, dtype=torch.float32, device="cuda")
+        cs = st.c()
+        self._check(lib().rt3d_cnn_forward(self._h, C.byref(cs), _ptr(y), _stream()))
+        return y
+
+    def cnn_train_step(self, st: DeviceState, truth: torch.Tensor, lr=1e-3, beta1=0.9, beta2=0.999,
+                       eps=1e-8, loss: torch.Tensor | None = None) -> torch.Tensor:
+        """One Adam step on a state and its true depths [S, P] (NaN = absent).
+        Returns the device tensor (loss, matched slots), filled asynchronously."""
+        if loss is None:
+            loss = torch.zeros(2, dtype=torch.float32, device="cuda")
+        truth = truth.contiguous()
+        opt = Adam(C.sizeof(Adam), lr, beta1, beta2, eps)
+        cs = st.c()
+        self._check(lib().rt3d_cnn_train_step(self._h, C.byref(cs), _ptr(truth), truth.shape[0],
+                                              C.byref(opt), _ptr(loss), _stream()))
+        return loss
 
     def gradients(self, st: DeviceState, off, ent, gain=None):
         P = st.frames * st.rows * st.cols

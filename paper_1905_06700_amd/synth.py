@@ -197,7 +197,7 @@ def head_scene(scene: int = 0, rows: int = 141, cols: int = 141, T: int = 4613,
     Z = render(rng, irf, T, depth, inten, b)
     return Scene(Z, irf, T, depth, inten, b,
                  dict(config=2, dz=0.05, p_xy=1.0, mean_signal=signal, r_min=0.2 * signal,
-                      r_init=0, k_init=3, occluder=M))
+                      r_init=1, k_init=3, occluder=M))
 
 
 def layers_scene(scene: int = 0, rows: int = 256, cols: int = 256, T: int = 1024, signal: float = 2.0,

@@ -38,6 +38,12 @@ def _scene(name):
         sc = synth.head_scene(7, rows=37, cols=23, T=777, signal=8.0, sbr=0.5)
         sc.meta.update(r_init=1, dz=0.07)
         return sc
+    if name == "ragged_r3":
+        # 7 x 7 photon pooling: interior pixels pool more photons than the
+        # library scores from LDS (its branch-and-bound path), border pixels fewer
+        sc = synth.head_scene(7, rows=37, cols=23, T=777, signal=8.0, sbr=0.5)
+        sc.meta.update(r_init=3, dz=0.07)
+        return sc
     raise KeyError(name)
 
 
@@ -92,7 +98,7 @@ def test_compaction_edge_cases():
 
 # ------------------------------------------------------------------ init
 
-@pytest.mark.parametrize("name", ["c1", "c2", "ragged"])
+@pytest.mark.parametrize("name", ["c1", "c2", "ragged", "ragged_r3"])
 def test_init_matches_oracle(name):
     sc = scene(name)
     O, ctx = pair(sc)
