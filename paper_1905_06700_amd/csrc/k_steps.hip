@@ -122,6 +122,28 @@ __device__ __forceinline__ void reduce_lanes(float& sz, float (&sh)[KM], float (
     }
 }
 
+// S and S' of the pixel's points, each sum split over the pixel's LPP lanes
+// (strided segments) and combined with shuffles; every lane ends with the
+// totals.
+__device__ __forceinline__ void s_eval_points(const DevModel& m, const PixPoints& q, int sub, float (&S)[KM],
+                                              float (&Sp)[KM])
+{
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+        S[k] = 0.f;
+        Sp[k] = 0.f;
+        if (k < q.c) s_eval(m, q.t[k], S[k], Sp[k], sub, LPP);
+    }
+#pragma unroll
+    for (int d = 1; d < LPP; d <<= 1) {
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+            S[k] += __shfl_xor(S[k], d, 64);
+            Sp[k] += __shfl_xor(Sp[k], d, 64);
+        }
+    }
+}
+
 // Common prologue: the pixel of this lane, its points and its entry range.
 struct Lane {
     long long pix;
@@ -161,6 +183,8 @@ __global__ __launch_bounds__(256) void k_depth_step(DevModel m, DevParams p, Sha
     float sz, shh[KM], shp[KM];
     accumulate(m, L.q, L.live ? s.b[L.pix] : 1.f, L.live ? L.G : 1.f, ent, L.e0, L.e1, sz, shh, shp);
     reduce_lanes(sz, shh, shp);
+    float Sv[KM], Spv[KM];
+    s_eval_points(m, L.q, L.sub, Sv, Spv);
     if (!L.live || L.sub != 0) return;
     const float scale = (float)p.beta_t * m.fisher_inv;
     const float dmax = (float)p.dmax;
@@ -168,9 +192,7 @@ __global__ __launch_bounds__(256) void k_depth_step(DevModel m, DevParams p, Sha
 #pragma unroll
     for (int k = 0; k < KM; ++k) {
         if (k < L.q.c && L.q.r[k] > 0.f) {
-            float S, Sp;
-            s_eval(m, L.q.t[k], S, Sp);
-            float step = -scale * (Sp + shp[k]);
+            float step = -scale * (Spv[k] + shp[k]);
             step = fminf(fmaxf(step, -dmax), dmax);
             double tn = L.q.t[k] + (double)step;
             tn = tn < 0.0 ? 0.0 : (tn > tmax ? tmax : tn);
@@ -189,13 +211,14 @@ __global__ __launch_bounds__(256) void k_intensity_step(DevModel m, DevParams p,
     float sz, shh[KM], shp[KM];
     accumulate(m, L.q, L.live ? s.b[L.pix] : 1.f, L.live ? L.G : 1.f, ent, L.e0, L.e1, sz, shh, shp);
     reduce_lanes(sz, shh, shp);
+    float Sv[KM], Spv[KM];
+    s_eval_points(m, L.q, L.sub, Sv, Spv);
     if (!L.live || L.sub != 0) return;
     const float br = (float)p.beta_r;
 #pragma unroll
     for (int k = 0; k < KM; ++k) {
         if (k < L.q.c) {
-            float S, Sp;
-            s_eval(m, L.q.t[k], S, Sp);
+            const float S = Sv[k];
             if (S > 0.f) {
                 const float v = L.q.r[k] * ((1.f - br) + br * shh[k] / S);
                 s.r[k * P + L.pix] = fmaxf(v, 0.f);
@@ -232,16 +255,16 @@ __global__ __launch_bounds__(256) void k_gradients(DevModel m, Shape sh, const u
     float sz, shh[KM], shp[KM];
     accumulate(m, L.q, L.live ? s.b[L.pix] : 1.f, L.live ? L.G : 1.f, ent, L.e0, L.e1, sz, shh, shp);
     reduce_lanes(sz, shh, shp);
+    float Sv[KM], Spv[KM];
+    s_eval_points(m, L.q, L.sub, Sv, Spv);
     if (L.pix >= P || L.sub != 0) return;
     const float G = L.G;
 #pragma unroll
     for (int k = 0; k < KM; ++k) {
         float vt = 0.f, vr = 0.f;
         if (k < L.q.c && G > 0.f) {
-            float S, Sp;
-            s_eval(m, L.q.t[k], S, Sp);
-            vt = G * L.q.r[k] * (Sp + shp[k]);
-            vr = G * (S - shh[k]);
+            vt = G * L.q.r[k] * (Spv[k] + shp[k]);
+            vr = G * (Sv[k] - shh[k]);
         }
         gt[k * P + L.pix] = vt;
         gr[k * P + L.pix] = vr;

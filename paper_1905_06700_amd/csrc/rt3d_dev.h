@@ -75,7 +75,10 @@ __device__ __forceinline__ void irf_eval(const DevModel& m, int tb, int a, float
 
 // S(t) = sum over bins of h(tb - t) and dS/dt = -sum h'(tb - t), by direct
 // summation over the IRF support (every lag shares the local parameter).
-__device__ __forceinline__ void s_eval(const DevModel& m, double t, float& S, float& Sp)
+// Lane `part` of `parts` sums the segments k0 + part, k0 + part + parts, ...
+// (parts = 1: the whole sum).
+__device__ __forceinline__ void s_eval(const DevModel& m, double t, float& S, float& Sp, int part = 0,
+                                       int parts = 1)
 {
     const double fl = floor(t);
     const int a = (int)fl;
@@ -85,7 +88,7 @@ __device__ __forceinline__ void s_eval(const DevModel& m, double t, float& S, fl
     // segment k holds bin tb = k + a - o + sh; keep 0 <= tb <= T - 1
     const int k0 = max(-1, m.o - a - sh), k1 = min(m.L - 1, m.T - 1 + m.o - a - sh);
     float acc = 0.f, accp = 0.f;
-    for (int k = k0; k <= k1; ++k) {
+    for (int k = k0 + part; k <= k1; k += parts) {
         float h, hp;
         cr_segment(m.cr[k + 1], s, h, hp);
         acc += h;
