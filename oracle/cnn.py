@@ -10,10 +10,14 @@ CPU leg use it; it shares no code with the GPU library.
 
 Reading (not in the paper; it only says denoisers are interchangeable):
   features, per pixel and slot k < 3 (valid_k = k < min(cnt, 3)):
-    d_k = clip((t_k - mean_k) / sigma_h, -8, 8), mean_k = mean of the valid
-          slot-k depths in the 5 x 5 window (same frame, inside the image);
-    a_k = log(1 + r_k);  v_k = 1;     (all three are 0 when slot k is invalid)
-  channels [d0 a0 v0 d1 a1 v1 d2 a2 v2] padded with zeros to 16;
+    neighbours of slot k: the points (any slot) of the 5 x 5 window (same
+          frame, inside the image, the point itself included) whose depth
+          lies within GATE sigma_h of t_k -- the same surface, as the 3-D
+          support of APSS selects it;
+    d_k = clip((t_k - mean_k) / sigma_h, -8, 8), mean_k = their mean depth;
+    a_k = log(1 + r_k);  v_k = 1;  n_k = their number / 25;
+          (all four are 0 when slot k is invalid)
+  channels [d0 a0 v0 n0 d1 a1 v1 n1 d2 a2 v2 n2] padded with zeros to 16;
   net: conv3x3(16->32)+ReLU, conv3x3(32->32)+ReLU, conv3x3(32->32)+ReLU,
        conv3x3(32->3), zero padding ("same"), weights w[ky][kx][cin][cout];
   output y_k = correction of slot k's depth in units of sigma_h;
@@ -28,6 +32,8 @@ from __future__ import annotations
 import numpy as np
 
 CIN = (16, 32, 32, 32)
+LIVE_IN = 12                      # feature channels that carry data (the rest pad to 16)
+GATE = 3.0                        # neighbour depth gate in units of sigma_h
 COUT = (32, 32, 32, 3)
 N_PARAMS = sum(9 * ci * co + co for ci, co in zip(CIN, COUT))
 
@@ -54,12 +60,12 @@ def he_init(seed: int) -> np.ndarray:
     rng = np.random.default_rng(seed)
     parts = []
     for ci, co in zip(CIN, COUT):
-        fan_in = 9 * (9 if ci == 16 else ci)       # the first layer has 9 live channels
+        fan_in = 9 * (LIVE_IN if ci == 16 else ci)  # the first layer has LIVE_IN live channels
         parts.append(rng.normal(0.0, np.sqrt(2.0 / fan_in), 9 * ci * co))
         parts.append(np.zeros(co))
     w = np.concatenate(parts).astype(np.float32)
     w_layers = unflatten(w)
-    w_layers[0][0][:, :, 9:, :] = 0.0               # padding channels carry nothing
+    w_layers[0][0][:, :, LIVE_IN:, :] = 0.0         # padding channels carry nothing
     return w
 
 
@@ -69,26 +75,32 @@ def f16(x):
 
 def features(t, r, cnt, sigma_h, F, H, W):
     """t, r: [P, K] (pixel-major, K >= 3); cnt [P] -> x [F, H, W, 16]."""
-    t = np.asarray(t, dtype=np.float64).reshape(F, H, W, -1)
-    r = np.asarray(r, dtype=np.float64).reshape(F, H, W, -1)
-    c = np.minimum(np.asarray(cnt).reshape(F, H, W), 3)
+    K = np.asarray(t).shape[-1]
+    t = np.asarray(t, dtype=np.float64).reshape(F, H, W, K)
+    r = np.asarray(r, dtype=np.float64).reshape(F, H, W, K)
+    call = np.minimum(np.asarray(cnt).reshape(F, H, W), K)
+    c = np.minimum(call, 3)
     x = np.zeros((F, H, W, 16))
     for k in range(3):
         valid = c > k
         tk = np.where(valid, t[..., k], 0.0)
-        vk = valid.astype(np.float64)
         s = np.zeros((F, H, W))
         n = np.zeros((F, H, W))
         for dy in range(-2, 3):
             for dx in range(-2, 3):
                 y0, y1 = max(0, -dy), min(H, H - dy)
                 x0, x1 = max(0, -dx), min(W, W - dx)
-                s[:, y0:y1, x0:x1] += tk[:, y0 + dy:y1 + dy, x0 + dx:x1 + dx]
-                n[:, y0:y1, x0:x1] += vk[:, y0 + dy:y1 + dy, x0 + dx:x1 + dx]
-        mean = np.where(n > 0, s / np.maximum(n, 1), 0.0)
-        x[..., 3 * k] = np.where(valid, np.clip((tk - mean) / sigma_h, -8, 8), 0.0)
-        x[..., 3 * k + 1] = np.where(valid, np.log1p(np.where(valid, r[..., k], 0.0)), 0.0)
-        x[..., 3 * k + 2] = vk
+                for k2 in range(K):
+                    tm = t[:, y0 + dy:y1 + dy, x0 + dx:x1 + dx, k2]
+                    ok = (call[:, y0 + dy:y1 + dy, x0 + dx:x1 + dx] > k2) & \
+                        (np.abs(tm - tk[:, y0:y1, x0:x1]) <= GATE * sigma_h)
+                    s[:, y0:y1, x0:x1] += np.where(ok, tm, 0.0)
+                    n[:, y0:y1, x0:x1] += ok
+        mean = s / np.maximum(n, 1)
+        x[..., 4 * k] = np.where(valid, np.clip((tk - mean) / sigma_h, -8, 8), 0.0)
+        x[..., 4 * k + 1] = np.where(valid, np.log1p(np.where(valid, r[..., k], 0.0)), 0.0)
+        x[..., 4 * k + 2] = valid
+        x[..., 4 * k + 3] = np.where(valid, n / 25.0, 0.0)
     return x
 
 

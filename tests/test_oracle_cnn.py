@@ -65,21 +65,36 @@ def test_features_hand_cases():
     cnt = np.ones(9, dtype=int)
     t[:, 0] = 100.0
     r[:, 0] = np.e - 1.0
-    t[4, 0] = 110.0                                   # centre sits 10 bins deeper
-    x = cnn.features(t, r, cnt, 2.0, F, H, W)
+    t[4, 0] = 104.0                                   # centre sits 4 bins deeper
+    x = cnn.features(t, r, cnt, 2.0, F, H, W)        # gate = 3 x 2 = 6 bins
     assert x.shape == (1, 3, 3, 16)
-    # the 5 x 5 window of any pixel of a 3 x 3 image holds all nine pixels
-    np.testing.assert_allclose(x[0, 1, 1, 0], (110.0 - 910.0 / 9) / 2.0)
-    np.testing.assert_allclose(x[0, 0, 0, 0], (100.0 - 910.0 / 9) / 2.0)
+    # the 5 x 5 window of any pixel of a 3 x 3 image holds all nine pixels, all
+    # within the gate of each other: mean 904 / 9
+    np.testing.assert_allclose(x[0, 1, 1, 0], (104.0 - 904.0 / 9) / 2.0)
+    np.testing.assert_allclose(x[0, 0, 0, 0], (100.0 - 904.0 / 9) / 2.0)
     np.testing.assert_allclose(x[..., 1], 1.0)
     np.testing.assert_allclose(x[..., 2], 1.0)
-    assert np.all(x[..., 3:] == 0)
-    # a four-point pixel still feeds its first three slots; large offsets clip at 8 sigma
-    cnt[0] = 4
-    t[0, :] = [1.0, 2.0, 3.0, 4.0]
+    np.testing.assert_allclose(x[..., 3], 9.0 / 25.0)
+    assert np.all(x[..., 4:] == 0)
+    # a centre 10 bins deeper is outside every neighbour's gate: alone on its surface
+    t[4, 0] = 110.0
     x = cnn.features(t, r, cnt, 2.0, F, H, W)
-    assert x[0, 0, 0, 5] == 1.0 and x[0, 0, 0, 8] == 1.0
-    assert x[0, 0, 0, 0] == -8.0
+    assert x[0, 1, 1, 0] == 0.0 and x[0, 1, 1, 3] == 1.0 / 25.0
+    np.testing.assert_allclose(x[0, 0, 0, 0], 0.0)
+    np.testing.assert_allclose(x[0, 0, 0, 3], 8.0 / 25.0)
+    # a second point of a pixel joins the neighbours of the slot whose gate it
+    # falls in, whatever its own slot; a four-point pixel feeds its first three slots
+    cnt[0] = 4
+    t[0, :] = [95.0, 101.0, 200.0, 300.0]
+    r[0, :] = np.e - 1.0
+    x = cnn.features(t, r, cnt, 2.0, F, H, W)
+    # pixel (0, 1), slot 0 at 100: neighbours 95 and 101 of pixel 0 and the six
+    # other 100s (the centre at 110 is out): 9 points, mean (95 + 101 + 700) / 9
+    np.testing.assert_allclose(x[0, 0, 1, 0], (100.0 - 896.0 / 9) / 2.0)
+    np.testing.assert_allclose(x[0, 0, 1, 3], 9.0 / 25.0)
+    assert x[0, 0, 0, 6] == 1.0 and x[0, 0, 0, 10] == 1.0
+    assert x[0, 0, 0, 8] == 0.0 and x[0, 0, 0, 11] == 1.0 / 25.0   # slot 2 at 200 is alone
+    assert np.all(x[0, 0, 0, 12:] == 0)
 
 
 def test_target_matching():
@@ -94,7 +109,7 @@ def test_target_matching():
 def test_training_reduces_loss_on_a_toy():
     rng = np.random.default_rng(4)
     x = rng.normal(size=(1, 8, 8, 16))
-    x[..., 9:] = 0
+    x[..., cnn.LIVE_IN:] = 0
     target = np.tanh(x[..., :3])
     mask = np.ones_like(target, dtype=bool)
     w = cnn.he_init(0).astype(np.float64)
