@@ -3,9 +3,10 @@
 // "Reconstruction algorithm"; Discussion, other denoisers trade quality for
 // speed).  Reading (not in the paper): a four-layer 3x3 convolutional network
 // on per-pixel slot maps (features of the first three slots: depth relative
-// to the 5x5 mean of that slot in sigma_h units, log(1 + r), valid flag)
-// predicting each slot's depth correction in sigma_h units; pixels with four
-// points keep APSS.
+// to the mean of the same-surface neighbours -- points of the 5x5 window
+// within 3 sigma_h -- in sigma_h units, log(1 + r), valid flag, neighbour
+// count) predicting each slot's depth correction in sigma_h units; pixels
+// with four points keep APSS.
 //
 // Every convolution is an implicit GEMM on the matrix cores:
 // v_mfma_f32_16x16x16_f16 (FP16 inputs, FP32 accumulation).  Activations are
@@ -216,6 +217,11 @@ __global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ 
 }
 
 // Features of the first three slots, FP16 [P][16].
+// Features of slots k < min(cnt, 3): the neighbours of slot k are the points
+// (any slot) of the 5x5 window (same frame, inside the image, itself
+// included) within CNN_GATE sigma_h of t_k; channels 4k .. 4k+3 hold
+// (t_k - their mean) / sigma_h clipped to [-8, 8], log(1 + r_k), 1 and their
+// number / 25.  The other channels are zero.
 __global__ __launch_bounds__(256) void k_cnn_pack(Shape sh, DevState s, float sigma_h, __half* __restrict__ x)
 {
     const long long P = sh.P;
@@ -225,27 +231,33 @@ __global__ __launch_bounds__(256) void k_cnn_pack(Shape sh, DevState s, float si
     const long long fr = pix / per_frame;
     const int i = (int)((pix / sh.cols) % sh.rows), j = (int)(pix % sh.cols);
     const int c = min(load_cnt(s.cnt, pix), 3);
+    const double gate = CNN_GATE * (double)sigma_h;
     float v[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) v[q] = 0.f;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         if (k >= c) continue;
+        const double tk = s.t[k * P + pix];
         double sum = 0.0;
         int n = 0;
         for (int i2 = max(0, i - 2); i2 <= min(sh.rows - 1, i + 2); ++i2)
             for (int j2 = max(0, j - 2); j2 <= min(sh.cols - 1, j + 2); ++j2) {
                 const long long pp = (fr * sh.rows + i2) * sh.cols + j2;
-                if (min(load_cnt(s.cnt, pp), 3) > k) {
-                    sum += s.t[k * P + pp];
-                    ++n;
+                const int c2 = load_cnt(s.cnt, pp);
+                for (int k2 = 0; k2 < c2; ++k2) {
+                    const double tm = s.t[k2 * P + pp];
+                    if (fabs(tm - tk) <= gate) {
+                        sum += tm;
+                        ++n;
+                    }
                 }
             }
-        const double tk = s.t[k * P + pix];
         const double mean = sum / n;
-        v[3 * k] = fminf(fmaxf((float)((tk - mean) / (double)sigma_h), -8.f), 8.f);
-        v[3 * k + 1] = log1pf(s.r[k * P + pix]);
-        v[3 * k + 2] = 1.f;
+        v[4 * k] = fminf(fmaxf((float)((tk - mean) / (double)sigma_h), -8.f), 8.f);
+        v[4 * k + 1] = log1pf(s.r[k * P + pix]);
+        v[4 * k + 2] = 1.f;
+        v[4 * k + 3] = (float)n / 25.f;
     }
 #pragma unroll
     for (int q = 0; q < 16; ++q) x[pix * 16 + q] = __float2half(v[q]);

@@ -23,7 +23,8 @@
 // ever scored exactly, so the cost follows the active bins, not T.
 //
 // When the pooled photons fit (INIT_ELDS entries, T <= INIT_SB x INIT_NB_LDS),
-// they are staged in LDS with the IRF weight tables, the bounds are kept per
+// they are staged in LDS, bucketed by 64-bin block, with the IRF weight
+// tables, the bounds are kept per
 // sub-block of INIT_SB tau (tighter, so fewer 64-tau blocks are scored), a
 // scored sub-block keeps its best in LDS, and after an accepted peak only the
 // sub-blocks that peak changes (tau that can see its claimed bins or fall
@@ -107,12 +108,14 @@ constexpr int INIT_SB = 16;
 constexpr int INIT_NB_LDS = 512;
 
 // 8-byte LDS words of one wavefront: the pooled CSR ranges, then either the
-// LDS path's block tables and staged photons or the HBM path's block bounds.
+// LDS path's block tables, bucketed photons and bucket ends, or the HBM path's
+// block bounds.
 inline __host__ __device__ size_t init_wave_words(int T, int r_init)
 {
     const size_t nb = (size_t)(T + 63) / 64, nbs = (size_t)(T + INIT_SB - 1) / INIT_SB;
     const size_t side = 2 * (size_t)r_init + 1;
-    const size_t staged = nbs <= INIT_NB_LDS ? init_block_words((int)nbs) + (size_t)INIT_ELDS / 2 : 0;
+    const size_t staged =
+        nbs <= INIT_NB_LDS ? init_block_words((int)nbs) + (size_t)INIT_ELDS / 2 + (nb + 2) / 2 : 0;
     return side * side + (nb > staged ? nb : staged);
 }
 
@@ -125,39 +128,50 @@ inline __host__ __device__ int q_levels(int L)
 }
 
 // Exact scores of block bb's 64 tau (one per lane): L(tau) = sum of
-// z q[t - tau + o] over the pooled photons in unclaimed bins t the block can
-// see, [wlo, whi].  Each pooled list (ascending bins, staged in LDS at
-// E[es[l] ..]) is read 64 photons at a time; ballots find the photons inside
-// the window and each is broadcast from the lane that loaded it.  Returns the
-// lane's (score, tau), or (-1, NO_TAU) where tau >= T or an accepted peak
-// suppresses it.
-__device__ __forceinline__ void score_block(const uint32_t* E, const uint2* lists, int npl, int bb,
-                                            const int* qt, int L, int o, int T, const Peaks& pk, int wnms,
-                                            long long& sv, int& st)
+// z q[t - tau + o] over the pooled photons in unclaimed bins t in the window
+// [wlo, whi] the block can see.  The photons are bucketed by 64-bin block in
+// LDS (bucket b ends at bend[b]); the window's buckets are read 64 photons at
+// a time and each photon is broadcast from the lane that loaded it, four at a
+// time so that their weight lookups overlap.  Photons of those buckets outside
+// the window fall outside the lag range and add nothing.  Returns the lane's
+// (score, tau), or (-1, NO_TAU) where tau >= T or an accepted peak suppresses
+// it.
+__device__ __forceinline__ void score_block(const uint32_t* E, const int* bend, int nb, int bb, const int* qt,
+                                            int L, int o, int T, const Peaks& pk, int wnms, long long& sv,
+                                            int& st)
 {
     const int lane = threadIdx.x & 63;
     const int tau = (bb << 6) + lane;
     const int wlo = (bb << 6) - o, whi = (bb << 6) + 63 - o + L - 1;
     long long sc = 0;
-    int es = 0;
-    for (int l = 0; l < npl; ++l) {
-        const uint2 rg = lists[l];
-        const int nl = (int)(rg.y - rg.x);
-        for (int c0 = 0; c0 < nl; c0 += 64) {
+    if (whi >= 0) {
+        const int b0 = max(0, wlo) >> 6, b1 = min(nb - 1, whi >> 6);
+        const int x0 = b0 > 0 ? bend[b0 - 1] : 0, x1 = bend[b1];
+        for (int c0 = x0; c0 < x1; c0 += 64) {
             const int x = c0 + lane;
-            const int vv = x < nl ? (int)E[es + x] : 0;
-            const int t = x < nl ? ent_bin((uint32_t)vv) : NO_TAU;
-            const int k0 = __popcll(__ballot(t < wlo)), k1 = __popcll(__ballot(t <= whi));
-            for (int k = k0; k < k1; ++k) {
-                const uint32_t v = (uint32_t)__builtin_amdgcn_readlane(vv, k);
-                const int tb = ent_bin(v);
-                if (pk.owner(tb) >= 0) continue;
-                const int lag = tb - tau + o;
-                if ((unsigned)lag < (unsigned)L) sc += (long long)ent_cnt(v) * (long long)qt[lag];
+            const int vv = x < x1 ? (int)E[x] : 0;
+            const int cnt = min(64, x1 - c0);
+            int k = 0;
+            for (; k + 4 <= cnt; k += 4) {
+                uint32_t v[4];
+                int lag[4], q[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    v[u] = (uint32_t)__builtin_amdgcn_readlane(vv, k + u);
+                    lag[u] = ent_bin(v[u]) - tau + o;
+                    const bool ok = (unsigned)lag[u] < (unsigned)L && pk.owner(ent_bin(v[u])) < 0;
+                    q[u] = ok ? qt[lag[u]] : 0;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) sc += (long long)ent_cnt(v[u]) * (long long)q[u];
             }
-            if (k1 < 64) break;                  // the rest of the list lies beyond the window
+            for (; k < cnt; ++k) {
+                const uint32_t v = (uint32_t)__builtin_amdgcn_readlane(vv, k);
+                const int lg = ent_bin(v) - tau + o;
+                if ((unsigned)lg < (unsigned)L && pk.owner(ent_bin(v)) < 0)
+                    sc += (long long)ent_cnt(v) * (long long)qt[lg];
+            }
         }
-        es += nl;
     }
     const bool valid = tau < T && !pk.suppressed(tau, wnms);
     sv = valid ? sc : -1;
@@ -181,6 +195,8 @@ __device__ __forceinline__ void argmax_reduce(long long& sv, int& st, int width)
     }
 }
 
+// QL: the IRF weight tables are staged in LDS (they fit INIT_QLDS ints).
+template <bool QL>
 __global__ __launch_bounds__(64 * INIT_WAVES) void k_init(DevModel m, DevParams p, Shape sh,
                                                           const uint32_t* __restrict__ off,
                                                           const uint32_t* __restrict__ ent,
@@ -195,14 +211,13 @@ __global__ __launch_bounds__(64 * INIT_WAVES) void k_init(DevModel m, DevParams 
     // workgroup before any wavefront leaves
     const int nq = L * (1 + q_levels(L));
     int* qs = reinterpret_cast<int*>(smem64 + INIT_WAVES * ww);
-    const bool q_lds = nq <= INIT_QLDS;
-    if (q_lds) {
+    if (QL) {
         for (int k = threadIdx.x; k < L; k += blockDim.x) qs[k] = m.q[k];
         for (int k = threadIdx.x; k < nq - L; k += blockDim.x) qs[L + k] = m.qst[k];
     }
     __syncthreads();
-    const int* qt = q_lds ? qs : m.q;
-    const int* qstt = q_lds ? qs + L : m.qst;
+    const int* qt = QL ? qs : m.q;
+    const int* qstt = QL ? qs + L : m.qst;
 
     const long long P = sh.P;
     const long long pix = (long long)blockIdx.x * INIT_WAVES + wv;
@@ -264,33 +279,53 @@ __global__ __launch_bounds__(64 * INIT_WAVES) void k_init(DevModel m, DevParams 
         unsigned long long* bnd = ub;                                   // [nbs] bounds
         long long* bsc = reinterpret_cast<long long*>(ub + nbs);        // [nbs] cached best score, -2 = none
         int* btau = reinterpret_cast<int*>(ub + 2 * nbs);               // [nbs] cached best tau
-        uint32_t* E = reinterpret_cast<uint32_t*>(ub + init_block_words(nbs));
+        uint32_t* E = reinterpret_cast<uint32_t*>(ub + init_block_words(nbs));   // [total] bucketed photons
+        int* bend = reinterpret_cast<int*>(E + INIT_ELDS);               // [nb] bucket ends
         for (int b = lane; b < nbs; b += 64) {
             bnd[b] = 0ull;
             bsc[b] = -2;
             btau[b] = NO_TAU;
         }
-        int es = 0;
+        for (int b = lane; b < nb; b += 64) bend[b] = 0;
+        wave_sync();
+        // photons per 64-bin bucket, photon total and the score bounds
         for (int l = 0; l < npl; ++l) {
             const uint2 rg = lists[l];
-            const int nl = (int)(rg.y - rg.x);
-            for (int x = lane; x < nl; x += 64) E[es + x] = ent[rg.x + x];
-            es += nl;
-        }
-        wave_sync();
-        for (int x = lane; x < total; x += 64) {
-            const uint32_t v = E[x];
-            const int t = ent_bin(v), z = ent_cnt(v);
-            if (t >= T) continue;
-            ntot += z;
-            const int tlo = max(0, t + o - L + 1), thi = min(T - 1, t + o);
-            for (int b = tlo / INIT_SB; b <= thi / INIT_SB; ++b) {
-                const int a0 = max(tlo, b * INIT_SB), a1 = min(thi, b * INIT_SB + INIT_SB - 1);
-                const int qm = q_range_max(qstt, L, t - a1 + o, t - a0 + o);
-                atomicAdd(&bnd[b], (unsigned long long)z * (unsigned long long)qm);
+            for (uint32_t e = rg.x + lane; e < rg.y; e += 64) {
+                const uint32_t v = ent[e];
+                const int t = ent_bin(v), z = ent_cnt(v);
+                atomicAdd(&bend[min(t >> 6, nb - 1)], 1);
+                if (t >= T) continue;
+                ntot += z;
+                const int tlo = max(0, t + o - L + 1), thi = min(T - 1, t + o);
+                for (int b = tlo / INIT_SB; b <= thi / INIT_SB; ++b) {
+                    const int a0 = max(tlo, b * INIT_SB), a1 = min(thi, b * INIT_SB + INIT_SB - 1);
+                    const int qm = q_range_max(qstt, L, t - a1 + o, t - a0 + o);
+                    atomicAdd(&bnd[b], (unsigned long long)z * (unsigned long long)qm);
+                }
             }
         }
         ntot = wave_sum(ntot);
+        wave_sync();
+        // bucket starts (exclusive prefix of the counts), then scatter; each
+        // bucket's cursor ends at the bucket's end
+        int carry = 0;
+        for (int c0 = 0; c0 < nb; c0 += 64) {
+            const int b = c0 + lane;
+            const int cnt = b < nb ? bend[b] : 0;
+            const int inc = (int)wave_incl_scan((uint32_t)cnt);
+            if (b < nb) bend[b] = carry + inc - cnt;
+            carry += __shfl(inc, 63, 64);
+        }
+        wave_sync();
+        for (int l = 0; l < npl; ++l) {
+            const uint2 rg = lists[l];
+            for (uint32_t e = rg.x + lane; e < rg.y; e += 64) {
+                const uint32_t v = ent[e];
+                const int pos = atomicAdd(&bend[min(ent_bin(v) >> 6, nb - 1)], 1);
+                E[pos] = v;
+            }
+        }
         wave_sync();
         for (int it = 0; it < p.k_init; ++it) {
             // best over the sub-blocks whose exact best is known
@@ -331,7 +366,7 @@ __global__ __launch_bounds__(64 * INIT_WAVES) void k_init(DevModel m, DevParams 
                 long long sv;
                 int st;
                 const int span = bb * INIT_SB / 64;
-                score_block(E, lists, npl, span, qt, L, o, T, pk, m.wnms, sv, st);
+                score_block(E, bend, nb, span, qt, L, o, T, pk, m.wnms, sv, st);
                 argmax_reduce(sv, st, INIT_SB);                  // best of each sub-block
                 const int sb = span * (64 / INIT_SB) + lane / INIT_SB;
                 if (lane % INIT_SB == 0 && sb < nbs) {
@@ -351,10 +386,14 @@ __global__ __launch_bounds__(64 * INIT_WAVES) void k_init(DevModel m, DevParams 
             for (int tb = a + lane; tb <= c; tb += 64) win += pk.owner(tb) < 0;
             win = wave_sum(win);
             long long nwin = 0;
-            for (int x = lane; x < total; x += 64) {
-                const uint32_t v = E[x];
-                const int tb = ent_bin(v);
-                if (tb >= a && tb <= c && pk.owner(tb) < 0) nwin += ent_cnt(v);
+            {
+                const int b0 = a >> 6, b1 = min(nb - 1, c >> 6);
+                const int x1 = bend[b1];
+                for (int x = (b0 > 0 ? bend[b0 - 1] : 0) + lane; x < x1; x += 64) {
+                    const uint32_t v = E[x];
+                    const int tb = ent_bin(v);
+                    if (tb >= a && tb <= c && pk.owner(tb) < 0) nwin += ent_cnt(v);
+                }
             }
             nwin = wave_sum(nwin);
             const double bw = (double)ntot * (double)win / (double)T;
@@ -639,7 +678,10 @@ hipError_t launch_init(const DevModel& m, const DevParams& p, const Shape& sh, c
     if (sh.P == 0) return hipSuccess;
     const size_t lds = init_lds_bytes(m.T, m.L, p.r_init);
     const unsigned nblk = (unsigned)((sh.P + INIT_WAVES - 1) / INIT_WAVES);
-    hipLaunchKernelGGL(k_init, dim3(nblk), dim3(64 * INIT_WAVES), lds, st, m, p, sh, off, ent, gain, s);
+    if ((size_t)m.L * (1 + q_levels(m.L)) <= (size_t)INIT_QLDS)
+        hipLaunchKernelGGL(k_init<true>, dim3(nblk), dim3(64 * INIT_WAVES), lds, st, m, p, sh, off, ent, gain, s);
+    else
+        hipLaunchKernelGGL(k_init<false>, dim3(nblk), dim3(64 * INIT_WAVES), lds, st, m, p, sh, off, ent, gain, s);
     return hipGetLastError();
 }
 

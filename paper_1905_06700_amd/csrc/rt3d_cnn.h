@@ -9,6 +9,7 @@
 namespace rt3d {
 
 constexpr int CNN_LAYERS = 4;
+constexpr double CNN_GATE = 3.0;   // neighbour depth gate of the features, in sigma_h
 // master (trained) channel counts and the counts stored for the matrix cores
 constexpr int CNN_CIN[CNN_LAYERS] = {16, 32, 32, 32};
 constexpr int CNN_COUT[CNN_LAYERS] = {32, 32, 32, 3};

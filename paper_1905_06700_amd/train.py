@@ -18,15 +18,22 @@ from . import rt3d
 RECORD_ITERS = (0, 1, 2, 4, 7, 11, 15, 19)
 
 
+LIVE_IN = 12   # feature channels that carry data
+
+
 def he_init(seed: int) -> np.ndarray:
-    """He-normal weights (zero biases) in the library's layout, from a seed."""
+    """He-normal weights (zero biases) in the library's layout, from a seed;
+    the last layer starts at zero, so training starts from the identity (no
+    depth correction)."""
     rng = np.random.default_rng(seed)
     parts = []
-    for ci, co in ((16, 32), (32, 32), (32, 32), (32, 3)):
-        live_in = 9 if ci == 16 else ci
+    for li, (ci, co) in enumerate(((16, 32), (32, 32), (32, 32), (32, 3))):
+        live_in = LIVE_IN if ci == 16 else ci
         w = rng.normal(0.0, np.sqrt(2.0 / (9 * live_in)), (3, 3, ci, co))
         if ci == 16:
-            w[:, :, 9:, :] = 0.0
+            w[:, :, LIVE_IN:, :] = 0.0
+        if li == 3:
+            w[:] = 0.0
         parts += [w.reshape(-1), np.zeros(co)]
     return np.concatenate(parts).astype(np.float32)
 
