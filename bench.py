@@ -128,6 +128,9 @@ def main():
     ap.add_argument("--kernel", default="depth", help="kernel group for the roofline object")
     ap.add_argument("--cpu-frames", type=int, default=2, help="frames the oracle times (0 = skip)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-APSS leg")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first copy MIB MiB device to device (a plain copy kernel of known size, the "
+                         "reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); frames are "
@@ -139,6 +142,16 @@ def main():
     import torch
 
     from paper_1905_06700_amd import rt3d, synth
+
+    if args.copy_calibration > 0:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy of {nbytes} bytes done")
+        del src, dst
 
     F = args.frames
     n_distinct = min(F, 8)

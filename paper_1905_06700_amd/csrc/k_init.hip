@@ -96,6 +96,7 @@ __device__ __forceinline__ int popc_ballot(bool x) { return __popcll(__ballot(x)
 constexpr int INIT_WAVES = 4;
 constexpr int INIT_ELDS = 1024;   // pooled entries a wavefront scores from LDS; more: branch and bound
 constexpr int INIT_QLDS = 4096;   // IRF weight tables (ints) up to this size are staged in LDS
+constexpr int INIT_QPAD = 128;    // zero weights on either side of the staged IRF weights
 constexpr int NO_TAU = 0x7fffffff;
 
 // Per-block tables of the LDS branch and bound, in 8-byte words: score bound,
@@ -127,15 +128,22 @@ inline __host__ __device__ int q_levels(int L)
     return n;
 }
 
+// Ints of the staged weight tables: the padded weights, then the range-maximum table.
+inline __host__ __device__ size_t q_staged_ints(int L) { return (size_t)L * (1 + q_levels(L)) + 2 * INIT_QPAD; }
+
 // Exact scores of block bb's 64 tau (one per lane): L(tau) = sum of
-// z q[t - tau + o] over the pooled photons in unclaimed bins t in the window
-// [wlo, whi] the block can see.  The photons are bucketed by 64-bin block in
-// LDS (bucket b ends at bend[b]); the window's buckets are read 64 photons at
-// a time and each photon is broadcast from the lane that loaded it, four at a
-// time so that their weight lookups overlap.  Photons of those buckets outside
-// the window fall outside the lag range and add nothing.  Returns the lane's
+// z q[t - tau + o] over the pooled photons in the window [wlo, whi] the block
+// can see (photons in claimed bins have had their count set to zero).  The
+// photons are bucketed by 64-bin block in LDS (bucket b ends at bend[b]); the
+// window's buckets are read 64 photons at a time and each photon is broadcast
+// from the lane that loaded it, four at a time so that their weight lookups
+// overlap.  Photons of those buckets outside the window add nothing: with QL
+// the staged weights carry INIT_QPAD zeros on either side (qt points at the
+// first weight), which covers every lag the window's buckets produce; lags
+// beyond, from bins >= T, are clamped onto the zeros.  Returns the lane's
 // (score, tau), or (-1, NO_TAU) where tau >= T or an accepted peak suppresses
 // it.
+template <bool QL>
 __device__ __forceinline__ void score_block(const uint32_t* E, const int* bend, int nb, int bb, const int* qt,
                                             int L, int o, int T, const Peaks& pk, int wnms, long long& sv,
                                             int& st)
@@ -154,22 +162,30 @@ __device__ __forceinline__ void score_block(const uint32_t* E, const int* bend, 
             int k = 0;
             for (; k + 4 <= cnt; k += 4) {
                 uint32_t v[4];
-                int lag[4], q[4];
+                int q[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     v[u] = (uint32_t)__builtin_amdgcn_readlane(vv, k + u);
-                    lag[u] = ent_bin(v[u]) - tau + o;
-                    const bool ok = (unsigned)lag[u] < (unsigned)L && pk.owner(ent_bin(v[u])) < 0;
-                    q[u] = ok ? qt[lag[u]] : 0;
+                    const int lag = ent_bin(v[u]) - tau + o;
+                    if (QL) {
+                        q[u] = qt[min(max(lag, -INIT_QPAD), L + INIT_QPAD - 1)];
+                    } else {
+                        q[u] = (unsigned)lag < (unsigned)L ? qt[lag] : 0;
+                    }
                 }
 #pragma unroll
                 for (int u = 0; u < 4; ++u) sc += (long long)ent_cnt(v[u]) * (long long)q[u];
             }
             for (; k < cnt; ++k) {
                 const uint32_t v = (uint32_t)__builtin_amdgcn_readlane(vv, k);
-                const int lg = ent_bin(v) - tau + o;
-                if ((unsigned)lg < (unsigned)L && pk.owner(ent_bin(v)) < 0)
-                    sc += (long long)ent_cnt(v) * (long long)qt[lg];
+                const int lag = ent_bin(v) - tau + o;
+                int q;
+                if (QL) {
+                    q = qt[min(max(lag, -INIT_QPAD), L + INIT_QPAD - 1)];
+                } else {
+                    q = (unsigned)lag < (unsigned)L ? qt[lag] : 0;
+                }
+                sc += (long long)ent_cnt(v) * (long long)q;
             }
         }
     }
@@ -209,15 +225,19 @@ __global__ __launch_bounds__(64 * INIT_WAVES) void k_init(DevModel m, DevParams 
     const size_t ww = init_wave_words(T, R);
     // IRF weights and their range-maximum table, staged by the whole
     // workgroup before any wavefront leaves
-    const int nq = L * (1 + q_levels(L));
+    // (layout: INIT_QPAD zeros, the L weights, INIT_QPAD zeros, the range-maximum table)
+    const int nlev = q_levels(L);
     int* qs = reinterpret_cast<int*>(smem64 + INIT_WAVES * ww);
     if (QL) {
-        for (int k = threadIdx.x; k < L; k += blockDim.x) qs[k] = m.q[k];
-        for (int k = threadIdx.x; k < nq - L; k += blockDim.x) qs[L + k] = m.qst[k];
+        for (int k = threadIdx.x; k < L + 2 * INIT_QPAD; k += blockDim.x) {
+            const int lag = k - INIT_QPAD;
+            qs[k] = (lag >= 0 && lag < L) ? m.q[lag] : 0;
+        }
+        for (int k = threadIdx.x; k < L * nlev; k += blockDim.x) qs[L + 2 * INIT_QPAD + k] = m.qst[k];
     }
     __syncthreads();
-    const int* qt = QL ? qs : m.q;
-    const int* qstt = QL ? qs + L : m.qst;
+    const int* qt = QL ? qs + INIT_QPAD : m.q;
+    const int* qstt = QL ? qs + L + 2 * INIT_QPAD : m.qst;
 
     const long long P = sh.P;
     const long long pix = (long long)blockIdx.x * INIT_WAVES + wv;
@@ -366,7 +386,7 @@ __global__ __launch_bounds__(64 * INIT_WAVES) void k_init(DevModel m, DevParams 
                 long long sv;
                 int st;
                 const int span = bb * INIT_SB / 64;
-                score_block(E, bend, nb, span, qt, L, o, T, pk, m.wnms, sv, st);
+                score_block<QL>(E, bend, nb, span, qt, L, o, T, pk, m.wnms, sv, st);
                 argmax_reduce(sv, st, INIT_SB);                  // best of each sub-block
                 const int sb = span * (64 / INIT_SB) + lane / INIT_SB;
                 if (lane % INIT_SB == 0 && sb < nbs) {
@@ -392,7 +412,7 @@ __global__ __launch_bounds__(64 * INIT_WAVES) void k_init(DevModel m, DevParams 
                 for (int x = (b0 > 0 ? bend[b0 - 1] : 0) + lane; x < x1; x += 64) {
                     const uint32_t v = E[x];
                     const int tb = ent_bin(v);
-                    if (tb >= a && tb <= c && pk.owner(tb) < 0) nwin += ent_cnt(v);
+                    if (tb >= a && tb <= c) nwin += ent_cnt(v);     // claimed photons count zero
                 }
             }
             nwin = wave_sum(nwin);
@@ -401,6 +421,15 @@ __global__ __launch_bounds__(64 * INIT_WAVES) void k_init(DevModel m, DevParams 
             const bool accept = win > 0 && nwin >= p.n_min && d >= 0.0 && d * d >= k2 * bw;
             if (!accept) break;
             pk.push(bestt, a, c, win);
+            // the peak claims the photons of its window: their counts drop to zero
+            {
+                const int b0 = a >> 6, b1 = min(nb - 1, c >> 6);
+                const int x1 = bend[b1];
+                for (int x = (b0 > 0 ? bend[b0 - 1] : 0) + lane; x < x1; x += 64) {
+                    const int tb = ent_bin(E[x]);
+                    if (tb >= a && tb <= c) E[x] &= 0xffff0000u;
+                }
+            }
             // forget the bests of blocks the new peak changes
             const int A0 = a + o - L + 1, A1 = c + o, S0 = bestt - m.wnms, S1 = bestt + m.wnms;
             for (int b = lane; b < nbs; b += 64) {
@@ -666,7 +695,7 @@ __global__ __launch_bounds__(256) void k_init_normals(DevParams p, Shape sh, Dev
 // LDS bytes of one init workgroup: the wavefronts' areas and the IRF weights.
 size_t init_lds_bytes(int T, int L, int r_init)
 {
-    const size_t nq = (size_t)L * (1 + q_levels(L));
+    const size_t nq = q_staged_ints(L);
     const size_t qwords = nq <= INIT_QLDS ? (nq + 1) / 2 : 0;
     return (INIT_WAVES * init_wave_words(T, r_init) + qwords) * sizeof(unsigned long long);
 }
@@ -678,7 +707,7 @@ hipError_t launch_init(const DevModel& m, const DevParams& p, const Shape& sh, c
     if (sh.P == 0) return hipSuccess;
     const size_t lds = init_lds_bytes(m.T, m.L, p.r_init);
     const unsigned nblk = (unsigned)((sh.P + INIT_WAVES - 1) / INIT_WAVES);
-    if ((size_t)m.L * (1 + q_levels(m.L)) <= (size_t)INIT_QLDS)
+    if (q_staged_ints(m.L) <= (size_t)INIT_QLDS)
         hipLaunchKernelGGL(k_init<true>, dim3(nblk), dim3(64 * INIT_WAVES), lds, st, m, p, sh, off, ent, gain, s);
     else
         hipLaunchKernelGGL(k_init<false>, dim3(nblk), dim3(64 * INIT_WAVES), lds, st, m, p, sh, off, ent, gain, s);
