@@ -24,12 +24,11 @@
 //
 // When the pooled photons fit (INIT_ELDS entries, T <= INIT_SB x INIT_NB_LDS),
 // they are staged in LDS, bucketed by 64-bin block, with the IRF weight
-// tables, the bounds are kept per
-// sub-block of INIT_SB tau (tighter, so fewer 64-tau blocks are scored), a
-// scored sub-block keeps its best in LDS, and after an accepted peak only the
-// sub-blocks that peak changes (tau that can see its claimed bins or fall
-// under its suppression) are scored again.  Otherwise the photons are read from HBM and every round scores
-// afresh.
+// tables; the bounds are kept per sub-block of INIT_SB tau (tighter, so fewer
+// 64-tau blocks are scored), a scored block keeps its best in LDS, and after
+// an accepted peak only the blocks that peak changes (tau that can see its
+// claimed bins or fall under its suppression) are scored again.  Otherwise
+// the photons are read from HBM and every round scores afresh.
 #include "rt3d_dev.h"
 
 namespace rt3d {
@@ -94,14 +93,17 @@ __device__ __forceinline__ int q_range_max(const int* qst, int L, int lo, int hi
 __device__ __forceinline__ int popc_ballot(bool x) { return __popcll(__ballot(x)); }
 
 constexpr int INIT_WAVES = 4;
-constexpr int INIT_ELDS = 1024;   // pooled entries a wavefront scores from LDS; more: branch and bound
+constexpr int INIT_ELDS = 768;    // pooled entries a wavefront scores from LDS; more: the HBM path
 constexpr int INIT_QLDS = 4096;   // IRF weight tables (ints) up to this size are staged in LDS
 constexpr int INIT_QPAD = 128;    // zero weights on either side of the staged IRF weights
 constexpr int NO_TAU = 0x7fffffff;
 
-// Per-block tables of the LDS branch and bound, in 8-byte words: score bound,
-// cached best score and cached best tau (int32).
-inline __host__ __device__ size_t init_block_words(int nb) { return 2 * (size_t)nb + ((size_t)nb + 1) / 2; }
+// Tables of the LDS branch and bound, in 8-byte words: a score bound per
+// sub-block, and per 64-tau block the cached best score and tau (int32).
+inline __host__ __device__ size_t init_block_words(int nbs, int nb)
+{
+    return (size_t)nbs + (size_t)nb + ((size_t)nb + 1) / 2;
+}
 
 // Width (tau) of the sub-blocks the LDS path bounds, and the number of
 // sub-blocks up to which it keeps their tables.
@@ -116,7 +118,7 @@ inline __host__ __device__ size_t init_wave_words(int T, int r_init)
     const size_t nb = (size_t)(T + 63) / 64, nbs = (size_t)(T + INIT_SB - 1) / INIT_SB;
     const size_t side = 2 * (size_t)r_init + 1;
     const size_t staged =
-        nbs <= INIT_NB_LDS ? init_block_words((int)nbs) + (size_t)INIT_ELDS / 2 + (nb + 2) / 2 : 0;
+        nbs <= INIT_NB_LDS ? init_block_words((int)nbs, (int)nb) + (size_t)INIT_ELDS / 2 + (nb + 2) / 2 : 0;
     return side * side + (nb > staged ? nb : staged);
 }
 
@@ -289,24 +291,25 @@ __global__ __launch_bounds__(64 * INIT_WAVES) void k_init(DevModel m, DevParams 
 
     const int nbs = (T + INIT_SB - 1) / INIT_SB;
     if (total <= INIT_ELDS && nbs <= INIT_NB_LDS) {
-        // Branch and bound from LDS.  Stage the pooled photon lists; per
-        // sub-block of INIT_SB tau keep a score bound (photons x the largest
-        // weight over the lags the sub-block sees) and, once scored, its exact
-        // best.  The sub-block with the largest bound is scored with the three
-        // others of its 64-tau block (one tau per lane).  After an accepted
-        // peak only sub-blocks whose tau can see its claimed bins or fall under
-        // its suppression lose their best.
-        unsigned long long* bnd = ub;                                   // [nbs] bounds
-        long long* bsc = reinterpret_cast<long long*>(ub + nbs);        // [nbs] cached best score, -2 = none
-        int* btau = reinterpret_cast<int*>(ub + 2 * nbs);               // [nbs] cached best tau
-        uint32_t* E = reinterpret_cast<uint32_t*>(ub + init_block_words(nbs));   // [total] bucketed photons
+        // Branch and bound from LDS.  Stage the pooled photons bucketed by
+        // 64-bin block; keep a score bound per sub-block of INIT_SB tau
+        // (photons x the largest weight over the lags the sub-block sees) and
+        // the exact best of every 64-tau block scored so far.  The unscored
+        // block holding the sub-block with the largest bound is scored next
+        // (one tau per lane).  After an accepted peak only the blocks whose tau
+        // can see its claimed bins or fall under its suppression lose their
+        // best.
+        unsigned long long* bnd = ub;                                   // [nbs] sub-block bounds
+        long long* bsc = reinterpret_cast<long long*>(ub + nbs);        // [nb] cached block best, -2 = none
+        int* btau = reinterpret_cast<int*>(ub + nbs + nb);              // [nb] cached block best tau
+        uint32_t* E = reinterpret_cast<uint32_t*>(ub + init_block_words(nbs, nb));   // [total] bucketed photons
         int* bend = reinterpret_cast<int*>(E + INIT_ELDS);               // [nb] bucket ends
-        for (int b = lane; b < nbs; b += 64) {
-            bnd[b] = 0ull;
+        for (int b = lane; b < nbs; b += 64) bnd[b] = 0ull;
+        for (int b = lane; b < nb; b += 64) {
             bsc[b] = -2;
             btau[b] = NO_TAU;
+            bend[b] = 0;
         }
-        for (int b = lane; b < nb; b += 64) bend[b] = 0;
         wave_sync();
         // photons per 64-bin bucket, photon total and the score bounds
         for (int l = 0; l < npl; ++l) {
@@ -348,10 +351,10 @@ __global__ __launch_bounds__(64 * INIT_WAVES) void k_init(DevModel m, DevParams 
         }
         wave_sync();
         for (int it = 0; it < p.k_init; ++it) {
-            // best over the sub-blocks whose exact best is known
+            // best over the blocks whose exact best is known
             long long best = -1;
             int bestt = NO_TAU;
-            for (int b = lane; b < nbs; b += 64) {
+            for (int b = lane; b < nb; b += 64) {
                 const long long v = bsc[b];
                 const int t = btau[b];
                 if (v > best || (v == best && t < bestt)) {
@@ -361,11 +364,11 @@ __global__ __launch_bounds__(64 * INIT_WAVES) void k_init(DevModel m, DevParams 
             }
             argmax_reduce(best, bestt, 64);
             while (true) {
-                // unscored sub-block with the largest bound (smallest index on ties)
+                // sub-block of an unscored block with the largest bound (smallest index on ties)
                 unsigned long long bu = 0;
                 int bb = NO_TAU;
                 for (int b = lane; b < nbs; b += 64) {
-                    if (bsc[b] != -2) continue;
+                    if (bsc[b * INIT_SB / 64] != -2) continue;
                     const unsigned long long u = bnd[b];
                     if (bb == NO_TAU || u > bu) {
                         bu = u;
@@ -387,13 +390,11 @@ __global__ __launch_bounds__(64 * INIT_WAVES) void k_init(DevModel m, DevParams 
                 int st;
                 const int span = bb * INIT_SB / 64;
                 score_block<QL>(E, bend, nb, span, qt, L, o, T, pk, m.wnms, sv, st);
-                argmax_reduce(sv, st, INIT_SB);                  // best of each sub-block
-                const int sb = span * (64 / INIT_SB) + lane / INIT_SB;
-                if (lane % INIT_SB == 0 && sb < nbs) {
-                    bsc[sb] = sv;
-                    btau[sb] = st;
+                argmax_reduce(sv, st, 64);                       // best of the block's 64 tau
+                if (lane == 0) {
+                    bsc[span] = sv;
+                    btau[span] = st;
                 }
-                argmax_reduce(sv, st, 64);                       // best of the 64 tau
                 wave_sync();
                 if (st != NO_TAU && (sv > best || (sv == best && st < bestt))) {
                     best = sv;
@@ -432,8 +433,8 @@ __global__ __launch_bounds__(64 * INIT_WAVES) void k_init(DevModel m, DevParams 
             }
             // forget the bests of blocks the new peak changes
             const int A0 = a + o - L + 1, A1 = c + o, S0 = bestt - m.wnms, S1 = bestt + m.wnms;
-            for (int b = lane; b < nbs; b += 64) {
-                const int ta = b * INIT_SB, tb = b * INIT_SB + INIT_SB - 1;
+            for (int b = lane; b < nb; b += 64) {
+                const int ta = b << 6, tb = (b << 6) + 63;
                 if ((ta <= A1 && tb >= A0) || (ta <= S1 && tb >= S0)) bsc[b] = -2;
             }
             wave_sync();
