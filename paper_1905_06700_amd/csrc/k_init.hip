@@ -93,7 +93,7 @@ __device__ __forceinline__ int q_range_max(const int* qst, int L, int lo, int hi
 __device__ __forceinline__ int popc_ballot(bool x) { return __popcll(__ballot(x)); }
 
 constexpr int INIT_WAVES = 4;
-constexpr int INIT_ELDS = 768;    // pooled entries a wavefront scores from LDS; more: the HBM path
+constexpr int INIT_ELDS = 640;    // pooled entries a wavefront scores from LDS; more: the HBM path
 constexpr int INIT_QLDS = 4096;   // IRF weight tables (ints) up to this size are staged in LDS
 constexpr int INIT_QPAD = 128;    // zero weights on either side of the staged IRF weights
 constexpr int NO_TAU = 0x7fffffff;
@@ -130,8 +130,8 @@ inline __host__ __device__ int q_levels(int L)
     return n;
 }
 
-// Ints of the staged weight tables: the padded weights, then the range-maximum table.
-inline __host__ __device__ size_t q_staged_ints(int L) { return (size_t)L * (1 + q_levels(L)) + 2 * INIT_QPAD; }
+// Ints of the staged weights (with their zero padding).
+inline __host__ __device__ size_t q_staged_ints(int L) { return (size_t)L + 2 * INIT_QPAD; }
 
 // Exact scores of block bb's 64 tau (one per lane): L(tau) = sum of
 // z q[t - tau + o] over the pooled photons in the window [wlo, whi] the block
@@ -227,19 +227,43 @@ __global__ __launch_bounds__(64 * INIT_WAVES) void k_init(DevModel m, DevParams 
     const size_t ww = init_wave_words(T, R);
     // IRF weights and their range-maximum table, staged by the whole
     // workgroup before any wavefront leaves
-    // (layout: INIT_QPAD zeros, the L weights, INIT_QPAD zeros, the range-maximum table)
-    const int nlev = q_levels(L);
+    // (layout: INIT_QPAD zeros, the L weights, INIT_QPAD zeros); the
+    // range-maximum table, read only for the bounds, stays in HBM
     int* qs = reinterpret_cast<int*>(smem64 + INIT_WAVES * ww);
     if (QL) {
         for (int k = threadIdx.x; k < L + 2 * INIT_QPAD; k += blockDim.x) {
             const int lag = k - INIT_QPAD;
             qs[k] = (lag >= 0 && lag < L) ? m.q[lag] : 0;
         }
-        for (int k = threadIdx.x; k < L * nlev; k += blockDim.x) qs[L + 2 * INIT_QPAD + k] = m.qst[k];
     }
     __syncthreads();
     const int* qt = QL ? qs + INIT_QPAD : m.q;
-    const int* qstt = QL ? qs + L + 2 * INIT_QPAD : m.qst;
+    const int* qstt = m.qst;
+    // With the weights in LDS and unimodal (rising to their first maximum
+    // qpk, falling after it), the largest weight over lags [lo, hi] is
+    // q[clamp(qpk, lo, hi)]; otherwise the range-maximum table answers.
+    int qpk = -1;
+    if (QL) {
+        const int lane0 = threadIdx.x & 63;
+        int qv = -1, qi = NO_TAU;
+        for (int k = lane0; k < L; k += 64)
+            if (qt[k] > qv) {
+                qv = qt[k];
+                qi = k;
+            }
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) {
+            const int ov = __shfl_xor(qv, d, 64), oi = __shfl_xor(qi, d, 64);
+            if (ov > qv || (ov == qv && oi < qi)) {
+                qv = ov;
+                qi = oi;
+            }
+        }
+        bool mono = true;
+        for (int k = lane0; k + 1 < L; k += 64)
+            if (k < qi ? qt[k] > qt[k + 1] : qt[k] < qt[k + 1]) mono = false;
+        qpk = __ballot(!mono) == 0ull ? qi : -1;
+    }
 
     const long long P = sh.P;
     const long long pix = (long long)blockIdx.x * INIT_WAVES + wv;
@@ -323,7 +347,8 @@ __global__ __launch_bounds__(64 * INIT_WAVES) void k_init(DevModel m, DevParams 
                 const int tlo = max(0, t + o - L + 1), thi = min(T - 1, t + o);
                 for (int b = tlo / INIT_SB; b <= thi / INIT_SB; ++b) {
                     const int a0 = max(tlo, b * INIT_SB), a1 = min(thi, b * INIT_SB + INIT_SB - 1);
-                    const int qm = q_range_max(qstt, L, t - a1 + o, t - a0 + o);
+                    const int lo = t - a1 + o, hi = t - a0 + o;
+                    const int qm = qpk >= 0 ? qt[min(max(qpk, lo), hi)] : q_range_max(qstt, L, lo, hi);
                     atomicAdd(&bnd[b], (unsigned long long)z * (unsigned long long)qm);
                 }
             }
