@@ -59,6 +59,7 @@ __device__ __forceinline__ void apss_project(bool ok, float W, float Px, float P
 }
 
 constexpr int LPA = 8;   // lanes per pixel: the window's pixels are split over them
+static_assert(LPA == 8, "the lane sums below are sums over 8 lanes");
 
 __global__ __launch_bounds__(256) void k_apss(DevModel m, DevParams p, Shape sh, DevState in, DevState out,
                                               int only_above)
@@ -86,8 +87,9 @@ __global__ __launch_bounds__(256) void k_apss(DevModel m, DevParams p, Shape sh,
     const float pxy = (float)p.p_xy;
     const double dz = p.dz;
     const double tmax = (double)(m.T - 1);
-    for (int k = 0; k < KM; ++k) {                  // every lane runs every slot (shuffles below)
+    for (int k = 0; k < KM; ++k) {                  // every lane runs the slot (lane sums below)
         const bool act = fit && k < c;
+        if (__ballot(live && k < c) == 0ull) break;  // no pixel of the wavefront has slot k
         const double tq = act ? in.t[k * P + pq] : 0.0;
         float W = 0.f, Px = 0.f, Py = 0.f, Pz = 0.f, Nx = 0.f, Ny = 0.f, Nz = 0.f, PN = 0.f, PP = 0.f, nn = 0.f;
         if (act) {
@@ -120,20 +122,17 @@ __global__ __launch_bounds__(256) void k_apss(DevModel m, DevParams p, Shape sh,
                 }
             }
         }
-        // sphere moments of the pixel's LPA lanes (fixed xor tree)
-#pragma unroll
-        for (int d = 1; d < LPA; d <<= 1) {
-            W += __shfl_xor(W, d, 64);
-            Px += __shfl_xor(Px, d, 64);
-            Py += __shfl_xor(Py, d, 64);
-            Pz += __shfl_xor(Pz, d, 64);
-            Nx += __shfl_xor(Nx, d, 64);
-            Ny += __shfl_xor(Ny, d, 64);
-            Nz += __shfl_xor(Nz, d, 64);
-            PN += __shfl_xor(PN, d, 64);
-            PP += __shfl_xor(PP, d, 64);
-            nn += __shfl_xor(nn, d, 64);
-        }
+        // sphere moments of the pixel's LPA lanes
+        W = oct_sum(W);
+        Px = oct_sum(Px);
+        Py = oct_sum(Py);
+        Pz = oct_sum(Pz);
+        Nx = oct_sum(Nx);
+        Ny = oct_sum(Ny);
+        Nz = oct_sum(Nz);
+        PN = oct_sum(PN);
+        PP = oct_sum(PP);
+        nn = oct_sum(nn);
         if (!live || sub != 0) continue;
         // lane 0 writes the slot: the projection when the fit succeeds, else the input
         double tn = in.t[k * P + pix];

@@ -109,16 +109,14 @@ __device__ __forceinline__ void accumulate(const DevModel& m, const PixPoints& q
 }
 
 // Sums the partials of the LPP lanes of a pixel (every lane ends with the total).
+static_assert(LPP == 4, "the lane reductions below are quad sums");
 __device__ __forceinline__ void reduce_lanes(float& sz, float (&sh)[KM], float (&shp)[KM])
 {
+    sz = quad_sum(sz);
 #pragma unroll
-    for (int d = 1; d < LPP; d <<= 1) {
-        sz += __shfl_xor(sz, d, 64);
-#pragma unroll
-        for (int k = 0; k < KM; ++k) {
-            sh[k] += __shfl_xor(sh[k], d, 64);
-            shp[k] += __shfl_xor(shp[k], d, 64);
-        }
+    for (int k = 0; k < KM; ++k) {
+        sh[k] = quad_sum(sh[k]);
+        shp[k] = quad_sum(shp[k]);
     }
 }
 
@@ -135,12 +133,9 @@ __device__ __forceinline__ void s_eval_points(const DevModel& m, const PixPoints
         if (k < q.c) s_eval(m, q.t[k], S[k], Sp[k], sub, LPP);
     }
 #pragma unroll
-    for (int d = 1; d < LPP; d <<= 1) {
-#pragma unroll
-        for (int k = 0; k < KM; ++k) {
-            S[k] += __shfl_xor(S[k], d, 64);
-            Sp[k] += __shfl_xor(Sp[k], d, 64);
-        }
+    for (int k = 0; k < KM; ++k) {
+        S[k] = quad_sum(S[k]);
+        Sp[k] = quad_sum(Sp[k]);
     }
 }
 

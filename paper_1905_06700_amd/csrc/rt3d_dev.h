@@ -119,6 +119,32 @@ __device__ __forceinline__ T wave_sum(T v)
     return v;
 }
 
+// Cross-lane moves inside small aligned lane groups on the VALU (DPP), with
+// no LDS traffic.  Every lane of the wavefront must be active.
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+
+// Sum over each aligned group of 4 lanes (every lane ends with its group's sum):
+// quad permutations [1,0,3,2] and [2,3,0,1].
+__device__ __forceinline__ float quad_sum(float v)
+{
+    v += dpp_move<0xB1>(v);
+    v += dpp_move<0x4E>(v);
+    return v;
+}
+
+// Sum over each aligned group of 8 lanes: the quad sums, then the half-row
+// mirror (lane i of 8 meets lane 7 - i, which holds the other quad's sum).
+__device__ __forceinline__ float oct_sum(float v)
+{
+    v = quad_sum(v);
+    v += dpp_move<0x141>(v);
+    return v;
+}
+
 // Inclusive prefix sum over the 64 lanes.
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
 {
