@@ -109,14 +109,16 @@ __device__ __forceinline__ void accumulate(const DevModel& m, const PixPoints& q
 }
 
 // Sums the partials of the LPP lanes of a pixel (every lane ends with the total).
-static_assert(LPP == 4, "the lane reductions below are quad sums");
+static_assert(LPP == 4 || LPP == 8, "the lane reductions are sums over 4 or 8 lanes");
+__device__ __forceinline__ float lane_sum(float v) { return LPP == 4 ? quad_sum(v) : oct_sum(v); }
+
 __device__ __forceinline__ void reduce_lanes(float& sz, float (&sh)[KM], float (&shp)[KM])
 {
-    sz = quad_sum(sz);
+    sz = lane_sum(sz);
 #pragma unroll
     for (int k = 0; k < KM; ++k) {
-        sh[k] = quad_sum(sh[k]);
-        shp[k] = quad_sum(shp[k]);
+        sh[k] = lane_sum(sh[k]);
+        shp[k] = lane_sum(shp[k]);
     }
 }
 
@@ -134,8 +136,8 @@ __device__ __forceinline__ void s_eval_points(const DevModel& m, const PixPoints
     }
 #pragma unroll
     for (int k = 0; k < KM; ++k) {
-        S[k] = quad_sum(S[k]);
-        Sp[k] = quad_sum(Sp[k]);
+        S[k] = lane_sum(S[k]);
+        Sp[k] = lane_sum(Sp[k]);
     }
 }
 

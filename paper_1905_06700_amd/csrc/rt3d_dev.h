@@ -88,6 +88,7 @@ __device__ __forceinline__ void s_eval(const DevModel& m, double t, float& S, fl
     // segment k holds bin tb = k + a - o + sh; keep 0 <= tb <= T - 1
     const int k0 = max(-1, m.o - a - sh), k1 = min(m.L - 1, m.T - 1 + m.o - a - sh);
     float acc = 0.f, accp = 0.f;
+#pragma unroll 4
     for (int k = k0 + part; k <= k1; k += parts) {
         float h, hp;
         cr_segment(m.cr[k + 1], s, h, hp);
