@@ -196,6 +196,65 @@ __device__ __forceinline__ void score_block(const uint32_t* E, const int* bend, 
     st = valid ? tau : NO_TAU;
 }
 
+// Whole-wavefront maximum / minimum on the VALU: DPP quad permutations, row
+// shifts by 4 and 8, then row broadcasts of lanes 15 and 31; lane 63 ends with
+// the result, which every lane reads.  Lanes without a DPP source contribute
+// the identity (0 for the maximum of unsigned keys, all ones for the minimum).
+// Every lane must be active.
+template <int CTRL>
+__device__ __forceinline__ unsigned dpp_u32(unsigned v, unsigned identity)
+{
+    return (unsigned)__builtin_amdgcn_update_dpp((int)identity, (int)v, CTRL, 0xF, 0xF, false);
+}
+
+template <int CTRL>
+__device__ __forceinline__ unsigned long long max_step_u64(unsigned long long v)
+{
+    const unsigned long long o = ((unsigned long long)dpp_u32<CTRL>((unsigned)(v >> 32), 0u) << 32) |
+                                 dpp_u32<CTRL>((unsigned)v, 0u);
+    return o > v ? o : v;
+}
+
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
+{
+    v = max_step_u64<0xB1>(v);
+    v = max_step_u64<0x4E>(v);
+    v = max_step_u64<0x114>(v);
+    v = max_step_u64<0x118>(v);
+    v = max_step_u64<0x142>(v);
+    v = max_step_u64<0x143>(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, 63);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), 63);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+template <int CTRL>
+__device__ __forceinline__ unsigned min_step_u32(unsigned v)
+{
+    const unsigned o = dpp_u32<CTRL>(v, 0xffffffffu);
+    return o < v ? o : v;
+}
+
+__device__ __forceinline__ unsigned wave_min_u32(unsigned v)
+{
+    v = min_step_u32<0xB1>(v);
+    v = min_step_u32<0x4E>(v);
+    v = min_step_u32<0x114>(v);
+    v = min_step_u32<0x118>(v);
+    v = min_step_u32<0x142>(v);
+    v = min_step_u32<0x143>(v);
+    return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// Wavefront argmax of (score >= -1, tau): largest score, smallest tau on ties.
+__device__ __forceinline__ void wave_argmax(long long& sv, int& st)
+{
+    const unsigned long long key = (unsigned long long)(sv + 1);
+    const unsigned long long mx = wave_max_u64(key);
+    st = (int)wave_min_u32(key == mx ? (unsigned)st : 0xffffffffu);
+    sv = (long long)mx - 1;
+}
+
 // Argmax of (score, tau) over aligned groups of `width` lanes (a power of
 // two <= 64): largest score, smallest tau on ties; every lane of a group ends
 // with the group's result.
@@ -387,7 +446,7 @@ __global__ __launch_bounds__(64 * INIT_WAVES) void k_init(DevModel m, DevParams 
                     bestt = t;
                 }
             }
-            argmax_reduce(best, bestt, 64);
+            wave_argmax(best, bestt);
             while (true) {
                 // sub-block of an unscored block with the largest bound (smallest index on ties)
                 unsigned long long bu = 0;
@@ -400,22 +459,25 @@ __global__ __launch_bounds__(64 * INIT_WAVES) void k_init(DevModel m, DevParams 
                         bb = b;
                     }
                 }
-#pragma unroll
-                for (int d = 32; d >= 1; d >>= 1) {
-                    const unsigned long long ou = __shfl_xor(bu, d, 64);
-                    const int ob = __shfl_xor(bb, d, 64);
-                    if (ob != NO_TAU && (bb == NO_TAU || ou > bu || (ou == bu && ob < bb))) {
-                        bu = ou;
-                        bb = ob;
-                    }
+                {
+                    const unsigned long long key = bb == NO_TAU ? 0ull : bu + 1;
+                    const unsigned long long mx = wave_max_u64(key);
+                    if (mx == 0ull) break;                           // every block scored
+                    bb = (int)wave_min_u32(key == mx ? (unsigned)bb : 0xffffffffu);
+                    bu = mx - 1;
                 }
-                if (bb == NO_TAU) break;
                 if ((long long)bu < best || ((long long)bu == best && bb * INIT_SB > bestt)) break;
                 long long sv;
                 int st;
                 const int span = bb * INIT_SB / 64;
                 score_block<QL>(E, bend, nb, span, qt, L, o, T, pk, m.wnms, sv, st);
-                argmax_reduce(sv, st, 64);                       // best of the block's 64 tau
+                {
+                    // best of the block's 64 tau (tau rises with the lane)
+                    const unsigned long long key = (unsigned long long)(sv + 1);
+                    const unsigned long long mx = wave_max_u64(key);
+                    st = __builtin_amdgcn_readlane(st, (int)__ffsll((long long)__ballot(key == mx)) - 1);
+                    sv = (long long)mx - 1;
+                }
                 if (lane == 0) {
                     bsc[span] = sv;
                     btau[span] = st;
