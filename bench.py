@@ -10,9 +10,11 @@ log-matched-filter initialisation, 20 iterations of depth / intensity /
 background updates with APSS, the intensity low-pass + threshold and the
 background filter, and output packing.
 
-Prints one JSON line: frames/s (value), Gbin/s and photon-bins/s, the
-roofline of one kernel timed live with HIP events over the timed region, and
-the FP64 CPU oracle timed on a bounded sample on this host.
+Prints one JSON line: frames/s (value), Gbin/s and photon-bins/s, the time
+of every kernel group per call, the roofline of the group taking the most time
+(timed live with HIP events over the timed region; HBM bytes from stored
+FETCH_SIZE / WRITE_SIZE counters when they match the current sources), and the
+FP64 CPU oracle timed on a bounded sample on this host.
 """
 from __future__ import annotations
 
@@ -39,6 +41,21 @@ def scene_params(sc):
     return dict(dz=m["dz"], r_min=m["r_min"], r_init=1, k_init=m["k_init"])
 
 
+# The init's integer score arithmetic (32-bit multiply-adds, 2 ops each) runs
+# on the vector ALU: 64 lanes per CU per clock x 2 ops x 256 CUs x 2.4 GHz.
+ALU_INT_PEAK_TOPS = 64 * 2 * 256 * 2.4e9 / 1e12
+
+# Kernel groups timed one at a time by the library's event timer.
+GROUPS = ["compact", "init", "normals", "depth", "apss", "merge", "intensity", "ifilter", "bkg", "bfilter",
+          "output"]
+
+# Library sources each group's code lives in (for matching stored byte counters).
+GROUP_SOURCES = {"compact": ["k_compact.hip"], "init": ["k_init.hip"], "normals": ["k_init.hip"],
+                 "depth": ["k_steps.hip"], "intensity": ["k_steps.hip"], "bkg": ["k_steps.hip"],
+                 "apss": ["k_apss.hip"], "merge": ["k_apss.hip"], "ifilter": ["k_filter.hip"],
+                 "bfilter": ["k_filter.hip"], "output": ["k_filter.hip", "k_compact.hip"]}
+
+
 def algorithmic_bytes(kernel, F, N, T, E, pts):
     """Bytes a kernel group must move per launch over F frames of N pixels:
     E active entries, pts live points (see the design notes for each row)."""
@@ -55,7 +72,57 @@ def algorithmic_bytes(kernel, F, N, T, E, pts):
     if kernel == "apss":
         # read t, n of every point once and write t, n, r (+ cnt, b copy)
         return pts * (8 + 12) + pts * (8 + 12 + 4) + 2 * FN + 8 * FN
+    if kernel == "merge":
+        return 2 * pts * (8 + 4 + 12) + 2 * FN
+    if kernel == "ifilter":
+        return 24 * pts + 2 * FN
+    if kernel == "bfilter":
+        return 16 * FN
+    if kernel == "normals":
+        return 8 * pts + FN + 12 * pts
+    if kernel == "output":
+        return pts * (8 + 4 + 12) + 4 * (FN + 1) + 4 * FN + FN + 8 * pts
     raise KeyError(kernel)
+
+
+def roofline_of(kernel, F, N, T, E, pooled, L, pts, avg_ms):
+    """Roofline object of one kernel group from its average launch time: HBM
+    bound with algorithmic bytes, except the init, which is bound by its
+    integer score arithmetic: 2 ops x L lags per pooled active entry (the
+    exact log-matched filter over every tau)."""
+    if kernel == "init":
+        ops = 2.0 * pooled * L
+        achieved = ops / (avg_ms / 1e3) / 1e12
+        return {"kernel": kernel, "bound": "alu", "achieved": round(achieved, 3), "peak": ALU_INT_PEAK_TOPS,
+                "unit": "TOP/s", "frac": round(achieved / ALU_INT_PEAK_TOPS, 4), "traffic": None,
+                "avg_launch_us": round(avg_ms * 1e3, 2), "algorithmic_ops_per_launch": int(ops)}
+    abytes = algorithmic_bytes(kernel, F, N, T, E, pts)
+    achieved = abytes / (avg_ms / 1e3) / 1e9
+    return {"kernel": kernel, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "avg_launch_us": round(avg_ms * 1e3, 2),
+            "algorithmic_bytes_per_launch": int(abytes)}
+
+
+def stored_traffic(kernel):
+    """HBM bytes per launch measured with FETCH_SIZE / WRITE_SIZE counters
+    (profiles/traffic_<kernel>_head141x141x4613.md), or None when the
+    kernel's sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_head141x141x4613.md")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    for line in open(path):
+        if line.startswith("traffic "):
+            rec = dict(kv.split("=", 1) for kv in line.split()[1:])
+    if not rec:
+        return None
+    h = hashlib.sha256()
+    for f in GROUP_SOURCES[kernel] + ["rt3d_dev.h"]:
+        h.update(open(os.path.join(ROOT, "paper_1905_06700_amd", "csrc", f), "rb").read())
+    if rec.get("sources_sha256") != h.hexdigest():
+        return None
+    return int(float(rec["bytes_per_launch"]))
 
 
 def learned_vs_apss(n_train=4, n_eval=4, steps=300, rows=256, cols=256, bins=1024):
@@ -125,7 +192,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--frames", type=int, default=16, help="frames per reconstruction call")
-    ap.add_argument("--kernel", default="depth", help="kernel group for the roofline object")
+    ap.add_argument("--kernel", default="", help="kernel group for the roofline object (default: the one "
+                                                  "taking the most time per call)")
     ap.add_argument("--cpu-frames", type=int, default=2, help="frames the oracle times (0 = skip)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-APSS leg")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -179,7 +247,22 @@ def main():
     pts = int(out.pt_off[-1].item())
     log(f"[bench] warmup done: {E} active entries, {pts} points")
 
-    ctx.profile(args.kernel)
+    # time of each kernel group per call (one call each, events around its launches);
+    # the roofline object follows the group that takes the most, timed again live
+    # over the timed region below
+    group = {}
+    for g in GROUPS:
+        ctx.profile(g)
+        step()
+        torch.cuda.synchronize()
+        ms, n = ctx.profile_read()
+        ctx.profile(None)
+        group[g] = (ms, int(n))
+    gtotal = sum(v[0] for v in group.values())
+    kernel = args.kernel or max(group, key=lambda g: group[g][0])
+    log(f"[bench] kernel groups per call: " + ", ".join(f"{g} {group[g][0]:.3f} ms" for g in GROUPS))
+
+    ctx.profile(kernel)
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
@@ -213,13 +296,19 @@ def main():
     torch.cuda.synchronize()
     latency_ms = e0.elapsed_time(e1) / 5
 
+    # pooled active entries (the init's (2 r_init + 1)^2 windows, r_init = 1)
+    nz = (Z != 0).sum(dim=-1, dtype=torch.int64)
+    pad = torch.nn.functional.pad(nz, (1, 1, 1, 1))
+    pooled = int(sum(pad[:, 1 + di:ROWS + 1 + di, 1 + dj:COLS + 1 + dj].sum().item()
+                     for di in (-1, 0, 1) for dj in (-1, 0, 1)))
     avg_ms = kms / max(klaunch, 1)
-    abytes = algorithmic_bytes(args.kernel, F, ROWS * COLS, BINS, E, pts)
-    achieved = abytes / (avg_ms / 1e3) / 1e9
-    roofline = {"kernel": args.kernel, "bound": "hbm", "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None, "avg_launch_us": round(avg_ms * 1e3, 2), "launches": int(klaunch),
-                "algorithmic_bytes_per_launch": int(abytes)}
+    roofline = roofline_of(kernel, F, ROWS * COLS, BINS, E, pooled, len(sc0.irf.probs), pts, avg_ms)
+    roofline["launches"] = int(klaunch)
+    traffic = stored_traffic(kernel)
+    if traffic is not None:
+        roofline["traffic"] = traffic
+    kernels = {g: {"ms_per_call": round(group[g][0], 4), "launches_per_call": group[g][1],
+                   "share": round(group[g][0] / gtotal, 4)} for g in GROUPS}
 
     cpu = None
     if args.cpu_frames > 0:
@@ -250,7 +339,7 @@ def main():
         "gbin_per_s": round(gbin, 2), "photon_bins_per_s": round(pbin, 1),
         "active_entries_per_frame": E // F, "points_per_frame": pts // F,
         "single_frame_latency_ms": round(latency_ms, 3), "wall_s": round(wall, 3),
-        "roofline": roofline, "cpu_baseline": cpu,
+        "roofline": roofline, "kernels": kernels, "cpu_baseline": cpu,
         "learned_vs_apss": None if args.no_learned else learned_vs_apss(),
         "paper_context": {"frames_per_s": 76.9, "ms_per_frame": 13, "hardware": "NVIDIA Titan Xp",
                           "data": "real head scan, ~3 photons/px, SBR 13"},
