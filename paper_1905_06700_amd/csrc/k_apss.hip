@@ -65,7 +65,7 @@ __global__ __launch_bounds__(256) void k_apss(DevModel m, DevParams p, Shape sh,
                                               int only_above)
 {
     const long long P = sh.P;
-    const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long gid = (long long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     const long long pix = gid / LPA;
     const int sub = (int)(gid % LPA);
     const bool live = pix < P;

@@ -21,7 +21,7 @@ namespace rt3d {
 __global__ __launch_bounds__(256) void k_ifilter(DevParams p, Shape sh, DevState in, DevState out)
 {
     const long long P = sh.P;
-    const long long pix = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long pix = (long long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (pix >= P) return;
     const int c = load_cnt(in.cnt, pix);
     const int per_frame = sh.rows * sh.cols;

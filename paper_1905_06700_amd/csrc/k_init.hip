@@ -325,7 +325,7 @@ __global__ __launch_bounds__(64 * INIT_WAVES) void k_init(DevModel m, DevParams 
     }
 
     const long long P = sh.P;
-    const long long pix = (long long)blockIdx.x * INIT_WAVES + wv;
+    const long long pix = (long long)xcd_block(blockIdx.x, gridDim.x) * INIT_WAVES + wv;
     if (pix >= P) return;                       // whole wavefront; no workgroup barriers below
     const int nb = (T + 63) >> 6;
     uint2* lists = reinterpret_cast<uint2*>(smem64 + (size_t)wv * ww);
@@ -722,7 +722,7 @@ __global__ __launch_bounds__(64 * INIT_WAVES) void k_init(DevModel m, DevParams 
 __global__ __launch_bounds__(256) void k_init_normals(DevParams p, Shape sh, DevState s)
 {
     const long long P = sh.P;
-    const long long pix = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long pix = (long long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (pix >= P) return;
     const int c = load_cnt(s.cnt, pix);
     const int per_frame = sh.rows * sh.cols;

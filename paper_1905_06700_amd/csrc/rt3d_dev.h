@@ -146,6 +146,16 @@ __device__ __forceinline__ float oct_sum(float v)
     return v;
 }
 
+// Workgroups are dispatched to the chip's 8 XCDs (each with its own L2) in
+// turn: block b runs on XCD b % 8.  For kernels that read neighbouring
+// pixels, remap so that each XCD takes one contiguous range of the work and
+// neighbouring pixels meet in the same L2.  A bijection of [0, nblocks).
+__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nblocks)
+{
+    const unsigned q = nblocks / 8, r = nblocks % 8, x = b % 8;
+    return x * q + (x < r ? x : r) + b / 8;
+}
+
 // Inclusive prefix sum over the 64 lanes.
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
 {
