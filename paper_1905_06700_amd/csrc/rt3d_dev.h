@@ -22,6 +22,13 @@ struct DevModel {
     int   wnms;           // peak suppression half width
     float sigma2;         // IRF variance
     float fisher_inv;     // 1 / (shift Fisher information per photon)
+    // S and S' of a point whose IRF support lies inside [0, T): all L + 1
+    // segments take part, and when none dips below zero on [0, 1] their sum
+    // is one cubic, s_c0 + s_c1 s + s_c2 s^2 + s_c3 s^3, whose slope loses
+    // s_z0 at s = 0 and s_z1 at s = 1 (segments whose value is exactly zero
+    // there, whose slope the clamp drops)
+    int    s_poly;
+    double s_c0, s_c1, s_c2, s_c3, s_z0, s_z1;
 };
 
 // Parameters as the kernels use them.
@@ -73,8 +80,10 @@ __device__ __forceinline__ void irf_eval(const DevModel& m, int tb, int a, float
     }
 }
 
-// S(t) = sum over bins of h(tb - t) and dS/dt = -sum h'(tb - t), by direct
-// summation over the IRF support (every lag shares the local parameter).
+// S(t) = sum over bins of h(tb - t) and dS/dt = -sum h'(tb - t) (every lag
+// shares the local parameter s).  Inside the domain, for an IRF whose segments
+// never dip below zero, the closed-form cubic of all segments; else by direct
+// summation over the segments that fall inside [0, T).
 // Lane `part` of `parts` sums the segments k0 + part, k0 + part + parts, ...
 // (parts = 1: the whole sum).
 __device__ __forceinline__ void s_eval(const DevModel& m, double t, float& S, float& Sp, int part = 0,
@@ -87,6 +96,19 @@ __device__ __forceinline__ void s_eval(const DevModel& m, double t, float& S, fl
     const float s = sh ? 1.f - f : 0.f;
     // segment k holds bin tb = k + a - o + sh; keep 0 <= tb <= T - 1
     const int k0 = max(-1, m.o - a - sh), k1 = min(m.L - 1, m.T - 1 + m.o - a - sh);
+    if (m.s_poly && k0 == -1 && k1 == m.L - 1) {   // every segment: one cubic (computed by part 0)
+        S = 0.f;
+        Sp = 0.f;
+        if (part == 0) {
+            const double sd = (double)s;
+            double dp = (3.0 * m.s_c3 * sd + 2.0 * m.s_c2) * sd + m.s_c1;
+            if (s == 0.f) dp -= m.s_z0;
+            else if (s == 1.f) dp -= m.s_z1;
+            S = (float)(((m.s_c3 * sd + m.s_c2) * sd + m.s_c1) * sd + m.s_c0);
+            Sp = (float)(-dp);
+        }
+        return;
+    }
     float acc = 0.f, accp = 0.f;
 #pragma unroll 4
     for (int k = k0 + part; k <= k1; k += parts) {

@@ -24,6 +24,8 @@ struct rt3d_ctx {
     rt3d_params p{};
     int T = 0, L = 0, o = 0;
     double sigma2 = 0.0, fisher = 0.0;
+    int s_poly = 0;
+    double s_c[4] = {0, 0, 0, 0}, s_z0 = 0.0, s_z1 = 0.0;   // S over all segments (see DevModel)
     int wl = 0, wr = 0, wnms = 0, apss_R = 0;
     double dmax = 0.0, dmerge = 0.0;
     std::vector<double> hbar;
@@ -175,6 +177,13 @@ DevModel dev_model(const rt3d_ctx* c)
     m.wnms = c->wnms;
     m.sigma2 = (float)c->sigma2;
     m.fisher_inv = (float)(1.0 / c->fisher);
+    m.s_poly = c->s_poly;
+    m.s_c0 = c->s_c[0];
+    m.s_c1 = c->s_c[1];
+    m.s_c2 = c->s_c[2];
+    m.s_c3 = c->s_c[3];
+    m.s_z0 = c->s_z0;
+    m.s_z1 = c->s_z1;
     return m;
 }
 
@@ -409,6 +418,36 @@ rt3d_status rt3d_create(const double* irf, uint32_t irf_len, int32_t irf_origin,
         d[2] = p0 - 2.5 * p1 + 2.0 * p2 - 0.5 * p3;
         d[3] = 0.5 * (p3 - p0) + 1.5 * (p1 - p2);
         cr[k + 1] = make_float4((float)d[0], (float)d[1], (float)d[2], (float)d[3]);
+    }
+    // S and S' of points whose IRF support lies inside the domain: the sum of
+    // all segments' cubics is one cubic when no segment dips below zero on
+    // [0, 1] (then the clamp at zero only drops the slope of segments whose
+    // value is exactly zero at s = 0 or s = 1)
+    {
+        bool ok = true;
+        for (int j = 0; j <= L; ++j) {
+            const double* d = &crd[(size_t)4 * j];
+            auto val = [&](double x) { return ((d[3] * x + d[2]) * x + d[1]) * x + d[0]; };
+            double lo = std::min(val(0.0), val(1.0));
+            const double A = 3.0 * d[3], B = 2.0 * d[2], Cc = d[1];   // slope: A x^2 + B x + Cc
+            if (A != 0.0) {
+                const double disc = B * B - 4.0 * A * Cc;
+                if (disc >= 0.0) {
+                    const double r = std::sqrt(disc);
+                    for (double x : {(-B - r) / (2.0 * A), (-B + r) / (2.0 * A)})
+                        if (x > 0.0 && x < 1.0) lo = std::min(lo, val(x));
+                }
+            } else if (B != 0.0) {
+                const double x = -Cc / B;
+                if (x > 0.0 && x < 1.0) lo = std::min(lo, val(x));
+            }
+            if (lo < 0.0) ok = false;
+            for (int i = 0; i < 4; ++i) c->s_c[i] += d[i];
+            const int k = j - 1;   // segment k joins samples k and k + 1
+            if (hb(k) == 0.0) c->s_z0 += d[1];
+            if (hb(k + 1) == 0.0) c->s_z1 += d[1] + 2.0 * d[2] + 3.0 * d[3];
+        }
+        c->s_poly = ok ? 1 : 0;
     }
     // shift Fisher information of one photon (no background), averaged over 32
     // sub-bin phases, over lags where h is at least 1e-3 of the largest sample
