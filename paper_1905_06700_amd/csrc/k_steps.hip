@@ -58,12 +58,37 @@ __device__ __forceinline__ void load_points(const DevState& s, long long P, long
 // Lanes per pixel: a pixel's active entries are split over LPP consecutive
 // lanes (entry e + LPP i), whose partial sums meet in a shuffle tree.
 constexpr int LPP = 4;
+constexpr int STEP_BATCH = 16;   // entries a lane loads at once
 
-// Partial sums over the entries e0, e0 + LPP, ... < e1 of one pixel:
+// Orders the LDS traffic of one wavefront (a pixel's lanes share its list).
+__device__ __forceinline__ void step_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Value of lane I of each aligned group of 4 lanes (DPP quad permutation).
+template <int I>
+__device__ __forceinline__ int quad_bcast(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, I * 0x55, 0xF, 0xF, true);
+}
+
+// Photons a pixel's entry list holds per batch in LDS.
+constexpr int STEP_LIST = STEP_BATCH * LPP;
+
+// Partial sums over one pixel's entries (e0p .. e1 - 1):
 // sz = sum z/lambda, sh[k] = sum z h_k/lambda, shp[k] = sum z h'_k/lambda.
+// The pixel's LPP lanes load its entries STEP_BATCH per lane at a time
+// (entry e0p + sub + LPP u).  h_k vanishes outside bins
+// [floor(t_k) - o - 1, floor(t_k) - o + L], so only entries inside the union
+// of these ranges (the points' support) are evaluated: they are compacted
+// into the pixel's LDS list and shared out over the lanes.  Every other entry
+// has lambda = g b and only adds z / (g b) to sz.
 __device__ __forceinline__ void accumulate(const DevModel& m, const PixPoints& q, float bb, float G,
-                                           const uint32_t* __restrict__ ent, uint32_t e0, uint32_t e1,
-                                           float& sz, float (&sh)[KM], float (&shp)[KM])
+                                           const uint32_t* __restrict__ ent, uint32_t e0p, uint32_t e1, int sub,
+                                           uint32_t* list, float& sz, float (&sh)[KM], float (&shp)[KM])
 {
     sz = 0.f;
 #pragma unroll
@@ -96,16 +121,44 @@ __device__ __forceinline__ void accumulate(const DevModel& m, const PixPoints& q
             }
         }
     };
-    // four entries in flight per lane, then the tail
-    uint32_t e = e0;
-    for (; e + 3 * LPP < e1; e += 4 * LPP) {
-        uint32_t v[4];
+    int lo = 0x7fffffff, hi = -0x7fffffff;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) v[u] = ent[e + u * LPP];
+    for (int k = 0; k < KM; ++k)
+        if (k < q.c) {
+            lo = min(lo, q.a[k] - m.o - 1);
+            hi = max(hi, q.a[k] - m.o + m.L);
+        }
+    float zout = 0.f;
+    for (uint32_t eb = e0p; eb < e1; eb += STEP_LIST) {    // the same trip count on the pixel's lanes
+        uint32_t v[STEP_BATCH];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) one(v[u]);
+        for (int u = 0; u < STEP_BATCH; ++u) {
+            const uint32_t x = eb + sub + u * LPP;
+            v[u] = x < e1 ? ent[x] : 0u;
+        }
+        unsigned inmask = 0;
+        int n = 0;
+#pragma unroll
+        for (int u = 0; u < STEP_BATCH; ++u) {
+            const bool valid = eb + sub + u * LPP < e1;
+            const int tb = ent_bin(v[u]);
+            const bool in = valid && tb >= lo && tb <= hi;
+            if (valid && !in) zout += (float)ent_cnt(v[u]);
+            inmask |= in ? (1u << u) : 0u;
+            n += in ? 1 : 0;
+        }
+        static_assert(LPP == 4, "the list offsets below are quad prefix sums");
+        const int n0 = quad_bcast<0>(n), n1 = quad_bcast<1>(n), n2 = quad_bcast<2>(n), n3 = quad_bcast<3>(n);
+        int w = (sub > 0 ? n0 : 0) + (sub > 1 ? n1 : 0) + (sub > 2 ? n2 : 0);
+        const int total = n0 + n1 + n2 + n3;
+#pragma unroll
+        for (int u = 0; u < STEP_BATCH; ++u)
+            if ((inmask >> u) & 1u) list[w++] = v[u];
+        step_sync();
+        for (int j = sub; j < total; j += LPP) one(list[j]);
+        step_sync();
     }
-    for (; e < e1; e += LPP) one(ent[e]);
+    sz += zout * invG * __builtin_amdgcn_rcpf(bb);
 }
 
 // Sums the partials of the LPP lanes of a pixel (every lane ends with the total).
@@ -148,7 +201,7 @@ struct Lane {
     bool live;
     float G;
     PixPoints q;
-    uint32_t e0, e1;
+    uint32_t e0, e1;   // the pixel's entries
 };
 
 __device__ __forceinline__ Lane lane_setup(const DevState& s, long long P, const uint32_t* __restrict__ off,
@@ -164,7 +217,7 @@ __device__ __forceinline__ Lane lane_setup(const DevState& s, long long P, const
     load_points(s, P, pp, L.q);
     if (!L.live) L.q.c = 0;
     const bool work = L.live && L.G > 0.f && (!need_points || L.q.c > 0);
-    L.e0 = work ? off[pp] + L.sub : 0;
+    L.e0 = work ? off[pp] : 0;
     L.e1 = work ? off[pp + 1] : 0;
     L.live = work;
     return L;
@@ -175,10 +228,12 @@ __global__ __launch_bounds__(256) void k_depth_step(DevModel m, DevParams p, Sha
                                                     const uint32_t* __restrict__ ent,
                                                     const float* __restrict__ gain, DevState s)
 {
+    __shared__ uint32_t lists[256 / LPP * STEP_LIST];
+    uint32_t* list = lists + (threadIdx.x / LPP) * STEP_LIST;
     const long long P = sh.P;
     const Lane L = lane_setup(s, P, off, gain, true);
     float sz, shh[KM], shp[KM];
-    accumulate(m, L.q, L.live ? s.b[L.pix] : 1.f, L.live ? L.G : 1.f, ent, L.e0, L.e1, sz, shh, shp);
+    accumulate(m, L.q, L.live ? s.b[L.pix] : 1.f, L.live ? L.G : 1.f, ent, L.e0, L.e1, L.sub, list, sz, shh, shp);
     reduce_lanes(sz, shh, shp);
     float Sv[KM], Spv[KM];
     s_eval_points(m, L.q, L.sub, Sv, Spv);
@@ -203,10 +258,12 @@ __global__ __launch_bounds__(256) void k_intensity_step(DevModel m, DevParams p,
                                                         const uint32_t* __restrict__ ent,
                                                         const float* __restrict__ gain, DevState s)
 {
+    __shared__ uint32_t lists[256 / LPP * STEP_LIST];
+    uint32_t* list = lists + (threadIdx.x / LPP) * STEP_LIST;
     const long long P = sh.P;
     const Lane L = lane_setup(s, P, off, gain, true);
     float sz, shh[KM], shp[KM];
-    accumulate(m, L.q, L.live ? s.b[L.pix] : 1.f, L.live ? L.G : 1.f, ent, L.e0, L.e1, sz, shh, shp);
+    accumulate(m, L.q, L.live ? s.b[L.pix] : 1.f, L.live ? L.G : 1.f, ent, L.e0, L.e1, L.sub, list, sz, shh, shp);
     reduce_lanes(sz, shh, shp);
     float Sv[KM], Spv[KM];
     s_eval_points(m, L.q, L.sub, Sv, Spv);
@@ -229,11 +286,13 @@ __global__ __launch_bounds__(256) void k_bg_step(DevModel m, DevParams p, Shape 
                                                  const uint32_t* __restrict__ ent,
                                                  const float* __restrict__ gain, DevState s)
 {
+    __shared__ uint32_t lists[256 / LPP * STEP_LIST];
+    uint32_t* list = lists + (threadIdx.x / LPP) * STEP_LIST;
     const long long P = sh.P;
     const Lane L = lane_setup(s, P, off, gain, false);
     const float bb = L.live ? s.b[L.pix] : 1.f;
     float sz, shh[KM], shp[KM];
-    accumulate(m, L.q, bb, L.live ? L.G : 1.f, ent, L.e0, L.e1, sz, shh, shp);
+    accumulate(m, L.q, bb, L.live ? L.G : 1.f, ent, L.e0, L.e1, L.sub, list, sz, shh, shp);
     reduce_lanes(sz, shh, shp);
     if (!L.live || L.sub != 0) return;
     const float bt = (float)p.beta_b;
@@ -247,10 +306,12 @@ __global__ __launch_bounds__(256) void k_gradients(DevModel m, Shape sh, const u
                                                    float* __restrict__ gt, float* __restrict__ gr,
                                                    float* __restrict__ gb)
 {
+    __shared__ uint32_t lists[256 / LPP * STEP_LIST];
+    uint32_t* list = lists + (threadIdx.x / LPP) * STEP_LIST;
     const long long P = sh.P;
     const Lane L = lane_setup(s, P, off, gain, false);
     float sz, shh[KM], shp[KM];
-    accumulate(m, L.q, L.live ? s.b[L.pix] : 1.f, L.live ? L.G : 1.f, ent, L.e0, L.e1, sz, shh, shp);
+    accumulate(m, L.q, L.live ? s.b[L.pix] : 1.f, L.live ? L.G : 1.f, ent, L.e0, L.e1, L.sub, list, sz, shh, shp);
     reduce_lanes(sz, shh, shp);
     float Sv[KM], Spv[KM];
     s_eval_points(m, L.q, L.sub, Sv, Spv);
