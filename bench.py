@@ -125,6 +125,41 @@ def stored_traffic(kernel):
     return int(float(rec["bytes_per_launch"]))
 
 
+def small_frames(F=64, reps=5):
+    """Batches of small frames (config 1 plane scenes, 32 x 32 x 300), where
+    the ~140 launches of a call dominate: direct calls against replays of a
+    recorded graph."""
+    import numpy as np
+    import torch
+
+    from paper_1905_06700_amd import rt3d, synth
+
+    scenes = [synth.plane_scene(s) for s in range(4)]
+    sc = scenes[0]
+    R, C, T = sc.rows, sc.cols, sc.T
+    Z = torch.stack([torch.from_numpy(scenes[f % 4].Z.view(np.int16)) for f in range(F)]).cuda()
+    m = sc.meta
+    ctx = rt3d.Context(sc.irf.probs, T, dz=m["dz"], r_min=m["r_min"], r_init=m["r_init"], k_init=m["k_init"])
+    ctx.workspace(F, R, C, F * R * C * 64)
+    out = ctx.make_output(F * R * C)
+    res = {"workload": f"{F} frames of {R}x{C}x{T} (tilted plane, 10 signal + 1 background photon/px) per call"}
+    g = ctx.graph(out, F, R, C, hist=Z)
+    for name, run in (("direct", lambda: ctx.reconstruct_into(out, F, R, C, hist=Z)), ("graph", g.launch)):
+        run()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            run()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        res[f"call_ms_{name}"] = round(ms, 3)
+        res[f"frames_per_s_{name}"] = round(F / (ms / 1e3), 1)
+    del g
+    return res
+
+
 def learned_vs_apss(n_train=4, n_eval=4, steps=300, rows=256, cols=256, bins=1024):
     """Learned denoiser against plain APSS on multi-layer scenes: train on the
     GPU (the library's forward/backward kernels), then time and score both on
@@ -295,6 +330,18 @@ def main():
     e1.record()
     torch.cuda.synchronize()
     latency_ms = e0.elapsed_time(e1) / 5
+    # the same frame replayed from a recorded graph (one launch per call)
+    g1 = ctx.graph(out1, 1, ROWS, COLS, hist=Z1)
+    for _ in range(2):
+        g1.launch()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(5):
+        g1.launch()
+    e1.record()
+    torch.cuda.synchronize()
+    latency_graph_ms = e0.elapsed_time(e1) / 5
+    del g1
 
     # pooled active entries (the init's (2 r_init + 1)^2 windows, r_init = 1)
     nz = (Z != 0).sum(dim=-1, dtype=torch.int64)
@@ -338,7 +385,8 @@ def main():
                    "frames_per_step": F, "rows": ROWS, "cols": COLS, "bins": BINS, "iterations": 20},
         "gbin_per_s": round(gbin, 2), "photon_bins_per_s": round(pbin, 1),
         "active_entries_per_frame": E // F, "points_per_frame": pts // F,
-        "single_frame_latency_ms": round(latency_ms, 3), "wall_s": round(wall, 3),
+        "single_frame_latency_ms": round(latency_ms, 3), "single_frame_latency_graph_ms": round(latency_graph_ms, 3),
+        "small_frames": small_frames(), "wall_s": round(wall, 3),
         "roofline": roofline, "kernels": kernels, "cpu_baseline": cpu,
         "learned_vs_apss": None if args.no_learned else learned_vs_apss(),
         "paper_context": {"frames_per_s": 76.9, "ms_per_frame": 13, "hardware": "NVIDIA Titan Xp",

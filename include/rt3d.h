@@ -190,6 +190,20 @@ rt3d_status rt3d_set_workspace(rt3d_ctx* ctx, void* dev_ptr, size_t bytes, uint3
 rt3d_status rt3d_reconstruct(rt3d_ctx* ctx, const rt3d_input* in, rt3d_output* out,
                              void* hip_stream);
 
+/* Replayable reconstruction: one rt3d_reconstruct call recorded into a HIP
+ * graph (its ~140 kernel launches become one graph launch).  The graph keeps
+ * the call's pointers -- input, output, gain and the context's workspace --
+ * so each replay repeats exactly that call on whatever the buffers then hold;
+ * the caller refills the input between replays and must not rebind the
+ * workspace or destroy the context while the graph exists.  Recording
+ * enqueues nothing; E_STATE while kernel timing (rt3d_profile) is on; the
+ * argument checks of rt3d_reconstruct apply.  rt3d_graph_launch is
+ * asynchronous on hip_stream.  rt3d_graph_destroy accepts NULL. */
+typedef struct rt3d_graph rt3d_graph;
+rt3d_status rt3d_graph_create(rt3d_ctx* ctx, const rt3d_input* in, rt3d_output* out, rt3d_graph** graph);
+rt3d_status rt3d_graph_launch(rt3d_graph* graph, void* hip_stream);
+void rt3d_graph_destroy(rt3d_graph* graph);
+
 /* Synchronise hip_stream, then report device-side errors, entry and point
  * counts of the last calls.  Returns the sticky device error (or OK). */
 rt3d_status rt3d_query(rt3d_ctx* ctx, void* hip_stream, rt3d_stats* st);

@@ -687,6 +687,67 @@ rt3d_status rt3d_reconstruct(rt3d_ctx* c, const rt3d_input* in, rt3d_output* out
     return RT3D_OK;
 }
 
+struct rt3d_graph {
+    rt3d_ctx* ctx = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+rt3d_status rt3d_graph_create(rt3d_ctx* c, const rt3d_input* in, rt3d_output* out, rt3d_graph** graph)
+{
+    if (!c) return RT3D_E_INVALID;
+    if (!graph) return fail(c, RT3D_E_INVALID, "graph is NULL");
+    *graph = nullptr;
+    if (c->prof_id >= 0) return fail(c, RT3D_E_STATE, "kernel timing is on; turn it off to record a graph");
+    hipStream_t cap = nullptr;
+    RT3D_HIP(c, hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeGlobal);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(cap);
+        return hip_fail(c, e, "hipStreamBeginCapture");
+    }
+    const rt3d_status s = rt3d_reconstruct(c, in, out, cap);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(cap, &g);
+    (void)hipStreamDestroy(cap);
+    if (s != RT3D_OK || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return s != RT3D_OK ? s : hip_fail(c, e, "hipStreamEndCapture");
+    }
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return hip_fail(c, e, "hipGraphInstantiate");
+    }
+    rt3d_graph* r = new (std::nothrow) rt3d_graph();
+    if (!r) {
+        (void)hipGraphExecDestroy(x);
+        (void)hipGraphDestroy(g);
+        return fail(c, RT3D_E_NOMEM, "graph allocation");
+    }
+    r->ctx = c;
+    r->graph = g;
+    r->exec = x;
+    *graph = r;
+    return RT3D_OK;
+}
+
+rt3d_status rt3d_graph_launch(rt3d_graph* g, void* hip_stream)
+{
+    if (!g) return RT3D_E_INVALID;
+    RT3D_HIP(g->ctx, hipGraphLaunch(g->exec, (hipStream_t)hip_stream));
+    return RT3D_OK;
+}
+
+void rt3d_graph_destroy(rt3d_graph* g)
+{
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+}
+
 rt3d_status rt3d_query(rt3d_ctx* c, void* hip_stream, rt3d_stats* st)
 {
     if (!c) return RT3D_E_INVALID;

@@ -25,7 +25,7 @@ STEP_INIT, STEP_DEPTH, STEP_APSS, STEP_MERGE, STEP_INTENSITY, STEP_IFILTER, STEP
 
 EXPORTS = ["rt3d_params_default", "rt3d_create", "rt3d_destroy", "rt3d_last_error", "rt3d_sigma2",
            "rt3d_workspace_bytes", "rt3d_set_workspace", "rt3d_reconstruct", "rt3d_query",
-           "rt3d_profile", "rt3d_profile_read",
+           "rt3d_profile", "rt3d_profile_read", "rt3d_graph_create", "rt3d_graph_launch", "rt3d_graph_destroy",
            "rt3d_debug_compact", "rt3d_debug_compact_events", "rt3d_debug_step", "rt3d_debug_gradients",
            "rt3d_cnn_set_weights", "rt3d_cnn_get_weights", "rt3d_cnn_last_gradient",
            "rt3d_cnn_forward", "rt3d_cnn_train_step"]
@@ -116,6 +116,12 @@ def lib():
         L.rt3d_profile.restype = st
         L.rt3d_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]
         L.rt3d_profile_read.restype = st
+        L.rt3d_graph_create.argtypes = [vp, C.POINTER(Input), C.POINTER(Output), C.POINTER(vp)]
+        L.rt3d_graph_create.restype = st
+        L.rt3d_graph_launch.argtypes = [vp, vp]
+        L.rt3d_graph_launch.restype = st
+        L.rt3d_graph_destroy.argtypes = [vp]
+        L.rt3d_graph_destroy.restype = None
         L.rt3d_debug_compact.argtypes = [vp, vp, C.c_uint32, vp, vp, C.c_uint64, vp]
         L.rt3d_debug_compact.restype = st
         L.rt3d_debug_compact_events.argtypes = [vp, vp, vp, C.c_uint64, C.c_uint32, vp, vp, vp, C.c_uint64, vp]
@@ -192,6 +198,22 @@ class Result:
     background: torch.Tensor  # float32 [P]
 
 
+class Graph:
+    """A recorded reconstruction (keeps its buffers alive); launch() replays it
+    on the current torch stream."""
+
+    def __init__(self, ctx, handle, keep):
+        self._ctx, self._h, self._keep = ctx, handle, keep
+
+    def launch(self):
+        self._ctx._check(lib().rt3d_graph_launch(self._h, _stream()))
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.rt3d_graph_destroy(self._h)
+            self._h = None
+
+
 class Context:
     """One rt3d context: an IRF, a bin count and parameters."""
 
@@ -262,10 +284,8 @@ class Context:
                       torch.zeros(cap, 3, dtype=torch.float32, device=dev) if normals else None,
                       torch.zeros(P, dtype=torch.float32, device=dev))
 
-    def reconstruct_into(self, out: Result, frames: int, rows: int, cols: int, hist=None, off=None,
-                         ent=None, gain=None, events=None):
-        """Enqueue one reconstruction on the current torch stream (no sync).
-        Input: hist, or (off, ent), or events = (pixel int32, bin int16, scratch int32)."""
+    def _io(self, out: Result, frames: int, rows: int, cols: int, hist=None, off=None, ent=None, gain=None,
+            events=None):
         inp = Input()
         inp.struct_size = C.sizeof(Input)
         inp.frames, inp.rows, inp.cols = frames, rows, cols
@@ -290,8 +310,23 @@ class Context:
         o.pt_off, o.depth, o.intensity = out.pt_off.data_ptr(), out.depth.data_ptr(), out.intensity.data_ptr()
         o.normal = out.normal.data_ptr() if out.normal is not None else None
         o.background = out.background.data_ptr()
+        return inp, o
+
+    def reconstruct_into(self, out: Result, frames: int, rows: int, cols: int, hist=None, off=None,
+                         ent=None, gain=None, events=None):
+        """Enqueue one reconstruction on the current torch stream (no sync).
+        Input: hist, or (off, ent), or events = (pixel int32, bin int16, scratch int32)."""
+        inp, o = self._io(out, frames, rows, cols, hist, off, ent, gain, events)
         self._check(lib().rt3d_reconstruct(self._h, C.byref(inp), C.byref(o), _stream()))
         return out
+
+    def graph(self, out: Result, frames: int, rows: int, cols: int, hist=None, off=None, ent=None, gain=None,
+              events=None) -> "Graph":
+        """Record reconstruct_into with these buffers as a replayable graph."""
+        inp, o = self._io(out, frames, rows, cols, hist, off, ent, gain, events)
+        h = C.c_void_p()
+        self._check(lib().rt3d_graph_create(self._h, C.byref(inp), C.byref(o), C.byref(h)))
+        return Graph(self, h, (out, hist, off, ent, gain, events))
 
     def reconstruct(self, hist, gain=None, max_entries=None) -> Result:
         """hist: cuda uint16 [frames, rows, cols, bins] (or [rows, cols, bins])."""
