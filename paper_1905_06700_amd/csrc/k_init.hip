@@ -12,23 +12,30 @@
 // only.  Intensity = own photons in the claimed bins minus background over
 // the IRF mass there; background = own photons outside the claimed bins.
 //
-// Mapping: one wavefront per pixel, four pixels per workgroup.  The argmax
-// over tau is an exact branch and bound over blocks of 64 consecutive tau
-// (one tau per lane): an upper bound of every block's best score,
-// sum over pooled photons of z * max q over the lags the block can see, is
-// scattered into LDS with 64-bit integer atomics; blocks are then scored
-// exactly in decreasing bound order until no remaining bound can beat (or tie
-// at a smaller tau) the best score found.  The bound only counts photons, so
-// it stays valid after photons are claimed.  Only a few blocks per pixel are
-// ever scored exactly, so the cost follows the active bins, not T.
+// Mapping: one wavefront per pixel, four pixels per workgroup.  The window's
+// rows are contiguous ranges of the photon lists (pixel-major CSR), so the
+// pooled photons are (2 r_init + 1) ranges.  The argmax over tau is an exact
+// branch and bound over blocks of 64 consecutive tau (one tau per lane): an
+// upper bound of every block's best score, sum over pooled photons of z *
+// max q over the lags the block can see, is scattered into LDS with integer
+// atomics; blocks are then scored exactly in decreasing bound order until no
+// remaining bound can beat (or tie at a smaller tau) the best score found.
+// The bound only counts photons, so it stays valid after photons are claimed.
+// Only a few blocks per pixel are ever scored exactly, so the cost follows the
+// active bins, not T.
 //
-// When the pooled photons fit (INIT_ELDS entries, T <= INIT_SB x INIT_NB_LDS),
-// they are staged in LDS, bucketed by 64-bin block, with the IRF weight
-// tables; the bounds are kept per sub-block of INIT_SB tau (tighter, so fewer
-// 64-tau blocks are scored), a scored block keeps its best in LDS, and after
-// an accepted peak only the blocks that peak changes (tau that can see its
-// claimed bins or fall under its suppression) are scored again.  Otherwise
-// the photons are read from HBM and every round scores afresh.
+// When the pooled photons fit (INIT_ELDS entries, T <= INIT_SB x INIT_NB_LDS)
+// and the weights are staged in LDS, the photons are read once into registers
+// and staged in LDS bucketed by 64-bin block; the bounds are kept per
+// sub-block of INIT_SB tau (tighter, so fewer 64-tau blocks are scored) from a
+// sliding-maximum weight table; each lane keeps the bound and cached best of
+// the blocks lane and lane + 64; after an accepted peak only the blocks that
+// peak changes (tau that can see its claimed bins or fall under its
+// suppression) are scored again.  This path also needs the pixel's photon
+// total times the largest weight to fit 32 bits: every score and bound then
+// does, and the search runs on 32-bit integers (24-bit multiply-adds, exact
+// here).  Pixels outside these limits read their photons from HBM and score
+// every round afresh with 64-bit sums.
 #include "rt3d_dev.h"
 
 namespace rt3d {
@@ -94,107 +101,33 @@ __device__ __forceinline__ int popc_ballot(bool x) { return __popcll(__ballot(x)
 
 constexpr int INIT_WAVES = 4;
 constexpr int INIT_ELDS = 640;    // pooled entries a wavefront scores from LDS; more: the HBM path
+constexpr int INIT_EPL = INIT_ELDS / 64;   // pooled entries per lane
 constexpr int INIT_QLDS = 4096;   // IRF weight tables (ints) up to this size are staged in LDS
 constexpr int INIT_QPAD = 128;    // zero weights on either side of the staged IRF weights
 constexpr int NO_TAU = 0x7fffffff;
 
-// Tables of the LDS branch and bound, in 8-byte words: a score bound per
-// sub-block, and per 64-tau block the cached best score and tau (int32).
-inline __host__ __device__ size_t init_block_words(int nbs, int nb)
-{
-    return (size_t)nbs + (size_t)nb + ((size_t)nb + 1) / 2;
-}
-
 // Width (tau) of the sub-blocks the LDS path bounds, and the number of
-// sub-blocks up to which it keeps their tables.
+// sub-blocks up to which it keeps their tables (at most two 64-tau blocks per
+// lane).
 constexpr int INIT_SB = 16;
 constexpr int INIT_NB_LDS = 512;
+static_assert(INIT_NB_LDS * INIT_SB <= 128 * 64, "two blocks per lane");
 
-// 8-byte LDS words of one wavefront: the pooled CSR ranges, then either the
-// LDS path's block tables, bucketed photons and bucket ends, or the HBM path's
-// block bounds.
+// 8-byte LDS words of one wavefront: the HBM path's per-pixel photon ranges,
+// then either the LDS path's sub-block bounds, bucketed photons and bucket
+// ends, or the HBM path's block bounds.
 inline __host__ __device__ size_t init_wave_words(int T, int r_init)
 {
     const size_t nb = (size_t)(T + 63) / 64, nbs = (size_t)(T + INIT_SB - 1) / INIT_SB;
     const size_t side = 2 * (size_t)r_init + 1;
-    const size_t staged =
-        nbs <= INIT_NB_LDS ? init_block_words((int)nbs, (int)nb) + (size_t)INIT_ELDS / 2 + (nb + 2) / 2 : 0;
+    const size_t staged = nbs <= INIT_NB_LDS ? (nbs + 1) / 2 + (size_t)INIT_ELDS / 2 + (nb + 2) / 2 : 0;
     return side * side + (nb > staged ? nb : staged);
 }
 
-// Levels of the range-maximum table of an IRF of L samples.
-inline __host__ __device__ int q_levels(int L)
-{
-    int n = 1;
-    while ((1 << n) <= L) ++n;
-    return n;
-}
-
-// Ints of the staged weights (with their zero padding).
+// Ints of the staged weights (with their zero padding), and of the sliding
+// maximum table: M[x] = max q[x - INIT_SB + 1 .. x] (q = 0 outside [0, L)).
 inline __host__ __device__ size_t q_staged_ints(int L) { return (size_t)L + 2 * INIT_QPAD; }
-
-// Exact scores of block bb's 64 tau (one per lane): L(tau) = sum of
-// z q[t - tau + o] over the pooled photons in the window [wlo, whi] the block
-// can see (photons in claimed bins have had their count set to zero).  The
-// photons are bucketed by 64-bin block in LDS (bucket b ends at bend[b]); the
-// window's buckets are read 64 photons at a time and each photon is broadcast
-// from the lane that loaded it, four at a time so that their weight lookups
-// overlap.  Photons of those buckets outside the window add nothing: with QL
-// the staged weights carry INIT_QPAD zeros on either side (qt points at the
-// first weight), which covers every lag the window's buckets produce; lags
-// beyond, from bins >= T, are clamped onto the zeros.  Returns the lane's
-// (score, tau), or (-1, NO_TAU) where tau >= T or an accepted peak suppresses
-// it.
-template <bool QL>
-__device__ __forceinline__ void score_block(const uint32_t* E, const int* bend, int nb, int bb, const int* qt,
-                                            int L, int o, int T, const Peaks& pk, int wnms, long long& sv,
-                                            int& st)
-{
-    const int lane = threadIdx.x & 63;
-    const int tau = (bb << 6) + lane;
-    const int wlo = (bb << 6) - o, whi = (bb << 6) + 63 - o + L - 1;
-    long long sc = 0;
-    if (whi >= 0) {
-        const int b0 = max(0, wlo) >> 6, b1 = min(nb - 1, whi >> 6);
-        const int x0 = b0 > 0 ? bend[b0 - 1] : 0, x1 = bend[b1];
-        for (int c0 = x0; c0 < x1; c0 += 64) {
-            const int x = c0 + lane;
-            const int vv = x < x1 ? (int)E[x] : 0;
-            const int cnt = min(64, x1 - c0);
-            int k = 0;
-            for (; k + 4 <= cnt; k += 4) {
-                uint32_t v[4];
-                int q[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    v[u] = (uint32_t)__builtin_amdgcn_readlane(vv, k + u);
-                    const int lag = ent_bin(v[u]) - tau + o;
-                    if (QL) {
-                        q[u] = qt[min(max(lag, -INIT_QPAD), L + INIT_QPAD - 1)];
-                    } else {
-                        q[u] = (unsigned)lag < (unsigned)L ? qt[lag] : 0;
-                    }
-                }
-#pragma unroll
-                for (int u = 0; u < 4; ++u) sc += (long long)ent_cnt(v[u]) * (long long)q[u];
-            }
-            for (; k < cnt; ++k) {
-                const uint32_t v = (uint32_t)__builtin_amdgcn_readlane(vv, k);
-                const int lag = ent_bin(v) - tau + o;
-                int q;
-                if (QL) {
-                    q = qt[min(max(lag, -INIT_QPAD), L + INIT_QPAD - 1)];
-                } else {
-                    q = (unsigned)lag < (unsigned)L ? qt[lag] : 0;
-                }
-                sc += (long long)ent_cnt(v) * (long long)q;
-            }
-        }
-    }
-    const bool valid = tau < T && !pk.suppressed(tau, wnms);
-    sv = valid ? sc : -1;
-    st = valid ? tau : NO_TAU;
-}
+inline __host__ __device__ size_t q_window_ints(int L) { return (size_t)L + INIT_SB - 1; }
 
 // Whole-wavefront maximum / minimum on the VALU: DPP quad permutations, row
 // shifts by 4 and 8, then row broadcasts of lanes 15 and 31; lane 63 ends with
@@ -229,6 +162,24 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
 }
 
 template <int CTRL>
+__device__ __forceinline__ unsigned max_step_u32(unsigned v)
+{
+    const unsigned o = dpp_u32<CTRL>(v, 0u);
+    return o > v ? o : v;
+}
+
+__device__ __forceinline__ unsigned wave_max_u32(unsigned v)
+{
+    v = max_step_u32<0xB1>(v);
+    v = max_step_u32<0x4E>(v);
+    v = max_step_u32<0x114>(v);
+    v = max_step_u32<0x118>(v);
+    v = max_step_u32<0x142>(v);
+    v = max_step_u32<0x143>(v);
+    return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+template <int CTRL>
 __device__ __forceinline__ unsigned min_step_u32(unsigned v)
 {
     const unsigned o = dpp_u32<CTRL>(v, 0xffffffffu);
@@ -246,29 +197,207 @@ __device__ __forceinline__ unsigned wave_min_u32(unsigned v)
     return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
 }
 
-// Wavefront argmax of (score >= -1, tau): largest score, smallest tau on ties.
-__device__ __forceinline__ void wave_argmax(long long& sv, int& st)
+// Exact scores of block bb's 64 tau (one per lane): L(tau) = sum of
+// z q[t - tau + o] over the pooled photons in the window [wlo, whi] the block
+// can see (photons in claimed bins have had their count set to zero).  The
+// photons are bucketed by 64-bin block in LDS (bucket b ends at bend[b]); the
+// window's buckets are read 64 photons at a time and each photon is broadcast
+// from the lane that loaded it, four at a time so that their weight lookups
+// overlap.  qs holds the weights with INIT_QPAD zeros on either side; the
+// window's buckets hold bins within 126 of it (photons with bins >= T were
+// staged as zero counts at the last bucket's last bin), so every lag indexes
+// the padded table without a clamp.
+__device__ __forceinline__ uint32_t score_block(const uint32_t* E, const int* bend, int nb, int bb, const int* qs, int L,
+                                         int o)
 {
-    const unsigned long long key = (unsigned long long)(sv + 1);
-    const unsigned long long mx = wave_max_u64(key);
-    st = (int)wave_min_u32(key == mx ? (unsigned)st : 0xffffffffu);
-    sv = (long long)mx - 1;
+    const int lane = threadIdx.x & 63;
+    const int lo = INIT_QPAD + o - ((bb << 6) + lane);    // qs index of bin 0 for this lane's tau
+    const int wlo = (bb << 6) - o, whi = (bb << 6) + 63 - o + L - 1;
+    uint32_t sc = 0;
+    if (whi < 0) return sc;
+    const int b0 = max(0, wlo) >> 6, b1 = min(nb - 1, whi >> 6);
+    const int x0 = __builtin_amdgcn_readfirstlane(b0 > 0 ? bend[b0 - 1] : 0);
+    const int x1 = __builtin_amdgcn_readfirstlane(bend[b1]);
+    for (int c0 = x0; c0 < x1; c0 += 64) {
+        const int x = c0 + lane;
+        const int vv = x < x1 ? (int)E[x] : 0;
+        const int cnt = min(64, x1 - c0);
+        int k = 0;
+        for (; k + 4 <= cnt; k += 4) {
+            uint32_t v[4];
+            int q[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                v[u] = (uint32_t)__builtin_amdgcn_readlane(vv, k + u);
+                q[u] = qs[lo + ent_bin(v[u])];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) sc += __umul24((unsigned)ent_cnt(v[u]), (unsigned)q[u]);
+        }
+        for (; k < cnt; ++k) {
+            const uint32_t v = (uint32_t)__builtin_amdgcn_readlane(vv, k);
+            sc += __umul24((unsigned)ent_cnt(v), (unsigned)qs[lo + ent_bin(v)]);
+        }
+    }
+    return sc;
 }
 
-// Argmax of (score, tau) over aligned groups of `width` lanes (a power of
-// two <= 64): largest score, smallest tau on ties; every lane of a group ends
-// with the group's result.
-__device__ __forceinline__ void argmax_reduce(long long& sv, int& st, int width)
+// Branch-and-bound search of the LDS path for the pooled photons pe (entries
+// lane + 64 u < total; bucket cursors in bend hold each bucket's start).  The
+// caller has checked that ntot x the largest weight fits 32 bits and the
+// weights 24 bits: every bound and score is then an exact 32-bit sum of exact
+// 24-bit products.  On return pk holds the accepted peaks.
+__device__ __forceinline__ void lds_search(const DevModel& m, const DevParams& p, int T, int L, int o, int nb,
+                                           int nbs, const uint32_t (&pe)[INIT_EPL], int total, long long ntot,
+                                           const int* qs, const int* M, uint32_t* bnd, uint32_t* E, int* bend,
+                                           Peaks& pk)
 {
+    const int lane = threadIdx.x & 63;
+    // stage the photons bucketed by 64-bin block; bins >= T become zero
+    // counts at the last bucket's last bin.  Each photon raises the bound of
+    // every sub-block whose tau can see it by z x the largest weight over
+    // those lags (M, indexed by the lag of the sub-block's first tau).
 #pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) {
-        if (d >= width) continue;
-        const long long ov = __shfl_xor(sv, d, 64);
-        const int ot = __shfl_xor(st, d, 64);
-        if (ov > sv || (ov == sv && ot < st)) {
-            sv = ov;
-            st = ot;
+    for (int u = 0; u < INIT_EPL; ++u) {
+        if (lane + 64 * u >= total) break;
+        const uint32_t v = pe[u];
+        const int t = ent_bin(v), z = ent_cnt(v);
+        const int pos = atomicAdd(&bend[min(t >> 6, nb - 1)], 1);
+        E[pos] = t < T ? v : ((uint32_t)(64 * nb - 1) << 16);
+        if (t >= T) continue;
+        const int tlo = max(0, t + o - L + 1), thi = min(T - 1, t + o);
+        for (int b = tlo / INIT_SB; b <= thi / INIT_SB; ++b) atomicAdd(&bnd[b], __umul24((unsigned)z, (unsigned)M[t + o - INIT_SB * b]));
+    }
+    wave_sync();
+    // blocks lane and lane + 64: the largest sub-block bound and the first
+    // tau of the first sub-block holding it; the cached exact best
+    uint32_t bmx[2], bsc[2];
+    int bsub[2], btau[2];
+    bool cached[2], has[2];
+#pragma unroll
+    for (int s2 = 0; s2 < 2; ++s2) {
+        const int b = lane + 64 * s2;
+        uint32_t mx = 0;
+        int sub = NO_TAU;
+        if (b < nb) {
+#pragma unroll
+            for (int c = 0; c < 64 / INIT_SB; ++c) {
+                const int sb = b * (64 / INIT_SB) + c;
+                if (sb < nbs) {
+                    const uint32_t u = bnd[sb];
+                    if (sub == NO_TAU || u > mx) {
+                        mx = u;
+                        sub = sb * INIT_SB;
+                    }
+                }
+            }
         }
+        bmx[s2] = mx;
+        bsub[s2] = sub;
+        cached[s2] = b >= nb;     // blocks past the end are never picked
+        has[s2] = false;
+        bsc[s2] = 0;
+        btau[s2] = NO_TAU;
+    }
+    const double k2 = p.kappa * p.kappa;
+    for (int it = 0; it < p.k_init; ++it) {
+        // best over the blocks whose exact best is known
+        uint32_t best = 0;
+        int bestt = NO_TAU;
+        bool hb;
+        {
+            uint32_t key = 0;
+            int kt = NO_TAU;
+#pragma unroll
+            for (int s2 = 0; s2 < 2; ++s2)
+                if (cached[s2] && has[s2] && (bsc[s2] + 1 > key || (bsc[s2] + 1 == key && btau[s2] < kt))) {
+                    key = bsc[s2] + 1;
+                    kt = btau[s2];
+                }
+            const uint32_t mx = wave_max_u32(key);
+            hb = mx != 0;
+            if (hb) {
+                best = mx - 1;
+                bestt = (int)wave_min_u32(key == mx ? (unsigned)kt : 0xffffffffu);
+            }
+        }
+        while (true) {
+            // the unscored block with the largest bound (smallest index on ties)
+            uint32_t key = 0;
+#pragma unroll
+            for (int s2 = 0; s2 < 2; ++s2)
+                if (!cached[s2] && bmx[s2] + 1 > key) key = bmx[s2] + 1;
+            const uint32_t mx = wave_max_u32(key);
+            if (mx == 0) break;                                   // every block scored
+            unsigned cand = 0xffffffffu;
+#pragma unroll
+            for (int s2 = 1; s2 >= 0; --s2)
+                if (!cached[s2] && bmx[s2] + 1 == mx) cand = (unsigned)(lane + 64 * s2);
+            const int bb = (int)wave_min_u32(cand);
+            const uint32_t bu = mx - 1;
+            const int hi = bb >> 6;                               // wave-uniform
+            const int subt = __builtin_amdgcn_readlane(hi ? bsub[1] : bsub[0], bb & 63);
+            if (hb && (bu < best || (bu == best && subt > bestt))) break;
+            // exact scores of its 64 tau, and their best (tau rises with the lane)
+            const int tau = (bb << 6) + lane;
+            const uint32_t sc = score_block(E, bend, nb, bb, qs, L, o);
+            const bool valid = tau < T && !pk.suppressed(tau, m.wnms);
+            const uint32_t sk = valid ? sc + 1 : 0;
+            const uint32_t smx = wave_max_u32(sk);
+            int st = NO_TAU;
+            if (smx != 0) st = (bb << 6) + (int)__ffsll((long long)__ballot(sk == smx)) - 1;
+            if (lane == (bb & 63)) {
+                if (hi) {
+                    cached[1] = true;
+                    has[1] = smx != 0;
+                    bsc[1] = smx - 1;
+                    btau[1] = st;
+                } else {
+                    cached[0] = true;
+                    has[0] = smx != 0;
+                    bsc[0] = smx - 1;
+                    btau[0] = st;
+                }
+            }
+            if (smx != 0 && (!hb || smx - 1 > best || (smx - 1 == best && st < bestt))) {
+                best = smx - 1;
+                bestt = st;
+                hb = true;
+            }
+        }
+        if (!hb) break;                      // every tau suppressed
+        const int a = max(0, bestt - m.wl), c = min(T - 1, bestt + m.wr);
+        int win = 0;
+        for (int tb = a + lane; tb <= c; tb += 64) win += pk.owner(tb) < 0;
+        win = wave_sum(win);
+        long long nwin = 0;
+        const int b0 = a >> 6, b1 = min(nb - 1, c >> 6);
+        const int x0 = b0 > 0 ? bend[b0 - 1] : 0, x1 = bend[b1];
+        for (int x = x0 + lane; x < x1; x += 64) {
+            const uint32_t v = E[x];
+            const int tb = ent_bin(v);
+            if (tb >= a && tb <= c) nwin += ent_cnt(v);        // claimed photons count zero
+        }
+        nwin = wave_sum(nwin);
+        const double bw = (double)ntot * (double)win / (double)T;
+        const double d = (double)nwin - bw;
+        const bool accept = win > 0 && nwin >= p.n_min && d >= 0.0 && d * d >= k2 * bw;
+        if (!accept) break;
+        pk.push(bestt, a, c, win);
+        // the peak claims the photons of its window: their counts drop to zero
+        for (int x = x0 + lane; x < x1; x += 64) {
+            const int tb = ent_bin(E[x]);
+            if (tb >= a && tb <= c) E[x] &= 0xffff0000u;
+        }
+        // forget the bests of blocks the new peak changes
+        const int A0 = a + o - L + 1, A1 = c + o, S0 = bestt - m.wnms, S1 = bestt + m.wnms;
+#pragma unroll
+        for (int s2 = 0; s2 < 2; ++s2) {
+            const int b = lane + 64 * s2;
+            const int ta = b << 6, tb = (b << 6) + 63;
+            if (b < nb && ((ta <= A1 && tb >= A0) || (ta <= S1 && tb >= S0))) cached[s2] = false;
+        }
+        wave_sync();
     }
 }
 
@@ -284,44 +413,32 @@ __global__ __launch_bounds__(64 * INIT_WAVES) void k_init(DevModel m, DevParams 
     const int T = m.T, L = m.L, o = m.o;
     const int R = p.r_init, side = 2 * R + 1;
     const size_t ww = init_wave_words(T, R);
-    // IRF weights and their range-maximum table, staged by the whole
-    // workgroup before any wavefront leaves
-    // (layout: INIT_QPAD zeros, the L weights, INIT_QPAD zeros); the
-    // range-maximum table, read only for the bounds, stays in HBM
+    // IRF weights (INIT_QPAD zeros, the L weights, INIT_QPAD zeros) and their
+    // sliding maximum over INIT_SB lags, staged by the whole workgroup before
+    // any wavefront leaves; the range-maximum table of the HBM path stays in
+    // HBM
     int* qs = reinterpret_cast<int*>(smem64 + INIT_WAVES * ww);
+    int* M = qs + q_staged_ints(L);
     if (QL) {
         for (int k = threadIdx.x; k < L + 2 * INIT_QPAD; k += blockDim.x) {
             const int lag = k - INIT_QPAD;
             qs[k] = (lag >= 0 && lag < L) ? m.q[lag] : 0;
         }
+        __syncthreads();
+        for (int x = threadIdx.x; x < L + INIT_SB - 1; x += blockDim.x) {
+            int mx = 0;
+#pragma unroll
+            for (int d = 0; d < INIT_SB; ++d) mx = max(mx, qs[INIT_QPAD + x - d]);
+            M[x] = mx;
+        }
     }
     __syncthreads();
     const int* qt = QL ? qs + INIT_QPAD : m.q;
     const int* qstt = m.qst;
-    // With the weights in LDS and unimodal (rising to their first maximum
-    // qpk, falling after it), the largest weight over lags [lo, hi] is
-    // q[clamp(qpk, lo, hi)]; otherwise the range-maximum table answers.
-    int qpk = -1;
+    int qmax = 0;
     if (QL) {
-        const int lane0 = threadIdx.x & 63;
-        int qv = -1, qi = NO_TAU;
-        for (int k = lane0; k < L; k += 64)
-            if (qt[k] > qv) {
-                qv = qt[k];
-                qi = k;
-            }
-#pragma unroll
-        for (int d = 32; d >= 1; d >>= 1) {
-            const int ov = __shfl_xor(qv, d, 64), oi = __shfl_xor(qi, d, 64);
-            if (ov > qv || (ov == qv && oi < qi)) {
-                qv = ov;
-                qi = oi;
-            }
-        }
-        bool mono = true;
-        for (int k = lane0; k + 1 < L; k += 64)
-            if (k < qi ? qt[k] > qt[k + 1] : qt[k] < qt[k + 1]) mono = false;
-        qpk = __ballot(!mono) == 0ull ? qi : -1;
+        for (int k = lane; k < L; k += 64) qmax = max(qmax, qt[k]);
+        qmax = (int)wave_max_u32((unsigned)qmax);
     }
 
     const long long P = sh.P;
@@ -350,72 +467,72 @@ __global__ __launch_bounds__(64 * INIT_WAVES) void k_init(DevModel m, DevParams 
     const long long fr = pix / per_frame;
     const int i = (int)((pix / sh.cols) % sh.rows), j = (int)(pix % sh.cols);
 
-    // pooled photon lists: the CSR ranges of the window's pixels
-    int npl = 0, total = 0;
-    for (int i2 = i - R; i2 <= i + R; ++i2) {
-        if (i2 < 0 || i2 >= sh.rows) continue;
-        for (int j2 = j - R; j2 <= j + R; ++j2) {
-            if (j2 < 0 || j2 >= sh.cols) continue;
-            const long long pp = (fr * sh.rows + i2) * sh.cols + j2;
-            const uint32_t e0 = off[pp], e1 = off[pp + 1];
-            if (lane == 0) lists[npl] = make_uint2(e0, e1);
-            total += (int)(e1 - e0);
-            ++npl;
+    // pooled photons: lane r < side holds the CSR range of window row i - R + r
+    // (the row's pixels are consecutive, so their photons are one range)
+    uint32_t rs = 0, re = 0;
+    {
+        const int i2 = i - R + lane;
+        if (lane < side && i2 >= 0 && i2 < sh.rows) {
+            const long long base = (fr * sh.rows + i2) * sh.cols;
+            rs = off[base + max(0, j - R)];
+            re = off[base + min(sh.cols - 1, j + R) + 1];
         }
     }
-    wave_sync();
+    const uint32_t rlen = re - rs;
+    const uint32_t rend = wave_incl_scan(rlen);                 // pooled index just past row lane
+    const int total = (int)__builtin_amdgcn_readlane((int)rend, 63);
 
     Peaks pk;
     pk.n = 0;
 #pragma unroll
     for (int j = 0; j < KM; ++j) pk.t[j] = pk.a[j] = pk.c[j] = pk.w[j] = 0;
-    const double k2 = p.kappa * p.kappa;
-    long long ntot = 0;
 
+    // Branch and bound from LDS when the pool fits, the weights are staged,
+    // and every score fits 32 bits (checked once the photons are read).
     const int nbs = (T + INIT_SB - 1) / INIT_SB;
-    if (total <= INIT_ELDS && nbs <= INIT_NB_LDS) {
-        // Branch and bound from LDS.  Stage the pooled photons bucketed by
-        // 64-bin block; keep a score bound per sub-block of INIT_SB tau
-        // (photons x the largest weight over the lags the sub-block sees) and
-        // the exact best of every 64-tau block scored so far.  The unscored
-        // block holding the sub-block with the largest bound is scored next
-        // (one tau per lane).  After an accepted peak only the blocks whose tau
-        // can see its claimed bins or fall under its suppression lose their
-        // best.
-        unsigned long long* bnd = ub;                                   // [nbs] sub-block bounds
-        long long* bsc = reinterpret_cast<long long*>(ub + nbs);        // [nb] cached block best, -2 = none
-        int* btau = reinterpret_cast<int*>(ub + nbs + nb);              // [nb] cached block best tau
-        uint32_t* E = reinterpret_cast<uint32_t*>(ub + init_block_words(nbs, nb));   // [total] bucketed photons
-        int* bend = reinterpret_cast<int*>(E + INIT_ELDS);               // [nb] bucket ends
-        for (int b = lane; b < nbs; b += 64) bnd[b] = 0ull;
-        for (int b = lane; b < nb; b += 64) {
-            bsc[b] = -2;
-            btau[b] = NO_TAU;
-            bend[b] = 0;
-        }
-        wave_sync();
-        // photons per 64-bin bucket, photon total and the score bounds
-        for (int l = 0; l < npl; ++l) {
-            const uint2 rg = lists[l];
-            for (uint32_t e = rg.x + lane; e < rg.y; e += 64) {
-                const uint32_t v = ent[e];
-                const int t = ent_bin(v), z = ent_cnt(v);
-                atomicAdd(&bend[min(t >> 6, nb - 1)], 1);
-                if (t >= T) continue;
-                ntot += z;
-                const int tlo = max(0, t + o - L + 1), thi = min(T - 1, t + o);
-                for (int b = tlo / INIT_SB; b <= thi / INIT_SB; ++b) {
-                    const int a0 = max(tlo, b * INIT_SB), a1 = min(thi, b * INIT_SB + INIT_SB - 1);
-                    const int lo = t - a1 + o, hi = t - a0 + o;
-                    const int qm = qpk >= 0 ? qt[min(max(qpk, lo), hi)] : q_range_max(qstt, L, lo, hi);
-                    atomicAdd(&bnd[b], (unsigned long long)z * (unsigned long long)qm);
-                }
+    bool lds = QL && total <= INIT_ELDS && nbs <= INIT_NB_LDS && qmax < (1 << 24);
+    uint32_t pe[INIT_EPL];
+    long long ntot = 0;
+    if (lds) {
+        // read the pooled photons once: entry k of the pool is lane k % 64's
+        // pe[k / 64]
+        uint32_t src[INIT_EPL];
+#pragma unroll
+        for (int u = 0; u < INIT_EPL; ++u) src[u] = 0;
+        for (int r = 0; r < side; ++r) {
+            const uint32_t r0 = (uint32_t)__builtin_amdgcn_readlane((int)(rend - rlen), r);
+            const uint32_t rb = (uint32_t)__builtin_amdgcn_readlane((int)rs, r);
+#pragma unroll
+            for (int u = 0; u < INIT_EPL; ++u) {
+                const uint32_t k = (uint32_t)(lane + 64 * u);
+                if (k >= r0) src[u] = rb + (k - r0);
             }
         }
+#pragma unroll
+        for (int u = 0; u < INIT_EPL; ++u) pe[u] = lane + 64 * u < total ? ent[src[u]] : 0u;
+#pragma unroll
+        for (int u = 0; u < INIT_EPL; ++u)
+            if (lane + 64 * u < total && ent_bin(pe[u]) < T) ntot += ent_cnt(pe[u]);
         ntot = wave_sum(ntot);
+        lds = (unsigned long long)ntot * (unsigned long long)qmax <= 0xfffffffeull;
+    }
+    if (lds) {
+        // Count the photons per 64-bin bucket, scan the counts into bucket
+        // starts, then stage, bound and search them.
+        uint32_t* bnd = reinterpret_cast<uint32_t*>(ub);                 // [nbs] sub-block bounds
+        uint32_t* E = reinterpret_cast<uint32_t*>(ub + (nbs + 1) / 2);   // [INIT_ELDS] bucketed photons
+        int* bend = reinterpret_cast<int*>(E + INIT_ELDS);              // [nb] bucket ends
+        for (int b = lane; b < nbs; b += 64) bnd[b] = 0u;
+        for (int b = lane; b < nb; b += 64) bend[b] = 0;
         wave_sync();
-        // bucket starts (exclusive prefix of the counts), then scatter; each
-        // bucket's cursor ends at the bucket's end
+#pragma unroll
+        for (int u = 0; u < INIT_EPL; ++u) {
+            if (lane + 64 * u >= total) break;
+            atomicAdd(&bend[min(ent_bin(pe[u]) >> 6, nb - 1)], 1);
+        }
+        wave_sync();
+        // bucket starts (exclusive prefix of the counts); each bucket's cursor
+        // ends at the bucket's end once the photons are staged
         int carry = 0;
         for (int c0 = 0; c0 < nb; c0 += 64) {
             const int b = c0 + lane;
@@ -425,108 +542,22 @@ __global__ __launch_bounds__(64 * INIT_WAVES) void k_init(DevModel m, DevParams 
             carry += __shfl(inc, 63, 64);
         }
         wave_sync();
-        for (int l = 0; l < npl; ++l) {
-            const uint2 rg = lists[l];
-            for (uint32_t e = rg.x + lane; e < rg.y; e += 64) {
-                const uint32_t v = ent[e];
-                const int pos = atomicAdd(&bend[min(ent_bin(v) >> 6, nb - 1)], 1);
-                E[pos] = v;
+        lds_search(m, p, T, L, o, nb, nbs, pe, total, ntot, qs, M, bnd, E, bend, pk);
+    } else {
+        // the window's pixels' photon lists (each ascending in t)
+        const int npl = side * side;
+        for (int w = lane; w < npl; w += 64) {
+            const int i2 = i - R + w / side, j2 = j - R + w % side;
+            uint2 rg = make_uint2(0u, 0u);
+            if (i2 >= 0 && i2 < sh.rows && j2 >= 0 && j2 < sh.cols) {
+                const long long pp = (fr * sh.rows + i2) * sh.cols + j2;
+                rg = make_uint2(off[pp], off[pp + 1]);
             }
+            lists[w] = rg;
         }
         wave_sync();
-        for (int it = 0; it < p.k_init; ++it) {
-            // best over the blocks whose exact best is known
-            long long best = -1;
-            int bestt = NO_TAU;
-            for (int b = lane; b < nb; b += 64) {
-                const long long v = bsc[b];
-                const int t = btau[b];
-                if (v > best || (v == best && t < bestt)) {
-                    best = v;
-                    bestt = t;
-                }
-            }
-            wave_argmax(best, bestt);
-            while (true) {
-                // sub-block of an unscored block with the largest bound (smallest index on ties)
-                unsigned long long bu = 0;
-                int bb = NO_TAU;
-                for (int b = lane; b < nbs; b += 64) {
-                    if (bsc[b * INIT_SB / 64] != -2) continue;
-                    const unsigned long long u = bnd[b];
-                    if (bb == NO_TAU || u > bu) {
-                        bu = u;
-                        bb = b;
-                    }
-                }
-                {
-                    const unsigned long long key = bb == NO_TAU ? 0ull : bu + 1;
-                    const unsigned long long mx = wave_max_u64(key);
-                    if (mx == 0ull) break;                           // every block scored
-                    bb = (int)wave_min_u32(key == mx ? (unsigned)bb : 0xffffffffu);
-                    bu = mx - 1;
-                }
-                if ((long long)bu < best || ((long long)bu == best && bb * INIT_SB > bestt)) break;
-                long long sv;
-                int st;
-                const int span = bb * INIT_SB / 64;
-                score_block<QL>(E, bend, nb, span, qt, L, o, T, pk, m.wnms, sv, st);
-                {
-                    // best of the block's 64 tau (tau rises with the lane)
-                    const unsigned long long key = (unsigned long long)(sv + 1);
-                    const unsigned long long mx = wave_max_u64(key);
-                    st = __builtin_amdgcn_readlane(st, (int)__ffsll((long long)__ballot(key == mx)) - 1);
-                    sv = (long long)mx - 1;
-                }
-                if (lane == 0) {
-                    bsc[span] = sv;
-                    btau[span] = st;
-                }
-                wave_sync();
-                if (st != NO_TAU && (sv > best || (sv == best && st < bestt))) {
-                    best = sv;
-                    bestt = st;
-                }
-            }
-            if (bestt == NO_TAU) break;          // every tau suppressed
-            const int a = max(0, bestt - m.wl), c = min(T - 1, bestt + m.wr);
-            int win = 0;
-            for (int tb = a + lane; tb <= c; tb += 64) win += pk.owner(tb) < 0;
-            win = wave_sum(win);
-            long long nwin = 0;
-            {
-                const int b0 = a >> 6, b1 = min(nb - 1, c >> 6);
-                const int x1 = bend[b1];
-                for (int x = (b0 > 0 ? bend[b0 - 1] : 0) + lane; x < x1; x += 64) {
-                    const uint32_t v = E[x];
-                    const int tb = ent_bin(v);
-                    if (tb >= a && tb <= c) nwin += ent_cnt(v);     // claimed photons count zero
-                }
-            }
-            nwin = wave_sum(nwin);
-            const double bw = (double)ntot * (double)win / (double)T;
-            const double d = (double)nwin - bw;
-            const bool accept = win > 0 && nwin >= p.n_min && d >= 0.0 && d * d >= k2 * bw;
-            if (!accept) break;
-            pk.push(bestt, a, c, win);
-            // the peak claims the photons of its window: their counts drop to zero
-            {
-                const int b0 = a >> 6, b1 = min(nb - 1, c >> 6);
-                const int x1 = bend[b1];
-                for (int x = (b0 > 0 ? bend[b0 - 1] : 0) + lane; x < x1; x += 64) {
-                    const int tb = ent_bin(E[x]);
-                    if (tb >= a && tb <= c) E[x] &= 0xffff0000u;
-                }
-            }
-            // forget the bests of blocks the new peak changes
-            const int A0 = a + o - L + 1, A1 = c + o, S0 = bestt - m.wnms, S1 = bestt + m.wnms;
-            for (int b = lane; b < nb; b += 64) {
-                const int ta = b << 6, tb = (b << 6) + 63;
-                if ((ta <= A1 && tb >= A0) || (ta <= S1 && tb >= S0)) bsc[b] = -2;
-            }
-            wave_sync();
-        }
-    } else {
+        ntot = 0;
+        const double k2 = p.kappa * p.kappa;
         // Branch and bound over blocks of 64 tau, reading the photons from HBM.
         for (int b = lane; b < nb; b += 64) ub[b] = 0ull;
         wave_sync();
@@ -784,7 +815,7 @@ __global__ __launch_bounds__(256) void k_init_normals(DevParams p, Shape sh, Dev
 size_t init_lds_bytes(int T, int L, int r_init)
 {
     const size_t nq = q_staged_ints(L);
-    const size_t qwords = nq <= INIT_QLDS ? (nq + 1) / 2 : 0;
+    const size_t qwords = nq <= INIT_QLDS ? (nq + q_window_ints(L) + 1) / 2 : 0;
     return (INIT_WAVES * init_wave_words(T, r_init) + qwords) * sizeof(unsigned long long);
 }
 

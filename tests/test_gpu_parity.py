@@ -44,6 +44,16 @@ def _scene(name):
         sc = synth.head_scene(7, rows=37, cols=23, T=777, signal=8.0, sbr=0.5)
         sc.meta.update(r_init=3, dz=0.07)
         return sc
+    if name == "bright":
+        # the top ten rows' counts scaled by 400: pools there hold photon totals
+        # whose product with the largest filter weight passes 2^32 (the 64-bit
+        # search), the rest stay within it (the 32-bit one), and pixels on the
+        # seam pool both
+        sc = synth.head_scene(3, rows=24, cols=19, T=777, signal=8.0, sbr=0.5)
+        assert int(sc.Z.max()) * 400 < 65535
+        sc.Z[:10] = sc.Z[:10] * np.uint16(400)
+        sc.meta.update(r_init=1, dz=0.07)
+        return sc
     raise KeyError(name)
 
 
@@ -98,7 +108,7 @@ def test_compaction_edge_cases():
 
 # ------------------------------------------------------------------ init
 
-@pytest.mark.parametrize("name", ["c1", "c2", "ragged", "ragged_r3"])
+@pytest.mark.parametrize("name", ["c1", "c2", "ragged", "ragged_r3", "bright"])
 def test_init_matches_oracle(name):
     sc = scene(name)
     O, ctx = pair(sc)
