@@ -151,7 +151,7 @@ __global__ __launch_bounds__(64 * CP_WAVES) void k_compact_count(const uint16_t*
 #pragma unroll
         for (int k = 0; k < 8; ++k) c += z[k] != 0;
     }
-    c = wave_sum(c);
+    c = wave_sum_u32(c);
     if (lane == 0) counts[p] = c;
 }
 
@@ -179,7 +179,7 @@ __global__ __launch_bounds__(64 * CP_WAVES) void k_compact_fill(const uint16_t* 
 #pragma unroll
         for (int k = 0; k < 8; ++k) c += z[k] != 0;
         uint32_t inc = wave_incl_scan(c);
-        uint32_t tot = __shfl(inc, 63, 64);
+        uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
         uint64_t pos = run + (inc - c);
 #pragma unroll
         for (int k = 0; k < 8; ++k) {

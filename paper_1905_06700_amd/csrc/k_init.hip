@@ -104,6 +104,7 @@ constexpr int INIT_ELDS = 640;    // pooled entries a wavefront scores from LDS;
 constexpr int INIT_EPL = INIT_ELDS / 64;   // pooled entries per lane
 constexpr int INIT_QLDS = 4096;   // IRF weight tables (ints) up to this size are staged in LDS
 constexpr int INIT_QPAD = 128;    // zero weights on either side of the staged IRF weights
+constexpr int INIT_BWS = 5;       // the LDS path buckets photons by 2^INIT_BWS bins
 constexpr int NO_TAU = 0x7fffffff;
 
 // Width (tau) of the sub-blocks the LDS path bounds, and the number of
@@ -120,7 +121,8 @@ inline __host__ __device__ size_t init_wave_words(int T, int r_init)
 {
     const size_t nb = (size_t)(T + 63) / 64, nbs = (size_t)(T + INIT_SB - 1) / INIT_SB;
     const size_t side = 2 * (size_t)r_init + 1;
-    const size_t staged = nbs <= INIT_NB_LDS ? (nbs + 1) / 2 + (size_t)INIT_ELDS / 2 + (nb + 2) / 2 : 0;
+    const size_t nk = ((size_t)T + (1u << INIT_BWS) - 1) >> INIT_BWS;
+    const size_t staged = nbs <= INIT_NB_LDS ? (nbs + 1) / 2 + (size_t)INIT_ELDS / 2 + (nk + 2) / 2 : 0;
     return side * side + (nb > staged ? nb : staged);
 }
 
@@ -197,25 +199,34 @@ __device__ __forceinline__ unsigned wave_min_u32(unsigned v)
     return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
 }
 
+// acc + z q on the VALU as one 24-bit multiply-add, z from a scalar register
+// (exact for z, q < 2^24 and a result below 2^32).
+__device__ __forceinline__ uint32_t mad_u24(uint32_t z, uint32_t q, uint32_t acc)
+{
+    asm("v_mad_u32_u24 %0, %1, %2, %0" : "+v"(acc) : "s"(z), "v"(q));
+    return acc;
+}
+
 // Exact scores of block bb's 64 tau (one per lane): L(tau) = sum of
 // z q[t - tau + o] over the pooled photons in the window [wlo, whi] the block
 // can see (photons in claimed bins have had their count set to zero).  The
-// photons are bucketed by 64-bin block in LDS (bucket b ends at bend[b]); the
-// window's buckets are read 64 photons at a time and each photon is broadcast
-// from the lane that loaded it, four at a time so that their weight lookups
-// overlap.  qs holds the weights with INIT_QPAD zeros on either side; the
-// window's buckets hold bins within 126 of it (photons with bins >= T were
-// staged as zero counts at the last bucket's last bin), so every lag indexes
-// the padded table without a clamp.
-__device__ __forceinline__ uint32_t score_block(const uint32_t* E, const int* bend, int nb, int bb, const int* qs, int L,
-                                         int o)
+// photons are bucketed by 2^INIT_BWS bins in LDS (bucket b ends at bend[b],
+// nk buckets); the window's buckets are read 64 photons at a time and each
+// photon is broadcast from the lane that loaded it, four at a time so that
+// their weight lookups overlap.  qs holds the weights with INIT_QPAD zeros on
+// either side; the window's buckets hold bins within 2^INIT_BWS - 1 of it
+// (photons with bins >= T were staged as zero counts at the last bucket's
+// last bin), so every lag lies in [-63 - 31, L + 62 + 31] and indexes the
+// padded table without a clamp.
+__device__ __forceinline__ uint32_t score_block(const uint32_t* E, const int* bend, int nk, int bb, const int* qs,
+                                                int L, int o)
 {
     const int lane = threadIdx.x & 63;
     const int lo = INIT_QPAD + o - ((bb << 6) + lane);    // qs index of bin 0 for this lane's tau
     const int wlo = (bb << 6) - o, whi = (bb << 6) + 63 - o + L - 1;
     uint32_t sc = 0;
     if (whi < 0) return sc;
-    const int b0 = max(0, wlo) >> 6, b1 = min(nb - 1, whi >> 6);
+    const int b0 = max(0, wlo) >> INIT_BWS, b1 = min(nk - 1, whi >> INIT_BWS);
     const int x0 = __builtin_amdgcn_readfirstlane(b0 > 0 ? bend[b0 - 1] : 0);
     const int x1 = __builtin_amdgcn_readfirstlane(bend[b1]);
     for (int c0 = x0; c0 < x1; c0 += 64) {
@@ -232,11 +243,11 @@ __device__ __forceinline__ uint32_t score_block(const uint32_t* E, const int* be
                 q[u] = qs[lo + ent_bin(v[u])];
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) sc += __umul24((unsigned)ent_cnt(v[u]), (unsigned)q[u]);
+            for (int u = 0; u < 4; ++u) sc = mad_u24((uint32_t)ent_cnt(v[u]), (uint32_t)q[u], sc);
         }
         for (; k < cnt; ++k) {
             const uint32_t v = (uint32_t)__builtin_amdgcn_readlane(vv, k);
-            sc += __umul24((unsigned)ent_cnt(v), (unsigned)qs[lo + ent_bin(v)]);
+            sc = mad_u24((uint32_t)ent_cnt(v), (uint32_t)qs[lo + ent_bin(v)], sc);
         }
     }
     return sc;
@@ -248,25 +259,33 @@ __device__ __forceinline__ uint32_t score_block(const uint32_t* E, const int* be
 // weights 24 bits: every bound and score is then an exact 32-bit sum of exact
 // 24-bit products.  On return pk holds the accepted peaks.
 __device__ __forceinline__ void lds_search(const DevModel& m, const DevParams& p, int T, int L, int o, int nb,
-                                           int nbs, const uint32_t (&pe)[INIT_EPL], int total, long long ntot,
+                                           int nbs, int nk, const uint32_t (&pe)[INIT_EPL], int total, long long ntot,
                                            const int* qs, const int* M, uint32_t* bnd, uint32_t* E, int* bend,
                                            Peaks& pk)
 {
     const int lane = threadIdx.x & 63;
-    // stage the photons bucketed by 64-bin block; bins >= T become zero
-    // counts at the last bucket's last bin.  Each photon raises the bound of
-    // every sub-block whose tau can see it by z x the largest weight over
-    // those lags (M, indexed by the lag of the sub-block's first tau).
+    // stage the photons bucketed by 2^INIT_BWS bins; bins >= T become zero
+    // counts at the last bucket's last bin
 #pragma unroll
     for (int u = 0; u < INIT_EPL; ++u) {
         if (lane + 64 * u >= total) break;
         const uint32_t v = pe[u];
-        const int t = ent_bin(v), z = ent_cnt(v);
-        const int pos = atomicAdd(&bend[min(t >> 6, nb - 1)], 1);
-        E[pos] = t < T ? v : ((uint32_t)(64 * nb - 1) << 16);
+        const int t = ent_bin(v);
+        const int pos = atomicAdd(&bend[min(t >> INIT_BWS, nk - 1)], 1);
+        E[pos] = t < T ? v : ((uint32_t)((nk << INIT_BWS) - 1) << 16);
+    }
+    // each photon raises the bound of every sub-block whose tau can see it by
+    // z x the largest weight over those lags (M, indexed by the lag of the
+    // sub-block's first tau, which falls by INIT_SB per sub-block)
+#pragma unroll
+    for (int u = 0; u < INIT_EPL; ++u) {
+        if (lane + 64 * u >= total) break;
+        const int t = ent_bin(pe[u]), z = ent_cnt(pe[u]);
         if (t >= T) continue;
-        const int tlo = max(0, t + o - L + 1), thi = min(T - 1, t + o);
-        for (int b = tlo / INIT_SB; b <= thi / INIT_SB; ++b) atomicAdd(&bnd[b], __umul24((unsigned)z, (unsigned)M[t + o - INIT_SB * b]));
+        const int blo = max(0, t + o - L + 1) / INIT_SB, bhi = min(T - 1, t + o) / INIT_SB;
+        const int* Mx = M + (t + o - INIT_SB * bhi);
+#pragma unroll 2
+        for (int b = bhi; b >= blo; --b, Mx += INIT_SB) atomicAdd(&bnd[b], __umul24((unsigned)z, (unsigned)*Mx));
     }
     wave_sync();
     // blocks lane and lane + 64: the largest sub-block bound and the first
@@ -340,7 +359,7 @@ __device__ __forceinline__ void lds_search(const DevModel& m, const DevParams& p
             if (hb && (bu < best || (bu == best && subt > bestt))) break;
             // exact scores of its 64 tau, and their best (tau rises with the lane)
             const int tau = (bb << 6) + lane;
-            const uint32_t sc = score_block(E, bend, nb, bb, qs, L, o);
+            const uint32_t sc = score_block(E, bend, nk, bb, qs, L, o);
             const bool valid = tau < T && !pk.suppressed(tau, m.wnms);
             const uint32_t sk = valid ? sc + 1 : 0;
             const uint32_t smx = wave_max_u32(sk);
@@ -367,23 +386,23 @@ __device__ __forceinline__ void lds_search(const DevModel& m, const DevParams& p
         }
         if (!hb) break;                      // every tau suppressed
         const int a = max(0, bestt - m.wl), c = min(T - 1, bestt + m.wr);
-        int win = 0;
+        uint32_t win = 0;
         for (int tb = a + lane; tb <= c; tb += 64) win += pk.owner(tb) < 0;
-        win = wave_sum(win);
-        long long nwin = 0;
-        const int b0 = a >> 6, b1 = min(nb - 1, c >> 6);
+        win = wave_sum_u32(win);
+        uint32_t nwin = 0;                                      // at most ntot
+        const int b0 = a >> INIT_BWS, b1 = min(nk - 1, c >> INIT_BWS);
         const int x0 = b0 > 0 ? bend[b0 - 1] : 0, x1 = bend[b1];
         for (int x = x0 + lane; x < x1; x += 64) {
             const uint32_t v = E[x];
             const int tb = ent_bin(v);
             if (tb >= a && tb <= c) nwin += ent_cnt(v);        // claimed photons count zero
         }
-        nwin = wave_sum(nwin);
+        nwin = wave_sum_u32(nwin);
         const double bw = (double)ntot * (double)win / (double)T;
         const double d = (double)nwin - bw;
-        const bool accept = win > 0 && nwin >= p.n_min && d >= 0.0 && d * d >= k2 * bw;
+        const bool accept = win > 0 && (long long)nwin >= p.n_min && d >= 0.0 && d * d >= k2 * bw;
         if (!accept) break;
-        pk.push(bestt, a, c, win);
+        pk.push(bestt, a, c, (int)win);
         // the peak claims the photons of its window: their counts drop to zero
         for (int x = x0 + lane; x < x1; x += 64) {
             const int tb = ent_bin(E[x]);
@@ -455,14 +474,6 @@ __global__ __launch_bounds__(64 * INIT_WAVES) void k_init(DevModel m, DevParams 
         s.n[(1 * KM + lane) * P + pix] = 0.f;
         s.n[(2 * KM + lane) * P + pix] = -1.f;
     }
-    const float G = gain ? gain[pix] : 1.f;
-    if (!(G > 0.f)) {
-        if (lane == 0) {
-            s.cnt[pix] = 0;
-            s.b[pix] = (float)p.b_min;
-        }
-        return;
-    }
     const int per_frame = sh.rows * sh.cols;
     const long long fr = pix / per_frame;
     const int i = (int)((pix / sh.cols) % sh.rows), j = (int)(pix % sh.cols);
@@ -477,6 +488,14 @@ __global__ __launch_bounds__(64 * INIT_WAVES) void k_init(DevModel m, DevParams 
             rs = off[base + max(0, j - R)];
             re = off[base + min(sh.cols - 1, j + R) + 1];
         }
+    }
+    const float G = gain ? gain[pix] : 1.f;
+    if (!(G > 0.f)) {
+        if (lane == 0) {
+            s.cnt[pix] = 0;
+            s.b[pix] = (float)p.b_min;
+        }
+        return;
     }
     const uint32_t rlen = re - rs;
     const uint32_t rend = wave_incl_scan(rlen);                 // pooled index just past row lane
@@ -510,39 +529,41 @@ __global__ __launch_bounds__(64 * INIT_WAVES) void k_init(DevModel m, DevParams 
         }
 #pragma unroll
         for (int u = 0; u < INIT_EPL; ++u) pe[u] = lane + 64 * u < total ? ent[src[u]] : 0u;
+        uint32_t nt = 0;                        // at most INIT_ELDS x 65535
 #pragma unroll
         for (int u = 0; u < INIT_EPL; ++u)
-            if (lane + 64 * u < total && ent_bin(pe[u]) < T) ntot += ent_cnt(pe[u]);
-        ntot = wave_sum(ntot);
+            if (lane + 64 * u < total && ent_bin(pe[u]) < T) nt += ent_cnt(pe[u]);
+        ntot = wave_sum_u32(nt);
         lds = (unsigned long long)ntot * (unsigned long long)qmax <= 0xfffffffeull;
     }
     if (lds) {
         // Count the photons per 64-bin bucket, scan the counts into bucket
         // starts, then stage, bound and search them.
+        const int nk = (T + (1 << INIT_BWS) - 1) >> INIT_BWS;
         uint32_t* bnd = reinterpret_cast<uint32_t*>(ub);                 // [nbs] sub-block bounds
         uint32_t* E = reinterpret_cast<uint32_t*>(ub + (nbs + 1) / 2);   // [INIT_ELDS] bucketed photons
-        int* bend = reinterpret_cast<int*>(E + INIT_ELDS);              // [nb] bucket ends
+        int* bend = reinterpret_cast<int*>(E + INIT_ELDS);              // [nk] bucket ends
         for (int b = lane; b < nbs; b += 64) bnd[b] = 0u;
-        for (int b = lane; b < nb; b += 64) bend[b] = 0;
+        for (int b = lane; b < nk; b += 64) bend[b] = 0;
         wave_sync();
 #pragma unroll
         for (int u = 0; u < INIT_EPL; ++u) {
             if (lane + 64 * u >= total) break;
-            atomicAdd(&bend[min(ent_bin(pe[u]) >> 6, nb - 1)], 1);
+            atomicAdd(&bend[min(ent_bin(pe[u]) >> INIT_BWS, nk - 1)], 1);
         }
         wave_sync();
         // bucket starts (exclusive prefix of the counts); each bucket's cursor
         // ends at the bucket's end once the photons are staged
-        int carry = 0;
-        for (int c0 = 0; c0 < nb; c0 += 64) {
+        uint32_t carry = 0;
+        for (int c0 = 0; c0 < nk; c0 += 64) {
             const int b = c0 + lane;
-            const int cnt = b < nb ? bend[b] : 0;
-            const int inc = (int)wave_incl_scan((uint32_t)cnt);
-            if (b < nb) bend[b] = carry + inc - cnt;
-            carry += __shfl(inc, 63, 64);
+            const uint32_t cnt = b < nk ? (uint32_t)bend[b] : 0u;
+            const uint32_t inc = wave_incl_scan(cnt);
+            if (b < nk) bend[b] = (int)(carry + inc - cnt);
+            carry += (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
         }
         wave_sync();
-        lds_search(m, p, T, L, o, nb, nbs, pe, total, ntot, qs, M, bnd, E, bend, pk);
+        lds_search(m, p, T, L, o, nb, nbs, nk, pe, total, ntot, qs, M, bnd, E, bend, pk);
     } else {
         // the window's pixels' photon lists (each ascending in t)
         const int npl = side * side;

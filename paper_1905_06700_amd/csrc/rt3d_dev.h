@@ -178,15 +178,34 @@ __device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nblocks)
     return x * q + (x < r ? x : r) + b / 8;
 }
 
-// Inclusive prefix sum over the 64 lanes.
+// Value of another lane by a DPP move, or 0 where the move has no source lane
+// or the lane's row is outside ROW_MASK.  Every lane must be active.
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ uint32_t dpp_or_zero(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xF, false);
+}
+
+// Inclusive prefix sum over the 64 lanes on the VALU: shifts by 1, 2, 4 and 8
+// lanes inside each row of 16, then row 0's total into row 1 and row 2's into
+// row 3 (broadcast of lane 15), then lane 31's prefix into rows 2 and 3.
+// Every lane must be active.
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
 {
-    const int l = lane_id();
+    v += dpp_or_zero<0x111>(v);
+    v += dpp_or_zero<0x112>(v);
+    v += dpp_or_zero<0x114>(v);
+    v += dpp_or_zero<0x118>(v);
+    v += dpp_or_zero<0x142, 0xA>(v);
+    v += dpp_or_zero<0x143, 0xC>(v);
+    return v;
+}
+
+// Sum over the 64 lanes (every lane gets it), by a butterfly of lane swaps.
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
+{
 #pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        uint32_t o = __shfl_up(v, d, 64);
-        if (l >= d) v += o;
-    }
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
     return v;
 }
 
