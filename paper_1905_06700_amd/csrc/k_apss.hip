@@ -14,10 +14,14 @@
 // (clipped to [-h, h]); its normal becomes grad s there, facing the sensor.
 // Jacobi: every query reads the state before the step.
 //
-// Mapping: eight lanes per pixel split the (2R+1)^2 pixel window around it;
-// each accumulates the sphere moments of its share in FP32, in coordinates
-// local to the query (positions formed in FP64), and the eight partial
-// moment sets meet in a fixed wavefront-shuffle tree.
+// Mapping: a workgroup takes a tile of ATY x ATX pixels of one frame; it stages the
+// tile's point state with an R-pixel halo in LDS (depths in FP64, normals,
+// counts), then one thread per pixel fits and projects the pixel's points,
+// accumulating the sphere moments over the (2R+1)^2 window from LDS in FP32,
+// in coordinates local to the query (depth differences formed in FP64).
+// Windows whose staged tile does not fit in 64 KB of LDS take a variant with
+// eight lanes per pixel reading the state from global memory, the partial
+// moment sets meeting in a fixed wavefront-shuffle tree.
 #include "rt3d_dev.h"
 
 namespace rt3d {
@@ -55,6 +59,108 @@ __device__ __forceinline__ void apss_project(bool ok, float W, float Px, float P
         n[0] = gx * inv;
         n[1] = gy * inv;
         n[2] = gz * inv;
+    }
+}
+
+constexpr int ATX = 16, ATY = 16;   // tile of the LDS variant: columns, rows
+
+// LDS bytes of a staged tile with an R-pixel halo: per pixel KM depths (FP64),
+// 3 x KM normal components and the count.
+inline size_t apss_tile_bytes(int R)
+{
+    const size_t SX = ATX + 2 * (size_t)R, SY = ATY + 2 * (size_t)R;
+    return SX * SY * (KM * sizeof(double) + 3 * KM * sizeof(float) + sizeof(int));
+}
+
+__global__ __launch_bounds__(ATX * ATY) void k_apss_tile(DevModel m, DevParams p, Shape sh, DevState in,
+                                                       DevState out, int only_above, int tiles_x, int tiles_y)
+{
+    extern __shared__ double apss_lds[];
+    const int R = p.apss_R, S = ATX + 2 * R, NS = S * (ATY + 2 * R);
+    double* tl = apss_lds;                                      // [KM][NS] depths
+    float* nl = reinterpret_cast<float*>(tl + KM * NS);         // [3][KM][NS] normals
+    int* cl = reinterpret_cast<int*>(nl + 3 * KM * NS);         // [NS] counts (0 outside the frame)
+    const long long P = sh.P;
+    const int tile = (int)xcd_block(blockIdx.x, gridDim.x);
+    const int tpf = tiles_x * tiles_y;
+    const int fr = tile / tpf, tr = tile % tpf;
+    const int i0 = (tr / tiles_x) * ATY, j0 = (tr % tiles_x) * ATX;
+    const long long fbase = (long long)fr * sh.rows * sh.cols;
+    // stage the tile and its halo (every slot, so no load waits on a count)
+    for (int x = threadIdx.x; x < NS; x += ATX * ATY) {
+        const int i2 = i0 - R + x / S, j2 = j0 - R + x % S;
+        int c = 0;
+        if (i2 >= 0 && i2 < sh.rows && j2 >= 0 && j2 < sh.cols) {
+            const long long pp = fbase + (long long)i2 * sh.cols + j2;
+            c = load_cnt(in.cnt, pp);
+#pragma unroll
+            for (int k = 0; k < KM; ++k) {
+                tl[k * NS + x] = in.t[k * P + pp];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) nl[(a * KM + k) * NS + x] = in.n[(a * KM + k) * P + pp];
+            }
+        }
+        cl[x] = c;
+    }
+    __syncthreads();
+    const int ty = threadIdx.x / ATX, tx = threadIdx.x % ATX;
+    const int i = i0 + ty, j = j0 + tx;
+    if (i >= sh.rows || j >= sh.cols) return;
+    const long long pix = fbase + (long long)i * sh.cols + j;
+    const int xc = (ty + R) * S + tx + R;
+    const int c = cl[xc];
+    out.cnt[pix] = (uint8_t)c;
+    out.b[pix] = in.b[pix];
+#pragma unroll
+    for (int k = 0; k < KM; ++k) out.r[k * P + pix] = in.r[k * P + pix];
+    const bool fit = !(only_above >= 0 && c <= only_above);
+    const float h = (float)p.h_apss, h2 = h * h, inv_h2 = 1.f / h2;
+    const float pxy = (float)p.p_xy;
+    const double dz = p.dz;
+    const double tmax = (double)(m.T - 1);
+    for (int k = 0; k < c; ++k) {
+        const double tq = tl[k * NS + xc];
+        float W = 0.f, Px = 0.f, Py = 0.f, Pz = 0.f, Nx = 0.f, Ny = 0.f, Nz = 0.f, PN = 0.f, PP = 0.f, nn = 0.f;
+        if (fit) {
+            for (int di = -R; di <= R; ++di) {
+                const float yy = (float)di * pxy;
+                for (int dj = -R; dj <= R; ++dj) {
+                    // pixels whose lateral offset alone reaches h hold no neighbour
+                    const float yx = (float)dj * pxy;
+                    const float dl = fmaf(yx, yx, yy * yy);
+                    if (!(dl < h2)) continue;
+                    const int x = xc + di * S + dj;
+                    const int cc = cl[x];
+                    for (int k2 = 0; k2 < cc; ++k2) {
+                        const float yz = (float)((tl[k2 * NS + x] - tq) * dz);
+                        const float d2 = fmaf(yz, yz, dl);
+                        if (!(d2 < h2)) continue;
+                        float a = 1.f - d2 * inv_h2;
+                        a = a * a;
+                        const float w = a * a;
+                        const float nx = nl[(0 * KM + k2) * NS + x];
+                        const float ny = nl[(1 * KM + k2) * NS + x];
+                        const float nz = nl[(2 * KM + k2) * NS + x];
+                        W += w;
+                        Px = fmaf(w, yx, Px);
+                        Py = fmaf(w, yy, Py);
+                        Pz = fmaf(w, yz, Pz);
+                        Nx = fmaf(w, nx, Nx);
+                        Ny = fmaf(w, ny, Ny);
+                        Nz = fmaf(w, nz, Nz);
+                        PN = fmaf(w, yx * nx + yy * ny + yz * nz, PN);
+                        PP = fmaf(w, d2, PP);
+                        nn += 1.f;
+                    }
+                }
+            }
+        }
+        double tn = tq;
+        float on[3] = {nl[(0 * KM + k) * NS + xc], nl[(1 * KM + k) * NS + xc], nl[(2 * KM + k) * NS + xc]};
+        apss_project(fit && nn >= (float)p.m_min, W, Px, Py, Pz, Nx, Ny, Nz, PN, PP, h, h2, dz, tmax, tn, on);
+        out.t[k * P + pix] = tn;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) out.n[(a * KM + k) * P + pix] = on[a];
     }
 }
 
@@ -97,11 +203,13 @@ __global__ __launch_bounds__(256) void k_apss(DevModel m, DevParams p, Shape sh,
                 const int i2 = i + widx / side - R, j2 = j + widx % side - R;
                 if (i2 < 0 || i2 >= sh.rows || j2 < 0 || j2 >= sh.cols) continue;
                 const float yy = (float)(i2 - i) * pxy, yx = (float)(j2 - j) * pxy;
+                const float dl = fmaf(yx, yx, yy * yy);
+                if (!(dl < h2)) continue;                  // no neighbour in this pixel
                 const long long pp = (fr * sh.rows + i2) * sh.cols + j2;
                 const int cc = load_cnt(in.cnt, pp);
                 for (int k2 = 0; k2 < cc; ++k2) {
                     const float yz = (float)((in.t[k2 * P + pp] - tq) * dz);
-                    const float d2 = yx * yx + yy * yy + yz * yz;
+                    const float d2 = fmaf(yz, yz, dl);
                     if (!(d2 < h2)) continue;
                     float a = 1.f - d2 * inv_h2;
                     a = a * a;
@@ -217,8 +325,16 @@ hipError_t launch_apss(const DevModel& m, const DevParams& p, const Shape& sh, D
                        int only_above, hipStream_t st)
 {
     if (sh.P == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_apss, dim3((unsigned)((sh.P * LPA + 255) / 256)), dim3(256), 0, st, m, p, sh, in, out,
-                       only_above);
+    const size_t lds = apss_tile_bytes(p.apss_R);
+    if (lds <= 65536) {
+        const int tx = (sh.cols + ATX - 1) / ATX, ty = (sh.rows + ATY - 1) / ATY;
+        const long long nt = (long long)sh.F * tx * ty;
+        hipLaunchKernelGGL(k_apss_tile, dim3((unsigned)nt), dim3(ATX * ATY), lds, st, m, p, sh, in, out, only_above,
+                           tx, ty);
+    } else {
+        hipLaunchKernelGGL(k_apss, dim3((unsigned)((sh.P * LPA + 255) / 256)), dim3(256), 0, st, m, p, sh, in, out,
+                           only_above);
+    }
     return hipGetLastError();
 }
 
