@@ -23,12 +23,15 @@ struct DevModel {
     float sigma2;         // IRF variance
     float fisher_inv;     // 1 / (shift Fisher information per photon)
     // S and S' of a point whose IRF support lies inside [0, T): all L + 1
-    // segments take part, and when none dips below zero on [0, 1] their sum
-    // is one cubic, s_c0 + s_c1 s + s_c2 s^2 + s_c3 s^3, whose slope loses
-    // s_z0 at s = 0 and s_z1 at s = 1 (segments whose value is exactly zero
-    // there, whose slope the clamp drops)
-    int    s_poly;
-    double s_c0, s_c1, s_c2, s_c3, s_z0, s_z1;
+    // segments take part, and their sum clamped at zero is a piecewise cubic
+    // in the shared local parameter s.  s_tab holds the s_np + 1 breakpoints
+    // (0 = b_0 < ... < b_np = 1), then per piece the coefficients c0..c3 of
+    // c0 + c1 s + c2 s^2 + c3 s^3; s_v0 / s_d0 and s_v1 / s_d1 are the value
+    // and slope at s = 0 and s = 1 (segments not positive there drop out).
+    // s_np = 0: direct summation.
+    int           s_np;
+    const double* s_tab;
+    double        s_v0, s_d0, s_v1, s_d1;
 };
 
 // Parameters as the kernels use them.
@@ -96,16 +99,24 @@ __device__ __forceinline__ void s_eval(const DevModel& m, double t, float& S, fl
     const float s = sh ? 1.f - f : 0.f;
     // segment k holds bin tb = k + a - o + sh; keep 0 <= tb <= T - 1
     const int k0 = max(-1, m.o - a - sh), k1 = min(m.L - 1, m.T - 1 + m.o - a - sh);
-    if (m.s_poly && k0 == -1 && k1 == m.L - 1) {   // every segment: one cubic (computed by part 0)
+    if (m.s_np > 0 && k0 == -1 && k1 == m.L - 1) {   // every segment: the piecewise cubic (by part 0)
         S = 0.f;
         Sp = 0.f;
         if (part == 0) {
-            const double sd = (double)s;
-            double dp = (3.0 * m.s_c3 * sd + 2.0 * m.s_c2) * sd + m.s_c1;
-            if (s == 0.f) dp -= m.s_z0;
-            else if (s == 1.f) dp -= m.s_z1;
-            S = (float)(((m.s_c3 * sd + m.s_c2) * sd + m.s_c1) * sd + m.s_c0);
-            Sp = (float)(-dp);
+            if (s == 0.f) {
+                S = (float)m.s_v0;
+                Sp = (float)(-m.s_d0);
+            } else if (s == 1.f) {
+                S = (float)m.s_v1;
+                Sp = (float)(-m.s_d1);
+            } else {
+                const double sd = (double)s;
+                int i = 0;
+                while (i + 1 < m.s_np && sd >= m.s_tab[i + 1]) ++i;
+                const double* c = m.s_tab + (m.s_np + 1) + 4 * i;
+                S = (float)(((c[3] * sd + c[2]) * sd + c[1]) * sd + c[0]);
+                Sp = (float)(-((3.0 * c[3] * sd + 2.0 * c[2]) * sd + c[1]));
+            }
         }
         return;
     }

@@ -24,14 +24,16 @@ struct rt3d_ctx {
     rt3d_params p{};
     int T = 0, L = 0, o = 0;
     double sigma2 = 0.0, fisher = 0.0;
-    int s_poly = 0;
-    double s_c[4] = {0, 0, 0, 0}, s_z0 = 0.0, s_z1 = 0.0;   // S over all segments (see DevModel)
+    int s_np = 0;                      // pieces of S over all segments (0: direct summation)
+    std::vector<double> s_tab;         // breakpoints then piece coefficients (see DevModel)
+    double s_v0 = 0, s_d0 = 0, s_v1 = 0, s_d1 = 0;
     int wl = 0, wr = 0, wnms = 0, apss_R = 0;
     double dmax = 0.0, dmerge = 0.0;
     std::vector<double> hbar;
     int device = 0;
     // device tables (owned)
     float4* d_cr = nullptr;
+    double* d_stab = nullptr;
     int32_t* d_q = nullptr;
     int32_t* d_qst = nullptr;
     double* d_hbar = nullptr;
@@ -60,6 +62,8 @@ struct rt3d_ctx {
 namespace {
 
 constexpr size_t ALIGN = 256;
+// pieces of the table of S beyond which the gradient kernels sum S directly
+constexpr int S_PIECES_MAX = 256;
 
 size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
@@ -177,13 +181,12 @@ DevModel dev_model(const rt3d_ctx* c)
     m.wnms = c->wnms;
     m.sigma2 = (float)c->sigma2;
     m.fisher_inv = (float)(1.0 / c->fisher);
-    m.s_poly = c->s_poly;
-    m.s_c0 = c->s_c[0];
-    m.s_c1 = c->s_c[1];
-    m.s_c2 = c->s_c[2];
-    m.s_c3 = c->s_c[3];
-    m.s_z0 = c->s_z0;
-    m.s_z1 = c->s_z1;
+    m.s_np = c->s_np;
+    m.s_tab = c->d_stab;
+    m.s_v0 = c->s_v0;
+    m.s_d0 = c->s_d0;
+    m.s_v1 = c->s_v1;
+    m.s_d1 = c->s_d1;
     return m;
 }
 
@@ -419,35 +422,82 @@ rt3d_status rt3d_create(const double* irf, uint32_t irf_len, int32_t irf_origin,
         d[3] = 0.5 * (p3 - p0) + 1.5 * (p1 - p2);
         cr[k + 1] = make_float4((float)d[0], (float)d[1], (float)d[2], (float)d[3]);
     }
-    // S and S' of points whose IRF support lies inside the domain: the sum of
-    // all segments' cubics is one cubic when no segment dips below zero on
-    // [0, 1] (then the clamp at zero only drops the slope of segments whose
-    // value is exactly zero at s = 0 or s = 1)
+    // S and S' of points whose IRF support lies inside the domain, as a
+    // piecewise cubic in the local parameter s that every segment shares:
+    // between consecutive zeros (in (0, 1)) of the segments' cubics each
+    // segment keeps its sign, so the sum of the segments clamped at zero is
+    // one cubic per piece.  At s = 0 and s = 1 segments whose value is not
+    // positive drop out with their slope; those sums are kept apart.
     {
-        bool ok = true;
+        std::vector<double> brk = {0.0, 1.0};
         for (int j = 0; j <= L; ++j) {
             const double* d = &crd[(size_t)4 * j];
             auto val = [&](double x) { return ((d[3] * x + d[2]) * x + d[1]) * x + d[0]; };
-            double lo = std::min(val(0.0), val(1.0));
-            const double A = 3.0 * d[3], B = 2.0 * d[2], Cc = d[1];   // slope: A x^2 + B x + Cc
+            // monotone stretches of [0, 1] between the slope's zeros, each
+            // bisected where the cubic changes sign
+            std::vector<double> cut = {0.0, 1.0};
+            const double A = 3.0 * d[3], B = 2.0 * d[2], Cc = d[1];
             if (A != 0.0) {
                 const double disc = B * B - 4.0 * A * Cc;
                 if (disc >= 0.0) {
                     const double r = std::sqrt(disc);
                     for (double x : {(-B - r) / (2.0 * A), (-B + r) / (2.0 * A)})
-                        if (x > 0.0 && x < 1.0) lo = std::min(lo, val(x));
+                        if (x > 0.0 && x < 1.0) cut.push_back(x);
                 }
             } else if (B != 0.0) {
                 const double x = -Cc / B;
-                if (x > 0.0 && x < 1.0) lo = std::min(lo, val(x));
+                if (x > 0.0 && x < 1.0) cut.push_back(x);
             }
-            if (lo < 0.0) ok = false;
-            for (int i = 0; i < 4; ++i) c->s_c[i] += d[i];
-            const int k = j - 1;   // segment k joins samples k and k + 1
-            if (hb(k) == 0.0) c->s_z0 += d[1];
-            if (hb(k + 1) == 0.0) c->s_z1 += d[1] + 2.0 * d[2] + 3.0 * d[3];
+            std::sort(cut.begin(), cut.end());
+            for (size_t u = 0; u + 1 < cut.size(); ++u) {
+                double lo = cut[u], hi = cut[u + 1];
+                double flo = val(lo), fhi = val(hi);
+                if (!((flo < 0.0 && fhi > 0.0) || (flo > 0.0 && fhi < 0.0))) continue;
+                for (int it = 0; it < 200 && hi - lo > 0.0; ++it) {
+                    const double mid = 0.5 * (lo + hi);
+                    if (mid <= lo || mid >= hi) break;
+                    const double fm = val(mid);
+                    if ((fm < 0.0) == (flo < 0.0)) {
+                        lo = mid;
+                        flo = fm;
+                    } else {
+                        hi = mid;
+                    }
+                }
+                brk.push_back(0.5 * (lo + hi));
+            }
         }
-        c->s_poly = ok ? 1 : 0;
+        std::sort(brk.begin(), brk.end());
+        brk.erase(std::unique(brk.begin(), brk.end()), brk.end());
+        std::vector<double> coef;
+        for (size_t u = 0; u + 1 < brk.size(); ++u) {
+            const double mid = 0.5 * (brk[u] + brk[u + 1]);
+            double cs[4] = {0, 0, 0, 0};
+            for (int j = 0; j <= L; ++j) {
+                const double* d = &crd[(size_t)4 * j];
+                if (((d[3] * mid + d[2]) * mid + d[1]) * mid + d[0] > 0.0)
+                    for (int i = 0; i < 4; ++i) cs[i] += d[i];
+            }
+            coef.insert(coef.end(), cs, cs + 4);
+        }
+        for (int j = 0; j <= L; ++j) {
+            const double* d = &crd[(size_t)4 * j];
+            if (d[0] > 0.0) {
+                c->s_v0 += d[0];
+                c->s_d0 += d[1];
+            }
+            const double v1 = d[0] + d[1] + d[2] + d[3];
+            if (v1 > 0.0) {
+                c->s_v1 += v1;
+                c->s_d1 += d[1] + 2.0 * d[2] + 3.0 * d[3];
+            }
+        }
+        const int np = (int)brk.size() - 1;
+        if (np >= 1 && np <= S_PIECES_MAX) {
+            c->s_np = np;
+            c->s_tab = brk;
+            c->s_tab.insert(c->s_tab.end(), coef.begin(), coef.end());
+        }
     }
     // shift Fisher information of one photon (no background), averaged over 32
     // sub-bin phases, over lags where h is at least 1e-3 of the largest sample
@@ -513,6 +563,9 @@ rt3d_status rt3d_create(const double* irf, uint32_t irf_len, int32_t irf_origin,
     if (e == hipSuccess) e = hipMalloc(&c->d_qst, sizeof(int32_t) * qst.size());
     if (e == hipSuccess) e = hipMalloc(&c->d_hbar, sizeof(double) * L);
     if (e == hipSuccess) e = hipMalloc(&c->d_bw, sizeof(float) * bw.size());
+    if (e == hipSuccess && c->s_np > 0) e = hipMalloc(&c->d_stab, sizeof(double) * c->s_tab.size());
+    if (e == hipSuccess && c->s_np > 0)
+        e = hipMemcpy(c->d_stab, c->s_tab.data(), sizeof(double) * c->s_tab.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->d_cr, cr.data(), sizeof(float4) * cr.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->d_q, q.data(), sizeof(int32_t) * q.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->d_qst, qst.data(), sizeof(int32_t) * qst.size(), hipMemcpyHostToDevice);
@@ -572,6 +625,7 @@ void rt3d_destroy(rt3d_ctx* c)
     int prev = 0;
     bool switched = hipGetDevice(&prev) == hipSuccess && prev != c->device && hipSetDevice(c->device) == hipSuccess;
     if (c->d_cr) (void)hipFree(c->d_cr);
+    if (c->d_stab) (void)hipFree(c->d_stab);
     if (c->d_q) (void)hipFree(c->d_q);
     if (c->d_qst) (void)hipFree(c->d_qst);
     if (c->d_hbar) (void)hipFree(c->d_hbar);
