@@ -35,23 +35,27 @@ struct PixPoints {
     double t[KM];
 };
 
+// Every slot is read whatever the count (the state holds KM slots per pixel),
+// so that no load waits on another; slots at or beyond the count are zeroed.
 __device__ __forceinline__ void load_points(const DevState& s, long long P, long long pix, PixPoints& q)
 {
+    double tv[KM];
+    float rv[KM];
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+        tv[k] = s.t[k * P + pix];
+        rv[k] = s.r[k * P + pix];
+    }
     q.c = load_cnt(s.cnt, pix);
 #pragma unroll
     for (int k = 0; k < KM; ++k) {
-        q.t[k] = 0.0;
-        q.r[k] = 0.f;
-        q.a[k] = 0;
-        q.f[k] = 0.f;
-        if (k < q.c) {
-            double t = s.t[k * P + pix];
-            double fl = floor(t);
-            q.t[k] = t;
-            q.a[k] = (int)fl;
-            q.f[k] = (float)(t - fl);
-            q.r[k] = s.r[k * P + pix];
-        }
+        const bool on = k < q.c;
+        const double t = on ? tv[k] : 0.0;
+        const double fl = floor(t);
+        q.t[k] = t;
+        q.a[k] = (int)fl;
+        q.f[k] = (float)(t - fl);
+        q.r[k] = on ? rv[k] : 0.f;
     }
 }
 
@@ -68,24 +72,19 @@ __device__ __forceinline__ void step_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Value of lane I of each aligned group of 4 lanes (DPP quad permutation).
-template <int I>
-__device__ __forceinline__ int quad_bcast(int v)
-{
-    return __builtin_amdgcn_update_dpp(0, v, I * 0x55, 0xF, 0xF, true);
-}
-
-// Photons a pixel's entry list holds per batch in LDS.
+// Entries of one batch of a pixel (STEP_BATCH per lane), staged in LDS.
 constexpr int STEP_LIST = STEP_BATCH * LPP;
 
 // Partial sums over one pixel's entries (e0p .. e1 - 1):
 // sz = sum z/lambda, sh[k] = sum z h_k/lambda, shp[k] = sum z h'_k/lambda.
-// The pixel's LPP lanes load its entries STEP_BATCH per lane at a time
-// (entry e0p + sub + LPP u).  h_k vanishes outside bins
-// [floor(t_k) - o - 1, floor(t_k) - o + L], so only entries inside the union
-// of these ranges (the points' support) are evaluated: they are compacted
-// into the pixel's LDS list and shared out over the lanes.  Every other entry
-// has lambda = g b and only adds z / (g b) to sz.
+// h_k vanishes outside bins [floor(t_k) - o - 1, floor(t_k) - o + L], so only
+// entries inside the union [lo, hi] of these ranges (the points' support) are
+// evaluated; every other entry has lambda = g b and only adds z / (g b) to
+// sz.  The pixel's LPP lanes load its entries STEP_BATCH per lane at a time
+// (entry e0p + sub + LPP u) and stage the batch in the pixel's LDS list.  The
+// entries ascend in bin, so the batch's support entries are one contiguous
+// run: the lanes count the entries below lo and up to hi, and then evaluate
+// the run from LDS, its entries shared out over the lanes in turn.
 __device__ __forceinline__ void accumulate(const DevModel& m, const PixPoints& q, float bb, float G,
                                            const uint32_t* __restrict__ ent, uint32_t e0p, uint32_t e1, int sub,
                                            uint32_t* list, float& sz, float (&sh)[KM], float (&shp)[KM])
@@ -97,30 +96,6 @@ __device__ __forceinline__ void accumulate(const DevModel& m, const PixPoints& q
         shp[k] = 0.f;
     }
     const float invG = 1.f / G;
-    auto one = [&](uint32_t v) {
-        const int tb = ent_bin(v);
-        const float z = (float)ent_cnt(v);
-        float h[KM], hp[KM];
-        float lam = bb;
-#pragma unroll
-        for (int k = 0; k < KM; ++k) {
-            h[k] = 0.f;
-            hp[k] = 0.f;
-            if (k < q.c) {
-                irf_eval(m, tb, q.a[k], q.f[k], h[k], hp[k]);
-                lam = fmaf(q.r[k], h[k], lam);
-            }
-        }
-        const float zl = z * invG * __builtin_amdgcn_rcpf(lam);
-        sz += zl;
-#pragma unroll
-        for (int k = 0; k < KM; ++k) {
-            if (k < q.c) {
-                sh[k] = fmaf(zl, h[k], sh[k]);
-                shp[k] = fmaf(zl, hp[k], shp[k]);
-            }
-        }
-    };
     int lo = 0x7fffffff, hi = -0x7fffffff;
 #pragma unroll
     for (int k = 0; k < KM; ++k)
@@ -128,7 +103,7 @@ __device__ __forceinline__ void accumulate(const DevModel& m, const PixPoints& q
             lo = min(lo, q.a[k] - m.o - 1);
             hi = max(hi, q.a[k] - m.o + m.L);
         }
-    float zout = 0.f;
+    int zout = 0;                                         // photons of this lane's entries outside the run
     for (uint32_t eb = e0p; eb < e1; eb += STEP_LIST) {    // the same trip count on the pixel's lanes
         uint32_t v[STEP_BATCH];
 #pragma unroll
@@ -136,29 +111,48 @@ __device__ __forceinline__ void accumulate(const DevModel& m, const PixPoints& q
             const uint32_t x = eb + sub + u * LPP;
             v[u] = x < e1 ? ent[x] : 0u;
         }
-        unsigned inmask = 0;
-        int n = 0;
+        uint32_t nlo = 0, nhi = 0;
 #pragma unroll
         for (int u = 0; u < STEP_BATCH; ++u) {
-            const bool valid = eb + sub + u * LPP < e1;
             const int tb = ent_bin(v[u]);
-            const bool in = valid && tb >= lo && tb <= hi;
-            if (valid && !in) zout += (float)ent_cnt(v[u]);
-            inmask |= in ? (1u << u) : 0u;
-            n += in ? 1 : 0;
+            const bool valid = eb + sub + u * LPP < e1;
+            const bool below = valid && tb < lo, upto = valid && tb <= hi;
+            nlo += below ? 1u : 0u;
+            nhi += upto ? 1u : 0u;
+            zout += upto && !below ? 0 : ent_cnt(v[u]);     // zero where not valid
+            list[sub + u * LPP] = v[u];
         }
-        static_assert(LPP == 4, "the list offsets below are quad prefix sums");
-        const int n0 = quad_bcast<0>(n), n1 = quad_bcast<1>(n), n2 = quad_bcast<2>(n), n3 = quad_bcast<3>(n);
-        int w = (sub > 0 ? n0 : 0) + (sub > 1 ? n1 : 0) + (sub > 2 ? n2 : 0);
-        const int total = n0 + n1 + n2 + n3;
-#pragma unroll
-        for (int u = 0; u < STEP_BATCH; ++u)
-            if ((inmask >> u) & 1u) list[w++] = v[u];
+        nlo = quad_sum_u32(nlo);
+        nhi = quad_sum_u32(nhi);
         step_sync();
-        for (int j = sub; j < total; j += LPP) one(list[j]);
+        for (uint32_t j = nlo + sub; j < nhi; j += LPP) {
+            const uint32_t v1 = list[j];
+            const int tb = ent_bin(v1);
+            const float z = (float)ent_cnt(v1);
+            float h[KM], hp[KM];
+            float lam = bb;
+#pragma unroll
+            for (int k = 0; k < KM; ++k) {
+                h[k] = 0.f;
+                hp[k] = 0.f;
+                if (k < q.c) {
+                    irf_eval(m, tb, q.a[k], q.f[k], h[k], hp[k]);
+                    lam = fmaf(q.r[k], h[k], lam);
+                }
+            }
+            const float zl = z * invG * __builtin_amdgcn_rcpf(lam);
+            sz += zl;
+#pragma unroll
+            for (int k = 0; k < KM; ++k) {
+                if (k < q.c) {
+                    sh[k] = fmaf(zl, h[k], sh[k]);
+                    shp[k] = fmaf(zl, hp[k], shp[k]);
+                }
+            }
+        }
         step_sync();
     }
-    sz += zout * invG * __builtin_amdgcn_rcpf(bb);
+    sz += (float)zout * invG * __builtin_amdgcn_rcpf(bb);
 }
 
 // Sums the partials of the LPP lanes of a pixel (every lane ends with the total).
@@ -213,12 +207,13 @@ __device__ __forceinline__ Lane lane_setup(const DevState& s, long long P, const
     L.sub = (int)(gid % LPP);
     L.live = L.pix < P;
     const long long pp = L.live ? L.pix : 0;
+    const uint32_t e0 = off[pp], e1 = off[pp + 1];
     L.G = L.live ? (gain ? gain[pp] : 1.f) : 0.f;
     load_points(s, P, pp, L.q);
     if (!L.live) L.q.c = 0;
     const bool work = L.live && L.G > 0.f && (!need_points || L.q.c > 0);
-    L.e0 = work ? off[pp] : 0;
-    L.e1 = work ? off[pp + 1] : 0;
+    L.e0 = work ? e0 : 0;
+    L.e1 = work ? e1 : 0;
     L.live = work;
     return L;
 }

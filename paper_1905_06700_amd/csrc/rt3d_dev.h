@@ -170,6 +170,13 @@ __device__ __forceinline__ float quad_sum(float v)
     return v;
 }
 
+__device__ __forceinline__ uint32_t quad_sum_u32(uint32_t v)
+{
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, true);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, true);
+    return v;
+}
+
 // Sum over each aligned group of 8 lanes: the quad sums, then the half-row
 // mirror (lane i of 8 meets lane 7 - i, which holds the other quad's sum).
 __device__ __forceinline__ float oct_sum(float v)
