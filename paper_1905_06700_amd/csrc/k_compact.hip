@@ -136,37 +136,22 @@ __device__ __forceinline__ void load8(const uint16_t* __restrict__ Z, long long 
         if (i0 + k < lo || i0 + k >= hi) z[k] = 0;
 }
 
-__global__ __launch_bounds__(64 * CP_WAVES) void k_compact_count(const uint16_t* __restrict__ Z, long long P,
-                                                                 int T, uint32_t* __restrict__ counts)
+// Pass 1: each pixel's histogram is read once; its non-zero bins, as entries
+// (t << 16 | z) in ascending t, go to the pixel's staging slot of CP_STAGE
+// entries (the first CP_STAGE of them when it has more), and its entry count
+// to counts[p].  One wavefront per pixel; each lane holds 8 consecutive bins
+// and a wavefront prefix sum of the lanes' non-zero counts places them.
+__global__ __launch_bounds__(64 * CP_WAVES) void k_compact_stage(const uint16_t* __restrict__ Z, long long P,
+                                                                 int T, uint32_t* __restrict__ counts,
+                                                                 uint32_t* __restrict__ stage)
 {
     const long long p = (long long)blockIdx.x * CP_WAVES + (threadIdx.x >> 6);
     if (p >= P) return;
     const int lane = threadIdx.x & 63;
     const long long lo = p * T, hi = lo + T, total = P * T;
     const long long vs = lo >> 3, ve = (hi + 7) >> 3;
-    uint32_t c = 0;
-    for (long long v = vs + lane; v < ve; v += 64) {
-        uint16_t z[8];
-        load8(Z, v, lo, hi, total, z);
-#pragma unroll
-        for (int k = 0; k < 8; ++k) c += z[k] != 0;
-    }
-    c = wave_sum_u32(c);
-    if (lane == 0) counts[p] = c;
-}
-
-__global__ __launch_bounds__(64 * CP_WAVES) void k_compact_fill(const uint16_t* __restrict__ Z, long long P,
-                                                                int T, const uint32_t* __restrict__ off,
-                                                                uint32_t* __restrict__ ent, uint64_t cap,
-                                                                int32_t* __restrict__ err)
-{
-    const long long p = (long long)blockIdx.x * CP_WAVES + (threadIdx.x >> 6);
-    if (p >= P) return;
-    const int lane = threadIdx.x & 63;
-    const long long lo = p * T, hi = lo + T, total = P * T;
-    const long long vs = lo >> 3, ve = (hi + 7) >> 3;
-    uint64_t run = off[p];
-    bool overflow = false;
+    uint32_t* slot = stage + p * CP_STAGE;
+    uint32_t run = 0;
     for (long long vb = vs; vb < ve; vb += 64) {       // uniform over the wave
         const long long v = vb + lane;
         uint16_t z[8];
@@ -178,32 +163,84 @@ __global__ __launch_bounds__(64 * CP_WAVES) void k_compact_fill(const uint16_t* 
         uint32_t c = 0;
 #pragma unroll
         for (int k = 0; k < 8; ++k) c += z[k] != 0;
-        uint32_t inc = wave_incl_scan(c);
-        uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
-        uint64_t pos = run + (inc - c);
+        const uint32_t inc = wave_incl_scan(c);
+        uint32_t pos = run + (inc - c);
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             if (z[k]) {
-                uint32_t bin = (uint32_t)((v << 3) + k - lo);
-                if (pos < cap) ent[pos] = (bin << 16) | z[k];
-                else overflow = true;
+                const uint32_t bin = (uint32_t)((v << 3) + k - lo);
+                if (pos < CP_STAGE) slot[pos] = (bin << 16) | z[k];
                 ++pos;
             }
         }
-        run += tot;
+        run += (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
+    }
+    if (lane == 0) counts[p] = run;
+}
+
+// Pass 2 (after the scan of the counts into off): each pixel's entries move
+// from its staging slot to off[p]; a pixel with more than CP_STAGE entries
+// reads its histogram again.  Entries past `cap` are dropped (E_CAPACITY).
+__global__ __launch_bounds__(64 * CP_WAVES) void k_compact_copy(const uint16_t* __restrict__ Z, long long P,
+                                                                int T, const uint32_t* __restrict__ off,
+                                                                const uint32_t* __restrict__ stage,
+                                                                uint32_t* __restrict__ ent, uint64_t cap,
+                                                                int32_t* __restrict__ err)
+{
+    const long long p = (long long)blockIdx.x * CP_WAVES + (threadIdx.x >> 6);
+    if (p >= P) return;
+    const int lane = threadIdx.x & 63;
+    const uint64_t base = off[p];
+    const uint32_t n = off[p + 1] - off[p];
+    bool overflow = false;
+    if (n <= (uint32_t)CP_STAGE) {
+        const uint32_t* slot = stage + p * CP_STAGE;
+        for (uint32_t k = lane; k < n; k += 64) {
+            if (base + k < cap) ent[base + k] = slot[k];
+            else overflow = true;
+        }
+    } else {
+        const long long lo = p * T, hi = lo + T, total = P * T;
+        const long long vs = lo >> 3, ve = (hi + 7) >> 3;
+        uint64_t run = base;
+        for (long long vb = vs; vb < ve; vb += 64) {   // uniform over the wave
+            const long long v = vb + lane;
+            uint16_t z[8];
+            if (v < ve) load8(Z, v, lo, hi, total, z);
+            else {
+#pragma unroll
+                for (int k = 0; k < 8; ++k) z[k] = 0;
+            }
+            uint32_t c = 0;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) c += z[k] != 0;
+            const uint32_t inc = wave_incl_scan(c);
+            uint64_t pos = run + (inc - c);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                if (z[k]) {
+                    const uint32_t bin = (uint32_t)((v << 3) + k - lo);
+                    if (pos < cap) ent[pos] = (bin << 16) | z[k];
+                    else overflow = true;
+                    ++pos;
+                }
+            }
+            run += (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
+        }
     }
     if (overflow) *err = RT3D_E_CAPACITY;
 }
 
 hipError_t launch_compact(const uint16_t* Z, long long P, int T, uint32_t* off, uint32_t* ent, uint64_t cap,
-                          uint32_t* counts, uint32_t* partial, int32_t* err, hipStream_t st)
+                          uint32_t* counts, uint32_t* partial, uint32_t* stage, int32_t* err, hipStream_t st)
 {
     unsigned nb = (unsigned)((P + CP_WAVES - 1) / CP_WAVES);
-    if (nb > 0) hipLaunchKernelGGL(k_compact_count, dim3(nb), dim3(64 * CP_WAVES), 0, st, Z, P, T, counts);
+    if (nb > 0) hipLaunchKernelGGL(k_compact_stage, dim3(nb), dim3(64 * CP_WAVES), 0, st, Z, P, T, counts, stage);
     hipError_t e = launch_scan(counts, off, P, partial, cap, err, st);
     if (e != hipSuccess) return e;
     if (nb > 0)
-        hipLaunchKernelGGL(k_compact_fill, dim3(nb), dim3(64 * CP_WAVES), 0, st, Z, P, T, off, ent, cap, err);
+        hipLaunchKernelGGL(k_compact_copy, dim3(nb), dim3(64 * CP_WAVES), 0, st, Z, P, T, off, stage, ent, cap,
+                           err);
     return hipGetLastError();
 }
 

@@ -235,8 +235,12 @@ hipError_t launch_scan(const uint32_t* in, uint32_t* out, long long n, uint32_t*
                        uint64_t cap, int32_t* err, hipStream_t st);
 size_t scan_partial_elems(long long n);
 
+// Entries of a pixel the compaction stages per pixel (workspace: P x CP_STAGE);
+// pixels with more read their histogram a second time.
+constexpr int CP_STAGE = 128;
+
 hipError_t launch_compact(const uint16_t* Z, long long P, int T, uint32_t* off, uint32_t* ent,
-                          uint64_t cap, uint32_t* counts, uint32_t* partial, int32_t* err,
+                          uint64_t cap, uint32_t* counts, uint32_t* partial, uint32_t* stage, int32_t* err,
                           hipStream_t st);
 
 hipError_t launch_compact_events(const uint32_t* pix, const uint16_t* bin, uint64_t n, long long P, int T,

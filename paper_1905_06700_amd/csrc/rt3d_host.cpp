@@ -73,6 +73,7 @@ struct Workspace {
     uint32_t* counts;
     uint32_t* partial;
     uint32_t* evoff;
+    uint32_t* stage;
     DevState A, B;
     float* btmp;
     CnnBuffers cnn;
@@ -97,6 +98,7 @@ Workspace carve(uint8_t* base, long long P, uint64_t E, bool with_cnn = false, u
     w.counts = (uint32_t*)take(sizeof(uint32_t) * std::max<long long>(P, 1));
     w.partial = (uint32_t*)take(sizeof(uint32_t) * scan_partial_elems(P));
     w.evoff = (uint32_t*)take(sizeof(uint32_t) * (P + 1));
+    w.stage = (uint32_t*)take(sizeof(uint32_t) * CP_STAGE * std::max<long long>(P, 1));
     for (DevState* s : {&w.A, &w.B}) {
         s->t = (double*)take(sizeof(double) * KM * P);
         s->r = (float*)take(sizeof(float) * KM * P);
@@ -706,7 +708,7 @@ rt3d_status rt3d_reconstruct(rt3d_ctx* c, const rt3d_input* in, rt3d_output* out
         if (!in->hist) return fail(c, RT3D_E_INVALID, "hist is NULL");
         if (((uintptr_t)in->hist) % 16) return fail(c, RT3D_E_INVALID, "hist not 16-byte aligned");
         RT3D_LAUNCH(c, RT3D_KERNEL_COMPACT, st,
-                    launch_compact(in->hist, sh.P, c->T, w.off, w.ent, c->ws_E, w.counts, w.partial, w.err, st));
+                    launch_compact(in->hist, sh.P, c->T, w.off, w.ent, c->ws_E, w.counts, w.partial, w.stage, w.err, st));
         off = w.off;
         ent = w.ent;
         c->last_compacted = true;
@@ -834,7 +836,7 @@ rt3d_status rt3d_debug_compact(rt3d_ctx* c, const uint16_t* hist, uint32_t npix,
     Workspace w;
     rt3d_status s = need_ws(c, npix, w);
     if (s != RT3D_OK) return s;
-    RT3D_HIP(c, launch_compact(hist, npix, c->T, off, ent, capacity, w.counts, w.partial, w.err,
+    RT3D_HIP(c, launch_compact(hist, npix, c->T, off, ent, capacity, w.counts, w.partial, w.stage, w.err,
                                (hipStream_t)hip_stream));
     return RT3D_OK;
 }
