@@ -46,8 +46,7 @@ def scene_params(sc):
 ALU_INT_PEAK_TOPS = 64 * 2 * 256 * 2.4e9 / 1e12
 
 # Kernel groups timed one at a time by the library's event timer.
-GROUPS = ["compact", "init", "normals", "depth", "apss", "merge", "intensity", "ifilter", "bkg", "bfilter",
-          "output"]
+GROUPS = ["compact", "init", "normals", "depth", "apss", "intensity", "ifilter", "bkg", "bfilter", "output"]
 
 # Library sources each group's code lives in (for matching stored byte counters).
 GROUP_SOURCES = {"compact": ["k_compact.hip"], "init": ["k_init.hip"], "normals": ["k_init.hip"],
@@ -64,7 +63,8 @@ def algorithmic_bytes(kernel, F, N, T, E, pts):
         return 2 * FN * T + 4 * E + 4 * (FN + 1)
     if kernel in ("depth", "intensity"):
         # entries + offsets + count + background, point depth (f64) and intensity read,
-        # updated depth or intensity written
+        # updated depth or intensity written (the intensity group also merges, which
+        # for points in depth order and apart reads nothing more)
         wr = 8 if kernel == "depth" else 4
         return 4 * E + 4 * (FN + 1) + FN + 4 * FN + 12 * pts + wr * pts
     if kernel == "bkg":

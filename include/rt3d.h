@@ -220,8 +220,8 @@ rt3d_status rt3d_query(rt3d_ctx* ctx, void* hip_stream, rt3d_stats* st);
 #define RT3D_KERNEL_NORMALS   2   /* initial normals */
 #define RT3D_KERNEL_DEPTH     3   /* depth gradient step */
 #define RT3D_KERNEL_APSS      4   /* APSS */
-#define RT3D_KERNEL_MERGE     5   /* in-pixel merge */
-#define RT3D_KERNEL_INTENSITY 6   /* intensity gradient step */
+#define RT3D_KERNEL_MERGE     5   /* in-pixel merge launched alone (the step entry point only) */
+#define RT3D_KERNEL_INTENSITY 6   /* in-pixel merge fused with the intensity gradient step */
 #define RT3D_KERNEL_IFILTER   7   /* intensity low-pass and threshold */
 #define RT3D_KERNEL_BKG       8   /* background gradient step */
 #define RT3D_KERNEL_BFILTER   9   /* background filter (row and column passes) */

@@ -254,7 +254,8 @@ __global__ __launch_bounds__(256) void k_apss(DevModel m, DevParams p, Shape sh,
 
 // Reading (not in the paper): points of one pixel closer than d_merge bins in
 // depth describe one surface; in depth order they merge into the
-// intensity-weighted depth, summed intensity and weighted normal.
+// intensity-weighted depth, summed intensity and weighted normal
+// (merge_points).
 __global__ __launch_bounds__(256) void k_merge(DevParams p, Shape sh, DevState s)
 {
     const long long P = sh.P;
@@ -274,51 +275,8 @@ __global__ __launch_bounds__(256) void k_merge(DevParams p, Shape sh, DevState s
             nz[k] = s.n[(2 * KM + k) * P + pix];
         }
     }
-    // stable insertion sort by depth
-    for (int a = 1; a < c; ++a)
-        for (int b = a; b > 0 && t[b] < t[b - 1]; --b) {
-            double x = t[b]; t[b] = t[b - 1]; t[b - 1] = x;
-            float y = r[b]; r[b] = r[b - 1]; r[b - 1] = y;
-            y = nx[b]; nx[b] = nx[b - 1]; nx[b - 1] = y;
-            y = ny[b]; ny[b] = ny[b - 1]; ny[b - 1] = y;
-            y = nz[b]; nz[b] = nz[b - 1]; nz[b - 1] = y;
-        }
-    const double dm = p.d_merge;
-    int a = 0;
-    while (a + 1 < c) {
-        if (t[a + 1] - t[a] < dm) {
-            const double ra = r[a], rb = r[a + 1];
-            const double tt = (ra + rb > 0.0) ? (ra * t[a] + rb * t[a + 1]) / (ra + rb) : 0.5 * (t[a] + t[a + 1]);
-            const float mx = r[a] * nx[a] + r[a + 1] * nx[a + 1];
-            const float my = r[a] * ny[a] + r[a + 1] * ny[a + 1];
-            const float mz = r[a] * nz[a] + r[a + 1] * nz[a + 1];
-            const float nrm = sqrtf(mx * mx + my * my + mz * mz);
-            if (nrm > 0.f) {
-                nx[a] = mx / nrm;
-                ny[a] = my / nrm;
-                nz[a] = mz / nrm;
-            }
-            t[a] = tt;
-            r[a] = (float)(ra + rb);
-            for (int b = a + 1; b + 1 < c; ++b) {
-                t[b] = t[b + 1]; r[b] = r[b + 1];
-                nx[b] = nx[b + 1]; ny[b] = ny[b + 1]; nz[b] = nz[b + 1];
-            }
-            --c;
-        } else {
-            ++a;
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < KM; ++k) {
-        const bool live = k < c;
-        s.t[k * P + pix] = live ? t[k] : 0.0;
-        s.r[k * P + pix] = live ? r[k] : 0.f;
-        s.n[(0 * KM + k) * P + pix] = live ? nx[k] : 0.f;
-        s.n[(1 * KM + k) * P + pix] = live ? ny[k] : 0.f;
-        s.n[(2 * KM + k) * P + pix] = live ? nz[k] : -1.f;
-    }
-    s.cnt[pix] = (uint8_t)c;
+    merge_points(t, r, nx, ny, nz, c, p.d_merge);
+    store_points(s, P, pix, t, r, nx, ny, nz, c);
 }
 
 hipError_t launch_apss(const DevModel& m, const DevParams& p, const Shape& sh, DevState in, DevState out,

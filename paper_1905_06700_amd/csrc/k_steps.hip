@@ -248,6 +248,48 @@ __global__ __launch_bounds__(256) void k_depth_step(DevModel m, DevParams p, Sha
     }
 }
 
+// The in-pixel merge ahead of the intensity step: every lane of the pixel
+// merges its copy of the points (merge_points); lane 0 writes the merged
+// state.  Pixels whose points are in depth order and at least d_merge apart
+// (almost all) keep their state untouched.
+__device__ __forceinline__ void merge_lane(const DevState& s, long long P, const DevParams& p, long long pix,
+                                           int sub, PixPoints& q)
+{
+    const int c0 = q.c;
+    bool need = false;
+#pragma unroll
+    for (int k = 1; k < KM; ++k)
+        if (k < c0 && (q.t[k] < q.t[k - 1] || q.t[k] - q.t[k - 1] < p.d_merge)) need = true;
+    if (!need) return;
+    double t[KM];
+    float r[KM], nx[KM], ny[KM], nz[KM];
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+        t[k] = q.t[k];
+        r[k] = q.r[k];
+        nx[k] = s.n[(0 * KM + k) * P + pix];
+        ny[k] = s.n[(1 * KM + k) * P + pix];
+        nz[k] = s.n[(2 * KM + k) * P + pix];
+    }
+    int c = c0;
+    merge_points(t, r, nx, ny, nz, c, p.d_merge);
+    if (sub == 0) store_points(s, P, pix, t, r, nx, ny, nz, c);
+    q.c = c;
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+        const bool on = k < c;
+        const double tk = on ? t[k] : 0.0;
+        const double fl = floor(tk);
+        q.t[k] = tk;
+        q.a[k] = (int)fl;
+        q.f[k] = (float)(tk - fl);
+        q.r[k] = on ? r[k] : 0.f;
+    }
+}
+
+// MERGE: the in-pixel merge runs first (the loop's order: merge, then the
+// intensity step on the merged points).
+template <bool MERGE>
 __global__ __launch_bounds__(256) void k_intensity_step(DevModel m, DevParams p, Shape sh,
                                                         const uint32_t* __restrict__ off,
                                                         const uint32_t* __restrict__ ent,
@@ -256,7 +298,8 @@ __global__ __launch_bounds__(256) void k_intensity_step(DevModel m, DevParams p,
     __shared__ uint32_t lists[256 / LPP * STEP_LIST];
     uint32_t* list = lists + (threadIdx.x / LPP) * STEP_LIST;
     const long long P = sh.P;
-    const Lane L = lane_setup(s, P, off, gain, true);
+    Lane L = lane_setup(s, P, off, gain, true);
+    if (MERGE && L.pix < P) merge_lane(s, P, p, L.pix, L.sub, L.q);
     float sz, shh[KM], shp[KM];
     accumulate(m, L.q, L.live ? s.b[L.pix] : 1.f, L.live ? L.G : 1.f, ent, L.e0, L.e1, L.sub, list, sz, shh, shp);
     reduce_lanes(sz, shh, shp);
@@ -337,11 +380,15 @@ hipError_t launch_depth_step(const DevModel& m, const DevParams& p, const Shape&
 }
 
 hipError_t launch_intensity_step(const DevModel& m, const DevParams& p, const Shape& sh, const uint32_t* off,
-                                 const uint32_t* ent, const float* gain, DevState s, hipStream_t st)
+                                 const uint32_t* ent, const float* gain, DevState s, bool merge, hipStream_t st)
 {
     if (sh.P == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_intensity_step, dim3(blocks_for(sh.P * LPP, 256)), dim3(256), 0, st, m, p, sh, off, ent,
-                       gain, s);
+    if (merge)
+        hipLaunchKernelGGL(k_intensity_step<true>, dim3(blocks_for(sh.P * LPP, 256)), dim3(256), 0, st, m, p, sh,
+                           off, ent, gain, s);
+    else
+        hipLaunchKernelGGL(k_intensity_step<false>, dim3(blocks_for(sh.P * LPP, 256)), dim3(256), 0, st, m, p, sh,
+                           off, ent, gain, s);
     return hipGetLastError();
 }
 

@@ -134,6 +134,69 @@ __device__ __forceinline__ void s_eval(const DevModel& m, double t, float& S, fl
 
 __device__ __forceinline__ int ent_bin(uint32_t e) { return (int)(e >> 16); }
 
+// In-pixel merge of c points (reading; the paper does not say how duplicate
+// points of one pixel are treated): a stable insertion sort by depth, then,
+// in depth order, a point closer than dm bins to the next merges with it into
+// the intensity-weighted depth (the plain mean when both intensities are 0),
+// the summed intensity and the intensity-weighted normal, normalised (the
+// first point's normal when the weighted sum vanishes); the merged point is
+// compared with the next.  c drops by one per merge.
+__device__ __forceinline__ void merge_points(double (&t)[KM], float (&r)[KM], float (&nx)[KM], float (&ny)[KM],
+                                             float (&nz)[KM], int& c, double dm)
+{
+    for (int a = 1; a < c; ++a)
+        for (int b = a; b > 0 && t[b] < t[b - 1]; --b) {
+            double x = t[b]; t[b] = t[b - 1]; t[b - 1] = x;
+            float y = r[b]; r[b] = r[b - 1]; r[b - 1] = y;
+            y = nx[b]; nx[b] = nx[b - 1]; nx[b - 1] = y;
+            y = ny[b]; ny[b] = ny[b - 1]; ny[b - 1] = y;
+            y = nz[b]; nz[b] = nz[b - 1]; nz[b - 1] = y;
+        }
+    int a = 0;
+    while (a + 1 < c) {
+        if (t[a + 1] - t[a] < dm) {
+            const double ra = r[a], rb = r[a + 1];
+            const double tt = (ra + rb > 0.0) ? (ra * t[a] + rb * t[a + 1]) / (ra + rb) : 0.5 * (t[a] + t[a + 1]);
+            const float mx = r[a] * nx[a] + r[a + 1] * nx[a + 1];
+            const float my = r[a] * ny[a] + r[a + 1] * ny[a + 1];
+            const float mz = r[a] * nz[a] + r[a + 1] * nz[a + 1];
+            const float nrm = sqrtf(mx * mx + my * my + mz * mz);
+            if (nrm > 0.f) {
+                nx[a] = mx / nrm;
+                ny[a] = my / nrm;
+                nz[a] = mz / nrm;
+            }
+            t[a] = tt;
+            r[a] = (float)(ra + rb);
+            for (int b = a + 1; b + 1 < c; ++b) {
+                t[b] = t[b + 1]; r[b] = r[b + 1];
+                nx[b] = nx[b + 1]; ny[b] = ny[b + 1]; nz[b] = nz[b + 1];
+            }
+            --c;
+        } else {
+            ++a;
+        }
+    }
+}
+
+// Writes a pixel's c points to its KM slots (empty slots: zero depth and
+// intensity, normal facing the sensor) and its count.
+__device__ __forceinline__ void store_points(const DevState& s, long long P, long long pix, const double (&t)[KM],
+                                             const float (&r)[KM], const float (&nx)[KM], const float (&ny)[KM],
+                                             const float (&nz)[KM], int c)
+{
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+        const bool live = k < c;
+        s.t[k * P + pix] = live ? t[k] : 0.0;
+        s.r[k * P + pix] = live ? r[k] : 0.f;
+        s.n[(0 * KM + k) * P + pix] = live ? nx[k] : 0.f;
+        s.n[(1 * KM + k) * P + pix] = live ? ny[k] : 0.f;
+        s.n[(2 * KM + k) * P + pix] = live ? nz[k] : -1.f;
+    }
+    s.cnt[pix] = (uint8_t)c;
+}
+
 // Live slot count of a pixel, clamped to the slot capacity.
 __device__ __forceinline__ int load_cnt(const uint8_t* cnt, long long pix)
 {
@@ -255,9 +318,10 @@ hipError_t launch_init_normals(const DevParams& p, const Shape& sh, DevState s, 
 hipError_t launch_depth_step(const DevModel& m, const DevParams& p, const Shape& sh,
                              const uint32_t* off, const uint32_t* ent, const float* gain,
                              DevState s, hipStream_t st);
+// merge: the in-pixel merge first, fused (the loop's order)
 hipError_t launch_intensity_step(const DevModel& m, const DevParams& p, const Shape& sh,
                                  const uint32_t* off, const uint32_t* ent, const float* gain,
-                                 DevState s, hipStream_t st);
+                                 DevState s, bool merge, hipStream_t st);
 hipError_t launch_bg_step(const DevModel& m, const DevParams& p, const Shape& sh,
                           const uint32_t* off, const uint32_t* ent, const float* gain, DevState s,
                           hipStream_t st);

@@ -312,8 +312,8 @@ rt3d_status iterate(rt3d_ctx* c, const Shape& sh, const uint32_t* off, const uin
         RT3D_HIP(c, launch_copy_state(sh, A, B, st));
         cur = B;
     }
-    RT3D_LAUNCH(c, RT3D_KERNEL_MERGE, st, launch_merge(p, sh, cur, st));
-    RT3D_LAUNCH(c, RT3D_KERNEL_INTENSITY, st, launch_intensity_step(m, p, sh, off, ent, gain, cur, st));
+    // the in-pixel merge runs fused ahead of the intensity step
+    RT3D_LAUNCH(c, RT3D_KERNEL_INTENSITY, st, launch_intensity_step(m, p, sh, off, ent, gain, cur, true, st));
     RT3D_LAUNCH(c, RT3D_KERNEL_IFILTER, st, launch_ifilter(p, sh, cur, A, st));
     RT3D_LAUNCH(c, RT3D_KERNEL_BKG, st, launch_bg_step(m, p, sh, off, ent, gain, A, st));
     RT3D_LAUNCH(c, RT3D_KERNEL_BFILTER, st, launch_bfilter(c->d_bw, c->rb, sh, (float)c->p.b_min, A.b, btmp, st));
@@ -901,7 +901,7 @@ rt3d_status rt3d_debug_step(rt3d_ctx* c, int32_t step, const uint32_t* off, cons
         RT3D_HIP(c, launch_merge(p, sh, O, st));
         return RT3D_OK;
     case RT3D_STEP_INTENSITY:
-        RT3D_HIP(c, launch_intensity_step(m, p, sh, off, ent, gain, O, st));
+        RT3D_HIP(c, launch_intensity_step(m, p, sh, off, ent, gain, O, false, st));
         return RT3D_OK;
     case RT3D_STEP_BKG:
         RT3D_HIP(c, launch_bg_step(m, p, sh, off, ent, gain, O, st));

@@ -213,6 +213,39 @@ def test_single_steps_match_oracle(name):
     np.testing.assert_allclose(sg.b, so.b, rtol=1e-5, atol=1e-12)
 
 
+def test_iteration_merges_close_points_like_oracle():
+    """One whole iteration (the loop fuses the in-pixel merge into the
+    intensity step) on a state where every fifth single-point pixel holds a
+    second point closer than d_merge, half of them out of depth order."""
+    from gpu_util import to_dev_u32
+    sc = scene("c1")
+    O, ctx = pair(sc)
+    off_o, ent_o = csr(sc)
+    off, ent = to_dev_u32(off_o), to_dev_u32(ent_o)
+    s0 = _state_after(sc, O, 2)
+    dm = O.p.d_merge if O.p.d_merge > 0 else max(1.0, np.sqrt(O.m.sigma2))
+    picks = np.nonzero(s0.cnt == 1)[0][::5]
+    assert picks.size > 50
+    for n, q in enumerate(picks):
+        t, r, nv = s0.t[q, 0], s0.r[q, 0], s0.n[q, 0].copy()
+        close = (t + 0.4 * dm, 0.5 * r) if n % 2 else (t - 0.3 * dm, 0.7 * r)
+        if n % 4 < 2:      # the added point in slot 0: depths out of order when it lies deeper
+            s0.t[q, :2] = [close[0], t]
+            s0.r[q, :2] = [close[1], r]
+        else:
+            s0.t[q, :2] = [t, close[0]]
+            s0.r[q, :2] = [r, close[1]]
+        s0.n[q, 1] = nv
+        s0.cnt[q] = 2
+    print(f"[gpu-parity] merge-iteration: {picks.size} pixels with an added close point", flush=True)
+    so = O.iterate(off_o, ent_o, s0.copy())
+    sg = device_to_oracle(ctx.step(rt3d.STEP_ITERATION, oracle_to_device(s0), off, ent), 4)
+    same = sg.cnt == so.cnt
+    assert same[picks].mean() >= 0.99 and same.mean() >= 0.999
+    lv = (np.arange(4)[None, :] < so.cnt[:, None]) & same[:, None]
+    assert np.abs(sg.t - so.t)[lv].max() <= 1e-3
+
+
 # ------------------------------------------------------------------ whole loop
 
 def _compare_final(sc, so, res, P):
