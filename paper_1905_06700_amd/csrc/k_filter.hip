@@ -18,48 +18,75 @@
 
 namespace rt3d {
 
-__global__ __launch_bounds__(256) void k_ifilter(DevParams p, Shape sh, DevState in, DevState out)
+// Intensity filter and threshold on 16 x 16 pixel tiles of one frame: the
+// tile's depths, intensities and counts with a one-pixel halo are staged in
+// LDS, then one thread per pixel filters its points.
+constexpr int IFT = 16;
+constexpr int IFS = IFT + 2;
+
+__global__ __launch_bounds__(IFT * IFT) void k_ifilter_tile(DevParams p, Shape sh, DevState in, DevState out,
+                                                            int tiles_x, int tiles_y)
 {
+    __shared__ double tl[KM][IFS * IFS];
+    __shared__ float rl[KM][IFS * IFS];
+    __shared__ int cl[IFS * IFS];
     const long long P = sh.P;
-    const long long pix = (long long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (pix >= P) return;
-    const int c = load_cnt(in.cnt, pix);
-    const int per_frame = sh.rows * sh.cols;
-    const long long fr = pix / per_frame;
-    const int i = (int)((pix / sh.cols) % sh.rows), j = (int)(pix % sh.cols);
+    const int tile = (int)xcd_block(blockIdx.x, gridDim.x);
+    const int tpf = tiles_x * tiles_y;
+    const int fr = tile / tpf, tr = tile % tpf;
+    const int i0 = (tr / tiles_x) * IFT, j0 = (tr % tiles_x) * IFT;
+    const long long fbase = (long long)fr * sh.rows * sh.cols;
+    for (int x = threadIdx.x; x < IFS * IFS; x += IFT * IFT) {
+        const int i2 = i0 - 1 + x / IFS, j2 = j0 - 1 + x % IFS;
+        int c = 0;
+        if (i2 >= 0 && i2 < sh.rows && j2 >= 0 && j2 < sh.cols) {
+            const long long pp = fbase + (long long)i2 * sh.cols + j2;
+            c = load_cnt(in.cnt, pp);
+#pragma unroll
+            for (int k = 0; k < KM; ++k) {
+                tl[k][x] = in.t[k * P + pp];
+                rl[k][x] = in.r[k * P + pp];
+            }
+        }
+        cl[x] = c;
+    }
+    __syncthreads();
+    const int ty = threadIdx.x / IFT, tx = threadIdx.x % IFT;
+    const int i = i0 + ty, j = j0 + tx;
+    if (i >= sh.rows || j >= sh.cols) return;
+    const long long pix = fbase + (long long)i * sh.cols + j;
+    const int xc = (ty + 1) * IFS + tx + 1;
+    const int c = cl[xc];
     const float hi2 = (float)(p.h_int * p.h_int);
     const float pxy = (float)p.p_xy;
     const double dz = p.dz;
     const float rmin = (float)p.r_min;
+    int nside = 0;
+    for (int di = -1; di <= 1; ++di)
+        for (int dj = -1; dj <= 1; ++dj)
+            if (!(di == 0 && dj == 0) && i + di >= 0 && i + di < sh.rows && j + dj >= 0 && j + dj < sh.cols) ++nside;
     int nk = 0;
-    for (int k = 0; k < KM; ++k) {
-        if (k >= c) break;
-        const double tq = in.t[k * P + pix];
-        const float rq = in.r[k * P + pix];
-        float sum = rq;
-        int nside = 0;
+    for (int k = 0; k < c; ++k) {
+        const double tq = tl[k][xc];
+        float sum = rl[k][xc];
         for (int di = -1; di <= 1; ++di) {
-            const int i2 = i + di;
-            if (i2 < 0 || i2 >= sh.rows) continue;
             const float dy = (float)di * pxy;
             for (int dj = -1; dj <= 1; ++dj) {
-                const int j2 = j + dj;
-                if ((di == 0 && dj == 0) || j2 < 0 || j2 >= sh.cols) continue;
-                ++nside;
+                if (di == 0 && dj == 0) continue;
                 const float dx = (float)dj * pxy;
-                const long long pp = (fr * sh.rows + i2) * sh.cols + j2;
-                const int cc = load_cnt(in.cnt, pp);
+                const int x = xc + di * IFS + dj;
+                const int cc = cl[x];                   // 0 outside the image
                 int best = -1;
                 float bd = 0.f;
                 for (int k2 = 0; k2 < cc; ++k2) {
-                    const float ddz = (float)((in.t[k2 * P + pp] - tq) * dz);
+                    const float ddz = (float)((tl[k2][x] - tq) * dz);
                     const float d2 = dx * dx + dy * dy + ddz * ddz;
                     if (best < 0 || d2 < bd) {
                         best = k2;
                         bd = d2;
                     }
                 }
-                if (best >= 0 && bd < hi2) sum += in.r[best * P + pp];
+                if (best >= 0 && bd < hi2) sum += rl[best][x];
             }
         }
         const float rn = sum / (float)(1 + nside);
@@ -116,11 +143,67 @@ __global__ __launch_bounds__(256) void k_bfilter_cols(const float* __restrict__ 
     b[pix] = fmaxf(a, b_min);
 }
 
-__global__ __launch_bounds__(256) void k_bfloor(Shape sh, float b_min, float* __restrict__ b)
+__global__ __launch_bounds__(256) void k_bfloor(Shape sh, float b_min, const float* __restrict__ src,
+                                                float* __restrict__ dst)
 {
     const long long pix = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (pix >= sh.P) return;
-    b[pix] = fmaxf(b[pix], b_min);
+    dst[pix] = fmaxf(src[pix], b_min);
+}
+
+// Both passes on 16 x 16 output tiles of one frame: the source region with an
+// rb-pixel circular halo is staged in LDS, the row pass fills the halo rows'
+// columns of the tile, the column pass writes the tile.  Per output the sums
+// run over the taps in the same order as the two separate passes, so the
+// result is the same to the bit.
+constexpr int BFT = 16;
+
+inline size_t bfilter_tile_floats(int rb)
+{
+    const size_t S = BFT + 2 * (size_t)rb;
+    return S * S + S * BFT + 2 * (size_t)rb + 1;
+}
+
+__device__ __forceinline__ int wrap_index(int v, int n)
+{
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+__global__ __launch_bounds__(BFT * BFT) void k_bfilter_tile(const float* __restrict__ w, int rb, Shape sh,
+                                                            float b_min, const float* __restrict__ src,
+                                                            float* __restrict__ dst, int tiles_x, int tiles_y)
+{
+    extern __shared__ float bf_lds[];
+    const int S = BFT + 2 * rb;
+    float* reg = bf_lds;              // [S][S]: rows i0 - rb .., columns j0 - rb .. (circular)
+    float* tmp = reg + S * S;         // [S][BFT]: row pass
+    float* wl = tmp + S * BFT;        // [2 rb + 1] taps
+    const int tile = (int)xcd_block(blockIdx.x, gridDim.x);
+    const int tpf = tiles_x * tiles_y;
+    const int fr = tile / tpf, tr = tile % tpf;
+    const int i0 = (tr / tiles_x) * BFT, j0 = (tr % tiles_x) * BFT;
+    const long long fbase = (long long)fr * sh.rows * sh.cols;
+    for (int k = threadIdx.x; k < 2 * rb + 1; k += BFT * BFT) wl[k] = w[k];
+    for (int x = threadIdx.x; x < S * S; x += BFT * BFT) {
+        const int ii = wrap_index(i0 - rb + x / S, sh.rows), jj = wrap_index(j0 - rb + x % S, sh.cols);
+        reg[x] = src[fbase + (long long)ii * sh.cols + jj];
+    }
+    __syncthreads();
+    for (int x = threadIdx.x; x < S * BFT; x += BFT * BFT) {
+        const int r = x / BFT, c = x % BFT;
+        const float* row = reg + r * S + c + rb;
+        float a = 0.f;
+        for (int d = -rb; d <= rb; ++d) a = fmaf(wl[d + rb], row[d], a);
+        tmp[x] = a;
+    }
+    __syncthreads();
+    const int ty = threadIdx.x / BFT, tx = threadIdx.x % BFT;
+    const int i = i0 + ty, j = j0 + tx;
+    if (i >= sh.rows || j >= sh.cols) return;
+    float a = 0.f;
+    for (int d = -rb; d <= rb; ++d) a = fmaf(wl[d + rb], tmp[(ty + rb + d) * BFT + tx], a);
+    dst[fbase + (long long)i * sh.cols + j] = fmaxf(a, b_min);
 }
 
 __global__ __launch_bounds__(256) void k_copy_state(Shape sh, DevState in, DevState out)
@@ -179,19 +262,30 @@ static inline unsigned nblk(long long n) { return (unsigned)((n + 255) / 256); }
 hipError_t launch_ifilter(const DevParams& p, const Shape& sh, DevState in, DevState out, hipStream_t st)
 {
     if (sh.P == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_ifilter, dim3(nblk(sh.P)), dim3(256), 0, st, p, sh, in, out);
+    const int tx = (sh.cols + IFT - 1) / IFT, ty = (sh.rows + IFT - 1) / IFT;
+    hipLaunchKernelGGL(k_ifilter_tile, dim3((unsigned)((long long)sh.F * tx * ty)), dim3(IFT * IFT), 0, st, p, sh,
+                       in, out, tx, ty);
     return hipGetLastError();
 }
 
-hipError_t launch_bfilter(const float* w, int rb, const Shape& sh, float b_min, float* b, float* tmp, hipStream_t st)
+hipError_t launch_bfilter(const float* w, int rb, const Shape& sh, float b_min, const float* src, float* dst,
+                          float* tmp, hipStream_t st)
 {
     if (sh.P == 0) return hipSuccess;
     if (rb <= 0) {
-        hipLaunchKernelGGL(k_bfloor, dim3(nblk(sh.P)), dim3(256), 0, st, sh, b_min, b);
+        hipLaunchKernelGGL(k_bfloor, dim3(nblk(sh.P)), dim3(256), 0, st, sh, b_min, src, dst);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(k_bfilter_rows, dim3(nblk(sh.P)), dim3(256), 0, st, w, rb, sh, b, tmp);
-    hipLaunchKernelGGL(k_bfilter_cols, dim3(nblk(sh.P)), dim3(256), 0, st, w, rb, sh, b_min, tmp, b);
+    const size_t lds = sizeof(float) * bfilter_tile_floats(rb);
+    if (lds <= 49152) {
+        const int tx = (sh.cols + BFT - 1) / BFT, ty = (sh.rows + BFT - 1) / BFT;
+        hipLaunchKernelGGL(k_bfilter_tile, dim3((unsigned)((long long)sh.F * tx * ty)), dim3(BFT * BFT), lds, st, w,
+                           rb, sh, b_min, src, dst, tx, ty);
+        return hipGetLastError();
+    }
+    // wide filters: the row pass into tmp, the column pass into dst
+    hipLaunchKernelGGL(k_bfilter_rows, dim3(nblk(sh.P)), dim3(256), 0, st, w, rb, sh, src, tmp);
+    hipLaunchKernelGGL(k_bfilter_cols, dim3(nblk(sh.P)), dim3(256), 0, st, w, rb, sh, b_min, tmp, dst);
     return hipGetLastError();
 }
 

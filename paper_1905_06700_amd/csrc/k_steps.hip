@@ -319,23 +319,30 @@ __global__ __launch_bounds__(256) void k_intensity_step(DevModel m, DevParams p,
     }
 }
 
+// The background step writes the new b to bdst (the state's own b, or a
+// second buffer the background filter reads); dead pixels keep their b.
 __global__ __launch_bounds__(256) void k_bg_step(DevModel m, DevParams p, Shape sh,
                                                  const uint32_t* __restrict__ off,
                                                  const uint32_t* __restrict__ ent,
-                                                 const float* __restrict__ gain, DevState s)
+                                                 const float* __restrict__ gain, DevState s, float* bdst)
 {
     __shared__ uint32_t lists[256 / LPP * STEP_LIST];
     uint32_t* list = lists + (threadIdx.x / LPP) * STEP_LIST;
     const long long P = sh.P;
     const Lane L = lane_setup(s, P, off, gain, false);
-    const float bb = L.live ? s.b[L.pix] : 1.f;
+    const float braw = L.pix < P ? s.b[L.pix] : 1.f;
+    const float bb = L.live ? braw : 1.f;
     float sz, shh[KM], shp[KM];
     accumulate(m, L.q, bb, L.live ? L.G : 1.f, ent, L.e0, L.e1, L.sub, list, sz, shh, shp);
     reduce_lanes(sz, shh, shp);
-    if (!L.live || L.sub != 0) return;
+    if (L.pix >= P || L.sub != 0) return;
+    if (!L.live) {
+        bdst[L.pix] = braw;
+        return;
+    }
     const float bt = (float)p.beta_b;
     const float v = bb * ((1.f - bt) + bt * sz / (float)m.T);
-    s.b[L.pix] = fmaxf(v, (float)p.b_min);
+    bdst[L.pix] = fmaxf(v, (float)p.b_min);
 }
 
 __global__ __launch_bounds__(256) void k_gradients(DevModel m, Shape sh, const uint32_t* __restrict__ off,
@@ -393,10 +400,11 @@ hipError_t launch_intensity_step(const DevModel& m, const DevParams& p, const Sh
 }
 
 hipError_t launch_bg_step(const DevModel& m, const DevParams& p, const Shape& sh, const uint32_t* off,
-                          const uint32_t* ent, const float* gain, DevState s, hipStream_t st)
+                          const uint32_t* ent, const float* gain, DevState s, float* bdst, hipStream_t st)
 {
     if (sh.P == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bg_step, dim3(blocks_for(sh.P * LPP, 256)), dim3(256), 0, st, m, p, sh, off, ent, gain, s);
+    hipLaunchKernelGGL(k_bg_step, dim3(blocks_for(sh.P * LPP, 256)), dim3(256), 0, st, m, p, sh, off, ent, gain, s,
+                       bdst ? bdst : s.b);
     return hipGetLastError();
 }
 

@@ -322,9 +322,10 @@ hipError_t launch_depth_step(const DevModel& m, const DevParams& p, const Shape&
 hipError_t launch_intensity_step(const DevModel& m, const DevParams& p, const Shape& sh,
                                  const uint32_t* off, const uint32_t* ent, const float* gain,
                                  DevState s, bool merge, hipStream_t st);
+// bdst: where the new background goes (nullptr: the state's own b)
 hipError_t launch_bg_step(const DevModel& m, const DevParams& p, const Shape& sh,
                           const uint32_t* off, const uint32_t* ent, const float* gain, DevState s,
-                          hipStream_t st);
+                          float* bdst, hipStream_t st);
 hipError_t launch_gradients(const DevModel& m, const DevParams& p, const Shape& sh,
                             const uint32_t* off, const uint32_t* ent, const float* gain,
                             DevState s, float* gt, float* gr, float* gb, hipStream_t st);
@@ -335,7 +336,9 @@ hipError_t launch_apss(const DevModel& m, const DevParams& p, const Shape& sh, D
 hipError_t launch_merge(const DevParams& p, const Shape& sh, DevState s, hipStream_t st);
 hipError_t launch_ifilter(const DevParams& p, const Shape& sh, DevState in, DevState out,
                           hipStream_t st);
-hipError_t launch_bfilter(const float* w, int rb, const Shape& sh, float b_min, float* b,
+// dst = the filtered src floored at b_min (src and dst distinct; tmp: P floats
+// for filters too wide for the tiled kernel)
+hipError_t launch_bfilter(const float* w, int rb, const Shape& sh, float b_min, const float* src, float* dst,
                           float* tmp, hipStream_t st);
 hipError_t launch_copy_state(const Shape& sh, DevState in, DevState out, hipStream_t st);
 

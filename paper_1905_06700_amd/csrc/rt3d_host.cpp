@@ -315,8 +315,10 @@ rt3d_status iterate(rt3d_ctx* c, const Shape& sh, const uint32_t* off, const uin
     // the in-pixel merge runs fused ahead of the intensity step
     RT3D_LAUNCH(c, RT3D_KERNEL_INTENSITY, st, launch_intensity_step(m, p, sh, off, ent, gain, cur, true, st));
     RT3D_LAUNCH(c, RT3D_KERNEL_IFILTER, st, launch_ifilter(p, sh, cur, A, st));
-    RT3D_LAUNCH(c, RT3D_KERNEL_BKG, st, launch_bg_step(m, p, sh, off, ent, gain, A, st));
-    RT3D_LAUNCH(c, RT3D_KERNEL_BFILTER, st, launch_bfilter(c->d_bw, c->rb, sh, (float)c->p.b_min, A.b, btmp, st));
+    // the background step writes btmp; the filter brings it back into A.b
+    RT3D_LAUNCH(c, RT3D_KERNEL_BKG, st, launch_bg_step(m, p, sh, off, ent, gain, A, btmp, st));
+    RT3D_LAUNCH(c, RT3D_KERNEL_BFILTER, st,
+                launch_bfilter(c->d_bw, c->rb, sh, (float)c->p.b_min, btmp, A.b, B.b, st));
     return RT3D_OK;
 }
 
@@ -904,13 +906,15 @@ rt3d_status rt3d_debug_step(rt3d_ctx* c, int32_t step, const uint32_t* off, cons
         RT3D_HIP(c, launch_intensity_step(m, p, sh, off, ent, gain, O, false, st));
         return RT3D_OK;
     case RT3D_STEP_BKG:
-        RT3D_HIP(c, launch_bg_step(m, p, sh, off, ent, gain, O, st));
+        RT3D_HIP(c, launch_bg_step(m, p, sh, off, ent, gain, O, nullptr, st));
         return RT3D_OK;
     case RT3D_STEP_BFILTER: {
         Workspace w;
         rt3d_status s = need_ws(c, sh.P, w);
         if (s != RT3D_OK) return s;
-        RT3D_HIP(c, launch_bfilter(c->d_bw, c->rb, sh, (float)c->p.b_min, O.b, w.btmp, st));
+        // filtered into the workspace, then back into the state
+        RT3D_HIP(c, launch_bfilter(c->d_bw, c->rb, sh, (float)c->p.b_min, O.b, w.btmp, w.B.b, st));
+        RT3D_HIP(c, hipMemcpyAsync(O.b, w.btmp, sizeof(float) * sh.P, hipMemcpyDeviceToDevice, st));
         return RT3D_OK;
     }
     case RT3D_STEP_ITERATION: {

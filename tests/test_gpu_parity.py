@@ -246,6 +246,27 @@ def test_iteration_merges_close_points_like_oracle():
     assert np.abs(sg.t - so.t)[lv].max() <= 1e-3
 
 
+@pytest.mark.parametrize("sigma_b", [0.0, 2.0, 12.0])
+def test_background_filter_widths(sigma_b):
+    """The background filter alone on three frames of 37 x 23 and two of 5 x 7
+    (smaller than the filter's reach, so the circular halo wraps more than
+    once): the floor only (sigma_b = 0), the tiled kernel (2) and the two-pass
+    kernels of wide filters (12, radius 48)."""
+    irf = synth.gaussian_irf(1.5, 9).probs
+    rng = np.random.default_rng(int(sigma_b * 10) + 3)
+    for F, rows, cols in ((3, 37, 23), (2, 5, 7)):
+        s0 = oracle.State(F, rows, cols, 4)
+        s0.b[:] = rng.gamma(2.0, 0.01, s0.npix)
+        s0.b[::17] = 0.0                         # below the floor
+        prm = dict(sigma_b=sigma_b, b_min=1e-3)
+        O = oracle.Oracle(oracle.Model(irf, 50), oracle.Params(**prm))
+        ctx = rt3d.Context(irf, 50, **prm)
+        so = O.bg_filter(s0.copy())
+        print(f"[gpu-parity] background filter sigma_b {sigma_b}: {F} x {rows} x {cols}", flush=True)
+        sg = device_to_oracle(ctx.step(rt3d.STEP_BFILTER, oracle_to_device(s0)), 4)
+        np.testing.assert_allclose(sg.b, so.b, rtol=1e-5, atol=1e-12)
+
+
 # ------------------------------------------------------------------ whole loop
 
 def _compare_final(sc, so, res, P):
