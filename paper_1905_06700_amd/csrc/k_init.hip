@@ -403,20 +403,51 @@ __device__ __forceinline__ void lds_search(const DevModel& m, const DevParams& p
         const bool accept = win > 0 && (long long)nwin >= p.n_min && d >= 0.0 && d * d >= k2 * bw;
         if (!accept) break;
         pk.push(bestt, a, c, (int)win);
-        // the peak claims the photons of its window: their counts drop to zero
+        // the peak claims the photons of its window: their counts drop to zero,
+        // and their terms leave the bounds (which stay exact sums over the
+        // unclaimed photons, so later rounds prune near the claimed peak)
         for (int x = x0 + lane; x < x1; x += 64) {
-            const int tb = ent_bin(E[x]);
-            if (tb >= a && tb <= c) E[x] &= 0xffff0000u;
+            const uint32_t v = E[x];
+            const int tb = ent_bin(v), z = ent_cnt(v);
+            if (tb >= a && tb <= c) {
+                E[x] = v & 0xffff0000u;
+                if (z > 0) {
+                    const int blo = max(0, tb + o - L + 1) / INIT_SB, bhi = min(T - 1, tb + o) / INIT_SB;
+                    const int* Mx = M + (tb + o - INIT_SB * bhi);
+                    for (int b = bhi; b >= blo; --b, Mx += INIT_SB)
+                        atomicSub(&bnd[b], __umul24((unsigned)z, (unsigned)*Mx));
+                }
+            }
         }
-        // forget the bests of blocks the new peak changes
+        wave_sync();
+        // blocks the new peak changes: tau that see its claimed bins (their
+        // bounds are recomputed) or fall under its suppression forget their
+        // best
         const int A0 = a + o - L + 1, A1 = c + o, S0 = bestt - m.wnms, S1 = bestt + m.wnms;
 #pragma unroll
         for (int s2 = 0; s2 < 2; ++s2) {
             const int b = lane + 64 * s2;
             const int ta = b << 6, tb = (b << 6) + 63;
-            if (b < nb && ((ta <= A1 && tb >= A0) || (ta <= S1 && tb >= S0))) cached[s2] = false;
+            const bool seen = ta <= A1 && tb >= A0;
+            if (b < nb && (seen || (ta <= S1 && tb >= S0))) cached[s2] = false;
+            if (b < nb && seen) {
+                uint32_t mx = 0;
+                int sub = NO_TAU;
+#pragma unroll
+                for (int q = 0; q < 64 / INIT_SB; ++q) {
+                    const int sb = b * (64 / INIT_SB) + q;
+                    if (sb < nbs) {
+                        const uint32_t u = bnd[sb];
+                        if (sub == NO_TAU || u > mx) {
+                            mx = u;
+                            sub = sb * INIT_SB;
+                        }
+                    }
+                }
+                bmx[s2] = mx;
+                bsub[s2] = sub;
+            }
         }
-        wave_sync();
     }
 }
 
