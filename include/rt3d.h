@@ -113,6 +113,17 @@ typedef struct rt3d_input {
     const uint16_t* ev_bin;
     uint32_t* ev_scratch;
     uint64_t n_events;
+    /* Frames of different sizes in one call (both NULL: every frame is rows x cols).
+     * Host arrays of `frames` entries: frame f is frame_rows[f] x frame_cols[f]
+     * pixels and its pixels follow those of frame f - 1 (pixel-major within the
+     * frame), in the histograms, the CSR, the gain, the output and the event
+     * pixel numbers alike; rows and cols are then ignored and P is the sum of
+     * the frames' pixels (the workspace must be sized for at least that many).
+     * Consecutive frames of one size are processed as one group.  E_INVALID for
+     * a zero or oversized frame, E_UNSUPPORTED with the learned denoiser when
+     * the sizes differ. */
+    const uint32_t* frame_rows;
+    const uint32_t* frame_cols;
 } rt3d_input;
 
 typedef struct rt3d_output {

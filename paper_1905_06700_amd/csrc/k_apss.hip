@@ -76,11 +76,11 @@ __global__ __launch_bounds__(ATX * ATY) void k_apss_tile(DevModel m, DevParams p
                                                        DevState out, int only_above, int tiles_x, int tiles_y)
 {
     extern __shared__ double apss_lds[];
-    const int R = p.apss_R, S = ATX + 2 * R, NS = S * (ATY + 2 * R);
+    const int R = p.apss_R, SX = ATX + 2 * R, NS = SX * (ATY + 2 * R);
     double* tl = apss_lds;                                      // [KM][NS] depths
     float* nl = reinterpret_cast<float*>(tl + KM * NS);         // [3][KM][NS] normals
     int* cl = reinterpret_cast<int*>(nl + 3 * KM * NS);         // [NS] counts (0 outside the frame)
-    const long long P = sh.P;
+    const long long S = sh.S;
     const int tile = (int)xcd_block(blockIdx.x, gridDim.x);
     const int tpf = tiles_x * tiles_y;
     const int fr = tile / tpf, tr = tile % tpf;
@@ -88,16 +88,16 @@ __global__ __launch_bounds__(ATX * ATY) void k_apss_tile(DevModel m, DevParams p
     const long long fbase = (long long)fr * sh.rows * sh.cols;
     // stage the tile and its halo (every slot, so no load waits on a count)
     for (int x = threadIdx.x; x < NS; x += ATX * ATY) {
-        const int i2 = i0 - R + x / S, j2 = j0 - R + x % S;
+        const int i2 = i0 - R + x / SX, j2 = j0 - R + x % SX;
         int c = 0;
         if (i2 >= 0 && i2 < sh.rows && j2 >= 0 && j2 < sh.cols) {
             const long long pp = fbase + (long long)i2 * sh.cols + j2;
             c = load_cnt(in.cnt, pp);
 #pragma unroll
             for (int k = 0; k < KM; ++k) {
-                tl[k * NS + x] = in.t[k * P + pp];
+                tl[k * NS + x] = in.t[k * S + pp];
 #pragma unroll
-                for (int a = 0; a < 3; ++a) nl[(a * KM + k) * NS + x] = in.n[(a * KM + k) * P + pp];
+                for (int a = 0; a < 3; ++a) nl[(a * KM + k) * NS + x] = in.n[(a * KM + k) * S + pp];
             }
         }
         cl[x] = c;
@@ -107,12 +107,12 @@ __global__ __launch_bounds__(ATX * ATY) void k_apss_tile(DevModel m, DevParams p
     const int i = i0 + ty, j = j0 + tx;
     if (i >= sh.rows || j >= sh.cols) return;
     const long long pix = fbase + (long long)i * sh.cols + j;
-    const int xc = (ty + R) * S + tx + R;
+    const int xc = (ty + R) * SX + tx + R;
     const int c = cl[xc];
     out.cnt[pix] = (uint8_t)c;
     out.b[pix] = in.b[pix];
 #pragma unroll
-    for (int k = 0; k < KM; ++k) out.r[k * P + pix] = in.r[k * P + pix];
+    for (int k = 0; k < KM; ++k) out.r[k * S + pix] = in.r[k * S + pix];
     const bool fit = !(only_above >= 0 && c <= only_above);
     const float h = (float)p.h_apss, h2 = h * h, inv_h2 = 1.f / h2;
     const float pxy = (float)p.p_xy;
@@ -129,7 +129,7 @@ __global__ __launch_bounds__(ATX * ATY) void k_apss_tile(DevModel m, DevParams p
                     const float yx = (float)dj * pxy;
                     const float dl = fmaf(yx, yx, yy * yy);
                     if (!(dl < h2)) continue;
-                    const int x = xc + di * S + dj;
+                    const int x = xc + di * SX + dj;
                     const int cc = cl[x];
                     for (int k2 = 0; k2 < cc; ++k2) {
                         const float yz = (float)((tl[k2 * NS + x] - tq) * dz);
@@ -158,9 +158,9 @@ __global__ __launch_bounds__(ATX * ATY) void k_apss_tile(DevModel m, DevParams p
         double tn = tq;
         float on[3] = {nl[(0 * KM + k) * NS + xc], nl[(1 * KM + k) * NS + xc], nl[(2 * KM + k) * NS + xc]};
         apss_project(fit && nn >= (float)p.m_min, W, Px, Py, Pz, Nx, Ny, Nz, PN, PP, h, h2, dz, tmax, tn, on);
-        out.t[k * P + pix] = tn;
+        out.t[k * S + pix] = tn;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) out.n[(a * KM + k) * P + pix] = on[a];
+        for (int a = 0; a < 3; ++a) out.n[(a * KM + k) * S + pix] = on[a];
     }
 }
 
@@ -170,7 +170,7 @@ static_assert(LPA == 8, "the lane sums below are sums over 8 lanes");
 __global__ __launch_bounds__(256) void k_apss(DevModel m, DevParams p, Shape sh, DevState in, DevState out,
                                               int only_above)
 {
-    const long long P = sh.P;
+    const long long P = sh.P, S = sh.S;
     const long long gid = (long long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     const long long pix = gid / LPA;
     const int sub = (int)(gid % LPA);
@@ -182,7 +182,7 @@ __global__ __launch_bounds__(256) void k_apss(DevModel m, DevParams p, Shape sh,
             out.cnt[pix] = (uint8_t)c;
             out.b[pix] = in.b[pix];
         }
-        if (sub < KM) out.r[sub * P + pix] = in.r[sub * P + pix];   // depth and normal: lane 0 below
+        if (sub < KM) out.r[sub * S + pix] = in.r[sub * S + pix];   // depth and normal: lane 0 below
     }
     const bool fit = live && !(only_above >= 0 && c <= only_above);
     const int per_frame = sh.rows * sh.cols;
@@ -196,7 +196,7 @@ __global__ __launch_bounds__(256) void k_apss(DevModel m, DevParams p, Shape sh,
     for (int k = 0; k < KM; ++k) {                  // every lane runs the slot (lane sums below)
         const bool act = fit && k < c;
         if (__ballot(live && k < c) == 0ull) break;  // no pixel of the wavefront has slot k
-        const double tq = act ? in.t[k * P + pq] : 0.0;
+        const double tq = act ? in.t[k * S + pq] : 0.0;
         float W = 0.f, Px = 0.f, Py = 0.f, Pz = 0.f, Nx = 0.f, Ny = 0.f, Nz = 0.f, PN = 0.f, PP = 0.f, nn = 0.f;
         if (act) {
             for (int widx = sub; widx < side * side; widx += LPA) {
@@ -208,15 +208,15 @@ __global__ __launch_bounds__(256) void k_apss(DevModel m, DevParams p, Shape sh,
                 const long long pp = (fr * sh.rows + i2) * sh.cols + j2;
                 const int cc = load_cnt(in.cnt, pp);
                 for (int k2 = 0; k2 < cc; ++k2) {
-                    const float yz = (float)((in.t[k2 * P + pp] - tq) * dz);
+                    const float yz = (float)((in.t[k2 * S + pp] - tq) * dz);
                     const float d2 = fmaf(yz, yz, dl);
                     if (!(d2 < h2)) continue;
                     float a = 1.f - d2 * inv_h2;
                     a = a * a;
                     const float w = a * a;
-                    const float nx = in.n[(0 * KM + k2) * P + pp];
-                    const float ny = in.n[(1 * KM + k2) * P + pp];
-                    const float nz = in.n[(2 * KM + k2) * P + pp];
+                    const float nx = in.n[(0 * KM + k2) * S + pp];
+                    const float ny = in.n[(1 * KM + k2) * S + pp];
+                    const float nz = in.n[(2 * KM + k2) * S + pp];
                     W += w;
                     Px = fmaf(w, yx, Px);
                     Py = fmaf(w, yy, Py);
@@ -243,12 +243,12 @@ __global__ __launch_bounds__(256) void k_apss(DevModel m, DevParams p, Shape sh,
         nn = oct_sum(nn);
         if (!live || sub != 0) continue;
         // lane 0 writes the slot: the projection when the fit succeeds, else the input
-        double tn = in.t[k * P + pix];
-        float on[3] = {in.n[(0 * KM + k) * P + pix], in.n[(1 * KM + k) * P + pix], in.n[(2 * KM + k) * P + pix]};
+        double tn = in.t[k * S + pix];
+        float on[3] = {in.n[(0 * KM + k) * S + pix], in.n[(1 * KM + k) * S + pix], in.n[(2 * KM + k) * S + pix]};
         apss_project(act && nn >= (float)p.m_min, W, Px, Py, Pz, Nx, Ny, Nz, PN, PP, h, h2, dz, tmax, tn, on);
-        out.t[k * P + pix] = tn;
+        out.t[k * S + pix] = tn;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) out.n[(a * KM + k) * P + pix] = on[a];
+        for (int a = 0; a < 3; ++a) out.n[(a * KM + k) * S + pix] = on[a];
     }
 }
 

@@ -30,7 +30,7 @@ __global__ __launch_bounds__(IFT * IFT) void k_ifilter_tile(DevParams p, Shape s
     __shared__ double tl[KM][IFS * IFS];
     __shared__ float rl[KM][IFS * IFS];
     __shared__ int cl[IFS * IFS];
-    const long long P = sh.P;
+    const long long P = sh.P, S = sh.S;
     const int tile = (int)xcd_block(blockIdx.x, gridDim.x);
     const int tpf = tiles_x * tiles_y;
     const int fr = tile / tpf, tr = tile % tpf;
@@ -44,8 +44,8 @@ __global__ __launch_bounds__(IFT * IFT) void k_ifilter_tile(DevParams p, Shape s
             c = load_cnt(in.cnt, pp);
 #pragma unroll
             for (int k = 0; k < KM; ++k) {
-                tl[k][x] = in.t[k * P + pp];
-                rl[k][x] = in.r[k * P + pp];
+                tl[k][x] = in.t[k * S + pp];
+                rl[k][x] = in.r[k * S + pp];
             }
         }
         cl[x] = c;
@@ -91,18 +91,18 @@ __global__ __launch_bounds__(IFT * IFT) void k_ifilter_tile(DevParams p, Shape s
         }
         const float rn = sum / (float)(1 + nside);
         if (rn < rmin) continue;
-        out.t[nk * P + pix] = tq;
-        out.r[nk * P + pix] = rn;
+        out.t[nk * S + pix] = tq;
+        out.r[nk * S + pix] = rn;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) out.n[(a * KM + nk) * P + pix] = in.n[(a * KM + k) * P + pix];
+        for (int a = 0; a < 3; ++a) out.n[(a * KM + nk) * S + pix] = in.n[(a * KM + k) * S + pix];
         ++nk;
     }
     for (int k = nk; k < KM; ++k) {
-        out.t[k * P + pix] = 0.0;
-        out.r[k * P + pix] = 0.f;
-        out.n[(0 * KM + k) * P + pix] = 0.f;
-        out.n[(1 * KM + k) * P + pix] = 0.f;
-        out.n[(2 * KM + k) * P + pix] = -1.f;
+        out.t[k * S + pix] = 0.0;
+        out.r[k * S + pix] = 0.f;
+        out.n[(0 * KM + k) * S + pix] = 0.f;
+        out.n[(1 * KM + k) * S + pix] = 0.f;
+        out.n[(2 * KM + k) * S + pix] = -1.f;
     }
     out.cnt[pix] = (uint8_t)nk;
     out.b[pix] = in.b[pix];

@@ -491,7 +491,7 @@ __global__ __launch_bounds__(64 * INIT_WAVES) void k_init(DevModel m, DevParams 
         qmax = (int)wave_max_u32((unsigned)qmax);
     }
 
-    const long long P = sh.P;
+    const long long P = sh.P, S = sh.S;
     const long long pix = (long long)xcd_block(blockIdx.x, gridDim.x) * INIT_WAVES + wv;
     if (pix >= P) return;                       // whole wavefront; no workgroup barriers below
     const int nb = (T + 63) >> 6;
@@ -499,11 +499,11 @@ __global__ __launch_bounds__(64 * INIT_WAVES) void k_init(DevModel m, DevParams 
     unsigned long long* ub = smem64 + (size_t)wv * ww + side * side;
 
     if (lane < KM) {
-        s.t[lane * P + pix] = 0.0;
-        s.r[lane * P + pix] = 0.f;
-        s.n[(0 * KM + lane) * P + pix] = 0.f;
-        s.n[(1 * KM + lane) * P + pix] = 0.f;
-        s.n[(2 * KM + lane) * P + pix] = -1.f;
+        s.t[lane * S + pix] = 0.0;
+        s.r[lane * S + pix] = 0.f;
+        s.n[(0 * KM + lane) * S + pix] = 0.f;
+        s.n[(1 * KM + lane) * S + pix] = 0.f;
+        s.n[(2 * KM + lane) * S + pix] = -1.f;
     }
     const int per_frame = sh.rows * sh.cols;
     const long long fr = pix / per_frame;
@@ -790,8 +790,8 @@ __global__ __launch_bounds__(64 * INIT_WAVES) void k_init(DevModel m, DevParams 
 #pragma unroll
     for (int k = 0; k < KM; ++k)
         if (k < nk) {
-            s.t[k * P + pix] = (double)kt[k];
-            s.r[k * P + pix] = kr[k];
+            s.t[k * S + pix] = (double)kt[k];
+            s.r[k * S + pix] = kr[k];
         }
     s.cnt[pix] = (uint8_t)nk;
     const double bown = den > 0 ? (double)num / (double)den : 0.0;
@@ -804,7 +804,7 @@ __global__ __launch_bounds__(64 * INIT_WAVES) void k_init(DevModel m, DevParams 
 // or (0, 0, -1) with fewer than 3 neighbours or a near-singular system.
 __global__ __launch_bounds__(256) void k_init_normals(DevParams p, Shape sh, DevState s)
 {
-    const long long P = sh.P;
+    const long long P = sh.P, S = sh.S;
     const long long pix = (long long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (pix >= P) return;
     const int c = load_cnt(s.cnt, pix);
@@ -815,7 +815,7 @@ __global__ __launch_bounds__(256) void k_init_normals(DevParams p, Shape sh, Dev
     const int R = p.apss_R;
     for (int k = 0; k < KM; ++k) {
         if (k >= c) break;
-        const double tq = s.t[k * P + pix];
+        const double tq = s.t[k * S + pix];
         double M00 = 0, M01 = 0, M02 = 0, M11 = 0, M12 = 0, M22 = 0, v0 = 0, v1 = 0, v2 = 0, W = 0;
         int nn = 0;
         for (int i2 = i - R; i2 <= i + R; ++i2) {
@@ -826,7 +826,7 @@ __global__ __launch_bounds__(256) void k_init_normals(DevParams p, Shape sh, Dev
                 const int cc = load_cnt(s.cnt, pp);
                 for (int k2 = 0; k2 < cc; ++k2) {
                     const double x = (j2 - j) * p.p_xy, y = (i2 - i) * p.p_xy;
-                    const double z = (s.t[k2 * P + pp] - tq) * p.dz;
+                    const double z = (s.t[k2 * S + pp] - tq) * p.dz;
                     const double d2 = x * x + y * y + z * z;
                     if (!(d2 < h2)) continue;
                     double a = 1.0 - d2 / h2;
@@ -857,9 +857,9 @@ __global__ __launch_bounds__(256) void k_init_normals(DevParams p, Shape sh, Dev
                 nz = (float)(-1.0 / nrm);
             }
         }
-        s.n[(0 * KM + k) * P + pix] = nx;
-        s.n[(1 * KM + k) * P + pix] = ny;
-        s.n[(2 * KM + k) * P + pix] = nz;
+        s.n[(0 * KM + k) * S + pix] = nx;
+        s.n[(1 * KM + k) * S + pix] = ny;
+        s.n[(2 * KM + k) * S + pix] = nz;
     }
 }
 

@@ -50,9 +50,14 @@ struct DevState {
     float*   b;
 };
 
+// F frames of rows x cols pixels, P = F * rows * cols.  S is the stride of the
+// state's slot planes: P when the state holds these pixels alone, more when
+// they are one group of a batch of unevenly sized frames (the state pointers
+// then point at the group's first pixel).
 struct Shape {
     int F, rows, cols;
-    long long P;    // F * rows * cols
+    long long P;
+    long long S;
 };
 
 // ---------------------------------------------------------------------------

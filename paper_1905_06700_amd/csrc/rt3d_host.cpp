@@ -255,6 +255,7 @@ Workspace carve_ctx(const rt3d_ctx* c, uint8_t* base, long long P, uint64_t E, u
         sh.cols = (int)cols;
         sh.F = (int)(P / ((long long)rows * cols));
         sh.P = P;
+        sh.S = P;
         groups = cnn_wgrad_groups(sh);
     }
     return carve(base, P, E, uses_cnn(c), groups);
@@ -288,19 +289,43 @@ Shape shape_of(uint32_t F, uint32_t rows, uint32_t cols)
     sh.rows = (int)rows;
     sh.cols = (int)cols;
     sh.P = (long long)F * rows * cols;
+    sh.S = sh.P;
     return sh;
 }
 
+// A run of consecutive frames of one size within a batch: its first pixel and
+// its shape (slot stride = the whole batch's pixel count).
+struct Group {
+    long long base;
+    Shape sh;
+};
+
+// The state of a group: every array advanced to the group's first pixel.
+DevState state_at(DevState s, long long base)
+{
+    s.t += base;
+    s.r += base;
+    s.n += base;
+    s.cnt += base;
+    s.b += base;
+    return s;
+}
+
 // One iteration of the loop on state A (in/out) with B as the second buffer.
-rt3d_status iterate(rt3d_ctx* c, const Shape& sh, const uint32_t* off, const uint32_t* ent, const float* gain,
-                    DevState A, DevState B, float* btmp, const CnnBuffers* cnn, hipStream_t st)
+// Per-pixel steps run once over the batch (sh); steps that read neighbouring
+// pixels run once per group of equally sized frames.
+rt3d_status iterate(rt3d_ctx* c, const Shape& sh, const std::vector<Group>& groups, const uint32_t* off,
+                    const uint32_t* ent, const float* gain, DevState A, DevState B, float* btmp,
+                    const CnnBuffers* cnn, hipStream_t st)
 {
     const DevModel m = dev_model(c);
     const DevParams p = dev_params(c);
     RT3D_LAUNCH(c, RT3D_KERNEL_DEPTH, st, launch_depth_step(m, p, sh, off, ent, gain, A, st));
     DevState cur = A;
     if (c->p.denoiser == RT3D_DENOISE_APSS) {
-        RT3D_LAUNCH(c, RT3D_KERNEL_APSS, st, launch_apss(m, p, sh, A, B, -1, st));
+        for (const Group& g : groups)
+            RT3D_LAUNCH(c, RT3D_KERNEL_APSS, st,
+                        launch_apss(m, p, g.sh, state_at(A, g.base), state_at(B, g.base), -1, st));
         cur = B;
     } else if (c->p.denoiser == RT3D_DENOISE_CNN) {
         // APSS only for pixels holding more points than the network's three slots
@@ -314,11 +339,15 @@ rt3d_status iterate(rt3d_ctx* c, const Shape& sh, const uint32_t* off, const uin
     }
     // the in-pixel merge runs fused ahead of the intensity step
     RT3D_LAUNCH(c, RT3D_KERNEL_INTENSITY, st, launch_intensity_step(m, p, sh, off, ent, gain, cur, true, st));
-    RT3D_LAUNCH(c, RT3D_KERNEL_IFILTER, st, launch_ifilter(p, sh, cur, A, st));
+    for (const Group& g : groups)
+        RT3D_LAUNCH(c, RT3D_KERNEL_IFILTER, st,
+                    launch_ifilter(p, g.sh, state_at(cur, g.base), state_at(A, g.base), st));
     // the background step writes btmp; the filter brings it back into A.b
     RT3D_LAUNCH(c, RT3D_KERNEL_BKG, st, launch_bg_step(m, p, sh, off, ent, gain, A, btmp, st));
-    RT3D_LAUNCH(c, RT3D_KERNEL_BFILTER, st,
-                launch_bfilter(c->d_bw, c->rb, sh, (float)c->p.b_min, btmp, A.b, B.b, st));
+    for (const Group& g : groups)
+        RT3D_LAUNCH(c, RT3D_KERNEL_BFILTER, st,
+                    launch_bfilter(c->d_bw, c->rb, g.sh, (float)c->p.b_min, btmp + g.base, A.b + g.base,
+                                   B.b + g.base, st));
     return RT3D_OK;
 }
 
@@ -695,11 +724,42 @@ rt3d_status rt3d_reconstruct(rt3d_ctx* c, const rt3d_input* in, rt3d_output* out
     if (!c) return RT3D_E_INVALID;
     if (!in || in->struct_size != sizeof(rt3d_input)) return fail(c, RT3D_E_INVALID, "input NULL or struct_size mismatch");
     if (!out || out->struct_size != sizeof(rt3d_output)) return fail(c, RT3D_E_INVALID, "output NULL or struct_size mismatch");
-    if (!shape_ok(in->frames, in->rows, in->cols))
-        return fail(c, RT3D_E_INVALID, "frames x rows x cols must be in 1 .. 2^31-1");
     if (!out->pt_off || !out->depth || !out->intensity || !out->background || out->capacity == 0)
         return fail(c, RT3D_E_INVALID, "output pointers NULL or capacity 0");
-    const Shape sh = shape_of(in->frames, in->rows, in->cols);
+    // frames and their groups of equal size (one group when every frame is rows x cols)
+    Shape sh;
+    std::vector<Group> groups;
+    if (in->frame_rows || in->frame_cols) {
+        if (!in->frame_rows || !in->frame_cols || in->frames == 0)
+            return fail(c, RT3D_E_INVALID, "frame_rows and frame_cols go together, with frames >= 1");
+        long long P = 0;
+        for (uint32_t f = 0; f < in->frames; ++f) {
+            const uint32_t r = in->frame_rows[f], q = in->frame_cols[f];
+            if (!shape_ok(1, r, q)) return fail(c, RT3D_E_INVALID, "a frame's rows x cols must be in 1 .. 2^31-1");
+            if (!groups.empty() && groups.back().sh.rows == (int)r && groups.back().sh.cols == (int)q) {
+                Shape& g = groups.back().sh;
+                ++g.F;
+                g.P += (long long)r * q;
+            } else {
+                Group g;
+                g.base = P;
+                g.sh = shape_of(1, r, q);
+                groups.push_back(g);
+            }
+            P += (long long)r * q;
+            if (P >= (1ll << 31)) return fail(c, RT3D_E_INVALID, "the frames' pixels must total below 2^31");
+        }
+        for (Group& g : groups) g.sh.S = P;
+        sh = shape_of(1, 1, (uint32_t)P);
+        if (groups.size() > 1 && c->p.denoiser == RT3D_DENOISE_CNN)
+            return fail(c, RT3D_E_UNSUPPORTED, "the learned denoiser needs frames of one size");
+    } else {
+        if (!shape_ok(in->frames, in->rows, in->cols))
+            return fail(c, RT3D_E_INVALID, "frames x rows x cols must be in 1 .. 2^31-1");
+        sh = shape_of(in->frames, in->rows, in->cols);
+        groups.push_back(Group{0, sh});
+    }
+    if (groups.size() == 1) sh = groups[0].sh;
     Workspace w;
     rt3d_status s = need_ws(c, sh.P, w);
     if (s != RT3D_OK) return s;
@@ -735,10 +795,14 @@ rt3d_status rt3d_reconstruct(rt3d_ctx* c, const rt3d_input* in, rt3d_output* out
     c->last_P = sh.P;
     const DevModel m = dev_model(c);
     const DevParams p = dev_params(c);
-    RT3D_LAUNCH(c, RT3D_KERNEL_INIT, st, launch_init(m, p, sh, off, ent, in->gain, w.A, w.err, st));
-    RT3D_LAUNCH(c, RT3D_KERNEL_NORMALS, st, launch_init_normals(p, sh, w.A, st));
+    for (const Group& g : groups)
+        RT3D_LAUNCH(c, RT3D_KERNEL_INIT, st,
+                    launch_init(m, p, g.sh, off + g.base, ent, in->gain ? in->gain + g.base : nullptr,
+                                state_at(w.A, g.base), w.err, st));
+    for (const Group& g : groups)
+        RT3D_LAUNCH(c, RT3D_KERNEL_NORMALS, st, launch_init_normals(p, g.sh, state_at(w.A, g.base), st));
     for (int it = 0; it < c->p.n_iter; ++it) {
-        s = iterate(c, sh, off, ent, in->gain, w.A, w.B, w.btmp, &w.cnn, st);
+        s = iterate(c, sh, groups, off, ent, in->gain, w.A, w.B, w.btmp, &w.cnn, st);
         if (s != RT3D_OK) return s;
     }
     RT3D_LAUNCH(c, RT3D_KERNEL_OUTPUT, st, launch_output(sh, w.A, out, w.counts, w.partial, w.err, st));
@@ -921,7 +985,7 @@ rt3d_status rt3d_debug_step(rt3d_ctx* c, int32_t step, const uint32_t* off, cons
         Workspace w;
         rt3d_status s = need_ws(c, sh.P, w);
         if (s != RT3D_OK) return s;
-        return iterate(c, sh, off, ent, gain, O, w.B, w.btmp, &w.cnn, st);
+        return iterate(c, sh, std::vector<Group>{Group{0, sh}}, off, ent, gain, O, w.B, w.btmp, &w.cnn, st);
     }
     default:
         return fail(c, RT3D_E_INVALID, "unknown step");

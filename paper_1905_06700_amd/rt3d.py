@@ -62,7 +62,7 @@ class Input(C.Structure):
                 ("rows", C.c_uint32), ("cols", C.c_uint32), ("hist", C.c_void_p),
                 ("off", C.c_void_p), ("ent", C.c_void_p), ("gain", C.c_void_p),
                 ("ev_pixel", C.c_void_p), ("ev_bin", C.c_void_p), ("ev_scratch", C.c_void_p),
-                ("n_events", C.c_uint64)]
+                ("n_events", C.c_uint64), ("frame_rows", C.c_void_p), ("frame_cols", C.c_void_p)]
 
 
 class Output(C.Structure):
@@ -285,10 +285,16 @@ class Context:
                       torch.zeros(P, dtype=torch.float32, device=dev))
 
     def _io(self, out: Result, frames: int, rows: int, cols: int, hist=None, off=None, ent=None, gain=None,
-            events=None):
+            events=None, frame_shapes=None):
         inp = Input()
         inp.struct_size = C.sizeof(Input)
         inp.frames, inp.rows, inp.cols = frames, rows, cols
+        if frame_shapes is not None:
+            assert len(frame_shapes) == frames
+            fr = (C.c_uint32 * frames)(*[int(r) for r, _ in frame_shapes])
+            fc = (C.c_uint32 * frames)(*[int(q) for _, q in frame_shapes])
+            inp.frame_rows, inp.frame_cols = C.addressof(fr), C.addressof(fc)
+            inp._shape_arrays = (fr, fc)           # alive while the call reads them
         if hist is not None:
             assert hist.dtype == torch.uint16 or hist.dtype == torch.int16
             assert hist.is_cuda and hist.is_contiguous()
@@ -313,17 +319,19 @@ class Context:
         return inp, o
 
     def reconstruct_into(self, out: Result, frames: int, rows: int, cols: int, hist=None, off=None,
-                         ent=None, gain=None, events=None):
+                         ent=None, gain=None, events=None, frame_shapes=None):
         """Enqueue one reconstruction on the current torch stream (no sync).
-        Input: hist, or (off, ent), or events = (pixel int32, bin int16, scratch int32)."""
-        inp, o = self._io(out, frames, rows, cols, hist, off, ent, gain, events)
+        Input: hist, or (off, ent), or events = (pixel int32, bin int16, scratch int32).
+        frame_shapes: [(rows, cols)] per frame for frames of different sizes, whose
+        pixels follow one another (rows and cols are then ignored)."""
+        inp, o = self._io(out, frames, rows, cols, hist, off, ent, gain, events, frame_shapes)
         self._check(lib().rt3d_reconstruct(self._h, C.byref(inp), C.byref(o), _stream()))
         return out
 
     def graph(self, out: Result, frames: int, rows: int, cols: int, hist=None, off=None, ent=None, gain=None,
-              events=None) -> "Graph":
+              events=None, frame_shapes=None) -> "Graph":
         """Record reconstruct_into with these buffers as a replayable graph."""
-        inp, o = self._io(out, frames, rows, cols, hist, off, ent, gain, events)
+        inp, o = self._io(out, frames, rows, cols, hist, off, ent, gain, events, frame_shapes)
         h = C.c_void_p()
         self._check(lib().rt3d_graph_create(self._h, C.byref(inp), C.byref(o), C.byref(h)))
         return Graph(self, h, (out, hist, off, ent, gain, events))
