@@ -160,6 +160,53 @@ def small_frames(F=64, reps=5):
     return res
 
 
+def uneven_frames(reps=3):
+    """Eight scenes of different sizes (sides 48 .. 160 pixels, 1024 bins,
+    head-shaped generator with the config-2 IRF, 3 signal photons/px at SBR
+    0.5): one call over all of them (neighbour steps per size group) against
+    one call per scene, back to back on the stream."""
+    import numpy as np
+    import torch
+
+    from paper_1905_06700_amd import rt3d, synth
+
+    sides = [48, 64, 80, 96, 112, 128, 144, 160]
+    T = 1024
+    scs = [synth.head_scene(64 + k, rows=n, cols=n, T=T, signal=3.0, sbr=0.5) for k, n in enumerate(sides)]
+    m = scs[0].meta
+    ctx = rt3d.Context(scs[0].irf.probs, T, dz=m["dz"], r_min=m["r_min"], r_init=m["r_init"], k_init=m["k_init"])
+    Zs = [torch.from_numpy(np.ascontiguousarray(sc.Z).view(np.int16)).cuda() for sc in scs]
+    Z = torch.cat([z.reshape(-1, T) for z in Zs]).contiguous()
+    P = int(Z.shape[0])
+    ctx.workspace(1, 1, P, P * 64)
+    out = ctx.make_output(P)
+    outs = [ctx.make_output(n * n) for n in sides]
+    shapes = [(n, n) for n in sides]
+
+    def one_call():
+        ctx.reconstruct_into(out, len(sides), 1, 1, hist=Z, frame_shapes=shapes)
+
+    def per_scene():
+        for n, z, o in zip(sides, Zs, outs):
+            ctx.reconstruct_into(o, 1, n, n, hist=z)
+
+    res = {"workload": f"8 scenes of {sides[0]}^2 .. {sides[-1]}^2 pixels x {T} bins ({P} pixels), one call "
+                       "against one call per scene"}
+    for name, run in (("one_call", one_call), ("per_scene", per_scene)):
+        run()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            run()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        res[f"ms_{name}"] = round(ms, 3)
+        res[f"scenes_per_s_{name}"] = round(len(sides) / (ms / 1e3), 1)
+    return res
+
+
 def learned_vs_apss(n_train=4, n_eval=4, steps=300, rows=256, cols=256, bins=1024):
     """Learned denoiser against plain APSS on multi-layer scenes: train on the
     GPU (the library's forward/backward kernels), then time and score both on
@@ -386,7 +433,7 @@ def main():
         "gbin_per_s": round(gbin, 2), "photon_bins_per_s": round(pbin, 1),
         "active_entries_per_frame": E // F, "points_per_frame": pts // F,
         "single_frame_latency_ms": round(latency_ms, 3), "single_frame_latency_graph_ms": round(latency_graph_ms, 3),
-        "small_frames": small_frames(), "wall_s": round(wall, 3),
+        "small_frames": small_frames(), "uneven_frames": uneven_frames(), "wall_s": round(wall, 3),
         "roofline": roofline, "kernels": kernels, "cpu_baseline": cpu,
         "learned_vs_apss": None if args.no_learned else learned_vs_apss(),
         "paper_context": {"frames_per_s": 76.9, "ms_per_frame": 13, "hardware": "NVIDIA Titan Xp",

@@ -62,7 +62,7 @@ __device__ __forceinline__ void apss_project(bool ok, float W, float Px, float P
     }
 }
 
-constexpr int ATX = 16, ATY = 16;   // tile of the LDS variant: columns, rows
+constexpr int ATX = TILE, ATY = TILE;   // tile of the LDS variant: columns, rows
 
 // LDS bytes of a staged tile with an R-pixel halo: per pixel KM depths (FP64),
 // 3 x KM normal components and the count.
@@ -72,16 +72,22 @@ inline size_t apss_tile_bytes(int R)
     return SX * SY * (KM * sizeof(double) + 3 * KM * sizeof(float) + sizeof(int));
 }
 
-__global__ __launch_bounds__(ATX * ATY) void k_apss_tile(DevModel m, DevParams p, Shape sh, DevState in,
-                                                       DevState out, int only_above, int tiles_x, int tiles_y)
+__global__ __launch_bounds__(ATX * ATY) void k_apss_tile(DevModel m, DevParams p, Tiles tg, DevState in,
+                                                       DevState out, int only_above)
 {
     extern __shared__ double apss_lds[];
     const int R = p.apss_R, SX = ATX + 2 * R, NS = SX * (ATY + 2 * R);
     double* tl = apss_lds;                                      // [KM][NS] depths
     float* nl = reinterpret_cast<float*>(tl + KM * NS);         // [3][KM][NS] normals
     int* cl = reinterpret_cast<int*>(nl + 3 * KM * NS);         // [NS] counts (0 outside the frame)
+    const int tile0 = (int)xcd_block(blockIdx.x, gridDim.x);
+    const int g = tile_group(tg, tile0);
+    const Shape sh = group_shape(tg, g);
+    in = state_at(in, tg.base[g]);
+    out = state_at(out, tg.base[g]);
     const long long S = sh.S;
-    const int tile = (int)xcd_block(blockIdx.x, gridDim.x);
+    const int tile = tile0 - tg.tile0[g];
+    const int tiles_x = (sh.cols + ATX - 1) / ATX, tiles_y = (sh.rows + ATY - 1) / ATY;
     const int tpf = tiles_x * tiles_y;
     const int fr = tile / tpf, tr = tile % tpf;
     const int i0 = (tr / tiles_x) * ATY, j0 = (tr % tiles_x) * ATX;
@@ -279,21 +285,29 @@ __global__ __launch_bounds__(256) void k_merge(DevParams p, Shape sh, DevState s
     store_points(s, P, pix, t, r, nx, ny, nz, c);
 }
 
+hipError_t launch_apss_tiles(const DevModel& m, const DevParams& p, const Tiles& tg, DevState in, DevState out,
+                             int only_above, hipStream_t st)
+{
+    if (tg.n == 0 || tg.tile0[tg.n] == 0) return hipSuccess;
+    const size_t lds = apss_tile_bytes(p.apss_R);
+    if (lds <= 65536) {
+        hipLaunchKernelGGL(k_apss_tile, dim3((unsigned)tg.tile0[tg.n]), dim3(ATX * ATY), lds, st, m, p, tg, in, out,
+                           only_above);
+        return hipGetLastError();
+    }
+    for (int g = 0; g < tg.n; ++g) {
+        const Shape sh = group_shape(tg, g);
+        hipLaunchKernelGGL(k_apss, dim3((unsigned)((sh.P * LPA + 255) / 256)), dim3(256), 0, st, m, p, sh,
+                           state_at(in, tg.base[g]), state_at(out, tg.base[g]), only_above);
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_apss(const DevModel& m, const DevParams& p, const Shape& sh, DevState in, DevState out,
                        int only_above, hipStream_t st)
 {
     if (sh.P == 0) return hipSuccess;
-    const size_t lds = apss_tile_bytes(p.apss_R);
-    if (lds <= 65536) {
-        const int tx = (sh.cols + ATX - 1) / ATX, ty = (sh.rows + ATY - 1) / ATY;
-        const long long nt = (long long)sh.F * tx * ty;
-        hipLaunchKernelGGL(k_apss_tile, dim3((unsigned)nt), dim3(ATX * ATY), lds, st, m, p, sh, in, out, only_above,
-                           tx, ty);
-    } else {
-        hipLaunchKernelGGL(k_apss, dim3((unsigned)((sh.P * LPA + 255) / 256)), dim3(256), 0, st, m, p, sh, in, out,
-                           only_above);
-    }
-    return hipGetLastError();
+    return launch_apss_tiles(m, p, tiles_of(sh), in, out, only_above, st);
 }
 
 hipError_t launch_merge(const DevParams& p, const Shape& sh, DevState s, hipStream_t st)

@@ -21,17 +21,22 @@ namespace rt3d {
 // Intensity filter and threshold on 16 x 16 pixel tiles of one frame: the
 // tile's depths, intensities and counts with a one-pixel halo are staged in
 // LDS, then one thread per pixel filters its points.
-constexpr int IFT = 16;
+constexpr int IFT = TILE;
 constexpr int IFS = IFT + 2;
 
-__global__ __launch_bounds__(IFT * IFT) void k_ifilter_tile(DevParams p, Shape sh, DevState in, DevState out,
-                                                            int tiles_x, int tiles_y)
+__global__ __launch_bounds__(IFT * IFT) void k_ifilter_tile(DevParams p, Tiles tg, DevState in, DevState out)
 {
     __shared__ double tl[KM][IFS * IFS];
     __shared__ float rl[KM][IFS * IFS];
     __shared__ int cl[IFS * IFS];
-    const long long P = sh.P, S = sh.S;
-    const int tile = (int)xcd_block(blockIdx.x, gridDim.x);
+    const int tile0 = (int)xcd_block(blockIdx.x, gridDim.x);
+    const int g = tile_group(tg, tile0);
+    const Shape sh = group_shape(tg, g);
+    in = state_at(in, tg.base[g]);
+    out = state_at(out, tg.base[g]);
+    const long long S = sh.S;
+    const int tile = tile0 - tg.tile0[g];
+    const int tiles_x = (sh.cols + IFT - 1) / IFT, tiles_y = (sh.rows + IFT - 1) / IFT;
     const int tpf = tiles_x * tiles_y;
     const int fr = tile / tpf, tr = tile % tpf;
     const int i0 = (tr / tiles_x) * IFT, j0 = (tr % tiles_x) * IFT;
@@ -156,7 +161,7 @@ __global__ __launch_bounds__(256) void k_bfloor(Shape sh, float b_min, const flo
 // columns of the tile, the column pass writes the tile.  Per output the sums
 // run over the taps in the same order as the two separate passes, so the
 // result is the same to the bit.
-constexpr int BFT = 16;
+constexpr int BFT = TILE;
 
 inline size_t bfilter_tile_floats(int rb)
 {
@@ -170,16 +175,22 @@ __device__ __forceinline__ int wrap_index(int v, int n)
     return v < 0 ? v + n : v;
 }
 
-__global__ __launch_bounds__(BFT * BFT) void k_bfilter_tile(const float* __restrict__ w, int rb, Shape sh,
+__global__ __launch_bounds__(BFT * BFT) void k_bfilter_tile(const float* __restrict__ w, int rb, Tiles tg,
                                                             float b_min, const float* __restrict__ src,
-                                                            float* __restrict__ dst, int tiles_x, int tiles_y)
+                                                            float* __restrict__ dst)
 {
     extern __shared__ float bf_lds[];
     const int S = BFT + 2 * rb;
     float* reg = bf_lds;              // [S][S]: rows i0 - rb .., columns j0 - rb .. (circular)
     float* tmp = reg + S * S;         // [S][BFT]: row pass
     float* wl = tmp + S * BFT;        // [2 rb + 1] taps
-    const int tile = (int)xcd_block(blockIdx.x, gridDim.x);
+    const int tile0 = (int)xcd_block(blockIdx.x, gridDim.x);
+    const int g = tile_group(tg, tile0);
+    const Shape sh = group_shape(tg, g);
+    src += tg.base[g];
+    dst += tg.base[g];
+    const int tile = tile0 - tg.tile0[g];
+    const int tiles_x = (sh.cols + BFT - 1) / BFT, tiles_y = (sh.rows + BFT - 1) / BFT;
     const int tpf = tiles_x * tiles_y;
     const int fr = tile / tpf, tr = tile % tpf;
     const int i0 = (tr / tiles_x) * BFT, j0 = (tr % tiles_x) * BFT;
@@ -259,12 +270,40 @@ __global__ __launch_bounds__(256) void k_out_pack(Shape sh, DevState s, const ui
 
 static inline unsigned nblk(long long n) { return (unsigned)((n + 255) / 256); }
 
+hipError_t launch_ifilter_tiles(const DevParams& p, const Tiles& tg, DevState in, DevState out, hipStream_t st)
+{
+    if (tg.n == 0 || tg.tile0[tg.n] == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ifilter_tile, dim3((unsigned)tg.tile0[tg.n]), dim3(IFT * IFT), 0, st, p, tg, in, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_ifilter(const DevParams& p, const Shape& sh, DevState in, DevState out, hipStream_t st)
 {
     if (sh.P == 0) return hipSuccess;
-    const int tx = (sh.cols + IFT - 1) / IFT, ty = (sh.rows + IFT - 1) / IFT;
-    hipLaunchKernelGGL(k_ifilter_tile, dim3((unsigned)((long long)sh.F * tx * ty)), dim3(IFT * IFT), 0, st, p, sh,
-                       in, out, tx, ty);
+    return launch_ifilter_tiles(p, tiles_of(sh), in, out, st);
+}
+
+hipError_t launch_bfilter_tiles(const float* w, int rb, const Tiles& tg, float b_min, const float* src, float* dst,
+                                float* tmp, hipStream_t st)
+{
+    if (tg.n == 0 || tg.tile0[tg.n] == 0) return hipSuccess;
+    const size_t lds = sizeof(float) * bfilter_tile_floats(rb);
+    if (rb > 0 && lds <= 49152) {
+        hipLaunchKernelGGL(k_bfilter_tile, dim3((unsigned)tg.tile0[tg.n]), dim3(BFT * BFT), lds, st, w, rb, tg, b_min,
+                           src, dst);
+        return hipGetLastError();
+    }
+    for (int g = 0; g < tg.n; ++g) {
+        const Shape sh = group_shape(tg, g);
+        const long long b = tg.base[g];
+        if (rb <= 0) {
+            hipLaunchKernelGGL(k_bfloor, dim3(nblk(sh.P)), dim3(256), 0, st, sh, b_min, src + b, dst + b);
+        } else {
+            // wide filters: the row pass into tmp, the column pass into dst
+            hipLaunchKernelGGL(k_bfilter_rows, dim3(nblk(sh.P)), dim3(256), 0, st, w, rb, sh, src + b, tmp + b);
+            hipLaunchKernelGGL(k_bfilter_cols, dim3(nblk(sh.P)), dim3(256), 0, st, w, rb, sh, b_min, tmp + b, dst + b);
+        }
+    }
     return hipGetLastError();
 }
 
@@ -272,21 +311,7 @@ hipError_t launch_bfilter(const float* w, int rb, const Shape& sh, float b_min, 
                           float* tmp, hipStream_t st)
 {
     if (sh.P == 0) return hipSuccess;
-    if (rb <= 0) {
-        hipLaunchKernelGGL(k_bfloor, dim3(nblk(sh.P)), dim3(256), 0, st, sh, b_min, src, dst);
-        return hipGetLastError();
-    }
-    const size_t lds = sizeof(float) * bfilter_tile_floats(rb);
-    if (lds <= 49152) {
-        const int tx = (sh.cols + BFT - 1) / BFT, ty = (sh.rows + BFT - 1) / BFT;
-        hipLaunchKernelGGL(k_bfilter_tile, dim3((unsigned)((long long)sh.F * tx * ty)), dim3(BFT * BFT), lds, st, w,
-                           rb, sh, b_min, src, dst, tx, ty);
-        return hipGetLastError();
-    }
-    // wide filters: the row pass into tmp, the column pass into dst
-    hipLaunchKernelGGL(k_bfilter_rows, dim3(nblk(sh.P)), dim3(256), 0, st, w, rb, sh, src, tmp);
-    hipLaunchKernelGGL(k_bfilter_cols, dim3(nblk(sh.P)), dim3(256), 0, st, w, rb, sh, b_min, tmp, dst);
-    return hipGetLastError();
+    return launch_bfilter_tiles(w, rb, tiles_of(sh), b_min, src, dst, tmp, st);
 }
 
 hipError_t launch_copy_state(const Shape& sh, DevState in, DevState out, hipStream_t st)

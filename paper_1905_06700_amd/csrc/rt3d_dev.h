@@ -60,6 +60,74 @@ struct Shape {
     long long S;
 };
 
+// The state of a group of a batch: every array advanced to its first pixel.
+__host__ __device__ inline DevState state_at(DevState s, long long base)
+{
+    s.t += base;
+    s.r += base;
+    s.n += base;
+    s.cnt += base;
+    s.b += base;
+    return s;
+}
+
+// Groups of equally sized frames that one launch of a tiled kernel covers
+// (the kernels that read neighbouring pixels work on 16 x 16 pixel tiles of
+// one frame): group g holds F[g] frames of rows[g] x cols[g] pixels from pixel
+// base[g] on, and owns tiles tile0[g] .. tile0[g + 1] - 1 of the grid.
+constexpr int TILE = 16;
+constexpr int TILE_GROUPS = 16;
+struct Tiles {
+    int n;
+    long long S;                       // slot stride of the state
+    long long base[TILE_GROUPS];
+    int F[TILE_GROUPS], rows[TILE_GROUPS], cols[TILE_GROUPS];
+    int tile0[TILE_GROUPS + 1];
+};
+
+// Group of a tile (wave-uniform: the tile is the workgroup's).
+__device__ __forceinline__ int tile_group(const Tiles& tg, int tile)
+{
+    int g = 0;
+    while (g + 1 < tg.n && tile >= tg.tile0[g + 1]) ++g;
+    return g;
+}
+
+__host__ __device__ inline Shape group_shape(const Tiles& tg, int g)
+{
+    Shape sh;
+    sh.F = tg.F[g];
+    sh.rows = tg.rows[g];
+    sh.cols = tg.cols[g];
+    sh.P = (long long)sh.F * sh.rows * sh.cols;
+    sh.S = tg.S;
+    return sh;
+}
+
+// Appends group (base, sh) to tg; false when tg is full.
+inline bool tiles_add(Tiles& tg, long long base, const Shape& sh)
+{
+    if (tg.n == 0) tg.tile0[0] = 0;
+    if (tg.n >= TILE_GROUPS) return false;
+    const int g = tg.n++;
+    tg.base[g] = base;
+    tg.F[g] = sh.F;
+    tg.rows[g] = sh.rows;
+    tg.cols[g] = sh.cols;
+    tg.S = sh.S;
+    const long long nt = (long long)sh.F * ((sh.rows + TILE - 1) / TILE) * ((sh.cols + TILE - 1) / TILE);
+    tg.tile0[g + 1] = tg.tile0[g] + (int)nt;
+    return true;
+}
+
+// One group: the whole shape from pixel 0.
+inline Tiles tiles_of(const Shape& sh)
+{
+    Tiles tg{};
+    tiles_add(tg, 0, sh);
+    return tg;
+}
+
 // ---------------------------------------------------------------------------
 // Model evaluation in FP32 local coordinates.
 
@@ -336,6 +404,12 @@ hipError_t launch_gradients(const DevModel& m, const DevParams& p, const Shape& 
                             DevState s, float* gt, float* gr, float* gb, hipStream_t st);
 
 // only_above >= 0: pixels with at most that many points are copied, not fitted
+hipError_t launch_apss_tiles(const DevModel& m, const DevParams& p, const Tiles& tg, DevState in, DevState out,
+                             int only_above, hipStream_t st);
+hipError_t launch_ifilter_tiles(const DevParams& p, const Tiles& tg, DevState in, DevState out, hipStream_t st);
+// dst = the filtered src floored at b_min, per group (src, dst, tmp: the batch's arrays)
+hipError_t launch_bfilter_tiles(const float* w, int rb, const Tiles& tg, float b_min, const float* src, float* dst,
+                                float* tmp, hipStream_t st);
 hipError_t launch_apss(const DevModel& m, const DevParams& p, const Shape& sh, DevState in,
                        DevState out, int only_above, hipStream_t st);
 hipError_t launch_merge(const DevParams& p, const Shape& sh, DevState s, hipStream_t st);

@@ -300,17 +300,6 @@ struct Group {
     Shape sh;
 };
 
-// The state of a group: every array advanced to the group's first pixel.
-DevState state_at(DevState s, long long base)
-{
-    s.t += base;
-    s.r += base;
-    s.n += base;
-    s.cnt += base;
-    s.b += base;
-    return s;
-}
-
 // One iteration of the loop on state A (in/out) with B as the second buffer.
 // Per-pixel steps run once over the batch (sh); steps that read neighbouring
 // pixels run once per group of equally sized frames.
@@ -322,10 +311,16 @@ rt3d_status iterate(rt3d_ctx* c, const Shape& sh, const std::vector<Group>& grou
     const DevParams p = dev_params(c);
     RT3D_LAUNCH(c, RT3D_KERNEL_DEPTH, st, launch_depth_step(m, p, sh, off, ent, gain, A, st));
     DevState cur = A;
+    // the groups as tile tables of at most TILE_GROUPS groups (one launch each)
+    std::vector<Tiles> tiles(1, Tiles{});
+    for (const Group& g : groups)
+        if (!tiles_add(tiles.back(), g.base, g.sh)) {
+            tiles.push_back(Tiles{});
+            tiles_add(tiles.back(), g.base, g.sh);
+        }
     if (c->p.denoiser == RT3D_DENOISE_APSS) {
-        for (const Group& g : groups)
-            RT3D_LAUNCH(c, RT3D_KERNEL_APSS, st,
-                        launch_apss(m, p, g.sh, state_at(A, g.base), state_at(B, g.base), -1, st));
+        for (const Tiles& tg : tiles)
+            RT3D_LAUNCH(c, RT3D_KERNEL_APSS, st, launch_apss_tiles(m, p, tg, A, B, -1, st));
         cur = B;
     } else if (c->p.denoiser == RT3D_DENOISE_CNN) {
         // APSS only for pixels holding more points than the network's three slots
@@ -339,15 +334,13 @@ rt3d_status iterate(rt3d_ctx* c, const Shape& sh, const std::vector<Group>& grou
     }
     // the in-pixel merge runs fused ahead of the intensity step
     RT3D_LAUNCH(c, RT3D_KERNEL_INTENSITY, st, launch_intensity_step(m, p, sh, off, ent, gain, cur, true, st));
-    for (const Group& g : groups)
-        RT3D_LAUNCH(c, RT3D_KERNEL_IFILTER, st,
-                    launch_ifilter(p, g.sh, state_at(cur, g.base), state_at(A, g.base), st));
+    for (const Tiles& tg : tiles)
+        RT3D_LAUNCH(c, RT3D_KERNEL_IFILTER, st, launch_ifilter_tiles(p, tg, cur, A, st));
     // the background step writes btmp; the filter brings it back into A.b
     RT3D_LAUNCH(c, RT3D_KERNEL_BKG, st, launch_bg_step(m, p, sh, off, ent, gain, A, btmp, st));
-    for (const Group& g : groups)
+    for (const Tiles& tg : tiles)
         RT3D_LAUNCH(c, RT3D_KERNEL_BFILTER, st,
-                    launch_bfilter(c->d_bw, c->rb, g.sh, (float)c->p.b_min, btmp + g.base, A.b + g.base,
-                                   B.b + g.base, st));
+                    launch_bfilter_tiles(c->d_bw, c->rb, tg, (float)c->p.b_min, btmp, A.b, B.b, st));
     return RT3D_OK;
 }
 
