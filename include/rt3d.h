@@ -124,7 +124,16 @@ typedef struct rt3d_input {
      * the sizes differ. */
     const uint32_t* frame_rows;
     const uint32_t* frame_cols;
+    /* RT3D_FLAG_* bits. */
+    uint32_t flags;
 } rt3d_input;
+
+/* Warm start (video): skip the initialisation; the iterations start from the
+ * point state and background the previous reconstruction on this context left
+ * (its output), for new photon data of the same frames and frame sizes.
+ * E_STATE when the context holds no such state (no earlier call, a different
+ * batch shape, or a step-by-step call in between). */
+#define RT3D_FLAG_WARM_START 1u
 
 typedef struct rt3d_output {
     uint32_t struct_size;      /* sizeof(rt3d_output) */

@@ -49,6 +49,8 @@ struct rt3d_ctx {
     // last call facts
     long long last_P = 0;
     bool last_compacted = false;
+    // the batch layout whose final state the workspace holds (warm starts)
+    std::vector<long long> state_layout;
     // learned denoiser weights (always allocated; zero until set)
     CnnWeights cnn;
     bool cnn_set = false;
@@ -263,6 +265,7 @@ Workspace carve_ctx(const rt3d_ctx* c, uint8_t* base, long long P, uint64_t E, u
 
 rt3d_status need_ws(rt3d_ctx* c, long long P, Workspace& w)
 {
+    c->state_layout.clear();     // a reconstruction sets it again once it has enqueued its output
     if (!c->ws) return fail(c, RT3D_E_NOMEM, "no workspace bound (rt3d_set_workspace)");
     if (P > c->ws_P) return fail(c, RT3D_E_NOMEM, "batch larger than the workspace was sized for");
     w = carve_ctx(c, c->ws, c->ws_P, c->ws_E, c->ws_rows, c->ws_cols);
@@ -683,6 +686,7 @@ rt3d_status rt3d_set_workspace(rt3d_ctx* c, void* dev_ptr, size_t bytes, uint32_
 {
     if (!c) return RT3D_E_INVALID;
     c->ws = nullptr;
+    c->state_layout.clear();
     c->ws_P = 0;
     c->ws_E = 0;
     if (!dev_ptr || bytes == 0) return fail(c, RT3D_E_INVALID, "workspace pointer NULL or size 0");
@@ -753,6 +757,7 @@ rt3d_status rt3d_reconstruct(rt3d_ctx* c, const rt3d_input* in, rt3d_output* out
         groups.push_back(Group{0, sh});
     }
     if (groups.size() == 1) sh = groups[0].sh;
+    const std::vector<long long> prev_layout = c->state_layout;   // need_ws forgets it
     Workspace w;
     rt3d_status s = need_ws(c, sh.P, w);
     if (s != RT3D_OK) return s;
@@ -788,17 +793,27 @@ rt3d_status rt3d_reconstruct(rt3d_ctx* c, const rt3d_input* in, rt3d_output* out
     c->last_P = sh.P;
     const DevModel m = dev_model(c);
     const DevParams p = dev_params(c);
-    for (const Group& g : groups)
-        RT3D_LAUNCH(c, RT3D_KERNEL_INIT, st,
-                    launch_init(m, p, g.sh, off + g.base, ent, in->gain ? in->gain + g.base : nullptr,
-                                state_at(w.A, g.base), w.err, st));
-    for (const Group& g : groups)
-        RT3D_LAUNCH(c, RT3D_KERNEL_NORMALS, st, launch_init_normals(p, g.sh, state_at(w.A, g.base), st));
+    // the layout of this batch: its groups' bases and shapes
+    std::vector<long long> layout;
+    for (const Group& g : groups) layout.insert(layout.end(), {g.base, g.sh.F, g.sh.rows, g.sh.cols});
+    if (in->flags & RT3D_FLAG_WARM_START) {
+        if (layout != prev_layout)
+            return fail(c, RT3D_E_STATE, "warm start: no final state of a batch of these frames in the workspace");
+    } else {
+        for (const Group& g : groups)
+            RT3D_LAUNCH(c, RT3D_KERNEL_INIT, st,
+                        launch_init(m, p, g.sh, off + g.base, ent, in->gain ? in->gain + g.base : nullptr,
+                                    state_at(w.A, g.base), w.err, st));
+        for (const Group& g : groups)
+            RT3D_LAUNCH(c, RT3D_KERNEL_NORMALS, st, launch_init_normals(p, g.sh, state_at(w.A, g.base), st));
+    }
+    c->state_layout.clear();
     for (int it = 0; it < c->p.n_iter; ++it) {
         s = iterate(c, sh, groups, off, ent, in->gain, w.A, w.B, w.btmp, &w.cnn, st);
         if (s != RT3D_OK) return s;
     }
     RT3D_LAUNCH(c, RT3D_KERNEL_OUTPUT, st, launch_output(sh, w.A, out, w.counts, w.partial, w.err, st));
+    c->state_layout = layout;
     return RT3D_OK;
 }
 

@@ -32,6 +32,7 @@ EXPORTS = ["rt3d_params_default", "rt3d_create", "rt3d_destroy", "rt3d_last_erro
 KERNELS = ["compact", "init", "normals", "depth", "apss", "merge", "intensity", "ifilter", "bkg",
            "bfilter", "output", "cnn"]
 DENOISE_CNN = 2
+FLAG_WARM_START = 1
 CNN_PARAMS = 24003
 
 
@@ -62,7 +63,8 @@ class Input(C.Structure):
                 ("rows", C.c_uint32), ("cols", C.c_uint32), ("hist", C.c_void_p),
                 ("off", C.c_void_p), ("ent", C.c_void_p), ("gain", C.c_void_p),
                 ("ev_pixel", C.c_void_p), ("ev_bin", C.c_void_p), ("ev_scratch", C.c_void_p),
-                ("n_events", C.c_uint64), ("frame_rows", C.c_void_p), ("frame_cols", C.c_void_p)]
+                ("n_events", C.c_uint64), ("frame_rows", C.c_void_p), ("frame_cols", C.c_void_p),
+                ("flags", C.c_uint32)]
 
 
 class Output(C.Structure):
@@ -285,8 +287,9 @@ class Context:
                       torch.zeros(P, dtype=torch.float32, device=dev))
 
     def _io(self, out: Result, frames: int, rows: int, cols: int, hist=None, off=None, ent=None, gain=None,
-            events=None, frame_shapes=None):
+            events=None, frame_shapes=None, warm_start=False):
         inp = Input()
+        inp.flags = FLAG_WARM_START if warm_start else 0
         inp.struct_size = C.sizeof(Input)
         inp.frames, inp.rows, inp.cols = frames, rows, cols
         if frame_shapes is not None:
@@ -319,12 +322,13 @@ class Context:
         return inp, o
 
     def reconstruct_into(self, out: Result, frames: int, rows: int, cols: int, hist=None, off=None,
-                         ent=None, gain=None, events=None, frame_shapes=None):
+                         ent=None, gain=None, events=None, frame_shapes=None, warm_start=False):
         """Enqueue one reconstruction on the current torch stream (no sync).
         Input: hist, or (off, ent), or events = (pixel int32, bin int16, scratch int32).
         frame_shapes: [(rows, cols)] per frame for frames of different sizes, whose
-        pixels follow one another (rows and cols are then ignored)."""
-        inp, o = self._io(out, frames, rows, cols, hist, off, ent, gain, events, frame_shapes)
+        pixels follow one another (rows and cols are then ignored).
+        warm_start: start from the previous call's final state (same frames)."""
+        inp, o = self._io(out, frames, rows, cols, hist, off, ent, gain, events, frame_shapes, warm_start)
         self._check(lib().rt3d_reconstruct(self._h, C.byref(inp), C.byref(o), _stream()))
         return out
 
