@@ -85,6 +85,12 @@ typedef struct rt3d_params {
     int32_t  w_nms;      /* peak suppression half width, bins; <= 0: ceil(max(1, 2 sigma_h)) */
     int32_t  m_min;      /* minimum APSS neighbours (3) */
     int32_t  denoiser;   /* RT3D_DENOISE_APSS (default), RT3D_DENOISE_CNN or RT3D_DENOISE_NONE */
+    int32_t  fused_loop; /* with APSS, a batch of frames of one size of at most 4096 pixels can run
+                          * all iterations in one launch (one workgroup per frame, steps separated
+                          * by workgroup barriers) instead of one launch per step.  1: always
+                          * (when eligible); 0: never; -1 (default): the choice rt3d_autotune
+                          * measured for this batch shape, else when the batch holds at least
+                          * 64 frames (fewer frames leave most compute units idle) */
 } rt3d_params;
 
 /* Input kinds. */
@@ -247,7 +253,18 @@ rt3d_status rt3d_query(rt3d_ctx* ctx, void* hip_stream, rt3d_stats* st);
 #define RT3D_KERNEL_BFILTER   9   /* background filter (row and column passes) */
 #define RT3D_KERNEL_OUTPUT   10   /* output packing (count, scan, pack) */
 #define RT3D_KERNEL_CNN      11   /* learned denoiser forward (features + four convolutions) */
-#define RT3D_KERNEL_COUNT    12
+#define RT3D_KERNEL_LOOP     12   /* every iteration in one launch (params.fused_loop) */
+#define RT3D_KERNEL_COUNT    13
+/* Autotuning.  Times a reconstruction of this input both ways the library can
+ * map the loop onto the GPU (one launch per step; all iterations in one
+ * launch, one workgroup per frame) and keeps the faster for this batch shape
+ * (frames x rows x cols) in the context, where params.fused_loop = -1 uses it.
+ * Synchronises the stream; the output holds the last timed reconstruction.
+ * *fused (may be NULL) receives the choice: 1 one launch, 0 per step; a batch
+ * that cannot take the one-launch loop gets 0 without timing.  Not while a
+ * graph is being recorded. */
+rt3d_status rt3d_autotune(rt3d_ctx* ctx, const rt3d_input* in, rt3d_output* out, void* hip_stream,
+                          int32_t* fused);
 rt3d_status rt3d_profile(rt3d_ctx* ctx, int32_t id);
 rt3d_status rt3d_profile_read(rt3d_ctx* ctx, double* total_ms, uint64_t* launches);
 

@@ -26,42 +26,6 @@
 
 namespace rt3d {
 
-// Sphere fit from the moments and projection of the query along its line of
-// sight: updates depth t (bins) and normal n when the fit is usable.
-__device__ __forceinline__ void apss_project(bool ok, float W, float Px, float Py, float Pz, float Nx, float Ny,
-                                             float Nz, float PN, float PP, float h, float h2, double dz, double tmax,
-                                             double& t, float (&n)[3])
-{
-    if (!ok) return;
-    const float invW = 1.f / W;
-    const float PdP = Px * Px + Py * Py + Pz * Pz;
-    const float PdN = Px * Nx + Py * Ny + Pz * Nz;
-    const float D = PP - PdP * invW;
-    if (!(D > 1e-12f * W * h2)) return;
-    const float u4 = 0.5f * (PN - PdN * invW) / D;
-    const float ulx = (Nx - 2.f * u4 * Px) * invW;
-    const float uly = (Ny - 2.f * u4 * Py) * invW;
-    const float ulz = (Nz - 2.f * u4 * Pz) * invW;
-    const float u0 = -(ulx * Px + uly * Py + ulz * Pz + u4 * PP) * invW;
-    const float nul = sqrtf(ulx * ulx + uly * uly + ulz * ulz);
-    if (!(fabsf(ulz) > 1e-6f * nul)) return;
-    const float disc = ulz * ulz - 4.f * u4 * u0;
-    float sroot;
-    if (disc < 0.f) sroot = -ulz / (2.f * u4);
-    else sroot = -2.f * u0 / (ulz + copysignf(sqrtf(disc), ulz));
-    sroot = fminf(fmaxf(sroot, -h), h);
-    double tn = t + (double)sroot / dz;
-    t = tn < 0.0 ? 0.0 : (tn > tmax ? tmax : tn);
-    const float gx = ulx, gy = uly, gz = ulz + 2.f * u4 * sroot;
-    const float gn = sqrtf(gx * gx + gy * gy + gz * gz);
-    if (gn > 0.f) {
-        const float inv = (gz > 0.f ? -1.f : 1.f) / gn;
-        n[0] = gx * inv;
-        n[1] = gy * inv;
-        n[2] = gz * inv;
-    }
-}
-
 constexpr int ATX = TILE, ATY = TILE;   // tile of the LDS variant: columns, rows
 
 // LDS bytes of a staged tile with an R-pixel halo: per pixel KM depths (FP64),

@@ -27,38 +27,6 @@
 
 namespace rt3d {
 
-struct PixPoints {
-    int    c;
-    int    a[KM];    // floor(t)
-    float  f[KM];    // t - floor(t)
-    float  r[KM];
-    double t[KM];
-};
-
-// Every slot is read whatever the count (the state holds KM slots per pixel),
-// so that no load waits on another; slots at or beyond the count are zeroed.
-__device__ __forceinline__ void load_points(const DevState& s, long long P, long long pix, PixPoints& q)
-{
-    double tv[KM];
-    float rv[KM];
-#pragma unroll
-    for (int k = 0; k < KM; ++k) {
-        tv[k] = s.t[k * P + pix];
-        rv[k] = s.r[k * P + pix];
-    }
-    q.c = load_cnt(s.cnt, pix);
-#pragma unroll
-    for (int k = 0; k < KM; ++k) {
-        const bool on = k < q.c;
-        const double t = on ? tv[k] : 0.0;
-        const double fl = floor(t);
-        q.t[k] = t;
-        q.a[k] = (int)fl;
-        q.f[k] = (float)(t - fl);
-        q.r[k] = on ? rv[k] : 0.f;
-    }
-}
-
 // Lanes per pixel: a pixel's active entries are split over LPP consecutive
 // lanes (entry e + LPP i), whose partial sums meet in a shuffle tree.
 constexpr int LPP = 4;
@@ -233,19 +201,9 @@ __global__ __launch_bounds__(256) void k_depth_step(DevModel m, DevParams p, Sha
     float Sv[KM], Spv[KM];
     s_eval_points(m, L.q, L.sub, Sv, Spv);
     if (!L.live || L.sub != 0) return;
-    const float scale = (float)p.beta_t * m.fisher_inv;
-    const float dmax = (float)p.dmax;
-    const double tmax = (double)(m.T - 1);
 #pragma unroll
-    for (int k = 0; k < KM; ++k) {
-        if (k < L.q.c && L.q.r[k] > 0.f) {
-            float step = -scale * (Spv[k] + shp[k]);
-            step = fminf(fmaxf(step, -dmax), dmax);
-            double tn = L.q.t[k] + (double)step;
-            tn = tn < 0.0 ? 0.0 : (tn > tmax ? tmax : tn);
-            s.t[k * P + L.pix] = tn;
-        }
-    }
+    for (int k = 0; k < KM; ++k)
+        if (k < L.q.c && L.q.r[k] > 0.f) s.t[k * P + L.pix] = depth_next(m, p, L.q.t[k], Spv[k], shp[k]);
 }
 
 // The in-pixel merge ahead of the intensity step: every lane of the pixel
@@ -306,17 +264,9 @@ __global__ __launch_bounds__(256) void k_intensity_step(DevModel m, DevParams p,
     float Sv[KM], Spv[KM];
     s_eval_points(m, L.q, L.sub, Sv, Spv);
     if (!L.live || L.sub != 0) return;
-    const float br = (float)p.beta_r;
 #pragma unroll
-    for (int k = 0; k < KM; ++k) {
-        if (k < L.q.c) {
-            const float S = Sv[k];
-            if (S > 0.f) {
-                const float v = L.q.r[k] * ((1.f - br) + br * shh[k] / S);
-                s.r[k * P + L.pix] = fmaxf(v, 0.f);
-            }
-        }
-    }
+    for (int k = 0; k < KM; ++k)
+        if (k < L.q.c && Sv[k] > 0.f) s.r[k * P + L.pix] = intensity_next(p, L.q.r[k], Sv[k], shh[k]);
 }
 
 // The background step writes the new b to bdst (the state's own b, or a
@@ -340,9 +290,7 @@ __global__ __launch_bounds__(256) void k_bg_step(DevModel m, DevParams p, Shape 
         bdst[L.pix] = braw;
         return;
     }
-    const float bt = (float)p.beta_b;
-    const float v = bb * ((1.f - bt) + bt * sz / (float)m.T);
-    bdst[L.pix] = fmaxf(v, (float)p.b_min);
+    bdst[L.pix] = background_next(m, p, bb, sz);
 }
 
 __global__ __launch_bounds__(256) void k_gradients(DevModel m, Shape sh, const uint32_t* __restrict__ off,

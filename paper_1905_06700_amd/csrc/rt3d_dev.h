@@ -207,6 +207,14 @@ __device__ __forceinline__ void s_eval(const DevModel& m, double t, float& S, fl
 
 __device__ __forceinline__ int ent_bin(uint32_t e) { return (int)(e >> 16); }
 
+// Live slot count of a pixel, clamped to the slot capacity.
+__device__ __forceinline__ int load_cnt(const uint8_t* cnt, long long pix)
+{
+    int c = cnt[pix];
+    return c < KM ? c : KM;
+}
+__device__ __forceinline__ int ent_cnt(uint32_t e) { return (int)(e & 0xffffu); }
+
 // In-pixel merge of c points (reading; the paper does not say how duplicate
 // points of one pixel are treated): a stable insertion sort by depth, then,
 // in depth order, a point closer than dm bins to the next merges with it into
@@ -252,6 +260,102 @@ __device__ __forceinline__ void merge_points(double (&t)[KM], float (&r)[KM], fl
     }
 }
 
+// Sphere fit from the moments and projection of the query along its line of
+// sight: updates depth t (bins) and normal n when the fit is usable.
+__device__ __forceinline__ void apss_project(bool ok, float W, float Px, float Py, float Pz, float Nx, float Ny,
+                                             float Nz, float PN, float PP, float h, float h2, double dz, double tmax,
+                                             double& t, float (&n)[3])
+{
+    if (!ok) return;
+    const float invW = 1.f / W;
+    const float PdP = Px * Px + Py * Py + Pz * Pz;
+    const float PdN = Px * Nx + Py * Ny + Pz * Nz;
+    const float D = PP - PdP * invW;
+    if (!(D > 1e-12f * W * h2)) return;
+    const float u4 = 0.5f * (PN - PdN * invW) / D;
+    const float ulx = (Nx - 2.f * u4 * Px) * invW;
+    const float uly = (Ny - 2.f * u4 * Py) * invW;
+    const float ulz = (Nz - 2.f * u4 * Pz) * invW;
+    const float u0 = -(ulx * Px + uly * Py + ulz * Pz + u4 * PP) * invW;
+    const float nul = sqrtf(ulx * ulx + uly * uly + ulz * ulz);
+    if (!(fabsf(ulz) > 1e-6f * nul)) return;
+    const float disc = ulz * ulz - 4.f * u4 * u0;
+    float sroot;
+    if (disc < 0.f) sroot = -ulz / (2.f * u4);
+    else sroot = -2.f * u0 / (ulz + copysignf(sqrtf(disc), ulz));
+    sroot = fminf(fmaxf(sroot, -h), h);
+    double tn = t + (double)sroot / dz;
+    t = tn < 0.0 ? 0.0 : (tn > tmax ? tmax : tn);
+    const float gx = ulx, gy = uly, gz = ulz + 2.f * u4 * sroot;
+    const float gn = sqrtf(gx * gx + gy * gy + gz * gz);
+    if (gn > 0.f) {
+        const float inv = (gz > 0.f ? -1.f : 1.f) / gn;
+        n[0] = gx * inv;
+        n[1] = gy * inv;
+        n[2] = gz * inv;
+    }
+}
+
+struct PixPoints {
+    int    c;
+    int    a[KM];    // floor(t)
+    float  f[KM];    // t - floor(t)
+    float  r[KM];
+    double t[KM];
+};
+
+// Every slot is read whatever the count (the state holds KM slots per pixel),
+// so that no load waits on another; slots at or beyond the count are zeroed.
+__device__ __forceinline__ void load_points(const DevState& s, long long P, long long pix, PixPoints& q)
+{
+    double tv[KM];
+    float rv[KM];
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+        tv[k] = s.t[k * P + pix];
+        rv[k] = s.r[k * P + pix];
+    }
+    q.c = load_cnt(s.cnt, pix);
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+        const bool on = k < q.c;
+        const double t = on ? tv[k] : 0.0;
+        const double fl = floor(t);
+        q.t[k] = t;
+        q.a[k] = (int)fl;
+        q.f[k] = (float)(t - fl);
+        q.r[k] = on ? rv[k] : 0.f;
+    }
+}
+
+// The step updates of one point / pixel (readings of the step sizes):
+// depth: t - (beta_t / I_h) (S' + sum z h'/lambda), clipped to dmax, clamped
+// to [0, T-1]; intensity (for S > 0): r [(1 - beta_r) + beta_r sum z h /
+// (lambda S)], at least 0; background: b [(1 - beta_b) + beta_b sum z /
+// (lambda T)], at least b_min.
+__device__ __forceinline__ double depth_next(const DevModel& m, const DevParams& p, double t, float Sp, float shp)
+{
+    const float scale = (float)p.beta_t * m.fisher_inv;
+    const float dmax = (float)p.dmax;
+    const double tmax = (double)(m.T - 1);
+    float step = -scale * (Sp + shp);
+    step = fminf(fmaxf(step, -dmax), dmax);
+    const double tn = t + (double)step;
+    return tn < 0.0 ? 0.0 : (tn > tmax ? tmax : tn);
+}
+
+__device__ __forceinline__ float intensity_next(const DevParams& p, float r, float S, float shh)
+{
+    const float br = (float)p.beta_r;
+    return fmaxf(r * ((1.f - br) + br * shh / S), 0.f);
+}
+
+__device__ __forceinline__ float background_next(const DevModel& m, const DevParams& p, float bb, float sz)
+{
+    const float bt = (float)p.beta_b;
+    return fmaxf(bb * ((1.f - bt) + bt * sz / (float)m.T), (float)p.b_min);
+}
+
 // Writes a pixel's c points to its KM slots (empty slots: zero depth and
 // intensity, normal facing the sensor) and its count.
 __device__ __forceinline__ void store_points(const DevState& s, long long P, long long pix, const double (&t)[KM],
@@ -270,13 +374,6 @@ __device__ __forceinline__ void store_points(const DevState& s, long long P, lon
     s.cnt[pix] = (uint8_t)c;
 }
 
-// Live slot count of a pixel, clamped to the slot capacity.
-__device__ __forceinline__ int load_cnt(const uint8_t* cnt, long long pix)
-{
-    int c = cnt[pix];
-    return c < KM ? c : KM;
-}
-__device__ __forceinline__ int ent_cnt(uint32_t e) { return (int)(e & 0xffffu); }
 
 // Wave-level helpers (wave64).
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
@@ -420,6 +517,14 @@ hipError_t launch_ifilter(const DevParams& p, const Shape& sh, DevState in, DevS
 hipError_t launch_bfilter(const float* w, int rb, const Shape& sh, float b_min, const float* src, float* dst,
                           float* tmp, hipStream_t st);
 hipError_t launch_copy_state(const Shape& sh, DevState in, DevState out, hipStream_t st);
+
+// Every iteration in one launch for frames of at most LOOP_MAX_PIX pixels:
+// state A in and out, B the second buffer, bt a P-float background scratch,
+// w the 2 rb + 1 background filter taps (rb <= 0: the floor only).
+constexpr int LOOP_MAX_PIX = 4096;
+hipError_t launch_loop(const DevModel& m, const DevParams& p, const Shape& sh, const uint32_t* off,
+                       const uint32_t* ent, const float* gain, DevState A, DevState B, float* bt, const float* w,
+                       int rb, int n_iter, hipStream_t st);
 
 hipError_t launch_output(const Shape& sh, DevState s, rt3d_output* out, uint32_t* counts,
                          uint32_t* partial, int32_t* err, hipStream_t st);

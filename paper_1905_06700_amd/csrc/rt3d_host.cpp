@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -51,6 +52,9 @@ struct rt3d_ctx {
     bool last_compacted = false;
     // the batch layout whose final state the workspace holds (warm starts)
     std::vector<long long> state_layout;
+    // rt3d_autotune's choices: (frames, rows, cols, fused)
+    std::vector<std::array<long long, 4>> tuned;
+    int force_fused = -2;              // set by rt3d_autotune while it times one way
     // learned denoiser weights (always allocated; zero until set)
     CnnWeights cnn;
     bool cnn_set = false;
@@ -233,6 +237,7 @@ rt3d_status check_params(const rt3d_params* p, uint32_t bins, std::string& why)
     if (!(p->sigma_b >= 0) || p->sigma_b > 64) { why = "sigma_b outside [0, 64]"; return RT3D_E_INVALID; }
     if (!(p->sbr_guess > 0)) { why = "sbr_guess must be > 0"; return RT3D_E_INVALID; }
     if (p->r_init < 0 || p->r_init > 8) { why = "r_init outside 0..8"; return RT3D_E_INVALID; }
+    if (p->fused_loop < -1 || p->fused_loop > 1) { why = "fused_loop must be -1, 0 or 1"; return RT3D_E_INVALID; }
     if (p->denoiser != RT3D_DENOISE_APSS && p->denoiser != RT3D_DENOISE_NONE && p->denoiser != RT3D_DENOISE_CNN) {
         why = "unknown denoiser"; return RT3D_E_UNSUPPORTED;
     }
@@ -302,6 +307,23 @@ struct Group {
     long long base;
     Shape sh;
 };
+
+// Whether a batch can run every iteration in one launch (APSS, frames of one
+// size of at most LOOP_MAX_PIX pixels), and whether it does.
+bool loop_eligible(const rt3d_ctx* c, const std::vector<Group>& groups, const Shape& sh)
+{
+    return c->p.denoiser == RT3D_DENOISE_APSS && groups.size() == 1 &&
+           (long long)sh.rows * sh.cols <= LOOP_MAX_PIX;
+}
+
+bool use_fused(const rt3d_ctx* c, const Shape& sh)
+{
+    if (c->force_fused >= 0) return c->force_fused == 1;
+    if (c->p.fused_loop >= 0) return c->p.fused_loop == 1;
+    for (const auto& t : c->tuned)
+        if (t[0] == sh.F && t[1] == sh.rows && t[2] == sh.cols) return t[3] == 1;
+    return sh.F >= 64;
+}
 
 // One iteration of the loop on state A (in/out) with B as the second buffer.
 // Per-pixel steps run once over the batch (sh); steps that read neighbouring
@@ -378,6 +400,7 @@ void rt3d_params_default(rt3d_params* p)
     p->w_nms = 0;
     p->m_min = 3;
     p->denoiser = RT3D_DENOISE_APSS;
+    p->fused_loop = -1;
 }
 
 rt3d_status rt3d_create(const double* irf, uint32_t irf_len, int32_t irf_origin, uint32_t bins,
@@ -808,9 +831,14 @@ rt3d_status rt3d_reconstruct(rt3d_ctx* c, const rt3d_input* in, rt3d_output* out
             RT3D_LAUNCH(c, RT3D_KERNEL_NORMALS, st, launch_init_normals(p, g.sh, state_at(w.A, g.base), st));
     }
     c->state_layout.clear();
-    for (int it = 0; it < c->p.n_iter; ++it) {
-        s = iterate(c, sh, groups, off, ent, in->gain, w.A, w.B, w.btmp, &w.cnn, st);
-        if (s != RT3D_OK) return s;
+    if (loop_eligible(c, groups, sh) && use_fused(c, sh)) {
+        RT3D_LAUNCH(c, RT3D_KERNEL_LOOP, st,
+                    launch_loop(m, p, sh, off, ent, in->gain, w.A, w.B, w.btmp, c->d_bw, c->rb, c->p.n_iter, st));
+    } else {
+        for (int it = 0; it < c->p.n_iter; ++it) {
+            s = iterate(c, sh, groups, off, ent, in->gain, w.A, w.B, w.btmp, &w.cnn, st);
+            if (s != RT3D_OK) return s;
+        }
     }
     RT3D_LAUNCH(c, RT3D_KERNEL_OUTPUT, st, launch_output(sh, w.A, out, w.counts, w.partial, w.err, st));
     c->state_layout = layout;
@@ -860,6 +888,56 @@ rt3d_status rt3d_graph_create(rt3d_ctx* c, const rt3d_input* in, rt3d_output* ou
     r->graph = g;
     r->exec = x;
     *graph = r;
+    return RT3D_OK;
+}
+
+rt3d_status rt3d_autotune(rt3d_ctx* c, const rt3d_input* in, rt3d_output* out, void* hip_stream,
+                          int32_t* fused)
+{
+    if (!c) return RT3D_E_INVALID;
+    if (fused) *fused = 0;
+    if (!in || in->struct_size != sizeof(rt3d_input)) return fail(c, RT3D_E_INVALID, "input NULL or struct_size mismatch");
+    uint32_t F = in->frames, R = in->rows, Q = in->cols;
+    if (in->frame_rows || in->frame_cols) {
+        if (!in->frame_rows || !in->frame_cols || F == 0)
+            return fail(c, RT3D_E_INVALID, "frame_rows and frame_cols go together, with frames >= 1");
+        R = in->frame_rows[0];
+        Q = in->frame_cols[0];
+        for (uint32_t f = 1; f < F; ++f)
+            if (in->frame_rows[f] != R || in->frame_cols[f] != Q) return RT3D_OK;   // several sizes: per step
+    }
+    if (c->p.denoiser != RT3D_DENOISE_APSS || (long long)R * Q > LOOP_MAX_PIX) return RT3D_OK;
+    rt3d_input cold = *in;
+    cold.flags &= ~RT3D_FLAG_WARM_START;
+    hipStream_t st = (hipStream_t)hip_stream;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipError_t e = hipEventCreate(&ev[0]);
+    if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+    float ms[2] = {0.f, 0.f};
+    rt3d_status s = RT3D_OK;
+    for (int way = 0; way < 2 && e == hipSuccess && s == RT3D_OK; ++way) {
+        c->force_fused = way;
+        s = rt3d_reconstruct(c, &cold, out, st);                   // untimed
+        if (s == RT3D_OK) e = hipEventRecord(ev[0], st);
+        for (int k = 0; k < 3 && s == RT3D_OK && e == hipSuccess; ++k) s = rt3d_reconstruct(c, &cold, out, st);
+        if (s == RT3D_OK && e == hipSuccess) e = hipEventRecord(ev[1], st);
+        if (s == RT3D_OK && e == hipSuccess) e = hipEventSynchronize(ev[1]);
+        if (s == RT3D_OK && e == hipSuccess) e = hipEventElapsedTime(&ms[way], ev[0], ev[1]);
+    }
+    c->force_fused = -2;
+    for (hipEvent_t x : ev)
+        if (x) (void)hipEventDestroy(x);
+    if (s != RT3D_OK) return s;
+    if (e != hipSuccess) return hip_fail(c, e, "autotune timing");
+    const int choice = ms[1] < ms[0] ? 1 : 0;
+    bool found = false;
+    for (auto& t : c->tuned)
+        if (t[0] == F && t[1] == R && t[2] == Q) {
+            t[3] = choice;
+            found = true;
+        }
+    if (!found) c->tuned.push_back({(long long)F, (long long)R, (long long)Q, (long long)choice});
+    if (fused) *fused = choice;
     return RT3D_OK;
 }
 

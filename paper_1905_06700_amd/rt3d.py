@@ -26,11 +26,12 @@ STEP_INIT, STEP_DEPTH, STEP_APSS, STEP_MERGE, STEP_INTENSITY, STEP_IFILTER, STEP
 EXPORTS = ["rt3d_params_default", "rt3d_create", "rt3d_destroy", "rt3d_last_error", "rt3d_sigma2",
            "rt3d_workspace_bytes", "rt3d_set_workspace", "rt3d_reconstruct", "rt3d_query",
            "rt3d_profile", "rt3d_profile_read", "rt3d_graph_create", "rt3d_graph_launch", "rt3d_graph_destroy",
+           "rt3d_autotune",
            "rt3d_debug_compact", "rt3d_debug_compact_events", "rt3d_debug_step", "rt3d_debug_gradients",
            "rt3d_cnn_set_weights", "rt3d_cnn_get_weights", "rt3d_cnn_last_gradient",
            "rt3d_cnn_forward", "rt3d_cnn_train_step"]
 KERNELS = ["compact", "init", "normals", "depth", "apss", "merge", "intensity", "ifilter", "bkg",
-           "bfilter", "output", "cnn"]
+           "bfilter", "output", "cnn", "loop"]
 DENOISE_CNN = 2
 FLAG_WARM_START = 1
 CNN_PARAMS = 24003
@@ -55,7 +56,7 @@ class Params(C.Structure):
                 ("r_min", C.c_double), ("d_merge", C.c_double), ("sigma_b", C.c_double),
                 ("b_min", C.c_double), ("sbr_guess", C.c_double), ("r_init", C.c_int32),
                 ("n_min", C.c_int32), ("kappa", C.c_double), ("w_nms", C.c_int32),
-                ("m_min", C.c_int32), ("denoiser", C.c_int32)]
+                ("m_min", C.c_int32), ("denoiser", C.c_int32), ("fused_loop", C.c_int32)]
 
 
 class Input(C.Structure):
@@ -118,6 +119,8 @@ def lib():
         L.rt3d_profile.restype = st
         L.rt3d_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]
         L.rt3d_profile_read.restype = st
+        L.rt3d_autotune.argtypes = [vp, C.POINTER(Input), C.POINTER(Output), vp, C.POINTER(C.c_int32)]
+        L.rt3d_autotune.restype = st
         L.rt3d_graph_create.argtypes = [vp, C.POINTER(Input), C.POINTER(Output), C.POINTER(vp)]
         L.rt3d_graph_create.restype = st
         L.rt3d_graph_launch.argtypes = [vp, vp]
@@ -331,6 +334,15 @@ class Context:
         inp, o = self._io(out, frames, rows, cols, hist, off, ent, gain, events, frame_shapes, warm_start)
         self._check(lib().rt3d_reconstruct(self._h, C.byref(inp), C.byref(o), _stream()))
         return out
+
+    def autotune(self, out: Result, frames: int, rows: int, cols: int, hist=None, off=None, ent=None, gain=None,
+                 events=None, frame_shapes=None) -> int:
+        """Time both loop mappings on this input (synchronises) and keep the faster
+        for this batch shape; returns 1 (all iterations in one launch) or 0 (per step)."""
+        inp, o = self._io(out, frames, rows, cols, hist, off, ent, gain, events, frame_shapes)
+        fused = C.c_int32(0)
+        self._check(lib().rt3d_autotune(self._h, C.byref(inp), C.byref(o), _stream(), C.byref(fused)))
+        return int(fused.value)
 
     def graph(self, out: Result, frames: int, rows: int, cols: int, hist=None, off=None, ent=None, gain=None,
               events=None, frame_shapes=None) -> "Graph":

@@ -18,7 +18,7 @@ Inputs: config-1 plane (32 x 32 x 300), config-2 head shape (141 x 141 x
 import numpy as np
 import pytest
 
-from gpu_util import device_to_oracle, oracle_to_device, pair, to_dev_hist, u32
+from gpu_util import device_to_oracle, oracle_to_device, pair, params_for, to_dev_hist, u32
 
 pytestmark = pytest.mark.gpu
 
@@ -292,10 +292,13 @@ def _compare_final(sc, so, res, P):
     return frac, np.array(errs), cnt_g, depth, inten, pt_off
 
 
-@pytest.mark.parametrize("name", ["c1", "c2", "ragged"])
-def test_reconstruction_matches_oracle(name):
+@pytest.mark.parametrize("name,fused", [("c1", 1), ("c1", 0), ("c2", 1), ("ragged", 1), ("ragged", 0)])
+def test_reconstruction_matches_oracle(name, fused):
+    """fused = 1: frames of at most 4096 pixels (c1, ragged) run every iteration
+    in one launch; fused = 0: one launch per step (the path of larger frames)."""
     sc = scene(name)
-    O, ctx = pair(sc)
+    O, _ = pair(sc)
+    ctx = rt3d.Context(sc.irf.probs, sc.T, **params_for(sc), fused_loop=fused)
     off_o, ent_o = csr(sc)
     so = O.reconstruct(off_o, ent_o, oracle.State(1, sc.rows, sc.cols, 4))
     res = ctx.reconstruct(to_dev_hist(sc.Z)[None])
@@ -303,7 +306,7 @@ def test_reconstruction_matches_oracle(name):
     assert st.device_error == 0
     assert st.entries == len(ent_o)
     frac, errs, cnt_g, depth, inten, pt_off = _compare_final(sc, so, res, sc.rows * sc.cols)
-    print(f"[gpu-parity] {name}: count agreement {frac:.5f}, max depth err {errs.max():.2e} bins "
+    print(f"[gpu-parity] {name} (fused loop {fused}): count agreement {frac:.5f}, max depth err {errs.max():.2e} bins "
           f"over {len(errs)} pixels", flush=True)
     assert frac >= 0.999
     assert errs.max() <= 1e-3
@@ -320,6 +323,31 @@ def test_reconstruction_is_deterministic():
     for x, y in ((a.pt_off, b.pt_off), (a.depth, b.depth), (a.intensity, b.intensity),
                  (a.background, b.background)):
         assert torch.equal(x, y)
+
+
+def test_autotune_choice_is_kept_and_reconstructs_identically():
+    """rt3d_autotune times both loop mappings on a 64-frame batch of 32 x 32
+    frames and keeps one; later calls on that batch shape (fused_loop = -1)
+    give what a context forced to that mapping gives."""
+    scs = [synth.plane_scene(s) for s in range(4)]
+    sc = scs[0]
+    F, R, C = 64, sc.rows, sc.cols
+    Z = torch.stack([to_dev_hist(scs[f % 4].Z) for f in range(F)]).contiguous()
+    ctx = rt3d.Context(sc.irf.probs, sc.T, **params_for(sc))
+    ctx.workspace(F, R, C, F * R * C * 64)
+    out = ctx.make_output(F * R * C)
+    choice = ctx.autotune(out, F, R, C, hist=Z)
+    print(f"[gpu-parity] autotune: {'one launch' if choice else 'per step'} for {F} x {R} x {C}", flush=True)
+    assert choice in (0, 1)
+    ctx.reconstruct_into(out, F, R, C, hist=Z)
+    forced = rt3d.Context(sc.irf.probs, sc.T, **params_for(sc), fused_loop=choice)
+    ref = forced.reconstruct(Z)
+    assert ctx.query().device_error == 0 and forced.query().device_error == 0
+    for name in ("pt_off", "background"):
+        assert torch.equal(getattr(out, name), getattr(ref, name)), name
+    n = int(ref.pt_off[-1].item())
+    for name in ("depth", "intensity"):
+        assert torch.equal(getattr(out, name)[:n], getattr(ref, name)[:n]), name
 
 
 def test_batched_frames_equal_single_frames():
