@@ -207,6 +207,48 @@ def uneven_frames(reps=3):
     return res
 
 
+def hbm_regime(scenes, F=64):
+    """The gradient-step and APSS kernels where their data no longer fits the
+    256 MB MALL: F head-shaped frames per call (the entries alone take 4.3 MB
+    per frame).  Per kernel group: average launch time, algorithmic bytes per
+    launch and the fraction of the 8 TB/s HBM peak they make."""
+    import numpy as np
+    import torch
+
+    from paper_1905_06700_amd import rt3d
+
+    sc0 = scenes[0]
+    n = len(scenes)
+    Z = torch.stack([torch.from_numpy(scenes[f % n].Z.view(np.int16)) for f in range(F)]).cuda()
+    ctx = rt3d.Context(sc0.irf.probs, BINS, **scene_params(sc0))
+    ctx.workspace(F, ROWS, COLS, int(F * ROWS * COLS * 200))
+    P = F * ROWS * COLS
+    out = ctx.make_output(P)
+    ctx.reconstruct_into(out, F, ROWS, COLS, hist=Z)
+    st = ctx.query()
+    E, pts = int(st.entries), int(out.pt_off[-1].item())
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    ctx.reconstruct_into(out, F, ROWS, COLS, hist=Z)
+    e1.record()
+    torch.cuda.synchronize()
+    res = {"workload": f"{F} frames of {ROWS}x{COLS}x{BINS} per call (entries {E * 4 / 1e6:.0f} MB, past the MALL)",
+           "frames_per_s": round(F / (e0.elapsed_time(e1) / 1e3), 1)}
+    for g in ("depth", "intensity", "bkg", "apss"):
+        ctx.profile(g)
+        ctx.reconstruct_into(out, F, ROWS, COLS, hist=Z)
+        torch.cuda.synchronize()
+        ms, nl = ctx.profile_read()
+        ctx.profile(None)
+        avg = ms / max(int(nl), 1)
+        ab = algorithmic_bytes(g, F, ROWS * COLS, BINS, E, pts)
+        gbs = ab / (avg / 1e3) / 1e9
+        res[g] = {"avg_launch_us": round(avg * 1e3, 2), "algorithmic_bytes_per_launch": int(ab),
+                  "achieved_GBs": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
+    del Z
+    return res
+
+
 def learned_vs_apss(n_train=4, n_eval=4, steps=300, rows=256, cols=256, bins=1024):
     """Learned denoiser against plain APSS on multi-layer scenes: train on the
     GPU (the library's forward/backward kernels), then time and score both on
@@ -433,7 +475,8 @@ def main():
         "gbin_per_s": round(gbin, 2), "photon_bins_per_s": round(pbin, 1),
         "active_entries_per_frame": E // F, "points_per_frame": pts // F,
         "single_frame_latency_ms": round(latency_ms, 3), "single_frame_latency_graph_ms": round(latency_graph_ms, 3),
-        "small_frames": small_frames(), "uneven_frames": uneven_frames(), "wall_s": round(wall, 3),
+        "small_frames": small_frames(), "uneven_frames": uneven_frames(), "hbm_regime": hbm_regime(scenes),
+        "wall_s": round(wall, 3),
         "roofline": roofline, "kernels": kernels, "cpu_baseline": cpu,
         "learned_vs_apss": None if args.no_learned else learned_vs_apss(),
         "paper_context": {"frames_per_s": 76.9, "ms_per_frame": 13, "hardware": "NVIDIA Titan Xp",
