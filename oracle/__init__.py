@@ -131,6 +131,18 @@ def _declare(L):
     for name in ("or_iterate", "or_reconstruct"):
         getattr(L, name).argtypes = [C.c_void_p, _P, C.c_int, C.c_int, C.c_int, _u32p, _u32p,
                                      _dp, _dp, _dp, _dp, _ip, _dp]
+    _i = C.c_int
+    L.or_sr_nll.restype = C.c_double
+    L.or_sr_nll.argtypes = [C.c_void_p, _i, _i, _i, _i, _u32p, _u32p, _i, _dp, _dp, _ip, _dp, _dp]
+    L.or_sr_grad.argtypes = [C.c_void_p, _i, _i, _i, _i, _u32p, _u32p, _i, _dp, _dp, _ip, _dp, _dp,
+                             _dp, _dp, _dp, _dp, _dp, _dp]
+    L.or_sr_depth_step.argtypes = [C.c_void_p, _P, _i, _i, _i, _i, _u32p, _u32p, _dp, _dp, _dp, _ip, _dp]
+    L.or_sr_intensity_step.argtypes = [C.c_void_p, _P, _i, _i, _i, _i, _u32p, _u32p, _dp, _dp, _dp, _ip, _dp]
+    L.or_sr_bg_step.argtypes = [C.c_void_p, _P, _i, _i, _i, _i, _u32p, _u32p, _dp, _dp, _dp, _ip, _dp]
+    L.or_sr_expand.argtypes = [_i, _i, _i, _i, _i, _dp, _dp, _ip, _dp, _dp, _dp, _ip]
+    for name in ("or_sr_iterate", "or_sr_reconstruct"):
+        getattr(L, name).argtypes = [C.c_void_p, _P, _i, _i, _i, _i, _u32p, _u32p,
+                                     _dp, _dp, _dp, _dp, _ip, _dp]
 
 
 class Model:
@@ -239,6 +251,26 @@ class State:
         return s
 
 
+class SRState(State):
+    """Super-resolved state (Results, dynamic scenes): the point arrays t, r, n,
+    cnt of `State` on the point grid of (rows s) x (cols s) pixels per frame,
+    while b and g belong to the rows x cols lidar pixels."""
+
+    def __init__(self, F, rows, cols, s, K, g=None):
+        super().__init__(F, rows * s, cols * s, K)
+        self.s, self.lrows, self.lcols = s, rows, cols
+        nl = F * rows * cols
+        self.b = np.zeros(nl)
+        self.g = np.ones(nl) if g is None else np.ascontiguousarray(g, dtype=np.float64).reshape(-1)
+        assert self.g.size == nl
+
+    def copy(self) -> "SRState":
+        c = SRState(self.F, self.lrows, self.lcols, self.s, self.K, self.g.copy())
+        for a in ("t", "r", "n", "cnt", "b"):
+            setattr(c, a, getattr(self, a).copy())
+        return c
+
+
 class Oracle:
     """The oracle's steps bound to one IRF model and parameter set."""
 
@@ -320,4 +352,46 @@ class Oracle:
     def reconstruct(self, off, ent, s: State) -> State:
         lib().or_reconstruct(self.m._h, self._P, s.F, s.rows, s.cols, off, _ent(ent), s.g,
                              s.t, s.r, s.n, s.cnt, s.b)
+        return s
+
+    # -- super-resolution (s x s point-grid pixels per lidar pixel) ----------
+    def _sr(self, s: SRState):
+        return (s.s, s.F, s.lrows, s.lcols)
+
+    def sr_nll(self, off, ent, s: SRState) -> float:
+        return lib().or_sr_nll(self.m._h, *self._sr(s), off, _ent(ent), s.K, s.t, s.r, s.cnt, s.b, s.g)
+
+    def sr_grad(self, off, ent, s: SRState):
+        gt, gr = np.zeros_like(s.t), np.zeros_like(s.r)
+        at, ar = np.zeros_like(s.t), np.zeros_like(s.r)
+        gb, ab = np.zeros_like(s.b), np.zeros_like(s.b)
+        lib().or_sr_grad(self.m._h, *self._sr(s), off, _ent(ent), s.K, s.t, s.r, s.cnt, s.b, s.g,
+                         gt, gr, gb, at, ar, ab)
+        return (gt, gr, gb), (at, ar, ab)
+
+    def sr_depth_step(self, off, ent, s: SRState) -> SRState:
+        lib().or_sr_depth_step(self.m._h, self._P, *self._sr(s), off, _ent(ent), s.g, s.t, s.r, s.cnt, s.b)
+        return s
+
+    def sr_intensity_step(self, off, ent, s: SRState) -> SRState:
+        lib().or_sr_intensity_step(self.m._h, self._P, *self._sr(s), off, _ent(ent), s.g, s.t, s.r, s.cnt, s.b)
+        return s
+
+    def sr_bg_step(self, off, ent, s: SRState) -> SRState:
+        lib().or_sr_bg_step(self.m._h, self._P, *self._sr(s), off, _ent(ent), s.g, s.t, s.r, s.cnt, s.b)
+        return s
+
+    def sr_expand(self, coarse: State, s: SRState) -> SRState:
+        """The lidar-grid initialisation `coarse` spread over the point grid (normals facing the sensor)."""
+        lib().or_sr_expand(s.K, *self._sr(s), coarse.t, coarse.r, coarse.cnt, s.t, s.r, s.n, s.cnt)
+        s.b[:] = coarse.b
+        return s
+
+    def sr_iterate(self, off, ent, s: SRState) -> SRState:
+        lib().or_sr_iterate(self.m._h, self._P, *self._sr(s), off, _ent(ent), s.g, s.t, s.r, s.n, s.cnt, s.b)
+        return s
+
+    def sr_reconstruct(self, off, ent, s: SRState) -> SRState:
+        lib().or_sr_reconstruct(self.m._h, self._P, *self._sr(s), off, _ent(ent), s.g, s.t, s.r, s.n, s.cnt,
+                                s.b)
         return s

@@ -12,7 +12,9 @@
  *     threshold for intensity, identity or an FFT-style image filter for
  *     background;
  *   - Methods, "3D Reconstruction algorithm": per-pixel initialisation and
- *     gradient steps, cost linear in the number of active (non-zero) bins.
+ *     gradient steps, cost linear in the number of active (non-zero) bins;
+ *   - Results, dynamic scenes (and Discussion): the super-resolution map f,
+ *     several point-grid pixels per lidar pixel.
  * APSS (algebraic point set surfaces) is the sphere fit of the cited APSS
  * work, derived here from its least-squares definition.
  *
@@ -954,4 +956,289 @@ void or_reconstruct(const or_model* m, const or_params* p, int F, int rows, int 
     or_init(m, p, F, rows, cols, off, ent, g, t, r, n, cnt, b);
     or_init_normals(p, F, rows, cols, t, cnt, n);
     for (int it = 0; it < p->n_iter; ++it) or_iterate(m, p, F, rows, cols, off, ent, g, t, r, n, cnt, b);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Super-resolution (Results, dynamic scenes; Discussion)                    */
+/* ------------------------------------------------------------------------ */
+
+/* The map f may undersample: the point cloud lives on a grid s times finer
+ * than the lidar pixels, frame f holding (rows s) x (cols s) point-grid pixels,
+ * and the s x s point-grid pixels (i s + u, j s + v), 0 <= u, v < s, all map
+ * to lidar pixel (i, j).  Gain and background stay per lidar pixel; the
+ * lidar pixel's Poisson intensity adds the points of all its s^2 point-grid
+ * pixels:
+ *   lambda_{p,t} = g_p ( sum_{q -> p} sum_{n in q} r_n h(t - t_n) + b_p ).
+ * Point arrays (t, r, n, cnt) are indexed by point-grid pixel, b and g by
+ * lidar pixel; rows and cols below are the lidar frame's. */
+
+/* Point-grid pixel of sub-position u (row-major in the s x s block) of lidar
+ * pixel p. */
+static int64_t sr_sub(int s, int rows, int cols, int64_t p, int u)
+{
+    int64_t fr = p / ((int64_t)rows * cols);
+    int64_t i = (p / cols) % rows, j = p % cols;
+    int64_t fi = i * s + u / s, fj = j * s + u % s;
+    return (fr * rows * s + fi) * ((int64_t)cols * s) + fj;
+}
+
+static double sr_lambda(const or_model* m, int s, int rows, int cols, int K, int64_t p,
+                        const double* t, const double* r, const int* cnt, double b, double g, int tb)
+{
+    double acc = 0.0;
+    for (int u = 0; u < s * s; ++u) {
+        int64_t q = sr_sub(s, rows, cols, p, u);
+        for (int k = 0; k < cnt[q]; ++k) {
+            double h, hp;
+            h_eval(m, tb - t[q * K + k], &h, &hp);
+            acc += r[q * K + k] * h;
+        }
+    }
+    return g * (acc + b);
+}
+
+/* NLL of the super-resolved model (the same active-bin identity as or_nll:
+ * sum_t lambda_t = g (sum over the lidar pixel's points r S(t_n) + T b)). */
+double or_sr_nll(const or_model* m, int s, int F, int rows, int cols, const uint32_t* off,
+                 const uint32_t* ent, int K, const double* t, const double* r, const int* cnt,
+                 const double* b, const double* g)
+{
+    double total = 0.0;
+    int64_t npix = (int64_t)F * rows * cols;
+    for (int64_t p = 0; p < npix; ++p) {
+        if (!(g[p] > 0.0)) continue;
+        double sumS = 0.0;
+        for (int u = 0; u < s * s; ++u) {
+            int64_t q = sr_sub(s, rows, cols, p, u);
+            for (int k = 0; k < cnt[q]; ++k) {
+                double S, Sp;
+                S_eval(m, t[q * K + k], &S, &Sp);
+                sumS += r[q * K + k] * S;
+            }
+        }
+        double term = g[p] * (sumS + m->T * b[p]);
+        for (uint32_t e = off[p]; e < off[p + 1]; ++e) {
+            int tb = ent_t(ent[e]), z = ent_z(ent[e]);
+            term -= z * log(sr_lambda(m, s, rows, cols, K, p, t, r, cnt, b[p], g[p], tb));
+            term += lgamma(z + 1.0);
+        }
+        total += term;
+    }
+    return total;
+}
+
+/* Partial derivatives: a point n of point-grid pixel q -> p sees its lidar
+ * pixel's lambda,
+ *   d/dt_n = g_p r_n [ S'(t_n) + sum_{E_p} z h'(t - t_n)/lambda_{p,t} ]
+ *   d/dr_n = g_p     [ S(t_n)  - sum_{E_p} z h(t - t_n)/lambda_{p,t}  ]
+ *   d/db_p = g_p     [ T       - sum_{E_p} z / lambda_{p,t}           ]
+ * with the sums of the absolute values of the terms (at, ar, ab) as in or_grad.
+ * gt, gr, at, ar: [point-grid pixels][K]; gb, ab: [lidar pixels]. */
+void or_sr_grad(const or_model* m, int s, int F, int rows, int cols, const uint32_t* off,
+                const uint32_t* ent, int K, const double* t, const double* r, const int* cnt,
+                const double* b, const double* g, double* gt, double* gr, double* gb,
+                double* at, double* ar, double* ab)
+{
+    int64_t npix = (int64_t)F * rows * cols;
+    for (int64_t p = 0; p < npix; ++p) {
+        double G = g[p], sb = 0.0;
+        for (int u = 0; u < s * s; ++u) {
+            int64_t q = sr_sub(s, rows, cols, p, u);
+            for (int k = 0; k < K; ++k) {
+                int64_t x = q * K + k;
+                gt[x] = gr[x] = at[x] = ar[x] = 0.0;
+            }
+        }
+        if (G > 0.0)
+            for (uint32_t e = off[p]; e < off[p + 1]; ++e) {
+                int tb = ent_t(ent[e]), z = ent_z(ent[e]);
+                sb += z / sr_lambda(m, s, rows, cols, K, p, t, r, cnt, b[p], G, tb);
+            }
+        for (int u = 0; u < s * s && G > 0.0; ++u) {
+            int64_t q = sr_sub(s, rows, cols, p, u);
+            for (int k = 0; k < cnt[q]; ++k) {
+                int64_t x = q * K + k;
+                double st = 0.0, ast = 0.0, sr = 0.0;
+                for (uint32_t e = off[p]; e < off[p + 1]; ++e) {
+                    int tb = ent_t(ent[e]), z = ent_z(ent[e]);
+                    double lam = sr_lambda(m, s, rows, cols, K, p, t, r, cnt, b[p], G, tb);
+                    double h, hp;
+                    h_eval(m, tb - t[x], &h, &hp);
+                    st += z * hp / lam;
+                    ast += z * fabs(hp) / lam;
+                    sr += z * h / lam;
+                }
+                double S, Sp, asp = 0.0;
+                S_eval(m, t[x], &S, &Sp);
+                for (int tt = 0; tt < m->T; ++tt) {
+                    double h, hp;
+                    h_eval(m, tt - t[x], &h, &hp);
+                    asp += fabs(hp);
+                }
+                gt[x] = G * r[x] * (Sp + st);
+                at[x] = G * fabs(r[x]) * (asp + ast);
+                gr[x] = G * (S - sr);
+                ar[x] = G * (S + sr);
+            }
+        }
+        gb[p] = G > 0.0 ? G * (m->T - sb) : 0.0;
+        ab[p] = G > 0.0 ? G * (m->T + sb) : 0.0;
+    }
+}
+
+/* The three gradient steps of or_depth_step / or_intensity_step / or_bg_step
+ * under the super-resolved lambda (same step sizes; Jacobi: every point of a
+ * lidar pixel sees lambda from before the step). */
+void or_sr_depth_step(const or_model* m, const or_params* p, int s, int F, int rows, int cols,
+                      const uint32_t* off, const uint32_t* ent, const double* g,
+                      double* t, const double* r, const int* cnt, const double* b)
+{
+    int K = p->k_max;
+    int64_t npix = (int64_t)F * rows * cols, nfine = npix * s * s;
+    double dmax = p->dmax > 0.0 ? p->dmax : fmax(0.5, 1.0 / sqrt(m->fisher));
+    double* t0 = (double*)malloc(sizeof(double) * nfine * K);
+    memcpy(t0, t, sizeof(double) * nfine * K);
+    for (int64_t pix = 0; pix < npix; ++pix) {
+        double G = g[pix];
+        if (!(G > 0.0)) continue;
+        for (int u = 0; u < s * s; ++u) {
+            int64_t q = sr_sub(s, rows, cols, pix, u);
+            for (int k = 0; k < cnt[q]; ++k) {
+                int64_t x = q * K + k;
+                if (!(r[x] > 0.0)) continue;
+                double acc = 0.0;
+                for (uint32_t e = off[pix]; e < off[pix + 1]; ++e) {
+                    int tb = ent_t(ent[e]), z = ent_z(ent[e]);
+                    double lam = sr_lambda(m, s, rows, cols, K, pix, t0, r, cnt, b[pix], G, tb);
+                    double h, hp;
+                    h_eval(m, tb - t0[x], &h, &hp);
+                    acc += z * hp / lam;
+                }
+                double S, Sp;
+                S_eval(m, t0[x], &S, &Sp);
+                double step = -p->beta_t * (Sp + acc) / m->fisher;
+                if (step > dmax) step = dmax;
+                if (step < -dmax) step = -dmax;
+                double tn = t0[x] + step;
+                if (tn < 0.0) tn = 0.0;
+                if (tn > m->T - 1) tn = m->T - 1;
+                t[x] = tn;
+            }
+        }
+    }
+    free(t0);
+}
+
+void or_sr_intensity_step(const or_model* m, const or_params* p, int s, int F, int rows, int cols,
+                          const uint32_t* off, const uint32_t* ent, const double* g,
+                          const double* t, double* r, const int* cnt, const double* b)
+{
+    int K = p->k_max;
+    int64_t npix = (int64_t)F * rows * cols, nfine = npix * s * s;
+    double* r0 = (double*)malloc(sizeof(double) * nfine * K);
+    memcpy(r0, r, sizeof(double) * nfine * K);
+    for (int64_t pix = 0; pix < npix; ++pix) {
+        double G = g[pix];
+        if (!(G > 0.0)) continue;
+        for (int u = 0; u < s * s; ++u) {
+            int64_t q = sr_sub(s, rows, cols, pix, u);
+            for (int k = 0; k < cnt[q]; ++k) {
+                int64_t x = q * K + k;
+                double S, Sp;
+                S_eval(m, t[x], &S, &Sp);
+                if (!(S > 0.0)) continue;
+                double acc = 0.0;
+                for (uint32_t e = off[pix]; e < off[pix + 1]; ++e) {
+                    int tb = ent_t(ent[e]), z = ent_z(ent[e]);
+                    double lam = sr_lambda(m, s, rows, cols, K, pix, t, r0, cnt, b[pix], G, tb);
+                    double h, hp;
+                    h_eval(m, tb - t[x], &h, &hp);
+                    acc += z * h / lam;
+                }
+                double v = r0[x] * ((1.0 - p->beta_r) + p->beta_r * acc / S);
+                r[x] = v > 0.0 ? v : 0.0;
+            }
+        }
+    }
+    free(r0);
+}
+
+void or_sr_bg_step(const or_model* m, const or_params* p, int s, int F, int rows, int cols,
+                   const uint32_t* off, const uint32_t* ent, const double* g,
+                   const double* t, const double* r, const int* cnt, double* b)
+{
+    int K = p->k_max;
+    int64_t npix = (int64_t)F * rows * cols;
+    for (int64_t pix = 0; pix < npix; ++pix) {
+        double G = g[pix];
+        if (!(G > 0.0)) continue;
+        double acc = 0.0;
+        for (uint32_t e = off[pix]; e < off[pix + 1]; ++e) {
+            int tb = ent_t(ent[e]), z = ent_z(ent[e]);
+            acc += z / sr_lambda(m, s, rows, cols, K, pix, t, r, cnt, b[pix], G, tb);
+        }
+        double v = b[pix] * ((1.0 - p->beta_b) + p->beta_b * acc / m->T);
+        b[pix] = v > p->b_min ? v : p->b_min;
+    }
+}
+
+/* Initial point-grid state (reading; the paper does not say how the finer
+ * cloud starts): every point-grid pixel takes the points its lidar pixel's
+ * initialisation found (tc, rc, cntc, lidar-pixel arrays), with the intensity
+ * shared equally over the s^2 point-grid pixels so that lambda is unchanged.
+ * Normals face the sensor until or_init_normals fits them on the point grid. */
+void or_sr_expand(int K, int s, int F, int rows, int cols, const double* tc, const double* rc,
+                  const int* cntc, double* t, double* r, double* n, int* cnt)
+{
+    int64_t npix = (int64_t)F * rows * cols;
+    for (int64_t p = 0; p < npix; ++p)
+        for (int u = 0; u < s * s; ++u) {
+            int64_t q = sr_sub(s, rows, cols, p, u);
+            cnt[q] = cntc[p];
+            for (int k = 0; k < K; ++k) {
+                int live = k < cntc[p];
+                t[q * K + k] = live ? tc[p * K + k] : 0.0;
+                r[q * K + k] = live ? rc[p * K + k] / ((double)s * s) : 0.0;
+                n[(q * K + k) * 3 + 0] = 0.0;
+                n[(q * K + k) * 3 + 1] = 0.0;
+                n[(q * K + k) * 3 + 2] = -1.0;
+            }
+        }
+}
+
+/* One iteration with the super-resolved data term: the depth, intensity and
+ * background gradient steps see lidar pixels; APSS, the merge and the
+ * intensity low-pass act on the point grid; the background filter on the
+ * lidar grid. */
+void or_sr_iterate(const or_model* m, const or_params* p, int s, int F, int rows, int cols,
+                   const uint32_t* off, const uint32_t* ent, const double* g,
+                   double* t, double* r, double* n, int* cnt, double* b)
+{
+    int64_t nfine = (int64_t)F * rows * cols * s * s;
+    or_sr_depth_step(m, p, s, F, rows, cols, off, ent, g, t, r, cnt, b);
+    if (p->use_apss) or_apss(p, F, rows * s, cols * s, m->T, t, n, cnt);
+    or_merge(m, p, nfine, t, r, n, cnt);
+    or_sr_intensity_step(m, p, s, F, rows, cols, off, ent, g, t, r, cnt, b);
+    or_intensity_filter(p, F, rows * s, cols * s, t, r, n, cnt);
+    or_sr_bg_step(m, p, s, F, rows, cols, off, ent, g, t, r, cnt, b);
+    or_bg_filter(p, F, rows, cols, b);
+}
+
+/* Initialisation on the lidar grid (or_init), expansion to the point grid,
+ * normals there, then n_iter iterations. */
+void or_sr_reconstruct(const or_model* m, const or_params* p, int s, int F, int rows, int cols,
+                       const uint32_t* off, const uint32_t* ent, const double* g,
+                       double* t, double* r, double* n, int* cnt, double* b)
+{
+    int K = p->k_max;
+    int64_t npix = (int64_t)F * rows * cols;
+    double* tc = (double*)calloc((size_t)npix * K, sizeof(double));
+    double* rc = (double*)calloc((size_t)npix * K, sizeof(double));
+    double* nc = (double*)calloc((size_t)npix * K * 3, sizeof(double));
+    int* cntc = (int*)calloc((size_t)npix, sizeof(int));
+    or_init(m, p, F, rows, cols, off, ent, g, tc, rc, nc, cntc, b);
+    or_sr_expand(K, s, F, rows, cols, tc, rc, cntc, t, r, n, cnt);
+    or_init_normals(p, F, rows * s, cols * s, t, cnt, n);
+    for (int it = 0; it < p->n_iter; ++it) or_sr_iterate(m, p, s, F, rows, cols, off, ent, g, t, r, n, cnt, b);
+    free(tc); free(rc); free(nc); free(cntc);
 }

@@ -119,6 +119,36 @@ void or_reconstruct(const or_model* m, const or_params* p, int F, int rows, int 
                     const uint32_t* off, const uint32_t* ent, const double* g,
                     double* t, double* r, double* n, int* cnt, double* b);
 
+/* Super-resolution (Results, dynamic scenes): s x s point-grid pixels per
+ * lidar pixel.  rows, cols are the lidar frame's; t, r, n, cnt (and gt, gr,
+ * at, ar) are indexed by point-grid pixel of the (rows s) x (cols s) frames,
+ * b and g (and gb, ab) by lidar pixel.  s = 1 is the plain model. */
+double or_sr_nll(const or_model* m, int s, int F, int rows, int cols, const uint32_t* off,
+                 const uint32_t* ent, int K, const double* t, const double* r, const int* cnt,
+                 const double* b, const double* g);
+void or_sr_grad(const or_model* m, int s, int F, int rows, int cols, const uint32_t* off,
+                const uint32_t* ent, int K, const double* t, const double* r, const int* cnt,
+                const double* b, const double* g, double* gt, double* gr, double* gb,
+                double* at, double* ar, double* ab);
+void or_sr_depth_step(const or_model* m, const or_params* p, int s, int F, int rows, int cols,
+                      const uint32_t* off, const uint32_t* ent, const double* g,
+                      double* t, const double* r, const int* cnt, const double* b);
+void or_sr_intensity_step(const or_model* m, const or_params* p, int s, int F, int rows, int cols,
+                          const uint32_t* off, const uint32_t* ent, const double* g,
+                          const double* t, double* r, const int* cnt, const double* b);
+void or_sr_bg_step(const or_model* m, const or_params* p, int s, int F, int rows, int cols,
+                   const uint32_t* off, const uint32_t* ent, const double* g,
+                   const double* t, const double* r, const int* cnt, double* b);
+void or_sr_expand(int K, int s, int F, int rows, int cols, const double* tc, const double* rc,
+                  const int* cntc, double* t, double* r, double* n, int* cnt);
+/* parity unpinned as a whole (like or_iterate / or_reconstruct) */
+void or_sr_iterate(const or_model* m, const or_params* p, int s, int F, int rows, int cols,
+                   const uint32_t* off, const uint32_t* ent, const double* g,
+                   double* t, double* r, double* n, int* cnt, double* b);
+void or_sr_reconstruct(const or_model* m, const or_params* p, int s, int F, int rows, int cols,
+                       const uint32_t* off, const uint32_t* ent, const double* g,
+                       double* t, double* r, double* n, int* cnt, double* b);
+
 #ifdef __cplusplus
 }
 #endif

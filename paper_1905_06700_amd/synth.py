@@ -246,6 +246,41 @@ def layers_scene(scene: int = 0, rows: int = 256, cols: int = 256, T: int = 1024
                       r_init=1, k_init=4))
 
 
+def sr_scene(scene: int = 0, rows: int = 32, cols: int = 32, s: int = 3, T: int = 153, signal: float = 3.0,
+             sbr: float = 0.5, theta=None, config: int = 3) -> Scene:
+    """Super-resolution scene (the paper's 32 x 32 x 153 array video, whose
+    point cloud is estimated on a grid three times finer): the truth lives on
+    the (rows s) x (cols s) point grid -- a tilted background plane spanning
+    bins 0.45 T .. 0.75 T and a disc (radius a quarter of the frame) 25 bins
+    nearer whose centre moves with `scene` (video frames) -- and each lidar
+    pixel collects the photons of its s x s point-grid pixels.  Gaussian IRF
+    sigma 1.5 bins; mean `signal` photons per lidar pixel at the given SBR;
+    reflectivity U[0.5, 1].  `depth` / `intensity` are the point grid's;
+    Z [rows, cols, T] is the lidar's.  meta p_xy = 1 world unit per
+    point-grid pixel, dz = 0.1 s (the lidar pixel pitch s world units)."""
+    rng = np.random.default_rng(seed_of(config, 500 + scene))
+    irf = gaussian_irf(1.5, 9)
+    R, C = rows * s, cols * s
+    th = rng.uniform(0.0, np.pi / 2) if theta is None else float(theta)
+    i, j = np.mgrid[0:R, 0:C].astype(np.float64)
+    u = j * np.cos(th) + i * np.sin(th)
+    span = u.max() - u.min()
+    plane = T * (0.45 + 0.30 * (u - u.min()) / (span if span > 0 else 1.0))
+    ph = 2.0 * np.pi * scene / 50.0
+    ci, cj = R * (0.5 + 0.2 * np.sin(ph)), C * (0.5 + 0.2 * np.cos(ph))
+    disc = (i - ci) ** 2 + (j - cj) ** 2 < (0.25 * min(R, C)) ** 2
+    depth = np.where(disc, plane - 25.0, plane)[None]
+    rho = rng.uniform(0.5, 1.0, (1, R, C))
+    inten = rho * (signal / (s * s)) / 0.75
+    b = signal / sbr / T
+    Zf = render(rng, irf, T, depth, inten, b / (s * s))
+    Z = Zf.reshape(rows, s, cols, s, T).sum(axis=(1, 3), dtype=np.int64)
+    assert Z.max(initial=0) < 65535
+    return Scene(Z.astype(np.uint16), irf, T, depth, inten, b,
+                 dict(config=config, sr=s, dz=0.1 * s, p_xy=1.0, mean_signal=signal,
+                      r_min=0.2 * signal / (s * s), r_init=0, k_init=3))
+
+
 def random_gain(rng_seed: int, rows: int, cols: int, dead_frac: float = 0.02) -> np.ndarray:
     """Per-pixel detector gain in [0.5, 1.5] with a fraction of dead (0) pixels."""
     rng = np.random.default_rng(rng_seed)
