@@ -91,6 +91,19 @@ typedef struct rt3d_params {
                           * (when eligible); 0: never; -1 (default): the choice rt3d_autotune
                           * measured for this batch shape, else when the batch holds at least
                           * 64 frames (fewer frames leave most compute units idle) */
+    int32_t  sr;         /* super-resolution factor s, 1..4 (1): the point cloud is estimated on a
+                          * grid s times finer than the lidar pixels (Results, dynamic scenes: the
+                          * map f sends s x s point-grid pixels to one lidar pixel, whose Poisson
+                          * intensity adds all their points; gain and background stay per lidar
+                          * pixel).  With s > 1: rows and cols of rt3d_input, the histograms, CSR,
+                          * gain, events and rt3d_set_workspace are the lidar's; the output's
+                          * pt_off has F (rows s) (cols s) + 1 entries over point-grid pixels
+                          * (pixel (f, i, j) of the (rows s) x (cols s) frames) and its background
+                          * F rows cols; p_xy is the point grid's pitch; the initialisation runs on
+                          * the lidar grid and every point-grid pixel starts from its lidar pixel's
+                          * points with 1/s^2 of the intensity.  Frames of one size only
+                          * (E_UNSUPPORTED with frame_rows / frame_cols), no learned denoiser
+                          * (E_UNSUPPORTED at create), per-step kernels only (fused_loop ignored). */
 } rt3d_params;
 
 /* Input kinds. */
@@ -150,6 +163,8 @@ typedef struct rt3d_output {
     float*    normal;          /* device [capacity * 3] or NULL: unit surface normal (x, y, z) */
     float*    background;      /* device [P]: background in photons per bin */
 } rt3d_output;
+/* (With params.sr = s > 1, P above is the point grid's pixel count for pt_off
+ * and the lidar's for background; see rt3d_params.sr.) */
 
 /* Per-point state in device memory, slot-major structure of arrays, as the
  * library keeps it between steps; used by the step-by-step entry points. */
@@ -161,6 +176,9 @@ typedef struct rt3d_state {
     uint8_t* cnt;   /* [P] live slots 0..cnt-1, ascending depth */
     float*   b;     /* [P] background */
 } rt3d_state;
+/* With params.sr = s > 1 a state describes the point grid (rows and cols are
+ * the point grid's, multiples of s) and b[0 .. frames (rows/s) (cols/s) - 1]
+ * holds the lidar pixels' background (the rest of b is unused). */
 
 typedef struct rt3d_stats {
     uint32_t struct_size;      /* sizeof(rt3d_stats) */
@@ -294,7 +312,12 @@ rt3d_status rt3d_debug_compact_events(rt3d_ctx* ctx, const uint32_t* ev_pixel, c
                                       uint32_t* ent, uint64_t capacity, void* hip_stream);
 
 /* Steps.  `in` is read, `out` is written in full (it must not alias `in`);
- * off/ent are the active-bin lists, gain may be NULL. */
+ * off/ent are the active-bin lists, gain may be NULL.  With params.sr = s > 1
+ * the states are point-grid states (see rt3d_state), off/ent/gain the lidar
+ * pixels'; the gradient steps use the super-resolved lambda, the background
+ * filter acts on the lidar background, and the initialisation runs on the
+ * lidar grid before its points spread over the point grid (it needs a
+ * workspace for the lidar frames). */
 #define RT3D_STEP_INIT       0  /* log-matched-filter initialisation + initial normals (reads no state) */
 #define RT3D_STEP_DEPTH      1  /* gradient step on depth */
 #define RT3D_STEP_APSS       2  /* APSS depth denoiser */
@@ -310,7 +333,8 @@ rt3d_status rt3d_debug_step(rt3d_ctx* ctx, int32_t step, const uint32_t* off, co
 
 /* Raw partial derivatives of the negative log-likelihood (Results,
  * "Observation model"): gt, gr device float [RT3D_K_MAX][P] (slots >= cnt
- * written 0), gb device float [P]. */
+ * written 0), gb device float [P] (with params.sr = s > 1: P point-grid
+ * pixels for gt, gr and the lidar pixels for gb). */
 rt3d_status rt3d_debug_gradients(rt3d_ctx* ctx, const uint32_t* off, const uint32_t* ent,
                                  const float* gain, const rt3d_state* st,
                                  float* gt, float* gr, float* gb, void* hip_stream);

@@ -15,7 +15,7 @@ LIB = os.path.join(HERE, "librt3d.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["rt3d_host.cpp", "k_compact.hip", "k_init.hip", "k_steps.hip", "k_apss.hip", "k_filter.hip",
-           "k_cnn.hip", "k_events.hip", "k_loop.hip"]
+           "k_cnn.hip", "k_events.hip", "k_loop.hip", "k_sr.hip"]
 FLAGS = ["-O3", "--offload-arch=gfx950", "-fPIC", "-std=c++17",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-result"]

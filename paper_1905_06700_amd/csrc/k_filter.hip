@@ -243,7 +243,7 @@ __global__ __launch_bounds__(256) void k_out_count(Shape sh, const uint8_t* __re
 __global__ __launch_bounds__(256) void k_out_pack(Shape sh, DevState s, const uint32_t* __restrict__ pt_off,
                                                   uint32_t capacity, double* __restrict__ depth,
                                                   float* __restrict__ inten, float* __restrict__ normal,
-                                                  float* __restrict__ bg, int32_t* __restrict__ err)
+                                                  float* __restrict__ bg, long long n_bg, int32_t* __restrict__ err)
 {
     const long long P = sh.P;
     const long long pix = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -264,7 +264,7 @@ __global__ __launch_bounds__(256) void k_out_pack(Shape sh, DevState s, const ui
             for (int a = 0; a < 3; ++a) normal[at * 3 + a] = s.n[(a * KM + k) * P + pix];
         }
     }
-    bg[pix] = s.b[pix];
+    if (pix < n_bg) bg[pix] = s.b[pix];
     if (overflow) *err = RT3D_E_CAPACITY;
 }
 
@@ -322,7 +322,7 @@ hipError_t launch_copy_state(const Shape& sh, DevState in, DevState out, hipStre
 }
 
 hipError_t launch_output(const Shape& sh, DevState s, rt3d_output* out, uint32_t* counts, uint32_t* partial,
-                         int32_t* err, hipStream_t st)
+                         int32_t* err, long long n_bg, hipStream_t st)
 {
     if (sh.P > 0)
         hipLaunchKernelGGL(k_out_count, dim3(nblk(sh.P)), dim3(256), 0, st, sh, s.cnt, counts);
@@ -330,7 +330,7 @@ hipError_t launch_output(const Shape& sh, DevState s, rt3d_output* out, uint32_t
     if (e != hipSuccess) return e;
     if (sh.P > 0)
         hipLaunchKernelGGL(k_out_pack, dim3(nblk(sh.P)), dim3(256), 0, st, sh, s, out->pt_off, out->capacity,
-                           out->depth, out->intensity, out->normal, out->background, err);
+                           out->depth, out->intensity, out->normal, out->background, n_bg, err);
     return hipGetLastError();
 }
 

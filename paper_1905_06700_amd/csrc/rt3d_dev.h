@@ -526,7 +526,23 @@ hipError_t launch_loop(const DevModel& m, const DevParams& p, const Shape& sh, c
                        const uint32_t* ent, const float* gain, DevState A, DevState B, float* bt, const float* w,
                        int rb, int n_iter, hipStream_t st);
 
+// n_bg: background values written (sh.P, or the lidar pixels under super-resolution)
 hipError_t launch_output(const Shape& sh, DevState s, rt3d_output* out, uint32_t* counts,
-                         uint32_t* partial, int32_t* err, hipStream_t st);
+                         uint32_t* partial, int32_t* err, long long n_bg, hipStream_t st);
+
+// Super-resolution: s x s point-grid pixels per lidar pixel.  lid: the lidar
+// frames; the state's point arrays have slot stride Pf (point-grid pixels),
+// its b[0 .. lid.P - 1] is the lidar background.  step: RT3D_STEP_DEPTH,
+// _INTENSITY or _BKG (bdst: where the new background goes, nullptr: st.b).
+constexpr int SR_MAX = 4;
+hipError_t launch_sr_step(int step, const DevModel& m, const DevParams& p, const Shape& lid, int s, long long Pf,
+                          const uint32_t* off, const uint32_t* ent, const float* gain, DevState st, float* bdst,
+                          hipStream_t stream);
+// gt, gr: [KM][Pf], gb: [lid.P]
+hipError_t launch_sr_gradients(const DevModel& m, const DevParams& p, const Shape& lid, int s, long long Pf,
+                               const uint32_t* off, const uint32_t* ent, const float* gain, DevState st, float* gt,
+                               float* gr, float* gb, hipStream_t stream);
+// lid (slot stride lid.P) spread over the point grid into out (stride Pf)
+hipError_t launch_sr_expand(const Shape& lsh, int s, long long Pf, DevState lid, DevState out, hipStream_t stream);
 
 }  // namespace rt3d

@@ -87,9 +87,10 @@ struct Workspace {
     size_t bytes;
 };
 
-// Carves the workspace for P pixels and E entries; with base == nullptr it
-// only measures.
-Workspace carve(uint8_t* base, long long P, uint64_t E, bool with_cnn = false, unsigned cnn_groups = 0)
+// Carves the workspace for P pixels (Ps >= P of them in the point state:
+// more under super-resolution) and E entries; with base == nullptr it only
+// measures.
+Workspace carve(uint8_t* base, long long P, long long Ps, uint64_t E, bool with_cnn = false, unsigned cnn_groups = 0)
 {
     Workspace w{};
     size_t at = 0;
@@ -101,16 +102,16 @@ Workspace carve(uint8_t* base, long long P, uint64_t E, bool with_cnn = false, u
     w.err = (int32_t*)take(sizeof(int32_t) * 4);
     w.off = (uint32_t*)take(sizeof(uint32_t) * (P + 1));
     w.ent = (uint32_t*)take(sizeof(uint32_t) * std::max<uint64_t>(E, 1));
-    w.counts = (uint32_t*)take(sizeof(uint32_t) * std::max<long long>(P, 1));
-    w.partial = (uint32_t*)take(sizeof(uint32_t) * scan_partial_elems(P));
+    w.counts = (uint32_t*)take(sizeof(uint32_t) * std::max<long long>(Ps, 1));
+    w.partial = (uint32_t*)take(sizeof(uint32_t) * scan_partial_elems(Ps));
     w.evoff = (uint32_t*)take(sizeof(uint32_t) * (P + 1));
     w.stage = (uint32_t*)take(sizeof(uint32_t) * CP_STAGE * std::max<long long>(P, 1));
     for (DevState* s : {&w.A, &w.B}) {
-        s->t = (double*)take(sizeof(double) * KM * P);
-        s->r = (float*)take(sizeof(float) * KM * P);
-        s->n = (float*)take(sizeof(float) * 3 * KM * P);
-        s->cnt = (uint8_t*)take(P);
-        s->b = (float*)take(sizeof(float) * P);
+        s->t = (double*)take(sizeof(double) * KM * Ps);
+        s->r = (float*)take(sizeof(float) * KM * Ps);
+        s->n = (float*)take(sizeof(float) * 3 * KM * Ps);
+        s->cnt = (uint8_t*)take(Ps);
+        s->b = (float*)take(sizeof(float) * Ps);
     }
     w.btmp = (float*)take(sizeof(float) * P);
     if (with_cnn) {
@@ -238,6 +239,10 @@ rt3d_status check_params(const rt3d_params* p, uint32_t bins, std::string& why)
     if (!(p->sbr_guess > 0)) { why = "sbr_guess must be > 0"; return RT3D_E_INVALID; }
     if (p->r_init < 0 || p->r_init > 8) { why = "r_init outside 0..8"; return RT3D_E_INVALID; }
     if (p->fused_loop < -1 || p->fused_loop > 1) { why = "fused_loop must be -1, 0 or 1"; return RT3D_E_INVALID; }
+    if (p->sr < 1 || p->sr > SR_MAX) { why = "sr outside 1..4"; return RT3D_E_INVALID; }
+    if (p->sr > 1 && p->denoiser == RT3D_DENOISE_CNN) {
+        why = "super-resolution with the learned denoiser"; return RT3D_E_UNSUPPORTED;
+    }
     if (p->denoiser != RT3D_DENOISE_APSS && p->denoiser != RT3D_DENOISE_NONE && p->denoiser != RT3D_DENOISE_CNN) {
         why = "unknown denoiser"; return RT3D_E_UNSUPPORTED;
     }
@@ -265,7 +270,8 @@ Workspace carve_ctx(const rt3d_ctx* c, uint8_t* base, long long P, uint64_t E, u
         sh.S = P;
         groups = cnn_wgrad_groups(sh);
     }
-    return carve(base, P, E, uses_cnn(c), groups);
+    const long long sr = c->p.sr;
+    return carve(base, P, P * sr * sr, E, uses_cnn(c), groups);
 }
 
 rt3d_status need_ws(rt3d_ctx* c, long long P, Workspace& w)
@@ -369,6 +375,58 @@ rt3d_status iterate(rt3d_ctx* c, const Shape& sh, const std::vector<Group>& grou
     return RT3D_OK;
 }
 
+// The point grid of lidar frames `lid` under super-resolution factor sr.
+Shape point_grid(const Shape& lid, int sr)
+{
+    Shape f = lid;
+    f.rows = lid.rows * sr;
+    f.cols = lid.cols * sr;
+    f.P = (long long)f.F * f.rows * f.cols;
+    f.S = f.P;
+    return f;
+}
+
+// One iteration under super-resolution: the gradient steps per lidar pixel
+// (lid), APSS, merge and intensity filter on the point grid (fsh), the
+// background filter on the lidar grid (the lidar background is A.b[0 .. lid.P)).
+rt3d_status iterate_sr(rt3d_ctx* c, const Shape& lid, const uint32_t* off, const uint32_t* ent, const float* gain,
+                       DevState A, DevState B, float* btmp, hipStream_t st)
+{
+    const DevModel m = dev_model(c);
+    const DevParams p = dev_params(c);
+    const int sr = c->p.sr;
+    const Shape fsh = point_grid(lid, sr);
+    RT3D_LAUNCH(c, RT3D_KERNEL_DEPTH, st,
+                launch_sr_step(RT3D_STEP_DEPTH, m, p, lid, sr, fsh.P, off, ent, gain, A, nullptr, st));
+    if (c->p.denoiser == RT3D_DENOISE_APSS)
+        RT3D_LAUNCH(c, RT3D_KERNEL_APSS, st, launch_apss(m, p, fsh, A, B, -1, st));
+    else
+        RT3D_HIP(c, launch_copy_state(fsh, A, B, st));
+    RT3D_LAUNCH(c, RT3D_KERNEL_MERGE, st, launch_merge(p, fsh, B, st));
+    RT3D_LAUNCH(c, RT3D_KERNEL_INTENSITY, st,
+                launch_sr_step(RT3D_STEP_INTENSITY, m, p, lid, sr, fsh.P, off, ent, gain, B, nullptr, st));
+    RT3D_LAUNCH(c, RT3D_KERNEL_IFILTER, st, launch_ifilter(p, fsh, B, A, st));
+    RT3D_LAUNCH(c, RT3D_KERNEL_BKG, st,
+                launch_sr_step(RT3D_STEP_BKG, m, p, lid, sr, fsh.P, off, ent, gain, A, btmp, st));
+    RT3D_LAUNCH(c, RT3D_KERNEL_BFILTER, st,
+                launch_bfilter(c->d_bw, c->rb, lid, (float)c->p.b_min, btmp, A.b, B.b, st));
+    return RT3D_OK;
+}
+
+// Initialisation under super-resolution: the lidar-grid initialisation into
+// B (slot stride lid.P), spread over the point grid into A, normals there.
+rt3d_status init_sr(rt3d_ctx* c, const Shape& lid, const uint32_t* off, const uint32_t* ent, const float* gain,
+                    DevState A, DevState B, int32_t* err, hipStream_t st)
+{
+    const DevModel m = dev_model(c);
+    const DevParams p = dev_params(c);
+    const Shape fsh = point_grid(lid, c->p.sr);
+    RT3D_LAUNCH(c, RT3D_KERNEL_INIT, st, launch_init(m, p, lid, off, ent, gain, B, err, st));
+    RT3D_HIP(c, launch_sr_expand(lid, c->p.sr, fsh.P, B, A, st));
+    RT3D_LAUNCH(c, RT3D_KERNEL_NORMALS, st, launch_init_normals(p, fsh, A, st));
+    return RT3D_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -401,6 +459,7 @@ void rt3d_params_default(rt3d_params* p)
     p->m_min = 3;
     p->denoiser = RT3D_DENOISE_APSS;
     p->fused_loop = -1;
+    p->sr = 1;
 }
 
 rt3d_status rt3d_create(const double* irf, uint32_t irf_len, int32_t irf_origin, uint32_t bins,
@@ -773,6 +832,7 @@ rt3d_status rt3d_reconstruct(rt3d_ctx* c, const rt3d_input* in, rt3d_output* out
         sh = shape_of(1, 1, (uint32_t)P);
         if (groups.size() > 1 && c->p.denoiser == RT3D_DENOISE_CNN)
             return fail(c, RT3D_E_UNSUPPORTED, "the learned denoiser needs frames of one size");
+        if (c->p.sr > 1) return fail(c, RT3D_E_UNSUPPORTED, "super-resolution needs frames of one size");
     } else {
         if (!shape_ok(in->frames, in->rows, in->cols))
             return fail(c, RT3D_E_INVALID, "frames x rows x cols must be in 1 .. 2^31-1");
@@ -780,6 +840,8 @@ rt3d_status rt3d_reconstruct(rt3d_ctx* c, const rt3d_input* in, rt3d_output* out
         groups.push_back(Group{0, sh});
     }
     if (groups.size() == 1) sh = groups[0].sh;
+    if (sh.P * c->p.sr * c->p.sr >= (1ll << 31))
+        return fail(c, RT3D_E_INVALID, "the point grid's pixels must total below 2^31");
     const std::vector<long long> prev_layout = c->state_layout;   // need_ws forgets it
     Workspace w;
     rt3d_status s = need_ws(c, sh.P, w);
@@ -822,6 +884,9 @@ rt3d_status rt3d_reconstruct(rt3d_ctx* c, const rt3d_input* in, rt3d_output* out
     if (in->flags & RT3D_FLAG_WARM_START) {
         if (layout != prev_layout)
             return fail(c, RT3D_E_STATE, "warm start: no final state of a batch of these frames in the workspace");
+    } else if (c->p.sr > 1) {
+        s = init_sr(c, sh, off, ent, in->gain, w.A, w.B, w.err, st);
+        if (s != RT3D_OK) return s;
     } else {
         for (const Group& g : groups)
             RT3D_LAUNCH(c, RT3D_KERNEL_INIT, st,
@@ -831,7 +896,12 @@ rt3d_status rt3d_reconstruct(rt3d_ctx* c, const rt3d_input* in, rt3d_output* out
             RT3D_LAUNCH(c, RT3D_KERNEL_NORMALS, st, launch_init_normals(p, g.sh, state_at(w.A, g.base), st));
     }
     c->state_layout.clear();
-    if (loop_eligible(c, groups, sh) && use_fused(c, sh)) {
+    if (c->p.sr > 1) {
+        for (int it = 0; it < c->p.n_iter; ++it) {
+            s = iterate_sr(c, sh, off, ent, in->gain, w.A, w.B, w.btmp, st);
+            if (s != RT3D_OK) return s;
+        }
+    } else if (loop_eligible(c, groups, sh) && use_fused(c, sh)) {
         RT3D_LAUNCH(c, RT3D_KERNEL_LOOP, st,
                     launch_loop(m, p, sh, off, ent, in->gain, w.A, w.B, w.btmp, c->d_bw, c->rb, c->p.n_iter, st));
     } else {
@@ -840,7 +910,8 @@ rt3d_status rt3d_reconstruct(rt3d_ctx* c, const rt3d_input* in, rt3d_output* out
             if (s != RT3D_OK) return s;
         }
     }
-    RT3D_LAUNCH(c, RT3D_KERNEL_OUTPUT, st, launch_output(sh, w.A, out, w.counts, w.partial, w.err, st));
+    RT3D_LAUNCH(c, RT3D_KERNEL_OUTPUT, st,
+                launch_output(point_grid(sh, c->p.sr), w.A, out, w.counts, w.partial, w.err, sh.P, st));
     c->state_layout = layout;
     return RT3D_OK;
 }
@@ -1010,6 +1081,59 @@ rt3d_status rt3d_debug_compact_events(rt3d_ctx* c, const uint32_t* ev_pixel, con
     return RT3D_OK;
 }
 
+// rt3d_debug_step under super-resolution (arguments checked by the caller):
+// states on the point grid, the lidar frames are theirs divided by sr.
+static rt3d_status debug_step_sr(rt3d_ctx* c, int32_t step, const uint32_t* off, const uint32_t* ent,
+                                 const float* gain, const rt3d_state* in, rt3d_state* out, hipStream_t st)
+{
+    const int sr = c->p.sr;
+    if (out->rows % sr || out->cols % sr)
+        return fail(c, RT3D_E_INVALID, "point-grid rows and cols must be multiples of sr");
+    const Shape fsh = shape_of(out->frames, out->rows, out->cols);
+    const Shape lid = shape_of(out->frames, out->rows / sr, out->cols / sr);
+    const DevModel m = dev_model(c);
+    const DevParams p = dev_params(c);
+    DevState O = dev_state(out);
+    Workspace w{};
+    const bool needs_ws = step == RT3D_STEP_INIT || step == RT3D_STEP_BFILTER || step == RT3D_STEP_ITERATION;
+    if (needs_ws) {
+        rt3d_status s = need_ws(c, lid.P, w);
+        if (s != RT3D_OK) return s;
+    }
+    switch (step) {
+    case RT3D_STEP_INIT:
+        return init_sr(c, lid, off, ent, gain, O, w.B, w.err, st);
+    case RT3D_STEP_APSS:
+        RT3D_HIP(c, launch_apss(m, p, fsh, dev_state(in), O, -1, st));
+        return RT3D_OK;
+    case RT3D_STEP_IFILTER:
+        RT3D_HIP(c, launch_ifilter(p, fsh, dev_state(in), O, st));
+        return RT3D_OK;
+    default:
+        break;
+    }
+    if (step < 0 || step > RT3D_STEP_ITERATION) return fail(c, RT3D_E_INVALID, "unknown step");
+    RT3D_HIP(c, launch_copy_state(fsh, dev_state(in), O, st));
+    switch (step) {
+    case RT3D_STEP_DEPTH:
+    case RT3D_STEP_INTENSITY:
+    case RT3D_STEP_BKG:
+        RT3D_HIP(c, launch_sr_step(step, m, p, lid, sr, fsh.P, off, ent, gain, O, nullptr, st));
+        return RT3D_OK;
+    case RT3D_STEP_MERGE:
+        RT3D_HIP(c, launch_merge(p, fsh, O, st));
+        return RT3D_OK;
+    case RT3D_STEP_BFILTER:
+        RT3D_HIP(c, launch_bfilter(c->d_bw, c->rb, lid, (float)c->p.b_min, O.b, w.btmp, w.B.b, st));
+        RT3D_HIP(c, hipMemcpyAsync(O.b, w.btmp, sizeof(float) * lid.P, hipMemcpyDeviceToDevice, st));
+        return RT3D_OK;
+    case RT3D_STEP_ITERATION:
+        return iterate_sr(c, lid, off, ent, gain, O, w.B, w.btmp, st);
+    default:
+        return fail(c, RT3D_E_INVALID, "unknown step");
+    }
+}
+
 rt3d_status rt3d_debug_step(rt3d_ctx* c, int32_t step, const uint32_t* off, const uint32_t* ent, const float* gain,
                             const rt3d_state* in, rt3d_state* out, void* hip_stream)
 {
@@ -1029,6 +1153,7 @@ rt3d_status rt3d_debug_step(rt3d_ctx* c, int32_t step, const uint32_t* off, cons
     const DevModel m = dev_model(c);
     const DevParams p = dev_params(c);
     DevState O = dev_state(out);
+    if (c->p.sr > 1) return debug_step_sr(c, step, off, ent, gain, in, out, st);
     switch (step) {
     case RT3D_STEP_INIT:
         RT3D_HIP(c, launch_init(m, p, sh, off, ent, gain, O, nullptr, st));
@@ -1085,6 +1210,15 @@ rt3d_status rt3d_debug_gradients(rt3d_ctx* c, const uint32_t* off, const uint32_
     if (!state_ok(s) || !off || !ent || !gt || !gr || !gb) return fail(c, RT3D_E_INVALID, "NULL argument");
     if (!shape_ok(s->frames, s->rows, s->cols)) return fail(c, RT3D_E_INVALID, "bad state shape");
     const Shape sh = shape_of(s->frames, s->rows, s->cols);
+    const int sr = c->p.sr;
+    if (sr > 1) {
+        if (s->rows % sr || s->cols % sr)
+            return fail(c, RT3D_E_INVALID, "point-grid rows and cols must be multiples of sr");
+        const Shape lid = shape_of(s->frames, s->rows / sr, s->cols / sr);
+        RT3D_HIP(c, launch_sr_gradients(dev_model(c), dev_params(c), lid, sr, sh.P, off, ent, gain, dev_state(s), gt,
+                                        gr, gb, (hipStream_t)hip_stream));
+        return RT3D_OK;
+    }
     RT3D_HIP(c, launch_gradients(dev_model(c), dev_params(c), sh, off, ent, gain, dev_state(s), gt, gr, gb,
                                  (hipStream_t)hip_stream));
     return RT3D_OK;

@@ -56,7 +56,8 @@ class Params(C.Structure):
                 ("r_min", C.c_double), ("d_merge", C.c_double), ("sigma_b", C.c_double),
                 ("b_min", C.c_double), ("sbr_guess", C.c_double), ("r_init", C.c_int32),
                 ("n_min", C.c_int32), ("kappa", C.c_double), ("w_nms", C.c_int32),
-                ("m_min", C.c_int32), ("denoiser", C.c_int32), ("fused_loop", C.c_int32)]
+                ("m_min", C.c_int32), ("denoiser", C.c_int32), ("fused_loop", C.c_int32),
+                ("sr", C.c_int32)]
 
 
 class Input(C.Structure):
@@ -280,14 +281,16 @@ class Context:
         return st
 
     # -- whole reconstruction ------------------------------------------------
-    def make_output(self, P: int, capacity: int | None = None, normals: bool = True) -> Result:
+    def make_output(self, P: int, capacity: int | None = None, normals: bool = True,
+                    n_bg: int | None = None) -> Result:
+        """Output buffers for P (point-grid) pixels and n_bg (lidar) background values (default P)."""
         cap = P * K_MAX if capacity is None else capacity
         dev = "cuda"
         return Result(torch.zeros(P + 1, dtype=torch.int32, device=dev),
                       torch.zeros(cap, dtype=torch.float64, device=dev),
                       torch.zeros(cap, dtype=torch.float32, device=dev),
                       torch.zeros(cap, 3, dtype=torch.float32, device=dev) if normals else None,
-                      torch.zeros(P, dtype=torch.float32, device=dev))
+                      torch.zeros(P if n_bg is None else n_bg, dtype=torch.float32, device=dev))
 
     def _io(self, out: Result, frames: int, rows: int, cols: int, hist=None, off=None, ent=None, gain=None,
             events=None, frame_shapes=None, warm_start=False):
@@ -316,6 +319,11 @@ class Context:
             inp.kind = IN_PHOTON_CSR
             inp.off, inp.ent = off.data_ptr(), ent.data_ptr()
         inp.gain = gain.data_ptr() if gain is not None else None
+        # the library trusts these sizes: point-grid pixels for pt_off, lidar pixels for background
+        npix = sum(int(r) * int(q) for r, q in frame_shapes) if frame_shapes is not None else frames * rows * cols
+        sr = self.params.sr
+        assert out.pt_off.numel() >= npix * sr * sr + 1 and out.background.numel() >= npix, \
+            "output buffers smaller than the batch"
         o = Output()
         o.struct_size = C.sizeof(Output)
         o.capacity = out.depth.numel()
@@ -361,7 +369,8 @@ class Context:
         P = F * R * Cc
         me = int(max_entries) if max_entries is not None else min(P * T, 2 ** 32 - 1)
         self.workspace(F, R, Cc, me)
-        out = self.make_output(P)
+        sr = self.params.sr
+        out = self.make_output(P * sr * sr, n_bg=P)
         self.reconstruct_into(out, F, R, Cc, hist=hist, gain=gain)
         return out
 
@@ -402,10 +411,11 @@ class Context:
         out = DeviceState.empty(F, R, Cc)
         cin = st_in.c() if st_in is not None else None
         cout = out.c()
-        if step in (STEP_BFILTER, STEP_ITERATION):
-            P = F * R * Cc
+        sr = self.params.sr
+        if step in (STEP_BFILTER, STEP_ITERATION) or (sr > 1 and step == STEP_INIT):
+            P = F * R * Cc // (sr * sr)          # the workspace is sized in lidar pixels
             if self._ws_shape is None or self._ws_shape[0] * self._ws_shape[1] * self._ws_shape[2] < P:
-                self.workspace(F, R, Cc, 1)
+                self.workspace(1, 1, P, 1)
         self._check(lib().rt3d_debug_step(self._h, step, _ptr(off), _ptr(ent), _ptr(gain),
                                           C.byref(cin) if cin is not None else None, C.byref(cout),
                                           _stream()))
@@ -455,7 +465,7 @@ class Context:
         P = st.frames * st.rows * st.cols
         gt = torch.zeros(K_MAX, P, dtype=torch.float32, device="cuda")
         gr = torch.zeros(K_MAX, P, dtype=torch.float32, device="cuda")
-        gb = torch.zeros(P, dtype=torch.float32, device="cuda")
+        gb = torch.zeros(P // self.params.sr ** 2, dtype=torch.float32, device="cuda")
         cs = st.c()
         self._check(lib().rt3d_debug_gradients(self._h, _ptr(off), _ptr(ent), _ptr(gain), C.byref(cs),
                                                _ptr(gt), _ptr(gr), _ptr(gb), _stream()))

@@ -67,3 +67,29 @@ def pair(scene: synth.Scene, **kw):
     O = oracle.Oracle(model, oracle.Params(**{k: v for k, v in p.items() if k != "denoiser"}))
     ctx = rt3d.Context(scene.irf.probs, scene.T, **p)
     return O, ctx
+
+
+def sr_to_device(s: oracle.SRState) -> rt3d.DeviceState:
+    """Super-resolved oracle state -> point-grid device state whose b holds the
+    lidar background in its first lidar-pixel entries."""
+    d = oracle_to_device(_as_plain(s))
+    b = torch.zeros(s.npix, dtype=torch.float32)
+    b[:s.b.size] = torch.from_numpy(s.b.astype(np.float32))
+    d.b = b.cuda()
+    return d
+
+
+def _as_plain(s: oracle.SRState) -> oracle.State:
+    p = oracle.State(s.F, s.rows, s.cols, s.K)
+    for a in ("t", "r", "n", "cnt"):
+        setattr(p, a, getattr(s, a))
+    return p
+
+
+def device_to_sr(d: rt3d.DeviceState, k_max: int, sr: int, g=None) -> oracle.SRState:
+    s = oracle.SRState(d.frames, d.rows // sr, d.cols // sr, sr, k_max, g)
+    p = device_to_oracle(d, k_max)
+    for a in ("t", "r", "n", "cnt"):
+        setattr(s, a, getattr(p, a))
+    s.b[:] = p.b[:s.b.size]
+    return s

@@ -1,0 +1,189 @@
+"""Super-resolution (Results, dynamic scenes: s x s point-grid pixels per lidar
+pixel), through the C ABI, against the oracle's super-resolved functions:
+the initial spread over the point grid, the raw gradients, each gradient step
+and whole reconstructions, with the same bars as the plain model."""
+import numpy as np
+import pytest
+
+from gpu_util import device_to_sr, sr_to_device, to_dev_hist, to_dev_u32, u32
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import oracle  # noqa: E402
+from paper_1905_06700_amd import rt3d, synth  # noqa: E402
+
+_CASES = {}
+
+
+def case(name):
+    """(scenes, s): lidar frames, T and photon levels of the paper's array video
+    (32 x 32 x 153 reconstructed on a 3x finer grid), at test sizes."""
+    if name not in _CASES:
+        if name == "s3":        # 48 x 36 point grid: a ragged 16 x 16 tile edge
+            _CASES[name] = ([synth.sr_scene(0, rows=16, cols=12, s=3)], 3)
+        elif name == "s2_bright":   # more than 64 active bins per lidar pixel: several entry batches
+            _CASES[name] = ([synth.sr_scene(1, rows=10, cols=13, s=2, T=300, signal=40.0, sbr=0.25)], 2)
+        elif name == "s4":      # s^2 K = 64 lanes
+            _CASES[name] = ([synth.sr_scene(2, rows=6, cols=9, s=4)], 4)
+        elif name == "s3_video":    # two frames of a moving object in one call
+            _CASES[name] = ([synth.sr_scene(k, rows=12, cols=12, s=3) for k in (3, 9)], 3)
+    return _CASES[name]
+
+
+def pair_sr(sc, s, **kw):
+    m = sc.meta
+    p = dict(dz=m["dz"], p_xy=m["p_xy"], r_min=m["r_min"], r_init=m["r_init"], k_init=m["k_init"])
+    p.update(kw)
+    O = oracle.Oracle(oracle.Model(sc.irf.probs, sc.T), oracle.Params(**p))
+    ctx = rt3d.Context(sc.irf.probs, sc.T, sr=s, **p)
+    return O, ctx
+
+
+def lidar_csr(scs):
+    Z = np.stack([sc.Z for sc in scs])
+    return oracle.compact(Z)
+
+
+def sr_init(O, scs, s, off, ent):
+    """The oracle's initial super-resolved state: lidar-grid init, spread, normals."""
+    F, R, C = len(scs), scs[0].rows, scs[0].cols
+    coarse = O.init(off, ent, oracle.State(F, R, C, 4), normals=False)
+    st = O.sr_expand(coarse, oracle.SRState(F, R, C, s, 4))
+    O.init_normals(st)
+    return st
+
+
+@pytest.mark.parametrize("name", ["s3", "s2_bright", "s4"])
+def test_sr_init_matches_oracle(name):
+    scs, s = case(name)
+    sc = scs[0]
+    O, ctx = pair_sr(sc, s)
+    off, ent = lidar_csr(scs)
+    so = sr_init(O, scs, s, off, ent)
+    print(f"[gpu-sr] init {name}: {sc.rows}x{sc.cols} lidar, s={s}", flush=True)
+    d = ctx.step(rt3d.STEP_INIT, None, to_dev_u32(off), to_dev_u32(ent), shape=(1, sc.rows * s, sc.cols * s))
+    sg = device_to_sr(d, 4, s)
+    np.testing.assert_array_equal(sg.cnt, so.cnt)
+    np.testing.assert_array_equal(sg.t, so.t)
+    np.testing.assert_allclose(sg.r, so.r, rtol=2e-6, atol=1e-7)
+    np.testing.assert_allclose(sg.b, so.b, rtol=2e-6, atol=1e-12)
+    np.testing.assert_allclose(sg.n, so.n, atol=2e-6)
+
+
+def _state_after(O, scs, s, off, ent, iters):
+    st = sr_init(O, scs, s, off, ent)
+    for _ in range(iters):
+        O.sr_iterate(off, ent, st)
+    return st
+
+
+@pytest.mark.parametrize("name", ["s3", "s2_bright", "s4"])
+@pytest.mark.parametrize("iters", [0, 2])
+def test_sr_gradients_match_oracle(name, iters):
+    scs, s = case(name)
+    O, ctx = pair_sr(scs[0], s)
+    off, ent = lidar_csr(scs)
+    st = _state_after(O, scs, s, off, ent, iters)
+    st.g[::7] = 0.0                                  # dead lidar pixels
+    st.g[1::7] = 0.6
+    (gt, gr, gb), (at, ar, ab) = O.sr_grad(off, ent, st)
+    gain = torch.from_numpy(st.g.astype(np.float32)).cuda()
+    print(f"[gpu-sr] gradients {name} after {iters} iterations", flush=True)
+    dgt, dgr, dgb = ctx.gradients(sr_to_device(st), to_dev_u32(off), to_dev_u32(ent), gain)
+    dgt = dgt.cpu().numpy()[:4].T.astype(np.float64)
+    dgr = dgr.cpu().numpy()[:4].T.astype(np.float64)
+    dgb = dgb.cpu().numpy().astype(np.float64)
+    live = np.arange(4)[None, :] < st.cnt[:, None]
+    assert live.sum() > 0
+    for g_gpu, g_or, a in ((dgt, gt, at), (dgr, gr, ar)):
+        err = np.abs(g_gpu - g_or)[live]
+        assert np.all(err <= 1e-4 * a[live] + 1e-30), (err.max(), (err / a[live]).max())
+        assert np.all(g_gpu[~live] == 0)
+    assert np.all(np.abs(dgb - gb) <= 1e-4 * ab + 1e-30)
+
+
+@pytest.mark.parametrize("name", ["s3", "s2_bright", "s4"])
+def test_sr_single_steps_match_oracle(name):
+    scs, s = case(name)
+    O, ctx = pair_sr(scs[0], s)
+    off_o, ent_o = lidar_csr(scs)
+    off, ent = to_dev_u32(off_o), to_dev_u32(ent_o)
+    s0 = _state_after(O, scs, s, off_o, ent_o, 2)
+    din = sr_to_device(s0)
+    live = np.arange(4)[None, :] < s0.cnt[:, None]
+    print(f"[gpu-sr] steps {name}", flush=True)
+
+    so = O.sr_depth_step(off_o, ent_o, s0.copy())
+    sg = device_to_sr(ctx.step(rt3d.STEP_DEPTH, din, off, ent), 4, s)
+    assert np.abs(sg.t - so.t)[live].max() <= 2e-4
+
+    so = O.sr_intensity_step(off_o, ent_o, s0.copy())
+    sg = device_to_sr(ctx.step(rt3d.STEP_INTENSITY, din, off, ent), 4, s)
+    np.testing.assert_allclose(sg.r[live], so.r[live], rtol=1e-5, atol=1e-6)
+
+    so = O.sr_bg_step(off_o, ent_o, s0.copy())
+    sg = device_to_sr(ctx.step(rt3d.STEP_BKG, din, off, ent), 4, s)
+    np.testing.assert_allclose(sg.b, so.b, rtol=1e-5, atol=1e-12)
+
+    so = O.bg_filter(_lidar_b(s0))
+    sg = device_to_sr(ctx.step(rt3d.STEP_BFILTER, din), 4, s)
+    np.testing.assert_allclose(sg.b, so.b, rtol=1e-5, atol=1e-12)
+
+
+def _lidar_b(st):
+    """A lidar-grid state carrying st's background (for the background filter)."""
+    c = oracle.State(st.F, st.lrows, st.lcols, st.K)
+    c.b[:] = st.b
+    return c
+
+
+@pytest.mark.parametrize("name", ["s3", "s2_bright", "s4", "s3_video"])
+def test_sr_reconstruction_matches_oracle(name):
+    scs, s = case(name)
+    O, ctx = pair_sr(scs[0], s)
+    off, ent = lidar_csr(scs)
+    F, R, C = len(scs), scs[0].rows, scs[0].cols
+    so = O.sr_reconstruct(off, ent, oracle.SRState(F, R, C, s, 4))
+    print(f"[gpu-sr] reconstruct {name}: {F} frame(s) of {R}x{C} lidar pixels, s={s}", flush=True)
+    res = ctx.reconstruct(torch.stack([to_dev_hist(sc.Z) for sc in scs]))
+    st = ctx.query()
+    assert st.device_error == 0
+    assert st.entries == len(ent)
+    pt = u32(res.pt_off).astype(np.int64)
+    assert pt.size == F * R * s * C * s + 1 and res.background.numel() == F * R * C
+    cnt = np.diff(pt)
+    same = cnt == so.cnt
+    # depth errors where the point-grid pixel's 5 x 5 neighbourhood counts agree
+    bad = (~same).reshape(F, R * s, C * s)
+    nb = np.zeros_like(bad)
+    for di in range(-2, 3):
+        for dj in range(-2, 3):
+            nb |= np.roll(np.roll(bad, di, 1), dj, 2)
+    depth = res.depth.cpu().numpy()
+    errs = [np.abs(depth[pt[q]:pt[q] + so.cnt[q]] - so.t[q, :so.cnt[q]]).max()
+            for q in np.nonzero(~nb.reshape(-1) & (so.cnt > 0))[0]]
+    print(f"[gpu-sr] {name}: count agreement {same.mean():.5f}, max depth err {max(errs):.2e} bins "
+          f"over {len(errs)} pixels", flush=True)
+    assert same.mean() >= 0.999
+    assert len(errs) > 0.5 * so.npix and max(errs) <= 1e-3
+    np.testing.assert_allclose(res.background.cpu().numpy(), so.b, rtol=1e-3, atol=1e-9)
+
+
+def test_sr_refusals():
+    scs, s = case("s3")
+    sc = scs[0]
+    with pytest.raises(rt3d.Rt3dError) as e:
+        rt3d.Context(sc.irf.probs, sc.T, sr=2, denoiser=rt3d.DENOISE_CNN)
+    assert e.value.status == rt3d.E_UNSUPPORTED
+    with pytest.raises(rt3d.Rt3dError) as e:
+        rt3d.Context(sc.irf.probs, sc.T, sr=5)
+    assert e.value.status == rt3d.E_INVALID
+    _, ctx = pair_sr(sc, s)
+    Z = torch.cat([to_dev_hist(sc.Z).reshape(-1, sc.T)] * 2)
+    P = int(Z.shape[0])
+    ctx.workspace(1, 1, P, P * 64)
+    out = ctx.make_output(P * s * s, n_bg=P)
+    with pytest.raises(rt3d.Rt3dError) as e:       # frames of different sizes
+        ctx.reconstruct_into(out, 2, 1, 1, hist=Z, frame_shapes=[(sc.rows, sc.cols), (sc.cols, sc.rows)])
+    assert e.value.status == rt3d.E_UNSUPPORTED
