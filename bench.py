@@ -249,6 +249,60 @@ def hbm_regime(scenes, F=64):
     return res
 
 
+def super_resolution(reps=5):
+    """The paper's array-video mode: 32 x 32 x 153 lidar frames (a moving disc
+    over a tilted plane, 3 signal photons/px at SBR 0.5) reconstructed on a
+    96 x 96 point grid (s = 3): one frame per call, direct and replayed from a
+    recorded graph (the paper's per-frame latency), and 64 frames per call."""
+    import numpy as np
+    import torch
+
+    from paper_1905_06700_amd import rt3d, synth
+
+    s, R, C = 3, 32, 32
+    scs = [synth.sr_scene(k, rows=R, cols=C, s=s) for k in range(8)]
+    sc, m = scs[0], scs[0].meta
+    ctx = rt3d.Context(sc.irf.probs, sc.T, sr=s, dz=m["dz"], p_xy=m["p_xy"], r_min=m["r_min"],
+                       r_init=m["r_init"], k_init=m["k_init"])
+    res = {"workload": f"{R}x{C}x{sc.T} lidar frames on a {R * s}x{C * s} point grid (moving disc over a plane, "
+                       "3 signal photons/px, SBR 0.5), 20 iterations, APSS",
+           "paper_context": {"ms_per_frame": 20, "hardware": "NVIDIA Titan Xp", "data": "real 32x32x153 array "
+                             "video at 320 m reconstructed on 96x96"}}
+
+    def timed(run):
+        run()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            run()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    for F in (1, 64):
+        Z = torch.stack([torch.from_numpy(scs[f % len(scs)].Z.view(np.int16)) for f in range(F)]).cuda()
+        ctx.workspace(F, R, C, F * R * C * sc.T)
+        out = ctx.make_output(F * R * C * s * s, n_bg=F * R * C)
+        ms = timed(lambda: ctx.reconstruct_into(out, F, R, C, hist=Z))
+        res[f"call_ms_{F}_frames"] = round(ms, 3)
+        res[f"frames_per_s_{F}_frames"] = round(F / (ms / 1e3), 1)
+        if F == 1:
+            g = ctx.graph(out, F, R, C, hist=Z)
+            ms = timed(g.launch)
+            res["call_ms_1_frame_graph"] = round(ms, 3)
+            del g
+        else:
+            ctx.profile("depth")
+            ctx.reconstruct_into(out, F, R, C, hist=Z)
+            torch.cuda.synchronize()
+            kms, n = ctx.profile_read()
+            ctx.profile(None)
+            res["depth_step_us_64_frames"] = round(kms / max(int(n), 1) * 1e3, 2)
+        assert ctx.query().device_error == 0
+    return res
+
+
 def learned_vs_apss(n_train=4, n_eval=4, steps=300, rows=256, cols=256, bins=1024):
     """Learned denoiser against plain APSS on multi-layer scenes: train on the
     GPU (the library's forward/backward kernels), then time and score both on
@@ -476,6 +530,7 @@ def main():
         "active_entries_per_frame": E // F, "points_per_frame": pts // F,
         "single_frame_latency_ms": round(latency_ms, 3), "single_frame_latency_graph_ms": round(latency_graph_ms, 3),
         "small_frames": small_frames(), "uneven_frames": uneven_frames(), "hbm_regime": hbm_regime(scenes),
+        "super_resolution": super_resolution(),
         "wall_s": round(wall, 3),
         "roofline": roofline, "kernels": kernels, "cpu_baseline": cpu,
         "learned_vs_apss": None if args.no_learned else learned_vs_apss(),
