@@ -98,6 +98,7 @@ def _declare(L):
     L.or_model_new.restype = C.c_void_p
     L.or_model_new.argtypes = [_dp, C.c_int, C.c_int, C.c_int]
     L.or_model_free.argtypes = [C.c_void_p]
+    L.or_model_set_classes.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
     L.or_model_origin.restype = C.c_int
     L.or_model_origin.argtypes = [C.c_void_p]
     L.or_model_sigma2.restype = C.c_double
@@ -272,11 +273,27 @@ class SRState(State):
 
 
 class Oracle:
-    """The oracle's steps bound to one IRF model and parameter set."""
+    """The oracle's steps bound to one IRF model and parameter set.
 
-    def __init__(self, model: Model, params: Params):
+    Per-pixel IRFs (the observation model's h_ij): irf_class[p] names pixel
+    p's model, 0 = `model`, k >= 1 = irf_models[k - 1] (numbers past the list
+    count as 0).  The class table is attached to `model` while this oracle
+    lives."""
+
+    def __init__(self, model: Model, params: Params, irf_models=None, irf_class=None):
         self.m, self.p = model, params
         self._pc = params.c()
+        self._cls = None
+        if irf_class is not None:
+            self._models = [model] + list(irf_models or [])
+            self._marr = (C.c_void_p * len(self._models))(*[mm._h for mm in self._models])
+            self._cls = np.ascontiguousarray(irf_class, dtype=np.uint8).reshape(-1)
+            lib().or_model_set_classes(model._h, len(self._models), self._marr,
+                                       self._cls.ctypes.data_as(C.c_void_p))
+
+    def __del__(self):
+        if getattr(self, "_cls", None) is not None and _lib is not None and getattr(self.m, "_h", None):
+            _lib.or_model_set_classes(self.m._h, 0, None, None)
 
     @property
     def _P(self):

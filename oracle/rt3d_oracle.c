@@ -40,7 +40,20 @@ struct or_model {
     double  sigma2; /* IRF variance in bins^2 */
     double  fisher; /* shift Fisher information per photon, 1/bins^2 */
     int     wl, wr; /* peak window half widths (5% / 95% cumulative mass) */
+    /* per-pixel IRFs (or_model_set_classes): pixel p uses cls_m[cls[p]]
+     * (class numbers >= ncls count as 0); no table: this model everywhere */
+    int                ncls;
+    or_model* const*   cls_m;
+    const uint8_t*     cls;
 };
+
+/* The IRF of pixel pix (Observation model: h_ij is known per pixel). */
+static const or_model* pm(const or_model* m, int64_t pix)
+{
+    if (!m->cls) return m;
+    int k = m->cls[pix];
+    return m->cls_m[k < m->ncls ? k : 0];
+}
 
 static void h_eval(const or_model* m, double tau, double* h, double* hp);
 
@@ -124,6 +137,17 @@ void or_model_free(or_model* m)
     if (!m) return;
     free(m->hbar); free(m);
 }
+/* Per-pixel IRFs: pixel p of every later call uses models[cls[p]] (n models,
+ * models[0] normally m itself; numbers >= n use models[0]); cls == NULL
+ * restores m everywhere.  The arrays are the caller's and must outlive the
+ * calls.  All models share T. */
+void or_model_set_classes(or_model* m, int n, or_model* const* models, const uint8_t* cls)
+{
+    m->ncls = cls ? n : 0;
+    m->cls_m = cls ? models : NULL;
+    m->cls = cls;
+}
+
 int    or_model_origin(const or_model* m) { return m->o; }
 double or_model_sigma2(const or_model* m) { return m->sigma2; }
 double or_model_fisher(const or_model* m) { return m->fisher; }
@@ -234,18 +258,19 @@ double or_nll(const or_model* m, int64_t npix, const uint32_t* off, const uint32
     double total = 0.0;
     for (int64_t p = 0; p < npix; ++p) {
         if (!(g[p] > 0.0)) continue;
+        const or_model* mp = pm(m, p);
         const double* tp = t + p * k_max;
         const double* rp = r + p * k_max;
         double sumS = 0.0;
         for (int k = 0; k < cnt[p]; ++k) {
             double S, Sp;
-            S_eval(m, tp[k], &S, &Sp);
+            S_eval(mp, tp[k], &S, &Sp);
             sumS += rp[k] * S;
         }
         double term = g[p] * (sumS + m->T * b[p]);
         for (uint32_t e = off[p]; e < off[p + 1]; ++e) {
             int tb = ent_t(ent[e]), z = ent_z(ent[e]);
-            double lam = lambda_at(m, k_max, tp, rp, cnt[p], b[p], g[p], tb);
+            double lam = lambda_at(mp, k_max, tp, rp, cnt[p], b[p], g[p], tb);
             term -= z * log(lam);
             term += lgamma(z + 1.0);
         }
@@ -262,7 +287,7 @@ double or_nll_dense(const or_model* m, int64_t npix, const uint16_t* Z,
     for (int64_t p = 0; p < npix; ++p) {
         if (!(g[p] > 0.0)) continue;
         for (int tb = 0; tb < m->T; ++tb) {
-            double lam = lambda_at(m, k_max, t + p * k_max, r + p * k_max, cnt[p], b[p], g[p], tb);
+            double lam = lambda_at(pm(m, p), k_max, t + p * k_max, r + p * k_max, cnt[p], b[p], g[p], tb);
             int z = Z[p * m->T + tb];
             total += lam - z * log(lam) + lgamma(z + 1.0);
         }
@@ -282,6 +307,7 @@ void or_grad(const or_model* m, int64_t npix, const uint32_t* off, const uint32_
              double* at, double* ar, double* ab)
 {
     for (int64_t p = 0; p < npix; ++p) {
+        const or_model* mp = pm(m, p);
         const double* tp = t + p * k_max;
         const double* rp = r + p * k_max;
         double G = g[p];
@@ -292,10 +318,10 @@ void or_grad(const or_model* m, int64_t npix, const uint32_t* off, const uint32_
         if (G > 0.0) {
             for (uint32_t e = off[p]; e < off[p + 1]; ++e) {
                 int tb = ent_t(ent[e]), z = ent_z(ent[e]);
-                double lam = lambda_at(m, k_max, tp, rp, c, b[p], G, tb);
+                double lam = lambda_at(mp, k_max, tp, rp, c, b[p], G, tb);
                 for (int k = 0; k < c; ++k) {
                     double h, hp;
-                    h_eval(m, tb - tp[k], &h, &hp);
+                    h_eval(mp, tb - tp[k], &h, &hp);
                     st[k] += z * hp / lam;
                     ast[k] += z * fabs(hp) / lam;
                     sr[k] += z * h / lam;
@@ -310,12 +336,12 @@ void or_grad(const or_model* m, int64_t npix, const uint32_t* off, const uint32_
         }
         for (int k = 0; k < c; ++k) {
             double S, Sp;
-            S_eval(m, tp[k], &S, &Sp);
+            S_eval(mp, tp[k], &S, &Sp);
             /* S' is itself a sum over bins: its terms count in the scale */
             double asp = 0.0;
             for (int t = 0; t < m->T; ++t) {
                 double h, hp;
-                h_eval(m, t - tp[k], &h, &hp);
+                h_eval(mp, t - tp[k], &h, &hp);
                 asp += fabs(hp);
             }
             gt[p * k_max + k] = G * rp[k] * (Sp + st[k]);
@@ -406,17 +432,24 @@ void or_init(const or_model* m, const or_params* p, int F, int rows, int cols,
              const uint32_t* off, const uint32_t* ent, const double* g,
              double* t, double* r, double* n, int* cnt, double* b)
 {
-    int T = m->T, L = m->L, o = m->o, K = p->k_max;
+    int T = m->T, K = p->k_max;
     int64_t npix = (int64_t)F * rows * cols;
-    int64_t* q = (int64_t*)malloc(sizeof(int64_t) * L);
-    or_lmf_table(m, p->sbr_guess, q);
+    int64_t* q = (int64_t*)malloc(sizeof(int64_t) * T);
     int64_t* agg = (int64_t*)malloc(sizeof(int64_t) * T);
     int64_t* score = (int64_t*)malloc(sizeof(int64_t) * T);
     char* supp = (char*)malloc(T);
     char* claimed = (char*)malloc(T);   /* bin -> 1 + index of the accepted peak owning it */
-    int wnms = p->w_nms > 0 ? p->w_nms : (int)ceil(fmax(1.0, 2.0 * sqrt(m->sigma2)));
     int Ri = p->r_init;
+    const or_model* mq = NULL;          /* the model q was built for */
     for (int64_t pix = 0; pix < npix; ++pix) {
+        /* the pixel's IRF scores its window's pooled photons */
+        const or_model* mm = pm(m, pix);
+        int L = mm->L, o = mm->o;
+        int wnms = p->w_nms > 0 ? p->w_nms : (int)ceil(fmax(1.0, 2.0 * sqrt(mm->sigma2)));
+        if (mm != mq) {
+            or_lmf_table(mm, p->sbr_guess, q);
+            mq = mm;
+        }
         for (int k = 0; k < K; ++k) {
             t[pix * K + k] = 0.0; r[pix * K + k] = 0.0;
             n[(pix * K + k) * 3 + 0] = 0.0; n[(pix * K + k) * 3 + 1] = 0.0; n[(pix * K + k) * 3 + 2] = -1.0;
@@ -459,8 +492,8 @@ void or_init(const or_model* m, const or_params* p, int F, int rows, int cols,
                 if (best < 0 || score[tau] > bestv) { best = tau; bestv = score[tau]; }
             }
             if (best < 0) break;
-            int a = best - m->wl < 0 ? 0 : best - m->wl;
-            int c = best + m->wr > T - 1 ? T - 1 : best + m->wr;
+            int a = best - mm->wl < 0 ? 0 : best - mm->wl;
+            int c = best + mm->wr > T - 1 ? T - 1 : best + mm->wr;
             /* the window's bins not already claimed by an accepted peak */
             int win = 0;
             int64_t nwin = 0;
@@ -506,7 +539,7 @@ void or_init(const or_model* m, const or_params* p, int F, int rows, int cols,
             int keep = den > 0 ? (nown[k] * den > num * win) : (nown[k] > 0);
             double H = 0.0;
             for (int tb = lo[k]; tb <= hi[k]; ++tb)
-                if (claimed[tb] == k + 1) H += hb(m, tb - pk[k] + o);
+                if (claimed[tb] == k + 1) H += hb(mm, tb - pk[k] + o);
             if (!keep || !(H > 0.0)) continue;
             double excess = den > 0 ? (double)nown[k] - (double)num * (double)win / (double)den
                                     : (double)nown[k];
@@ -599,12 +632,13 @@ void or_depth_step(const or_model* m, const or_params* p, int64_t npix,
                    double* t, const double* r, const int* cnt, const double* b)
 {
     int K = p->k_max;
-    double dmax = p->dmax > 0.0 ? p->dmax : fmax(0.5, 1.0 / sqrt(m->fisher));
     double* t0 = (double*)malloc(sizeof(double) * K);
     for (int64_t pix = 0; pix < npix; ++pix) {
         double G = g[pix];
         int c = cnt[pix];
         if (!(G > 0.0) || c == 0) continue;
+        const or_model* mp = pm(m, pix);
+        double dmax = p->dmax > 0.0 ? p->dmax : fmax(0.5, 1.0 / sqrt(mp->fisher));
         double* tp = t + pix * K;
         const double* rp = r + pix * K;
         for (int k = 0; k < c; ++k) t0[k] = tp[k];
@@ -613,14 +647,14 @@ void or_depth_step(const or_model* m, const or_params* p, int64_t npix,
             double acc = 0.0;
             for (uint32_t e = off[pix]; e < off[pix + 1]; ++e) {
                 int tb = ent_t(ent[e]), z = ent_z(ent[e]);
-                double lam = lambda_at(m, K, t0, rp, c, b[pix], G, tb);
+                double lam = lambda_at(mp, K, t0, rp, c, b[pix], G, tb);
                 double h, hp;
-                h_eval(m, tb - t0[k], &h, &hp);
+                h_eval(mp, tb - t0[k], &h, &hp);
                 acc += z * hp / lam;
             }
             double S, Sp;
-            S_eval(m, t0[k], &S, &Sp);
-            double step = -p->beta_t * (Sp + acc) / m->fisher;
+            S_eval(mp, t0[k], &S, &Sp);
+            double step = -p->beta_t * (Sp + acc) / mp->fisher;
             if (step > dmax) step = dmax;
             if (step < -dmax) step = -dmax;
             double tn = t0[k] + step;
@@ -719,10 +753,10 @@ void or_merge(const or_model* m, const or_params* p, int64_t npix,
               double* t, double* r, double* n, int* cnt)
 {
     int K = p->k_max;
-    double dm = p->d_merge > 0.0 ? p->d_merge : fmax(1.0, sqrt(m->sigma2));
     for (int64_t pix = 0; pix < npix; ++pix) {
         int c = cnt[pix];
         if (c < 2) continue;
+        double dm = p->d_merge > 0.0 ? p->d_merge : fmax(1.0, sqrt(pm(m, pix)->sigma2));
         double* tp = t + pix * K;
         double* rp = r + pix * K;
         double* np = n + pix * K * 3;
@@ -777,19 +811,20 @@ void or_intensity_step(const or_model* m, const or_params* p, int64_t npix,
         double G = g[pix];
         int c = cnt[pix];
         if (!(G > 0.0) || c == 0) continue;
+        const or_model* mp = pm(m, pix);
         const double* tp = t + pix * K;
         double* rp = r + pix * K;
         for (int k = 0; k < c; ++k) r0[k] = rp[k];
         for (int k = 0; k < c; ++k) {
             double S, Sp;
-            S_eval(m, tp[k], &S, &Sp);
+            S_eval(mp, tp[k], &S, &Sp);
             if (!(S > 0.0)) continue;
             double acc = 0.0;
             for (uint32_t e = off[pix]; e < off[pix + 1]; ++e) {
                 int tb = ent_t(ent[e]), z = ent_z(ent[e]);
-                double lam = lambda_at(m, K, tp, r0, c, b[pix], G, tb);
+                double lam = lambda_at(mp, K, tp, r0, c, b[pix], G, tb);
                 double h, hp;
-                h_eval(m, tb - tp[k], &h, &hp);
+                h_eval(mp, tb - tp[k], &h, &hp);
                 acc += z * h / lam;
             }
             double v = r0[k] * ((1.0 - p->beta_r) + p->beta_r * acc / S);
@@ -878,7 +913,7 @@ void or_bg_step(const or_model* m, const or_params* p, int64_t npix,
         double acc = 0.0;
         for (uint32_t e = off[pix]; e < off[pix + 1]; ++e) {
             int tb = ent_t(ent[e]), z = ent_z(ent[e]);
-            double lam = lambda_at(m, K, t + pix * K, r + pix * K, cnt[pix], b[pix], G, tb);
+            double lam = lambda_at(pm(m, pix), K, t + pix * K, r + pix * K, cnt[pix], b[pix], G, tb);
             acc += z / lam;
         }
         double v = b[pix] * ((1.0 - p->beta_b) + p->beta_b * acc / m->T);

@@ -61,6 +61,10 @@ typedef struct or_model or_model;
 /* IRF model: normalised samples, Catmull-Rom interpolant, sigma_h^2, shift Fisher information. */
 or_model* or_model_new(const double* irf, int L, int origin, int T);
 void      or_model_free(or_model* m);
+/* Per-pixel IRFs h_ij (Observation model): pixel p of every later call on m
+ * uses models[cls[p]] (cls[p] >= n: models[0]); cls = NULL: m everywhere.
+ * The super-resolved functions (or_sr_*) use m alone. */
+void      or_model_set_classes(or_model* m, int n, or_model* const* models, const uint8_t* cls);
 int       or_model_origin(const or_model* m);
 double    or_model_sigma2(const or_model* m);
 double    or_model_fisher(const or_model* m);
