@@ -145,6 +145,13 @@ typedef struct rt3d_input {
     const uint32_t* frame_cols;
     /* RT3D_FLAG_* bits. */
     uint32_t flags;
+    /* Per-pixel IRFs h_ij (Results, "Observation model": the response is known
+     * per pixel): optional device uint8 irf_class[P], the class (0 = the IRF of
+     * rt3d_create, k = the k-th rt3d_add_irf) of every pixel; numbers the
+     * context has no IRF for count as 0.  NULL: class 0 everywhere.  Each
+     * IRF-dependent kernel then runs once per class of the context.
+     * E_UNSUPPORTED with super-resolution or the learned denoiser. */
+    const uint8_t* irf_class;
 } rt3d_input;
 
 /* Warm start (video): skip the initialisation; the iterations start from the
@@ -203,6 +210,17 @@ void rt3d_params_default(rt3d_params* p);
  * E_INVALID on bad arguments, E_DEVICE on a HIP failure. */
 rt3d_status rt3d_create(const double* irf, uint32_t irf_len, int32_t irf_origin, uint32_t bins,
                         const rt3d_params* p, rt3d_ctx** out);
+
+/* Per-pixel IRFs: adds IRF class *id (1, 2, ... < RT3D_MAX_IRFS) to the
+ * context, with the same rules and the same model as rt3d_create's IRF (its
+ * own length and origin; every table derived from it: S, the Fisher
+ * information and so the depth step and its clip, the peak windows and
+ * suppression width, the merge distance).  rt3d_input.irf_class names each
+ * pixel's class.  Uploads the tables (blocking, on the context's device).
+ * E_INVALID for a rejected IRF or a full context, E_UNSUPPORTED with
+ * super-resolution or the learned denoiser, E_DEVICE on a HIP failure. */
+#define RT3D_MAX_IRFS 16
+rt3d_status rt3d_add_irf(rt3d_ctx* ctx, const double* irf, uint32_t irf_len, int32_t irf_origin, int32_t* id);
 
 /* Destroy a context (NULL allowed).  Caller memory is not freed. */
 void rt3d_destroy(rt3d_ctx* ctx);
@@ -338,6 +356,11 @@ rt3d_status rt3d_debug_step(rt3d_ctx* ctx, int32_t step, const uint32_t* off, co
 rt3d_status rt3d_debug_gradients(rt3d_ctx* ctx, const uint32_t* off, const uint32_t* ent,
                                  const float* gain, const rt3d_state* st,
                                  float* gt, float* gr, float* gb, void* hip_stream);
+
+/* The per-pixel IRF classes (device uint8 [P], as rt3d_input.irf_class) that
+ * rt3d_debug_step and rt3d_debug_gradients use from now on; NULL: class 0
+ * everywhere.  The array must stay valid while those calls use it. */
+rt3d_status rt3d_debug_irf_class(rt3d_ctx* ctx, const uint8_t* irf_class);
 
 /* ---------------------------------------------------------------------------
  * Learned depth denoiser.  The paper lets any denoiser act as the proximal

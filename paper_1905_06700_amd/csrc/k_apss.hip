@@ -226,11 +226,12 @@ __global__ __launch_bounds__(256) void k_apss(DevModel m, DevParams p, Shape sh,
 // depth describe one surface; in depth order they merge into the
 // intensity-weighted depth, summed intensity and weighted normal
 // (merge_points).
-__global__ __launch_bounds__(256) void k_merge(DevParams p, Shape sh, DevState s)
+// (m: only the pixels of its IRF class; d_merge in p is that class's)
+__global__ __launch_bounds__(256) void k_merge(DevModel m, DevParams p, Shape sh, DevState s)
 {
     const long long P = sh.P;
     const long long pix = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (pix >= P) return;
+    if (pix >= P || !in_class(m, pix)) return;
     int c = load_cnt(s.cnt, pix);
     if (c < 2) return;
     double t[KM];
@@ -274,10 +275,10 @@ hipError_t launch_apss(const DevModel& m, const DevParams& p, const Shape& sh, D
     return launch_apss_tiles(m, p, tiles_of(sh), in, out, only_above, st);
 }
 
-hipError_t launch_merge(const DevParams& p, const Shape& sh, DevState s, hipStream_t st)
+hipError_t launch_merge(const DevModel& m, const DevParams& p, const Shape& sh, DevState s, hipStream_t st)
 {
     if (sh.P == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_merge, dim3((unsigned)((sh.P + 255) / 256)), dim3(256), 0, st, p, sh, s);
+    hipLaunchKernelGGL(k_merge, dim3((unsigned)((sh.P + 255) / 256)), dim3(256), 0, st, m, p, sh, s);
     return hipGetLastError();
 }
 

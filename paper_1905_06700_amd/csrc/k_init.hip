@@ -493,7 +493,8 @@ __global__ __launch_bounds__(64 * INIT_WAVES) void k_init(DevModel m, DevParams 
 
     const long long P = sh.P, S = sh.S;
     const long long pix = (long long)xcd_block(blockIdx.x, gridDim.x) * INIT_WAVES + wv;
-    if (pix >= P) return;                       // whole wavefront; no workgroup barriers below
+    // whole wavefront (pixels of other IRF classes: their own launch); no workgroup barriers below
+    if (pix >= P || !in_class(m, pix)) return;
     const int nb = (T + 63) >> 6;
     uint2* lists = reinterpret_cast<uint2*>(smem64 + (size_t)wv * ww);
     unsigned long long* ub = smem64 + (size_t)wv * ww + side * side;

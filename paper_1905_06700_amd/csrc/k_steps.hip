@@ -160,20 +160,23 @@ __device__ __forceinline__ void s_eval_points(const DevModel& m, const PixPoints
 struct Lane {
     long long pix;
     int sub;
+    bool member;       // a pixel of the launch's IRF class (every pixel with one IRF)
     bool live;
     float G;
     PixPoints q;
     uint32_t e0, e1;   // the pixel's entries
 };
 
-__device__ __forceinline__ Lane lane_setup(const DevState& s, long long P, const uint32_t* __restrict__ off,
-                                           const float* __restrict__ gain, bool need_points)
+__device__ __forceinline__ Lane lane_setup(const DevModel& m, const DevState& s, long long P,
+                                           const uint32_t* __restrict__ off, const float* __restrict__ gain,
+                                           bool need_points)
 {
     Lane L;
     const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     L.pix = gid / LPP;
     L.sub = (int)(gid % LPP);
-    L.live = L.pix < P;
+    L.member = L.pix < P && in_class(m, L.pix);
+    L.live = L.member;
     const long long pp = L.live ? L.pix : 0;
     const uint32_t e0 = off[pp], e1 = off[pp + 1];
     L.G = L.live ? (gain ? gain[pp] : 1.f) : 0.f;
@@ -194,7 +197,7 @@ __global__ __launch_bounds__(256) void k_depth_step(DevModel m, DevParams p, Sha
     __shared__ uint32_t lists[256 / LPP * STEP_LIST];
     uint32_t* list = lists + (threadIdx.x / LPP) * STEP_LIST;
     const long long P = sh.P;
-    const Lane L = lane_setup(s, P, off, gain, true);
+    const Lane L = lane_setup(m, s, P, off, gain, true);
     float sz, shh[KM], shp[KM];
     accumulate(m, L.q, L.live ? s.b[L.pix] : 1.f, L.live ? L.G : 1.f, ent, L.e0, L.e1, L.sub, list, sz, shh, shp);
     reduce_lanes(sz, shh, shp);
@@ -256,8 +259,8 @@ __global__ __launch_bounds__(256) void k_intensity_step(DevModel m, DevParams p,
     __shared__ uint32_t lists[256 / LPP * STEP_LIST];
     uint32_t* list = lists + (threadIdx.x / LPP) * STEP_LIST;
     const long long P = sh.P;
-    Lane L = lane_setup(s, P, off, gain, true);
-    if (MERGE && L.pix < P) merge_lane(s, P, p, L.pix, L.sub, L.q);
+    Lane L = lane_setup(m, s, P, off, gain, true);
+    if (MERGE && L.member) merge_lane(s, P, p, L.pix, L.sub, L.q);
     float sz, shh[KM], shp[KM];
     accumulate(m, L.q, L.live ? s.b[L.pix] : 1.f, L.live ? L.G : 1.f, ent, L.e0, L.e1, L.sub, list, sz, shh, shp);
     reduce_lanes(sz, shh, shp);
@@ -279,13 +282,13 @@ __global__ __launch_bounds__(256) void k_bg_step(DevModel m, DevParams p, Shape 
     __shared__ uint32_t lists[256 / LPP * STEP_LIST];
     uint32_t* list = lists + (threadIdx.x / LPP) * STEP_LIST;
     const long long P = sh.P;
-    const Lane L = lane_setup(s, P, off, gain, false);
+    const Lane L = lane_setup(m, s, P, off, gain, false);
     const float braw = L.pix < P ? s.b[L.pix] : 1.f;
     const float bb = L.live ? braw : 1.f;
     float sz, shh[KM], shp[KM];
     accumulate(m, L.q, bb, L.live ? L.G : 1.f, ent, L.e0, L.e1, L.sub, list, sz, shh, shp);
     reduce_lanes(sz, shh, shp);
-    if (L.pix >= P || L.sub != 0) return;
+    if (!L.member || L.sub != 0) return;
     if (!L.live) {
         bdst[L.pix] = braw;
         return;
@@ -302,13 +305,13 @@ __global__ __launch_bounds__(256) void k_gradients(DevModel m, Shape sh, const u
     __shared__ uint32_t lists[256 / LPP * STEP_LIST];
     uint32_t* list = lists + (threadIdx.x / LPP) * STEP_LIST;
     const long long P = sh.P;
-    const Lane L = lane_setup(s, P, off, gain, false);
+    const Lane L = lane_setup(m, s, P, off, gain, false);
     float sz, shh[KM], shp[KM];
     accumulate(m, L.q, L.live ? s.b[L.pix] : 1.f, L.live ? L.G : 1.f, ent, L.e0, L.e1, L.sub, list, sz, shh, shp);
     reduce_lanes(sz, shh, shp);
     float Sv[KM], Spv[KM];
     s_eval_points(m, L.q, L.sub, Sv, Spv);
-    if (L.pix >= P || L.sub != 0) return;
+    if (!L.member || L.sub != 0) return;
     const float G = L.G;
 #pragma unroll
     for (int k = 0; k < KM; ++k) {

@@ -32,7 +32,20 @@ struct DevModel {
     int           s_np;
     const double* s_tab;
     double        s_v0, s_d0, s_v1, s_d1;
+    // Per-pixel IRFs: cls[pix] is the pixel's class and a launch with this
+    // model (class cls_id of n_cls) touches only the pixels of its class
+    // (numbers >= n_cls count as 0); cls = nullptr: every pixel.
+    const uint8_t* cls;
+    int            cls_id, n_cls;
 };
+
+// Whether pixel pix belongs to the launch's IRF class.
+__device__ __forceinline__ bool in_class(const DevModel& m, long long pix)
+{
+    if (!m.cls) return true;
+    const int k = m.cls[pix];
+    return (k < m.n_cls ? k : 0) == m.cls_id;
+}
 
 // Parameters as the kernels use them.
 struct DevParams {
@@ -509,7 +522,7 @@ hipError_t launch_bfilter_tiles(const float* w, int rb, const Tiles& tg, float b
                                 float* tmp, hipStream_t st);
 hipError_t launch_apss(const DevModel& m, const DevParams& p, const Shape& sh, DevState in,
                        DevState out, int only_above, hipStream_t st);
-hipError_t launch_merge(const DevParams& p, const Shape& sh, DevState s, hipStream_t st);
+hipError_t launch_merge(const DevModel& m, const DevParams& p, const Shape& sh, DevState s, hipStream_t st);
 hipError_t launch_ifilter(const DevParams& p, const Shape& sh, DevState in, DevState out,
                           hipStream_t st);
 // dst = the filtered src floored at b_min (src and dst distinct; tmp: P floats

@@ -21,23 +21,31 @@ size_t init_lds_bytes(int T, int L, int r_init);
 
 using namespace rt3d;
 
-struct rt3d_ctx {
-    rt3d_params p{};
-    int T = 0, L = 0, o = 0;
+// Everything the kernels need to know about one IRF (host facts and the
+// device tables it owns).
+struct IrfTables {
+    int L = 0, o = 0;
     double sigma2 = 0.0, fisher = 0.0;
     int s_np = 0;                      // pieces of S over all segments (0: direct summation)
     std::vector<double> s_tab;         // breakpoints then piece coefficients (see DevModel)
     double s_v0 = 0, s_d0 = 0, s_v1 = 0, s_d1 = 0;
-    int wl = 0, wr = 0, wnms = 0, apss_R = 0;
+    int wl = 0, wr = 0, wnms = 0;
     double dmax = 0.0, dmerge = 0.0;
     std::vector<double> hbar;
-    int device = 0;
-    // device tables (owned)
     float4* d_cr = nullptr;
     double* d_stab = nullptr;
     int32_t* d_q = nullptr;
     int32_t* d_qst = nullptr;
     double* d_hbar = nullptr;
+};
+
+struct rt3d_ctx {
+    rt3d_params p{};
+    int T = 0, apss_R = 0;
+    // IRF classes: 0 is rt3d_create's, later ones rt3d_add_irf's (per-pixel IRFs)
+    std::vector<IrfTables> irf;
+    const uint8_t* debug_cls = nullptr;   // class map of the step-by-step entry points
+    int device = 0;
     float* d_bw = nullptr;
     int rb = 0;
     // workspace (caller's)
@@ -133,6 +141,222 @@ Workspace carve(uint8_t* base, long long P, long long Ps, uint64_t E, bool with_
     return w;
 }
 
+// Tables of one IRF (normalised samples, Catmull-Rom segments, the piecewise
+// cubic of S, the shift Fisher information, peak windows, log-matched-filter
+// weights and their range maxima), built in FP64 and uploaded to the current
+// device.  E_INVALID for an unusable IRF, E_DEVICE on a HIP failure (what was
+// allocated is in t for free_irf).
+// The host-side checks of an IRF (no device call).
+rt3d_status check_irf(const double* irf, uint32_t irf_len, int32_t irf_origin, int T, const rt3d_params* p)
+{
+    if (!irf || irf_len == 0 || irf_len > (uint32_t)T) return RT3D_E_INVALID;
+    double sum = 0.0;
+    for (uint32_t k = 0; k < irf_len; ++k) {
+        if (!std::isfinite(irf[k]) || irf[k] < 0.0) return RT3D_E_INVALID;
+        sum += irf[k];
+    }
+    if (!(sum > 0.0)) return RT3D_E_INVALID;
+    if (irf_origin >= (int32_t)irf_len) return RT3D_E_INVALID;
+    if (init_lds_bytes(T, (int)irf_len, p->r_init) > 65536) return RT3D_E_UNSUPPORTED;
+    return RT3D_OK;
+}
+
+rt3d_status build_irf(const double* irf, uint32_t irf_len, int32_t irf_origin, int T, const rt3d_params* p,
+                      IrfTables& t)
+{
+    const rt3d_status ok = check_irf(irf, irf_len, irf_origin, T, p);
+    if (ok != RT3D_OK) return ok;
+    double sum = 0.0;
+    for (uint32_t k = 0; k < irf_len; ++k) sum += irf[k];
+    t.L = (int)irf_len;
+    t.hbar.resize(irf_len);
+    for (uint32_t k = 0; k < irf_len; ++k) t.hbar[k] = irf[k] / sum;
+    if (irf_origin < 0) {
+        int best = 0;
+        for (int k = 1; k < t.L; ++k)
+            if (t.hbar[k] > t.hbar[best]) best = k;
+        irf_origin = best;
+    }
+    t.o = irf_origin;
+    // moments and windows of the normalised IRF
+    double mu = 0.0;
+    for (int k = 0; k < t.L; ++k) mu += k * t.hbar[k];
+    double var = 0.0;
+    for (int k = 0; k < t.L; ++k) var += t.hbar[k] * (k - mu) * (k - mu);
+    t.sigma2 = var;
+    const double sh = std::sqrt(var);
+    {
+        double acc = 0.0;
+        int lo = -1, hi = -1;
+        for (int k = 0; k < t.L; ++k) {
+            acc += t.hbar[k];
+            if (lo < 0 && acc >= 0.05) lo = k;
+            if (hi < 0 && acc >= 0.95) hi = k;
+        }
+        if (lo < 0) lo = 0;
+        if (hi < 0) hi = t.L - 1;
+        t.wl = std::max(0, t.o - lo);
+        t.wr = std::max(0, hi - t.o);
+    }
+    t.wnms = p->w_nms > 0 ? p->w_nms : (int)std::ceil(std::max(1.0, 2.0 * sh));
+    t.dmerge = p->d_merge > 0 ? p->d_merge : std::max(1.0, sh);
+
+    const int L = t.L;
+    // Catmull-Rom cubic of each segment between samples k and k+1, k = -1..L-1
+    // (samples beyond the IRF are zero): value c0 + c1 s + c2 s^2 + c3 s^3
+    auto hb = [&](int k) { return (k >= 0 && k < L) ? t.hbar[k] : 0.0; };
+    std::vector<float4> cr(L + 1);
+    std::vector<double> crd((size_t)4 * (L + 1));
+    for (int k = -1; k < L; ++k) {
+        const double p0 = hb(k - 1), p1 = hb(k), p2 = hb(k + 1), p3 = hb(k + 2);
+        double* d = &crd[(size_t)4 * (k + 1)];
+        d[0] = p1;
+        d[1] = 0.5 * (p2 - p0);
+        d[2] = p0 - 2.5 * p1 + 2.0 * p2 - 0.5 * p3;
+        d[3] = 0.5 * (p3 - p0) + 1.5 * (p1 - p2);
+        cr[k + 1] = make_float4((float)d[0], (float)d[1], (float)d[2], (float)d[3]);
+    }
+    // S and S' of points whose IRF support lies inside the domain, as a
+    // piecewise cubic in the local parameter s that every segment shares:
+    // between consecutive zeros (in (0, 1)) of the segments' cubics each
+    // segment keeps its sign, so the sum of the segments clamped at zero is
+    // one cubic per piece.  At s = 0 and s = 1 segments whose value is not
+    // positive drop out with their slope; those sums are kept apart.
+    {
+        std::vector<double> brk = {0.0, 1.0};
+        for (int j = 0; j <= L; ++j) {
+            const double* d = &crd[(size_t)4 * j];
+            auto val = [&](double x) { return ((d[3] * x + d[2]) * x + d[1]) * x + d[0]; };
+            // monotone stretches of [0, 1] between the slope's zeros, each
+            // bisected where the cubic changes sign
+            std::vector<double> cut = {0.0, 1.0};
+            const double A = 3.0 * d[3], B = 2.0 * d[2], Cc = d[1];
+            if (A != 0.0) {
+                const double disc = B * B - 4.0 * A * Cc;
+                if (disc >= 0.0) {
+                    const double r = std::sqrt(disc);
+                    for (double x : {(-B - r) / (2.0 * A), (-B + r) / (2.0 * A)})
+                        if (x > 0.0 && x < 1.0) cut.push_back(x);
+                }
+            } else if (B != 0.0) {
+                const double x = -Cc / B;
+                if (x > 0.0 && x < 1.0) cut.push_back(x);
+            }
+            std::sort(cut.begin(), cut.end());
+            for (size_t u = 0; u + 1 < cut.size(); ++u) {
+                double lo = cut[u], hi = cut[u + 1];
+                double flo = val(lo), fhi = val(hi);
+                if (!((flo < 0.0 && fhi > 0.0) || (flo > 0.0 && fhi < 0.0))) continue;
+                for (int it = 0; it < 200 && hi - lo > 0.0; ++it) {
+                    const double mid = 0.5 * (lo + hi);
+                    if (mid <= lo || mid >= hi) break;
+                    const double fm = val(mid);
+                    if ((fm < 0.0) == (flo < 0.0)) {
+                        lo = mid;
+                        flo = fm;
+                    } else {
+                        hi = mid;
+                    }
+                }
+                brk.push_back(0.5 * (lo + hi));
+            }
+        }
+        std::sort(brk.begin(), brk.end());
+        brk.erase(std::unique(brk.begin(), brk.end()), brk.end());
+        std::vector<double> coef;
+        for (size_t u = 0; u + 1 < brk.size(); ++u) {
+            const double mid = 0.5 * (brk[u] + brk[u + 1]);
+            double cs[4] = {0, 0, 0, 0};
+            for (int j = 0; j <= L; ++j) {
+                const double* d = &crd[(size_t)4 * j];
+                if (((d[3] * mid + d[2]) * mid + d[1]) * mid + d[0] > 0.0)
+                    for (int i = 0; i < 4; ++i) cs[i] += d[i];
+            }
+            coef.insert(coef.end(), cs, cs + 4);
+        }
+        for (int j = 0; j <= L; ++j) {
+            const double* d = &crd[(size_t)4 * j];
+            if (d[0] > 0.0) {
+                t.s_v0 += d[0];
+                t.s_d0 += d[1];
+            }
+            const double v1 = d[0] + d[1] + d[2] + d[3];
+            if (v1 > 0.0) {
+                t.s_v1 += v1;
+                t.s_d1 += d[1] + 2.0 * d[2] + 3.0 * d[3];
+            }
+        }
+        const int np = (int)brk.size() - 1;
+        if (np >= 1 && np <= S_PIECES_MAX) {
+            t.s_np = np;
+            t.s_tab = brk;
+            t.s_tab.insert(t.s_tab.end(), coef.begin(), coef.end());
+        }
+    }
+    // shift Fisher information of one photon (no background), averaged over 32
+    // sub-bin phases, over lags where h is at least 1e-3 of the largest sample
+    {
+        double hmax = 0.0;
+        for (int k = 0; k < L; ++k) hmax = std::max(hmax, t.hbar[k]);
+        double acc = 0.0;
+        for (int j = 0; j < 32; ++j) {
+            for (int l = -t.o - 1; l <= L - t.o; ++l) {
+                const double x = l + j / 32.0 + t.o;
+                if (!(x > -1.0) || !(x < L)) continue;
+                const int k = (int)std::floor(x);
+                const double sl = x - k;
+                const double* d = &crd[(size_t)4 * (k + 1)];
+                const double h = ((d[3] * sl + d[2]) * sl + d[1]) * sl + d[0];
+                if (!(h > 0.0) || h < 1e-3 * hmax) continue;
+                const double hp = (3.0 * d[3] * sl + 2.0 * d[2]) * sl + d[1];
+                acc += hp * hp / h;
+            }
+        }
+        t.fisher = acc / 32.0;
+    }
+    if (!(t.fisher > 0.0)) return RT3D_E_INVALID;
+    t.dmax = p->dmax > 0 ? p->dmax : std::max(0.5, 1.0 / std::sqrt(t.fisher));
+    // log-matched filter weights, 16 fractional bits
+    std::vector<int32_t> q(L);
+    const double inv_eps = p->sbr_guess * (double)T;
+    for (int k = 0; k < L; ++k) q[k] = (int32_t)std::llround(std::log1p(t.hbar[k] * inv_eps) * 65536.0);
+    // range-maximum table of q: level l holds max q[k .. k + 2^l - 1]
+    int nlev = 1;
+    while ((1 << nlev) <= L) ++nlev;
+    std::vector<int32_t> qst((size_t)nlev * L);
+    for (int k = 0; k < L; ++k) qst[k] = q[k];
+    for (int l = 1; l < nlev; ++l)
+        for (int k = 0; k < L; ++k) {
+            const int a = qst[(size_t)(l - 1) * L + k];
+            const int k2 = k + (1 << (l - 1));
+            const int b = k2 < L ? qst[(size_t)(l - 1) * L + k2] : a;
+            qst[(size_t)l * L + k] = std::max(a, b);
+        }
+    hipError_t e = hipMalloc(&t.d_cr, sizeof(float4) * cr.size());
+    if (e == hipSuccess) e = hipMalloc(&t.d_q, sizeof(int32_t) * q.size());
+    if (e == hipSuccess) e = hipMalloc(&t.d_qst, sizeof(int32_t) * qst.size());
+    if (e == hipSuccess) e = hipMalloc(&t.d_hbar, sizeof(double) * L);
+    if (e == hipSuccess && t.s_np > 0) e = hipMalloc(&t.d_stab, sizeof(double) * t.s_tab.size());
+    if (e == hipSuccess && t.s_np > 0)
+        e = hipMemcpy(t.d_stab, t.s_tab.data(), sizeof(double) * t.s_tab.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(t.d_cr, cr.data(), sizeof(float4) * cr.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(t.d_q, q.data(), sizeof(int32_t) * q.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(t.d_qst, qst.data(), sizeof(int32_t) * qst.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(t.d_hbar, t.hbar.data(), sizeof(double) * L, hipMemcpyHostToDevice);
+    return e == hipSuccess ? RT3D_OK : RT3D_E_DEVICE;
+}
+
+void free_irf(IrfTables& t)
+{
+    for (void* ptr : {(void*)t.d_cr, (void*)t.d_stab, (void*)t.d_q, (void*)t.d_qst, (void*)t.d_hbar})
+        if (ptr) (void)hipFree(ptr);
+    t.d_cr = nullptr;
+    t.d_stab = nullptr;
+    t.d_q = nullptr;
+    t.d_qst = nullptr;
+    t.d_hbar = nullptr;
+}
+
 rt3d_status fail(rt3d_ctx* c, rt3d_status st, const std::string& msg)
 {
     if (c) c->err = msg;
@@ -175,31 +399,38 @@ bool prof_begin(rt3d_ctx* c, int id, hipStream_t st, size_t& slot)
         if (e_ != hipSuccess) return hip_fail(ctx, e_, #call);   \
     } while (0)
 
-DevModel dev_model(const rt3d_ctx* c)
+// The model of IRF class k; with a per-pixel class map `cls`, a launch with
+// it touches only the pixels of class k (class numbers past the context's
+// classes count as 0).
+DevModel dev_model(const rt3d_ctx* c, int k = 0, const uint8_t* cls = nullptr)
 {
+    const IrfTables& t = c->irf[k];
     DevModel m{};
-    m.cr = c->d_cr;
-    m.q = c->d_q;
-    m.qst = c->d_qst;
-    m.hbar = c->d_hbar;
+    m.cr = t.d_cr;
+    m.q = t.d_q;
+    m.qst = t.d_qst;
+    m.hbar = t.d_hbar;
     m.T = c->T;
-    m.L = c->L;
-    m.o = c->o;
-    m.wl = c->wl;
-    m.wr = c->wr;
-    m.wnms = c->wnms;
-    m.sigma2 = (float)c->sigma2;
-    m.fisher_inv = (float)(1.0 / c->fisher);
-    m.s_np = c->s_np;
-    m.s_tab = c->d_stab;
-    m.s_v0 = c->s_v0;
-    m.s_d0 = c->s_d0;
-    m.s_v1 = c->s_v1;
-    m.s_d1 = c->s_d1;
+    m.L = t.L;
+    m.o = t.o;
+    m.wl = t.wl;
+    m.wr = t.wr;
+    m.wnms = t.wnms;
+    m.sigma2 = (float)t.sigma2;
+    m.fisher_inv = (float)(1.0 / t.fisher);
+    m.s_np = t.s_np;
+    m.s_tab = t.d_stab;
+    m.s_v0 = t.s_v0;
+    m.s_d0 = t.s_d0;
+    m.s_v1 = t.s_v1;
+    m.s_d1 = t.s_d1;
+    m.cls = cls;
+    m.cls_id = k;
+    m.n_cls = (int)c->irf.size();
     return m;
 }
 
-DevParams dev_params(const rt3d_ctx* c)
+DevParams dev_params(const rt3d_ctx* c, int k = 0)
 {
     DevParams d{};
     const rt3d_params& p = c->p;
@@ -214,11 +445,11 @@ DevParams dev_params(const rt3d_ctx* c)
     d.h_apss = p.h_apss;
     d.h_int = p.h_int;
     d.beta_t = p.beta_t;
-    d.dmax = c->dmax;
+    d.dmax = c->irf[k].dmax;
     d.beta_r = p.beta_r;
     d.beta_b = p.beta_b;
     d.r_min = p.r_min;
-    d.d_merge = c->dmerge;
+    d.d_merge = c->irf[k].dmerge;
     d.b_min = p.b_min;
     d.kappa = p.kappa;
     return d;
@@ -331,16 +562,24 @@ bool use_fused(const rt3d_ctx* c, const Shape& sh)
     return sh.F >= 64;
 }
 
+// IRF classes a call launches its IRF-dependent kernels for: every class of
+// the context with a per-pixel class map, else class 0 alone.
+int n_classes(const rt3d_ctx* c, const uint8_t* cls) { return cls ? (int)c->irf.size() : 1; }
+
 // One iteration of the loop on state A (in/out) with B as the second buffer.
-// Per-pixel steps run once over the batch (sh); steps that read neighbouring
-// pixels run once per group of equally sized frames.
+// Per-pixel steps run once over the batch (sh), once per IRF class with a
+// class map cls; steps that read neighbouring pixels run once per group of
+// equally sized frames.
 rt3d_status iterate(rt3d_ctx* c, const Shape& sh, const std::vector<Group>& groups, const uint32_t* off,
                     const uint32_t* ent, const float* gain, DevState A, DevState B, float* btmp,
-                    const CnnBuffers* cnn, hipStream_t st)
+                    const CnnBuffers* cnn, const uint8_t* cls, hipStream_t st)
 {
     const DevModel m = dev_model(c);
     const DevParams p = dev_params(c);
-    RT3D_LAUNCH(c, RT3D_KERNEL_DEPTH, st, launch_depth_step(m, p, sh, off, ent, gain, A, st));
+    const int nc = n_classes(c, cls);
+    for (int k = 0; k < nc; ++k)
+        RT3D_LAUNCH(c, RT3D_KERNEL_DEPTH, st,
+                    launch_depth_step(dev_model(c, k, cls), dev_params(c, k), sh, off, ent, gain, A, st));
     DevState cur = A;
     // the groups as tile tables of at most TILE_GROUPS groups (one launch each)
     std::vector<Tiles> tiles(1, Tiles{});
@@ -356,19 +595,23 @@ rt3d_status iterate(rt3d_ctx* c, const Shape& sh, const std::vector<Group>& grou
     } else if (c->p.denoiser == RT3D_DENOISE_CNN) {
         // APSS only for pixels holding more points than the network's three slots
         RT3D_LAUNCH(c, RT3D_KERNEL_APSS, st, launch_apss(m, p, sh, A, B, 3, st));
-        RT3D_LAUNCH(c, RT3D_KERNEL_CNN, st, launch_cnn_forward(sh, B, (float)std::sqrt(c->sigma2), c->cnn, *cnn, st));
-        RT3D_HIP(c, launch_cnn_apply(sh, *cnn, (float)std::sqrt(c->sigma2), (double)(c->T - 1), B, st));
+        RT3D_LAUNCH(c, RT3D_KERNEL_CNN, st, launch_cnn_forward(sh, B, (float)std::sqrt(c->irf[0].sigma2), c->cnn, *cnn, st));
+        RT3D_HIP(c, launch_cnn_apply(sh, *cnn, (float)std::sqrt(c->irf[0].sigma2), (double)(c->T - 1), B, st));
         cur = B;
     } else {
         RT3D_HIP(c, launch_copy_state(sh, A, B, st));
         cur = B;
     }
     // the in-pixel merge runs fused ahead of the intensity step
-    RT3D_LAUNCH(c, RT3D_KERNEL_INTENSITY, st, launch_intensity_step(m, p, sh, off, ent, gain, cur, true, st));
+    for (int k = 0; k < nc; ++k)
+        RT3D_LAUNCH(c, RT3D_KERNEL_INTENSITY, st,
+                    launch_intensity_step(dev_model(c, k, cls), dev_params(c, k), sh, off, ent, gain, cur, true, st));
     for (const Tiles& tg : tiles)
         RT3D_LAUNCH(c, RT3D_KERNEL_IFILTER, st, launch_ifilter_tiles(p, tg, cur, A, st));
     // the background step writes btmp; the filter brings it back into A.b
-    RT3D_LAUNCH(c, RT3D_KERNEL_BKG, st, launch_bg_step(m, p, sh, off, ent, gain, A, btmp, st));
+    for (int k = 0; k < nc; ++k)
+        RT3D_LAUNCH(c, RT3D_KERNEL_BKG, st,
+                    launch_bg_step(dev_model(c, k, cls), dev_params(c, k), sh, off, ent, gain, A, btmp, st));
     for (const Tiles& tg : tiles)
         RT3D_LAUNCH(c, RT3D_KERNEL_BFILTER, st,
                     launch_bfilter_tiles(c->d_bw, c->rb, tg, (float)c->p.b_min, btmp, A.b, B.b, st));
@@ -402,7 +645,7 @@ rt3d_status iterate_sr(rt3d_ctx* c, const Shape& lid, const uint32_t* off, const
         RT3D_LAUNCH(c, RT3D_KERNEL_APSS, st, launch_apss(m, p, fsh, A, B, -1, st));
     else
         RT3D_HIP(c, launch_copy_state(fsh, A, B, st));
-    RT3D_LAUNCH(c, RT3D_KERNEL_MERGE, st, launch_merge(p, fsh, B, st));
+    RT3D_LAUNCH(c, RT3D_KERNEL_MERGE, st, launch_merge(m, p, fsh, B, st));
     RT3D_LAUNCH(c, RT3D_KERNEL_INTENSITY, st,
                 launch_sr_step(RT3D_STEP_INTENSITY, m, p, lid, sr, fsh.P, off, ent, gain, B, nullptr, st));
     RT3D_LAUNCH(c, RT3D_KERNEL_IFILTER, st, launch_ifilter(p, fsh, B, A, st));
@@ -471,187 +714,26 @@ rt3d_status rt3d_create(const double* irf, uint32_t irf_len, int32_t irf_origin,
     std::string why;
     rt3d_status ps = check_params(p, bins, why);
     if (ps != RT3D_OK) return ps;
-    double sum = 0.0;
-    for (uint32_t k = 0; k < irf_len; ++k) {
-        if (!std::isfinite(irf[k]) || irf[k] < 0.0) return RT3D_E_INVALID;
-        sum += irf[k];
-    }
-    if (!(sum > 0.0)) return RT3D_E_INVALID;
-    if (irf_origin >= (int32_t)irf_len) return RT3D_E_INVALID;
-    if (init_lds_bytes((int)bins, (int)irf_len, p->r_init) > 65536) return RT3D_E_UNSUPPORTED;
+    ps = check_irf(irf, irf_len, irf_origin, (int)bins, p);
+    if (ps != RT3D_OK) return ps;
 
     rt3d_ctx* c = new (std::nothrow) rt3d_ctx();
     if (!c) return RT3D_E_NOMEM;
     c->p = *p;
     c->T = (int)bins;
-    c->L = (int)irf_len;
-    c->hbar.resize(irf_len);
-    for (uint32_t k = 0; k < irf_len; ++k) c->hbar[k] = irf[k] / sum;
-    if (irf_origin < 0) {
-        int best = 0;
-        for (int k = 1; k < c->L; ++k)
-            if (c->hbar[k] > c->hbar[best]) best = k;
-        irf_origin = best;
-    }
-    c->o = irf_origin;
-    // moments and windows of the normalised IRF
-    double mu = 0.0;
-    for (int k = 0; k < c->L; ++k) mu += k * c->hbar[k];
-    double var = 0.0;
-    for (int k = 0; k < c->L; ++k) var += c->hbar[k] * (k - mu) * (k - mu);
-    c->sigma2 = var;
-    const double sh = std::sqrt(var);
-    {
-        double acc = 0.0;
-        int lo = -1, hi = -1;
-        for (int k = 0; k < c->L; ++k) {
-            acc += c->hbar[k];
-            if (lo < 0 && acc >= 0.05) lo = k;
-            if (hi < 0 && acc >= 0.95) hi = k;
-        }
-        if (lo < 0) lo = 0;
-        if (hi < 0) hi = c->L - 1;
-        c->wl = std::max(0, c->o - lo);
-        c->wr = std::max(0, hi - c->o);
-    }
-    c->wnms = p->w_nms > 0 ? p->w_nms : (int)std::ceil(std::max(1.0, 2.0 * sh));
-    c->dmerge = p->d_merge > 0 ? p->d_merge : std::max(1.0, sh);
     c->apss_R = (int)std::ceil(p->h_apss / p->p_xy);
-
-    const int L = c->L, T = c->T;
-    // Catmull-Rom cubic of each segment between samples k and k+1, k = -1..L-1
-    // (samples beyond the IRF are zero): value c0 + c1 s + c2 s^2 + c3 s^3
-    auto hb = [&](int k) { return (k >= 0 && k < L) ? c->hbar[k] : 0.0; };
-    std::vector<float4> cr(L + 1);
-    std::vector<double> crd((size_t)4 * (L + 1));
-    for (int k = -1; k < L; ++k) {
-        const double p0 = hb(k - 1), p1 = hb(k), p2 = hb(k + 1), p3 = hb(k + 2);
-        double* d = &crd[(size_t)4 * (k + 1)];
-        d[0] = p1;
-        d[1] = 0.5 * (p2 - p0);
-        d[2] = p0 - 2.5 * p1 + 2.0 * p2 - 0.5 * p3;
-        d[3] = 0.5 * (p3 - p0) + 1.5 * (p1 - p2);
-        cr[k + 1] = make_float4((float)d[0], (float)d[1], (float)d[2], (float)d[3]);
-    }
-    // S and S' of points whose IRF support lies inside the domain, as a
-    // piecewise cubic in the local parameter s that every segment shares:
-    // between consecutive zeros (in (0, 1)) of the segments' cubics each
-    // segment keeps its sign, so the sum of the segments clamped at zero is
-    // one cubic per piece.  At s = 0 and s = 1 segments whose value is not
-    // positive drop out with their slope; those sums are kept apart.
-    {
-        std::vector<double> brk = {0.0, 1.0};
-        for (int j = 0; j <= L; ++j) {
-            const double* d = &crd[(size_t)4 * j];
-            auto val = [&](double x) { return ((d[3] * x + d[2]) * x + d[1]) * x + d[0]; };
-            // monotone stretches of [0, 1] between the slope's zeros, each
-            // bisected where the cubic changes sign
-            std::vector<double> cut = {0.0, 1.0};
-            const double A = 3.0 * d[3], B = 2.0 * d[2], Cc = d[1];
-            if (A != 0.0) {
-                const double disc = B * B - 4.0 * A * Cc;
-                if (disc >= 0.0) {
-                    const double r = std::sqrt(disc);
-                    for (double x : {(-B - r) / (2.0 * A), (-B + r) / (2.0 * A)})
-                        if (x > 0.0 && x < 1.0) cut.push_back(x);
-                }
-            } else if (B != 0.0) {
-                const double x = -Cc / B;
-                if (x > 0.0 && x < 1.0) cut.push_back(x);
-            }
-            std::sort(cut.begin(), cut.end());
-            for (size_t u = 0; u + 1 < cut.size(); ++u) {
-                double lo = cut[u], hi = cut[u + 1];
-                double flo = val(lo), fhi = val(hi);
-                if (!((flo < 0.0 && fhi > 0.0) || (flo > 0.0 && fhi < 0.0))) continue;
-                for (int it = 0; it < 200 && hi - lo > 0.0; ++it) {
-                    const double mid = 0.5 * (lo + hi);
-                    if (mid <= lo || mid >= hi) break;
-                    const double fm = val(mid);
-                    if ((fm < 0.0) == (flo < 0.0)) {
-                        lo = mid;
-                        flo = fm;
-                    } else {
-                        hi = mid;
-                    }
-                }
-                brk.push_back(0.5 * (lo + hi));
-            }
-        }
-        std::sort(brk.begin(), brk.end());
-        brk.erase(std::unique(brk.begin(), brk.end()), brk.end());
-        std::vector<double> coef;
-        for (size_t u = 0; u + 1 < brk.size(); ++u) {
-            const double mid = 0.5 * (brk[u] + brk[u + 1]);
-            double cs[4] = {0, 0, 0, 0};
-            for (int j = 0; j <= L; ++j) {
-                const double* d = &crd[(size_t)4 * j];
-                if (((d[3] * mid + d[2]) * mid + d[1]) * mid + d[0] > 0.0)
-                    for (int i = 0; i < 4; ++i) cs[i] += d[i];
-            }
-            coef.insert(coef.end(), cs, cs + 4);
-        }
-        for (int j = 0; j <= L; ++j) {
-            const double* d = &crd[(size_t)4 * j];
-            if (d[0] > 0.0) {
-                c->s_v0 += d[0];
-                c->s_d0 += d[1];
-            }
-            const double v1 = d[0] + d[1] + d[2] + d[3];
-            if (v1 > 0.0) {
-                c->s_v1 += v1;
-                c->s_d1 += d[1] + 2.0 * d[2] + 3.0 * d[3];
-            }
-        }
-        const int np = (int)brk.size() - 1;
-        if (np >= 1 && np <= S_PIECES_MAX) {
-            c->s_np = np;
-            c->s_tab = brk;
-            c->s_tab.insert(c->s_tab.end(), coef.begin(), coef.end());
-        }
-    }
-    // shift Fisher information of one photon (no background), averaged over 32
-    // sub-bin phases, over lags where h is at least 1e-3 of the largest sample
-    {
-        double hmax = 0.0;
-        for (int k = 0; k < L; ++k) hmax = std::max(hmax, c->hbar[k]);
-        double acc = 0.0;
-        for (int j = 0; j < 32; ++j) {
-            for (int l = -c->o - 1; l <= L - c->o; ++l) {
-                const double x = l + j / 32.0 + c->o;
-                if (!(x > -1.0) || !(x < L)) continue;
-                const int k = (int)std::floor(x);
-                const double sl = x - k;
-                const double* d = &crd[(size_t)4 * (k + 1)];
-                const double h = ((d[3] * sl + d[2]) * sl + d[1]) * sl + d[0];
-                if (!(h > 0.0) || h < 1e-3 * hmax) continue;
-                const double hp = (3.0 * d[3] * sl + 2.0 * d[2]) * sl + d[1];
-                acc += hp * hp / h;
-            }
-        }
-        c->fisher = acc / 32.0;
-    }
-    if (!(c->fisher > 0.0)) {
+    if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;
-        return RT3D_E_INVALID;
+        return RT3D_E_DEVICE;
     }
-    c->dmax = p->dmax > 0 ? p->dmax : std::max(0.5, 1.0 / std::sqrt(c->fisher));
-    // log-matched filter weights, 16 fractional bits
-    std::vector<int32_t> q(L);
-    const double inv_eps = p->sbr_guess * (double)T;
-    for (int k = 0; k < L; ++k) q[k] = (int32_t)std::llround(std::log1p(c->hbar[k] * inv_eps) * 65536.0);
-    // range-maximum table of q: level l holds max q[k .. k + 2^l - 1]
-    int nlev = 1;
-    while ((1 << nlev) <= L) ++nlev;
-    std::vector<int32_t> qst((size_t)nlev * L);
-    for (int k = 0; k < L; ++k) qst[k] = q[k];
-    for (int l = 1; l < nlev; ++l)
-        for (int k = 0; k < L; ++k) {
-            const int a = qst[(size_t)(l - 1) * L + k];
-            const int k2 = k + (1 << (l - 1));
-            const int b = k2 < L ? qst[(size_t)(l - 1) * L + k2] : a;
-            qst[(size_t)l * L + k] = std::max(a, b);
+    {
+        c->irf.emplace_back();
+        const rt3d_status bs = build_irf(irf, irf_len, irf_origin, c->T, p, c->irf[0]);
+        if (bs != RT3D_OK) {
+            rt3d_destroy(c);
+            return bs;
         }
+    }
     // background filter taps
     std::vector<float> bw;
     if (p->sigma_b > 0.0) {
@@ -668,19 +750,7 @@ rt3d_status rt3d_create(const double* irf, uint32_t irf_len, int32_t irf_origin,
         bw.push_back(1.0f);
     }
 
-    hipError_t e = hipGetDevice(&c->device);
-    if (e == hipSuccess) e = hipMalloc(&c->d_cr, sizeof(float4) * cr.size());
-    if (e == hipSuccess) e = hipMalloc(&c->d_q, sizeof(int32_t) * q.size());
-    if (e == hipSuccess) e = hipMalloc(&c->d_qst, sizeof(int32_t) * qst.size());
-    if (e == hipSuccess) e = hipMalloc(&c->d_hbar, sizeof(double) * L);
-    if (e == hipSuccess) e = hipMalloc(&c->d_bw, sizeof(float) * bw.size());
-    if (e == hipSuccess && c->s_np > 0) e = hipMalloc(&c->d_stab, sizeof(double) * c->s_tab.size());
-    if (e == hipSuccess && c->s_np > 0)
-        e = hipMemcpy(c->d_stab, c->s_tab.data(), sizeof(double) * c->s_tab.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(c->d_cr, cr.data(), sizeof(float4) * cr.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(c->d_q, q.data(), sizeof(int32_t) * q.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(c->d_qst, qst.data(), sizeof(int32_t) * qst.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(c->d_hbar, c->hbar.data(), sizeof(double) * L, hipMemcpyHostToDevice);
+    hipError_t e = hipMalloc(&c->d_bw, sizeof(float) * bw.size());
     if (e == hipSuccess) e = hipMemcpy(c->d_bw, bw.data(), sizeof(float) * bw.size(), hipMemcpyHostToDevice);
     // learned-denoiser weights: FP32 master, Adam moments, FP16 layouts, biases (all zero)
     if (e == hipSuccess) e = hipMalloc(&c->cnn.master, sizeof(float) * 3 * CNN_PARAMS);
@@ -735,11 +805,7 @@ void rt3d_destroy(rt3d_ctx* c)
     if (!c) return;
     int prev = 0;
     bool switched = hipGetDevice(&prev) == hipSuccess && prev != c->device && hipSetDevice(c->device) == hipSuccess;
-    if (c->d_cr) (void)hipFree(c->d_cr);
-    if (c->d_stab) (void)hipFree(c->d_stab);
-    if (c->d_q) (void)hipFree(c->d_q);
-    if (c->d_qst) (void)hipFree(c->d_qst);
-    if (c->d_hbar) (void)hipFree(c->d_hbar);
+    for (IrfTables& t : c->irf) free_irf(t);
     if (c->d_bw) (void)hipFree(c->d_bw);
     for (hipEvent_t ev : c->prof_ev) (void)hipEventDestroy(ev);
     if (c->cnn.master) (void)hipFree(c->cnn.master);
@@ -754,7 +820,7 @@ void rt3d_destroy(rt3d_ctx* c)
 
 const char* rt3d_last_error(const rt3d_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
-double rt3d_sigma2(const rt3d_ctx* c) { return c ? c->sigma2 : 0.0; }
+double rt3d_sigma2(const rt3d_ctx* c) { return c ? c->irf[0].sigma2 : 0.0; }
 
 size_t rt3d_workspace_bytes(const rt3d_ctx* c, uint32_t frames, uint32_t rows, uint32_t cols, uint64_t max_entries)
 {
@@ -842,6 +908,9 @@ rt3d_status rt3d_reconstruct(rt3d_ctx* c, const rt3d_input* in, rt3d_output* out
     if (groups.size() == 1) sh = groups[0].sh;
     if (sh.P * c->p.sr * c->p.sr >= (1ll << 31))
         return fail(c, RT3D_E_INVALID, "the point grid's pixels must total below 2^31");
+    const uint8_t* cls = in->irf_class;
+    if (cls && (c->p.sr > 1 || c->p.denoiser == RT3D_DENOISE_CNN))
+        return fail(c, RT3D_E_UNSUPPORTED, "per-pixel IRFs with super-resolution or the learned denoiser");
     const std::vector<long long> prev_layout = c->state_layout;   // need_ws forgets it
     Workspace w;
     rt3d_status s = need_ws(c, sh.P, w);
@@ -889,9 +958,11 @@ rt3d_status rt3d_reconstruct(rt3d_ctx* c, const rt3d_input* in, rt3d_output* out
         if (s != RT3D_OK) return s;
     } else {
         for (const Group& g : groups)
-            RT3D_LAUNCH(c, RT3D_KERNEL_INIT, st,
-                        launch_init(m, p, g.sh, off + g.base, ent, in->gain ? in->gain + g.base : nullptr,
-                                    state_at(w.A, g.base), w.err, st));
+            for (int k = 0; k < n_classes(c, cls); ++k)
+                RT3D_LAUNCH(c, RT3D_KERNEL_INIT, st,
+                            launch_init(dev_model(c, k, cls ? cls + g.base : nullptr), dev_params(c, k), g.sh,
+                                        off + g.base, ent, in->gain ? in->gain + g.base : nullptr,
+                                        state_at(w.A, g.base), w.err, st));
         for (const Group& g : groups)
             RT3D_LAUNCH(c, RT3D_KERNEL_NORMALS, st, launch_init_normals(p, g.sh, state_at(w.A, g.base), st));
     }
@@ -901,12 +972,12 @@ rt3d_status rt3d_reconstruct(rt3d_ctx* c, const rt3d_input* in, rt3d_output* out
             s = iterate_sr(c, sh, off, ent, in->gain, w.A, w.B, w.btmp, st);
             if (s != RT3D_OK) return s;
         }
-    } else if (loop_eligible(c, groups, sh) && use_fused(c, sh)) {
+    } else if (!cls && loop_eligible(c, groups, sh) && use_fused(c, sh)) {
         RT3D_LAUNCH(c, RT3D_KERNEL_LOOP, st,
                     launch_loop(m, p, sh, off, ent, in->gain, w.A, w.B, w.btmp, c->d_bw, c->rb, c->p.n_iter, st));
     } else {
         for (int it = 0; it < c->p.n_iter; ++it) {
-            s = iterate(c, sh, groups, off, ent, in->gain, w.A, w.B, w.btmp, &w.cnn, st);
+            s = iterate(c, sh, groups, off, ent, in->gain, w.A, w.B, w.btmp, &w.cnn, cls, st);
             if (s != RT3D_OK) return s;
         }
     }
@@ -1121,7 +1192,7 @@ static rt3d_status debug_step_sr(rt3d_ctx* c, int32_t step, const uint32_t* off,
         RT3D_HIP(c, launch_sr_step(step, m, p, lid, sr, fsh.P, off, ent, gain, O, nullptr, st));
         return RT3D_OK;
     case RT3D_STEP_MERGE:
-        RT3D_HIP(c, launch_merge(p, fsh, O, st));
+        RT3D_HIP(c, launch_merge(m, p, fsh, O, st));
         return RT3D_OK;
     case RT3D_STEP_BFILTER:
         RT3D_HIP(c, launch_bfilter(c->d_bw, c->rb, lid, (float)c->p.b_min, O.b, w.btmp, w.B.b, st));
@@ -1153,10 +1224,16 @@ rt3d_status rt3d_debug_step(rt3d_ctx* c, int32_t step, const uint32_t* off, cons
     const DevModel m = dev_model(c);
     const DevParams p = dev_params(c);
     DevState O = dev_state(out);
-    if (c->p.sr > 1) return debug_step_sr(c, step, off, ent, gain, in, out, st);
+    const uint8_t* cls = c->debug_cls;
+    const int nc = n_classes(c, cls);
+    if (c->p.sr > 1) {
+        if (cls) return fail(c, RT3D_E_UNSUPPORTED, "per-pixel IRFs with super-resolution");
+        return debug_step_sr(c, step, off, ent, gain, in, out, st);
+    }
     switch (step) {
     case RT3D_STEP_INIT:
-        RT3D_HIP(c, launch_init(m, p, sh, off, ent, gain, O, nullptr, st));
+        for (int k = 0; k < nc; ++k)
+            RT3D_HIP(c, launch_init(dev_model(c, k, cls), dev_params(c, k), sh, off, ent, gain, O, nullptr, st));
         RT3D_HIP(c, launch_init_normals(p, sh, O, st));
         return RT3D_OK;
     case RT3D_STEP_APSS:
@@ -1172,16 +1249,20 @@ rt3d_status rt3d_debug_step(rt3d_ctx* c, int32_t step, const uint32_t* off, cons
     RT3D_HIP(c, launch_copy_state(sh, dev_state(in), O, st));
     switch (step) {
     case RT3D_STEP_DEPTH:
-        RT3D_HIP(c, launch_depth_step(m, p, sh, off, ent, gain, O, st));
+        for (int k = 0; k < nc; ++k)
+            RT3D_HIP(c, launch_depth_step(dev_model(c, k, cls), dev_params(c, k), sh, off, ent, gain, O, st));
         return RT3D_OK;
     case RT3D_STEP_MERGE:
-        RT3D_HIP(c, launch_merge(p, sh, O, st));
+        for (int k = 0; k < nc; ++k) RT3D_HIP(c, launch_merge(dev_model(c, k, cls), dev_params(c, k), sh, O, st));
         return RT3D_OK;
     case RT3D_STEP_INTENSITY:
-        RT3D_HIP(c, launch_intensity_step(m, p, sh, off, ent, gain, O, false, st));
+        for (int k = 0; k < nc; ++k)
+            RT3D_HIP(c, launch_intensity_step(dev_model(c, k, cls), dev_params(c, k), sh, off, ent, gain, O, false,
+                                              st));
         return RT3D_OK;
     case RT3D_STEP_BKG:
-        RT3D_HIP(c, launch_bg_step(m, p, sh, off, ent, gain, O, nullptr, st));
+        for (int k = 0; k < nc; ++k)
+            RT3D_HIP(c, launch_bg_step(dev_model(c, k, cls), dev_params(c, k), sh, off, ent, gain, O, nullptr, st));
         return RT3D_OK;
     case RT3D_STEP_BFILTER: {
         Workspace w;
@@ -1196,7 +1277,7 @@ rt3d_status rt3d_debug_step(rt3d_ctx* c, int32_t step, const uint32_t* off, cons
         Workspace w;
         rt3d_status s = need_ws(c, sh.P, w);
         if (s != RT3D_OK) return s;
-        return iterate(c, sh, std::vector<Group>{Group{0, sh}}, off, ent, gain, O, w.B, w.btmp, &w.cnn, st);
+        return iterate(c, sh, std::vector<Group>{Group{0, sh}}, off, ent, gain, O, w.B, w.btmp, &w.cnn, cls, st);
     }
     default:
         return fail(c, RT3D_E_INVALID, "unknown step");
@@ -1212,6 +1293,7 @@ rt3d_status rt3d_debug_gradients(rt3d_ctx* c, const uint32_t* off, const uint32_
     const Shape sh = shape_of(s->frames, s->rows, s->cols);
     const int sr = c->p.sr;
     if (sr > 1) {
+        if (c->debug_cls) return fail(c, RT3D_E_UNSUPPORTED, "per-pixel IRFs with super-resolution");
         if (s->rows % sr || s->cols % sr)
             return fail(c, RT3D_E_INVALID, "point-grid rows and cols must be multiples of sr");
         const Shape lid = shape_of(s->frames, s->rows / sr, s->cols / sr);
@@ -1219,8 +1301,39 @@ rt3d_status rt3d_debug_gradients(rt3d_ctx* c, const uint32_t* off, const uint32_
                                         gr, gb, (hipStream_t)hip_stream));
         return RT3D_OK;
     }
-    RT3D_HIP(c, launch_gradients(dev_model(c), dev_params(c), sh, off, ent, gain, dev_state(s), gt, gr, gb,
-                                 (hipStream_t)hip_stream));
+    for (int k = 0; k < n_classes(c, c->debug_cls); ++k)
+        RT3D_HIP(c, launch_gradients(dev_model(c, k, c->debug_cls), dev_params(c, k), sh, off, ent, gain,
+                                     dev_state(s), gt, gr, gb, (hipStream_t)hip_stream));
+    return RT3D_OK;
+}
+
+rt3d_status rt3d_debug_irf_class(rt3d_ctx* c, const uint8_t* irf_class)
+{
+    if (!c) return RT3D_E_INVALID;
+    c->debug_cls = irf_class;
+    return RT3D_OK;
+}
+
+rt3d_status rt3d_add_irf(rt3d_ctx* c, const double* irf, uint32_t irf_len, int32_t irf_origin, int32_t* id)
+{
+    if (!c) return RT3D_E_INVALID;
+    if (c->irf.size() >= (size_t)RT3D_MAX_IRFS) return fail(c, RT3D_E_INVALID, "the context holds RT3D_MAX_IRFS IRFs");
+    if (c->p.sr > 1 || c->p.denoiser == RT3D_DENOISE_CNN)
+        return fail(c, RT3D_E_UNSUPPORTED, "per-pixel IRFs with super-resolution or the learned denoiser");
+    const rt3d_status ok = check_irf(irf, irf_len, irf_origin, c->T, &c->p);
+    if (ok != RT3D_OK) return fail(c, ok, "IRF rejected");
+    int prev = 0;
+    const bool switched =
+        hipGetDevice(&prev) == hipSuccess && prev != c->device && hipSetDevice(c->device) == hipSuccess;
+    IrfTables t;
+    const rt3d_status s = build_irf(irf, irf_len, irf_origin, c->T, &c->p, t);
+    if (switched) (void)hipSetDevice(prev);
+    if (s != RT3D_OK) {
+        free_irf(t);
+        return fail(c, s, s == RT3D_E_DEVICE ? "HIP failure uploading the IRF tables" : "IRF rejected");
+    }
+    c->irf.push_back(std::move(t));
+    if (id) *id = (int32_t)c->irf.size() - 1;
     return RT3D_OK;
 }
 
@@ -1284,7 +1397,7 @@ rt3d_status rt3d_cnn_forward(rt3d_ctx* c, const rt3d_state* st, float* y, void* 
     if (s != RT3D_OK) return s;
     const Shape sh = shape_of(st->frames, st->rows, st->cols);
     hipStream_t hs = (hipStream_t)hip_stream;
-    RT3D_HIP(c, launch_cnn_forward(sh, dev_state(st), (float)std::sqrt(c->sigma2), c->cnn, w.cnn, hs));
+    RT3D_HIP(c, launch_cnn_forward(sh, dev_state(st), (float)std::sqrt(c->irf[0].sigma2), c->cnn, w.cnn, hs));
     RT3D_HIP(c, launch_cnn_unpack(sh, w.cnn, y, hs));
     return RT3D_OK;
 }
@@ -1302,7 +1415,7 @@ rt3d_status rt3d_cnn_train_step(rt3d_ctx* c, const rt3d_state* st, const float* 
     if (s != RT3D_OK) return s;
     const Shape sh = shape_of(st->frames, st->rows, st->cols);
     CnnAdam a{opt->lr, opt->beta1, opt->beta2, opt->eps};
-    RT3D_HIP(c, launch_cnn_train_step(sh, dev_state(st), (float)std::sqrt(c->sigma2), truth, (int)n_surf, c->cnn,
+    RT3D_HIP(c, launch_cnn_train_step(sh, dev_state(st), (float)std::sqrt(c->irf[0].sigma2), truth, (int)n_surf, c->cnn,
                                       w.cnn, a, loss, (hipStream_t)hip_stream));
     return RT3D_OK;
 }

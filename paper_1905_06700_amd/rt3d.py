@@ -26,7 +26,7 @@ STEP_INIT, STEP_DEPTH, STEP_APSS, STEP_MERGE, STEP_INTENSITY, STEP_IFILTER, STEP
 EXPORTS = ["rt3d_params_default", "rt3d_create", "rt3d_destroy", "rt3d_last_error", "rt3d_sigma2",
            "rt3d_workspace_bytes", "rt3d_set_workspace", "rt3d_reconstruct", "rt3d_query",
            "rt3d_profile", "rt3d_profile_read", "rt3d_graph_create", "rt3d_graph_launch", "rt3d_graph_destroy",
-           "rt3d_autotune",
+           "rt3d_autotune", "rt3d_add_irf", "rt3d_debug_irf_class",
            "rt3d_debug_compact", "rt3d_debug_compact_events", "rt3d_debug_step", "rt3d_debug_gradients",
            "rt3d_cnn_set_weights", "rt3d_cnn_get_weights", "rt3d_cnn_last_gradient",
            "rt3d_cnn_forward", "rt3d_cnn_train_step"]
@@ -66,7 +66,7 @@ class Input(C.Structure):
                 ("off", C.c_void_p), ("ent", C.c_void_p), ("gain", C.c_void_p),
                 ("ev_pixel", C.c_void_p), ("ev_bin", C.c_void_p), ("ev_scratch", C.c_void_p),
                 ("n_events", C.c_uint64), ("frame_rows", C.c_void_p), ("frame_cols", C.c_void_p),
-                ("flags", C.c_uint32)]
+                ("flags", C.c_uint32), ("irf_class", C.c_void_p)]
 
 
 class Output(C.Structure):
@@ -136,6 +136,10 @@ def lib():
         L.rt3d_debug_step.restype = st
         L.rt3d_debug_gradients.argtypes = [vp, vp, vp, vp, C.POINTER(State), vp, vp, vp, vp]
         L.rt3d_debug_gradients.restype = st
+        L.rt3d_add_irf.argtypes = [vp, C.POINTER(C.c_double), C.c_uint32, C.c_int32, C.POINTER(C.c_int32)]
+        L.rt3d_add_irf.restype = st
+        L.rt3d_debug_irf_class.argtypes = [vp, vp]
+        L.rt3d_debug_irf_class.restype = st
         fp = C.POINTER(C.c_float)
         for name in ("rt3d_cnn_set_weights", "rt3d_cnn_get_weights", "rt3d_cnn_last_gradient"):
             getattr(L, name).argtypes = [vp, fp, C.c_size_t]
@@ -235,6 +239,7 @@ class Context:
         self.bins = int(bins)
         self._ws = None
         self._ws_shape = None
+        self._debug_cls = None
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -292,8 +297,22 @@ class Context:
                       torch.zeros(cap, 3, dtype=torch.float32, device=dev) if normals else None,
                       torch.zeros(P if n_bg is None else n_bg, dtype=torch.float32, device=dev))
 
+    def add_irf(self, irf, origin: int = -1) -> int:
+        """Add a per-pixel IRF class (rt3d_add_irf); returns its number."""
+        irf = [float(x) for x in irf]
+        arr = (C.c_double * len(irf))(*irf)
+        k = C.c_int32()
+        self._check(lib().rt3d_add_irf(self._h, arr, len(irf), int(origin), C.byref(k)))
+        return k.value
+
+    def debug_irf_class(self, cls):
+        """Per-pixel IRF classes (cuda uint8 [P] or None) of the step-by-step calls."""
+        assert cls is None or (cls.is_cuda and cls.dtype == torch.uint8 and cls.is_contiguous())
+        self._debug_cls = cls                         # alive while the library uses it
+        self._check(lib().rt3d_debug_irf_class(self._h, _ptr(cls)))
+
     def _io(self, out: Result, frames: int, rows: int, cols: int, hist=None, off=None, ent=None, gain=None,
-            events=None, frame_shapes=None, warm_start=False):
+            events=None, frame_shapes=None, warm_start=False, irf_class=None):
         inp = Input()
         inp.flags = FLAG_WARM_START if warm_start else 0
         inp.struct_size = C.sizeof(Input)
@@ -319,8 +338,12 @@ class Context:
             inp.kind = IN_PHOTON_CSR
             inp.off, inp.ent = off.data_ptr(), ent.data_ptr()
         inp.gain = gain.data_ptr() if gain is not None else None
-        # the library trusts these sizes: point-grid pixels for pt_off, lidar pixels for background
         npix = sum(int(r) * int(q) for r, q in frame_shapes) if frame_shapes is not None else frames * rows * cols
+        if irf_class is not None:
+            assert irf_class.is_cuda and irf_class.dtype == torch.uint8 and irf_class.is_contiguous()
+            assert irf_class.numel() >= npix, "irf_class smaller than the batch"
+            inp.irf_class = irf_class.data_ptr()
+        # the library trusts these sizes: point-grid pixels for pt_off, lidar pixels for background
         sr = self.params.sr
         assert out.pt_off.numel() >= npix * sr * sr + 1 and out.background.numel() >= npix, \
             "output buffers smaller than the batch"
@@ -333,13 +356,15 @@ class Context:
         return inp, o
 
     def reconstruct_into(self, out: Result, frames: int, rows: int, cols: int, hist=None, off=None,
-                         ent=None, gain=None, events=None, frame_shapes=None, warm_start=False):
+                         ent=None, gain=None, events=None, frame_shapes=None, warm_start=False, irf_class=None):
         """Enqueue one reconstruction on the current torch stream (no sync).
         Input: hist, or (off, ent), or events = (pixel int32, bin int16, scratch int32).
         frame_shapes: [(rows, cols)] per frame for frames of different sizes, whose
         pixels follow one another (rows and cols are then ignored).
-        warm_start: start from the previous call's final state (same frames)."""
-        inp, o = self._io(out, frames, rows, cols, hist, off, ent, gain, events, frame_shapes, warm_start)
+        warm_start: start from the previous call's final state (same frames).
+        irf_class: cuda uint8 [P], each pixel's IRF class (see add_irf)."""
+        inp, o = self._io(out, frames, rows, cols, hist, off, ent, gain, events, frame_shapes, warm_start,
+                          irf_class)
         self._check(lib().rt3d_reconstruct(self._h, C.byref(inp), C.byref(o), _stream()))
         return out
 
@@ -360,7 +385,7 @@ class Context:
         self._check(lib().rt3d_graph_create(self._h, C.byref(inp), C.byref(o), C.byref(h)))
         return Graph(self, h, (out, hist, off, ent, gain, events))
 
-    def reconstruct(self, hist, gain=None, max_entries=None) -> Result:
+    def reconstruct(self, hist, gain=None, max_entries=None, irf_class=None) -> Result:
         """hist: cuda uint16 [frames, rows, cols, bins] (or [rows, cols, bins])."""
         if hist.dim() == 3:
             hist = hist.unsqueeze(0)
@@ -371,7 +396,7 @@ class Context:
         self.workspace(F, R, Cc, me)
         sr = self.params.sr
         out = self.make_output(P * sr * sr, n_bg=P)
-        self.reconstruct_into(out, F, R, Cc, hist=hist, gain=gain)
+        self.reconstruct_into(out, F, R, Cc, hist=hist, gain=gain, irf_class=irf_class)
         return out
 
     # -- step-by-step entry points -----------------------------------------

@@ -281,6 +281,29 @@ def sr_scene(scene: int = 0, rows: int = 32, cols: int = 32, s: int = 3, T: int 
                       r_min=0.2 * signal / (s * s), r_init=0, k_init=3))
 
 
+def irf_class_scene(scene: int = 0, rows: int = 40, cols: int = 36, T: int = 777, signal: float = 8.0,
+                    sbr: float = 0.5, config: int = 6):
+    """Per-pixel IRFs (the observation model's h_ij): three detector classes
+    -- Gaussian sigma 1.5 bins, Gaussian sigma 3 bins, and the ex-Gaussian of
+    config 2 -- assigned to pixels in seeded random blocks of 4 x 4 (a
+    detector array whose tiles differ), over the head-shaped geometry (bumpy
+    surface and a 30% occluder 200 bins nearer, scaled to T).  Each pixel's
+    photons follow its own IRF.  Returns (scene with irf = class 0's IRF,
+    [IRF of every class], uint8 class map [rows, cols])."""
+    rng = np.random.default_rng(seed_of(config, scene))
+    irfs = [gaussian_irf(1.5, 9), gaussian_irf(3.0, 12), exgauss_irf(3.0, 10.0, -18, 118)]
+    bi, bj = (rows + 3) // 4, (cols + 3) // 4
+    cls = np.kron(rng.integers(0, len(irfs), (bi, bj)), np.ones((4, 4), np.int64))[:rows, :cols].astype(np.uint8)
+    base = head_scene(5000 + scene, rows=rows, cols=cols, T=T, signal=signal, sbr=sbr)
+    Z = np.zeros_like(base.Z)
+    for k, irf in enumerate(irfs):
+        Zk = render(rng, irf, T, base.depth, base.intensity, base.background)
+        Z[cls == k] = Zk[cls == k]
+    sc = Scene(Z, irfs[0], T, base.depth, base.intensity, base.background,
+               dict(base.meta, config=config, r_init=0))
+    return sc, irfs, cls
+
+
 def random_gain(rng_seed: int, rows: int, cols: int, dead_frac: float = 0.02) -> np.ndarray:
     """Per-pixel detector gain in [0.5, 1.5] with a fraction of dead (0) pixels."""
     rng = np.random.default_rng(rng_seed)

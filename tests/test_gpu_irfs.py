@@ -1,0 +1,192 @@
+"""Per-pixel IRFs (Results, "Observation model": h_ij is known per pixel),
+through the C ABI, against the oracle with the same class map: three IRF
+classes (two Gaussians and the ex-Gaussian, different lengths and origins) in
+4 x 4 pixel blocks.  Initialisation, raw gradients, single steps and whole
+reconstructions, with the bars of the single-IRF tests; a batch of frames of
+two sizes against each frame alone; the refusals."""
+import numpy as np
+import pytest
+
+from gpu_util import device_to_oracle, oracle_to_device, params_for, to_dev_hist, to_dev_u32, u32
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import oracle  # noqa: E402
+from paper_1905_06700_amd import rt3d, synth  # noqa: E402
+
+_CASES = {}
+
+
+def case(name="irfs"):
+    if name not in _CASES:
+        if name == "irfs":
+            _CASES[name] = synth.irf_class_scene(0)
+        elif name == "irfs_small":
+            _CASES[name] = synth.irf_class_scene(1, rows=19, cols=26)
+    return _CASES[name]
+
+
+def pair_irfs(sc, irfs, cls, **kw):
+    p = params_for(sc, **kw)
+    models = [oracle.Model(i.probs, sc.T) for i in irfs]
+    O = oracle.Oracle(models[0], oracle.Params(**p), irf_models=models[1:], irf_class=cls.reshape(-1))
+    O._keep = models
+    ctx = rt3d.Context(irfs[0].probs, sc.T, **p)
+    for i in irfs[1:]:
+        ctx.add_irf(i.probs)
+    return O, ctx
+
+
+def dev_cls(cls):
+    return torch.from_numpy(np.ascontiguousarray(cls.reshape(-1))).cuda()
+
+
+def test_irf_classes_init_matches_oracle():
+    sc, irfs, cls = case()
+    O, ctx = pair_irfs(sc, irfs, cls)
+    off, ent = oracle.compact(sc.Z[None])
+    so = O.init(off, ent, oracle.State(1, sc.rows, sc.cols, 4))
+    c = dev_cls(cls)
+    ctx.debug_irf_class(c)
+    print(f"[gpu-irfs] init {sc.rows}x{sc.cols}x{sc.T}, classes {np.bincount(cls.ravel())}", flush=True)
+    d = ctx.step(rt3d.STEP_INIT, None, to_dev_u32(off), to_dev_u32(ent), shape=(1, sc.rows, sc.cols))
+    sg = device_to_oracle(d, 4)
+    np.testing.assert_array_equal(sg.cnt, so.cnt)
+    np.testing.assert_array_equal(sg.t, so.t)
+    np.testing.assert_allclose(sg.r, so.r, rtol=2e-6, atol=1e-6)
+    np.testing.assert_allclose(sg.b, so.b, rtol=2e-6, atol=1e-12)
+    np.testing.assert_allclose(sg.n, so.n, atol=2e-6)
+
+
+def _state_after(O, sc, off, ent, iters):
+    s = O.init(off, ent, oracle.State(1, sc.rows, sc.cols, 4))
+    for _ in range(iters):
+        O.iterate(off, ent, s)
+    return s
+
+
+@pytest.mark.parametrize("iters", [0, 3])
+def test_irf_classes_gradients_match_oracle(iters):
+    sc, irfs, cls = case()
+    O, ctx = pair_irfs(sc, irfs, cls)
+    off, ent = oracle.compact(sc.Z[None])
+    s = _state_after(O, sc, off, ent, iters)
+    (gt, gr, gb), (at, ar, ab) = O.grad(off, ent, s)
+    ctx.debug_irf_class(dev_cls(cls))
+    print(f"[gpu-irfs] gradients after {iters} iterations", flush=True)
+    dgt, dgr, dgb = ctx.gradients(oracle_to_device(s), to_dev_u32(off), to_dev_u32(ent))
+    dgt = dgt.cpu().numpy()[:4].T.astype(np.float64)
+    dgr = dgr.cpu().numpy()[:4].T.astype(np.float64)
+    dgb = dgb.cpu().numpy().astype(np.float64)
+    live = np.arange(4)[None, :] < s.cnt[:, None]
+    for g_gpu, g_or, a in ((dgt, gt, at), (dgr, gr, ar)):
+        err = np.abs(g_gpu - g_or)[live]
+        assert np.all(err <= 1e-4 * a[live] + 1e-30), (err.max(), (err / a[live]).max())
+    assert np.all(np.abs(dgb - gb) <= 1e-4 * ab + 1e-30)
+
+
+def test_irf_classes_single_steps_match_oracle():
+    sc, irfs, cls = case()
+    O, ctx = pair_irfs(sc, irfs, cls)
+    off_o, ent_o = oracle.compact(sc.Z[None])
+    off, ent = to_dev_u32(off_o), to_dev_u32(ent_o)
+    s0 = _state_after(O, sc, off_o, ent_o, 2)
+    din = oracle_to_device(s0)
+    live = np.arange(4)[None, :] < s0.cnt[:, None]
+    ctx.debug_irf_class(dev_cls(cls))
+    print("[gpu-irfs] single steps", flush=True)
+
+    so = O.depth_step(off_o, ent_o, s0.copy())
+    sg = device_to_oracle(ctx.step(rt3d.STEP_DEPTH, din, off, ent), 4)
+    assert np.abs(sg.t - so.t)[live].max() <= 2e-4
+
+    so = O.merge(s0.copy())
+    sg = device_to_oracle(ctx.step(rt3d.STEP_MERGE, din), 4)
+    np.testing.assert_array_equal(sg.cnt, so.cnt)
+
+    so = O.intensity_step(off_o, ent_o, s0.copy())
+    sg = device_to_oracle(ctx.step(rt3d.STEP_INTENSITY, din, off, ent), 4)
+    np.testing.assert_allclose(sg.r[live], so.r[live], rtol=1e-5, atol=1e-6)
+
+    so = O.bg_step(off_o, ent_o, s0.copy())
+    sg = device_to_oracle(ctx.step(rt3d.STEP_BKG, din, off, ent), 4)
+    np.testing.assert_allclose(sg.b, so.b, rtol=1e-5, atol=1e-12)
+
+
+@pytest.mark.parametrize("name", ["irfs", "irfs_small"])
+def test_irf_classes_reconstruction_matches_oracle(name):
+    sc, irfs, cls = case(name)
+    O, ctx = pair_irfs(sc, irfs, cls)
+    off, ent = oracle.compact(sc.Z[None])
+    so = O.reconstruct(off, ent, oracle.State(1, sc.rows, sc.cols, 4))
+    print(f"[gpu-irfs] reconstruct {name}", flush=True)
+    res = ctx.reconstruct(to_dev_hist(sc.Z)[None], irf_class=dev_cls(cls))
+    assert ctx.query().device_error == 0
+    pt = u32(res.pt_off).astype(np.int64)
+    cnt = np.diff(pt)
+    same = cnt == so.cnt
+    bad = (~same).reshape(sc.rows, sc.cols)
+    nb = np.zeros_like(bad)
+    for di in range(-2, 3):
+        for dj in range(-2, 3):
+            nb |= np.roll(np.roll(bad, di, 0), dj, 1)
+    depth = res.depth.cpu().numpy()
+    errs = [np.abs(depth[pt[p]:pt[p] + so.cnt[p]] - so.t[p, :so.cnt[p]]).max()
+            for p in np.nonzero(~nb.reshape(-1) & (so.cnt > 0))[0]]
+    print(f"[gpu-irfs] {name}: count agreement {same.mean():.5f}, max depth err {max(errs):.2e} bins", flush=True)
+    assert same.mean() >= 0.999
+    assert max(errs) <= 1e-3
+    np.testing.assert_allclose(res.background.cpu().numpy(), so.b, rtol=1e-3, atol=1e-9)
+    # the same data with every pixel taking class 0 differs (the classes are used)
+    one = ctx.reconstruct(to_dev_hist(sc.Z)[None])
+    assert not torch.equal(one.depth[:int(pt[-1])], res.depth[:int(pt[-1])])
+
+
+def test_irf_classes_uneven_batch_equals_frames_alone():
+    (sa, irfs, ca), (sb, _, cb) = case("irfs"), case("irfs_small")
+    ctx = rt3d.Context(irfs[0].probs, sa.T, **params_for(sa), fused_loop=0)
+    for i in irfs[1:]:
+        ctx.add_irf(i.probs)
+    alone = []
+    for sc, cl in ((sa, ca), (sb, cb)):
+        r = ctx.reconstruct(to_dev_hist(sc.Z)[None], irf_class=dev_cls(cl))
+        alone.append((u32(r.pt_off).astype(np.int64), r.depth.cpu(), r.background.cpu()))
+    shapes = [(sa.rows, sa.cols), (sb.rows, sb.cols)]
+    Z = torch.cat([to_dev_hist(sa.Z).reshape(-1, sa.T), to_dev_hist(sb.Z).reshape(-1, sb.T)]).contiguous()
+    cl = torch.cat([dev_cls(ca), dev_cls(cb)]).contiguous()
+    P = int(Z.shape[0])
+    ctx.workspace(1, 1, P, P * 64)
+    out = ctx.make_output(P)
+    print("[gpu-irfs] uneven batch", flush=True)
+    ctx.reconstruct_into(out, 2, 1, 1, hist=Z, frame_shapes=shapes, irf_class=cl)
+    assert ctx.query().device_error == 0
+    pt = u32(out.pt_off).astype(np.int64)
+    n0 = sa.rows * sa.cols
+    for f, (b, n) in enumerate(((0, n0), (n0, sb.rows * sb.cols))):
+        po, dep, bg = alone[f]
+        np.testing.assert_array_equal(pt[b:b + n + 1] - pt[b], po, err_msg=f"frame {f}")
+        assert torch.equal(out.depth[pt[b]:pt[b + n]].cpu(), dep[:int(po[-1])]), f"frame {f} depth"
+        assert torch.equal(out.background[b:b + n].cpu(), bg), f"frame {f} background"
+
+
+def test_irf_classes_refusals():
+    sc, irfs, cls = case()
+    ctx = rt3d.Context(irfs[0].probs, sc.T)
+    with pytest.raises(rt3d.Rt3dError) as e:
+        ctx.add_irf([0.0, 0.0])
+    assert e.value.status == rt3d.E_INVALID
+    ids = [ctx.add_irf(irfs[1].probs) for _ in range(rt3d_max_irfs() - 1)]
+    assert ids == list(range(1, rt3d_max_irfs()))
+    with pytest.raises(rt3d.Rt3dError) as e:
+        ctx.add_irf(irfs[1].probs)
+    assert e.value.status == rt3d.E_INVALID
+    for kw in (dict(sr=2), dict(denoiser=rt3d.DENOISE_CNN)):
+        c2 = rt3d.Context(irfs[0].probs, sc.T, **kw)
+        with pytest.raises(rt3d.Rt3dError) as e:
+            c2.add_irf(irfs[1].probs)
+        assert e.value.status == rt3d.E_UNSUPPORTED
+
+
+def rt3d_max_irfs():
+    return 16
