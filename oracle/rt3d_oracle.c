@@ -360,10 +360,41 @@ void or_grad(const or_model* m, int64_t npix, const uint32_t* off, const uint32_
 
 /* Squared world distance between slot ka of pixel (fa, ia, ja) and slot kb of
  * pixel (fb, ib, jb): X = j p_xy, Y = i p_xy, Z = t dz (orthographic). */
-static double dist2(const or_params* p, int ia, int ja, double ta, int ib, int jb, double tb)
+/* The map f from (pixel, depth) to world coordinates (Observation model: the
+ * camera parameters, such as the focal length, enter f).  persp = 0:
+ * orthographic, X = j p_xy, Y = i p_xy, Z = t dz.  persp > 0 (reading): a
+ * pinhole camera at the origin looking along +Z; pixel (i, j) of a rows x cols
+ * frame sees along the unit ray v of (persp (j - cx), persp (i - cy), 1),
+ * cx = (cols - 1)/2, cy = (rows - 1)/2 (persp: the tangent of one pixel's
+ * angle), and depth t is the range t dz along that ray (time of flight), so
+ * the point is t dz v. */
+static void ray(const or_params* p, int rows, int cols, int i, int j, double v[3])
 {
-    double dx = (jb - ja) * p->p_xy, dy = (ib - ia) * p->p_xy, dzz = (tb - ta) * p->dz;
-    return dx * dx + dy * dy + dzz * dzz;
+    if (!(p->persp > 0.0)) { v[0] = 0.0; v[1] = 0.0; v[2] = 1.0; return; }
+    double u = p->persp * (j - 0.5 * (cols - 1)), w = p->persp * (i - 0.5 * (rows - 1));
+    double nrm = sqrt(u * u + w * w + 1.0);
+    v[0] = u / nrm; v[1] = w / nrm; v[2] = 1.0 / nrm;
+}
+
+/* World position of point (ib, jb, tb) relative to point (ia, ja, ta). */
+static void rel(const or_params* p, int rows, int cols, int ia, int ja, double ta, int ib, int jb, double tb,
+                double y[3])
+{
+    if (!(p->persp > 0.0)) {
+        y[0] = (jb - ja) * p->p_xy; y[1] = (ib - ia) * p->p_xy; y[2] = (tb - ta) * p->dz;
+        return;
+    }
+    double va[3], vb[3];
+    ray(p, rows, cols, ia, ja, va);
+    ray(p, rows, cols, ib, jb, vb);
+    for (int c = 0; c < 3; ++c) y[c] = (tb * vb[c] - ta * va[c]) * p->dz;
+}
+
+static double dist2(const or_params* p, int rows, int cols, int ia, int ja, double ta, int ib, int jb, double tb)
+{
+    double y[3];
+    rel(p, rows, cols, ia, ja, ta, ib, jb, tb, y);
+    return y[0] * y[0] + y[1] * y[1] + y[2] * y[2];
 }
 
 static int apss_radius(const or_params* p) { return (int)ceil(p->h_apss / p->p_xy); }
@@ -388,7 +419,7 @@ static int neighbours(const or_params* p, int F, int rows, int cols, const doubl
             if (j2 < 0 || j2 >= cols) continue;
             int64_t pp = (fr * rows + i2) * cols + j2;
             for (int k = 0; k < cnt[pp]; ++k) {
-                if (dist2(p, i, j, t[q], i2, j2, t[pp * K + k]) < h2) {
+                if (dist2(p, rows, cols, i, j, t[q], i2, j2, t[pp * K + k]) < h2) {
                     if (n < cap) out[n] = pp * K + k;
                     ++n;
                 }
@@ -588,7 +619,9 @@ void or_init_normals(const or_params* p, int F, int rows, int cols,
             for (int a = 0; a < nn && a < cap; ++a) {
                 int64_t pm = nb[a] / K;
                 int i2 = (int)((pm / cols) % rows), j2 = (int)(pm % cols);
-                double x = (j2 - j) * p->p_xy, y = (i2 - i) * p->p_xy, z = (t[nb[a]] - t[q]) * p->dz;
+                double yv[3];
+                rel(p, rows, cols, i, j, t[q], i2, j2, t[nb[a]], yv);
+                double x = yv[0], y = yv[1], z = yv[2];
                 double w = apss_weight(x * x + y * y + z * z, h2);
                 double basis[3] = {1.0, x, y};
                 for (int r0 = 0; r0 < 3; ++r0) {
@@ -612,6 +645,11 @@ void or_init_normals(const or_params* p, int F, int rows, int cols,
             double c1 = d1 / det, c2 = d2 / det;
             double nrm = sqrt(c1 * c1 + c2 * c2 + 1.0);
             nq[0] = c1 / nrm; nq[1] = c2 / nrm; nq[2] = -1.0 / nrm;
+            /* facing the sensor: against the pixel's ray */
+            double vr[3];
+            ray(p, rows, cols, i, j, vr);
+            if (nq[0] * vr[0] + nq[1] * vr[1] + nq[2] * vr[2] > 0.0)
+                for (int c = 0; c < 3; ++c) nq[c] = -nq[c];
         }
     }
     free(nb);
@@ -704,7 +742,8 @@ void or_apss(const or_params* p, int F, int rows, int cols, int T,
             for (int a = 0; a < nn && a < cap; ++a) {
                 int64_t pm = nb[a] / K;
                 int i2 = (int)((pm / cols) % rows), j2 = (int)(pm % cols);
-                double y[3] = {(j2 - j) * p->p_xy, (i2 - i) * p->p_xy, (t0[nb[a]] - t0[q]) * p->dz};
+                double y[3];
+                rel(p, rows, cols, i, j, t0[q], i2, j2, t0[nb[a]], y);
                 const double* nm = n0 + nb[a] * 3;
                 double yy = y[0] * y[0] + y[1] * y[1] + y[2] * y[2];
                 double w = apss_weight(yy, h2);
@@ -721,7 +760,10 @@ void or_apss(const or_params* p, int F, int rows, int cols, int T,
             double ul[3];
             for (int c = 0; c < 3; ++c) ul[c] = (N[c] - 2.0 * u4 * P[c]) / W;
             double u0 = -(ul[0] * P[0] + ul[1] * P[1] + ul[2] * P[2] + u4 * PP) / W;
-            double bz = ul[2];
+            /* the query moves along its own line of sight v: y = s v */
+            double v[3];
+            ray(p, rows, cols, i, j, v);
+            double bz = ul[0] * v[0] + ul[1] * v[1] + ul[2] * v[2];
             double nul = sqrt(ul[0] * ul[0] + ul[1] * ul[1] + ul[2] * ul[2]);
             if (!(fabs(bz) > 1e-6 * nul)) continue;
             double disc = bz * bz - 4.0 * u4 * u0;
@@ -734,10 +776,10 @@ void or_apss(const or_params* p, int F, int rows, int cols, int T,
             if (tn < 0.0) tn = 0.0;
             if (tn > T - 1) tn = T - 1;
             t[q] = tn;
-            double gr[3] = {ul[0], ul[1], ul[2] + 2.0 * u4 * s};
+            double gr[3] = {ul[0] + 2.0 * u4 * s * v[0], ul[1] + 2.0 * u4 * s * v[1], ul[2] + 2.0 * u4 * s * v[2]};
             double gn = sqrt(gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2]);
             if (gn > 0.0) {
-                double sg = gr[2] > 0.0 ? -1.0 : 1.0;
+                double sg = gr[0] * v[0] + gr[1] * v[1] + gr[2] * v[2] > 0.0 ? -1.0 : 1.0;
                 for (int c = 0; c < 3; ++c) n[q * 3 + c] = sg * gr[c] / gn;
             }
         }
@@ -868,7 +910,7 @@ void or_intensity_filter(const or_params* p, int F, int rows, int cols,
                     int best = -1;
                     double bd = 0.0;
                     for (int k2 = 0; k2 < cnt[pp]; ++k2) {
-                        double d2 = dist2(p, i, j, t[q], i2, j2, t[pp * K + k2]);
+                        double d2 = dist2(p, rows, cols, i, j, t[q], i2, j2, t[pp * K + k2]);
                         if (best < 0 || d2 < bd) { best = k2; bd = d2; }
                     }
                     if (best >= 0 && bd < hi2) { sum += r[pp * K + best]; ++deg; }

@@ -13,7 +13,8 @@
  *   - bins t = 0..T-1; pixel p = (f*rows + i)*cols + j (frame, row, column);
  *   - depth is in bins, as a real number; it is the position of the IRF
  *     origin (sample index `origin` of the given IRF);
- *   - world coordinates are orthographic: X = j*p_xy, Y = i*p_xy, Z = t*dz;
+ *   - world coordinates are orthographic, X = j*p_xy, Y = i*p_xy, Z = t*dz,
+ *     or (persp > 0) those of a pinhole camera: t*dz along the pixel's ray;
  *   - per-pixel point state is pixel-major with stride k_max:
  *       t[p*k_max + k], r[p*k_max + k], n[(p*k_max + k)*3 + c],
  *     cnt[p] live points in slots 0..cnt-1, ascending depth;
@@ -54,6 +55,8 @@ typedef struct or_params {
     int    w_nms;       /* non-maximum suppression half width; <= 0: auto */
     int    m_min;       /* minimum APSS neighbours */
     int    use_apss;    /* 1 = APSS depth denoiser, 0 = none */
+    double persp;       /* 0: orthographic map f; > 0: pinhole camera, tangent of one pixel's angle,
+                           depth = range along the pixel's ray (see rel() in the source) */
 } or_params;
 
 typedef struct or_model or_model;
