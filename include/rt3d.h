@@ -104,6 +104,19 @@ typedef struct rt3d_params {
                           * points with 1/s^2 of the intensity.  Frames of one size only
                           * (E_UNSUPPORTED with frame_rows / frame_cols), no learned denoiser
                           * (E_UNSUPPORTED at create), per-step kernels only (fused_loop ignored). */
+    double   persp;      /* camera model of the map f (Results, "Observation model": camera parameters
+                          * such as the focal length).  0 (default): orthographic, X = j p_xy,
+                          * Y = i p_xy, Z = t dz.  > 0: a pinhole camera at the origin looking along
+                          * +Z; pixel (i, j) of a rows x cols frame sees along the unit ray of
+                          * (persp (j - cx), persp (i - cy), 1), cx = (cols - 1)/2, cy = (rows - 1)/2
+                          * (persp: the tangent of one pixel's angle, pixel pitch / focal length),
+                          * and depth t is the range t dz along that ray.  APSS, the intensity graph
+                          * and the initial normals then use these positions, APSS moves a point
+                          * along its own ray and normals face the sensor.  p_xy still sets the
+                          * neighbour window, R = ceil(h_apss / p_xy): set it to the smallest
+                          * lateral pixel footprint (range x persp) of the scene.  E_UNSUPPORTED
+                          * when that window's tile does not fit the APSS kernel's LDS (R > 5);
+                          * per-step kernels only (fused_loop ignored). */
 } rt3d_params;
 
 /* Input kinds. */

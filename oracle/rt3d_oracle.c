@@ -645,10 +645,16 @@ void or_init_normals(const or_params* p, int F, int rows, int cols,
             double c1 = d1 / det, c2 = d2 / det;
             double nrm = sqrt(c1 * c1 + c2 * c2 + 1.0);
             nq[0] = c1 / nrm; nq[1] = c2 / nrm; nq[2] = -1.0 / nrm;
-            /* facing the sensor: against the pixel's ray */
+            /* facing the sensor: against the pixel's ray.  Reading for the
+             * pinhole camera: a plane containing the line of sight (within
+             * 1e-6, e.g. two points of one pixel among three neighbours) has
+             * no side facing the sensor; its point takes n = -v. */
             double vr[3];
             ray(p, rows, cols, i, j, vr);
-            if (nq[0] * vr[0] + nq[1] * vr[1] + nq[2] * vr[2] > 0.0)
+            double nv = nq[0] * vr[0] + nq[1] * vr[1] + nq[2] * vr[2];
+            if (p->persp > 0.0 && fabs(nv) <= 1e-6)
+                for (int c = 0; c < 3; ++c) nq[c] = -vr[c];
+            else if (nv > 0.0)
                 for (int c = 0; c < 3; ++c) nq[c] = -nq[c];
         }
     }
@@ -778,8 +784,13 @@ void or_apss(const or_params* p, int F, int rows, int cols, int T,
             t[q] = tn;
             double gr[3] = {ul[0] + 2.0 * u4 * s * v[0], ul[1] + 2.0 * u4 * s * v[1], ul[2] + 2.0 * u4 * s * v[2]};
             double gn = sqrt(gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2]);
-            if (gn > 0.0) {
-                double sg = gr[0] * v[0] + gr[1] * v[1] + gr[2] * v[2] > 0.0 ? -1.0 : 1.0;
+            double gv = gr[0] * v[0] + gr[1] * v[1] + gr[2] * v[2];
+            if (p->persp > 0.0 && fabs(gv) <= 1e-6 * gn) {
+                /* pinhole camera, gradient perpendicular to the line of sight
+                 * (the vertex of a missed sphere): the normal faces the sensor */
+                for (int c = 0; c < 3; ++c) n[q * 3 + c] = -v[c];
+            } else if (gn > 0.0) {
+                double sg = gv > 0.0 ? -1.0 : 1.0;
                 for (int c = 0; c < 3; ++c) n[q * 3 + c] = sg * gr[c] / gn;
             }
         }

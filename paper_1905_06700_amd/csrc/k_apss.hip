@@ -36,6 +36,12 @@ inline size_t apss_tile_bytes(int R)
     return SX * SY * (KM * sizeof(double) + 3 * KM * sizeof(float) + sizeof(int));
 }
 
+size_t apss_lds_bytes(int R) { return apss_tile_bytes(R); }
+
+// PERSP: positions of the pinhole camera (t dz along each pixel's ray,
+// differences formed in FP64), no lateral pre-test, projection along the
+// query's ray; else the orthographic map.
+template <bool PERSP>
 __global__ __launch_bounds__(ATX * ATY) void k_apss_tile(DevModel m, DevParams p, Tiles tg, DevState in,
                                                        DevState out, int only_above)
 {
@@ -88,22 +94,39 @@ __global__ __launch_bounds__(ATX * ATY) void k_apss_tile(DevModel m, DevParams p
     const float pxy = (float)p.p_xy;
     const double dz = p.dz;
     const double tmax = (double)(m.T - 1);
+    double vq[3] = {0.0, 0.0, 1.0};
+    float rq[3] = {0.f, 0.f, 1.f};
+    if (PERSP) {
+        ray_dir(p.persp, sh.rows, sh.cols, i, j, vq);
+        for (int a = 0; a < 3; ++a) rq[a] = (float)vq[a];
+    }
     for (int k = 0; k < c; ++k) {
         const double tq = tl[k * NS + xc];
         float W = 0.f, Px = 0.f, Py = 0.f, Pz = 0.f, Nx = 0.f, Ny = 0.f, Nz = 0.f, PN = 0.f, PP = 0.f, nn = 0.f;
         if (fit) {
             for (int di = -R; di <= R; ++di) {
-                const float yy = (float)di * pxy;
+                const float yy0 = (float)di * pxy;
                 for (int dj = -R; dj <= R; ++dj) {
-                    // pixels whose lateral offset alone reaches h hold no neighbour
-                    const float yx = (float)dj * pxy;
-                    const float dl = fmaf(yx, yx, yy * yy);
-                    if (!(dl < h2)) continue;
+                    // orthographic: pixels whose lateral offset alone reaches h hold no neighbour
+                    const float yx0 = (float)dj * pxy;
+                    const float dl = fmaf(yx0, yx0, yy0 * yy0);
+                    if (!PERSP && !(dl < h2)) continue;
                     const int x = xc + di * SX + dj;
                     const int cc = cl[x];
+                    double v2[3] = {0.0, 0.0, 1.0};
+                    if (PERSP && cc > 0) ray_dir(p.persp, sh.rows, sh.cols, i + di, j + dj, v2);
                     for (int k2 = 0; k2 < cc; ++k2) {
-                        const float yz = (float)((tl[k2 * NS + x] - tq) * dz);
-                        const float d2 = fmaf(yz, yz, dl);
+                        const double t2 = tl[k2 * NS + x];
+                        float yx = yx0, yy = yy0, yz, d2;
+                        if (PERSP) {
+                            yx = (float)((t2 * v2[0] - tq * vq[0]) * dz);
+                            yy = (float)((t2 * v2[1] - tq * vq[1]) * dz);
+                            yz = (float)((t2 * v2[2] - tq * vq[2]) * dz);
+                            d2 = fmaf(yx, yx, fmaf(yy, yy, yz * yz));
+                        } else {
+                            yz = (float)((t2 - tq) * dz);
+                            d2 = fmaf(yz, yz, dl);
+                        }
                         if (!(d2 < h2)) continue;
                         float a = 1.f - d2 * inv_h2;
                         a = a * a;
@@ -127,7 +150,8 @@ __global__ __launch_bounds__(ATX * ATY) void k_apss_tile(DevModel m, DevParams p
         }
         double tn = tq;
         float on[3] = {nl[(0 * KM + k) * NS + xc], nl[(1 * KM + k) * NS + xc], nl[(2 * KM + k) * NS + xc]};
-        apss_project(fit && nn >= (float)p.m_min, W, Px, Py, Pz, Nx, Ny, Nz, PN, PP, h, h2, dz, tmax, tn, on);
+        apss_project(fit && nn >= (float)p.m_min, W, Px, Py, Pz, Nx, Ny, Nz, PN, PP, h, h2, dz, tmax, tn, on,
+                     PERSP ? rq : nullptr);
         out.t[k * S + pix] = tn;
 #pragma unroll
         for (int a = 0; a < 3; ++a) out.n[(a * KM + k) * S + pix] = on[a];
@@ -255,9 +279,15 @@ hipError_t launch_apss_tiles(const DevModel& m, const DevParams& p, const Tiles&
 {
     if (tg.n == 0 || tg.tile0[tg.n] == 0) return hipSuccess;
     const size_t lds = apss_tile_bytes(p.apss_R);
+    if (p.persp > 0.0) {   // the host admits the perspective camera only where the tile fits
+        if (lds > 65536) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_apss_tile<true>, dim3((unsigned)tg.tile0[tg.n]), dim3(ATX * ATY), lds, st, m, p, tg, in,
+                           out, only_above);
+        return hipGetLastError();
+    }
     if (lds <= 65536) {
-        hipLaunchKernelGGL(k_apss_tile, dim3((unsigned)tg.tile0[tg.n]), dim3(ATX * ATY), lds, st, m, p, tg, in, out,
-                           only_above);
+        hipLaunchKernelGGL(k_apss_tile<false>, dim3((unsigned)tg.tile0[tg.n]), dim3(ATX * ATY), lds, st, m, p, tg, in,
+                           out, only_above);
         return hipGetLastError();
     }
     for (int g = 0; g < tg.n; ++g) {

@@ -24,6 +24,8 @@ namespace rt3d {
 constexpr int IFT = TILE;
 constexpr int IFS = IFT + 2;
 
+// PERSP: world distances of the pinhole camera (t dz along each pixel's ray).
+template <bool PERSP>
 __global__ __launch_bounds__(IFT * IFT) void k_ifilter_tile(DevParams p, Tiles tg, DevState in, DevState out)
 {
     __shared__ double tl[KM][IFS * IFS];
@@ -71,6 +73,8 @@ __global__ __launch_bounds__(IFT * IFT) void k_ifilter_tile(DevParams p, Tiles t
         for (int dj = -1; dj <= 1; ++dj)
             if (!(di == 0 && dj == 0) && i + di >= 0 && i + di < sh.rows && j + dj >= 0 && j + dj < sh.cols) ++nside;
     int nk = 0;
+    double vq[3] = {0.0, 0.0, 1.0};
+    if (PERSP) ray_dir(p.persp, sh.rows, sh.cols, i, j, vq);
     for (int k = 0; k < c; ++k) {
         const double tq = tl[k][xc];
         float sum = rl[k][xc];
@@ -81,11 +85,22 @@ __global__ __launch_bounds__(IFT * IFT) void k_ifilter_tile(DevParams p, Tiles t
                 const float dx = (float)dj * pxy;
                 const int x = xc + di * IFS + dj;
                 const int cc = cl[x];                   // 0 outside the image
+                double v2[3] = {0.0, 0.0, 1.0};
+                if (PERSP && cc > 0) ray_dir(p.persp, sh.rows, sh.cols, i + di, j + dj, v2);
                 int best = -1;
                 float bd = 0.f;
                 for (int k2 = 0; k2 < cc; ++k2) {
-                    const float ddz = (float)((tl[k2][x] - tq) * dz);
-                    const float d2 = dx * dx + dy * dy + ddz * ddz;
+                    float d2;
+                    if (PERSP) {
+                        const double t2 = tl[k2][x];
+                        const float ex = (float)((t2 * v2[0] - tq * vq[0]) * dz);
+                        const float ey = (float)((t2 * v2[1] - tq * vq[1]) * dz);
+                        const float ez = (float)((t2 * v2[2] - tq * vq[2]) * dz);
+                        d2 = ex * ex + ey * ey + ez * ez;
+                    } else {
+                        const float ddz = (float)((tl[k2][x] - tq) * dz);
+                        d2 = dx * dx + dy * dy + ddz * ddz;
+                    }
                     if (best < 0 || d2 < bd) {
                         best = k2;
                         bd = d2;
@@ -273,7 +288,12 @@ static inline unsigned nblk(long long n) { return (unsigned)((n + 255) / 256); }
 hipError_t launch_ifilter_tiles(const DevParams& p, const Tiles& tg, DevState in, DevState out, hipStream_t st)
 {
     if (tg.n == 0 || tg.tile0[tg.n] == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_ifilter_tile, dim3((unsigned)tg.tile0[tg.n]), dim3(IFT * IFT), 0, st, p, tg, in, out);
+    if (p.persp > 0.0)
+        hipLaunchKernelGGL(k_ifilter_tile<true>, dim3((unsigned)tg.tile0[tg.n]), dim3(IFT * IFT), 0, st, p, tg, in,
+                           out);
+    else
+        hipLaunchKernelGGL(k_ifilter_tile<false>, dim3((unsigned)tg.tile0[tg.n]), dim3(IFT * IFT), 0, st, p, tg, in,
+                           out);
     return hipGetLastError();
 }
 

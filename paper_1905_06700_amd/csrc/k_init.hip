@@ -814,6 +814,9 @@ __global__ __launch_bounds__(256) void k_init_normals(DevParams p, Shape sh, Dev
     const int i = (int)((pix / sh.cols) % sh.rows), j = (int)(pix % sh.cols);
     const double h2 = p.h_apss * p.h_apss;
     const int R = p.apss_R;
+    const bool persp = p.persp > 0.0;   // pinhole camera: t dz along each pixel's ray
+    double vq[3] = {0.0, 0.0, 1.0};
+    if (persp) ray_dir(p.persp, sh.rows, sh.cols, i, j, vq);
     for (int k = 0; k < KM; ++k) {
         if (k >= c) break;
         const double tq = s.t[k * S + pix];
@@ -825,9 +828,17 @@ __global__ __launch_bounds__(256) void k_init_normals(DevParams p, Shape sh, Dev
                 if (j2 < 0 || j2 >= sh.cols) continue;
                 const long long pp = (fr * sh.rows + i2) * sh.cols + j2;
                 const int cc = load_cnt(s.cnt, pp);
+                double vn[3] = {0.0, 0.0, 1.0};
+                if (persp && cc > 0) ray_dir(p.persp, sh.rows, sh.cols, i2, j2, vn);
                 for (int k2 = 0; k2 < cc; ++k2) {
-                    const double x = (j2 - j) * p.p_xy, y = (i2 - i) * p.p_xy;
-                    const double z = (s.t[k2 * S + pp] - tq) * p.dz;
+                    double x = (j2 - j) * p.p_xy, y = (i2 - i) * p.p_xy;
+                    double z = (s.t[k2 * S + pp] - tq) * p.dz;
+                    if (persp) {
+                        const double t2 = s.t[k2 * S + pp];
+                        x = (t2 * vn[0] - tq * vq[0]) * p.dz;
+                        y = (t2 * vn[1] - tq * vq[1]) * p.dz;
+                        z = (t2 * vn[2] - tq * vq[2]) * p.dz;
+                    }
                     const double d2 = x * x + y * y + z * z;
                     if (!(d2 < h2)) continue;
                     double a = 1.0 - d2 / h2;
@@ -853,9 +864,20 @@ __global__ __launch_bounds__(256) void k_init_normals(DevParams p, Shape sh, Dev
                                 + v0 * (M01 * M12 - M11 * M02);
                 const double c1 = d1 / det, c2 = d2 / det;
                 const double nrm = sqrt(c1 * c1 + c2 * c2 + 1.0);
-                nx = (float)(c1 / nrm);
-                ny = (float)(c2 / nrm);
-                nz = (float)(-1.0 / nrm);
+                // facing the sensor: against the pixel's ray (always so for the
+                // orthographic map); a plane containing the pinhole camera's
+                // line of sight (within 1e-6) takes n = -v
+                const double nv = (c1 * vq[0] + c2 * vq[1] - vq[2]) / nrm;
+                if (persp && fabs(nv) <= 1e-6) {
+                    nx = (float)(-vq[0]);
+                    ny = (float)(-vq[1]);
+                    nz = (float)(-vq[2]);
+                } else {
+                    const double sg = nv > 0.0 ? -1.0 : 1.0;
+                    nx = (float)(sg * c1 / nrm);
+                    ny = (float)(sg * c2 / nrm);
+                    nz = (float)(-sg / nrm);
+                }
             }
         }
         s.n[(0 * KM + k) * S + pix] = nx;

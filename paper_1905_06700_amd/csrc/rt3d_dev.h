@@ -52,7 +52,20 @@ struct DevParams {
     int    k_max, k_init, r_init, n_min, m_min, apss_R;
     double p_xy, dz, h_apss, h_int;
     double beta_t, dmax, beta_r, beta_b, r_min, d_merge, b_min, kappa;
+    double persp;   // 0: orthographic map f; > 0: pinhole camera (see ray_dir)
 };
+
+// Unit viewing ray of pixel (i, j) of a rows x cols frame under the pinhole
+// camera: (persp (j - cx), persp (i - cy), 1) normalised, cx = (cols - 1)/2,
+// cy = (rows - 1)/2; a point at depth t lies at t dz along it.
+__device__ __forceinline__ void ray_dir(double persp, int rows, int cols, int i, int j, double (&v)[3])
+{
+    const double u = persp * (j - 0.5 * (cols - 1)), w = persp * (i - 0.5 * (rows - 1));
+    const double inv = 1.0 / sqrt(u * u + w * w + 1.0);
+    v[0] = u * inv;
+    v[1] = w * inv;
+    v[2] = inv;
+}
 
 // Point state, slot-major structure of arrays (see rt3d_state).
 struct DevState {
@@ -274,10 +287,12 @@ __device__ __forceinline__ void merge_points(double (&t)[KM], float (&r)[KM], fl
 }
 
 // Sphere fit from the moments and projection of the query along its line of
-// sight: updates depth t (bins) and normal n when the fit is usable.
+// sight: updates depth t (bins) and normal n when the fit is usable.  ray:
+// the unit line of sight under the pinhole camera (nullptr: +Z, the
+// orthographic map); the normal faces the sensor (against the ray).
 __device__ __forceinline__ void apss_project(bool ok, float W, float Px, float Py, float Pz, float Nx, float Ny,
                                              float Nz, float PN, float PP, float h, float h2, double dz, double tmax,
-                                             double& t, float (&n)[3])
+                                             double& t, float (&n)[3], const float* ray = nullptr)
 {
     if (!ok) return;
     const float invW = 1.f / W;
@@ -291,18 +306,31 @@ __device__ __forceinline__ void apss_project(bool ok, float W, float Px, float P
     const float ulz = (Nz - 2.f * u4 * Pz) * invW;
     const float u0 = -(ulx * Px + uly * Py + ulz * Pz + u4 * PP) * invW;
     const float nul = sqrtf(ulx * ulx + uly * uly + ulz * ulz);
-    if (!(fabsf(ulz) > 1e-6f * nul)) return;
-    const float disc = ulz * ulz - 4.f * u4 * u0;
+    const float bz = ray ? ulx * ray[0] + uly * ray[1] + ulz * ray[2] : ulz;   // ul along the line of sight
+    if (!(fabsf(bz) > 1e-6f * nul)) return;
+    const float disc = bz * bz - 4.f * u4 * u0;
     float sroot;
-    if (disc < 0.f) sroot = -ulz / (2.f * u4);
-    else sroot = -2.f * u0 / (ulz + copysignf(sqrtf(disc), ulz));
+    if (disc < 0.f) sroot = -bz / (2.f * u4);
+    else sroot = -2.f * u0 / (bz + copysignf(sqrtf(disc), bz));
     sroot = fminf(fmaxf(sroot, -h), h);
     double tn = t + (double)sroot / dz;
     t = tn < 0.0 ? 0.0 : (tn > tmax ? tmax : tn);
-    const float gx = ulx, gy = uly, gz = ulz + 2.f * u4 * sroot;
+    float gx = ulx, gy = uly, gz = ulz + 2.f * u4 * sroot, gv = gz;
+    if (ray) {
+        gx = ulx + 2.f * u4 * sroot * ray[0];
+        gy = uly + 2.f * u4 * sroot * ray[1];
+        gz = ulz + 2.f * u4 * sroot * ray[2];
+        gv = gx * ray[0] + gy * ray[1] + gz * ray[2];
+    }
     const float gn = sqrtf(gx * gx + gy * gy + gz * gz);
-    if (gn > 0.f) {
-        const float inv = (gz > 0.f ? -1.f : 1.f) / gn;
+    if (ray && fabsf(gv) <= 1e-6f * gn) {
+        // pinhole camera, gradient perpendicular to the line of sight (the
+        // vertex of a missed sphere): the normal faces the sensor
+        n[0] = -ray[0];
+        n[1] = -ray[1];
+        n[2] = -ray[2];
+    } else if (gn > 0.f) {
+        const float inv = (gv > 0.f ? -1.f : 1.f) / gn;
         n[0] = gx * inv;
         n[1] = gy * inv;
         n[2] = gz * inv;
@@ -516,6 +544,8 @@ hipError_t launch_gradients(const DevModel& m, const DevParams& p, const Shape& 
 // only_above >= 0: pixels with at most that many points are copied, not fitted
 hipError_t launch_apss_tiles(const DevModel& m, const DevParams& p, const Tiles& tg, DevState in, DevState out,
                              int only_above, hipStream_t st);
+// LDS bytes of the APSS tile kernel for window radius R (the perspective camera needs it to fit 64 KB)
+size_t apss_lds_bytes(int R);
 hipError_t launch_ifilter_tiles(const DevParams& p, const Tiles& tg, DevState in, DevState out, hipStream_t st);
 // dst = the filtered src floored at b_min, per group (src, dst, tmp: the batch's arrays)
 hipError_t launch_bfilter_tiles(const float* w, int rb, const Tiles& tg, float b_min, const float* src, float* dst,

@@ -452,6 +452,7 @@ DevParams dev_params(const rt3d_ctx* c, int k = 0)
     d.d_merge = c->irf[k].dmerge;
     d.b_min = p.b_min;
     d.kappa = p.kappa;
+    d.persp = p.persp;
     return d;
 }
 
@@ -478,6 +479,10 @@ rt3d_status check_params(const rt3d_params* p, uint32_t bins, std::string& why)
         why = "unknown denoiser"; return RT3D_E_UNSUPPORTED;
     }
     if (std::ceil(p->h_apss / p->p_xy) > 16) { why = "h_apss / p_xy above 16 pixels"; return RT3D_E_UNSUPPORTED; }
+    if (!std::isfinite(p->persp) || p->persp < 0) { why = "persp must be finite and >= 0"; return RT3D_E_INVALID; }
+    if (p->persp > 0 && apss_lds_bytes((int)std::ceil(p->h_apss / p->p_xy)) > 65536) {
+        why = "the perspective camera's APSS window does not fit the tile kernel (R > 5)"; return RT3D_E_UNSUPPORTED;
+    }
     if (!(p->beta_t >= 0) || !(p->beta_r >= 0) || !(p->beta_b >= 0)) { why = "negative step scale"; return RT3D_E_INVALID; }
     if (!std::isfinite(p->r_min) || !std::isfinite(p->kappa) || p->kappa < 0) {
         why = "r_min / kappa not finite or kappa < 0"; return RT3D_E_INVALID;
@@ -549,7 +554,7 @@ struct Group {
 // size of at most LOOP_MAX_PIX pixels), and whether it does.
 bool loop_eligible(const rt3d_ctx* c, const std::vector<Group>& groups, const Shape& sh)
 {
-    return c->p.denoiser == RT3D_DENOISE_APSS && groups.size() == 1 &&
+    return c->p.denoiser == RT3D_DENOISE_APSS && groups.size() == 1 && !(c->p.persp > 0) &&
            (long long)sh.rows * sh.cols <= LOOP_MAX_PIX;
 }
 

@@ -304,6 +304,42 @@ def irf_class_scene(scene: int = 0, rows: int = 40, cols: int = 36, T: int = 777
     return sc, irfs, cls
 
 
+def persp_scene(scene: int = 0, rows: int = 32, cols: int = 28, T: int = 600, a: float = 0.05,
+                signal: float = 10.0, sbr: float = 1.0, config: int = 7) -> Scene:
+    """Perspective camera (a pinhole at the origin looking along +Z; pixel
+    (i, j) sees along the unit ray of (a (j - cx), a (i - cy), 1), depth =
+    range / dz along it, dz = 0.1): a tilted world plane through (0, 0, 30)
+    with normal (0.1, -0.05, -1) and, in front of it, a sphere of radius 5
+    centred at (1, -0.5, 22) that takes half of the signal of the rays it
+    meets (two surfaces there).  Gaussian IRF sigma 1.5 bins, mean `signal`
+    photons/pixel at the given SBR, reflectivity U[0.5, 1].  meta: persp = a,
+    p_xy = 0.6 (below the smallest pixel footprint, so the APSS window covers
+    h = 2)."""
+    rng = np.random.default_rng(seed_of(config, scene))
+    irf = gaussian_irf(1.5, 9)
+    dz = 0.1
+    i, j = np.mgrid[0:rows, 0:cols].astype(np.float64)
+    v = np.stack([a * (j - (cols - 1) / 2), a * (i - (rows - 1) / 2), np.ones_like(i)], axis=-1)
+    v /= np.linalg.norm(v, axis=-1, keepdims=True)
+    n0 = np.array([0.1, -0.05, -1.0])
+    n0 /= np.linalg.norm(n0)
+    rho_plane = (n0 @ np.array([0.0, 0.0, 30.0])) / (v @ n0)
+    C, Rs = np.array([1.0, -0.5, 22.0]), 5.0
+    b = v @ C
+    disc = b * b - C @ C + Rs * Rs
+    hit = disc > 0
+    rho_sphere = np.where(hit, b - np.sqrt(np.where(hit, disc, 0.0)), np.nan)
+    depth = np.stack([rho_sphere / dz, rho_plane / dz])
+    rho = rng.uniform(0.5, 1.0, (2, rows, cols))
+    amp = signal / 0.75
+    inten = np.stack([np.where(hit, 0.5 * amp * rho[0], 0.0), np.where(hit, 0.5, 1.0) * amp * rho[1]])
+    bkg = signal / sbr / T
+    Z = render(rng, irf, T, depth, inten, bkg)
+    return Scene(Z, irf, T, depth, inten, bkg,
+                 dict(config=config, dz=dz, p_xy=0.6, persp=a, mean_signal=signal, r_min=0.2 * signal,
+                      r_init=0, k_init=3))
+
+
 def random_gain(rng_seed: int, rows: int, cols: int, dead_frac: float = 0.02) -> np.ndarray:
     """Per-pixel detector gain in [0.5, 1.5] with a fraction of dead (0) pixels."""
     rng = np.random.default_rng(rng_seed)
