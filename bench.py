@@ -303,6 +303,64 @@ def super_resolution(reps=5):
     return res
 
 
+def observation_model(scenes, F=16, reps=3):
+    """Cost of the observation-model options on the head-shaped frames (16
+    per call): three per-pixel IRF classes (the scene's ex-Gaussian and two
+    Gaussians, on seeded 4 x 4 pixel blocks; each IRF-dependent kernel runs
+    once per class) and the pinhole camera (persp = 1/115, a pixel footprint
+    of about one world unit at the scene's ~115-unit range, p_xy = 0.9),
+    against the default single IRF and orthographic map.  Timing only: the
+    photons come from the scene's one IRF and orthographic geometry."""
+    import numpy as np
+    import torch
+
+    from paper_1905_06700_amd import rt3d, synth
+
+    n = len(scenes)
+    sc0 = scenes[0]
+    Z = torch.stack([torch.from_numpy(scenes[f % n].Z.view(np.int16)) for f in range(F)]).cuda()
+    P = F * ROWS * COLS
+    rng = np.random.default_rng(synth.seed_of(6, 99))
+    blocks = rng.integers(0, 3, (F, (ROWS + 3) // 4, (COLS + 3) // 4))
+    cls = np.kron(blocks, np.ones((1, 4, 4), np.int64))[:, :ROWS, :COLS].astype(np.uint8)
+    cls_d = torch.from_numpy(np.ascontiguousarray(cls.reshape(-1))).cuda()
+    base = scene_params(sc0)
+    variants = {"single_irf": (rt3d.Context(sc0.irf.probs, BINS, **base), None),
+                "three_irf_classes": (rt3d.Context(sc0.irf.probs, BINS, **base), cls_d),
+                "pinhole_camera": (rt3d.Context(sc0.irf.probs, BINS, **dict(base, persp=1 / 115.0, p_xy=0.9)), None)}
+    for i in (synth.gaussian_irf(1.5, 9), synth.gaussian_irf(3.0, 12)):
+        variants["three_irf_classes"][0].add_irf(i.probs)
+    res = {"workload": f"{F} frames of {ROWS}x{COLS}x{BINS} (head-shaped) per call"}
+    for name, (ctx, c) in variants.items():
+        ctx.workspace(F, ROWS, COLS, int(P * 200))
+        out = ctx.make_output(P)
+
+        def run():
+            ctx.reconstruct_into(out, F, ROWS, COLS, hist=Z, irf_class=c)
+
+        run()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            run()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        r = {"call_ms": round(ms, 3), "frames_per_s": round(F / (ms / 1e3), 1)}
+        for g in ("init", "depth", "apss", "ifilter"):
+            ctx.profile(g)
+            run()
+            torch.cuda.synchronize()
+            kms, nl = ctx.profile_read()
+            ctx.profile(None)
+            r[f"{g}_ms_per_call"] = round(kms, 4)
+        assert ctx.query().device_error == 0
+        res[name] = r
+    del Z
+    return res
+
+
 def learned_vs_apss(n_train=4, n_eval=4, steps=300, rows=256, cols=256, bins=1024):
     """Learned denoiser against plain APSS on multi-layer scenes: train on the
     GPU (the library's forward/backward kernels), then time and score both on
@@ -530,7 +588,7 @@ def main():
         "active_entries_per_frame": E // F, "points_per_frame": pts // F,
         "single_frame_latency_ms": round(latency_ms, 3), "single_frame_latency_graph_ms": round(latency_graph_ms, 3),
         "small_frames": small_frames(), "uneven_frames": uneven_frames(), "hbm_regime": hbm_regime(scenes),
-        "super_resolution": super_resolution(),
+        "super_resolution": super_resolution(), "observation_model": observation_model(scenes),
         "wall_s": round(wall, 3),
         "roofline": roofline, "kernels": kernels, "cpu_baseline": cpu,
         "learned_vs_apss": None if args.no_learned else learned_vs_apss(),
