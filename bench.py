@@ -383,7 +383,7 @@ def learned_vs_apss(n_train=4, n_eval=4, steps=300, rows=256, cols=256, bins=102
     log(f"[bench] learned denoiser: recording depth-block inputs of {n_train} training scenes")
     recorded = train.record_depth_inputs(apss, Ztr)
     net.workspace(n_train, rows, cols, n_train * rows * cols * 256)
-    hist = train.train(net, [(recorded, truth)], steps=steps, lr=2e-3, seed=0)
+    hist = train.train(net, [(recorded, truth)], steps=steps, lr=2e-3, seed=0, log_every=50, log=log)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     del recorded
