@@ -100,8 +100,13 @@ __global__ __launch_bounds__(ATX * ATY) void k_apss_tile(DevModel m, DevParams p
         ray_dir(p.persp, sh.rows, sh.cols, i, j, vq);
         for (int a = 0; a < 3; ++a) rq[a] = (float)vq[a];
     }
+    // pinhole camera: the query's unnormalised ray uq = (persp (j - cx), persp (i - cy), 1)
+    const float pa = (float)p.persp;
+    const float uq[3] = {pa * (float)(j - 0.5 * (sh.cols - 1)), pa * (float)(i - 0.5 * (sh.rows - 1)), 1.f};
+    const float uuq = fmaf(uq[0], uq[0], fmaf(uq[1], uq[1], 1.f));
     for (int k = 0; k < c; ++k) {
         const double tq = tl[k * NS + xc];
+        const float rho = (float)(tq * dz), rho2 = 0.999f * rho * rho;   // squared range, rounded down
         float W = 0.f, Px = 0.f, Py = 0.f, Pz = 0.f, Nx = 0.f, Ny = 0.f, Nz = 0.f, PN = 0.f, PP = 0.f, nn = 0.f;
         if (fit) {
             for (int di = -R; di <= R; ++di) {
@@ -114,7 +119,18 @@ __global__ __launch_bounds__(ATX * ATY) void k_apss_tile(DevModel m, DevParams p
                     const int x = xc + di * SX + dj;
                     const int cc = cl[x];
                     double v2[3] = {0.0, 0.0, 1.0};
-                    if (PERSP && cc > 0) ray_dir(p.persp, sh.rows, sh.cols, i + di, j + dj, v2);
+                    if (PERSP && cc > 0) {
+                        // every point of this pixel's ray is at least rho_q sin(theta) from
+                        // the query (theta: the angle between the two rays); skip the pixel
+                        // when that reaches h
+                        const float ax = pa * (float)dj, ay = pa * (float)di;   // u2 - uq = (ax, ay, 0)
+                        // |uq x u2| = |uq x (u2 - uq)|
+                        const float cx2 = -uq[2] * ay, cy2 = uq[2] * ax, cz2 = uq[0] * ay - uq[1] * ax;
+                        const float uu2 = fmaf(uq[0] + ax, uq[0] + ax, fmaf(uq[1] + ay, uq[1] + ay, 1.f));
+                        const float sin2 = (cx2 * cx2 + cy2 * cy2 + cz2 * cz2) / (uuq * uu2);
+                        if (!(rho2 * sin2 < h2)) continue;
+                        ray_dir(p.persp, sh.rows, sh.cols, i + di, j + dj, v2);
+                    }
                     for (int k2 = 0; k2 < cc; ++k2) {
                         const double t2 = tl[k2 * NS + x];
                         float yx = yx0, yy = yy0, yz, d2;

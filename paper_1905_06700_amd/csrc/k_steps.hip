@@ -173,9 +173,16 @@ __device__ __forceinline__ Lane lane_setup(const DevModel& m, const DevState& s,
 {
     Lane L;
     const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    L.pix = gid / LPP;
     L.sub = (int)(gid % LPP);
-    L.member = L.pix < P && in_class(m, L.pix);
+    if (m.lst) {   // the pixels of the launch's IRF class, from its list
+        const uint32_t b0 = m.lst_meta[m.cls_id], b1 = m.lst_meta[m.cls_id + 1];
+        const long long idx = gid / LPP;
+        L.member = idx < (long long)(b1 - b0);
+        L.pix = L.member ? (long long)m.lst[b0 + idx] : 0;
+    } else {
+        L.pix = gid / LPP;
+        L.member = L.pix < P && in_class(m, L.pix);
+    }
     L.live = L.member;
     const long long pp = L.live ? L.pix : 0;
     const uint32_t e0 = off[pp], e1 = off[pp + 1];
@@ -327,6 +334,78 @@ __global__ __launch_bounds__(256) void k_gradients(DevModel m, Shape sh, const u
 }
 
 static inline unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+// Per-class pixel lists (per-pixel IRFs).  meta[0 .. n] holds each class's
+// first list position (meta[n] = P), meta[RT3D_MAX_IRFS + 1 + k] the class's
+// cursor.  Each wavefront takes 64 consecutive pixels and appends the pixels
+// of every class in ascending order (a ballot rank), so list chunks stay
+// contiguous in memory; chunks follow in the order the wavefronts reach the
+// cursor, which no per-pixel step depends on.
+constexpr int CLASS_CUR = RT3D_MAX_IRFS + 1;
+
+__device__ __forceinline__ int class_of(const uint8_t* cls, long long pix, long long P, int n)
+{
+    if (pix >= P) return -1;
+    const int k = cls[pix];
+    return k < n ? k : 0;
+}
+
+__global__ void k_class_zero(uint32_t* meta)
+{
+    if (threadIdx.x < CLASS_META) meta[threadIdx.x] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_class_count(const uint8_t* __restrict__ cls, long long P, int n,
+                                                     uint32_t* meta)
+{
+    const long long pix = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = class_of(cls, pix, P, n);
+    for (int c = 0; c < n; ++c) {
+        const unsigned long long mask = __ballot(k == c);
+        if ((threadIdx.x & 63) == 0 && mask) atomicAdd(&meta[CLASS_CUR + c], (uint32_t)__popcll(mask));
+    }
+}
+
+__global__ void k_class_base(int n, uint32_t* meta)
+{
+    if (threadIdx.x != 0) return;
+    uint32_t acc = 0;
+    for (int c = 0; c < n; ++c) {
+        const uint32_t cnt = meta[CLASS_CUR + c];
+        meta[c] = acc;
+        meta[CLASS_CUR + c] = acc;
+        acc += cnt;
+    }
+    meta[n] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_class_scatter(const uint8_t* __restrict__ cls, long long P, int n,
+                                                       uint32_t* meta, uint32_t* __restrict__ list)
+{
+    const long long pix = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = class_of(cls, pix, P, n);
+    const int lane = (int)(threadIdx.x & 63);
+    const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    for (int c = 0; c < n; ++c) {
+        const unsigned long long mask = __ballot(k == c);
+        if (!mask) continue;
+        uint32_t b = 0;
+        if (lane == 0) b = atomicAdd(&meta[CLASS_CUR + c], (uint32_t)__popcll(mask));
+        b = (uint32_t)__shfl((int)b, 0, 64);
+        if (k == c) list[b + (uint32_t)__popcll(mask & below)] = (uint32_t)pix;
+    }
+}
+
+hipError_t launch_class_lists(const uint8_t* cls, long long P, int n, uint32_t* list, uint32_t* meta,
+                              hipStream_t st)
+{
+    if (n < 1 || n > RT3D_MAX_IRFS) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_class_zero, dim3(1), dim3(64), 0, st, meta);
+    if (P > 0) hipLaunchKernelGGL(k_class_count, dim3(blocks_for(P, 256)), dim3(256), 0, st, cls, P, n, meta);
+    hipLaunchKernelGGL(k_class_base, dim3(1), dim3(64), 0, st, n, meta);
+    if (P > 0) hipLaunchKernelGGL(k_class_scatter, dim3(blocks_for(P, 256)), dim3(256), 0, st, cls, P, n, meta, list);
+    return hipGetLastError();
+}
 
 hipError_t launch_depth_step(const DevModel& m, const DevParams& p, const Shape& sh, const uint32_t* off,
                              const uint32_t* ent, const float* gain, DevState s, hipStream_t st)

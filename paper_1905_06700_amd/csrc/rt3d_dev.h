@@ -37,6 +37,11 @@ struct DevModel {
     // (numbers >= n_cls count as 0); cls = nullptr: every pixel.
     const uint8_t* cls;
     int            cls_id, n_cls;
+    // Optional per-class pixel lists (launch_class_lists): the per-pixel
+    // steps then take lane group i to pixel lst[lst_meta[cls_id] + i] and
+    // leave past lst_meta[cls_id + 1] - lst_meta[cls_id] pixels.
+    const uint32_t* lst;
+    const uint32_t* lst_meta;
 };
 
 // Whether pixel pix belongs to the launch's IRF class.
@@ -537,6 +542,11 @@ hipError_t launch_intensity_step(const DevModel& m, const DevParams& p, const Sh
 hipError_t launch_bg_step(const DevModel& m, const DevParams& p, const Shape& sh,
                           const uint32_t* off, const uint32_t* ent, const float* gain, DevState s,
                           float* bdst, hipStream_t st);
+// Pixel lists of the n IRF classes of map cls over P pixels (list: P entries;
+// meta: CLASS_META words, meta[k] .. meta[k+1] - 1 the list positions of class k).
+constexpr int CLASS_META = 2 * (RT3D_MAX_IRFS + 1);
+hipError_t launch_class_lists(const uint8_t* cls, long long P, int n, uint32_t* list, uint32_t* meta,
+                              hipStream_t st);
 hipError_t launch_gradients(const DevModel& m, const DevParams& p, const Shape& sh,
                             const uint32_t* off, const uint32_t* ent, const float* gain,
                             DevState s, float* gt, float* gr, float* gb, hipStream_t st);

@@ -88,6 +88,8 @@ struct Workspace {
     uint32_t* partial;
     uint32_t* evoff;
     uint32_t* stage;
+    uint32_t* cls_list;                // per-class pixel lists (per-pixel IRFs)
+    uint32_t* cls_meta;
     DevState A, B;
     float* btmp;
     CnnBuffers cnn;
@@ -114,6 +116,8 @@ Workspace carve(uint8_t* base, long long P, long long Ps, uint64_t E, bool with_
     w.partial = (uint32_t*)take(sizeof(uint32_t) * scan_partial_elems(Ps));
     w.evoff = (uint32_t*)take(sizeof(uint32_t) * (P + 1));
     w.stage = (uint32_t*)take(sizeof(uint32_t) * CP_STAGE * std::max<long long>(P, 1));
+    w.cls_list = (uint32_t*)take(sizeof(uint32_t) * std::max<long long>(P, 1));
+    w.cls_meta = (uint32_t*)take(sizeof(uint32_t) * CLASS_META);
     for (DevState* s : {&w.A, &w.B}) {
         s->t = (double*)take(sizeof(double) * KM * Ps);
         s->r = (float*)take(sizeof(float) * KM * Ps);
@@ -402,7 +406,8 @@ bool prof_begin(rt3d_ctx* c, int id, hipStream_t st, size_t& slot)
 // The model of IRF class k; with a per-pixel class map `cls`, a launch with
 // it touches only the pixels of class k (class numbers past the context's
 // classes count as 0).
-DevModel dev_model(const rt3d_ctx* c, int k = 0, const uint8_t* cls = nullptr)
+DevModel dev_model(const rt3d_ctx* c, int k = 0, const uint8_t* cls = nullptr, const uint32_t* lst = nullptr,
+                   const uint32_t* lst_meta = nullptr)
 {
     const IrfTables& t = c->irf[k];
     DevModel m{};
@@ -427,6 +432,8 @@ DevModel dev_model(const rt3d_ctx* c, int k = 0, const uint8_t* cls = nullptr)
     m.cls = cls;
     m.cls_id = k;
     m.n_cls = (int)c->irf.size();
+    m.lst = cls ? lst : nullptr;
+    m.lst_meta = cls ? lst_meta : nullptr;
     return m;
 }
 
@@ -577,14 +584,16 @@ int n_classes(const rt3d_ctx* c, const uint8_t* cls) { return cls ? (int)c->irf.
 // equally sized frames.
 rt3d_status iterate(rt3d_ctx* c, const Shape& sh, const std::vector<Group>& groups, const uint32_t* off,
                     const uint32_t* ent, const float* gain, DevState A, DevState B, float* btmp,
-                    const CnnBuffers* cnn, const uint8_t* cls, hipStream_t st)
+                    const CnnBuffers* cnn, const uint8_t* cls, hipStream_t st, const uint32_t* lst = nullptr,
+                    const uint32_t* lst_meta = nullptr)
 {
     const DevModel m = dev_model(c);
     const DevParams p = dev_params(c);
     const int nc = n_classes(c, cls);
     for (int k = 0; k < nc; ++k)
         RT3D_LAUNCH(c, RT3D_KERNEL_DEPTH, st,
-                    launch_depth_step(dev_model(c, k, cls), dev_params(c, k), sh, off, ent, gain, A, st));
+                    launch_depth_step(dev_model(c, k, cls, lst, lst_meta), dev_params(c, k), sh, off, ent, gain, A,
+                                      st));
     DevState cur = A;
     // the groups as tile tables of at most TILE_GROUPS groups (one launch each)
     std::vector<Tiles> tiles(1, Tiles{});
@@ -610,13 +619,15 @@ rt3d_status iterate(rt3d_ctx* c, const Shape& sh, const std::vector<Group>& grou
     // the in-pixel merge runs fused ahead of the intensity step
     for (int k = 0; k < nc; ++k)
         RT3D_LAUNCH(c, RT3D_KERNEL_INTENSITY, st,
-                    launch_intensity_step(dev_model(c, k, cls), dev_params(c, k), sh, off, ent, gain, cur, true, st));
+                    launch_intensity_step(dev_model(c, k, cls, lst, lst_meta), dev_params(c, k), sh, off, ent, gain,
+                                          cur, true, st));
     for (const Tiles& tg : tiles)
         RT3D_LAUNCH(c, RT3D_KERNEL_IFILTER, st, launch_ifilter_tiles(p, tg, cur, A, st));
     // the background step writes btmp; the filter brings it back into A.b
     for (int k = 0; k < nc; ++k)
         RT3D_LAUNCH(c, RT3D_KERNEL_BKG, st,
-                    launch_bg_step(dev_model(c, k, cls), dev_params(c, k), sh, off, ent, gain, A, btmp, st));
+                    launch_bg_step(dev_model(c, k, cls, lst, lst_meta), dev_params(c, k), sh, off, ent, gain, A, btmp,
+                                   st));
     for (const Tiles& tg : tiles)
         RT3D_LAUNCH(c, RT3D_KERNEL_BFILTER, st,
                     launch_bfilter_tiles(c->d_bw, c->rb, tg, (float)c->p.b_min, btmp, A.b, B.b, st));
@@ -972,6 +983,7 @@ rt3d_status rt3d_reconstruct(rt3d_ctx* c, const rt3d_input* in, rt3d_output* out
             RT3D_LAUNCH(c, RT3D_KERNEL_NORMALS, st, launch_init_normals(p, g.sh, state_at(w.A, g.base), st));
     }
     c->state_layout.clear();
+    if (cls) RT3D_HIP(c, launch_class_lists(cls, sh.P, n_classes(c, cls), w.cls_list, w.cls_meta, st));
     if (c->p.sr > 1) {
         for (int it = 0; it < c->p.n_iter; ++it) {
             s = iterate_sr(c, sh, off, ent, in->gain, w.A, w.B, w.btmp, st);
@@ -982,7 +994,8 @@ rt3d_status rt3d_reconstruct(rt3d_ctx* c, const rt3d_input* in, rt3d_output* out
                     launch_loop(m, p, sh, off, ent, in->gain, w.A, w.B, w.btmp, c->d_bw, c->rb, c->p.n_iter, st));
     } else {
         for (int it = 0; it < c->p.n_iter; ++it) {
-            s = iterate(c, sh, groups, off, ent, in->gain, w.A, w.B, w.btmp, &w.cnn, cls, st);
+            s = iterate(c, sh, groups, off, ent, in->gain, w.A, w.B, w.btmp, &w.cnn, cls, st, w.cls_list,
+                        w.cls_meta);
             if (s != RT3D_OK) return s;
         }
     }
