@@ -15,18 +15,22 @@
 // State: point arrays (t, r, n, cnt) on the point grid with slot stride Pf;
 // the lidar pixels' background in b[0 .. P - 1] of the same state.
 //
-// Mapping: one wavefront per lidar pixel.  Lane l holds slot l % KM of the
-// block's point-grid pixel l / KM (s <= 4, so s^2 KM <= 64 lanes); the
-// block's live points are also staged in LDS.  The pixel's entries go through
-// 64 at a time, one per lane: a lane evaluates lambda of its entry over the
-// staged points and leaves z/(g lambda) and the bin in LDS; then each point's
-// lane sums the batch's z h'/lambda or z h/lambda.  The background's
-// sum z/lambda is a wavefront sum.
+// Mapping: sixteen lanes per lidar pixel, four lidar pixels per wavefront.
+// Lane u holds the points of the block's point-grid pixel u in registers
+// (s <= 4, so s^2 <= 16 lanes); the block's points are also staged in LDS.
+// The pixel's entries go through 16 at a time, one per lane: a lane
+// evaluates lambda of its entry over the staged points and leaves
+// z/(g lambda) and the bin in LDS; then every lane adds the batch's
+// z h'/lambda and z h/lambda to each of its points.  The background's
+// sum z/lambda is a sum over the sixteen lanes.
 #include "rt3d_dev.h"
 
 namespace rt3d {
 
-constexpr int SR_WAVES = 4;   // lidar pixels per workgroup
+// Lanes per lidar pixel (one per point-grid pixel of its block, s <= 4) and
+// lidar pixels per workgroup.
+constexpr int SR_GROUP = 16;
+constexpr int SR_GROUPS = 16;
 
 // What a launch of k_sr_step computes.
 enum SrWork { SR_DEPTH, SR_INTENSITY, SR_BKG, SR_GRADIENTS };
@@ -52,107 +56,126 @@ __device__ __forceinline__ long long sr_fine(long long p, int u, int s, int rows
 }
 
 template <SrWork WHICH>
-__global__ __launch_bounds__(64 * SR_WAVES) void k_sr_step(DevModel m, DevParams p, Shape lid, int s, long long Pf,
-                                                           const uint32_t* __restrict__ off,
-                                                           const uint32_t* __restrict__ ent,
-                                                           const float* __restrict__ gain, DevState st,
-                                                           float* __restrict__ bdst, float* __restrict__ gt,
-                                                           float* __restrict__ gr, float* __restrict__ gb)
+__global__ __launch_bounds__(SR_GROUP * SR_GROUPS) void k_sr_step(DevModel m, DevParams p, Shape lid, int s,
+                                                                 long long Pf, const uint32_t* __restrict__ off,
+                                                                 const uint32_t* __restrict__ ent,
+                                                                 const float* __restrict__ gain, DevState st,
+                                                                 float* __restrict__ bdst, float* __restrict__ gt,
+                                                                 float* __restrict__ gr, float* __restrict__ gb)
 {
-    __shared__ int s_a[SR_WAVES][64];
-    __shared__ float s_f[SR_WAVES][64];
-    __shared__ float s_r[SR_WAVES][64];
-    __shared__ float s_w[SR_WAVES][64];
-    __shared__ int s_tb[SR_WAVES][64];
-    const int wv = (int)(threadIdx.x / 64), lane = (int)(threadIdx.x & 63);
-    const long long pix = (long long)blockIdx.x * SR_WAVES + wv;
-    if (pix >= lid.P) return;                       // the whole wavefront
-    const int u = lane / KM, k = lane % KM;
-    const bool in_block = u < s * s;
-    const long long q = in_block ? sr_fine(pix, u, s, lid.rows, lid.cols) : 0;
-    const int c = in_block ? load_cnt(st.cnt, q) : 0;
-    const bool has = k < c;
-    const double t = has ? st.t[(long long)k * Pf + q] : 0.0;
-    const float r = has ? st.r[(long long)k * Pf + q] : 0.f;
-    const double fl = floor(t);
-    const int a = (int)fl;
-    const float f = (float)(t - fl);
-    const float G = gain ? gain[pix] : 1.f;
-    const float bb = st.b[pix];
-    const bool live = G > 0.f;                      // wave-uniform
-    // the block's live points, in lane order
-    const uint64_t mask = __ballot(has);
-    const int np = __popcll(mask);
-    const int at = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-    if (has) {
-        s_a[wv][at] = a;
-        s_f[wv][at] = f;
-        s_r[wv][at] = r;
+    __shared__ int s_a[SR_GROUPS][SR_GROUP * KM];
+    __shared__ float s_f[SR_GROUPS][SR_GROUP * KM];
+    __shared__ float s_r[SR_GROUPS][SR_GROUP * KM];
+    __shared__ float s_w[SR_GROUPS][SR_GROUP];
+    __shared__ int s_tb[SR_GROUPS][SR_GROUP];
+    const int g = (int)(threadIdx.x / SR_GROUP), u = (int)(threadIdx.x % SR_GROUP);
+    const long long pix = (long long)blockIdx.x * SR_GROUPS + g;
+    const bool valid = pix < lid.P;                 // the whole group
+    const long long pq = valid ? pix : 0;
+    // lane u: point-grid pixel u of the block, its points in registers
+    const bool in_block = valid && u < s * s;
+    const long long q = in_block ? sr_fine(pq, u, s, lid.rows, lid.cols) : 0;
+    PixPoints pts;
+    load_points(st, Pf, q, pts);
+    if (!in_block) pts.c = 0;
+    const float G = valid ? (gain ? gain[pq] : 1.f) : 0.f;
+    const float bb = st.b[pq];
+    const bool live = G > 0.f;                      // group-uniform
+    // the block's points staged in LDS, lane after lane (prefix of the counts in the group)
+    int before = 0, np = 0;
+    for (int v = 0; v < SR_GROUP; ++v) {
+        const int cv = __shfl(pts.c, (int)(threadIdx.x & ~(SR_GROUP - 1)) + v, 64);
+        before += v < u ? cv : 0;
+        np += cv;
     }
+#pragma unroll
+    for (int k = 0; k < KM; ++k)
+        if (k < pts.c) {
+            s_a[g][before + k] = pts.a[k];
+            s_f[g][before + k] = pts.f[k];
+            s_r[g][before + k] = pts.r[k];
+        }
     sr_sync();
-    float sh = 0.f, shp = 0.f, sz = 0.f;
-    if (live) {
-        const uint32_t e0 = off[pix], e1 = off[pix + 1];
-        const float invG = 1.f / G;
-        for (uint32_t eb = e0; eb < e1; eb += 64) {
-            const uint32_t x = eb + (uint32_t)lane;
-            const bool on = x < e1;
-            const uint32_t v = on ? ent[x] : 0u;
-            const int tb = ent_bin(v);
-            float lam = bb;
-            for (int n = 0; n < np; ++n) {
-                float h, hp;
-                irf_eval(m, tb, s_a[wv][n], s_f[wv][n], h, hp);
-                lam = fmaf(s_r[wv][n], h, lam);
-            }
-            const float w = on ? (float)ent_cnt(v) * invG * __builtin_amdgcn_rcpf(lam) : 0.f;
-            sz += w;
-            if (WHICH != SR_BKG) {
-                s_w[wv][lane] = w;
-                s_tb[wv][lane] = tb;
-                sr_sync();
-                if (has) {
-                    const int nb = (int)min(64u, e1 - eb);
-                    for (int y = 0; y < nb; ++y) {
+    float sh[KM], shp[KM], sz = 0.f;
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+        sh[k] = 0.f;
+        shp[k] = 0.f;
+    }
+    const uint32_t e0 = live ? off[pq] : 0u, e1 = live ? off[pq + 1] : 0u;
+    const float invG = live ? 1.f / G : 0.f;
+    for (uint32_t eb = e0; eb < e1; eb += SR_GROUP) {   // the same trip count on the group's lanes
+        const uint32_t x = eb + (uint32_t)u;
+        const bool on = x < e1;
+        const uint32_t v = on ? ent[x] : 0u;
+        const int tb = ent_bin(v);
+        float lam = bb;
+        for (int n = 0; n < np; ++n) {
+            float h, hp;
+            irf_eval(m, tb, s_a[g][n], s_f[g][n], h, hp);
+            lam = fmaf(s_r[g][n], h, lam);
+        }
+        const float w = on ? (float)ent_cnt(v) * invG * __builtin_amdgcn_rcpf(lam) : 0.f;
+        sz += w;
+        if (WHICH != SR_BKG) {
+            s_w[g][u] = w;
+            s_tb[g][u] = tb;
+            sr_sync();
+            const int nb = (int)min((uint32_t)SR_GROUP, e1 - eb);
+            for (int y = 0; y < nb; ++y) {
+                const float wy = s_w[g][y];
+                const int ty = s_tb[g][y];
+#pragma unroll
+                for (int k = 0; k < KM; ++k)
+                    if (k < pts.c) {
                         float h, hp;
-                        irf_eval(m, s_tb[wv][y], a, f, h, hp);
-                        sh = fmaf(s_w[wv][y], h, sh);
-                        shp = fmaf(s_w[wv][y], hp, shp);
+                        irf_eval(m, ty, pts.a[k], pts.f[k], h, hp);
+                        sh[k] = fmaf(wy, h, sh[k]);
+                        shp[k] = fmaf(wy, hp, shp[k]);
                     }
-                }
-                sr_sync();                          // reads done before the next batch's writes
             }
+            sr_sync();                              // reads done before the next batch's writes
         }
     }
-    if (WHICH == SR_BKG || WHICH == SR_GRADIENTS) sz = wave_sum(sz);
+    if (WHICH == SR_BKG || WHICH == SR_GRADIENTS) {
+#pragma unroll
+        for (int d = SR_GROUP / 2; d >= 1; d >>= 1) sz += __shfl_xor(sz, d, 64);
+    }
     if (WHICH == SR_DEPTH) {
-        if (live && has && r > 0.f) {
-            float S, Sp;
-            s_eval(m, t, S, Sp);
-            st.t[(long long)k * Pf + q] = depth_next(m, p, t, Sp, shp);
-        }
+        if (live)
+#pragma unroll
+            for (int k = 0; k < KM; ++k)
+                if (k < pts.c && pts.r[k] > 0.f) {
+                    float S, Sp;
+                    s_eval(m, pts.t[k], S, Sp);
+                    st.t[(long long)k * Pf + q] = depth_next(m, p, pts.t[k], Sp, shp[k]);
+                }
     } else if (WHICH == SR_INTENSITY) {
-        if (live && has) {
-            float S, Sp;
-            s_eval(m, t, S, Sp);
-            if (S > 0.f) st.r[(long long)k * Pf + q] = intensity_next(p, r, S, sh);
-        }
+        if (live)
+#pragma unroll
+            for (int k = 0; k < KM; ++k)
+                if (k < pts.c) {
+                    float S, Sp;
+                    s_eval(m, pts.t[k], S, Sp);
+                    if (S > 0.f) st.r[(long long)k * Pf + q] = intensity_next(p, pts.r[k], S, sh[k]);
+                }
     } else if (WHICH == SR_BKG) {
-        if (lane == 0) bdst[pix] = live ? background_next(m, p, bb, sz) : bb;
+        if (valid && u == 0) bdst[pix] = live ? background_next(m, p, bb, sz) : bb;
     } else {   // raw gradients: every slot of the block's point-grid pixels, and gb
-        if (in_block) {
-            float vt = 0.f, vr = 0.f;
-            if (live && has) {
-                float S, Sp;
-                s_eval(m, t, S, Sp);
-                vt = G * r * (Sp + shp);
-                vr = G * (S - sh);
+        if (in_block)
+#pragma unroll
+            for (int k = 0; k < KM; ++k) {
+                float vt = 0.f, vr = 0.f;
+                if (live && k < pts.c) {
+                    float S, Sp;
+                    s_eval(m, pts.t[k], S, Sp);
+                    vt = G * pts.r[k] * (Sp + shp[k]);
+                    vr = G * (S - sh[k]);
+                }
+                gt[(long long)k * Pf + q] = vt;
+                gr[(long long)k * Pf + q] = vr;
             }
-            gt[(long long)k * Pf + q] = vt;
-            gr[(long long)k * Pf + q] = vr;
-        }
-        if (lane == 0) gb[pix] = live ? G * ((float)m.T - sz) : 0.f;
+        if (valid && u == 0) gb[pix] = live ? G * ((float)m.T - sz) : 0.f;
     }
 }
 
@@ -191,8 +214,8 @@ static hipError_t sr_launch(const DevModel& m, const DevParams& p, const Shape& 
                             float* gt, float* gr, float* gb, hipStream_t stream)
 {
     if (lid.P == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_sr_step<WHICH>, dim3((unsigned)((lid.P + SR_WAVES - 1) / SR_WAVES)), dim3(64 * SR_WAVES), 0,
-                       stream, m, p, lid, s, Pf, off, ent, gain, st, bdst, gt, gr, gb);
+    hipLaunchKernelGGL(k_sr_step<WHICH>, dim3((unsigned)((lid.P + SR_GROUPS - 1) / SR_GROUPS)),
+                       dim3(SR_GROUP * SR_GROUPS), 0, stream, m, p, lid, s, Pf, off, ent, gain, st, bdst, gt, gr, gb);
     return hipGetLastError();
 }
 

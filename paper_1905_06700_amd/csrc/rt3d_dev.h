@@ -66,7 +66,11 @@ struct DevParams {
 __device__ __forceinline__ void ray_dir(double persp, int rows, int cols, int i, int j, double (&v)[3])
 {
     const double u = persp * (j - 0.5 * (cols - 1)), w = persp * (i - 0.5 * (rows - 1));
-    const double inv = 1.0 / sqrt(u * u + w * w + 1.0);
+    // 1/sqrt(q): the FP32 estimate and one Newton step in FP64 (relative error
+    // ~1e-14, without FP64 division and square root)
+    const double q = u * u + w * w + 1.0;
+    const double y0 = (double)__frsqrt_rn((float)q);
+    const double inv = y0 * (1.5 - 0.5 * q * y0 * y0);
     v[0] = u * inv;
     v[1] = w * inv;
     v[2] = inv;
