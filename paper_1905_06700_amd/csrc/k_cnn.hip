@@ -16,8 +16,12 @@
 //                    W' the tap-flipped transpose, gated by the ReLU of X
 //   backward weight: dW[tap][ci][co] = sum_p X[p + tap][ci] dY[p][co],
 //                    per-workgroup partials reduced in a fixed order
-// A workgroup owns 64 consecutive pixels of one image row (4 wavefronts x 16
-// pixels) and stages the 3-row halo and the layer's weights in LDS.
+// A forward / backward-data workgroup owns 64 consecutive pixels of CR = 4
+// image rows (one row per wavefront, four 16-pixel MFMA row tiles each) and
+// stages the CR + 2 halo rows and the layer's weights in LDS: every weight
+// fragment read from LDS feeds four row tiles, and the staged weights serve
+// 256 pixels.  The weight-gradient workgroup owns 64 pixels of one row at a
+// time.
 #include "rt3d_dev.h"
 #include "rt3d_cnn.h"
 
@@ -28,21 +32,22 @@ namespace rt3d {
 typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
 
-constexpr int CT = 64;   // output pixels per workgroup (one row segment)
+constexpr int CT = 64;   // output pixels per workgroup row (one row segment)
+constexpr int CR = 4;    // image rows per forward / backward-data workgroup (one per wavefront)
 
 __device__ __forceinline__ float4_t mfma16(half4_t a, half4_t b, float4_t c)
 {
     return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
 }
 
-// Stages rows y-1..y+1, columns x0-1..x0+CT of one frame (zero outside the
-// image) into LDS as [3][CT+2][C] halves.
-template <int C>
+// Stages rows y-1..y+NR-2, columns x0-1..x0+CT of one frame (zero outside
+// the image) into LDS as [NR][CT+2][C] halves.
+template <int C, int NR = 3>
 __device__ __forceinline__ void stage_halo(const __half* __restrict__ X, int F, int H, int W, int f, int y,
                                            int x0, __half* __restrict__ halo)
 {
     constexpr int VPP = C / 8;                       // 16-byte vectors per pixel
-    const int nvec = 3 * (CT + 2) * VPP;
+    const int nvec = NR * (CT + 2) * VPP;
     for (int v = threadIdx.x; v < nvec; v += blockDim.x) {
         const int c8 = v % VPP;
         const int px = (v / VPP) % (CT + 2);
@@ -66,53 +71,64 @@ __global__ __launch_bounds__(256) void k_conv3x3(const __half* __restrict__ X, c
 {
     constexpr int K = 9 * CIN;
     constexpr int NT = COUT / 16;
-    __shared__ __align__(16) __half halo[3 * (CT + 2) * CIN];
+    constexpr int MT = CT / 16;                      // row tiles per wavefront
+    __shared__ __align__(16) __half halo[(CR + 2) * (CT + 2) * CIN];
     __shared__ __align__(16) __half wsh[COUT * K];
     const int segs = (W + CT - 1) / CT;
+    const int bands = (H + CR - 1) / CR;
     const int seg = blockIdx.x % segs;
-    const int y = (blockIdx.x / segs) % H;
-    const int f = blockIdx.x / (segs * H);
+    const int y0 = ((blockIdx.x / segs) % bands) * CR;
+    const int f = blockIdx.x / (segs * bands);
     const int x0 = seg * CT;
-    stage_halo<CIN>(X, F, H, W, f, y, x0, halo);
+    stage_halo<CIN, CR + 2>(X, F, H, W, f, y0, x0, halo);
     for (int v = threadIdx.x; v < COUT * K / 8; v += blockDim.x)
         reinterpret_cast<uint4*>(wsh)[v] = reinterpret_cast<const uint4*>(Wt)[v];
     __syncthreads();
 
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;   // wavefront wv: image row y0 + wv
     const int i = lane & 15, g = lane >> 4;
-    float4_t acc[NT];
+    float4_t acc[MT][NT];
 #pragma unroll
-    for (int n = 0; n < NT; ++n) acc[n] = (float4_t){0.f, 0.f, 0.f, 0.f};
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int n = 0; n < NT; ++n) acc[mt][n] = (float4_t){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
         const int ky = tap / 3, kx = tap % 3;
-        const __half* arow = halo + ((ky * (CT + 2)) + wv * 16 + i + kx) * CIN;
+        const __half* arow = halo + (((wv + ky) * (CT + 2)) + i + kx) * CIN;
 #pragma unroll
         for (int cc = 0; cc < CIN / 16; ++cc) {
-            const half4_t a = *reinterpret_cast<const half4_t*>(arow + cc * 16 + 4 * g);
             const int k = tap * CIN + cc * 16 + 4 * g;
+            half4_t b[NT];
 #pragma unroll
-            for (int n = 0; n < NT; ++n) {
-                const half4_t b = *reinterpret_cast<const half4_t*>(wsh + (n * 16 + i) * K + k);
-                acc[n] = mfma16(a, b, acc[n]);
+            for (int n = 0; n < NT; ++n) b[n] = *reinterpret_cast<const half4_t*>(wsh + (n * 16 + i) * K + k);
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                const half4_t a = *reinterpret_cast<const half4_t*>(arow + mt * 16 * CIN + cc * 16 + 4 * g);
+#pragma unroll
+                for (int n = 0; n < NT; ++n) acc[mt][n] = mfma16(a, b[n], acc[mt][n]);
             }
         }
     }
-    // D[row = 4 g + r][col = i]: pixel x0 + 16 wv + 4 g + r, channel 16 n + i
+    // D[row = 4 g + r][col = i] of row tile mt: pixel x0 + 16 mt + 4 g + r of row y, channel 16 n + i
+    const int y = y0 + wv;
+    if (y >= H) return;
 #pragma unroll
     for (int n = 0; n < NT; ++n) {
         const int co = n * 16 + i;
         const float bco = (MODE != 2) ? bias[co] : 0.f;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int x = x0 + wv * 16 + 4 * g + r;
-            if (x >= W) continue;
-            const long long pix = ((long long)f * H + y) * W + x;
-            float v = acc[n][r] + bco;
-            if (MODE == 0) v = fmaxf(v, 0.f);
-            if (MODE == 2 && !(__half2float(Gate[pix * COUT + co]) > 0.f)) v = 0.f;
-            Y[pix * COUT + co] = __float2half(v);
-        }
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int x = x0 + mt * 16 + 4 * g + r;
+                if (x >= W) continue;
+                const long long pix = ((long long)f * H + y) * W + x;
+                float v = acc[mt][n][r] + bco;
+                if (MODE == 0) v = fmaxf(v, 0.f);
+                if (MODE == 2 && !(__half2float(Gate[pix * COUT + co]) > 0.f)) v = 0.f;
+                Y[pix * COUT + co] = __float2half(v);
+            }
     }
 }
 
@@ -232,35 +248,49 @@ __global__ __launch_bounds__(256) void k_cnn_pack(Shape sh, DevState s, float si
     const int i = (int)((pix / sh.cols) % sh.rows), j = (int)(pix % sh.cols);
     const int c = min(load_cnt(s.cnt, pix), 3);
     const double gate = CNN_GATE * (double)sigma_h;
+    double tk[3], sum[3] = {0.0, 0.0, 0.0};
+    int n[3] = {0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) tk[k] = k < c ? s.t[k * P + pix] : 0.0;
+    // each window point is read once and added to every slot it gates in
+    // (per slot, the terms arrive in window order)
+    for (int i2 = max(0, i - 2); i2 <= min(sh.rows - 1, i + 2); ++i2)
+        for (int j2 = max(0, j - 2); j2 <= min(sh.cols - 1, j + 2); ++j2) {
+            const long long pp = (fr * sh.rows + i2) * sh.cols + j2;
+            const int c2 = load_cnt(s.cnt, pp);
+            for (int k2 = 0; k2 < c2; ++k2) {
+                const double tm = s.t[k2 * P + pp];
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+                    if (k < c && fabs(tm - tk[k]) <= gate) {
+                        sum[k] += tm;
+                        ++n[k];
+                    }
+            }
+        }
     float v[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) v[q] = 0.f;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         if (k >= c) continue;
-        const double tk = s.t[k * P + pix];
-        double sum = 0.0;
-        int n = 0;
-        for (int i2 = max(0, i - 2); i2 <= min(sh.rows - 1, i + 2); ++i2)
-            for (int j2 = max(0, j - 2); j2 <= min(sh.cols - 1, j + 2); ++j2) {
-                const long long pp = (fr * sh.rows + i2) * sh.cols + j2;
-                const int c2 = load_cnt(s.cnt, pp);
-                for (int k2 = 0; k2 < c2; ++k2) {
-                    const double tm = s.t[k2 * P + pp];
-                    if (fabs(tm - tk) <= gate) {
-                        sum += tm;
-                        ++n;
-                    }
-                }
-            }
-        const double mean = sum / n;
-        v[4 * k] = fminf(fmaxf((float)((tk - mean) / (double)sigma_h), -8.f), 8.f);
+        const double mean = sum[k] / n[k];
+        v[4 * k] = fminf(fmaxf((float)((tk[k] - mean) / (double)sigma_h), -8.f), 8.f);
         v[4 * k + 1] = log1pf(s.r[k * P + pix]);
         v[4 * k + 2] = 1.f;
-        v[4 * k + 3] = (float)n / 25.f;
+        v[4 * k + 3] = (float)n[k] / 25.f;
     }
+    // the pixel's 16 halves as two 16-byte stores
+    uint4 o[2];
+    uint32_t* ow = reinterpret_cast<uint32_t*>(o);
 #pragma unroll
-    for (int q = 0; q < 16; ++q) x[pix * 16 + q] = __float2half(v[q]);
+    for (int q = 0; q < 8; ++q) {
+        const uint32_t lo = __half_as_ushort(__float2half(v[2 * q]));
+        const uint32_t hi = __half_as_ushort(__float2half(v[2 * q + 1]));
+        ow[q] = lo | (hi << 16);
+    }
+    reinterpret_cast<uint4*>(x + pix * 16)[0] = o[0];
+    reinterpret_cast<uint4*>(x + pix * 16)[1] = o[1];
 }
 
 // Slot k < 3 of a pixel with at most three points moves by sigma_h * y_k.
@@ -413,7 +443,11 @@ __global__ __launch_bounds__(256) void k_cnn_prepare(const float* __restrict__ m
 
 static inline unsigned nb256(long long n) { return (unsigned)((n + 255) / 256); }
 
-static unsigned conv_grid(const Shape& sh) { return (unsigned)(sh.F * sh.rows * ((sh.cols + CT - 1) / CT)); }
+// Forward / backward-data workgroups: 64 columns x CR rows each.
+static unsigned conv_grid(const Shape& sh)
+{
+    return (unsigned)(sh.F * ((sh.rows + CR - 1) / CR) * ((sh.cols + CT - 1) / CT));
+}
 
 unsigned cnn_wgrad_groups(const Shape& sh)
 {
