@@ -369,21 +369,21 @@ class Context:
         return out
 
     def autotune(self, out: Result, frames: int, rows: int, cols: int, hist=None, off=None, ent=None, gain=None,
-                 events=None, frame_shapes=None) -> int:
+                 events=None, frame_shapes=None, irf_class=None) -> int:
         """Time both loop mappings on this input (synchronises) and keep the faster
         for this batch shape; returns 1 (all iterations in one launch) or 0 (per step)."""
-        inp, o = self._io(out, frames, rows, cols, hist, off, ent, gain, events, frame_shapes)
+        inp, o = self._io(out, frames, rows, cols, hist, off, ent, gain, events, frame_shapes, irf_class=irf_class)
         fused = C.c_int32(0)
         self._check(lib().rt3d_autotune(self._h, C.byref(inp), C.byref(o), _stream(), C.byref(fused)))
         return int(fused.value)
 
     def graph(self, out: Result, frames: int, rows: int, cols: int, hist=None, off=None, ent=None, gain=None,
-              events=None, frame_shapes=None) -> "Graph":
+              events=None, frame_shapes=None, irf_class=None) -> "Graph":
         """Record reconstruct_into with these buffers as a replayable graph."""
-        inp, o = self._io(out, frames, rows, cols, hist, off, ent, gain, events, frame_shapes)
+        inp, o = self._io(out, frames, rows, cols, hist, off, ent, gain, events, frame_shapes, irf_class=irf_class)
         h = C.c_void_p()
         self._check(lib().rt3d_graph_create(self._h, C.byref(inp), C.byref(o), C.byref(h)))
-        return Graph(self, h, (out, hist, off, ent, gain, events))
+        return Graph(self, h, (out, hist, off, ent, gain, events, irf_class))
 
     def reconstruct(self, hist, gain=None, max_entries=None, irf_class=None) -> Result:
         """hist: cuda uint16 [frames, rows, cols, bins] (or [rows, cols, bins])."""
