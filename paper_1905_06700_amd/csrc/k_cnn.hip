@@ -16,12 +16,12 @@
 //                    W' the tap-flipped transpose, gated by the ReLU of X
 //   backward weight: dW[tap][ci][co] = sum_p X[p + tap][ci] dY[p][co],
 //                    per-workgroup partials reduced in a fixed order
-// A forward / backward-data workgroup owns 64 consecutive pixels of CR = 4
+// A forward / backward-data workgroup owns 64 consecutive pixels of CR = 8
 // image rows (one row per wavefront, four 16-pixel MFMA row tiles each) and
 // stages the CR + 2 halo rows and the layer's weights in LDS: every weight
 // fragment read from LDS feeds four row tiles, and the staged weights serve
-// 256 pixels.  The weight-gradient workgroup owns 64 pixels of one row at a
-// time.
+// 512 pixels (60 KB of LDS with the 32-channel halo).  The weight-gradient
+// workgroup owns 64 pixels of one row at a time.
 #include "rt3d_dev.h"
 #include "rt3d_cnn.h"
 
@@ -33,7 +33,7 @@ typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
 
 constexpr int CT = 64;   // output pixels per workgroup row (one row segment)
-constexpr int CR = 4;    // image rows per forward / backward-data workgroup (one per wavefront)
+constexpr int CR = 8;    // image rows per forward / backward-data workgroup (one per wavefront)
 
 __device__ __forceinline__ float4_t mfma16(half4_t a, half4_t b, float4_t c)
 {
@@ -65,7 +65,7 @@ __device__ __forceinline__ void stage_halo(const __half* __restrict__ X, int F, 
 // tap = ky * 3 + kx).  MODE 0: + bias, ReLU; 1: + bias (last layer); 2: gate by
 // (G > 0) (backward data, G = the layer input's activation), no bias.
 template <int CIN, int COUT, int MODE>
-__global__ __launch_bounds__(256) void k_conv3x3(const __half* __restrict__ X, const __half* __restrict__ Wt,
+__global__ __launch_bounds__(64 * CR) void k_conv3x3(const __half* __restrict__ X, const __half* __restrict__ Wt,
                                                  const float* __restrict__ bias, const __half* __restrict__ Gate,
                                                  __half* __restrict__ Y, int F, int H, int W)
 {
@@ -472,13 +472,13 @@ hipError_t launch_cnn_forward(const Shape& sh, DevState s, float sigma_h, const 
     if (sh.P == 0) return hipSuccess;
     hipLaunchKernelGGL(k_cnn_pack, dim3(nb256(sh.P)), dim3(256), 0, st, sh, s, sigma_h, b.act[0]);
     const unsigned g = conv_grid(sh);
-    hipLaunchKernelGGL((k_conv3x3<16, 32, 0>), dim3(g), dim3(256), 0, st, b.act[0], w.wt[0], w.bias[0], nullptr,
+    hipLaunchKernelGGL((k_conv3x3<16, 32, 0>), dim3(g), dim3(64 * CR), 0, st, b.act[0], w.wt[0], w.bias[0], nullptr,
                        b.act[1], sh.F, sh.rows, sh.cols);
-    hipLaunchKernelGGL((k_conv3x3<32, 32, 0>), dim3(g), dim3(256), 0, st, b.act[1], w.wt[1], w.bias[1], nullptr,
+    hipLaunchKernelGGL((k_conv3x3<32, 32, 0>), dim3(g), dim3(64 * CR), 0, st, b.act[1], w.wt[1], w.bias[1], nullptr,
                        b.act[2], sh.F, sh.rows, sh.cols);
-    hipLaunchKernelGGL((k_conv3x3<32, 32, 0>), dim3(g), dim3(256), 0, st, b.act[2], w.wt[2], w.bias[2], nullptr,
+    hipLaunchKernelGGL((k_conv3x3<32, 32, 0>), dim3(g), dim3(64 * CR), 0, st, b.act[2], w.wt[2], w.bias[2], nullptr,
                        b.act[3], sh.F, sh.rows, sh.cols);
-    hipLaunchKernelGGL((k_conv3x3<32, 16, 1>), dim3(g), dim3(256), 0, st, b.act[3], w.wt[3], w.bias[3], nullptr,
+    hipLaunchKernelGGL((k_conv3x3<32, 16, 1>), dim3(g), dim3(64 * CR), 0, st, b.act[3], w.wt[3], w.bias[3], nullptr,
                        b.act[4], sh.F, sh.rows, sh.cols);
     return hipGetLastError();
 }
@@ -518,21 +518,21 @@ hipError_t launch_cnn_train_step(const Shape& sh, DevState s, float sigma_h, con
                        sh.F, sh.rows, sh.cols);
     hipLaunchKernelGGL(k_wgrad_reduce, dim3(nb256(9 * 32 * 3 + 3)), dim3(256), 0, st, b.part, b.bpart, (int)gw, 32, 16,
                        32, 3, loss + 1, grad + off3);
-    hipLaunchKernelGGL((k_conv3x3<16, 32, 2>), dim3(g), dim3(256), 0, st, b.dy16, w.wb[3], nullptr, b.act[3], b.dA,
+    hipLaunchKernelGGL((k_conv3x3<16, 32, 2>), dim3(g), dim3(64 * CR), 0, st, b.dy16, w.wb[3], nullptr, b.act[3], b.dA,
                        sh.F, sh.rows, sh.cols);
     // layer 2
     hipLaunchKernelGGL((k_conv3x3_wgrad<32, 32>), dim3(gw), dim3(256), 0, st, b.act[2], b.dA, b.part, b.bpart,
                        sh.F, sh.rows, sh.cols);
     hipLaunchKernelGGL(k_wgrad_reduce, dim3(nb256(9 * 32 * 32 + 32)), dim3(256), 0, st, b.part, b.bpart, (int)gw, 32,
                        32, 32, 32, loss + 1, grad + off2);
-    hipLaunchKernelGGL((k_conv3x3<32, 32, 2>), dim3(g), dim3(256), 0, st, b.dA, w.wb[2], nullptr, b.act[2], b.dB,
+    hipLaunchKernelGGL((k_conv3x3<32, 32, 2>), dim3(g), dim3(64 * CR), 0, st, b.dA, w.wb[2], nullptr, b.act[2], b.dB,
                        sh.F, sh.rows, sh.cols);
     // layer 1
     hipLaunchKernelGGL((k_conv3x3_wgrad<32, 32>), dim3(gw), dim3(256), 0, st, b.act[1], b.dB, b.part, b.bpart,
                        sh.F, sh.rows, sh.cols);
     hipLaunchKernelGGL(k_wgrad_reduce, dim3(nb256(9 * 32 * 32 + 32)), dim3(256), 0, st, b.part, b.bpart, (int)gw, 32,
                        32, 32, 32, loss + 1, grad + off1);
-    hipLaunchKernelGGL((k_conv3x3<32, 32, 2>), dim3(g), dim3(256), 0, st, b.dB, w.wb[1], nullptr, b.act[1], b.dA,
+    hipLaunchKernelGGL((k_conv3x3<32, 32, 2>), dim3(g), dim3(64 * CR), 0, st, b.dB, w.wb[1], nullptr, b.act[1], b.dA,
                        sh.F, sh.rows, sh.cols);
     // layer 0 (16 -> 32): weight gradient only
     hipLaunchKernelGGL((k_conv3x3_wgrad<16, 32>), dim3(gw), dim3(256), 0, st, b.act[0], b.dA, b.part, b.bpart,
