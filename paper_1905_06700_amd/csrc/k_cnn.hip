@@ -238,28 +238,50 @@ __global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ 
 // included) within CNN_GATE sigma_h of t_k; channels 4k .. 4k+3 hold
 // (t_k - their mean) / sigma_h clipped to [-8, 8], log(1 + r_k), 1 and their
 // number / 25.  The other channels are zero.
-__global__ __launch_bounds__(256) void k_cnn_pack(Shape sh, DevState s, float sigma_h, __half* __restrict__ x)
+// Features of 16 x 16 pixel tiles: the tile's depths and counts with a
+// 2-pixel halo (the 5 x 5 windows) staged in LDS, one thread per pixel.
+constexpr int PKT = 16, PKS = PKT + 4;
+__global__ __launch_bounds__(PKT * PKT) void k_cnn_pack(Shape sh, DevState s, float sigma_h, __half* __restrict__ x)
 {
+    __shared__ double tl[KM][PKS * PKS];
+    __shared__ int cl[PKS * PKS];
     const long long P = sh.P;
-    const long long pix = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (pix >= P) return;
-    const int per_frame = sh.rows * sh.cols;
-    const long long fr = pix / per_frame;
-    const int i = (int)((pix / sh.cols) % sh.rows), j = (int)(pix % sh.cols);
-    const int c = min(load_cnt(s.cnt, pix), 3);
+    const int tiles_x = (sh.cols + PKT - 1) / PKT, tiles_y = (sh.rows + PKT - 1) / PKT;
+    const int tpf = tiles_x * tiles_y;
+    const int fr = (int)(blockIdx.x / tpf), tr = (int)(blockIdx.x % tpf);
+    const int i0 = (tr / tiles_x) * PKT, j0 = (tr % tiles_x) * PKT;
+    const long long fbase = (long long)fr * sh.rows * sh.cols;
+    for (int xx = threadIdx.x; xx < PKS * PKS; xx += PKT * PKT) {
+        const int i2 = i0 - 2 + xx / PKS, j2 = j0 - 2 + xx % PKS;
+        int c2 = 0;
+        if (i2 >= 0 && i2 < sh.rows && j2 >= 0 && j2 < sh.cols) {
+            const long long pp = fbase + (long long)i2 * sh.cols + j2;
+            c2 = load_cnt(s.cnt, pp);
+#pragma unroll
+            for (int k = 0; k < KM; ++k) tl[k][xx] = s.t[k * P + pp];
+        }
+        cl[xx] = c2;                                  // 0 outside the image
+    }
+    __syncthreads();
+    const int ty = threadIdx.x / PKT, tx = threadIdx.x % PKT;
+    const int i = i0 + ty, j = j0 + tx;
+    if (i >= sh.rows || j >= sh.cols) return;
+    const long long pix = fbase + (long long)i * sh.cols + j;
+    const int xc = (ty + 2) * PKS + tx + 2;
+    const int c = min(cl[xc], 3);
     const double gate = CNN_GATE * (double)sigma_h;
     double tk[3], sum[3] = {0.0, 0.0, 0.0};
     int n[3] = {0, 0, 0};
 #pragma unroll
-    for (int k = 0; k < 3; ++k) tk[k] = k < c ? s.t[k * P + pix] : 0.0;
+    for (int k = 0; k < 3; ++k) tk[k] = k < c ? tl[k][xc] : 0.0;
     // each window point is read once and added to every slot it gates in
-    // (per slot, the terms arrive in window order)
-    for (int i2 = max(0, i - 2); i2 <= min(sh.rows - 1, i + 2); ++i2)
-        for (int j2 = max(0, j - 2); j2 <= min(sh.cols - 1, j + 2); ++j2) {
-            const long long pp = (fr * sh.rows + i2) * sh.cols + j2;
-            const int c2 = load_cnt(s.cnt, pp);
+    // (per slot, the terms arrive in window order: rows, then columns, then slots)
+    for (int di = -2; di <= 2; ++di)
+        for (int dj = -2; dj <= 2; ++dj) {
+            const int xx = xc + di * PKS + dj;
+            const int c2 = cl[xx];
             for (int k2 = 0; k2 < c2; ++k2) {
-                const double tm = s.t[k2 * P + pp];
+                const double tm = tl[k2][xx];
 #pragma unroll
                 for (int k = 0; k < 3; ++k)
                     if (k < c && fabs(tm - tk[k]) <= gate) {
@@ -470,7 +492,8 @@ hipError_t launch_cnn_forward(const Shape& sh, DevState s, float sigma_h, const 
                               hipStream_t st)
 {
     if (sh.P == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_cnn_pack, dim3(nb256(sh.P)), dim3(256), 0, st, sh, s, sigma_h, b.act[0]);
+    const unsigned tiles = (unsigned)(sh.F * ((sh.rows + PKT - 1) / PKT) * ((sh.cols + PKT - 1) / PKT));
+    hipLaunchKernelGGL(k_cnn_pack, dim3(tiles), dim3(PKT * PKT), 0, st, sh, s, sigma_h, b.act[0]);
     const unsigned g = conv_grid(sh);
     hipLaunchKernelGGL((k_conv3x3<16, 32, 0>), dim3(g), dim3(64 * CR), 0, st, b.act[0], w.wt[0], w.bias[0], nullptr,
                        b.act[1], sh.F, sh.rows, sh.cols);
