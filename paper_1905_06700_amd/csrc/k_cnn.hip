@@ -16,12 +16,12 @@
 //                    W' the tap-flipped transpose, gated by the ReLU of X
 //   backward weight: dW[tap][ci][co] = sum_p X[p + tap][ci] dY[p][co],
 //                    per-workgroup partials reduced in a fixed order
-// A forward / backward-data workgroup owns 64 consecutive pixels of CR = 8
+// A forward / backward-data workgroup owns 64 consecutive pixels of CR = 4
 // image rows (one row per wavefront, four 16-pixel MFMA row tiles each) and
-// stages the CR + 2 halo rows and the layer's weights in LDS: every weight
-// fragment read from LDS feeds four row tiles, and the staged weights serve
-// 512 pixels (60 KB of LDS with the 32-channel halo).  The weight-gradient
-// workgroup owns 64 pixels of one row at a time.
+// stages the CR + 2 halo rows and the layer's weights in LDS, rows padded so
+// that a fragment read meets no bank conflict: every weight fragment read
+// from LDS feeds four row tiles, and the staged weights serve 256 pixels.
+// The weight-gradient workgroup owns 64 pixels of one row at a time.
 #include "rt3d_dev.h"
 #include "rt3d_cnn.h"
 
@@ -33,7 +33,11 @@ typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
 
 constexpr int CT = 64;   // output pixels per workgroup row (one row segment)
-constexpr int CR = 8;    // image rows per forward / backward-data workgroup (one per wavefront)
+constexpr int CR = 4;    // image rows per forward / backward-data workgroup (one per wavefront)
+// LDS row padding (halves) of the forward / backward-data halo pixels and
+// weight rows: strides of 4 mod 32 words put the 16 lanes of a fragment read
+// on distinct banks
+constexpr int CPAD = 4;
 
 __device__ __forceinline__ float4_t mfma16(half4_t a, half4_t b, float4_t c)
 {
@@ -41,8 +45,8 @@ __device__ __forceinline__ float4_t mfma16(half4_t a, half4_t b, float4_t c)
 }
 
 // Stages rows y-1..y+NR-2, columns x0-1..x0+CT of one frame (zero outside
-// the image) into LDS as [NR][CT+2][C] halves.
-template <int C, int NR = 3>
+// the image) into LDS as [NR][CT+2][C + PAD] halves.
+template <int C, int NR = 3, int PAD = 0>
 __device__ __forceinline__ void stage_halo(const __half* __restrict__ X, int F, int H, int W, int f, int y,
                                            int x0, __half* __restrict__ halo)
 {
@@ -56,7 +60,13 @@ __device__ __forceinline__ void stage_halo(const __half* __restrict__ X, int F, 
         uint4 val = make_uint4(0, 0, 0, 0);
         if (yy >= 0 && yy < H && xx >= 0 && xx < W)
             val = reinterpret_cast<const uint4*>(X + (((long long)f * H + yy) * W + xx) * C)[c8];
-        reinterpret_cast<uint4*>(halo)[v] = val;
+        if (PAD == 0) {
+            reinterpret_cast<uint4*>(halo)[v] = val;
+        } else {   // 8-byte aligned rows
+            uint2* d = reinterpret_cast<uint2*>(halo + (ry * (CT + 2) + px) * (C + PAD) + 8 * c8);
+            d[0] = make_uint2(val.x, val.y);
+            d[1] = make_uint2(val.z, val.w);
+        }
     }
     (void)F;
 }
@@ -72,17 +82,23 @@ __global__ __launch_bounds__(64 * CR) void k_conv3x3(const __half* __restrict__ 
     constexpr int K = 9 * CIN;
     constexpr int NT = COUT / 16;
     constexpr int MT = CT / 16;                      // row tiles per wavefront
-    __shared__ __align__(16) __half halo[(CR + 2) * (CT + 2) * CIN];
-    __shared__ __align__(16) __half wsh[COUT * K];
+    constexpr int HS = CIN + CPAD, WS = K + CPAD;    // LDS strides (halves) of a halo pixel, a weight row
+    __shared__ __align__(16) __half halo[(CR + 2) * (CT + 2) * HS];
+    __shared__ __align__(16) __half wsh[COUT * WS];
     const int segs = (W + CT - 1) / CT;
     const int bands = (H + CR - 1) / CR;
     const int seg = blockIdx.x % segs;
     const int y0 = ((blockIdx.x / segs) % bands) * CR;
     const int f = blockIdx.x / (segs * bands);
     const int x0 = seg * CT;
-    stage_halo<CIN, CR + 2>(X, F, H, W, f, y0, x0, halo);
-    for (int v = threadIdx.x; v < COUT * K / 8; v += blockDim.x)
-        reinterpret_cast<uint4*>(wsh)[v] = reinterpret_cast<const uint4*>(Wt)[v];
+    stage_halo<CIN, CR + 2, CPAD>(X, F, H, W, f, y0, x0, halo);
+    for (int v = threadIdx.x; v < COUT * K / 8; v += blockDim.x) {
+        const uint4 val = reinterpret_cast<const uint4*>(Wt)[v];
+        const int row = v / (K / 8), c8 = v % (K / 8);
+        uint2* d = reinterpret_cast<uint2*>(wsh + row * WS + 8 * c8);
+        d[0] = make_uint2(val.x, val.y);
+        d[1] = make_uint2(val.z, val.w);
+    }
     __syncthreads();
 
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;   // wavefront wv: image row y0 + wv
@@ -95,16 +111,16 @@ __global__ __launch_bounds__(64 * CR) void k_conv3x3(const __half* __restrict__ 
 #pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
         const int ky = tap / 3, kx = tap % 3;
-        const __half* arow = halo + (((wv + ky) * (CT + 2)) + i + kx) * CIN;
+        const __half* arow = halo + (((wv + ky) * (CT + 2)) + i + kx) * HS;
 #pragma unroll
         for (int cc = 0; cc < CIN / 16; ++cc) {
             const int k = tap * CIN + cc * 16 + 4 * g;
             half4_t b[NT];
 #pragma unroll
-            for (int n = 0; n < NT; ++n) b[n] = *reinterpret_cast<const half4_t*>(wsh + (n * 16 + i) * K + k);
+            for (int n = 0; n < NT; ++n) b[n] = *reinterpret_cast<const half4_t*>(wsh + (n * 16 + i) * WS + k);
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt) {
-                const half4_t a = *reinterpret_cast<const half4_t*>(arow + mt * 16 * CIN + cc * 16 + 4 * g);
+                const half4_t a = *reinterpret_cast<const half4_t*>(arow + mt * 16 * HS + cc * 16 + 4 * g);
 #pragma unroll
                 for (int n = 0; n < NT; ++n) acc[mt][n] = mfma16(a, b[n], acc[mt][n]);
             }
