@@ -230,6 +230,8 @@ rt3d_status rt3d_create(const double* irf, uint32_t irf_len, int32_t irf_origin,
  * information and so the depth step and its clip, the peak windows and
  * suppression width, the merge distance).  rt3d_input.irf_class names each
  * pixel's class.  Uploads the tables (blocking, on the context's device).
+ * A graph recorded before this call keeps the classes it was recorded with
+ * (its launches cover those classes only; higher numbers count as 0 there).
  * E_INVALID for a rejected IRF or a full context, E_UNSUPPORTED with
  * super-resolution or the learned denoiser, E_DEVICE on a HIP failure. */
 #define RT3D_MAX_IRFS 16
