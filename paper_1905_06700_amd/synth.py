@@ -340,6 +340,24 @@ def persp_scene(scene: int = 0, rows: int = 32, cols: int = 28, T: int = 600, a:
                       r_init=0, k_init=3))
 
 
+def stress_scene(scene: int = 0, side: int = 512, T: int = 2000, signal: float = 1.0, sbr: float = 0.01,
+                 empty: float = 0.15) -> Scene:
+    """Config 5 (stress): the multi-layer geometry of config 4 at side x side x
+    T, mean `signal` photons per pixel at the given SBR (1 photon, SBR 0.01:
+    100 background photons per pixel), and a fraction `empty` of the pixels
+    (a thresholded smooth field) with no surface at all."""
+    base_rng = np.random.default_rng(seed_of(5, 1000 + scene))
+    g = _blur_circular(base_rng.normal(0, 1, (side, side)), 8.0)
+    hole = g > np.quantile(g, 1.0 - empty)
+    sc = layers_scene(scene, rows=side, cols=side, T=T, signal=signal, sbr=sbr, config=5)
+    depth = np.where(hole[None], np.nan, sc.depth)
+    inten = np.where(hole[None], 0.0, sc.intensity)
+    rng = np.random.default_rng(seed_of(5, 2000 + scene))
+    Z = render(rng, sc.irf, T, depth, inten, sc.background)
+    meta = dict(sc.meta, config=5, empty=hole)
+    return Scene(Z, sc.irf, T, depth, inten, sc.background, meta)
+
+
 def random_gain(rng_seed: int, rows: int, cols: int, dead_frac: float = 0.02) -> np.ndarray:
     """Per-pixel detector gain in [0.5, 1.5] with a fraction of dead (0) pixels."""
     rng = np.random.default_rng(rng_seed)
