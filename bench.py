@@ -361,6 +361,53 @@ def observation_model(scenes, F=16, reps=3):
     return res
 
 
+def video_and_scenes(reps=5):
+    """Batched video with scenes in one launch: 64 frames of 32 x 32 x 153 (a
+    disc moving over a plane, 3 signal photons/px at SBR 0.5, zero-padded to
+    1024 bins, the video camera's Gaussian IRF as a second IRF class) with 16
+    head-shaped scenes of 96 x 96 x 1024 (3 signal photons/px, SBR 0.5)."""
+    import numpy as np
+    import torch
+
+    from paper_1905_06700_amd import rt3d, synth
+
+    T = 1024
+    video = [synth.sr_scene(k, rows=32, cols=32, s=1, T=153) for k in range(64)]
+    scenes = [synth.head_scene(700 + k, rows=96, cols=96, T=T, signal=3.0, sbr=0.5) for k in range(16)]
+    frames = []
+    for sc in video:
+        z = np.zeros((32, 32, T), np.uint16)
+        z[..., :sc.T] = sc.Z
+        frames.append(z)
+    frames += [sc.Z for sc in scenes]
+    shapes = [(32, 32)] * 64 + [(96, 96)] * 16
+    cls = torch.from_numpy(np.concatenate([np.full(32 * 32, 1, np.uint8)] * 64 +
+                                          [np.zeros(96 * 96, np.uint8)] * 16)).cuda()
+    Z = torch.cat([torch.from_numpy(z.view(np.int16)).cuda().reshape(-1, T) for z in frames]).contiguous()
+    P = int(Z.shape[0])
+    ctx = rt3d.Context(scenes[0].irf.probs, T, dz=scenes[0].meta["dz"], r_min=0.6, r_init=1, k_init=3)
+    ctx.add_irf(video[0].irf.probs)
+    ctx.workspace(1, 1, P, P * 64)
+    out = ctx.make_output(P)
+
+    def run():
+        ctx.reconstruct_into(out, len(frames), 1, 1, hist=Z, frame_shapes=shapes, irf_class=cls)
+
+    run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        run()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    assert ctx.query().device_error == 0
+    return {"workload": "64 frames of 32x32x153 (padded to 1024 bins, second IRF class) + 16 scenes of "
+                        "96x96x1024 in one call", "call_ms": round(ms, 3),
+            "frames_per_s": round(len(frames) / (ms / 1e3), 1)}
+
+
 def learned_vs_apss(n_train=4, n_eval=4, steps=300, rows=256, cols=256, bins=1024):
     """Learned denoiser against plain APSS on multi-layer scenes: train on the
     GPU (the library's forward/backward kernels), then time and score both on
@@ -589,6 +636,7 @@ def main():
         "single_frame_latency_ms": round(latency_ms, 3), "single_frame_latency_graph_ms": round(latency_graph_ms, 3),
         "small_frames": small_frames(), "uneven_frames": uneven_frames(), "hbm_regime": hbm_regime(scenes),
         "super_resolution": super_resolution(), "observation_model": observation_model(scenes),
+        "video_and_scenes": video_and_scenes(),
         "wall_s": round(wall, 3),
         "roofline": roofline, "kernels": kernels, "cpu_baseline": cpu,
         "learned_vs_apss": None if args.no_learned else learned_vs_apss(),

@@ -1,0 +1,94 @@
+"""Batched video with scenes in one launch (64 frames of 32 x 32 x 153 -- a
+disc moving over a plane, 3 signal photons per pixel at SBR 0.5 -- with 16
+head-shaped scenes of 96 x 96 x 1024): the video frames are zero-padded to the
+context's 1024 bins and their pixels take a second IRF class (the video
+camera's Gaussian; the scenes keep the ex-Gaussian).  A selection of the
+frames must come out of the batch exactly as from calls on each frame alone,
+and frames of both kinds must match the oracle run on them alone."""
+import numpy as np
+import pytest
+
+from gpu_util import to_dev_hist, u32
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import oracle  # noqa: E402
+from paper_1905_06700_amd import rt3d, synth  # noqa: E402
+
+T = 1024
+_B = {}
+
+
+def batch():
+    if not _B:
+        print("[gpu-mixed] generating 64 video frames and 16 scenes", flush=True)
+        video = [synth.sr_scene(k, rows=32, cols=32, s=1, T=153) for k in range(64)]
+        scenes = [synth.head_scene(700 + k, rows=96, cols=96, T=T, signal=3.0, sbr=0.5) for k in range(16)]
+        _B.update(video=video, scenes=scenes)
+    return _B["video"], _B["scenes"]
+
+
+def padded(sc):
+    Z = np.zeros((sc.rows, sc.cols, T), np.uint16)
+    Z[..., :sc.T] = sc.Z
+    return Z
+
+
+def context():
+    video, scenes = batch()
+    m = scenes[0].meta
+    p = dict(dz=m["dz"], p_xy=1.0, r_min=0.6, r_init=1, k_init=3)
+    ctx = rt3d.Context(scenes[0].irf.probs, T, **p)
+    assert ctx.add_irf(video[0].irf.probs) == 1
+    return ctx, p
+
+
+def test_video_and_scenes_in_one_launch():
+    video, scenes = batch()
+    ctx, p = context()
+    frames = [padded(sc) for sc in video] + [sc.Z for sc in scenes]
+    shapes = [(32, 32)] * 64 + [(96, 96)] * 16
+    classes = [np.full(32 * 32, 1, np.uint8)] * 64 + [np.zeros(96 * 96, np.uint8)] * 16
+    Z = torch.cat([to_dev_hist(z).reshape(-1, T) for z in frames]).contiguous()
+    cls = torch.from_numpy(np.concatenate(classes)).cuda()
+    P = int(Z.shape[0])
+    ctx.workspace(1, 1, P, P * 64)
+    out = ctx.make_output(P)
+    print(f"[gpu-mixed] one call: 64 x 32^2 + 16 x 96^2 = {P} pixels", flush=True)
+    ctx.reconstruct_into(out, len(frames), 1, 1, hist=Z, frame_shapes=shapes, irf_class=cls)
+    assert ctx.query().device_error == 0
+    pt = u32(out.pt_off).astype(np.int64)
+    bases = np.concatenate([[0], np.cumsum([r * c for r, c in shapes])])
+    # frames alone (same context, same classes)
+    for f in (0, 1, 37, 63, 64, 79):
+        r, c = shapes[f]
+        zf = to_dev_hist(frames[f])[None]
+        res = ctx.reconstruct(zf, irf_class=torch.from_numpy(classes[f]).cuda())
+        assert ctx.query().device_error == 0
+        po = u32(res.pt_off).astype(np.int64)
+        b = bases[f]
+        np.testing.assert_array_equal(pt[b:b + r * c + 1] - pt[b], po, err_msg=f"frame {f}")
+        k = int(po[-1])
+        assert torch.equal(out.depth[pt[b]:pt[b] + k].cpu(), res.depth[:k].cpu()), f"frame {f} depth"
+        assert torch.equal(out.background[b:b + r * c].cpu(), res.background.cpu()), f"frame {f} background"
+    # the oracle on frames of both kinds
+    for f in (5, 70):
+        r, c = shapes[f]
+        irf = video[0].irf if f < 64 else scenes[0].irf
+        O = oracle.Oracle(oracle.Model(irf.probs, T), oracle.Params(**p))
+        off, ent = oracle.compact(frames[f][None])
+        so = O.reconstruct(off, ent, oracle.State(1, r, c, 4))
+        b = bases[f]
+        cnt = np.diff(pt[b:b + r * c + 1])
+        same = cnt == so.cnt
+        depth = out.depth.cpu().numpy()
+        bad = (~same).reshape(r, c)
+        nb = np.zeros_like(bad)
+        for di in range(-2, 3):
+            for dj in range(-2, 3):
+                nb |= np.roll(np.roll(bad, di, 0), dj, 1)
+        errs = [np.abs(depth[pt[b + q]:pt[b + q] + so.cnt[q]] - so.t[q, :so.cnt[q]]).max()
+                for q in np.nonzero(~nb.reshape(-1) & (so.cnt > 0))[0]]
+        print(f"[gpu-mixed] frame {f}: count agreement {same.mean():.5f}, max depth err {max(errs):.2e}", flush=True)
+        assert same.mean() >= 0.999 and max(errs) <= 1e-3
