@@ -36,6 +36,21 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def host_cpu():
+    """Thread count and CPU model of this host (the oracle's timing context)."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"threads_available": n, "model": model}
+
+
 def scene_params(sc):
     m = sc.meta
     return dict(dz=m["dz"], r_min=m["r_min"], r_init=1, k_init=m["k_init"])
@@ -408,6 +423,69 @@ def video_and_scenes(reps=5):
             "frames_per_s": round(len(frames) / (ms / 1e3), 1)}
 
 
+def execution_time_sweep(reps=5):
+    """Time per frame as the frame grows and as the active bins per pixel grow
+    (Results, execution time of the method: pixel counts 32^2 .. 400^2 at about
+    4 active bins per pixel; 141 x 141 frames with the background raised until
+    2 .. 128 bins per pixel are active).  Head-shaped scenes, T = 4613, the
+    config-2 IRF.  Each point is timed two ways: one frame per call (the
+    paper's per-frame time), and frames batched up to ~16 x 141^2 pixels per
+    call (copies of the one frame), the per-frame cost when the GPU is full."""
+    import numpy as np
+    import torch
+
+    from paper_1905_06700_amd import rt3d, synth
+
+    def point(sc):
+        n = sc.rows * sc.cols
+        F = max(1, min(16, round(16 * ROWS * COLS / n), int(3e9 // (n * BINS * 2))))
+        Z1 = torch.from_numpy(sc.Z.view(np.int16)).cuda()
+        a_est = float((sc.Z != 0).sum()) / n
+        ctx = rt3d.Context(sc.irf.probs, BINS, **scene_params(sc))
+        ctx.workspace(F, sc.rows, sc.cols, int(F * n * (1.5 * a_est + 64)))
+        res = {}
+        for tag, f in (("single", 1), ("batched", F)):
+            Z = Z1[None].expand(f, -1, -1, -1).contiguous()
+            out = ctx.make_output(f * n)
+            for _ in range(2):
+                ctx.reconstruct_into(out, f, sc.rows, sc.cols, hist=Z)
+            torch.cuda.synchronize()
+            ms = []
+            for _ in range(reps):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                ctx.reconstruct_into(out, f, sc.rows, sc.cols, hist=Z)
+                e1.record()
+                torch.cuda.synchronize()
+                ms.append(e0.elapsed_time(e1))
+            st = ctx.query()
+            assert st.device_error == 0
+            res[f"ms_per_frame_{tag}"] = round(float(np.median(ms)) / f, 4)
+            if tag == "batched":
+                res["frames_per_batch"] = f
+            res["active_bins_per_px"] = round(st.entries / (f * n), 2)
+            del Z, out
+        del ctx, Z1
+        torch.cuda.empty_cache()
+        return res
+
+    pixels = []
+    for k, side in enumerate((32, 64, 96, 141, 200, 283, 400)):
+        sc = synth.head_scene(50 + k, rows=side, cols=side, signal=3.0, sbr=2.5)
+        log(f"[bench] sweep: {side}x{side}x{BINS}")
+        pixels.append(dict(pixels=side * side, side=side, **point(sc)))
+    bins = []
+    for k, A in enumerate((2, 4, 8, 16, 32, 64, 128)):
+        sig = min(3.0, 0.75 * A)
+        sc = synth.head_scene(60 + k, signal=sig, sbr=sig / (A - sig))
+        log(f"[bench] sweep: {ROWS}x{COLS}x{BINS}, about {A} active bins/px")
+        bins.append(dict(target_active_bins=A, **point(sc)))
+    return {"workload": "head-shaped scenes, T=4613, config-2 IRF; (a) sides 32..400 at ~3 signal + "
+                        "1.2 background photons/px; (b) 141x141 with background raised to 2..128 "
+                        "active bins/px",
+            "pixels": pixels, "active_bins": bins}
+
+
 def learned_vs_apss(n_train=4, n_eval=4, steps=300, rows=256, cols=256, bins=1024):
     """Learned denoiser against plain APSS on multi-layer scenes: train on the
     GPU (the library's forward/backward kernels), then time and score both on
@@ -479,6 +557,7 @@ def main():
                                                   "taking the most time per call)")
     ap.add_argument("--cpu-frames", type=int, default=2, help="frames the oracle times (0 = skip)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-APSS leg")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the execution-time sweep")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device to device (a plain copy kernel of known size, the "
                          "reference for HBM byte counters)")
@@ -613,15 +692,26 @@ def main():
         O = oracle.Oracle(m, oracle.Params(**scene_params(sc0)))
         nf = args.cpu_frames
         log(f"[bench] timing the FP64 oracle on {nf} full frames (1 thread)")
-        t0 = time.perf_counter()
+        split = {"compaction": 0.0, "init": 0.0, "iterations": 0.0}
         for f in range(nf):
+            t0 = time.perf_counter()
             off, ent = oracle.compact(scenes[f % n_distinct].Z[None])
-            O.reconstruct(off, ent, oracle.State(1, ROWS, COLS, 4))
-        el = time.perf_counter() - t0
+            t1 = time.perf_counter()
+            s = O.init(off, ent, oracle.State(1, ROWS, COLS, 4))
+            t2 = time.perf_counter()
+            for _ in range(20):
+                O.iterate(off, ent, s)
+            t3 = time.perf_counter()
+            split["compaction"] += t1 - t0
+            split["init"] += t2 - t1
+            split["iterations"] += t3 - t2
+        el = sum(split.values())
         cpu = {"value": round(nf / el, 4), "unit": "frames/s", "cores": 1, "kind": "oracle",
-               "sample": f"{nf} full {ROWS}x{COLS}x{BINS} frames (compaction + 20 iterations), "
+               "sample": f"{nf} full {ROWS}x{COLS}x{BINS} frames (compaction + init + 20 iterations), "
                          f"{el:.1f} s on one host thread",
-               "gbin_per_s": round(nf * ROWS * COLS * BINS / el / 1e9, 4)}
+               "gbin_per_s": round(nf * ROWS * COLS * BINS / el / 1e9, 4),
+               "ms_per_frame_split": {k: round(v * 1e3 / nf, 1) for k, v in split.items()},
+               "host": host_cpu()}
 
     res = {
         "metric": METRIC, "value": round(fps, 2), "unit": "frames/s", "n_gpus": 1,
@@ -637,6 +727,7 @@ def main():
         "small_frames": small_frames(), "uneven_frames": uneven_frames(), "hbm_regime": hbm_regime(scenes),
         "super_resolution": super_resolution(), "observation_model": observation_model(scenes),
         "video_and_scenes": video_and_scenes(),
+        "execution_time_sweep": None if args.no_sweep else execution_time_sweep(),
         "wall_s": round(wall, 3),
         "roofline": roofline, "kernels": kernels, "cpu_baseline": cpu,
         "learned_vs_apss": None if args.no_learned else learned_vs_apss(),

@@ -100,8 +100,13 @@ __device__ __forceinline__ int q_range_max(const int* qst, int L, int lo, int hi
 __device__ __forceinline__ int popc_ballot(bool x) { return __popcll(__ballot(x)); }
 
 constexpr int INIT_WAVES = 4;
-constexpr int INIT_ELDS = 640;    // pooled entries a wavefront scores from LDS; more: the HBM path
+constexpr int INIT_ELDS = 640;    // pooled entries a wavefront scores from LDS (held in registers)
 constexpr int INIT_EPL = INIT_ELDS / 64;   // pooled entries per lane
+// Pixels whose pool is larger, up to INIT_WIDE_ELDS entries, are listed and
+// scored from LDS by a second kernel that stages their photons in passes over
+// HBM; larger pools take the HBM path.
+constexpr int INIT_WIDE_ELDS = 2048;
+constexpr unsigned INIT_WIDE_GRID = 1024;
 constexpr int INIT_QLDS = 4096;   // IRF weight tables (ints) up to this size are staged in LDS
 constexpr int INIT_QPAD = 128;    // zero weights on either side of the staged IRF weights
 constexpr int INIT_BWS = 5;       // the LDS path buckets photons by 2^INIT_BWS bins
@@ -117,12 +122,12 @@ static_assert(INIT_NB_LDS * INIT_SB <= 128 * 64, "two blocks per lane");
 // 8-byte LDS words of one wavefront: the HBM path's per-pixel photon ranges,
 // then either the LDS path's sub-block bounds, bucketed photons and bucket
 // ends, or the HBM path's block bounds.
-inline __host__ __device__ size_t init_wave_words(int T, int r_init)
+inline __host__ __device__ size_t init_wave_words(int T, int r_init, size_t elds = INIT_ELDS)
 {
     const size_t nb = (size_t)(T + 63) / 64, nbs = (size_t)(T + INIT_SB - 1) / INIT_SB;
     const size_t side = 2 * (size_t)r_init + 1;
     const size_t nk = ((size_t)T + (1u << INIT_BWS) - 1) >> INIT_BWS;
-    const size_t staged = nbs <= INIT_NB_LDS ? (nbs + 1) / 2 + (size_t)INIT_ELDS / 2 + (nk + 2) / 2 : 0;
+    const size_t staged = nbs <= INIT_NB_LDS ? (nbs + 1) / 2 + elds / 2 + (nk + 2) / 2 : 0;
     return side * side + (nb > staged ? nb : staged);
 }
 
@@ -254,10 +259,13 @@ __device__ __forceinline__ uint32_t score_block(const uint32_t* E, const int* be
 }
 
 // Branch-and-bound search of the LDS path for the pooled photons pe (entries
-// lane + 64 u < total; bucket cursors in bend hold each bucket's start).  The
+// lane + 64 u < total; bucket cursors in bend hold each bucket's start), or,
+// with STAGED, for photons the caller has already bucketed into E (bend then
+// holds the bucket ends) and added to the bounds bnd.  The
 // caller has checked that ntot x the largest weight fits 32 bits and the
 // weights 24 bits: every bound and score is then an exact 32-bit sum of exact
 // 24-bit products.  On return pk holds the accepted peaks.
+template <bool STAGED>
 __device__ __forceinline__ void lds_search(const DevModel& m, const DevParams& p, int T, int L, int o, int nb,
                                            int nbs, int nk, const uint32_t (&pe)[INIT_EPL], int total, long long ntot,
                                            const int* qs, const int* M, uint32_t* bnd, uint32_t* E, int* bend,
@@ -268,7 +276,7 @@ __device__ __forceinline__ void lds_search(const DevModel& m, const DevParams& p
     // counts at the last bucket's last bin
 #pragma unroll
     for (int u = 0; u < INIT_EPL; ++u) {
-        if (lane + 64 * u >= total) break;
+        if (STAGED || lane + 64 * u >= total) break;
         const uint32_t v = pe[u];
         const int t = ent_bin(v);
         const int pos = atomicAdd(&bend[min(t >> INIT_BWS, nk - 1)], 1);
@@ -279,7 +287,7 @@ __device__ __forceinline__ void lds_search(const DevModel& m, const DevParams& p
     // sub-block's first tau, which falls by INIT_SB per sub-block)
 #pragma unroll
     for (int u = 0; u < INIT_EPL; ++u) {
-        if (lane + 64 * u >= total) break;
+        if (STAGED || lane + 64 * u >= total) break;
         const int t = ent_bin(pe[u]), z = ent_cnt(pe[u]);
         if (t >= T) continue;
         const int blo = max(0, t + o - L + 1) / INIT_SB, bhi = min(T - 1, t + o) / INIT_SB;
@@ -451,24 +459,14 @@ __device__ __forceinline__ void lds_search(const DevModel& m, const DevParams& p
     }
 }
 
-// QL: the IRF weight tables are staged in LDS (they fit INIT_QLDS ints).
+// Stages the IRF weights (INIT_QPAD zeros, the L weights, INIT_QPAD zeros)
+// and their sliding maximum over INIT_SB lags in LDS, with the whole
+// workgroup; returns the largest weight (wave-uniform).  Without QL the
+// weights stay in HBM and the result is 0.
 template <bool QL>
-__global__ __launch_bounds__(64 * INIT_WAVES) void k_init(DevModel m, DevParams p, Shape sh,
-                                                          const uint32_t* __restrict__ off,
-                                                          const uint32_t* __restrict__ ent,
-                                                          const float* __restrict__ gain, DevState s)
+__device__ __forceinline__ int stage_weights(const DevModel& m, int* qs, int* M)
 {
-    extern __shared__ unsigned long long smem64[];
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int T = m.T, L = m.L, o = m.o;
-    const int R = p.r_init, side = 2 * R + 1;
-    const size_t ww = init_wave_words(T, R);
-    // IRF weights (INIT_QPAD zeros, the L weights, INIT_QPAD zeros) and their
-    // sliding maximum over INIT_SB lags, staged by the whole workgroup before
-    // any wavefront leaves; the range-maximum table of the HBM path stays in
-    // HBM
-    int* qs = reinterpret_cast<int*>(smem64 + INIT_WAVES * ww);
-    int* M = qs + q_staged_ints(L);
+    const int L = m.L, lane = threadIdx.x & 63;
     if (QL) {
         for (int k = threadIdx.x; k < L + 2 * INIT_QPAD; k += blockDim.x) {
             const int lag = k - INIT_QPAD;
@@ -483,21 +481,50 @@ __global__ __launch_bounds__(64 * INIT_WAVES) void k_init(DevModel m, DevParams 
         }
     }
     __syncthreads();
-    const int* qt = QL ? qs + INIT_QPAD : m.q;
-    const int* qstt = m.qst;
     int qmax = 0;
     if (QL) {
-        for (int k = lane; k < L; k += 64) qmax = max(qmax, qt[k]);
+        for (int k = lane; k < L; k += 64) qmax = max(qmax, qs[INIT_QPAD + k]);
         qmax = (int)wave_max_u32((unsigned)qmax);
     }
+    return qmax;
+}
 
-    const long long P = sh.P, S = sh.S;
-    const long long pix = (long long)xcd_block(blockIdx.x, gridDim.x) * INIT_WAVES + wv;
-    // whole wavefront (pixels of other IRF classes: their own launch); no workgroup barriers below
-    if (pix >= P || !in_class(m, pix)) return;
+// Entry index of pooled photon k: window row r's photons (one CSR range,
+// starting at rs of lane r) take pooled indices from rend - rlen of lane r.
+__device__ __forceinline__ uint32_t pooled_src(uint32_t k, int side, uint32_t rend, uint32_t rlen, uint32_t rs)
+{
+    uint32_t src = 0;
+    for (int r = 0; r < side; ++r) {
+        const uint32_t r0 = (uint32_t)__builtin_amdgcn_readlane((int)(rend - rlen), r);
+        const uint32_t rb = (uint32_t)__builtin_amdgcn_readlane((int)rs, r);
+        if (k >= r0) src = rb + (k - r0);
+    }
+    return src;
+}
+
+// One wavefront's initialisation of pixel pix, with the wavefront's LDS area
+// at wbase.  QL: the weights are staged in LDS (qs, M; qmax their largest).
+// WIDE: the pool may hold up to INIT_WIDE_ELDS photons, staged in passes over
+// HBM; otherwise pools of INIT_ELDS to INIT_WIDE_ELDS photons that the LDS
+// path could score are appended to the list `wide` (count first) when it is
+// given, and left for the wide kernel.
+template <bool QL, bool WIDE>
+__device__ __forceinline__ void init_pixel(const DevModel& m, const DevParams& p, const Shape& sh,
+                                           const uint32_t* __restrict__ off, const uint32_t* __restrict__ ent,
+                                           const float* __restrict__ gain, DevState& s, long long pix,
+                                           unsigned long long* wbase, const int* qs, const int* M, int qmax,
+                                           uint32_t* wide)
+{
+    const int lane = threadIdx.x & 63;
+    const int T = m.T, L = m.L, o = m.o;
+    const int R = p.r_init, side = 2 * R + 1;
+    const int* qt = QL ? qs + INIT_QPAD : m.q;
+    const int* qstt = m.qst;
+    const long long S = sh.S;
     const int nb = (T + 63) >> 6;
-    uint2* lists = reinterpret_cast<uint2*>(smem64 + (size_t)wv * ww);
-    unsigned long long* ub = smem64 + (size_t)wv * ww + side * side;
+    uint2* lists = reinterpret_cast<uint2*>(wbase);
+    unsigned long long* ub = wbase + side * side;
+    (void)qt;
 
     if (lane < KM) {
         s.t[lane * S + pix] = 0.0;
@@ -541,10 +568,37 @@ __global__ __launch_bounds__(64 * INIT_WAVES) void k_init(DevModel m, DevParams 
     // Branch and bound from LDS when the pool fits, the weights are staged,
     // and every score fits 32 bits (checked once the photons are read).
     const int nbs = (T + INIT_SB - 1) / INIT_SB;
-    bool lds = QL && total <= INIT_ELDS && nbs <= INIT_NB_LDS && qmax < (1 << 24);
+    const bool ldsok = QL && nbs <= INIT_NB_LDS && qmax < (1 << 24);
+    if (!WIDE && wide && ldsok && total > INIT_ELDS && total <= INIT_WIDE_ELDS) {
+        if (lane == 0) wide[1 + atomicAdd(&wide[0], 1u)] = (uint32_t)pix;
+        return;
+    }
+    constexpr int ELDS = WIDE ? INIT_WIDE_ELDS : INIT_ELDS;
+    bool lds = ldsok && total <= ELDS;
     uint32_t pe[INIT_EPL];
     long long ntot = 0;
-    if (lds) {
+    const int nk = (T + (1 << INIT_BWS) - 1) >> INIT_BWS;
+    uint32_t* bnd = reinterpret_cast<uint32_t*>(ub);                 // [nbs] sub-block bounds
+    uint32_t* E = reinterpret_cast<uint32_t*>(ub + (nbs + 1) / 2);   // [ELDS] bucketed photons
+    int* bend = reinterpret_cast<int*>(E + ELDS);                   // [nk] bucket ends
+    if (lds && WIDE) {
+        // count the photons per bucket while totalling them (a first pass over HBM)
+        for (int b = lane; b < nbs; b += 64) bnd[b] = 0u;
+        for (int b = lane; b < nk; b += 64) bend[b] = 0;
+        wave_sync();
+        uint32_t nt = 0;                        // at most INIT_WIDE_ELDS x 65535
+        for (int c0 = 0; c0 < total; c0 += 64) {
+            const uint32_t x = pooled_src((uint32_t)(c0 + lane), side, rend, rlen, rs);
+            if (c0 + lane < total) {
+                const uint32_t v = ent[x];
+                if (ent_bin(v) < T) nt += ent_cnt(v);
+                atomicAdd(&bend[min(ent_bin(v) >> INIT_BWS, nk - 1)], 1);
+            }
+        }
+        ntot = wave_sum_u32(nt);
+        lds = (unsigned long long)ntot * (unsigned long long)qmax <= 0xfffffffeull;
+    }
+    if (lds && !WIDE) {
         // read the pooled photons once: entry k of the pool is lane k % 64's
         // pe[k / 64]
         uint32_t src[INIT_EPL];
@@ -569,19 +623,17 @@ __global__ __launch_bounds__(64 * INIT_WAVES) void k_init(DevModel m, DevParams 
         lds = (unsigned long long)ntot * (unsigned long long)qmax <= 0xfffffffeull;
     }
     if (lds) {
-        // Count the photons per 64-bin bucket, scan the counts into bucket
-        // starts, then stage, bound and search them.
-        const int nk = (T + (1 << INIT_BWS) - 1) >> INIT_BWS;
-        uint32_t* bnd = reinterpret_cast<uint32_t*>(ub);                 // [nbs] sub-block bounds
-        uint32_t* E = reinterpret_cast<uint32_t*>(ub + (nbs + 1) / 2);   // [INIT_ELDS] bucketed photons
-        int* bend = reinterpret_cast<int*>(E + INIT_ELDS);              // [nk] bucket ends
-        for (int b = lane; b < nbs; b += 64) bnd[b] = 0u;
-        for (int b = lane; b < nk; b += 64) bend[b] = 0;
-        wave_sync();
+        // Count the photons per 2^INIT_BWS-bin bucket, scan the counts into
+        // bucket starts, then stage, bound and search them.
+        if (!WIDE) {
+            for (int b = lane; b < nbs; b += 64) bnd[b] = 0u;
+            for (int b = lane; b < nk; b += 64) bend[b] = 0;
+            wave_sync();
 #pragma unroll
-        for (int u = 0; u < INIT_EPL; ++u) {
-            if (lane + 64 * u >= total) break;
-            atomicAdd(&bend[min(ent_bin(pe[u]) >> INIT_BWS, nk - 1)], 1);
+            for (int u = 0; u < INIT_EPL; ++u) {
+                if (lane + 64 * u >= total) break;
+                atomicAdd(&bend[min(ent_bin(pe[u]) >> INIT_BWS, nk - 1)], 1);
+            }
         }
         wave_sync();
         // bucket starts (exclusive prefix of the counts); each bucket's cursor
@@ -595,7 +647,28 @@ __global__ __launch_bounds__(64 * INIT_WAVES) void k_init(DevModel m, DevParams 
             carry += (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
         }
         wave_sync();
-        lds_search(m, p, T, L, o, nb, nbs, nk, pe, total, ntot, qs, M, bnd, E, bend, pk);
+        if (WIDE) {
+            // second pass over HBM: stage each photon in its bucket (bins >= T
+            // become zero counts at the last bucket's last bin) and add it to
+            // the bounds of the sub-blocks whose tau can see it
+            for (int c0 = 0; c0 < total; c0 += 64) {
+                const uint32_t x = pooled_src((uint32_t)(c0 + lane), side, rend, rlen, rs);
+                if (c0 + lane < total) {
+                    const uint32_t v = ent[x];
+                    const int t = ent_bin(v), z = ent_cnt(v);
+                    const int pos = atomicAdd(&bend[min(t >> INIT_BWS, nk - 1)], 1);
+                    E[pos] = t < T ? v : ((uint32_t)((nk << INIT_BWS) - 1) << 16);
+                    if (t < T) {
+                        const int blo = max(0, t + o - L + 1) / INIT_SB, bhi = min(T - 1, t + o) / INIT_SB;
+                        const int* Mx = M + (t + o - INIT_SB * bhi);
+                        for (int b = bhi; b >= blo; --b, Mx += INIT_SB)
+                            atomicAdd(&bnd[b], __umul24((unsigned)z, (unsigned)*Mx));
+                    }
+                }
+            }
+            wave_sync();
+        }
+        lds_search<WIDE>(m, p, T, L, o, nb, nbs, nk, pe, total, ntot, qs, M, bnd, E, bend, pk);
     } else {
         // the window's pixels' photon lists (each ascending in t)
         const int npl = side * side;
@@ -784,20 +857,67 @@ __global__ __launch_bounds__(64 * INIT_WAVES) void k_init(DevModel m, DevParams 
                 const int tt = kt[y]; kt[y] = kt[y + 1]; kt[y + 1] = tt;
                 const float rr = kr[y]; kr[y] = kr[y + 1]; kr[y + 1] = rr;
             }
-    int nk = 0;
+    int nkeep = 0;
 #pragma unroll
-    for (int k = 0; k < KM; ++k) nk += kk[k] ? 1 : 0;
-    if (nk > p.k_max) nk = p.k_max;
+    for (int k = 0; k < KM; ++k) nkeep += kk[k] ? 1 : 0;
+    if (nkeep > p.k_max) nkeep = p.k_max;
 #pragma unroll
     for (int k = 0; k < KM; ++k)
-        if (k < nk) {
+        if (k < nkeep) {
             s.t[k * S + pix] = (double)kt[k];
             s.r[k * S + pix] = kr[k];
         }
-    s.cnt[pix] = (uint8_t)nk;
+    s.cnt[pix] = (uint8_t)nkeep;
     const double bown = den > 0 ? (double)num / (double)den : 0.0;
     const double b0 = bown / (double)G;
     s.b[pix] = (float)(b0 > p.b_min ? b0 : p.b_min);
+}
+
+// QL: the IRF weight tables are staged in LDS (they fit INIT_QLDS ints).
+// wide: list of pixels left for k_init_wide (count first), or null.
+template <bool QL>
+__global__ __launch_bounds__(64 * INIT_WAVES) void k_init(DevModel m, DevParams p, Shape sh,
+                                                          const uint32_t* __restrict__ off,
+                                                          const uint32_t* __restrict__ ent,
+                                                          const float* __restrict__ gain, DevState s,
+                                                          uint32_t* wide)
+{
+    extern __shared__ unsigned long long smem64[];
+    const int wv = threadIdx.x >> 6;
+    const size_t ww = init_wave_words(m.T, p.r_init);
+    int* qs = reinterpret_cast<int*>(smem64 + INIT_WAVES * ww);
+    int* M = qs + q_staged_ints(m.L);
+    const int qmax = stage_weights<QL>(m, qs, M);
+    const long long pix = (long long)xcd_block(blockIdx.x, gridDim.x) * INIT_WAVES + wv;
+    // whole wavefront (pixels of other IRF classes: their own launch); no workgroup barriers below
+    if (pix >= sh.P || !in_class(m, pix)) return;
+    init_pixel<QL, false>(m, p, sh, off, ent, gain, s, pix, smem64 + (size_t)wv * ww, qs, M, qmax, wide);
+}
+
+// The pixels k_init listed (pools of INIT_ELDS to INIT_WIDE_ELDS photons),
+// a wavefront each, strided over a fixed grid.
+__global__ __launch_bounds__(64 * INIT_WAVES) void k_init_wide(DevModel m, DevParams p, Shape sh,
+                                                               const uint32_t* __restrict__ off,
+                                                               const uint32_t* __restrict__ ent,
+                                                               const float* __restrict__ gain, DevState s,
+                                                               const uint32_t* __restrict__ wide)
+{
+    extern __shared__ unsigned long long smem64[];
+    const uint32_t n = wide[0];
+    if ((size_t)blockIdx.x * INIT_WAVES >= n) return;                 // whole workgroup
+    const int wv = threadIdx.x >> 6;
+    const size_t ww = init_wave_words(m.T, p.r_init, INIT_WIDE_ELDS);
+    int* qs = reinterpret_cast<int*>(smem64 + INIT_WAVES * ww);
+    int* M = qs + q_staged_ints(m.L);
+    const int qmax = stage_weights<true>(m, qs, M);
+    for (size_t k = (size_t)blockIdx.x * INIT_WAVES + wv; k < n; k += (size_t)gridDim.x * INIT_WAVES)
+        init_pixel<true, true>(m, p, sh, off, ent, gain, s, (long long)wide[1 + k], smem64 + (size_t)wv * ww, qs,
+                               M, qmax, nullptr);
+}
+
+__global__ void k_init_reset(uint32_t* wide)
+{
+    if (threadIdx.x == 0) wide[0] = 0u;
 }
 
 // Initial normals (reading): weighted least-squares plane Z = a + c1 X + c2 Y
@@ -886,25 +1006,34 @@ __global__ __launch_bounds__(256) void k_init_normals(DevParams p, Shape sh, Dev
     }
 }
 
-// LDS bytes of one init workgroup: the wavefronts' areas and the IRF weights.
-size_t init_lds_bytes(int T, int L, int r_init)
+// LDS bytes of one init workgroup (wide: of the wide kernel): the
+// wavefronts' areas and the IRF weights.
+size_t init_lds_bytes(int T, int L, int r_init, bool wide)
 {
     const size_t nq = q_staged_ints(L);
     const size_t qwords = nq <= INIT_QLDS ? (nq + q_window_ints(L) + 1) / 2 : 0;
-    return (INIT_WAVES * init_wave_words(T, r_init) + qwords) * sizeof(unsigned long long);
+    return (INIT_WAVES * init_wave_words(T, r_init, wide ? INIT_WIDE_ELDS : INIT_ELDS) + qwords) *
+           sizeof(unsigned long long);
 }
 
 hipError_t launch_init(const DevModel& m, const DevParams& p, const Shape& sh, const uint32_t* off,
-                       const uint32_t* ent, const float* gain, DevState s, int32_t* err, hipStream_t st)
+                       const uint32_t* ent, const float* gain, DevState s, uint32_t* wide, hipStream_t st)
 {
-    (void)err;
     if (sh.P == 0) return hipSuccess;
-    const size_t lds = init_lds_bytes(m.T, m.L, p.r_init);
+    const size_t lds = init_lds_bytes(m.T, m.L, p.r_init, false);
     const unsigned nblk = (unsigned)((sh.P + INIT_WAVES - 1) / INIT_WAVES);
-    if (q_staged_ints(m.L) <= (size_t)INIT_QLDS)
-        hipLaunchKernelGGL(k_init<true>, dim3(nblk), dim3(64 * INIT_WAVES), lds, st, m, p, sh, off, ent, gain, s);
-    else
-        hipLaunchKernelGGL(k_init<false>, dim3(nblk), dim3(64 * INIT_WAVES), lds, st, m, p, sh, off, ent, gain, s);
+    if (q_staged_ints(m.L) > (size_t)INIT_QLDS) {
+        hipLaunchKernelGGL(k_init<false>, dim3(nblk), dim3(64 * INIT_WAVES), lds, st, m, p, sh, off, ent, gain, s,
+                           nullptr);
+        return hipGetLastError();
+    }
+    const size_t wlds = init_lds_bytes(m.T, m.L, p.r_init, true);
+    if (wlds > 65536 || sh.P >= (1ll << 32)) wide = nullptr;
+    if (wide) hipLaunchKernelGGL(k_init_reset, dim3(1), dim3(64), 0, st, wide);
+    hipLaunchKernelGGL(k_init<true>, dim3(nblk), dim3(64 * INIT_WAVES), lds, st, m, p, sh, off, ent, gain, s, wide);
+    if (wide)
+        hipLaunchKernelGGL(k_init_wide, dim3(std::min(nblk, INIT_WIDE_GRID)), dim3(64 * INIT_WAVES), wlds, st, m, p,
+                           sh, off, ent, gain, s, wide);
     return hipGetLastError();
 }
 

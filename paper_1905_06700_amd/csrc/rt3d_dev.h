@@ -530,8 +530,10 @@ hipError_t launch_compact_events(const uint32_t* pix, const uint16_t* bin, uint6
                                  uint32_t* evoff, uint32_t* scratch, uint32_t* off, uint32_t* ent, uint64_t cap,
                                  uint32_t* counts, uint32_t* partial, int32_t* err, hipStream_t st);
 
+// wide: P + 1 words of workspace (a count and a pixel list) for pools too
+// large for the first kernel's registers, or null (they take the HBM path).
 hipError_t launch_init(const DevModel& m, const DevParams& p, const Shape& sh, const uint32_t* off,
-                       const uint32_t* ent, const float* gain, DevState s, int32_t* err,
+                       const uint32_t* ent, const float* gain, DevState s, uint32_t* wide,
                        hipStream_t st);
 hipError_t launch_init_normals(const DevParams& p, const Shape& sh, DevState s, hipStream_t st);
 

@@ -16,7 +16,7 @@
 #include "rt3d_cnn.h"
 
 namespace rt3d {
-size_t init_lds_bytes(int T, int L, int r_init);
+size_t init_lds_bytes(int T, int L, int r_init, bool wide = false);
 }
 
 using namespace rt3d;
@@ -90,6 +90,7 @@ struct Workspace {
     uint32_t* stage;
     uint32_t* cls_list;                // per-class pixel lists (per-pixel IRFs)
     uint32_t* cls_meta;
+    uint32_t* wide;                    // the init's list of pixels with large pools (count first)
     DevState A, B;
     float* btmp;
     CnnBuffers cnn;
@@ -118,6 +119,7 @@ Workspace carve(uint8_t* base, long long P, long long Ps, uint64_t E, bool with_
     w.stage = (uint32_t*)take(sizeof(uint32_t) * CP_STAGE * std::max<long long>(P, 1));
     w.cls_list = (uint32_t*)take(sizeof(uint32_t) * std::max<long long>(P, 1));
     w.cls_meta = (uint32_t*)take(sizeof(uint32_t) * CLASS_META);
+    w.wide = (uint32_t*)take(sizeof(uint32_t) * (P + 1));
     for (DevState* s : {&w.A, &w.B}) {
         s->t = (double*)take(sizeof(double) * KM * Ps);
         s->r = (float*)take(sizeof(float) * KM * Ps);
@@ -675,12 +677,12 @@ rt3d_status iterate_sr(rt3d_ctx* c, const Shape& lid, const uint32_t* off, const
 // Initialisation under super-resolution: the lidar-grid initialisation into
 // B (slot stride lid.P), spread over the point grid into A, normals there.
 rt3d_status init_sr(rt3d_ctx* c, const Shape& lid, const uint32_t* off, const uint32_t* ent, const float* gain,
-                    DevState A, DevState B, int32_t* err, hipStream_t st)
+                    DevState A, DevState B, uint32_t* wide, hipStream_t st)
 {
     const DevModel m = dev_model(c);
     const DevParams p = dev_params(c);
     const Shape fsh = point_grid(lid, c->p.sr);
-    RT3D_LAUNCH(c, RT3D_KERNEL_INIT, st, launch_init(m, p, lid, off, ent, gain, B, err, st));
+    RT3D_LAUNCH(c, RT3D_KERNEL_INIT, st, launch_init(m, p, lid, off, ent, gain, B, wide, st));
     RT3D_HIP(c, launch_sr_expand(lid, c->p.sr, fsh.P, B, A, st));
     RT3D_LAUNCH(c, RT3D_KERNEL_NORMALS, st, launch_init_normals(p, fsh, A, st));
     return RT3D_OK;
@@ -970,7 +972,7 @@ rt3d_status rt3d_reconstruct(rt3d_ctx* c, const rt3d_input* in, rt3d_output* out
         if (layout != prev_layout)
             return fail(c, RT3D_E_STATE, "warm start: no final state of a batch of these frames in the workspace");
     } else if (c->p.sr > 1) {
-        s = init_sr(c, sh, off, ent, in->gain, w.A, w.B, w.err, st);
+        s = init_sr(c, sh, off, ent, in->gain, w.A, w.B, w.wide, st);
         if (s != RT3D_OK) return s;
     } else {
         for (const Group& g : groups)
@@ -978,7 +980,7 @@ rt3d_status rt3d_reconstruct(rt3d_ctx* c, const rt3d_input* in, rt3d_output* out
                 RT3D_LAUNCH(c, RT3D_KERNEL_INIT, st,
                             launch_init(dev_model(c, k, cls ? cls + g.base : nullptr), dev_params(c, k), g.sh,
                                         off + g.base, ent, in->gain ? in->gain + g.base : nullptr,
-                                        state_at(w.A, g.base), w.err, st));
+                                        state_at(w.A, g.base), w.wide, st));
         for (const Group& g : groups)
             RT3D_LAUNCH(c, RT3D_KERNEL_NORMALS, st, launch_init_normals(p, g.sh, state_at(w.A, g.base), st));
     }
@@ -1191,7 +1193,7 @@ static rt3d_status debug_step_sr(rt3d_ctx* c, int32_t step, const uint32_t* off,
     }
     switch (step) {
     case RT3D_STEP_INIT:
-        return init_sr(c, lid, off, ent, gain, O, w.B, w.err, st);
+        return init_sr(c, lid, off, ent, gain, O, w.B, w.wide, st);
     case RT3D_STEP_APSS:
         RT3D_HIP(c, launch_apss(m, p, fsh, dev_state(in), O, -1, st));
         return RT3D_OK;
@@ -1249,11 +1251,16 @@ rt3d_status rt3d_debug_step(rt3d_ctx* c, int32_t step, const uint32_t* off, cons
         return debug_step_sr(c, step, off, ent, gain, in, out, st);
     }
     switch (step) {
-    case RT3D_STEP_INIT:
+    case RT3D_STEP_INIT: {
+        // the pixel list of large pools lives in the bound workspace; without
+        // one that covers the frames those pools take the HBM path
+        uint32_t* wide = nullptr;
+        if (c->ws && c->ws_P >= sh.P) wide = carve_ctx(c, c->ws, c->ws_P, c->ws_E, c->ws_rows, c->ws_cols).wide;
         for (int k = 0; k < nc; ++k)
-            RT3D_HIP(c, launch_init(dev_model(c, k, cls), dev_params(c, k), sh, off, ent, gain, O, nullptr, st));
+            RT3D_HIP(c, launch_init(dev_model(c, k, cls), dev_params(c, k), sh, off, ent, gain, O, wide, st));
         RT3D_HIP(c, launch_init_normals(p, sh, O, st));
         return RT3D_OK;
+    }
     case RT3D_STEP_APSS:
         RT3D_HIP(c, launch_apss(m, p, sh, dev_state(in), O, -1, st));
         return RT3D_OK;

@@ -437,7 +437,7 @@ class Context:
         cin = st_in.c() if st_in is not None else None
         cout = out.c()
         sr = self.params.sr
-        if step in (STEP_BFILTER, STEP_ITERATION) or (sr > 1 and step == STEP_INIT):
+        if step in (STEP_BFILTER, STEP_ITERATION, STEP_INIT):
             P = F * R * Cc // (sr * sr)          # the workspace is sized in lidar pixels
             if self._ws_shape is None or self._ws_shape[0] * self._ws_shape[1] * self._ws_shape[2] < P:
                 self.workspace(1, 1, P, 1)

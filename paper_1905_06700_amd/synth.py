@@ -358,6 +358,22 @@ def stress_scene(scene: int = 0, side: int = 512, T: int = 2000, signal: float =
     return Scene(Z, sc.irf, T, depth, inten, sc.background, meta)
 
 
+def ramp_background_scene(scene: int = 0, rows: int = 36, cols: int = 44, T: int = 4613, signal: float = 5.0,
+                          bkg_lo: float = 20.0, bkg_hi: float = 330.0) -> Scene:
+    """Config-2 geometry and IRF with the background photons per pixel rising
+    linearly across the columns from bkg_lo to bkg_hi (the execution-time
+    sweep's range of active bins per pixel in one frame).  The per-pixel
+    background level is returned as the `background` array; every pixel has
+    unit gain."""
+    sc = head_scene(scene, rows=rows, cols=cols, T=T, signal=signal)
+    bph = np.broadcast_to(np.linspace(bkg_lo, bkg_hi, cols)[None, :], (rows, cols))
+    g = bph / bph.max()
+    rng = np.random.default_rng(seed_of(2, 3000 + scene))
+    # render's gain scales signal and background alike: divide the signal back out
+    Z = render(rng, sc.irf, T, sc.depth, sc.intensity / g[None], bph.max() / T, gain=g)
+    return Scene(Z, sc.irf, T, sc.depth, sc.intensity, bph / T, dict(sc.meta))
+
+
 def random_gain(rng_seed: int, rows: int, cols: int, dead_frac: float = 0.02) -> np.ndarray:
     """Per-pixel detector gain in [0.5, 1.5] with a fraction of dead (0) pixels."""
     rng = np.random.default_rng(rng_seed)
