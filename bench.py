@@ -264,6 +264,70 @@ def hbm_regime(scenes, F=64):
     return res
 
 
+def stress_batch(reps=3):
+    """The stress configuration: one uneven batch of 8 multi-layer scenes with
+    sides 128 .. 512 pixels x 2000 bins (1 signal photon per pixel at SBR
+    0.01, ~98 active bins per pixel, 15% of the pixels empty), 857 k pixels
+    and 3.4 GB of histograms per call, a working set well past the 256 MB
+    MALL.  Call time, and per kernel group the average launch time and the
+    fraction of the 8 TB/s HBM peak its algorithmic bytes make."""
+    import numpy as np
+    import torch
+
+    from paper_1905_06700_amd import rt3d, synth
+
+    sides = (128, 160, 192, 256, 320, 384, 448, 512)
+    parts, sc0 = [], None
+    for k, n in enumerate(sides):
+        log(f"[bench] stress: generating {n}x{n}x2000")
+        sc = synth.stress_scene(k, side=n)
+        sc0 = sc0 or sc
+        parts.append(torch.from_numpy(sc.Z.view(np.int16).reshape(-1, sc.T)).cuda())
+        del sc
+    Z = torch.cat(parts).contiguous()
+    del parts
+    P, T = int(Z.shape[0]), int(Z.shape[1])
+    shapes = [(n, n) for n in sides]
+    m = sc0.meta
+    ctx = rt3d.Context(sc0.irf.probs, T, dz=m["dz"], p_xy=m["p_xy"], r_min=m["r_min"], r_init=m["r_init"],
+                       k_init=m["k_init"])
+    ctx.workspace(1, 1, P, P * 130)
+    out = ctx.make_output(P)
+    run = lambda: ctx.reconstruct_into(out, len(sides), 1, 1, hist=Z, frame_shapes=shapes)
+    run()
+    torch.cuda.synchronize()
+    st = ctx.query()
+    assert st.device_error == 0
+    E, pts = int(st.entries), int(out.pt_off[-1].item())
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        run()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    res = {"workload": f"8 scenes {sides[0]}^2..{sides[-1]}^2 x {T} bins in one call ({P} pixels, "
+                       f"{E / P:.1f} active bins/px, 1 signal photon/px, SBR 0.01)",
+           "call_ms": round(ms, 3), "frames_per_s": round(len(sides) / (ms / 1e3), 1),
+           "gbin_per_s": round(P * T / (ms / 1e3) / 1e9, 1), "points": pts}
+    for g in GROUPS:
+        ctx.profile(g)
+        run()
+        torch.cuda.synchronize()
+        gms, nl = ctx.profile_read()
+        ctx.profile(None)
+        nl = max(int(nl), 1)
+        avg = gms / nl
+        r = {"ms_per_call": round(gms, 3), "launches": nl, "avg_launch_us": round(avg * 1e3, 1)}
+        if g != "init":
+            ab = algorithmic_bytes(g, 1, P, T, E, pts)
+            r["frac_hbm"] = round(ab / (avg / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+        res[g] = r
+    del Z, out, ctx
+    torch.cuda.empty_cache()
+    return res
+
+
 def super_resolution(reps=5):
     """The paper's array-video mode: 32 x 32 x 153 lidar frames (a moving disc
     over a tilted plane, 3 signal photons/px at SBR 0.5) reconstructed on a
@@ -558,6 +622,8 @@ def main():
     ap.add_argument("--cpu-frames", type=int, default=2, help="frames the oracle times (0 = skip)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-APSS leg")
     ap.add_argument("--no-sweep", action="store_true", help="skip the execution-time sweep")
+    ap.add_argument("--stress", action="store_true", help="add the stress batch (8 scenes up to 512^2 x 2000; "
+                                                          "about a minute of scene generation)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device to device (a plain copy kernel of known size, the "
                          "reference for HBM byte counters)")
@@ -728,6 +794,7 @@ def main():
         "super_resolution": super_resolution(), "observation_model": observation_model(scenes),
         "video_and_scenes": video_and_scenes(),
         "execution_time_sweep": None if args.no_sweep else execution_time_sweep(),
+        "stress_batch": stress_batch() if args.stress else None,
         "wall_s": round(wall, 3),
         "roofline": roofline, "kernels": kernels, "cpu_baseline": cpu,
         "learned_vs_apss": None if args.no_learned else learned_vs_apss(),

@@ -587,13 +587,21 @@ __device__ __forceinline__ void init_pixel(const DevModel& m, const DevParams& p
         for (int b = lane; b < nk; b += 64) bend[b] = 0;
         wave_sync();
         uint32_t nt = 0;                        // at most INIT_WIDE_ELDS x 65535
-        for (int c0 = 0; c0 < total; c0 += 64) {
-            const uint32_t x = pooled_src((uint32_t)(c0 + lane), side, rend, rlen, rs);
-            if (c0 + lane < total) {
-                const uint32_t v = ent[x];
-                if (ent_bin(v) < T) nt += ent_cnt(v);
-                atomicAdd(&bend[min(ent_bin(v) >> INIT_BWS, nk - 1)], 1);
+        // four 64-entry chunks per round, their loads in flight together
+        for (int c0 = 0; c0 < total; c0 += 256) {
+            uint32_t v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k = c0 + 64 * u + lane;
+                const uint32_t x = pooled_src((uint32_t)k, side, rend, rlen, rs);
+                v[u] = k < total ? ent[x] : 0u;
             }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (c0 + 64 * u + lane < total) {
+                    if (ent_bin(v[u]) < T) nt += ent_cnt(v[u]);
+                    atomicAdd(&bend[min(ent_bin(v[u]) >> INIT_BWS, nk - 1)], 1);
+                }
         }
         ntot = wave_sum_u32(nt);
         lds = (unsigned long long)ntot * (unsigned long long)qmax <= 0xfffffffeull;
@@ -651,10 +659,18 @@ __device__ __forceinline__ void init_pixel(const DevModel& m, const DevParams& p
             // second pass over HBM: stage each photon in its bucket (bins >= T
             // become zero counts at the last bucket's last bin) and add it to
             // the bounds of the sub-blocks whose tau can see it
-            for (int c0 = 0; c0 < total; c0 += 64) {
-                const uint32_t x = pooled_src((uint32_t)(c0 + lane), side, rend, rlen, rs);
-                if (c0 + lane < total) {
-                    const uint32_t v = ent[x];
+            for (int c0 = 0; c0 < total; c0 += 256) {
+                uint32_t vv[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int k = c0 + 64 * u + lane;
+                    const uint32_t x = pooled_src((uint32_t)k, side, rend, rlen, rs);
+                    vv[u] = k < total ? ent[x] : 0u;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (c0 + 64 * u + lane >= total) continue;
+                    const uint32_t v = vv[u];
                     const int t = ent_bin(v), z = ent_cnt(v);
                     const int pos = atomicAdd(&bend[min(t >> INIT_BWS, nk - 1)], 1);
                     E[pos] = t < T ? v : ((uint32_t)((nk << INIT_BWS) - 1) << 16);
