@@ -105,7 +105,7 @@ constexpr int INIT_EPL = INIT_ELDS / 64;   // pooled entries per lane
 // Pixels whose pool is larger, up to INIT_WIDE_ELDS entries, are listed and
 // scored from LDS by a second kernel that stages their photons in passes over
 // HBM; larger pools take the HBM path.
-constexpr int INIT_WIDE_ELDS = 2048;
+constexpr int INIT_WIDE_ELDS = 1536;
 constexpr unsigned INIT_WIDE_GRID = 1024;
 constexpr int INIT_QLDS = 4096;   // IRF weight tables (ints) up to this size are staged in LDS
 constexpr int INIT_QPAD = 128;    // zero weights on either side of the staged IRF weights
