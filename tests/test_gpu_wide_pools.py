@@ -114,3 +114,29 @@ def test_wide_pools_batch_equals_frames_alone():
         np.testing.assert_array_equal(pt[b:b + n + 1] - pt[b], po, err_msg=f"frame {f}")
         assert torch.equal(out.depth[pt[b]:pt[b + n]].cpu(), dep[:int(po[-1])]), f"frame {f} depth"
         assert torch.equal(out.background[b:b + n].cpu(), bg), f"frame {f} background"
+
+
+def test_wide_pools_with_irf_classes_match_oracle():
+    """Two IRF classes in 4 x 4 pixel blocks: one init launch per class, each
+    listing only its own class's large pools for the wide kernel."""
+    sc = scene()
+    p = params(sc)
+    irfs = [sc.irf, synth.gaussian_irf(2.0, 12)]
+    i, j = np.mgrid[0:sc.rows, 0:sc.cols]
+    cls = (((i // 4) + (j // 4)) % 2).astype(np.uint8).reshape(-1)
+    models = [oracle.Model(f.probs, sc.T) for f in irfs]
+    O = oracle.Oracle(models[0], oracle.Params(**p), irf_models=models[1:], irf_class=cls)
+    O._keep = models
+    ctx = rt3d.Context(irfs[0].probs, sc.T, **p)
+    ctx.add_irf(irfs[1].probs)
+    off, ent = oracle.compact(sc.Z[None])
+    so = O.init(off, ent, oracle.State(1, sc.rows, sc.cols, 4))
+    ctx.debug_irf_class(torch.from_numpy(cls).cuda())
+    print("[gpu-wide] init with two IRF classes", flush=True)
+    d = ctx.step(rt3d.STEP_INIT, None, to_dev_u32(off), to_dev_u32(ent), shape=(1, sc.rows, sc.cols))
+    assert ctx.query().device_error == 0
+    sg = device_to_oracle(d, 4)
+    np.testing.assert_array_equal(sg.cnt, so.cnt)
+    np.testing.assert_array_equal(sg.t, so.t)
+    np.testing.assert_allclose(sg.r, so.r, rtol=2e-6, atol=1e-6)
+    np.testing.assert_allclose(sg.b, so.b, rtol=2e-6, atol=1e-12)
