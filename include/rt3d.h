@@ -117,6 +117,13 @@ typedef struct rt3d_params {
                           * lateral pixel footprint (range x persp) of the scene.  E_UNSUPPORTED
                           * when that window's tile does not fit the APSS kernel's LDS (R > 5);
                           * per-step kernels only (fused_loop ignored). */
+    int32_t  ilp_box;    /* divisor of the intensity low-pass (Results, "Reconstruction algorithm",
+                          * intensity update: only points of one surface are correlated).  0 (default):
+                          * r_new = (r + sum of the neighbours found) / (1 + their number), the mean
+                          * over the point's surface, a pixel without a point of that surface taking
+                          * no part; 1: divided by 1 + the number of surrounding pixels inside the
+                          * image (a 3 x 3 box in which a missing neighbour counts as zero intensity,
+                          * which attenuates isolated points).  E_INVALID for other values. */
 } rt3d_params;
 
 /* Input kinds. */

@@ -52,7 +52,7 @@ class _Params(C.Structure):
                 ("d_merge", C.c_double), ("sigma_b", C.c_double), ("b_min", C.c_double),
                 ("sbr_guess", C.c_double), ("r_init", C.c_int), ("n_min", C.c_int),
                 ("kappa", C.c_double), ("w_nms", C.c_int), ("m_min", C.c_int),
-                ("use_apss", C.c_int), ("persp", C.c_double)]
+                ("use_apss", C.c_int), ("persp", C.c_double), ("ilp_box", C.c_int)]
 
 
 @dataclass
@@ -81,6 +81,7 @@ class Params:
     m_min: int = 3
     use_apss: int = 1
     persp: float = 0.0
+    ilp_box: int = 0
 
     def c(self) -> _Params:
         return _Params(**{f.name: getattr(self, f.name) for f in fields(self)})

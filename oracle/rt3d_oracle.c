@@ -666,8 +666,9 @@ void or_init_normals(const or_params* p, int F, int rows, int cols,
 /* ------------------------------------------------------------------------ */
 
 /* Gradient step on t (Reconstruction algorithm, depth update).  Reading of
- * the step size: Fisher scaling sigma_h^2/(g r), i.e.
- *   t_n <- clamp(t_n - beta_t sigma_h^2 [S'(t_n) + sum z h'(t - t_n)/lambda_t],
+ * the step size: the inverse of the expected curvature g r I_h, I_h the
+ * IRF's shift Fisher information per photon (a 1/Lipschitz step), i.e.
+ *   t_n <- clamp(t_n - (beta_t / I_h) [S'(t_n) + sum z h'(t - t_n)/lambda_t],
  * with the move clipped to |dmax| and t kept in [0, T-1].  All points of a
  * pixel use lambda from before the step (Jacobi).  Dead pixels and points of
  * zero intensity do not move. */
@@ -888,15 +889,18 @@ void or_intensity_step(const or_model* m, const or_params* p, int64_t npix,
 }
 
 /* Intensity denoiser (Reconstruction algorithm, intensity update): a low-pass
- * over nearest neighbours in the manifold the points define.  Reading: for
- * each of the 8 surrounding pixels the single point nearest in world space
- * (lowest slot on ties) is a neighbour if closer than h_int.  The new intensity
- * is a box mean over the point's 3 x 3 pixel neighbourhood on the manifold:
- * (r_n + sum of neighbour intensities) / (1 + number of surrounding pixels
- * inside the image), so a surrounding pixel with no point on the same surface
- * counts as zero intensity and isolated points are attenuated (Jacobi).
- * Points then below r_min are removed (minimum admissible intensity) and the
- * slots are compacted in depth order. */
+ * over nearest neighbours in the manifold the points define, which only
+ * correlates points lying on one surface.  Reading: for each of the 8
+ * surrounding pixels the single point nearest in world space (lowest slot on
+ * ties) is a neighbour if closer than h_int.  The new intensity is the mean
+ * over the point and its neighbours on its surface,
+ * (r_n + sum of neighbour intensities) / (1 + number of neighbours found)
+ * (Jacobi), so a pixel holding no point of that surface takes no part in the
+ * mean.  Option ilp_box = 1 divides by 1 + the number of surrounding pixels
+ * inside the image instead (a 3 x 3 box in which a missing neighbour counts
+ * as zero intensity, which attenuates isolated points).  Points then below
+ * r_min are removed (minimum admissible intensity) and the slots are
+ * compacted in depth order. */
 void or_intensity_filter(const or_params* p, int F, int rows, int cols,
                          double* t, double* r, double* n, int* cnt)
 {
@@ -926,7 +930,7 @@ void or_intensity_filter(const or_params* p, int F, int rows, int cols,
                     }
                     if (best >= 0 && bd < hi2) { sum += r[pp * K + best]; ++deg; }
                 }
-            rn[q] = sum / (1 + nside);
+            rn[q] = sum / (1 + (p->ilp_box ? nside : deg));
         }
     }
     for (int64_t pix = 0; pix < npix; ++pix) {

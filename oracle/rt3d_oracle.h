@@ -57,6 +57,9 @@ typedef struct or_params {
     int    use_apss;    /* 1 = APSS depth denoiser, 0 = none */
     double persp;       /* 0: orthographic map f; > 0: pinhole camera, tangent of one pixel's angle,
                            depth = range along the pixel's ray (see rel() in the source) */
+    int    ilp_box;     /* intensity low-pass divisor: 0 = 1 + same-surface neighbours found
+                           (the mean over the point's surface), 1 = 1 + surrounding pixels inside
+                           the image (a 3 x 3 box in which a missing neighbour counts as zero) */
 } or_params;
 
 typedef struct or_model or_model;

@@ -2,13 +2,15 @@
 // filter, state copies and output packing.
 //
 // Intensity (Results, "Reconstruction algorithm", intensity update: a
-// low-pass over nearest neighbours on the manifold the points define, then
-// removal of points below the minimum admissible intensity).  Reading: for
-// each of the 8 surrounding pixels inside the image the single point nearest
-// in world space (lowest slot on ties) is a neighbour when closer than h_int;
-// r_new = (r + sum of neighbour r) / (1 + number of surrounding pixels in the
-// image), Jacobi; then points with r_new < r_min are removed and the slots
-// compacted in depth order.
+// low-pass over nearest neighbours on the manifold the points define, which
+// correlates only points of one surface, then removal of points below the
+// minimum admissible intensity).  Reading: for each of the 8 surrounding
+// pixels inside the image the single point nearest in world space (lowest
+// slot on ties) is a neighbour when closer than h_int; r_new = (r + sum of
+// neighbour r) / (1 + number of neighbours found), Jacobi (p.ilp_box = 1:
+// divided by 1 + the number of surrounding pixels in the image instead); then
+// points with r_new < r_min are removed and the slots compacted in depth
+// order.
 //
 // Background (intensity update's sibling: an FFT-based image denoiser for
 // arrays, the identity for bistatic scanners).  Reading: circular
@@ -78,6 +80,7 @@ __global__ __launch_bounds__(IFT * IFT) void k_ifilter_tile(DevParams p, Tiles t
     for (int k = 0; k < c; ++k) {
         const double tq = tl[k][xc];
         float sum = rl[k][xc];
+        int deg = 0;
         for (int di = -1; di <= 1; ++di) {
             const float dy = (float)di * pxy;
             for (int dj = -1; dj <= 1; ++dj) {
@@ -106,10 +109,13 @@ __global__ __launch_bounds__(IFT * IFT) void k_ifilter_tile(DevParams p, Tiles t
                         bd = d2;
                     }
                 }
-                if (best >= 0 && bd < hi2) sum += rl[best][x];
+                if (best >= 0 && bd < hi2) {
+                    sum += rl[best][x];
+                    ++deg;
+                }
             }
         }
-        const float rn = sum / (float)(1 + nside);
+        const float rn = sum / (float)(1 + (p.ilp_box ? nside : deg));
         if (rn < rmin) continue;
         out.t[nk * S + pix] = tq;
         out.r[nk * S + pix] = rn;

@@ -231,6 +231,7 @@ __device__ __forceinline__ void ifilter_1(const DevParams& p, const Shape& sh, c
     for (int k = 0; k < c; ++k) {
         const double tq = in.t[k * S + pix];
         float sum = in.r[k * S + pix];
+        int deg = 0;
         for (int di = -1; di <= 1; ++di) {
             const float dy = (float)di * pxy;
             for (int dj = -1; dj <= 1; ++dj) {
@@ -250,10 +251,13 @@ __device__ __forceinline__ void ifilter_1(const DevParams& p, const Shape& sh, c
                         bd = d2;
                     }
                 }
-                if (best >= 0 && bd < hi2) sum += in.r[best * S + pp];
+                if (best >= 0 && bd < hi2) {
+                    sum += in.r[best * S + pp];
+                    ++deg;
+                }
             }
         }
-        const float rn = sum / (float)(1 + nside);
+        const float rn = sum / (float)(1 + (p.ilp_box ? nside : deg));
         if (rn < rmin) continue;
         out.t[nk * S + pix] = tq;
         out.r[nk * S + pix] = rn;

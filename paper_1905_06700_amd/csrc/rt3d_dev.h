@@ -55,6 +55,7 @@ __device__ __forceinline__ bool in_class(const DevModel& m, long long pix)
 // Parameters as the kernels use them.
 struct DevParams {
     int    k_max, k_init, r_init, n_min, m_min, apss_R;
+    int    ilp_box;   // intensity low-pass divisor: 0 = 1 + neighbours found, 1 = 1 + surrounding pixels
     double p_xy, dz, h_apss, h_int;
     double beta_t, dmax, beta_r, beta_b, r_min, d_merge, b_min, kappa;
     double persp;   // 0: orthographic map f; > 0: pinhole camera (see ray_dir)

@@ -449,6 +449,7 @@ DevParams dev_params(const rt3d_ctx* c, int k = 0)
     d.n_min = p.n_min;
     d.m_min = p.m_min;
     d.apss_R = c->apss_R;
+    d.ilp_box = p.ilp_box;
     d.p_xy = p.p_xy;
     d.dz = p.dz;
     d.h_apss = p.h_apss;
@@ -480,6 +481,7 @@ rt3d_status check_params(const rt3d_params* p, uint32_t bins, std::string& why)
     if (!(p->sbr_guess > 0)) { why = "sbr_guess must be > 0"; return RT3D_E_INVALID; }
     if (p->r_init < 0 || p->r_init > 8) { why = "r_init outside 0..8"; return RT3D_E_INVALID; }
     if (p->fused_loop < -1 || p->fused_loop > 1) { why = "fused_loop must be -1, 0 or 1"; return RT3D_E_INVALID; }
+    if (p->ilp_box != 0 && p->ilp_box != 1) { why = "ilp_box must be 0 or 1"; return RT3D_E_INVALID; }
     if (p->sr < 1 || p->sr > SR_MAX) { why = "sr outside 1..4"; return RT3D_E_INVALID; }
     if (p->sr > 1 && p->denoiser == RT3D_DENOISE_CNN) {
         why = "super-resolution with the learned denoiser"; return RT3D_E_UNSUPPORTED;
@@ -721,6 +723,7 @@ void rt3d_params_default(rt3d_params* p)
     p->denoiser = RT3D_DENOISE_APSS;
     p->fused_loop = -1;
     p->sr = 1;
+    p->ilp_box = 0;
 }
 
 rt3d_status rt3d_create(const double* irf, uint32_t irf_len, int32_t irf_origin, uint32_t bins,

@@ -57,7 +57,7 @@ class Params(C.Structure):
                 ("b_min", C.c_double), ("sbr_guess", C.c_double), ("r_init", C.c_int32),
                 ("n_min", C.c_int32), ("kappa", C.c_double), ("w_nms", C.c_int32),
                 ("m_min", C.c_int32), ("denoiser", C.c_int32), ("fused_loop", C.c_int32),
-                ("sr", C.c_int32), ("persp", C.c_double)]
+                ("sr", C.c_int32), ("persp", C.c_double), ("ilp_box", C.c_int32)]
 
 
 class Input(C.Structure):

@@ -102,29 +102,197 @@ def test_lmf_noiseless_template_recovers_depth(oracle_lib):
 
 
 def test_lmf_argmax_matches_exhaustive_float_search(oracle_lib):
-    """Peak = argmax over tau of sum z log(h(t - tau) + eps), by brute force."""
+    """Peak = argmax over tau of sum z log(h(t - tau) + eps) - log eps, by
+    brute force in float64.  The oracle scores with weights rounded to 16
+    fractional bits (exact integer sums), so each score is off by at most
+    0.5 sum(z) / 2^16; wherever the float top-two margin exceeds twice that
+    bound, the integer argmax must be the float argmax."""
     rng = np.random.default_rng(5)
     T = 150
     m = gauss_model(oracle_lib, T)
-    hbar = m.h(np.arange(-9, 10))[0]
     eps = 1.0 / T
-    for trial in range(20):
+    checked = 0
+    for trial in range(40):
         Z = rng.poisson(0.05, (1, 1, T)).astype(np.uint16)
         d = rng.integers(10, 140)
-        Z[0, 0, d - 2:d + 3] += rng.poisson(3.0, 5).astype(np.uint16)
+        Z[0, 0, d - 2:d + 3] += rng.poisson(3.0 if trial % 2 else 1.0, 5).astype(np.uint16)
         off, ent = oracle_lib.compact(Z)
         z = Z[0, 0].astype(float)
-        score = np.array([sum(z[t] * (np.log(m.h(t - tau)[0][0] + eps) - np.log(eps))
-                              for t in np.nonzero(z)[0]) for tau in range(T)])
+        nz = np.nonzero(z)[0]
+        score = np.array([sum(z[t] * (np.log(m.h(t - tau)[0][0] + eps) - np.log(eps)) for t in nz)
+                          for tau in range(T)])
         best = int(np.argmax(score))
         srt = np.sort(score)
-        if srt[-1] - srt[-2] < 1e-3:
-            continue                                   # near tie: fixed point rounding decides
+        bound = 0.5 * z.sum() / 2.0 ** 16
+        if srt[-1] - srt[-2] <= 2.0 * bound:
+            continue                                   # the rounding may decide this one
         s = oracle_lib.State(1, 1, 1, 4)
         O = oracle_lib.Oracle(m, oracle_lib.Params(n_min=1, kappa=0.0, k_init=1))
         O.init(off, ent, s)
         assert s.cnt[0] == 1 and s.t[0, 0] == best
-        assert hbar is not None
+        checked += 1
+    assert checked >= 36
+
+
+def test_lmf_weights_are_rounded_log_filter(oracle_lib):
+    """q_k = round(2^16 log(1 + h_k T sbr_guess)): within half a unit of the
+    float weight of the log-matched filter at each integer lag."""
+    T = 150
+    m = gauss_model(oracle_lib, T)
+    for sbr in (1.0, 0.1):
+        q = m.lmf_table(sbr)
+        h = m.h(np.arange(m.L) - m.origin)[0]
+        exact = 2.0 ** 16 * np.log1p(h * T * sbr)
+        assert np.all(np.abs(q - exact) <= 0.5)
+
+
+def test_lmf_pooled_window_hand_case(oracle_lib):
+    """r_init = 1 pools the photons of the 3 x 3 window (clipped at the frame
+    edge, not wrapped).  5 x 5 frame, 40 bins, IRF (1, 2, 1):
+      - centre (2, 2): own 3 photons at bin 10 and 2 at bin 25;
+      - its 8 neighbours: 2 photons each at bin 25;
+      - the outer ring: 4 photons each at bin 10, except (4, 4): 100 at bin 33.
+    Centre, own photons only (r_init 0): argmax 10.  Pooled 3 x 3: bin 10
+    holds 3, bin 25 holds 18, so the peak is 25 (a 5 x 5 pool would pick 33,
+    then 10).  Its window 24..26 holds 2 own photons; background from the 3
+    others over the 37 unclaimed bins: r0 = 2 - 3 * 3/37, b0 = 3/37.
+    Corner (0, 0) pools (0,0), (0,1), (1,0): 4 + 4 + 4 at bin 10 and (1,1):
+    2 at bin 25; a wrapped window would reach (4, 4)'s 100 at bin 33."""
+    T = 40
+    m = oracle_lib.Model(np.array([1.0, 2.0, 1.0]), T=T)
+    assert m.window() == (1, 1)
+    Z = np.zeros((1, 5, 5, T), dtype=np.uint16)
+    for i in range(5):
+        for j in range(5):
+            if max(abs(i - 2), abs(j - 2)) == 2:
+                Z[0, i, j, 10] = 4
+            elif max(abs(i - 2), abs(j - 2)) == 1:
+                Z[0, i, j, 25] = 2
+    Z[0, 4, 4, 10] = 0
+    Z[0, 4, 4, 33] = 100
+    Z[0, 2, 2, 10] = 3
+    Z[0, 2, 2, 25] = 2
+    off, ent = oracle_lib.compact(Z)
+    for r_init, t_centre in ((0, 10), (1, 25)):
+        s = oracle_lib.State(1, 5, 5, 4)
+        O = oracle_lib.Oracle(m, oracle_lib.Params(k_init=1, r_init=r_init, n_min=1, kappa=3.0, b_min=1e-8))
+        O.init(off, ent, s, normals=False)
+        c = 2 * 5 + 2
+        assert s.cnt[c] == 1 and s.t[c, 0] == t_centre
+        if r_init == 1:
+            assert abs(s.r[c, 0] - (2.0 - 3.0 * 3.0 / 37.0)) < 1e-12
+            assert abs(s.b[c] - 3.0 / 37.0) < 1e-15
+            assert s.cnt[0] == 1 and s.t[0, 0] == 10           # corner: not wrapped
+        else:
+            # own photons: 3 at bin 10 (window 9..11), 2 others over 37 bins
+            assert abs(s.r[c, 0] - (3.0 - 2.0 * 3.0 / 37.0)) < 1e-12
+            assert abs(s.b[c] - 2.0 / 37.0) < 1e-15
+
+
+def test_lmf_second_round_claims_and_keep_test_hand_case(oracle_lib):
+    """Pixel (1, 1) of the pooled-window case with k_init = 2: its 3 x 3 pool
+    holds 23 photons at bin 10 (five ring pixels and the centre) and 8 at bin
+    25, its own photons are the 2 at bin 25.  Round 1 takes 10 (accepted on
+    the pool, claims bins 9..11), round 2 scores the unclaimed photons and
+    takes 25 (claims 24..26).  The keep test uses the pixel's own photons: the
+    peak at 10 holds none and is dropped; the peak at 25 keeps
+    r0 = 2 - 0 * 3/34 = 2 and the background has no unclaimed photon left
+    (b0 = b_min).  With k_init = 1 only the dropped peak is found: no point."""
+    T = 40
+    m = oracle_lib.Model(np.array([1.0, 2.0, 1.0]), T=T)
+    Z = np.zeros((1, 5, 5, T), dtype=np.uint16)
+    for i in range(5):
+        for j in range(5):
+            if max(abs(i - 2), abs(j - 2)) == 2:
+                Z[0, i, j, 10] = 4
+            elif max(abs(i - 2), abs(j - 2)) == 1:
+                Z[0, i, j, 25] = 2
+    Z[0, 4, 4, 10] = 0
+    Z[0, 4, 4, 33] = 100
+    Z[0, 2, 2, 10] = 3
+    Z[0, 2, 2, 25] = 2
+    off, ent = oracle_lib.compact(Z)
+    q = 1 * 5 + 1
+    for k_init, cnt in ((1, 0), (2, 1)):
+        s = oracle_lib.State(1, 5, 5, 4)
+        O = oracle_lib.Oracle(m, oracle_lib.Params(k_init=k_init, r_init=1, n_min=1, kappa=3.0, b_min=1e-8))
+        O.init(off, ent, s, normals=False)
+        assert s.cnt[q] == cnt
+        if cnt:
+            assert s.t[q, 0] == 25 and abs(s.r[q, 0] - 2.0) < 1e-15
+            assert s.b[q] == 1e-8
+
+
+def test_lmf_later_rounds_score_unclaimed_photons_hand_case(oracle_lib):
+    """One pixel, 100 bins, IRF (1, 2, 4, 8, 4, 2, 1)/22 (window -2..+2,
+    suppression half width 3), no background: noiseless templates x20 at
+    depth 30 (440 photons) and x4 at depth 60 (88 photons).  After round 1
+    takes 30 and claims bins 28..32, round 2 scores the unclaimed photons
+    only: the first template's tails (20 photons at bins 27 and 33) score
+    20 q(4/22) at tau = 26 and 34, below the second template's score at 60.
+    Scoring every photon instead would put 288 > 261 (in units of log) at
+    tau = 26 and 34, just outside the suppression, and reject it.  Round 3
+    (tau = 26, tie with 34, smallest first) is rejected.  Own photons in the
+    claimed windows 400 and 80, the other 48 over 90 bins; the IRF mass in a
+    window is 20/22."""
+    T = 100
+    irf = np.array([1.0, 2.0, 4.0, 8.0, 4.0, 2.0, 1.0])
+    m = oracle_lib.Model(irf, T=T)
+    assert m.window() == (2, 2)
+    Z = np.zeros((1, 1, T), dtype=np.uint16)
+    Z[0, 0, 27:34] += (20 * irf).astype(np.uint16)
+    Z[0, 0, 57:64] += (4 * irf).astype(np.uint16)
+    off, ent = oracle_lib.compact(Z)
+    s = oracle_lib.State(1, 1, 1, 4)
+    O = oracle_lib.Oracle(m, oracle_lib.Params(k_init=3, r_init=0, n_min=2, kappa=3.0, b_min=1e-8))
+    O.init(off, ent, s, normals=False)
+    assert s.cnt[0] == 2
+    np.testing.assert_array_equal(s.t[0, :2], [30.0, 60.0])
+    H = 20.0 / 22.0
+    assert abs(s.b[0] - 48.0 / 90.0) < 1e-15
+    assert abs(s.r[0, 0] - (400.0 - 5.0 * 48.0 / 90.0) / H) < 1e-10
+    assert abs(s.r[0, 1] - (80.0 - 5.0 * 48.0 / 90.0) / H) < 1e-10
+
+
+def test_lmf_two_surfaces_on_background_hand_case(oracle_lib):
+    """One pixel, 100 bins, IRF (1, 2, 4, 2, 1)/10 (window -2..+2, suppression
+    half width ceil(2 sigma_h) = 3): noiseless templates of 100 photons at
+    depth 30 and 50 photons at depth 70 on one background photon per bin,
+    except bins 0..4, which are empty.
+      round 1: the larger template, 30 (symmetric data and filter), accepted;
+      round 2: on the unclaimed photons, 70, accepted;
+      round 3: the flat background's first full window is tau = 7 (window
+               5..9, 5 photons against 245 * 5/100 expected): rejected, stop.
+    Own photons (r_init = 0): 105 and 55 in the two claimed windows, the other
+    85 over the 90 unclaimed bins, so b0 = 85/90 (a claimed rejected window
+    would give 80/85, an unclaimed denominator 85/100) and
+    r0 = 105 - 5 * 85/90, 55 - 5 * 85/90 (the IRF mass in each window is 1)."""
+    T = 100
+    irf = np.array([1.0, 2.0, 4.0, 2.0, 1.0])
+    m = oracle_lib.Model(irf, T=T)
+    assert m.window() == (2, 2)
+    Z = np.ones((1, 1, T), dtype=np.uint16)
+    Z[0, 0, :5] = 0
+    Z[0, 0, 28:33] += (10 * irf).astype(np.uint16)
+    Z[0, 0, 68:73] += (5 * irf).astype(np.uint16)
+    assert int(Z.sum()) == 95 + 150
+    off, ent = oracle_lib.compact(Z)
+    s = oracle_lib.State(1, 1, 1, 4)
+    O = oracle_lib.Oracle(m, oracle_lib.Params(k_init=3, r_init=0, n_min=2, kappa=3.0, b_min=1e-8))
+    O.init(off, ent, s, normals=False)
+    assert s.cnt[0] == 2
+    np.testing.assert_array_equal(s.t[0, :2], [30.0, 70.0])
+    assert abs(s.b[0] - 85.0 / 90.0) < 1e-15
+    assert abs(s.r[0, 0] - (105.0 - 5.0 * 85.0 / 90.0)) < 1e-12
+    assert abs(s.r[0, 1] - (55.0 - 5.0 * 85.0 / 90.0)) < 1e-12
+    # k_init = 1 stops after the first peak: the second template's photons
+    # count as background
+    s = oracle_lib.State(1, 1, 1, 4)
+    O = oracle_lib.Oracle(m, oracle_lib.Params(k_init=1, r_init=0, n_min=2, kappa=3.0, b_min=1e-8))
+    O.init(off, ent, s, normals=False)
+    assert s.cnt[0] == 1 and s.t[0, 0] == 30.0
+    assert abs(s.b[0] - 140.0 / 95.0) < 1e-15
+    assert abs(s.r[0, 0] - (105.0 - 5.0 * 140.0 / 95.0)) < 1e-12
 
 
 def test_lmf_intensity_and_background_closed_form(oracle_lib):
@@ -256,31 +424,74 @@ def test_intensity_step_single_point_em_closed_form(oracle_lib):
     assert abs(s.r[0, 0] - 12.0 / (1.7 * S[0])) < 1e-12
 
 
-def test_intensity_filter_constant_field_and_graph(oracle_lib):
+def _graph_case(oracle_lib):
+    # centre pixel of 3x3; the neighbour set picks the nearest point per pixel
+    s = oracle_lib.State(1, 3, 3, 2)
+    s.cnt[:] = 1
+    s.t[:, 0] = 50.0
+    s.r[:, 0] = np.arange(9, dtype=float) + 1.0
+    s.t[0, 0] = 80.0                     # 3 world units away: not a neighbour
+    s.cnt[2] = 2
+    s.t[2, :2] = [40.0, 51.0]            # nearest of the two is slot 1 (0.1 away)
+    s.r[2, :2] = [100.0, 20.0]
+    return s
+
+
+@pytest.mark.parametrize("ilp_box", [0, 1])
+def test_intensity_filter_constant_field_and_graph(oracle_lib, ilp_box):
     rows, cols = 5, 6
-    p = oracle_lib.Params(k_max=2, dz=0.1, h_int=2.0, r_min=0.0)
+    p = oracle_lib.Params(k_max=2, dz=0.1, h_int=2.0, r_min=0.0, ilp_box=ilp_box)
     s = oracle_lib.State(1, rows, cols, 2)
     s.cnt[:] = 1
     s.t[:, 0] = 100.0
     s.r[:, 0] = 3.0
     O = oracle_lib.Oracle(gauss_model(oracle_lib, 500), p)
     O.intensity_filter(s)
-    np.testing.assert_allclose(s.r[:, 0], 3.0, rtol=1e-15)  # constant field, borders too
-    # hand case: centre pixel of 3x3; neighbour set picks the nearest point per pixel
+    # a constant field is invariant (the box reading only inside the image)
+    inner = np.zeros((rows, cols), bool)
+    inner[1:-1, 1:-1] = True
+    np.testing.assert_allclose(s.r[:, 0][inner.reshape(-1) | (ilp_box == 0)], 3.0, rtol=1e-15)
+    s = _graph_case(oracle_lib)
+    O.intensity_filter(s)
+    found = [2.0, 20.0, 4, 6, 7, 8, 9]       # pixel 0 (depth 80) is not on the surface
+    if ilp_box == 0:
+        # mean over the point and the seven neighbours on its surface
+        expect = (5.0 + sum(found)) / 8.0
+        # the corner (0,0) sits alone at depth 80: no neighbour, its intensity stays
+        expect_corner = 1.0
+    else:
+        # 3 x 3 box: the missing neighbour counts as zero
+        expect = (5.0 + sum(found)) / 9.0
+        expect_corner = 1.0 / 4
+    assert abs(s.r[4, 0] - expect) < 1e-12
+    assert abs(s.r[0, 0] - expect_corner) < 1e-15
+    # border pixel (0,1): neighbours (0,0) [not on the surface], (0,2) slot 1,
+    # (1,0), (1,1), (1,2); five pixels inside the image
+    s = _graph_case(oracle_lib)
+    O.intensity_filter(s)
+    nb = [20.0, 4, 5, 6]
+    assert abs(s.r[1, 0] - (2.0 + sum(nb)) / (1 + (5 if ilp_box else 4))) < 1e-12
+
+
+def test_intensity_filter_surface_mean_keeps_an_isolated_point(oracle_lib):
+    """The reading of the paper's low-pass (only points of one surface are
+    correlated): a point whose surrounding pixels hold no point of its surface
+    keeps its intensity and survives the threshold, while the 3 x 3 box reading
+    divides it by 9 and removes it."""
     s = oracle_lib.State(1, 3, 3, 2)
     s.cnt[:] = 1
     s.t[:, 0] = 50.0
-    s.r[:, 0] = np.arange(9, dtype=float)
-    s.t[0, 0] = 80.0                     # 3 world units away: not a neighbour
-    s.cnt[2] = 2
-    s.t[2, :2] = [40.0, 51.0]            # nearest of the two is slot 1 (0.1 away)
-    s.r[2, :2] = [100.0, 20.0]
-    O.intensity_filter(s)
-    expect = (4.0 + 1 + 20.0 + 3 + 5 + 6 + 7 + 8) / 9.0
-    assert abs(s.r[4, 0] - expect) < 1e-12
-    # corner pixel (0,0) sits alone at depth 80: its 3 surrounding pixels hold no
-    # point within h_int, so its intensity is divided by 1 + 3
-    assert abs(s.r[0, 0] - 0.0 / 4) < 1e-15
+    s.r[:, 0] = 4.0
+    s.t[4, 0] = 200.0                    # centre point far from its neighbours' surface
+    s.r[4, 0] = 3.0
+    for ilp_box, kept in ((0, True), (1, False)):
+        O = oracle_lib.Oracle(gauss_model(oracle_lib, 500),
+                              oracle_lib.Params(k_max=2, dz=0.1, h_int=2.0, r_min=1.0, ilp_box=ilp_box))
+        c = s.copy()
+        O.intensity_filter(c)
+        assert (c.cnt[4] == 1) == kept
+        if kept:
+            assert c.t[4, 0] == 200.0 and c.r[4, 0] == 3.0
 
 
 def test_intensity_threshold_removes_and_compacts(oracle_lib):
