@@ -373,6 +373,51 @@ class Oracle:
                              s.t, s.r, s.n, s.cnt, s.b)
         return s
 
+    # -- the learned denoiser in the depth block ----------------------------
+    def cnn_denoise(self, s: State, w, fp16: bool = True) -> State:
+        """Depth denoiser with the learned network (the loop's depth block with
+        another plugged-in denoiser; Results, "Reconstruction algorithm"):
+        pixels holding more than the network's three slots take the APSS step
+        (their fit reads every point of the pre-denoiser state, as APSS alone
+        does); the network then reads the features of the resulting state and
+        moves slot k < cnt of every pixel with at most three points by
+        sigma_h y_k, kept inside [0, T - 1].  Normals of those pixels stay.
+        fp16: the FP16 storage points of the network (features, weights,
+        activations, output) as the GPU keeps them."""
+        from . import cnn
+        sigma_h = float(np.sqrt(self.m.sigma2))
+        fitted = self.apss(s.copy())
+        four = s.cnt > 3
+        s.t[four] = fitted.t[four]
+        s.n[four] = fitted.n[four]
+        x = cnn.features(s.t, s.r, s.cnt, sigma_h, s.F, s.rows, s.cols)
+        y, _ = cnn.forward(x, w, fp16=fp16)
+        y = y.reshape(s.npix, 3)
+        for k in range(3):
+            mv = (s.cnt <= 3) & (s.cnt > k)
+            s.t[mv, k] = np.clip(s.t[mv, k] + sigma_h * y[mv, k], 0.0, self.m.T - 1)
+        return s
+
+    def iterate_cnn(self, off, ent, s: State, w, fp16: bool = True) -> State:
+        """One iteration of the loop with the learned depth denoiser in place of
+        APSS: depth step, cnn_denoise, merge, intensity step, intensity
+        low-pass and threshold, background step, background filter."""
+        self.depth_step(off, ent, s)
+        self.cnn_denoise(s, w, fp16)
+        self.merge(s)
+        self.intensity_step(off, ent, s)
+        self.intensity_filter(s)
+        self.bg_step(off, ent, s)
+        self.bg_filter(s)
+        return s
+
+    def reconstruct_cnn(self, off, ent, s: State, w, fp16: bool = True) -> State:
+        """Initialisation, then n_iter iterations with the learned depth denoiser."""
+        self.init(off, ent, s)
+        for _ in range(self.p.n_iter):
+            self.iterate_cnn(off, ent, s, w, fp16)
+        return s
+
     # -- super-resolution (s x s point-grid pixels per lidar pixel) ----------
     def _sr(self, s: SRState):
         return (s.s, s.F, s.lrows, s.lcols)

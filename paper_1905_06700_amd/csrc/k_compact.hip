@@ -34,8 +34,11 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t& total)
     return base + inc - v;
 }
 
+// Tile totals of the counts (each tile of SCAN_TILE counts fits 32 bits: the
+// counts are per-pixel entries, points or events, each below 2^16 per tile
+// element or summing below 2^31), widened to 64 bits.
 __global__ __launch_bounds__(SCAN_THREADS) void k_scan_reduce(const uint32_t* __restrict__ in,
-                                                              long long n, uint32_t* __restrict__ partial)
+                                                              long long n, uint64_t* __restrict__ partial)
 {
     long long base = (long long)blockIdx.x * SCAN_TILE + (long long)threadIdx.x * SCAN_ITEMS;
     uint32_t s = 0;
@@ -47,31 +50,46 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_reduce(const uint32_t* __
     if (threadIdx.x == 0) partial[blockIdx.x] = total;
 }
 
-// One block: exclusive scan of the tile totals in place; out[n] = grand total.
-// A grand total above `cap` (or above 32 bits) sets E_CAPACITY.
-__global__ __launch_bounds__(SCAN_THREADS) void k_scan_partials(uint32_t* __restrict__ partial,
+// One block: exclusive scan of the nb tile totals in place, in 64 bits (each
+// thread a contiguous run of tiles, then a scan of the run sums in LDS);
+// out[n] = the grand total clamped to `cap`.  A grand total above `cap` sets
+// E_CAPACITY.
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_partials(uint64_t* __restrict__ partial,
                                                                 long long nb, uint32_t* __restrict__ out_total,
                                                                 uint64_t cap, int32_t* __restrict__ err)
 {
-    uint32_t carry = 0;
-    uint64_t wide = 0;
-    for (long long b0 = 0; b0 < nb; b0 += SCAN_THREADS) {
-        long long i = b0 + threadIdx.x;
-        uint32_t v = i < nb ? partial[i] : 0u;
-        uint32_t total;
-        uint32_t ex = block_excl_scan(v, total);
-        if (i < nb) partial[i] = carry + ex;
-        carry += total;
-        wide += total;
+    __shared__ uint64_t run[SCAN_THREADS];
+    const long long per = (nb + SCAN_THREADS - 1) / SCAN_THREADS;
+    const long long b0 = (long long)threadIdx.x * per;
+    const long long b1 = b0 + per < nb ? b0 + per : nb;
+    uint64_t s = 0;
+    for (long long i = b0; i < b1; ++i) s += partial[i];
+    run[threadIdx.x] = s;
+    __syncthreads();
+    // Hillis-Steele inclusive scan of the run sums
+    for (int d = 1; d < SCAN_THREADS; d <<= 1) {
+        const uint64_t add = threadIdx.x >= (unsigned)d ? run[threadIdx.x - d] : 0ull;
+        __syncthreads();
+        run[threadIdx.x] += add;
+        __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        *out_total = carry;
-        if (err && wide > cap) *err = RT3D_E_CAPACITY;
+    uint64_t acc = run[threadIdx.x] - s;
+    for (long long i = b0; i < b1; ++i) {
+        const uint64_t v = partial[i];
+        partial[i] = acc;
+        acc += v;
+    }
+    if (threadIdx.x == SCAN_THREADS - 1) {
+        const uint64_t total = run[SCAN_THREADS - 1];
+        *out_total = (uint32_t)(total < cap ? total : cap);
+        if (err && total > cap) *err = RT3D_E_CAPACITY;
     }
 }
 
+// out[i] = the exclusive prefix of element i, clamped to `cap`: past the
+// capacity every list is empty, and a list that crosses it ends there.
 __global__ __launch_bounds__(SCAN_THREADS) void k_scan_apply(const uint32_t* __restrict__ in, long long n,
-                                                             const uint32_t* __restrict__ partial,
+                                                             const uint64_t* __restrict__ partial, uint64_t cap,
                                                              uint32_t* __restrict__ out)
 {
     long long base = (long long)blockIdx.x * SCAN_TILE + (long long)threadIdx.x * SCAN_ITEMS;
@@ -83,27 +101,31 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_apply(const uint32_t* __r
         s += v[k];
     }
     uint32_t total;
-    uint32_t run = partial[blockIdx.x] + block_excl_scan(s, total);
+    uint64_t run = partial[blockIdx.x] + block_excl_scan(s, total);
 #pragma unroll
     for (int k = 0; k < SCAN_ITEMS; ++k) {
-        if (base + k < n) out[base + k] = run;
+        if (base + k < n) out[base + k] = (uint32_t)(run < cap ? run : cap);
         run += v[k];
     }
 }
 
-size_t scan_partial_elems(long long n) { return (size_t)((n + SCAN_TILE - 1) / SCAN_TILE) + 1; }
+// 32-bit words of scan workspace for n elements: one 64-bit prefix per tile.
+size_t scan_partial_elems(long long n) { return 2 * ((size_t)((n + SCAN_TILE - 1) / SCAN_TILE) + 1); }
 
-// out[0..n] = exclusive prefix of in[0..n-1] followed by the total.  `in` and
-// `out` may alias (each tile reads its inputs before writing).
+// out[0..n] = exclusive prefix of in[0..n-1] followed by the total, every
+// value clamped to min(cap, 2^32 - 1) (a total above that sets E_CAPACITY).  `in` and `out` may alias (each tile reads its inputs before
+// writing).  partial: scan_partial_elems(n) words, 8-byte aligned.
 hipError_t launch_scan(const uint32_t* in, uint32_t* out, long long n, uint32_t* partial, uint64_t cap,
                        int32_t* err, hipStream_t st)
 {
+    uint64_t* part = reinterpret_cast<uint64_t*>(partial);
+    if (cap > 0xffffffffull) cap = 0xffffffffull;   // offsets are 32-bit
     long long nb = (n + SCAN_TILE - 1) / SCAN_TILE;
     if (nb > 0)
-        hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, st, in, n, partial);
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(SCAN_THREADS), 0, st, partial, nb, out + n, cap, err);
+        hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, st, in, n, part);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(SCAN_THREADS), 0, st, part, nb, out + n, cap, err);
     if (nb > 0)
-        hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, st, in, n, partial, out);
+        hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, st, in, n, part, cap, out);
     return hipGetLastError();
 }
 
@@ -180,7 +202,9 @@ __global__ __launch_bounds__(64 * CP_WAVES) void k_compact_stage(const uint16_t*
 
 // Pass 2 (after the scan of the counts into off): each pixel's entries move
 // from its staging slot to off[p]; a pixel with more than CP_STAGE entries
-// reads its histogram again.  Entries past `cap` are dropped (E_CAPACITY).
+// reads its histogram again.  Entries past `cap` are dropped (E_CAPACITY);
+// the scan has clamped the offsets to `cap`, so every later step sees the
+// lists cut at the capacity.
 __global__ __launch_bounds__(64 * CP_WAVES) void k_compact_copy(const uint16_t* __restrict__ Z, long long P,
                                                                 int T, const uint32_t* __restrict__ off,
                                                                 const uint32_t* __restrict__ stage,

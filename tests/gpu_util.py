@@ -93,3 +93,17 @@ def device_to_sr(d: rt3d.DeviceState, k_max: int, sr: int, g=None) -> oracle.SRS
         setattr(s, a, getattr(p, a))
     s.b[:] = p.b[:s.b.size]
     return s
+
+
+def intensity_err(inten, pt, so, pixels, base: int = 0) -> float:
+    """Largest relative difference |r - r_oracle| / r_oracle over the points of
+    the oracle pixels `pixels` (device points of pixel q at pt[base + q] ..)."""
+    r = inten.cpu().numpy() if isinstance(inten, torch.Tensor) else np.asarray(inten)
+    worst = 0.0
+    for q in pixels:
+        c = int(so.cnt[q])
+        if c:
+            ro = so.r[q, :c]
+            d = np.abs(r[pt[base + q]:pt[base + q] + c] - ro) / np.maximum(np.abs(ro), 1e-6)
+            worst = max(worst, float(d.max()))
+    return worst

@@ -1,9 +1,13 @@
 """GPU parity and gain of the learned depth denoiser, through the C ABI.
 
 Forward: the FP16-MFMA network against the FP64 oracle with the same FP16
-rounding points (features, weights, each layer's stored output).  Training:
-the weight gradient of one step against the oracle's backward pass, and the
-Adam update against the oracle's Adam.  Gain: a network trained on the GPU by
+rounding points (features, weights, each layer's stored output), element by
+element within 2e-3 of the output scale.  Training: each weight gradient
+element of one step within 1e-2 of its layer's largest against the oracle's
+backward pass, and the Adam update against the oracle's Adam.  In the loop:
+one iteration with the network as the depth denoiser (APSS for pixels with
+four points) against the oracle's iteration with the same network, and a
+short reconstruction.  Gain: a network trained on the GPU by
 the library's own kernels, on depth-block inputs recorded from plain-APSS
 runs of multi-layer scenes, reconstructs held-out scenes with a lower depth
 error than the method with no depth denoiser.
@@ -11,7 +15,7 @@ error than the method with no depth denoiser.
 import numpy as np
 import pytest
 
-from gpu_util import oracle_to_device, to_dev_hist, to_dev_u32, u32
+from gpu_util import device_to_oracle, oracle_to_device, to_dev_hist, to_dev_u32, u32
 
 pytestmark = pytest.mark.gpu
 
@@ -68,7 +72,7 @@ def test_cnn_forward_matches_oracle():
     scale = max(1.0, np.abs(yo).max())
     err = np.abs(y - yo).max()
     print(f"[gpu-cnn] forward max |gpu - oracle| = {err:.3e} (output scale {scale:.2f})", flush=True)
-    assert err <= 2e-2 * scale
+    assert err <= 2e-3 * scale
 
 
 def test_cnn_train_step_gradient_and_adam_match_oracle():
@@ -91,12 +95,109 @@ def test_cnn_train_step_gradient_and_adam_match_oracle():
     for li, (ci, co) in enumerate(zip(cnn.CIN, cnn.COUT)):
         n = 9 * ci * co + co
         a, b = g[at:at + n], go[at:at + n]
-        rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
-        print(f"[gpu-cnn] layer {li} weight-gradient relative error {rel:.2e}", flush=True)
-        assert rel <= 2e-2
+        rel = np.abs(a - b).max() / max(np.abs(b).max(), 1e-30)
+        print(f"[gpu-cnn] layer {li} weight-gradient max element error {rel:.2e} of the layer's largest",
+              flush=True)
+        assert rel <= 1e-2
         at += n
     w1, _, _ = cnn.adam(w.astype(np.float64), g, np.zeros_like(g), np.zeros_like(g), 1, 1e-3)
     np.testing.assert_allclose(ctx.cnn_get_weights(), w1, rtol=1e-5, atol=1e-6)
+
+
+_loop = {}
+
+
+def loop_setup():
+    """A multi-layer scene (four peaks sought, so some pixels hold four points)
+    after the initialisation and two plain iterations, and a CNN context."""
+    if "s" not in _loop:
+        sc = synth.layers_scene(4, rows=ROWS, cols=COLS, T=T, signal=6.0, sbr=0.2)
+        prm = params(sc)
+        O = oracle.Oracle(oracle.Model(sc.irf.probs, T), oracle.Params(**prm))
+        off, ent = oracle.compact(sc.Z[None])
+        s = O.init(off, ent, oracle.State(1, ROWS, COLS, 4))
+        for _ in range(2):
+            O.iterate(off, ent, s)
+        ctx = rt3d.Context(sc.irf.probs, T, denoiser=rt3d.DENOISE_CNN, **prm)
+        ctx.workspace(1, ROWS, COLS, ROWS * COLS * 200)
+        _loop.update(sc=sc, O=O, s=s, off=off, ent=ent, ctx=ctx, sig=float(np.sqrt(O.m.sigma2)), prm=prm)
+    return _loop
+
+
+def _net_scale(O, s, off, ent, w, sig):
+    """Largest |network output| on the state the depth block hands the network."""
+    s1 = O.depth_step(off, ent, s.copy())
+    x = cnn.features(s1.t, s1.r, s1.cnt, sig, 1, ROWS, COLS)
+    yo, _ = cnn.forward(x, w, fp16=True)
+    return max(1.0, float(np.abs(yo).max()))
+
+
+def test_cnn_iteration_matches_oracle():
+    """One whole iteration with the learned denoiser in the depth block: the
+    depth step, APSS for pixels with four points, the network's move of the
+    other pixels' slots, then merge, intensity step, intensity low-pass and
+    background steps, against the oracle's iteration with the same network
+    from the same state.  Bars derived from the steps': counts equal on
+    >= 99.9% of pixels; depths within 2e-4 bin (the depth step's bar) plus
+    sigma_h x 2e-3 x the output scale (the forward bar, moved by sigma_h)."""
+    c = loop_setup()
+    O, s, ctx, sig = c["O"], c["s"], c["ctx"], c["sig"]
+    w = weights(4)
+    ctx.cnn_set_weights(w)
+    w64 = w.astype(np.float64)
+    assert (s.cnt == 4).sum() > 0 and (s.cnt == 2).sum() > 0
+    so = O.iterate_cnn(c["off"], c["ent"], s.copy(), w64)
+    sg = device_to_oracle(ctx.step(rt3d.STEP_ITERATION, oracle_to_device(s), to_dev_u32(c["off"]),
+                                   to_dev_u32(c["ent"])), 4)
+    scale = _net_scale(O, s, c["off"], c["ent"], w64, sig)
+    same = sg.cnt == so.cnt
+    lv = (np.arange(4)[None, :] < so.cnt[:, None]) & same[:, None]
+    dt = np.abs(sg.t - so.t)[lv].max()
+    dr = (np.abs(sg.r - so.r) / np.maximum(so.r, 1e-6))[lv].max()
+    bar = 2e-4 + sig * 2e-3 * scale
+    print(f"[gpu-cnn] iteration: count agreement {same.mean():.5f}, max depth err {dt:.2e} bins (bar {bar:.2e}), "
+          f"max intensity err {dr:.2e} relative, four-point pixels {(s.cnt == 4).sum()}", flush=True)
+    assert same.mean() >= 0.999
+    assert dt <= bar
+    # background: equal to the background step's bar away from the filter's
+    # reach (radius ceil(4 sigma_b) = 8) of a pixel whose point count differs
+    bad = (~same).reshape(ROWS, COLS)
+    reach = np.zeros_like(bad)
+    for di in range(-8, 9):
+        for dj in range(-8, 9):
+            reach |= np.roll(np.roll(bad, di, 0), dj, 1)
+    reach = reach.reshape(-1)
+    assert (~reach).mean() > 0.8
+    np.testing.assert_allclose(sg.b[~reach], so.b[~reach], rtol=1e-5, atol=1e-12)
+
+
+def test_cnn_reconstruction_matches_oracle():
+    """A short reconstruction (initialisation and three iterations) with the
+    learned denoiser against the oracle's.  Each iteration adds at most the
+    one-iteration bar, so depths stay within three times it."""
+    c = loop_setup()
+    O, ctx, sig, sc = c["O"], c["ctx"], c["sig"], c["sc"]
+    w = weights(5)
+    w64 = w.astype(np.float64)
+    prm = dict(c["prm"], n_iter=3)
+    O3 = oracle.Oracle(O.m, oracle.Params(**prm))
+    so = O3.reconstruct_cnn(c["off"], c["ent"], oracle.State(1, ROWS, COLS, 4), w64)
+    net = rt3d.Context(sc.irf.probs, T, denoiser=rt3d.DENOISE_CNN, **prm)
+    net.cnn_set_weights(w)
+    res = net.reconstruct(to_dev_hist(sc.Z)[None], max_entries=ROWS * COLS * 200)
+    assert net.query().device_error == 0
+    pt = u32(res.pt_off).astype(np.int64)
+    cnt = np.diff(pt)
+    same = cnt == so.cnt
+    depth = res.depth.cpu().numpy()
+    errs = [np.abs(depth[pt[p]:pt[p] + so.cnt[p]] - so.t[p, :so.cnt[p]]).max()
+            for p in np.nonzero(same & (so.cnt > 0))[0]]
+    s0 = O3.init(c["off"], c["ent"], oracle.State(1, ROWS, COLS, 4))
+    bar = 3 * (2e-4 + sig * 2e-3 * _net_scale(O3, s0, c["off"], c["ent"], w64, sig))
+    print(f"[gpu-cnn] reconstruction (3 iterations): count agreement {same.mean():.5f}, "
+          f"max depth err {max(errs):.2e} bins (bar {bar:.2e})", flush=True)
+    assert same.mean() >= 0.999
+    assert max(errs) <= bar
 
 
 def _scores(scenes, res, sig, R, C):

@@ -7,7 +7,7 @@ state the previous call left)."""
 import numpy as np
 import pytest
 
-from gpu_util import params_for, to_dev_hist, u32
+from gpu_util import intensity_err, params_for, to_dev_hist, u32
 
 pytestmark = pytest.mark.gpu
 
@@ -26,11 +26,14 @@ def compare(res, so, rows, cols, name):
         for dj in range(-2, 3):
             nb |= np.roll(np.roll(bad, di, 1), dj, 2)
     depth = res.depth.cpu().numpy()
-    errs = [np.abs(depth[pt[p]:pt[p] + so.cnt[p]] - so.t[p, :so.cnt[p]]).max()
-            for p in np.nonzero(~nb.reshape(-1) & (so.cnt > 0))[0]]
-    print(f"[gpu-combos] {name}: count agreement {same.mean():.5f}, max depth err {max(errs):.2e} bins", flush=True)
+    good = np.nonzero(~nb.reshape(-1) & (so.cnt > 0))[0]
+    errs = [np.abs(depth[pt[p]:pt[p] + so.cnt[p]] - so.t[p, :so.cnt[p]]).max() for p in good]
+    ierr = intensity_err(res.intensity, pt, so, good)
+    print(f"[gpu-combos] {name}: count agreement {same.mean():.5f}, max depth err {max(errs):.2e} bins, "
+          f"max intensity err {ierr:.2e} relative", flush=True)
     assert same.mean() >= 0.999
     assert len(errs) >= 0.9 * (so.cnt > 0).sum() and max(errs) <= 1e-3
+    assert ierr <= 2e-5
 
 
 def test_graph_replay_with_irf_classes():

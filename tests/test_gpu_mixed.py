@@ -8,7 +8,7 @@ and frames of both kinds must match the oracle run on them alone."""
 import numpy as np
 import pytest
 
-from gpu_util import to_dev_hist, u32
+from gpu_util import intensity_err, to_dev_hist, u32
 
 pytestmark = pytest.mark.gpu
 
@@ -88,7 +88,9 @@ def test_video_and_scenes_in_one_launch():
         for di in range(-2, 3):
             for dj in range(-2, 3):
                 nb |= np.roll(np.roll(bad, di, 0), dj, 1)
-        errs = [np.abs(depth[pt[b + q]:pt[b + q] + so.cnt[q]] - so.t[q, :so.cnt[q]]).max()
-                for q in np.nonzero(~nb.reshape(-1) & (so.cnt > 0))[0]]
-        print(f"[gpu-mixed] frame {f}: count agreement {same.mean():.5f}, max depth err {max(errs):.2e}", flush=True)
-        assert same.mean() >= 0.999 and max(errs) <= 1e-3
+        good = np.nonzero(~nb.reshape(-1) & (so.cnt > 0))[0]
+        errs = [np.abs(depth[pt[b + q]:pt[b + q] + so.cnt[q]] - so.t[q, :so.cnt[q]]).max() for q in good]
+        ierr = intensity_err(out.intensity, pt, so, good, base=b)
+        print(f"[gpu-mixed] frame {f}: count agreement {same.mean():.5f}, max depth err {max(errs):.2e}, "
+              f"max intensity err {ierr:.2e} relative", flush=True)
+        assert same.mean() >= 0.999 and max(errs) <= 1e-3 and ierr <= 2e-5

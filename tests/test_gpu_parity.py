@@ -18,7 +18,7 @@ Inputs: config-1 plane (32 x 32 x 300), config-2 head shape (141 x 141 x
 import numpy as np
 import pytest
 
-from gpu_util import device_to_oracle, oracle_to_device, pair, params_for, to_dev_hist, u32
+from gpu_util import device_to_oracle, intensity_err, oracle_to_device, pair, params_for, to_dev_hist, u32
 
 pytestmark = pytest.mark.gpu
 
@@ -104,6 +104,32 @@ def test_compaction_edge_cases():
     with pytest.raises(rt3d.Rt3dError) as e:
         ctx.query()
     assert e.value.status == rt3d.E_CAPACITY
+
+
+def test_reconstruct_past_entry_capacity_is_truncated():
+    """A reconstruction whose active bins exceed the workspace's max_entries
+    reports E_CAPACITY and works on the lists cut at the capacity: the result
+    equals the oracle's reconstruction of those truncated lists (the offsets
+    clamped to the capacity, the entries beyond it dropped)."""
+    sc = scene("c1")
+    O, _ = pair(sc)
+    ctx = rt3d.Context(sc.irf.probs, sc.T, **params_for(sc), fused_loop=0)
+    off_o, ent_o = csr(sc)
+    cap = len(ent_o) * 3 // 5                          # ~40% of the pixels lose their lists
+    P = sc.rows * sc.cols
+    ctx.workspace(1, sc.rows, sc.cols, cap)
+    out = ctx.make_output(P)
+    ctx.reconstruct_into(out, 1, sc.rows, sc.cols, hist=to_dev_hist(sc.Z)[None])
+    with pytest.raises(rt3d.Rt3dError) as e:
+        ctx.query()
+    assert e.value.status == rt3d.E_CAPACITY
+    off_t = np.minimum(off_o, cap).astype(np.uint32)
+    so = O.reconstruct(off_t, ent_o[:cap].copy(), oracle.State(1, sc.rows, sc.cols, 4))
+    frac, errs, cnt_g, _, ierr, _ = _compare_final(sc, so, out, P)
+    print(f"[gpu-parity] truncated lists ({cap} of {len(ent_o)} entries): count agreement {frac:.5f}, "
+          f"max depth err {errs.max():.2e} bins, max intensity err {ierr:.2e}", flush=True)
+    assert np.all(cnt_g[np.diff(off_t.astype(np.int64)) == 0] == 0)     # no photons left: no point
+    assert frac >= 0.999 and errs.max() <= 1e-3 and ierr <= 2e-5
 
 
 # ------------------------------------------------------------------ init
@@ -289,7 +315,8 @@ def _compare_final(sc, so, res, P):
         c = so.cnt[p]
         if c:
             errs.append(np.abs(depth[pt_off[p]:pt_off[p] + c] - so.t[p, :c]).max())
-    return frac, np.array(errs), cnt_g, depth, inten, pt_off
+    ierr = intensity_err(inten, pt_off, so, np.nonzero(ok)[0])
+    return frac, np.array(errs), cnt_g, depth, ierr, pt_off
 
 
 @pytest.mark.parametrize("name,fused", [("c1", 1), ("c1", 0), ("c2", 1), ("ragged", 1), ("ragged", 0)])
@@ -305,11 +332,12 @@ def test_reconstruction_matches_oracle(name, fused):
     st = ctx.query()
     assert st.device_error == 0
     assert st.entries == len(ent_o)
-    frac, errs, cnt_g, depth, inten, pt_off = _compare_final(sc, so, res, sc.rows * sc.cols)
+    frac, errs, cnt_g, depth, ierr, pt_off = _compare_final(sc, so, res, sc.rows * sc.cols)
     print(f"[gpu-parity] {name} (fused loop {fused}): count agreement {frac:.5f}, max depth err {errs.max():.2e} bins "
-          f"over {len(errs)} pixels", flush=True)
+          f"over {len(errs)} pixels, max intensity err {ierr:.2e} relative", flush=True)
     assert frac >= 0.999
     assert errs.max() <= 1e-3
+    assert ierr <= 2e-5
     np.testing.assert_allclose(res.background.cpu().numpy(), so.b, rtol=1e-3, atol=1e-9)
 
 
@@ -376,6 +404,6 @@ def test_gain_and_dead_pixels():
     so = oracle.State(1, sc.rows, sc.cols, 4, g=g.reshape(-1))
     O.reconstruct(off_o, ent_o, so)
     res = ctx.reconstruct(to_dev_hist(Z)[None], gain=torch.from_numpy(g.astype(np.float32).reshape(-1)).cuda())
-    frac, errs, cnt_g, *_ = _compare_final(sc, so, res, sc.rows * sc.cols)
-    assert frac >= 0.999 and errs.max() <= 1e-3
+    frac, errs, cnt_g, _, ierr, _ = _compare_final(sc, so, res, sc.rows * sc.cols)
+    assert frac >= 0.999 and errs.max() <= 1e-3 and ierr <= 2e-5
     assert np.all(cnt_g[g.reshape(-1) == 0] == 0)

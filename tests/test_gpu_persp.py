@@ -7,7 +7,7 @@ the orthographic tests; the refusals."""
 import numpy as np
 import pytest
 
-from gpu_util import device_to_oracle, oracle_to_device, to_dev_hist, to_dev_u32, u32
+from gpu_util import intensity_err, device_to_oracle, oracle_to_device, to_dev_hist, to_dev_u32, u32
 
 pytestmark = pytest.mark.gpu
 
@@ -89,11 +89,14 @@ def test_persp_reconstruction_matches_oracle(k):
         for dj in range(-2, 3):
             nb |= np.roll(np.roll(bad, di, 0), dj, 1)
     depth = res.depth.cpu().numpy()
-    errs = [np.abs(depth[pt[p]:pt[p] + so.cnt[p]] - so.t[p, :so.cnt[p]]).max()
-            for p in np.nonzero(~nb.reshape(-1) & (so.cnt > 0))[0]]
-    print(f"[gpu-persp] scene {k}: count agreement {same.mean():.5f}, max depth err {max(errs):.2e} bins", flush=True)
+    good = np.nonzero(~nb.reshape(-1) & (so.cnt > 0))[0]
+    errs = [np.abs(depth[pt[p]:pt[p] + so.cnt[p]] - so.t[p, :so.cnt[p]]).max() for p in good]
+    ierr = intensity_err(res.intensity, pt, so, good)
+    print(f"[gpu-persp] scene {k}: count agreement {same.mean():.5f}, max depth err {max(errs):.2e} bins, "
+          f"max intensity err {ierr:.2e} relative", flush=True)
     assert same.mean() >= 0.999
     assert max(errs) <= 1e-3
+    assert ierr <= 2e-5
     np.testing.assert_allclose(res.background.cpu().numpy(), so.b, rtol=1e-3, atol=1e-9)
 
 

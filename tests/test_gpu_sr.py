@@ -5,7 +5,7 @@ and whole reconstructions, with the same bars as the plain model."""
 import numpy as np
 import pytest
 
-from gpu_util import device_to_sr, sr_to_device, to_dev_hist, to_dev_u32, u32
+from gpu_util import intensity_err, device_to_sr, sr_to_device, to_dev_hist, to_dev_u32, u32
 
 pytestmark = pytest.mark.gpu
 
@@ -161,12 +161,14 @@ def test_sr_reconstruction_matches_oracle(name):
         for dj in range(-2, 3):
             nb |= np.roll(np.roll(bad, di, 1), dj, 2)
     depth = res.depth.cpu().numpy()
-    errs = [np.abs(depth[pt[q]:pt[q] + so.cnt[q]] - so.t[q, :so.cnt[q]]).max()
-            for q in np.nonzero(~nb.reshape(-1) & (so.cnt > 0))[0]]
+    good = np.nonzero(~nb.reshape(-1) & (so.cnt > 0))[0]
+    errs = [np.abs(depth[pt[q]:pt[q] + so.cnt[q]] - so.t[q, :so.cnt[q]]).max() for q in good]
+    ierr = intensity_err(res.intensity, pt, so, good)
     print(f"[gpu-sr] {name}: count agreement {same.mean():.5f}, max depth err {max(errs):.2e} bins "
-          f"over {len(errs)} pixels", flush=True)
+          f"over {len(errs)} pixels, max intensity err {ierr:.2e} relative", flush=True)
     assert same.mean() >= 0.999
     assert len(errs) > 0.5 * so.npix and max(errs) <= 1e-3
+    assert ierr <= 2e-5
     np.testing.assert_allclose(res.background.cpu().numpy(), so.b, rtol=1e-3, atol=1e-9)
 
 

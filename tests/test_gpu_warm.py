@@ -5,7 +5,7 @@ output, read back)."""
 import numpy as np
 import pytest
 
-from gpu_util import pair, to_dev_hist, u32
+from gpu_util import intensity_err, pair, to_dev_hist, u32
 
 pytestmark = pytest.mark.gpu
 
@@ -60,7 +60,10 @@ def test_warm_start_matches_oracle_iterations():
     depth = b.depth.cpu().numpy()
     err = max(float(np.abs(depth[pt[p]:pt[p] + cnt[p]] - so.t[p, :cnt[p]]).max(initial=0))
               for p in np.nonzero(same)[0])
+    ierr = intensity_err(b.intensity, pt, so, np.nonzero(same)[0])
+    print(f"[gpu-warm] max depth err {err:.2e} bins, max intensity err {ierr:.2e} relative", flush=True)
     assert err <= 1e-3
+    assert ierr <= 2e-5
     np.testing.assert_allclose(b.background.cpu().numpy(), so.b, rtol=1e-4, atol=1e-9)
 
 

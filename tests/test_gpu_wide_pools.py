@@ -11,7 +11,7 @@ plain model, and a batch of two such frames equal to each alone."""
 import numpy as np
 import pytest
 
-from gpu_util import device_to_oracle, to_dev_hist, to_dev_u32, u32
+from gpu_util import intensity_err, device_to_oracle, to_dev_hist, to_dev_u32, u32
 
 pytestmark = pytest.mark.gpu
 
@@ -84,12 +84,14 @@ def test_wide_pools_reconstruction_matches_oracle():
         for dj in range(-2, 3):
             nb |= np.roll(np.roll(bad, di, 0), dj, 1)
     depth = res.depth.cpu().numpy()
-    errs = [np.abs(depth[pt[q]:pt[q] + so.cnt[q]] - so.t[q, :so.cnt[q]]).max()
-            for q in np.nonzero(~nb.reshape(-1) & (so.cnt > 0))[0]]
+    good = np.nonzero(~nb.reshape(-1) & (so.cnt > 0))[0]
+    errs = [np.abs(depth[pt[q]:pt[q] + so.cnt[q]] - so.t[q, :so.cnt[q]]).max() for q in good]
+    ierr = intensity_err(res.intensity, pt, so, good)
     print(f"[gpu-wide] count agreement {same.mean():.5f}, max depth err {max(errs):.2e} bins "
-          f"over {len(errs)} pixels", flush=True)
+          f"over {len(errs)} pixels, max intensity err {ierr:.2e} relative", flush=True)
     assert same.mean() >= 0.999
     assert len(errs) > 0.5 * so.npix and max(errs) <= 1e-3
+    assert ierr <= 2e-5
     np.testing.assert_allclose(res.background.cpu().numpy(), so.b, rtol=1e-3, atol=1e-9)
 
 

@@ -120,3 +120,82 @@ def test_training_reduces_loss_on_a_toy():
         loss, g = cnn.loss_and_grad(x, w, target, mask)
         w, m, v = cnn.adam(w, g, m, v, step, 3e-3)
     assert loss < 0.5 * l0
+
+
+# ---------------------------------------------------------------- the network inside the loop
+
+def _loop_case(k_init):
+    import oracle
+    from paper_1905_06700_amd import synth
+    sc = synth.layers_scene(5, rows=20, cols=22, T=1024, signal=6.0, sbr=0.2)
+    prm = dict(dz=sc.meta["dz"], r_min=sc.meta["r_min"], r_init=1, k_init=k_init)
+    O = oracle.Oracle(oracle.Model(sc.irf.probs, sc.T), oracle.Params(**prm))
+    off, ent = oracle.compact(sc.Z[None])
+    s = O.init(off, ent, oracle.State(1, sc.rows, sc.cols, 4))
+    O.iterate(off, ent, s)
+    return sc, prm, O, off, ent, s
+
+
+def test_zero_network_iteration_is_the_plain_iteration_without_denoiser():
+    """With every weight zero the network moves nothing; when no pixel holds
+    four points (three peaks sought) no APSS runs either, so an iteration with
+    the learned denoiser equals the loop's iteration with no depth denoiser,
+    bit for bit."""
+    import oracle
+    sc, prm, O, off, ent, s = _loop_case(3)
+    assert s.cnt.max() <= 3 and (s.cnt > 0).mean() > 0.5
+    a = O.iterate_cnn(off, ent, s.copy(), np.zeros(cnn.N_PARAMS))
+    plain = oracle.Oracle(O.m, oracle.Params(**prm, use_apss=0))
+    b = plain.iterate(off, ent, s.copy())
+    for name in ("t", "r", "n", "cnt", "b"):
+        np.testing.assert_array_equal(getattr(a, name), getattr(b, name), err_msg=name)
+
+
+def test_four_point_pixels_take_apss_and_others_stay_under_a_zero_network():
+    """Pixels with four points (more than the network's slots) take exactly
+    the APSS result, which reads the whole pre-denoiser state; the others keep
+    depth and normals when the network outputs zero."""
+    sc, prm, O, off, ent, s = _loop_case(3)
+    s = s.copy()
+    rng = np.random.default_rng(3)
+    pick = np.nonzero(s.cnt >= 1)[0][::7][:20]          # points added 60-80 bins behind the last
+    assert pick.size == 20
+    for q in pick:
+        c = s.cnt[q]
+        while c < 4:
+            s.t[q, c] = s.t[q, c - 1] + 60.0 + rng.uniform(0, 20)
+            s.r[q, c] = 1.0
+            s.n[q, c] = (0.0, 0.0, -1.0)
+            c += 1
+        s.cnt[q] = 4
+    ref = O.apss(s.copy())
+    out = O.cnn_denoise(s.copy(), np.zeros(cnn.N_PARAMS))
+    four = s.cnt == 4
+    assert four.sum() >= 20
+    np.testing.assert_array_equal(out.t[four], ref.t[four])
+    np.testing.assert_array_equal(out.n[four], ref.n[four])
+    np.testing.assert_array_equal(out.t[~four], s.t[~four])
+    np.testing.assert_array_equal(out.n[~four], s.n[~four])
+    assert np.any(ref.t[four] != s.t[four])             # APSS did move them
+
+
+def test_bias_only_network_moves_each_slot_by_sigma_h_times_its_output():
+    """A network whose only non-zero parameters are the last layer's biases
+    outputs those biases everywhere (every hidden activation is ReLU(0) = 0):
+    slot k < cnt of a pixel with at most three points moves by sigma_h c_k,
+    clamped to [0, T - 1]; slots past the count stay.  c = (0.25, -0.5, 60)
+    (exact in FP16) sends every third slot past the last bin."""
+    sc, prm, O, off, ent, s = _loop_case(3)
+    w = np.zeros(cnn.N_PARAMS)
+    c = np.array([0.25, -0.5, 60.0])
+    w[-3:] = c
+    sig = float(np.sqrt(O.m.sigma2))
+    out = O.cnn_denoise(s.copy(), w)
+    T = O.m.T
+    for k in range(4):
+        mv = (s.cnt > k) & (s.cnt <= 3) & (k < 3)
+        want = np.clip(s.t[mv, k] + sig * c[k], 0, T - 1) if k < 3 else s.t[mv, k]
+        np.testing.assert_allclose(out.t[mv, k], want, rtol=0, atol=1e-12)
+        np.testing.assert_array_equal(out.t[~mv, k], s.t[~mv, k])
+    assert np.all(out.t[(s.cnt > 2), 2] == T - 1)
+    np.testing.assert_array_equal(out.n, s.n)
