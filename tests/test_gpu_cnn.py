@@ -159,16 +159,37 @@ def test_cnn_iteration_matches_oracle():
           f"max intensity err {dr:.2e} relative, four-point pixels {(s.cnt == 4).sum()}", flush=True)
     assert same.mean() >= 0.999
     assert dt <= bar
-    # background: equal to the background step's bar away from the filter's
-    # reach (radius ceil(4 sigma_b) = 8) of a pixel whose point count differs
-    bad = (~same).reshape(ROWS, COLS)
-    reach = np.zeros_like(bad)
-    for di in range(-8, 9):
-        for dj in range(-8, 9):
-            reach |= np.roll(np.roll(bad, di, 0), dj, 1)
-    reach = reach.reshape(-1)
+    # background: the step's bar (1e-5 relative) plus twice the oracle's own
+    # response to FP16 rounding in the network, away from the filter's reach
+    # of a pixel whose point count differs
+    resp = _bg_rounding_response(O, s, c["off"], c["ent"], w64)
+    reach = _reach((~same).reshape(ROWS, COLS)).reshape(-1)
     assert (~reach).mean() > 0.8
-    np.testing.assert_allclose(sg.b[~reach], so.b[~reach], rtol=1e-5, atol=1e-12)
+    rel = np.abs(sg.b - so.b) / np.maximum(so.b, 1e-12)
+    print(f"[gpu-cnn] background: max relative err {rel[~reach].max():.2e} (bar {1e-5 + resp:.2e})", flush=True)
+    assert rel[~reach].max() <= 1e-5 + resp
+
+
+def _reach(bad, radius=8):
+    """Pixels within the background filter's reach (ceil(4 sigma_b) = 8) of a flagged pixel (circular)."""
+    reach = np.zeros_like(bad)
+    for di in range(-radius, radius + 1):
+        for dj in range(-radius, radius + 1):
+            reach |= np.roll(np.roll(bad, di, 0), dj, 1)
+    return reach
+
+
+def _bg_rounding_response(O, s, off, ent, w):
+    """Twice the largest relative difference of the oracle's end-of-iteration
+    background between the network with FP16 storage points and the same
+    network in FP64, away from the reach of pixels whose point count the two
+    give differently.  The background step reads the depths the network
+    moved, so output rounding in the network reaches the background; the
+    GPU's network rounds (in another order) at the same points."""
+    a = O.iterate_cnn(off, ent, s.copy(), w, fp16=True)
+    b = O.iterate_cnn(off, ent, s.copy(), w, fp16=False)
+    far = ~_reach((a.cnt != b.cnt).reshape(ROWS, COLS)).reshape(-1)
+    return 2.0 * float((np.abs(a.b - b.b) / np.maximum(b.b, 1e-12))[far].max())
 
 
 def test_cnn_reconstruction_matches_oracle():
