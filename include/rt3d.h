@@ -338,6 +338,24 @@ rt3d_status rt3d_profile_read(rt3d_ctx* ctx, double* total_ms, uint64_t* launche
 rt3d_status rt3d_debug_compact(rt3d_ctx* ctx, const uint16_t* hist, uint32_t npix,
                                uint32_t* off, uint32_t* ent, uint64_t capacity, void* hip_stream);
 
+/* The same histogram -> active-bin lists as rt3d_debug_compact, for callers
+ * that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): it allocates nothing and
+ * needs no workspace.  The per-pixel counts and the scan's tile prefixes live
+ * in a fixed device array of the library, one per GPU (RT3D_NOALLOC_SCRATCH_BYTES,
+ * held until the process ends); every histogram is read twice (no staging).
+ * npix <= RT3D_NOALLOC_MAX_PIXELS, else E_INVALID; hist: device uint16
+ * [npix][bins], 16-byte aligned; off: device [npix + 1]; ent: device
+ * [capacity] (capacity > 0).  Entries beyond capacity are dropped and
+ * E_CAPACITY is written to *dev_err (caller-owned device int32, never
+ * cleared by the call; NULL: not reported).  Asynchronous on hip_stream.
+ * Calls that overlap on one GPU (other streams or host threads) share the
+ * array and race: the caller orders them. */
+#define RT3D_NOALLOC_MAX_PIXELS 4194304u
+#define RT3D_NOALLOC_SCRATCH_BYTES 16810248u
+rt3d_status rt3d_compact_noalloc(rt3d_ctx* ctx, const uint16_t* hist, uint32_t npix, uint32_t* off,
+                                 uint32_t* ent, uint64_t capacity, int32_t* dev_err, void* hip_stream);
+
 /* Photon events -> the same active-bin lists (the photons a time-tagged
  * detector reports, counted per (pixel, bin); Methods: only bins with non-zero
  * counts are kept).  ev_pixel / ev_bin: device [n_events] (n_events < 2^31, any

@@ -8,6 +8,8 @@
 // load); a wave-level prefix sum places each lane's entries.
 #include "rt3d_dev.h"
 
+#include <mutex>
+
 namespace rt3d {
 
 constexpr int SCAN_THREADS = 256;
@@ -160,9 +162,10 @@ __device__ __forceinline__ void load8(const uint16_t* __restrict__ Z, long long 
 
 // Pass 1: each pixel's histogram is read once; its non-zero bins, as entries
 // (t << 16 | z) in ascending t, go to the pixel's staging slot of CP_STAGE
-// entries (the first CP_STAGE of them when it has more), and its entry count
-// to counts[p].  One wavefront per pixel; each lane holds 8 consecutive bins
-// and a wavefront prefix sum of the lanes' non-zero counts places them.
+// entries (the first CP_STAGE of them when it has more; no staging when
+// `stage` is null), and its entry count to counts[p].  One wavefront per
+// pixel; each lane holds 8 consecutive bins and a wavefront prefix sum of the
+// lanes' non-zero counts places them.
 __global__ __launch_bounds__(64 * CP_WAVES) void k_compact_stage(const uint16_t* __restrict__ Z, long long P,
                                                                  int T, uint32_t* __restrict__ counts,
                                                                  uint32_t* __restrict__ stage)
@@ -172,7 +175,7 @@ __global__ __launch_bounds__(64 * CP_WAVES) void k_compact_stage(const uint16_t*
     const int lane = threadIdx.x & 63;
     const long long lo = p * T, hi = lo + T, total = P * T;
     const long long vs = lo >> 3, ve = (hi + 7) >> 3;
-    uint32_t* slot = stage + p * CP_STAGE;
+    uint32_t* slot = stage ? stage + p * CP_STAGE : nullptr;
     uint32_t run = 0;
     for (long long vb = vs; vb < ve; vb += 64) {       // uniform over the wave
         const long long v = vb + lane;
@@ -191,7 +194,7 @@ __global__ __launch_bounds__(64 * CP_WAVES) void k_compact_stage(const uint16_t*
         for (int k = 0; k < 8; ++k) {
             if (z[k]) {
                 const uint32_t bin = (uint32_t)((v << 3) + k - lo);
-                if (pos < CP_STAGE) slot[pos] = (bin << 16) | z[k];
+                if (slot && pos < CP_STAGE) slot[pos] = (bin << 16) | z[k];
                 ++pos;
             }
         }
@@ -202,9 +205,9 @@ __global__ __launch_bounds__(64 * CP_WAVES) void k_compact_stage(const uint16_t*
 
 // Pass 2 (after the scan of the counts into off): each pixel's entries move
 // from its staging slot to off[p]; a pixel with more than CP_STAGE entries
-// reads its histogram again.  Entries past `cap` are dropped (E_CAPACITY);
-// the scan has clamped the offsets to `cap`, so every later step sees the
-// lists cut at the capacity.
+// (every pixel when `stage` is null) reads its histogram again.  Entries past
+// `cap` are dropped (E_CAPACITY); the scan has clamped the offsets to `cap`,
+// so every later step sees the lists cut at the capacity.
 __global__ __launch_bounds__(64 * CP_WAVES) void k_compact_copy(const uint16_t* __restrict__ Z, long long P,
                                                                 int T, const uint32_t* __restrict__ off,
                                                                 const uint32_t* __restrict__ stage,
@@ -217,7 +220,7 @@ __global__ __launch_bounds__(64 * CP_WAVES) void k_compact_copy(const uint16_t* 
     const uint64_t base = off[p];
     const uint32_t n = off[p + 1] - off[p];
     bool overflow = false;
-    if (n <= (uint32_t)CP_STAGE) {
+    if (stage && n <= (uint32_t)CP_STAGE) {
         const uint32_t* slot = stage + p * CP_STAGE;
         for (uint32_t k = lane; k < n; k += 64) {
             if (base + k < cap) ent[base + k] = slot[k];
@@ -266,6 +269,62 @@ hipError_t launch_compact(const uint16_t* Z, long long P, int T, uint32_t* off, 
         hipLaunchKernelGGL(k_compact_copy, dim3(nb), dim3(64 * CP_WAVES), 0, st, Z, P, T, off, stage, ent, cap,
                            err);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// compaction with no device allocation: the per-pixel counts and the scan's
+// tile prefixes live in a fixed array of the library (one copy per GPU), and
+// no entry is staged (the copy pass reads every histogram again).
+
+constexpr long long NOALLOC_MAX_PIX = 1ll << 22;
+constexpr size_t NOALLOC_ERR_WORDS = 64;   // error sink, keeps the counts 256-byte aligned
+constexpr size_t NOALLOC_WORDS = NOALLOC_ERR_WORDS + (size_t)NOALLOC_MAX_PIX + 2 * ((size_t)(NOALLOC_MAX_PIX + SCAN_TILE - 1) / SCAN_TILE + 1);
+
+static_assert(NOALLOC_MAX_PIX == RT3D_NOALLOC_MAX_PIXELS, "rt3d.h states the pixel limit");
+static_assert(sizeof(uint32_t) * NOALLOC_WORDS == RT3D_NOALLOC_SCRATCH_BYTES, "rt3d.h states the array size");
+
+static __device__ __align__(256) uint32_t scratch[NOALLOC_WORDS];
+
+namespace {
+std::mutex g_scratch_mu;
+uint32_t* g_scratch_ptr[256];   // the array's device address on each GPU (nullptr: not looked up yet)
+}
+
+long long noalloc_max_pixels() { return NOALLOC_MAX_PIX; }
+size_t noalloc_scratch_bytes() { return sizeof(uint32_t) * NOALLOC_WORDS; }
+
+// Device address of the array on the current GPU, looked up once per device.
+hipError_t noalloc_scratch(uint32_t** ptr)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 256) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* a = nullptr;
+        e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!a) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = static_cast<uint32_t*>(a);
+    }
+    *ptr = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+// The same lists as launch_compact (the arguments checked by the caller:
+// 0 < P <= NOALLOC_MAX_PIX); err: device word for E_CAPACITY, or null.
+hipError_t launch_compact_noalloc(const uint16_t* Z, long long P, int T, uint32_t* off, uint32_t* ent,
+                                  uint64_t cap, int32_t* err, hipStream_t st)
+{
+    if (P <= 0 || P > NOALLOC_MAX_PIX) return hipErrorInvalidValue;
+    uint32_t* base = nullptr;
+    hipError_t e = noalloc_scratch(&base);
+    if (e != hipSuccess) return e;
+    int32_t* sink = reinterpret_cast<int32_t*>(base);
+    uint32_t* counts = base + NOALLOC_ERR_WORDS;
+    uint32_t* partial = counts + NOALLOC_MAX_PIX;
+    return launch_compact(Z, P, T, off, ent, cap, counts, partial, nullptr, err ? err : sink, st);
 }
 
 }  // namespace rt3d

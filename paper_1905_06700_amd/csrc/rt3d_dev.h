@@ -527,6 +527,15 @@ hipError_t launch_compact(const uint16_t* Z, long long P, int T, uint32_t* off, 
                           uint64_t cap, uint32_t* counts, uint32_t* partial, uint32_t* stage, int32_t* err,
                           hipStream_t st);
 
+// The same lists with no device allocation and no workspace: counts and scan
+// prefixes in the library's fixed per-GPU array (P <= noalloc_max_pixels(),
+// noalloc_scratch_bytes() bytes), nothing staged; err: E_CAPACITY sink or null.
+long long noalloc_max_pixels();
+size_t noalloc_scratch_bytes();
+hipError_t noalloc_scratch(uint32_t** ptr);
+hipError_t launch_compact_noalloc(const uint16_t* Z, long long P, int T, uint32_t* off, uint32_t* ent,
+                                  uint64_t cap, int32_t* err, hipStream_t st);
+
 hipError_t launch_compact_events(const uint32_t* pix, const uint16_t* bin, uint64_t n, long long P, int T,
                                  uint32_t* evoff, uint32_t* scratch, uint32_t* off, uint32_t* ent, uint64_t cap,
                                  uint32_t* counts, uint32_t* partial, int32_t* err, hipStream_t st);

@@ -747,6 +747,13 @@ rt3d_status rt3d_create(const double* irf, uint32_t irf_len, int32_t irf_origin,
         delete c;
         return RT3D_E_DEVICE;
     }
+    {   // the device address of the fixed compaction array on this GPU (rt3d_compact_noalloc)
+        uint32_t* scratch_ptr = nullptr;
+        if (noalloc_scratch(&scratch_ptr) != hipSuccess) {
+            delete c;
+            return RT3D_E_DEVICE;
+        }
+    }
     {
         c->irf.emplace_back();
         const rt3d_status bs = build_irf(irf, irf_len, irf_origin, c->T, p, c->irf[0]);
@@ -1155,6 +1162,18 @@ rt3d_status rt3d_debug_compact(rt3d_ctx* c, const uint16_t* hist, uint32_t npix,
     if (s != RT3D_OK) return s;
     RT3D_HIP(c, launch_compact(hist, npix, c->T, off, ent, capacity, w.counts, w.partial, w.stage, w.err,
                                (hipStream_t)hip_stream));
+    return RT3D_OK;
+}
+
+rt3d_status rt3d_compact_noalloc(rt3d_ctx* c, const uint16_t* hist, uint32_t npix, uint32_t* off, uint32_t* ent,
+                                 uint64_t capacity, int32_t* dev_err, void* hip_stream)
+{
+    if (!c) return RT3D_E_INVALID;
+    if (!hist || !off || !ent || npix == 0 || capacity == 0) return fail(c, RT3D_E_INVALID, "NULL pointer or zero size");
+    if (((uintptr_t)hist) % 16) return fail(c, RT3D_E_INVALID, "hist not 16-byte aligned");
+    if ((long long)npix > noalloc_max_pixels())
+        return fail(c, RT3D_E_INVALID, "npix above RT3D_NOALLOC_MAX_PIXELS (" + std::to_string(noalloc_max_pixels()) + ")");
+    RT3D_HIP(c, launch_compact_noalloc(hist, npix, c->T, off, ent, capacity, dev_err, (hipStream_t)hip_stream));
     return RT3D_OK;
 }
 

@@ -16,6 +16,7 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librt3d.so")
 K_MAX = 4
+NOALLOC_MAX_PIXELS = 4194304   # RT3D_NOALLOC_MAX_PIXELS
 
 OK, E_INVALID, E_NOMEM, E_DEVICE, E_CAPACITY, E_STATE, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 DENOISE_NONE, DENOISE_APSS = 0, 1
@@ -27,7 +28,7 @@ EXPORTS = ["rt3d_params_default", "rt3d_create", "rt3d_destroy", "rt3d_last_erro
            "rt3d_workspace_bytes", "rt3d_set_workspace", "rt3d_reconstruct", "rt3d_query",
            "rt3d_profile", "rt3d_profile_read", "rt3d_graph_create", "rt3d_graph_launch", "rt3d_graph_destroy",
            "rt3d_autotune", "rt3d_add_irf", "rt3d_debug_irf_class",
-           "rt3d_debug_compact", "rt3d_debug_compact_events", "rt3d_debug_step", "rt3d_debug_gradients",
+           "rt3d_debug_compact", "rt3d_compact_noalloc", "rt3d_debug_compact_events", "rt3d_debug_step", "rt3d_debug_gradients",
            "rt3d_cnn_set_weights", "rt3d_cnn_get_weights", "rt3d_cnn_last_gradient",
            "rt3d_cnn_forward", "rt3d_cnn_train_step"]
 KERNELS = ["compact", "init", "normals", "depth", "apss", "merge", "intensity", "ifilter", "bkg",
@@ -130,6 +131,8 @@ def lib():
         L.rt3d_graph_destroy.restype = None
         L.rt3d_debug_compact.argtypes = [vp, vp, C.c_uint32, vp, vp, C.c_uint64, vp]
         L.rt3d_debug_compact.restype = st
+        L.rt3d_compact_noalloc.argtypes = [vp, vp, C.c_uint32, vp, vp, C.c_uint64, vp, vp]
+        L.rt3d_compact_noalloc.restype = st
         L.rt3d_debug_compact_events.argtypes = [vp, vp, vp, C.c_uint64, C.c_uint32, vp, vp, vp, C.c_uint64, vp]
         L.rt3d_debug_compact_events.restype = st
         L.rt3d_debug_step.argtypes = [vp, C.c_int32, vp, vp, vp, C.POINTER(State), C.POINTER(State), vp]
@@ -411,6 +414,16 @@ class Context:
             self.workspace(1, 1, P, 1)
         self._check(lib().rt3d_debug_compact(self._h, _ptr(hist), P, _ptr(off), _ptr(ent), cap, _stream()))
         return off, ent
+
+    def compact_noalloc(self, hist, off, ent, err=None):
+        """rt3d_compact_noalloc into caller buffers (cuda int32 off [P + 1],
+        ent [capacity], optional err int32 [1]); no workspace, no allocation."""
+        hist = hist.contiguous()
+        T = hist.shape[-1]
+        P = hist.numel() // T
+        assert off.dtype == torch.int32 and off.numel() >= P + 1 and ent.dtype == torch.int32
+        self._check(lib().rt3d_compact_noalloc(self._h, _ptr(hist), P, _ptr(off), _ptr(ent), ent.numel(),
+                                               _ptr(err) if err is not None else None, _stream()))
 
     def compact_events(self, pix, bins, npix: int, capacity=None):
         """Photon events (cuda int32 pixel, int16 bin, any order) -> (off, ent)."""
