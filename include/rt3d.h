@@ -29,8 +29,9 @@
  *
  * Errors: every call returns rt3d_status; on failure rt3d_last_error(ctx)
  * gives a message (valid until the next call on that context).  Errors found
- * on the device (capacity overflow) are sticky in the context and reported
- * by rt3d_query().
+ * on the device (capacity overflow, invalid events, non-finite output values)
+ * are sticky in the context's workspace and reported by rt3d_query(); when
+ * several occur, the word holds one of them.
  */
 #ifndef RT3D_H
 #define RT3D_H
@@ -50,6 +51,8 @@ typedef int32_t rt3d_status;
 #define RT3D_E_CAPACITY    -4   /* entry or point capacity exceeded; outputs truncated */
 #define RT3D_E_STATE       -5   /* call not valid in the context's state */
 #define RT3D_E_UNSUPPORTED -6   /* valid request this build does not handle */
+#define RT3D_E_NONFINITE   -7   /* a non-finite depth, intensity or background reached the output
+                                   (e.g. an intensity beyond FP32 range from a tiny gain) */
 
 #define RT3D_K_MAX 4            /* compile-time slot capacity per pixel */
 
@@ -141,7 +144,9 @@ typedef struct rt3d_input {
      * bins strictly ascending within a pixel, counts >= 1. */
     const uint32_t* off;
     const uint32_t* ent;
-    /* Optional device float gain[P] (g of the observation model); NULL = 1. */
+    /* Optional device float gain[P] (g of the observation model); NULL = 1.
+     * 0 marks a dead pixel; a gain that is not a finite number >= 0 is treated
+     * as 0 and leaves RT3D_E_INVALID for rt3d_query. */
     const float* gain;
     /* RT3D_IN_PHOTON_EVENTS: n_events (< 2^31) photons, in any order; device
      * ev_pixel[n_events] = f * rows * cols + i * cols + j and ev_bin[n_events] = bin.
@@ -189,7 +194,12 @@ typedef struct rt3d_output {
     float*    intensity;       /* device [capacity]: intensity in photons */
     float*    normal;          /* device [capacity * 3] or NULL: unit surface normal (x, y, z) */
     float*    background;      /* device [P]: background in photons per bin */
+    double*   world_z;         /* device [capacity] or NULL: the point's world Z coordinate, depth x dz
+                                  (orthographic) or depth x dz x the z component of the pixel's unit
+                                  ray (params.persp > 0); Results, "Observation model": the map f */
 } rt3d_output;
+/* struct_size: sizeof(rt3d_output), or offsetof(rt3d_output, world_z) for
+ * callers built before world_z existed (no world_z output then). */
 /* (With params.sr = s > 1, P above is the point grid's pixel count for pt_off
  * and the lidar's for background; see rt3d_params.sr.) */
 
@@ -431,6 +441,20 @@ typedef struct rt3d_adam {
 
 /* Host FP32 weights in / out (synchronous on the null stream).  Setting the
  * weights clears the Adam moments and step.  E_INVALID when n != RT3D_CNN_PARAMS. */
+/* Checkpoint of the network and its optimiser, so training resumes exactly:
+ * rt3d_denoiser_save writes (synchronously, after the device is idle) a
+ * little-endian file: the 8 bytes "RT3DCNN\0", uint32 version (1), uint32
+ * RT3D_CNN_PARAMS, uint32 layer count (4) and each layer's input and output
+ * channels, int64 Adam step, then FP32 master weights, Adam first moments and
+ * Adam second moments (RT3D_CNN_PARAMS each, in the weight layout above), and
+ * a uint64 FNV-1a hash of every byte before it.  rt3d_denoiser_load reads such
+ * a file into the context (weights, moments and step; blocking) and marks the
+ * network loaded.  E_INVALID for a NULL path, a file that is not such a
+ * checkpoint (magic, version, sizes, hash, non-finite values: the context is
+ * left unchanged), E_DEVICE on an I/O or HIP failure, E_STATE when the context
+ * was not created with RT3D_DENOISE_CNN. */
+rt3d_status rt3d_denoiser_save(rt3d_ctx* ctx, const char* path);
+rt3d_status rt3d_denoiser_load(rt3d_ctx* ctx, const char* path);
 rt3d_status rt3d_cnn_set_weights(rt3d_ctx* ctx, const float* host, size_t n);
 rt3d_status rt3d_cnn_get_weights(rt3d_ctx* ctx, float* host, size_t n);
 

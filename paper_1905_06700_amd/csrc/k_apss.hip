@@ -14,11 +14,13 @@
 // (clipped to [-h, h]); its normal becomes grad s there, facing the sensor.
 // Jacobi: every query reads the state before the step.
 //
-// Mapping: a workgroup takes a tile of ATY x ATX pixels of one frame; it stages the
-// tile's point state with an R-pixel halo in LDS (depths in FP64, normals,
-// counts), then one thread per pixel fits and projects the pixel's points,
-// accumulating the sphere moments over the (2R+1)^2 window from LDS in FP32,
-// in coordinates local to the query (depth differences formed in FP64).
+// Mapping: a workgroup takes a tile of ATY x ATX pixels of one frame; it stages
+// the counts and the live slots of the tile with a halo in LDS (depths in
+// FP64, normals), then one thread per pixel fits and projects the pixel's
+// points, accumulating the sphere moments over the window from LDS in FP32,
+// in coordinates local to the query (depth differences formed in FP64); under
+// the orthographic map the halo covers only the pixels whose lateral offset
+// stays below h, and each neighbour is read once for all the pixel's slots.
 // Windows whose staged tile does not fit in 64 KB of LDS take a variant with
 // eight lanes per pixel reading the state from global memory, the partial
 // moment sets meeting in a fixed wavefront-shuffle tree.
@@ -38,15 +40,33 @@ inline size_t apss_tile_bytes(int R)
 
 size_t apss_lds_bytes(int R) { return apss_tile_bytes(R); }
 
+// Halo the orthographic tile kernel stages: the largest ring r of window
+// pixels (Chebyshev distance r) whose nearest pixel, r pixels away along a
+// row, lies closer than h -- pixels of farther rings hold no neighbour.  The
+// same FP32 arithmetic as the kernel's lateral pre-test.
+int apss_staged_halo(double h_apss, double p_xy, int R)
+{
+    const float h = (float)h_apss, h2 = h * h, pxy = (float)p_xy;
+    int r = 0;
+    while (r < R) {
+        const float x = (float)(r + 1) * pxy;
+        if (!(x * x < h2)) break;
+        ++r;
+    }
+    return r;
+}
+
 // PERSP: positions of the pinhole camera (t dz along each pixel's ray,
 // differences formed in FP64), no lateral pre-test, projection along the
-// query's ray; else the orthographic map.
+// query's ray; else the orthographic map, staged halo p.apss_Rs.
+// carry: also copy the count, background and intensities to `out` (else
+// `out` receives only the depths and normals of the live slots).
 template <bool PERSP>
 __global__ __launch_bounds__(ATX * ATY) void k_apss_tile(DevModel m, DevParams p, Tiles tg, DevState in,
-                                                       DevState out, int only_above)
+                                                       DevState out, int only_above, int carry)
 {
     extern __shared__ double apss_lds[];
-    const int R = p.apss_R, SX = ATX + 2 * R, NS = SX * (ATY + 2 * R);
+    const int R = PERSP ? p.apss_R : p.apss_Rs, SX = ATX + 2 * R, NS = SX * (ATY + 2 * R);
     double* tl = apss_lds;                                      // [KM][NS] depths
     float* nl = reinterpret_cast<float*>(tl + KM * NS);         // [3][KM][NS] normals
     int* cl = reinterpret_cast<int*>(nl + 3 * KM * NS);         // [NS] counts (0 outside the frame)
@@ -62,21 +82,30 @@ __global__ __launch_bounds__(ATX * ATY) void k_apss_tile(DevModel m, DevParams p
     const int fr = tile / tpf, tr = tile % tpf;
     const int i0 = (tr / tiles_x) * ATY, j0 = (tr % tiles_x) * ATX;
     const long long fbase = (long long)fr * sh.rows * sh.cols;
-    // stage the tile and its halo (every slot, so no load waits on a count)
+    // stage the counts and slot 0 of the tile and its halo (slot 0 without
+    // waiting for the count: almost every pixel holds a point) ...
     for (int x = threadIdx.x; x < NS; x += ATX * ATY) {
         const int i2 = i0 - R + x / SX, j2 = j0 - R + x % SX;
         int c = 0;
         if (i2 >= 0 && i2 < sh.rows && j2 >= 0 && j2 < sh.cols) {
             const long long pp = fbase + (long long)i2 * sh.cols + j2;
             c = load_cnt(in.cnt, pp);
+            tl[x] = in.t[pp];
 #pragma unroll
-            for (int k = 0; k < KM; ++k) {
-                tl[k * NS + x] = in.t[k * S + pp];
-#pragma unroll
-                for (int a = 0; a < 3; ++a) nl[(a * KM + k) * NS + x] = in.n[(a * KM + k) * S + pp];
-            }
+            for (int a = 0; a < 3; ++a) nl[a * KM * NS + x] = in.n[a * KM * S + pp];
         }
         cl[x] = c;
+    }
+    __syncthreads();
+    // ... then the other live slots only
+    for (int y = threadIdx.x; y < (KM - 1) * NS; y += ATX * ATY) {
+        const int k = 1 + y / NS, x = y - (k - 1) * NS;
+        if (k < cl[x]) {
+            const long long pp = fbase + (long long)(i0 - R + x / SX) * sh.cols + (j0 - R + x % SX);
+            tl[k * NS + x] = in.t[k * S + pp];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) nl[(a * KM + k) * NS + x] = in.n[(a * KM + k) * S + pp];
+        }
     }
     __syncthreads();
     const int ty = threadIdx.x / ATX, tx = threadIdx.x % ATX;
@@ -85,41 +114,100 @@ __global__ __launch_bounds__(ATX * ATY) void k_apss_tile(DevModel m, DevParams p
     const long long pix = fbase + (long long)i * sh.cols + j;
     const int xc = (ty + R) * SX + tx + R;
     const int c = cl[xc];
-    out.cnt[pix] = (uint8_t)c;
-    out.b[pix] = in.b[pix];
+    if (carry) {
+        out.cnt[pix] = (uint8_t)c;
+        out.b[pix] = in.b[pix];
 #pragma unroll
-    for (int k = 0; k < KM; ++k) out.r[k * S + pix] = in.r[k * S + pix];
+        for (int k = 0; k < KM; ++k) out.r[k * S + pix] = in.r[k * S + pix];
+    }
+    if (c == 0) return;
     const bool fit = !(only_above >= 0 && c <= only_above);
     const float h = (float)p.h_apss, h2 = h * h, inv_h2 = 1.f / h2;
     const float pxy = (float)p.p_xy;
     const double dz = p.dz;
     const double tmax = (double)(m.T - 1);
-    double vq[3] = {0.0, 0.0, 1.0};
-    float rq[3] = {0.f, 0.f, 1.f};
-    if (PERSP) {
-        ray_dir(p.persp, sh.rows, sh.cols, i, j, vq);
-        for (int a = 0; a < 3; ++a) rq[a] = (float)vq[a];
-    }
-    // pinhole camera: the query's unnormalised ray uq = (persp (j - cx), persp (i - cy), 1)
-    const float pa = (float)p.persp;
-    const float uq[3] = {pa * (float)(j - 0.5 * (sh.cols - 1)), pa * (float)(i - 0.5 * (sh.rows - 1)), 1.f};
-    const float uuq = fmaf(uq[0], uq[0], fmaf(uq[1], uq[1], 1.f));
-    for (int k = 0; k < c; ++k) {
-        const double tq = tl[k * NS + xc];
-        const float rho = (float)(tq * dz), rho2 = 0.999f * rho * rho;   // squared range, rounded down
-        float W = 0.f, Px = 0.f, Py = 0.f, Pz = 0.f, Nx = 0.f, Ny = 0.f, Nz = 0.f, PN = 0.f, PP = 0.f, nn = 0.f;
+    if constexpr (!PERSP) {
+        // every live slot of the pixel against each neighbour in turn: the
+        // neighbour's depth and normal are read from LDS once for all slots
+        double tq[KM];
+        float W[KM], Px[KM], Py[KM], Pz[KM], Nx[KM], Ny[KM], Nz[KM], PN[KM], PP[KM], nn[KM];
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+            tq[k] = k < c ? tl[k * NS + xc] : 0.0;
+            W[k] = Px[k] = Py[k] = Pz[k] = Nx[k] = Ny[k] = Nz[k] = PN[k] = PP[k] = nn[k] = 0.f;
+        }
         if (fit) {
             for (int di = -R; di <= R; ++di) {
-                const float yy0 = (float)di * pxy;
+                const float yy = (float)di * pxy;
                 for (int dj = -R; dj <= R; ++dj) {
-                    // orthographic: pixels whose lateral offset alone reaches h hold no neighbour
-                    const float yx0 = (float)dj * pxy;
-                    const float dl = fmaf(yx0, yx0, yy0 * yy0);
-                    if (!PERSP && !(dl < h2)) continue;
+                    // pixels whose lateral offset alone reaches h hold no neighbour
+                    const float yx = (float)dj * pxy;
+                    const float dl = fmaf(yx, yx, yy * yy);
+                    if (!(dl < h2)) continue;
                     const int x = xc + di * SX + dj;
                     const int cc = cl[x];
-                    double v2[3] = {0.0, 0.0, 1.0};
-                    if (PERSP && cc > 0) {
+#pragma unroll
+                    for (int k2 = 0; k2 < KM; ++k2) {
+                        if (k2 >= cc) break;
+                        const double t2 = tl[k2 * NS + x];
+                        const float nx = nl[(0 * KM + k2) * NS + x];
+                        const float ny = nl[(1 * KM + k2) * NS + x];
+                        const float nz = nl[(2 * KM + k2) * NS + x];
+                        const float yn = fmaf(yx, nx, yy * ny);
+#pragma unroll
+                        for (int k = 0; k < KM; ++k) {
+                            if (k >= c) break;
+                            const float yz = (float)((t2 - tq[k]) * dz);
+                            const float d2 = fmaf(yz, yz, dl);
+                            if (!(d2 < h2)) continue;
+                            float a = 1.f - d2 * inv_h2;
+                            a = a * a;
+                            const float w = a * a;
+                            W[k] += w;
+                            Px[k] = fmaf(w, yx, Px[k]);
+                            Py[k] = fmaf(w, yy, Py[k]);
+                            Pz[k] = fmaf(w, yz, Pz[k]);
+                            Nx[k] = fmaf(w, nx, Nx[k]);
+                            Ny[k] = fmaf(w, ny, Ny[k]);
+                            Nz[k] = fmaf(w, nz, Nz[k]);
+                            PN[k] = fmaf(w, fmaf(yz, nz, yn), PN[k]);
+                            PP[k] = fmaf(w, d2, PP[k]);
+                            nn[k] += 1.f;
+                        }
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+            if (k >= c) break;
+            double tn = tq[k];
+            float on[3] = {nl[(0 * KM + k) * NS + xc], nl[(1 * KM + k) * NS + xc], nl[(2 * KM + k) * NS + xc]};
+            apss_project(fit && nn[k] >= (float)p.m_min, W[k], Px[k], Py[k], Pz[k], Nx[k], Ny[k], Nz[k], PN[k],
+                         PP[k], h, h2, dz, tmax, tn, on);
+            out.t[k * S + pix] = tn;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) out.n[(a * KM + k) * S + pix] = on[a];
+        }
+    } else {
+        double vq[3];
+        float rq[3];
+        ray_dir(p.persp, sh.rows, sh.cols, i, j, vq);
+        for (int a = 0; a < 3; ++a) rq[a] = (float)vq[a];
+        // the query's unnormalised ray uq = (persp (j - cx), persp (i - cy), 1)
+        const float pa = (float)p.persp;
+        const float uq[3] = {pa * (float)(j - 0.5 * (sh.cols - 1)), pa * (float)(i - 0.5 * (sh.rows - 1)), 1.f};
+        const float uuq = fmaf(uq[0], uq[0], fmaf(uq[1], uq[1], 1.f));
+        for (int k = 0; k < c; ++k) {
+            const double tq = tl[k * NS + xc];
+            const float rho = (float)(tq * dz), rho2 = 0.999f * rho * rho;   // squared range, rounded down
+            float W = 0.f, Px = 0.f, Py = 0.f, Pz = 0.f, Nx = 0.f, Ny = 0.f, Nz = 0.f, PN = 0.f, PP = 0.f, nn = 0.f;
+            if (fit) {
+                for (int di = -R; di <= R; ++di) {
+                    for (int dj = -R; dj <= R; ++dj) {
+                        const int x = xc + di * SX + dj;
+                        const int cc = cl[x];
+                        if (cc == 0) continue;
                         // every point of this pixel's ray is at least rho_q sin(theta) from
                         // the query (theta: the angle between the two rays); skip the pixel
                         // when that reaches h
@@ -129,48 +217,43 @@ __global__ __launch_bounds__(ATX * ATY) void k_apss_tile(DevModel m, DevParams p
                         const float uu2 = fmaf(uq[0] + ax, uq[0] + ax, fmaf(uq[1] + ay, uq[1] + ay, 1.f));
                         const float sin2 = (cx2 * cx2 + cy2 * cy2 + cz2 * cz2) / (uuq * uu2);
                         if (!(rho2 * sin2 < h2)) continue;
+                        double v2[3];
                         ray_dir(p.persp, sh.rows, sh.cols, i + di, j + dj, v2);
-                    }
-                    for (int k2 = 0; k2 < cc; ++k2) {
-                        const double t2 = tl[k2 * NS + x];
-                        float yx = yx0, yy = yy0, yz, d2;
-                        if (PERSP) {
-                            yx = (float)((t2 * v2[0] - tq * vq[0]) * dz);
-                            yy = (float)((t2 * v2[1] - tq * vq[1]) * dz);
-                            yz = (float)((t2 * v2[2] - tq * vq[2]) * dz);
-                            d2 = fmaf(yx, yx, fmaf(yy, yy, yz * yz));
-                        } else {
-                            yz = (float)((t2 - tq) * dz);
-                            d2 = fmaf(yz, yz, dl);
+                        for (int k2 = 0; k2 < cc; ++k2) {
+                            const double t2 = tl[k2 * NS + x];
+                            const float yx = (float)((t2 * v2[0] - tq * vq[0]) * dz);
+                            const float yy = (float)((t2 * v2[1] - tq * vq[1]) * dz);
+                            const float yz = (float)((t2 * v2[2] - tq * vq[2]) * dz);
+                            const float d2 = fmaf(yx, yx, fmaf(yy, yy, yz * yz));
+                            if (!(d2 < h2)) continue;
+                            float a = 1.f - d2 * inv_h2;
+                            a = a * a;
+                            const float w = a * a;
+                            const float nx = nl[(0 * KM + k2) * NS + x];
+                            const float ny = nl[(1 * KM + k2) * NS + x];
+                            const float nz = nl[(2 * KM + k2) * NS + x];
+                            W += w;
+                            Px = fmaf(w, yx, Px);
+                            Py = fmaf(w, yy, Py);
+                            Pz = fmaf(w, yz, Pz);
+                            Nx = fmaf(w, nx, Nx);
+                            Ny = fmaf(w, ny, Ny);
+                            Nz = fmaf(w, nz, Nz);
+                            PN = fmaf(w, yx * nx + yy * ny + yz * nz, PN);
+                            PP = fmaf(w, d2, PP);
+                            nn += 1.f;
                         }
-                        if (!(d2 < h2)) continue;
-                        float a = 1.f - d2 * inv_h2;
-                        a = a * a;
-                        const float w = a * a;
-                        const float nx = nl[(0 * KM + k2) * NS + x];
-                        const float ny = nl[(1 * KM + k2) * NS + x];
-                        const float nz = nl[(2 * KM + k2) * NS + x];
-                        W += w;
-                        Px = fmaf(w, yx, Px);
-                        Py = fmaf(w, yy, Py);
-                        Pz = fmaf(w, yz, Pz);
-                        Nx = fmaf(w, nx, Nx);
-                        Ny = fmaf(w, ny, Ny);
-                        Nz = fmaf(w, nz, Nz);
-                        PN = fmaf(w, yx * nx + yy * ny + yz * nz, PN);
-                        PP = fmaf(w, d2, PP);
-                        nn += 1.f;
                     }
                 }
             }
-        }
-        double tn = tq;
-        float on[3] = {nl[(0 * KM + k) * NS + xc], nl[(1 * KM + k) * NS + xc], nl[(2 * KM + k) * NS + xc]};
-        apss_project(fit && nn >= (float)p.m_min, W, Px, Py, Pz, Nx, Ny, Nz, PN, PP, h, h2, dz, tmax, tn, on,
-                     PERSP ? rq : nullptr);
-        out.t[k * S + pix] = tn;
+            double tn = tq;
+            float on[3] = {nl[(0 * KM + k) * NS + xc], nl[(1 * KM + k) * NS + xc], nl[(2 * KM + k) * NS + xc]};
+            apss_project(fit && nn >= (float)p.m_min, W, Px, Py, Pz, Nx, Ny, Nz, PN, PP, h, h2, dz, tmax, tn, on,
+                         rq);
+            out.t[k * S + pix] = tn;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) out.n[(a * KM + k) * S + pix] = on[a];
+            for (int a = 0; a < 3; ++a) out.n[(a * KM + k) * S + pix] = on[a];
+        }
     }
 }
 
@@ -291,19 +374,20 @@ __global__ __launch_bounds__(256) void k_merge(DevModel m, DevParams p, Shape sh
 }
 
 hipError_t launch_apss_tiles(const DevModel& m, const DevParams& p, const Tiles& tg, DevState in, DevState out,
-                             int only_above, hipStream_t st)
+                             int only_above, bool carry, hipStream_t st)
 {
     if (tg.n == 0 || tg.tile0[tg.n] == 0) return hipSuccess;
-    const size_t lds = apss_tile_bytes(p.apss_R);
     if (p.persp > 0.0) {   // the host admits the perspective camera only where the tile fits
+        const size_t lds = apss_tile_bytes(p.apss_R);
         if (lds > 65536) return hipErrorInvalidValue;
         hipLaunchKernelGGL(k_apss_tile<true>, dim3((unsigned)tg.tile0[tg.n]), dim3(ATX * ATY), lds, st, m, p, tg, in,
-                           out, only_above);
+                           out, only_above, (int)carry);
         return hipGetLastError();
     }
+    const size_t lds = apss_tile_bytes(p.apss_Rs);
     if (lds <= 65536) {
-        hipLaunchKernelGGL(k_apss_tile<false>, dim3((unsigned)tg.tile0[tg.n]), dim3(ATX * ATY), lds, st, m, p, tg, in,
-                           out, only_above);
+        hipLaunchKernelGGL(k_apss_tile<false>, dim3((unsigned)tg.tile0[tg.n]), dim3(ATX * ATY), lds, st, m, p, tg,
+                           in, out, only_above, (int)carry);
         return hipGetLastError();
     }
     for (int g = 0; g < tg.n; ++g) {
@@ -318,7 +402,7 @@ hipError_t launch_apss(const DevModel& m, const DevParams& p, const Shape& sh, D
                        int only_above, hipStream_t st)
 {
     if (sh.P == 0) return hipSuccess;
-    return launch_apss_tiles(m, p, tiles_of(sh), in, out, only_above, st);
+    return launch_apss_tiles(m, p, tiles_of(sh), in, out, only_above, true, st);
 }
 
 hipError_t launch_merge(const DevModel& m, const DevParams& p, const Shape& sh, DevState s, hipStream_t st)

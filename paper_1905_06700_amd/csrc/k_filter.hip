@@ -261,6 +261,9 @@ __global__ __launch_bounds__(256) void k_out_count(Shape sh, const uint8_t* __re
     counts[pix] = cnt[pix];
 }
 
+// Packs the slots into the caller's point lists; a non-finite depth,
+// intensity or background sets E_NONFINITE (overflow of the caller's
+// capacity sets E_CAPACITY).
 __global__ __launch_bounds__(256) void k_out_pack(Shape sh, DevState s, const uint32_t* __restrict__ pt_off,
                                                   uint32_t capacity, double* __restrict__ depth,
                                                   float* __restrict__ inten, float* __restrict__ normal,
@@ -271,22 +274,67 @@ __global__ __launch_bounds__(256) void k_out_pack(Shape sh, DevState s, const ui
     if (pix >= P) return;
     const int c = load_cnt(s.cnt, pix);
     const uint32_t base = pt_off[pix];
-    bool overflow = false;
+    bool overflow = false, nonfinite = false;
     for (int k = 0; k < c; ++k) {
         const uint64_t at = (uint64_t)base + k;
+        const double t = s.t[k * P + pix];
+        const float r = s.r[k * P + pix];
+        nonfinite |= !isfinite(t) || !isfinite(r);
         if (at >= capacity) {
             overflow = true;
             continue;
         }
-        depth[at] = s.t[k * P + pix];
-        inten[at] = s.r[k * P + pix];
+        depth[at] = t;
+        inten[at] = r;
         if (normal) {
 #pragma unroll
             for (int a = 0; a < 3; ++a) normal[at * 3 + a] = s.n[(a * KM + k) * P + pix];
         }
     }
-    if (pix < n_bg) bg[pix] = s.b[pix];
+    if (pix < n_bg) {
+        const float b = s.b[pix];
+        nonfinite |= !isfinite(b);
+        bg[pix] = b;
+    }
     if (overflow) *err = RT3D_E_CAPACITY;
+    if (nonfinite) *err = RT3D_E_NONFINITE;
+}
+
+// A gain that is not a finite non-negative number sets E_INVALID (the
+// kernels treat such a pixel as dead).
+__global__ __launch_bounds__(256) void k_check_gain(const float* __restrict__ gain, long long P,
+                                                    int32_t* __restrict__ err)
+{
+    const long long pix = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pix >= P) return;
+    const float g = gain[pix];
+    if (!(g >= 0.f && g <= 3.402823466e38f)) *err = RT3D_E_INVALID;
+}
+
+// World Z of the packed points of one group of equal-size frames (the map f
+// of the observation model): depth x dz, times the z component of the
+// pixel's unit ray under the pinhole camera.  s is the group's state, pt_off
+// the group's first pixel's entry of the output offsets.
+__global__ __launch_bounds__(256) void k_out_world_z(Shape sh, DevState s, const uint32_t* __restrict__ pt_off,
+                                                     uint32_t capacity, double dz, double persp,
+                                                     double* __restrict__ wz)
+{
+    const long long pix = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pix >= sh.P) return;
+    const int c = load_cnt(s.cnt, pix);
+    if (c == 0) return;
+    double scale = dz;
+    if (persp > 0.0) {
+        const long long q = pix % ((long long)sh.rows * sh.cols);
+        double v[3];
+        ray_dir(persp, sh.rows, sh.cols, (int)(q / sh.cols), (int)(q % sh.cols), v);
+        scale = dz * v[2];
+    }
+    const uint32_t base = pt_off[pix];
+    for (int k = 0; k < c; ++k) {
+        const uint64_t at = (uint64_t)base + k;
+        if (at < capacity) wz[at] = s.t[k * sh.S + pix] * scale;
+    }
 }
 
 static inline unsigned nblk(long long n) { return (unsigned)((n + 255) / 256); }
@@ -357,6 +405,22 @@ hipError_t launch_output(const Shape& sh, DevState s, rt3d_output* out, uint32_t
     if (sh.P > 0)
         hipLaunchKernelGGL(k_out_pack, dim3(nblk(sh.P)), dim3(256), 0, st, sh, s, out->pt_off, out->capacity,
                            out->depth, out->intensity, out->normal, out->background, n_bg, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_gain(const float* gain, long long P, int32_t* err, hipStream_t st)
+{
+    if (!gain || P == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_check_gain, dim3(nblk(P)), dim3(256), 0, st, gain, P, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_world_z(const Shape& g, long long base, DevState s, const rt3d_output* out, double dz,
+                          double persp, hipStream_t st)
+{
+    if (g.P == 0 || !out->world_z) return hipSuccess;
+    hipLaunchKernelGGL(k_out_world_z, dim3(nblk(g.P)), dim3(256), 0, st, g, state_at(s, base), out->pt_off + base,
+                       out->capacity, dz, persp, out->world_z);
     return hipGetLastError();
 }
 

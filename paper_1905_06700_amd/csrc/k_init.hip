@@ -548,7 +548,7 @@ __device__ __forceinline__ void init_pixel(const DevModel& m, const DevParams& p
             re = off[base + min(sh.cols - 1, j + R) + 1];
         }
     }
-    const float G = gain ? gain[pix] : 1.f;
+    const float G = gain_at(gain, pix);
     if (!(G > 0.f)) {
         if (lane == 0) {
             s.cnt[pix] = 0;

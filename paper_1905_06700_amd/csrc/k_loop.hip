@@ -78,7 +78,7 @@ __device__ __forceinline__ void depth_1(const DevModel& m, const DevParams& p, l
 {
     PixPoints q;
     load_points(s, S, pix, q);
-    const float G = gain ? gain[pix] : 1.f;
+    const float G = gain_at(gain, pix);
     if (q.c == 0 || !(G > 0.f)) return;
     float sz, shh[KM], shp[KM];
     accumulate_1(m, q, s.b[pix], G, ent, off[pix], off[pix + 1], sz, shh, shp);
@@ -118,7 +118,7 @@ __device__ __forceinline__ void intensity_1(const DevModel& m, const DevParams& 
         store_points(s, S, pix, t, r, nx, ny, nz, c);
         load_points(s, S, pix, q);
     }
-    const float G = gain ? gain[pix] : 1.f;
+    const float G = gain_at(gain, pix);
     if (q.c == 0 || !(G > 0.f)) return;
     float sz, shh[KM], shp[KM];
     accumulate_1(m, q, s.b[pix], G, ent, off[pix], off[pix + 1], sz, shh, shp);
@@ -138,7 +138,7 @@ __device__ __forceinline__ void background_1(const DevModel& m, const DevParams&
 {
     PixPoints q;
     load_points(s, S, pix, q);
-    const float G = gain ? gain[pix] : 1.f;
+    const float G = gain_at(gain, pix);
     const float bb = s.b[pix];
     if (!(G > 0.f)) {
         bdst[pix] = bb;

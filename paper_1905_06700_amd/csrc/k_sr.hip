@@ -78,7 +78,7 @@ __global__ __launch_bounds__(SR_GROUP * SR_GROUPS) void k_sr_step(DevModel m, De
     PixPoints pts;
     load_points(st, Pf, q, pts);
     if (!in_block) pts.c = 0;
-    const float G = valid ? (gain ? gain[pq] : 1.f) : 0.f;
+    const float G = valid ? gain_at(gain, pq) : 0.f;
     const float bb = st.b[pq];
     const bool live = G > 0.f;                      // group-uniform
     // the block's points staged in LDS, lane after lane (prefix of the counts in the group)

@@ -186,7 +186,7 @@ __device__ __forceinline__ Lane lane_setup(const DevModel& m, const DevState& s,
     L.live = L.member;
     const long long pp = L.live ? L.pix : 0;
     const uint32_t e0 = off[pp], e1 = off[pp + 1];
-    L.G = L.live ? (gain ? gain[pp] : 1.f) : 0.f;
+    L.G = L.live ? gain_at(gain, pp) : 0.f;
     load_points(s, P, pp, L.q);
     if (!L.live) L.q.c = 0;
     const bool work = L.live && L.G > 0.f && (!need_points || L.q.c > 0);

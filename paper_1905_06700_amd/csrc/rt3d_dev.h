@@ -55,6 +55,7 @@ __device__ __forceinline__ bool in_class(const DevModel& m, long long pix)
 // Parameters as the kernels use them.
 struct DevParams {
     int    k_max, k_init, r_init, n_min, m_min, apss_R;
+    int    apss_Rs;   // halo the orthographic APSS tile stages (rings beyond it are farther than h)
     int    ilp_box;   // intensity low-pass divisor: 0 = 1 + neighbours found, 1 = 1 + surrounding pixels
     double p_xy, dz, h_apss, h_int;
     double beta_t, dmax, beta_r, beta_b, r_min, d_merge, b_min, kappa;
@@ -347,6 +348,15 @@ __device__ __forceinline__ void apss_project(bool ok, float W, float Px, float P
     }
 }
 
+// Detector gain of pixel p (Results, "Observation model": g, 0 for a dead
+// pixel); a gain that is not a finite non-negative number also counts as
+// dead (rt3d_reconstruct reports it as E_INVALID).
+__device__ __forceinline__ float gain_at(const float* __restrict__ gain, long long p)
+{
+    const float g = gain ? gain[p] : 1.f;
+    return (g > 0.f && g <= 3.402823466e38f) ? g : 0.f;
+}
+
 struct PixPoints {
     int    c;
     int    a[KM];    // floor(t)
@@ -567,9 +577,14 @@ hipError_t launch_gradients(const DevModel& m, const DevParams& p, const Shape& 
                             const uint32_t* off, const uint32_t* ent, const float* gain,
                             DevState s, float* gt, float* gr, float* gb, hipStream_t st);
 
-// only_above >= 0: pixels with at most that many points are copied, not fitted
+// only_above >= 0: pixels with at most that many points are copied, not fitted;
+// carry: `out` also receives the counts, backgrounds and intensities (else only
+// the depths and normals of the live slots)
 hipError_t launch_apss_tiles(const DevModel& m, const DevParams& p, const Tiles& tg, DevState in, DevState out,
-                             int only_above, hipStream_t st);
+                             int only_above, bool carry, hipStream_t st);
+// The halo the orthographic APSS tile stages for support h_apss, pitch p_xy
+// and window radius R = ceil(h_apss / p_xy).
+int apss_staged_halo(double h_apss, double p_xy, int R);
 // LDS bytes of the APSS tile kernel for window radius R (the perspective camera needs it to fit 64 KB)
 size_t apss_lds_bytes(int R);
 hipError_t launch_ifilter_tiles(const DevParams& p, const Tiles& tg, DevState in, DevState out, hipStream_t st);
@@ -598,6 +613,13 @@ hipError_t launch_loop(const DevModel& m, const DevParams& p, const Shape& sh, c
 // n_bg: background values written (sh.P, or the lidar pixels under super-resolution)
 hipError_t launch_output(const Shape& sh, DevState s, rt3d_output* out, uint32_t* counts,
                          uint32_t* partial, int32_t* err, long long n_bg, hipStream_t st);
+// E_INVALID into *err when a gain of gain[0 .. P-1] is not a finite
+// non-negative number.
+hipError_t launch_check_gain(const float* gain, long long P, int32_t* err, hipStream_t st);
+// World Z of the packed points of the group of frames g whose first pixel is
+// `base` (out->world_z non-null), after launch_output.
+hipError_t launch_world_z(const Shape& g, long long base, DevState s, const rt3d_output* out, double dz,
+                          double persp, hipStream_t st);
 
 // Super-resolution: s x s point-grid pixels per lidar pixel.  lid: the lidar
 // frames; the state's point arrays have slot stride Pf (point-grid pixels),

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -449,6 +450,7 @@ DevParams dev_params(const rt3d_ctx* c, int k = 0)
     d.n_min = p.n_min;
     d.m_min = p.m_min;
     d.apss_R = c->apss_R;
+    d.apss_Rs = apss_staged_halo(p.h_apss, p.p_xy, c->apss_R);
     d.ilp_box = p.ilp_box;
     d.p_xy = p.p_xy;
     d.dz = p.dz;
@@ -586,8 +588,14 @@ int n_classes(const rt3d_ctx* c, const uint8_t* cls) { return cls ? (int)c->irf.
 // Per-pixel steps run once over the batch (sh), once per IRF class with a
 // class map cls; steps that read neighbouring pixels run once per group of
 // equally sized frames.
+// One iteration on the state whose planes `cur` points at; `alt` holds the
+// other buffer of each plane.  Kernels that read neighbours' values write the
+// planes they change to the other buffer (APSS: depths and normals; the
+// intensity filter: depths, intensities and counts), kernels that read only
+// their own pixel write in place, and the two sets of pointers are swapped
+// plane by plane, so no kernel copies a plane it does not change.
 rt3d_status iterate(rt3d_ctx* c, const Shape& sh, const std::vector<Group>& groups, const uint32_t* off,
-                    const uint32_t* ent, const float* gain, DevState A, DevState B, float* btmp,
+                    const uint32_t* ent, const float* gain, DevState& cur, DevState& alt, float* btmp,
                     const CnnBuffers* cnn, const uint8_t* cls, hipStream_t st, const uint32_t* lst = nullptr,
                     const uint32_t* lst_meta = nullptr)
 {
@@ -596,9 +604,8 @@ rt3d_status iterate(rt3d_ctx* c, const Shape& sh, const std::vector<Group>& grou
     const int nc = n_classes(c, cls);
     for (int k = 0; k < nc; ++k)
         RT3D_LAUNCH(c, RT3D_KERNEL_DEPTH, st,
-                    launch_depth_step(dev_model(c, k, cls, lst, lst_meta), dev_params(c, k), sh, off, ent, gain, A,
+                    launch_depth_step(dev_model(c, k, cls, lst, lst_meta), dev_params(c, k), sh, off, ent, gain, cur,
                                       st));
-    DevState cur = A;
     // the groups as tile tables of at most TILE_GROUPS groups (one launch each)
     std::vector<Tiles> tiles(1, Tiles{});
     for (const Group& g : groups)
@@ -607,34 +614,58 @@ rt3d_status iterate(rt3d_ctx* c, const Shape& sh, const std::vector<Group>& grou
             tiles_add(tiles.back(), g.base, g.sh);
         }
     if (c->p.denoiser == RT3D_DENOISE_APSS) {
+        DevState out = cur;
+        out.t = alt.t;
+        out.n = alt.n;
         for (const Tiles& tg : tiles)
-            RT3D_LAUNCH(c, RT3D_KERNEL_APSS, st, launch_apss_tiles(m, p, tg, A, B, -1, st));
-        cur = B;
+            RT3D_LAUNCH(c, RT3D_KERNEL_APSS, st, launch_apss_tiles(m, p, tg, cur, out, -1, false, st));
+        std::swap(cur.t, alt.t);
+        std::swap(cur.n, alt.n);
     } else if (c->p.denoiser == RT3D_DENOISE_CNN) {
         // APSS only for pixels holding more points than the network's three slots
-        RT3D_LAUNCH(c, RT3D_KERNEL_APSS, st, launch_apss(m, p, sh, A, B, 3, st));
-        RT3D_LAUNCH(c, RT3D_KERNEL_CNN, st, launch_cnn_forward(sh, B, (float)std::sqrt(c->irf[0].sigma2), c->cnn, *cnn, st));
-        RT3D_HIP(c, launch_cnn_apply(sh, *cnn, (float)std::sqrt(c->irf[0].sigma2), (double)(c->T - 1), B, st));
-        cur = B;
+        RT3D_LAUNCH(c, RT3D_KERNEL_APSS, st, launch_apss(m, p, sh, cur, alt, 3, st));
+        RT3D_LAUNCH(c, RT3D_KERNEL_CNN, st,
+                    launch_cnn_forward(sh, alt, (float)std::sqrt(c->irf[0].sigma2), c->cnn, *cnn, st));
+        RT3D_HIP(c, launch_cnn_apply(sh, *cnn, (float)std::sqrt(c->irf[0].sigma2), (double)(c->T - 1), alt, st));
+        std::swap(cur, alt);
     } else {
-        RT3D_HIP(c, launch_copy_state(sh, A, B, st));
-        cur = B;
+        RT3D_HIP(c, launch_copy_state(sh, cur, alt, st));
+        std::swap(cur, alt);
     }
     // the in-pixel merge runs fused ahead of the intensity step
     for (int k = 0; k < nc; ++k)
         RT3D_LAUNCH(c, RT3D_KERNEL_INTENSITY, st,
                     launch_intensity_step(dev_model(c, k, cls, lst, lst_meta), dev_params(c, k), sh, off, ent, gain,
                                           cur, true, st));
-    for (const Tiles& tg : tiles)
-        RT3D_LAUNCH(c, RT3D_KERNEL_IFILTER, st, launch_ifilter_tiles(p, tg, cur, A, st));
-    // the background step writes btmp; the filter brings it back into A.b
+    {   // normals and background move with their own pixel only: in place
+        DevState out = cur;
+        out.t = alt.t;
+        out.r = alt.r;
+        out.cnt = alt.cnt;
+        for (const Tiles& tg : tiles)
+            RT3D_LAUNCH(c, RT3D_KERNEL_IFILTER, st, launch_ifilter_tiles(p, tg, cur, out, st));
+        std::swap(cur.t, alt.t);
+        std::swap(cur.r, alt.r);
+        std::swap(cur.cnt, alt.cnt);
+    }
+    // the background step writes btmp; the filter brings it back into cur.b
     for (int k = 0; k < nc; ++k)
         RT3D_LAUNCH(c, RT3D_KERNEL_BKG, st,
-                    launch_bg_step(dev_model(c, k, cls, lst, lst_meta), dev_params(c, k), sh, off, ent, gain, A, btmp,
-                                   st));
+                    launch_bg_step(dev_model(c, k, cls, lst, lst_meta), dev_params(c, k), sh, off, ent, gain, cur,
+                                   btmp, st));
     for (const Tiles& tg : tiles)
         RT3D_LAUNCH(c, RT3D_KERNEL_BFILTER, st,
-                    launch_bfilter_tiles(c->d_bw, c->rb, tg, (float)c->p.b_min, btmp, A.b, B.b, st));
+                    launch_bfilter_tiles(c->d_bw, c->rb, tg, (float)c->p.b_min, btmp, cur.b, alt.b, st));
+    return RT3D_OK;
+}
+
+// Copies the state whose planes `cur` points at into `home`, when any of its
+// planes sits in the other buffer.
+rt3d_status settle(rt3d_ctx* c, const Shape& sh, const DevState& cur, const DevState& home, hipStream_t st)
+{
+    if (cur.t == home.t && cur.r == home.r && cur.n == home.n && cur.cnt == home.cnt && cur.b == home.b)
+        return RT3D_OK;
+    RT3D_HIP(c, launch_copy_state(sh, cur, home, st));
     return RT3D_OK;
 }
 
@@ -892,11 +923,17 @@ rt3d_status rt3d_set_workspace(rt3d_ctx* c, void* dev_ptr, size_t bytes, uint32_
 
 extern "C" {
 
-rt3d_status rt3d_reconstruct(rt3d_ctx* c, const rt3d_input* in, rt3d_output* out, void* hip_stream)
+rt3d_status rt3d_reconstruct(rt3d_ctx* c, const rt3d_input* in, rt3d_output* out_arg, void* hip_stream)
 {
     if (!c) return RT3D_E_INVALID;
     if (!in || in->struct_size != sizeof(rt3d_input)) return fail(c, RT3D_E_INVALID, "input NULL or struct_size mismatch");
-    if (!out || out->struct_size != sizeof(rt3d_output)) return fail(c, RT3D_E_INVALID, "output NULL or struct_size mismatch");
+    if (!out_arg || (out_arg->struct_size != sizeof(rt3d_output) &&
+                     out_arg->struct_size != offsetof(rt3d_output, world_z)))
+        return fail(c, RT3D_E_INVALID, "output NULL or struct_size mismatch");
+    // a caller's struct from before world_z: read only the fields it has
+    rt3d_output out_v{};
+    std::memcpy(&out_v, out_arg, out_arg->struct_size);
+    rt3d_output* out = &out_v;
     if (!out->pt_off || !out->depth || !out->intensity || !out->background || out->capacity == 0)
         return fail(c, RT3D_E_INVALID, "output pointers NULL or capacity 0");
     // frames and their groups of equal size (one group when every frame is rows x cols)
@@ -973,6 +1010,7 @@ rt3d_status rt3d_reconstruct(rt3d_ctx* c, const rt3d_input* in, rt3d_output* out
         return fail(c, RT3D_E_UNSUPPORTED, "unknown input kind");
     }
     c->last_P = sh.P;
+    RT3D_HIP(c, launch_check_gain(in->gain, sh.P, w.err, st));
     const DevModel m = dev_model(c);
     const DevParams p = dev_params(c);
     // the layout of this batch: its groups' bases and shapes
@@ -1005,14 +1043,22 @@ rt3d_status rt3d_reconstruct(rt3d_ctx* c, const rt3d_input* in, rt3d_output* out
         RT3D_LAUNCH(c, RT3D_KERNEL_LOOP, st,
                     launch_loop(m, p, sh, off, ent, in->gain, w.A, w.B, w.btmp, c->d_bw, c->rb, c->p.n_iter, st));
     } else {
+        DevState cur = w.A, alt = w.B;
         for (int it = 0; it < c->p.n_iter; ++it) {
-            s = iterate(c, sh, groups, off, ent, in->gain, w.A, w.B, w.btmp, &w.cnn, cls, st, w.cls_list,
+            s = iterate(c, sh, groups, off, ent, in->gain, cur, alt, w.btmp, &w.cnn, cls, st, w.cls_list,
                         w.cls_meta);
             if (s != RT3D_OK) return s;
         }
+        s = settle(c, sh, cur, w.A, st);
+        if (s != RT3D_OK) return s;
     }
     RT3D_LAUNCH(c, RT3D_KERNEL_OUTPUT, st,
                 launch_output(point_grid(sh, c->p.sr), w.A, out, w.counts, w.partial, w.err, sh.P, st));
+    if (out->world_z)
+        for (const Group& g : groups)
+            RT3D_LAUNCH(c, RT3D_KERNEL_OUTPUT, st,
+                        launch_world_z(c->p.sr > 1 ? point_grid(g.sh, c->p.sr) : g.sh, g.base, w.A, out, c->p.dz,
+                                       c->p.persp, st));
     c->state_layout = layout;
     return RT3D_OK;
 }
@@ -1324,7 +1370,10 @@ rt3d_status rt3d_debug_step(rt3d_ctx* c, int32_t step, const uint32_t* off, cons
         Workspace w;
         rt3d_status s = need_ws(c, sh.P, w);
         if (s != RT3D_OK) return s;
-        return iterate(c, sh, std::vector<Group>{Group{0, sh}}, off, ent, gain, O, w.B, w.btmp, &w.cnn, cls, st);
+        DevState cur = O, alt = w.B;
+        s = iterate(c, sh, std::vector<Group>{Group{0, sh}}, off, ent, gain, cur, alt, w.btmp, &w.cnn, cls, st);
+        if (s != RT3D_OK) return s;
+        return settle(c, sh, cur, O, st);
     }
     default:
         return fail(c, RT3D_E_INVALID, "unknown step");
@@ -1409,6 +1458,100 @@ rt3d_status rt3d_cnn_get_weights(rt3d_ctx* c, float* host, size_t n)
     if (!host || n != (size_t)CNN_PARAMS) return fail(c, RT3D_E_INVALID, "weights NULL or n != RT3D_CNN_PARAMS");
     RT3D_HIP(c, hipDeviceSynchronize());
     RT3D_HIP(c, hipMemcpy(host, c->cnn.master, sizeof(float) * n, hipMemcpyDeviceToHost));
+    return RT3D_OK;
+}
+
+// Checkpoint file of the network and its optimiser (layout in rt3d.h).
+namespace {
+constexpr char CKPT_MAGIC[8] = {'R', 'T', '3', 'D', 'C', 'N', 'N', '\0'};
+constexpr uint32_t CKPT_VERSION = 1;
+
+uint64_t fnv1a(const uint8_t* p, size_t n, uint64_t h = 1469598103934665603ull)
+{
+    for (size_t k = 0; k < n; ++k) {
+        h ^= p[k];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+// The header's bytes: magic, version, parameter count, layer count, each
+// layer's channels (uint32), then the Adam step (int64), all little-endian.
+constexpr size_t CKPT_HEAD = 8 + 4 * (3 + 2 * CNN_LAYERS) + 8;
+
+void put_u32(std::vector<uint8_t>& b, uint32_t v)
+{
+    for (int k = 0; k < 4; ++k) b.push_back((uint8_t)(v >> (8 * k)));
+}
+
+std::vector<uint8_t> ckpt_header(long long step)
+{
+    std::vector<uint8_t> b(CKPT_MAGIC, CKPT_MAGIC + 8);
+    put_u32(b, CKPT_VERSION);
+    put_u32(b, CNN_PARAMS);
+    put_u32(b, CNN_LAYERS);
+    for (int l = 0; l < CNN_LAYERS; ++l) {
+        put_u32(b, CNN_CIN[l]);
+        put_u32(b, CNN_COUT[l]);
+    }
+    for (int k = 0; k < 8; ++k) b.push_back((uint8_t)((uint64_t)step >> (8 * k)));
+    return b;
+}
+}  // namespace
+
+rt3d_status rt3d_denoiser_save(rt3d_ctx* c, const char* path)
+{
+    if (!c) return RT3D_E_INVALID;
+    if (!path) return fail(c, RT3D_E_INVALID, "path is NULL");
+    if (!uses_cnn(c)) return fail(c, RT3D_E_STATE, "context was not created with RT3D_DENOISE_CNN");
+    std::vector<float> buf((size_t)3 * CNN_PARAMS);
+    RT3D_HIP(c, hipDeviceSynchronize());
+    RT3D_HIP(c, hipMemcpy(buf.data(), c->cnn.master, sizeof(float) * buf.size(), hipMemcpyDeviceToHost));
+    const std::vector<uint8_t> h = ckpt_header(c->cnn.step);
+    uint64_t hash = fnv1a(h.data(), h.size());
+    hash = fnv1a(reinterpret_cast<const uint8_t*>(buf.data()), sizeof(float) * buf.size(), hash);
+    std::FILE* f = std::fopen(path, "wb");
+    if (!f) return fail(c, RT3D_E_DEVICE, std::string("cannot open ") + path + " for writing");
+    bool ok = std::fwrite(h.data(), 1, h.size(), f) == h.size() &&
+              std::fwrite(buf.data(), sizeof(float), buf.size(), f) == buf.size() &&
+              std::fwrite(&hash, sizeof hash, 1, f) == 1;
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok) return fail(c, RT3D_E_DEVICE, std::string("write to ") + path + " failed");
+    return RT3D_OK;
+}
+
+rt3d_status rt3d_denoiser_load(rt3d_ctx* c, const char* path)
+{
+    if (!c) return RT3D_E_INVALID;
+    if (!path) return fail(c, RT3D_E_INVALID, "path is NULL");
+    if (!uses_cnn(c)) return fail(c, RT3D_E_STATE, "context was not created with RT3D_DENOISE_CNN");
+    std::FILE* f = std::fopen(path, "rb");
+    if (!f) return fail(c, RT3D_E_DEVICE, std::string("cannot open ") + path);
+    std::vector<uint8_t> h(CKPT_HEAD);
+    std::vector<float> buf((size_t)3 * CNN_PARAMS);
+    uint64_t stored = 0;
+    char extra;
+    const bool read_ok = std::fread(h.data(), 1, h.size(), f) == h.size() &&
+                         std::fread(buf.data(), sizeof(float), buf.size(), f) == buf.size() &&
+                         std::fread(&stored, sizeof stored, 1, f) == 1 && std::fread(&extra, 1, 1, f) == 0;
+    std::fclose(f);
+    if (!read_ok) return fail(c, RT3D_E_INVALID, std::string(path) + ": not a checkpoint of this size");
+    long long step = 0;
+    for (int k = 0; k < 8; ++k) step |= (long long)((uint64_t)h[CKPT_HEAD - 8 + k] << (8 * k));
+    const std::vector<uint8_t> want = ckpt_header(step);
+    if (want != h) return fail(c, RT3D_E_INVALID, std::string(path) + ": magic, version or network shape differ");
+    uint64_t hash = fnv1a(h.data(), h.size());
+    hash = fnv1a(reinterpret_cast<const uint8_t*>(buf.data()), sizeof(float) * buf.size(), hash);
+    if (hash != stored) return fail(c, RT3D_E_INVALID, std::string(path) + ": hash mismatch");
+    if (step < 0) return fail(c, RT3D_E_INVALID, std::string(path) + ": negative Adam step");
+    for (float x : buf)
+        if (!std::isfinite(x)) return fail(c, RT3D_E_INVALID, std::string(path) + ": non-finite value");
+    RT3D_HIP(c, hipDeviceSynchronize());
+    RT3D_HIP(c, hipMemcpy(c->cnn.master, buf.data(), sizeof(float) * buf.size(), hipMemcpyHostToDevice));
+    c->cnn.step = step;
+    RT3D_HIP(c, launch_cnn_prepare(c->cnn, nullptr));
+    RT3D_HIP(c, hipDeviceSynchronize());
+    c->cnn_set = true;
     return RT3D_OK;
 }
 

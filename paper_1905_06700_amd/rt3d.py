@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "librt3d.so")
 K_MAX = 4
 NOALLOC_MAX_PIXELS = 4194304   # RT3D_NOALLOC_MAX_PIXELS
 
-OK, E_INVALID, E_NOMEM, E_DEVICE, E_CAPACITY, E_STATE, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+OK, E_INVALID, E_NOMEM, E_DEVICE, E_CAPACITY, E_STATE, E_UNSUPPORTED, E_NONFINITE = 0, -1, -2, -3, -4, -5, -6, -7
 DENOISE_NONE, DENOISE_APSS = 0, 1
 IN_HIST_U16, IN_PHOTON_CSR, IN_PHOTON_EVENTS = 0, 1, 2
 STEP_INIT, STEP_DEPTH, STEP_APSS, STEP_MERGE, STEP_INTENSITY, STEP_IFILTER, STEP_BKG, STEP_BFILTER, \
@@ -30,7 +30,7 @@ EXPORTS = ["rt3d_params_default", "rt3d_create", "rt3d_destroy", "rt3d_last_erro
            "rt3d_autotune", "rt3d_add_irf", "rt3d_debug_irf_class",
            "rt3d_debug_compact", "rt3d_compact_noalloc", "rt3d_debug_compact_events", "rt3d_debug_step", "rt3d_debug_gradients",
            "rt3d_cnn_set_weights", "rt3d_cnn_get_weights", "rt3d_cnn_last_gradient",
-           "rt3d_cnn_forward", "rt3d_cnn_train_step"]
+           "rt3d_cnn_forward", "rt3d_cnn_train_step", "rt3d_denoiser_save", "rt3d_denoiser_load"]
 KERNELS = ["compact", "init", "normals", "depth", "apss", "merge", "intensity", "ifilter", "bkg",
            "bfilter", "output", "cnn", "loop"]
 DENOISE_CNN = 2
@@ -73,7 +73,7 @@ class Input(C.Structure):
 class Output(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("capacity", C.c_uint32), ("pt_off", C.c_void_p),
                 ("depth", C.c_void_p), ("intensity", C.c_void_p), ("normal", C.c_void_p),
-                ("background", C.c_void_p)]
+                ("background", C.c_void_p), ("world_z", C.c_void_p)]
 
 
 class State(C.Structure):
@@ -151,6 +151,9 @@ def lib():
         L.rt3d_cnn_forward.restype = st
         L.rt3d_cnn_train_step.argtypes = [vp, C.POINTER(State), vp, C.c_uint32, C.POINTER(Adam), vp, vp]
         L.rt3d_cnn_train_step.restype = st
+        for f in (L.rt3d_denoiser_save, L.rt3d_denoiser_load):
+            f.argtypes = [vp, C.c_char_p]
+            f.restype = st
         _lib = L
     return _lib
 
@@ -209,6 +212,7 @@ class Result:
     intensity: torch.Tensor  # float32 [capacity]
     normal: torch.Tensor     # float32 [capacity, 3]
     background: torch.Tensor  # float32 [P]
+    world_z: torch.Tensor | None = None  # float64 [capacity] or None
 
 
 class Graph:
@@ -290,7 +294,7 @@ class Context:
 
     # -- whole reconstruction ------------------------------------------------
     def make_output(self, P: int, capacity: int | None = None, normals: bool = True,
-                    n_bg: int | None = None) -> Result:
+                    n_bg: int | None = None, world_z: bool = False) -> Result:
         """Output buffers for P (point-grid) pixels and n_bg (lidar) background values (default P)."""
         cap = P * K_MAX if capacity is None else capacity
         dev = "cuda"
@@ -298,7 +302,8 @@ class Context:
                       torch.zeros(cap, dtype=torch.float64, device=dev),
                       torch.zeros(cap, dtype=torch.float32, device=dev),
                       torch.zeros(cap, 3, dtype=torch.float32, device=dev) if normals else None,
-                      torch.zeros(P if n_bg is None else n_bg, dtype=torch.float32, device=dev))
+                      torch.zeros(P if n_bg is None else n_bg, dtype=torch.float32, device=dev),
+                      torch.zeros(cap, dtype=torch.float64, device=dev) if world_z else None)
 
     def add_irf(self, irf, origin: int = -1) -> int:
         """Add a per-pixel IRF class (rt3d_add_irf); returns its number."""
@@ -356,6 +361,7 @@ class Context:
         o.pt_off, o.depth, o.intensity = out.pt_off.data_ptr(), out.depth.data_ptr(), out.intensity.data_ptr()
         o.normal = out.normal.data_ptr() if out.normal is not None else None
         o.background = out.background.data_ptr()
+        o.world_z = out.world_z.data_ptr() if out.world_z is not None else None
         return inp, o
 
     def reconstruct_into(self, out: Result, frames: int, rows: int, cols: int, hist=None, off=None,
@@ -388,8 +394,9 @@ class Context:
         self._check(lib().rt3d_graph_create(self._h, C.byref(inp), C.byref(o), C.byref(h)))
         return Graph(self, h, (out, hist, off, ent, gain, events, irf_class))
 
-    def reconstruct(self, hist, gain=None, max_entries=None, irf_class=None) -> Result:
-        """hist: cuda uint16 [frames, rows, cols, bins] (or [rows, cols, bins])."""
+    def reconstruct(self, hist, gain=None, max_entries=None, irf_class=None, world_z=False) -> Result:
+        """hist: cuda uint16 [frames, rows, cols, bins] (or [rows, cols, bins]);
+        world_z: also return each point's world Z coordinate."""
         if hist.dim() == 3:
             hist = hist.unsqueeze(0)
         F, R, Cc, T = hist.shape
@@ -398,7 +405,7 @@ class Context:
         me = int(max_entries) if max_entries is not None else min(P * T, 2 ** 32 - 1)
         self.workspace(F, R, Cc, me)
         sr = self.params.sr
-        out = self.make_output(P * sr * sr, n_bg=P)
+        out = self.make_output(P * sr * sr, n_bg=P, world_z=world_z)
         self.reconstruct_into(out, F, R, Cc, hist=hist, gain=gain, irf_class=irf_class)
         return out
 
@@ -474,6 +481,13 @@ class Context:
 
     def cnn_get_weights(self):
         return self._host_vec(lib().rt3d_cnn_get_weights)
+
+    def denoiser_save(self, path: str):
+        """Checkpoint of the network, its Adam moments and step (rt3d_denoiser_save)."""
+        self._check(lib().rt3d_denoiser_save(self._h, os.fsencode(path)))
+
+    def denoiser_load(self, path: str):
+        self._check(lib().rt3d_denoiser_load(self._h, os.fsencode(path)))
 
     def cnn_last_gradient(self):
         return self._host_vec(lib().rt3d_cnn_last_gradient)
