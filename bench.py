@@ -37,7 +37,10 @@ def log(msg):
 
 
 def host_cpu():
-    """Thread count and CPU model of this host (the oracle's timing context)."""
+    """Thread count and CPU model of this host (the oracle's timing context):
+    /proc/cpuinfo's model name and lscpu's model lines.  Call it before the
+    GPU is initialised (it starts lscpu as a child process)."""
+    import subprocess
     model = ""
     try:
         with open("/proc/cpuinfo") as f:
@@ -47,8 +50,62 @@ def host_cpu():
                     break
     except OSError:
         pass
+    lscpu = {}
+    try:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for line in txt.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() in ("Model name", "BIOS Model name", "Socket(s)", "Core(s) per socket",
+                             "Thread(s) per core", "CPU(s)", "CPU max MHz"):
+                lscpu[k.strip()] = v.strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
     n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    return {"threads_available": n, "model": model}
+    return {"threads_available": n, "model": model, "lscpu": lscpu}
+
+
+# The oracle on all host cores: one frame per process, the processes started
+# (spawned, before the GPU is initialised) and released together.
+_BARRIER = None
+
+
+def _pool_init(barrier):
+    global _BARRIER
+    _BARRIER = barrier
+
+
+def _oracle_frame(s):
+    import oracle
+    from paper_1905_06700_amd import synth
+    sc = synth.head_scene(s)
+    O = oracle.Oracle(oracle.Model(sc.irf.probs, BINS), oracle.Params(**scene_params(sc)))
+    _BARRIER.wait()
+    t0 = time.time()
+    off, ent = oracle.compact(sc.Z[None])
+    t1 = time.time()
+    st = O.init(off, ent, oracle.State(1, ROWS, COLS, 4))
+    t2 = time.time()
+    for _ in range(20):
+        O.iterate(off, ent, st)
+    return t0, t1, t2, time.time()
+
+
+def oracle_all_cores(workers=16):
+    """Frames/s of the FP64 oracle with `workers` frames in parallel processes."""
+    import multiprocessing as mp
+    import oracle
+    oracle.build(force=False)
+    n = max(1, min(workers, host_cpu()["threads_available"]))
+    ctx = mp.get_context("spawn")
+    barrier = ctx.Barrier(n)
+    with ctx.Pool(n, initializer=_pool_init, initargs=(barrier,)) as pool:
+        times = pool.map(_oracle_frame, range(n))
+    wall = max(t[3] for t in times) - min(t[0] for t in times)
+    per = [t[3] - t[0] for t in times]
+    return {"value": round(n / wall, 4), "unit": "frames/s", "cores": n, "kind": "oracle",
+            "sample": f"{n} full {ROWS}x{COLS}x{BINS} frames (compaction + init + 20 iterations), one per "
+                      f"process on {n} host threads, {wall:.1f} s wall",
+            "seconds_per_frame_median": round(sorted(per)[len(per) // 2], 2)}
 
 
 def scene_params(sc):
@@ -85,8 +142,8 @@ def algorithmic_bytes(kernel, F, N, T, E, pts):
     if kernel == "bkg":
         return 4 * E + 4 * (FN + 1) + FN + 8 * FN + 12 * pts
     if kernel == "apss":
-        # read t, n of every point once and write t, n, r (+ cnt, b copy)
-        return pts * (8 + 12) + pts * (8 + 12 + 4) + 2 * FN + 8 * FN
+        # read the count of every pixel and t (f64), n of every point once; write t, n
+        return pts * (8 + 12) * 2 + FN
     if kernel == "merge":
         return 2 * pts * (8 + 4 + 12) + 2 * FN
     if kernel == "ifilter":
@@ -260,8 +317,26 @@ def hbm_regime(scenes, F=64):
         gbs = ab / (avg / 1e3) / 1e9
         res[g] = {"avg_launch_us": round(avg * 1e3, 2), "algorithmic_bytes_per_launch": int(ab),
                   "achieved_GBs": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
+        if g == "apss":
+            res[g].update(apss_valu(pts, avg))
     del Z
     return res
+
+
+# APSS arithmetic: 40 flop per neighbour evaluation over the (2R+1)^2 window
+# (R = ceil(h_apss / p_xy) = 2) and the live points of each window pixel.
+FP32_PEAK_TFLOPS = 157.3          # MI355X FP32 vector peak (counts packed FP32 instructions)
+FP32_NONPACKED_TFLOPS = 78.6      # without packed FP32 instructions, as this library is built
+
+
+def apss_valu(pts, avg_ms, R=2, N=ROWS * COLS, F=64):
+    """APSS flops per launch (40 (2R+1)^2 K flop per point, K = live points per
+    pixel) against the FP32 vector peaks."""
+    K = pts / (F * N)
+    flops = 40.0 * (2 * R + 1) ** 2 * K * pts
+    tf = flops / (avg_ms / 1e3) / 1e12
+    return {"algorithmic_flops_per_launch": int(flops), "achieved_TFLOPs": round(tf, 2),
+            "frac_valu": round(tf / FP32_PEAK_TFLOPS, 4), "frac_valu_nonpacked": round(tf / FP32_NONPACKED_TFLOPS, 4)}
 
 
 def stress_batch(reps=3):
@@ -550,64 +625,99 @@ def execution_time_sweep(reps=5):
             "pixels": pixels, "active_bins": bins}
 
 
-def learned_vs_apss(n_train=4, n_eval=4, steps=300, rows=256, cols=256, bins=1024):
-    """Learned denoiser against plain APSS on multi-layer scenes: train on the
-    GPU (the library's forward/backward kernels), then time and score both on
-    held-out scenes (depth RMSE with misses counted at 3 sigma_h)."""
+DENOISER_CHECKPOINT = os.path.join(ROOT, "paper_1905_06700_amd", "weights", "denoiser_c4.rt3dcnn")
+
+
+def _evaluate(ctx, scenes, rows, cols, bins, sig, batch=16):
+    """Reconstructs `scenes` in calls of `batch` frames; returns frames/s (of
+    the first full call, timed over 3 repeats) and the depth scores of
+    S33-style greedy matching within 3 sigma_h."""
+    import numpy as np
+    import torch
+
+    from paper_1905_06700_amd import train
+
+    P1 = rows * cols
+    errs, n_true, n_false, fps = [], [], [], None
+    for b0 in range(0, len(scenes), batch):
+        part = scenes[b0:b0 + batch]
+        F = len(part)
+        Z = torch.stack([torch.from_numpy(s.Z.view(np.int16)) for s in part]).cuda()
+        ctx.workspace(F, rows, cols, F * P1 * 200)
+        res = ctx.make_output(F * P1)
+        ctx.reconstruct_into(res, F, rows, cols, hist=Z)
+        torch.cuda.synchronize()
+        if fps is None:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(3):
+                ctx.reconstruct_into(res, F, rows, cols, hist=Z)
+            e1.record()
+            torch.cuda.synchronize()
+            fps = 3 * F / (e0.elapsed_time(e1) / 1e3)
+        pt = res.pt_off.cpu().numpy().view(np.uint32).astype(np.int64)
+        dep = res.depth.cpu().numpy()
+        for f, sc in enumerate(part):
+            sl = pt[f * P1:(f + 1) * P1 + 1] - pt[f * P1]
+            e, nt, nf = train.match_surfaces(sc.depth.reshape(sc.depth.shape[0], -1), sl, dep[pt[f * P1]:], 3 * sig)
+            errs.append(e)
+            n_true.append(nt)
+            n_false.append(nf)
+        del Z, res
+    out = {"frames_per_s": round(fps, 2)}
+    out.update(train.depth_scores(errs, n_true, n_false, len(scenes) * P1, 3 * sig))
+    return out
+
+
+def learned_vs_apss(rows=256, cols=256, bins=1024, n_eval=50, n_high=16):
+    """Learned denoiser against plain APSS: the network of the committed
+    checkpoint (trained on the GPU by paper_1905_06700_amd/train.py's recipe:
+    config-4 scenes, inputs recorded at iterations 1, 2, 5, 10, 20 of APSS runs,
+    64 x 64 crops, batch 32), else a short training run here.  Both paths
+    reconstruct the held-out config-4 scenes (seeds 10000 .. 10000 + n_eval - 1,
+    2 signal photons/px, SBR 0.05) and a brighter regime (6 photons/px, SBR
+    0.2) where most surfaces are found; depth scores by greedy matching within
+    3 sigma_h (misses count 3 sigma_h), frames/s on 16-frame calls."""
     import numpy as np
     import torch
 
     from paper_1905_06700_amd import rt3d, synth, train
 
-    t0 = time.perf_counter()
-    tr = [synth.layers_scene(s, rows=rows, cols=cols, T=bins) for s in range(n_train)]
-    ev = [synth.layers_scene(10000 + s, rows=rows, cols=cols, T=bins) for s in range(n_eval)]
-    p = dict(dz=tr[0].meta["dz"], r_min=tr[0].meta["r_min"], r_init=tr[0].meta["r_init"],
-             k_init=tr[0].meta["k_init"])
-    apss = rt3d.Context(tr[0].irf.probs, bins, **p)
-    net = rt3d.Context(tr[0].irf.probs, bins, denoiser=rt3d.DENOISE_CNN, **p)
-    Ztr = torch.stack([torch.from_numpy(s.Z.view(np.int16)) for s in tr]).cuda()
-    truth = torch.from_numpy(np.concatenate([s.depth.reshape(3, -1) for s in tr], axis=1)
-                             .astype(np.float32)).cuda()
-    log(f"[bench] learned denoiser: recording depth-block inputs of {n_train} training scenes")
-    recorded = train.record_depth_inputs(apss, Ztr)
-    net.workspace(n_train, rows, cols, n_train * rows * cols * 256)
-    hist = train.train(net, [(recorded, truth)], steps=steps, lr=2e-3, seed=0, log_every=50, log=log)
-    torch.cuda.synchronize()
-    train_s = time.perf_counter() - t0
-    del recorded
-    Zev = torch.stack([torch.from_numpy(s.Z.view(np.int16)) for s in ev]).cuda()
+    sc0 = synth.layers_scene(0, rows=8, cols=8, T=bins)
+    m = sc0.meta
+    p = dict(dz=m["dz"], r_min=m["r_min"], r_init=m["r_init"], k_init=m["k_init"])
+    apss = rt3d.Context(sc0.irf.probs, bins, **p)
+    net = rt3d.Context(sc0.irf.probs, bins, denoiser=rt3d.DENOISE_CNN, **p)
+    if os.path.exists(DENOISER_CHECKPOINT):
+        net.denoiser_load(DENOISER_CHECKPOINT)
+        training = {"checkpoint": os.path.relpath(DENOISER_CHECKPOINT, ROOT)}
+    else:
+        n_train = 64
+        log(f"[bench] learned denoiser: no checkpoint, training on {n_train} scenes here")
+        lists = (train.scene_lists((s, rows, cols, bins, 2.0, 0.05)) for s in range(n_train))
+        t0 = time.perf_counter()
+        hist = train.train_recipe(net, apss, lists, n_train, steps=800, rows=rows, cols=cols, log=log)
+        training = {"scenes": n_train, "steps": 800, "first_loss": round(hist[0][1], 4),
+                    "final_loss": round(hist[-1][1], 4), "seconds_incl_data": round(time.perf_counter() - t0, 1)}
     sig = float(np.sqrt(apss.sigma2))
-    out = {}
+    log(f"[bench] learned denoiser: generating {n_eval} held-out config-4 scenes")
+    ev = [synth.layers_scene(10000 + s, rows=rows, cols=cols, T=bins) for s in range(n_eval)]
+    out = {"workload": f"{rows}x{cols}x{bins} multi-layer scenes (up to 3 surfaces, 2 signal photons/px, SBR 0.05), "
+                       f"held-out seeds 10000..{10000 + n_eval - 1}, 16 frames per call",
+           "training": training}
     for name, ctx in (("apss", apss), ("cnn", net)):
-        ctx.workspace(n_eval, rows, cols, n_eval * rows * cols * 256)
-        res = ctx.make_output(n_eval * rows * cols)
-        ctx.reconstruct_into(res, n_eval, rows, cols, hist=Zev)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(3):
-            ctx.reconstruct_into(res, n_eval, rows, cols, hist=Zev)
-        e1.record()
-        torch.cuda.synchronize()
-        fps = 3 * n_eval / (e0.elapsed_time(e1) / 1e3)
-        pt = res.pt_off.cpu().numpy().view(np.uint32).astype(np.int64)
-        dep = res.depth.cpu().numpy()
-        rm, found = [], []
-        P1 = rows * cols
-        for f, s in enumerate(ev):
-            sl = pt[f * P1:(f + 1) * P1 + 1] - pt[f * P1]
-            r, fo = train.depth_rmse(s.depth.reshape(3, -1), sl, dep[pt[f * P1]:], 3 * sig)
-            rm.append(r)
-            found.append(fo)
-        out[name] = {"frames_per_s": round(fps, 2), "depth_rmse_bins": round(float(np.mean(rm)), 3),
-                     "found_within_3sigma": round(float(np.mean(found)), 4)}
-    out["rmse_ratio_cnn_over_apss"] = round(out["cnn"]["depth_rmse_bins"] / out["apss"]["depth_rmse_bins"], 4)
-    out["speedup_cnn_over_apss"] = round(out["cnn"]["frames_per_s"] / out["apss"]["frames_per_s"], 3)
-    out["workload"] = (f"{rows}x{cols}x{bins} multi-layer scenes (up to 3 surfaces, 2 signal photons/px, "
-                       f"SBR 0.05), {n_eval} held-out frames per call")
-    out["training"] = {"scenes": n_train, "steps": steps, "final_loss": round(hist[-1], 4),
-                       "first_loss": round(hist[0], 4), "seconds_incl_data": round(train_s, 1)}
+        out[name] = _evaluate(ctx, ev, rows, cols, bins, sig)
+    del ev
+    hi = [synth.layers_scene(10000 + s, rows=rows, cols=cols, T=bins, signal=6.0, sbr=0.2) for s in range(n_high)]
+    out["bright"] = {"workload": f"{rows}x{cols}x{bins} multi-layer scenes, 6 signal photons/px, SBR 0.2, "
+                                 f"held-out seeds 10000..{10000 + n_high - 1}"}
+    for name, ctx in (("apss", apss), ("cnn", net)):
+        out["bright"][name] = _evaluate(ctx, hi, rows, cols, bins, sig)
+    for d in (out, out["bright"]):
+        d["rmse_ratio_cnn_over_apss"] = round(d["cnn"]["depth_rmse_bins"] / d["apss"]["depth_rmse_bins"], 4)
+        d["rmse_found_ratio_cnn_over_apss"] = round(d["cnn"]["depth_rmse_found_bins"] /
+                                                    max(d["apss"]["depth_rmse_found_bins"], 1e-9), 4)
+        d["speedup_cnn_over_apss"] = round(d["cnn"]["frames_per_s"] / d["apss"]["frames_per_s"], 3)
     return out
 
 
@@ -622,8 +732,8 @@ def main():
     ap.add_argument("--cpu-frames", type=int, default=2, help="frames the oracle times (0 = skip)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-APSS leg")
     ap.add_argument("--no-sweep", action="store_true", help="skip the execution-time sweep")
-    ap.add_argument("--stress", action="store_true", help="add the stress batch (8 scenes up to 512^2 x 2000; "
-                                                          "about a minute of scene generation)")
+    ap.add_argument("--no-stress", action="store_true", help="skip the stress batch (8 scenes up to 512^2 x "
+                                                             "2000; about a minute of scene generation)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device to device (a plain copy kernel of known size, the "
                          "reference for HBM byte counters)")
@@ -633,6 +743,11 @@ def main():
               "independent, so N GPUs would each take whole frames (see the design notes).",
               file=sys.stderr)
         sys.exit(2)
+
+    # the oracle on every host core first: its worker processes start before
+    # this process touches the GPU
+    cpu_all = oracle_all_cores() if args.cpu_frames > 0 else None
+    host = host_cpu()
 
     import numpy as np
     import torch
@@ -772,12 +887,12 @@ def main():
             split["init"] += t2 - t1
             split["iterations"] += t3 - t2
         el = sum(split.values())
-        cpu = {"value": round(nf / el, 4), "unit": "frames/s", "cores": 1, "kind": "oracle",
-               "sample": f"{nf} full {ROWS}x{COLS}x{BINS} frames (compaction + init + 20 iterations), "
-                         f"{el:.1f} s on one host thread",
-               "gbin_per_s": round(nf * ROWS * COLS * BINS / el / 1e9, 4),
-               "ms_per_frame_split": {k: round(v * 1e3 / nf, 1) for k, v in split.items()},
-               "host": host_cpu()}
+        single = {"value": round(nf / el, 4), "unit": "frames/s", "cores": 1,
+                  "sample": f"{nf} full {ROWS}x{COLS}x{BINS} frames (compaction + init + 20 iterations), "
+                            f"{el:.1f} s on one host thread",
+                  "gbin_per_s": round(nf * ROWS * COLS * BINS / el / 1e9, 4),
+                  "ms_per_frame_split": {k: round(v * 1e3 / nf, 1) for k, v in split.items()}}
+        cpu = dict(cpu_all, single_thread=single, host=host)
 
     res = {
         "metric": METRIC, "value": round(fps, 2), "unit": "frames/s", "n_gpus": 1,
@@ -794,7 +909,7 @@ def main():
         "super_resolution": super_resolution(), "observation_model": observation_model(scenes),
         "video_and_scenes": video_and_scenes(),
         "execution_time_sweep": None if args.no_sweep else execution_time_sweep(),
-        "stress_batch": stress_batch() if args.stress else None,
+        "stress_batch": None if args.no_stress else stress_batch(),
         "wall_s": round(wall, 3),
         "roofline": roofline, "kernels": kernels, "cpu_baseline": cpu,
         "learned_vs_apss": None if args.no_learned else learned_vs_apss(),

@@ -163,9 +163,8 @@ typedef struct rt3d_input {
      * frame), in the histograms, the CSR, the gain, the output and the event
      * pixel numbers alike; rows and cols are then ignored and P is the sum of
      * the frames' pixels (the workspace must be sized for at least that many).
-     * Consecutive frames of one size are processed as one group.  E_INVALID for
-     * a zero or oversized frame, E_UNSUPPORTED with the learned denoiser when
-     * the sizes differ. */
+     * Consecutive frames of one size are processed as one group (the learned
+     * denoiser runs once per group).  E_INVALID for a zero or oversized frame. */
     const uint32_t* frame_rows;
     const uint32_t* frame_cols;
     /* RT3D_FLAG_* bits. */

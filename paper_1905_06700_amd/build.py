@@ -52,5 +52,31 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def build_sanitized(outdir: str) -> str:
+    """librt3d.so with AddressSanitizer and UndefinedBehavior Sanitizer in its
+    host code (device code as usual), and csrc/host_selftest.c linked against
+    it; returns the test executable's path (run it with
+    ASAN_OPTIONS=detect_leaks=0: the HIP runtime keeps its allocations)."""
+    os.makedirs(outdir, exist_ok=True)
+    san = ["-Xarch_host", "-fsanitize=address,undefined", "-Xarch_host", "-fno-omit-frame-pointer",
+           "-Xarch_host", "-fno-sanitize-recover=all"]
+    flags = [f for f in FLAGS if f != "-O3"] + ["-O1", "-g"] + san
+    procs, objs = [], []
+    for s in SOURCES:
+        obj = os.path.join(outdir, os.path.splitext(s)[0] + ".o")
+        procs.append((s, subprocess.Popen([HIPCC] + flags + ["-x", "hip", "-c", os.path.join(CSRC, s), "-o", obj],
+                                          stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
+        objs.append(obj)
+    failed = [s for s, p in procs if p.wait()]
+    if failed:
+        raise RuntimeError("hipcc failed for " + ", ".join(failed))
+    lib = os.path.join(outdir, "librt3d.so")
+    subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-shared", "-o", lib] + san + objs)
+    exe = os.path.join(outdir, "host_selftest")
+    subprocess.check_call([HIPCC, "-x", "c", os.path.join(CSRC, "host_selftest.c"), "-x", "none", "-o", exe, lib,
+                           "-Wl,-rpath," + outdir, "-lm"] + san)
+    return exe
+
+
 if __name__ == "__main__":
     print(build(verbose="-v" in sys.argv))

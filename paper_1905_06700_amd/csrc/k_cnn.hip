@@ -261,7 +261,7 @@ __global__ __launch_bounds__(PKT * PKT) void k_cnn_pack(Shape sh, DevState s, fl
 {
     __shared__ double tl[KM][PKS * PKS];
     __shared__ int cl[PKS * PKS];
-    const long long P = sh.P;
+    const long long S = sh.S;   // slot stride (the whole batch's pixels when sh is one group of it)
     const int tiles_x = (sh.cols + PKT - 1) / PKT, tiles_y = (sh.rows + PKT - 1) / PKT;
     const int tpf = tiles_x * tiles_y;
     const int fr = (int)(blockIdx.x / tpf), tr = (int)(blockIdx.x % tpf);
@@ -274,7 +274,7 @@ __global__ __launch_bounds__(PKT * PKT) void k_cnn_pack(Shape sh, DevState s, fl
             const long long pp = fbase + (long long)i2 * sh.cols + j2;
             c2 = load_cnt(s.cnt, pp);
 #pragma unroll
-            for (int k = 0; k < KM; ++k) tl[k][xx] = s.t[k * P + pp];
+            for (int k = 0; k < KM; ++k) tl[k][xx] = s.t[k * S + pp];
         }
         cl[xx] = c2;                                  // 0 outside the image
     }
@@ -314,7 +314,7 @@ __global__ __launch_bounds__(PKT * PKT) void k_cnn_pack(Shape sh, DevState s, fl
         if (k >= c) continue;
         const double mean = sum[k] / n[k];
         v[4 * k] = fminf(fmaxf((float)((tk[k] - mean) / (double)sigma_h), -8.f), 8.f);
-        v[4 * k + 1] = log1pf(s.r[k * P + pix]);
+        v[4 * k + 1] = log1pf(s.r[k * S + pix]);
         v[4 * k + 2] = 1.f;
         v[4 * k + 3] = (float)n[k] / 25.f;
     }
@@ -335,15 +335,15 @@ __global__ __launch_bounds__(PKT * PKT) void k_cnn_pack(Shape sh, DevState s, fl
 __global__ __launch_bounds__(256) void k_cnn_apply(Shape sh, const __half* __restrict__ y, float sigma_h,
                                                    double tmax, DevState s)
 {
-    const long long P = sh.P;
+    const long long S = sh.S;
     const long long pix = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (pix >= P) return;
+    if (pix >= sh.P) return;
     const int c = load_cnt(s.cnt, pix);
     if (c > 3) return;
     for (int k = 0; k < c; ++k) {
-        double t = s.t[k * P + pix] + (double)(sigma_h * __half2float(y[pix * 16 + k]));
+        double t = s.t[k * S + pix] + (double)(sigma_h * __half2float(y[pix * 16 + k]));
         t = t < 0.0 ? 0.0 : (t > tmax ? tmax : t);
-        s.t[k * P + pix] = t;
+        s.t[k * S + pix] = t;
     }
 }
 
@@ -477,6 +477,159 @@ __global__ __launch_bounds__(256) void k_cnn_prepare(const float* __restrict__ m
 }
 
 // ---------------------------------------------------------------------------
+// Fused inference: the four convolutions of one FT x FT output tile in one
+// workgroup, every intermediate activation kept in LDS (FP16, the rounding
+// the per-layer kernels apply when they store it).  Layer l computes its
+// output over the tile grown by 4 - l pixels on every side (the receptive
+// field of the layers after it); outputs at positions outside the image are
+// set to zero, which is the next layer's zero padding.  Matrix cores:
+// v_mfma_f32_16x16x32_f16 (lane i + 16 g holds row i, k = 8 g .. 8 g + 7 of A
+// and column i, the same k of B; D rows 4 g .. 4 g + 3 of column i).  The
+// B operand (the layer's weights) stays in registers for the whole layer; A
+// rows are output pixels, gathered from LDS per lane (one 16-byte chunk of 8
+// channels of the input pixel under the tap).
+constexpr int FT = 16;                   // output tile side
+constexpr int FR0 = FT + 8;              // side of the staged input features (4-pixel halo)
+
+typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ float4_t mfma32(half8_t a, half8_t b, float4_t c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
+
+// LDS offset (halves) of 16-byte chunk q of pixel p in a region of C-channel
+// pixels, the chunks of a pixel permuted by its index so that the same chunk
+// of 8 consecutive pixels lies in 8 distinct bank groups.
+template <int C>
+__device__ __forceinline__ int chunk_at(int p, int q)
+{
+    if (C == 32) return p * 32 + 8 * (q ^ ((p >> 1) & 3));
+    return p * 16 + 8 * (q ^ ((p >> 2) & 1));
+}
+
+// One layer over the RO x RO output region whose input region (RO + 2 wide)
+// sits in `in`.  NT output tiles of 16 channels; LAST: bias only, the FT x FT
+// result goes to y (FP16 [P][16]); else bias, ReLU, zero outside the image,
+// into `out` (32 channels).  (gy0, gx0): image position of the output
+// region's first pixel.
+template <int CIN, int NT, bool LAST>
+__device__ __forceinline__ void fused_layer(const __half* __restrict__ in, __half* __restrict__ out, int RO,
+                                            const __half* __restrict__ Wt, const float* __restrict__ bias, int gy0,
+                                            int gx0, int H, int W, long long fbase, __half* __restrict__ y)
+{
+    constexpr int K = 9 * CIN;
+    constexpr int KC = (K + 31) / 32;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int i = lane & 15, g = lane >> 4;
+    half8_t wf[KC][NT];
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+        for (int n = 0; n < NT; ++n) {
+            const int k0 = kc * 32 + 8 * g;
+            half8_t v = {};
+            if (k0 < K) v = *reinterpret_cast<const half8_t*>(Wt + (n * 16 + i) * K + k0);
+            wf[kc][n] = v;
+        }
+    float bco[NT];
+#pragma unroll
+    for (int n = 0; n < NT; ++n) bco[n] = bias[n * 16 + i];
+    const int RI = RO + 2, npx = RO * RO, nmt = (npx + 15) / 16;
+    for (int mt0 = wv; mt0 < nmt; mt0 += 8) {
+        int abase[2];
+        bool aval[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int m = (mt0 + 4 * u) * 16 + i;
+            aval[u] = (mt0 + 4 * u) < nmt && m < npx;
+            const int mm = aval[u] ? m : 0;
+            abase[u] = (mm / RO) * RI + mm % RO;          // input pixel under tap (0, 0)
+        }
+        float4_t acc[2][NT];
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int n = 0; n < NT; ++n) acc[u][n] = (float4_t){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc) {
+            int tap, q;
+            if (CIN == 32) {
+                tap = kc;
+                q = g;
+            } else {
+                tap = 2 * kc + (g >> 1);
+                q = g & 1;
+            }
+            const int dp = (tap / 3) * RI + tap % 3;
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                half8_t a = {};
+                if (aval[u] && tap < 9) a = *reinterpret_cast<const half8_t*>(in + chunk_at<CIN>(abase[u] + dp, q));
+#pragma unroll
+                for (int n = 0; n < NT; ++n) acc[u][n] = mfma32(a, wf[kc][n], acc[u][n]);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            if (mt0 + 4 * u >= nmt) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = (mt0 + 4 * u) * 16 + 4 * g + r;
+                if (m >= npx) continue;
+                const int oy = m / RO, ox = m % RO;
+                const int gy = gy0 + oy, gx = gx0 + ox;
+                const bool inside = gy >= 0 && gy < H && gx >= 0 && gx < W;
+#pragma unroll
+                for (int n = 0; n < NT; ++n) {
+                    const float v = acc[u][n][r] + bco[n];
+                    if (LAST) {
+                        if (inside) y[(fbase + (long long)gy * W + gx) * 16 + n * 16 + i] = __float2half(v);
+                    } else {
+                        const int ch = n * 16 + i;
+                        out[chunk_at<32>(m, ch >> 3) + (ch & 7)] = __float2half(inside ? fmaxf(v, 0.f) : 0.f);
+                    }
+                }
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_cnn_fused(const __half* __restrict__ x, const __half* __restrict__ w0,
+                                                   const __half* __restrict__ w1, const __half* __restrict__ w2,
+                                                   const __half* __restrict__ w3, const float* __restrict__ b0,
+                                                   const float* __restrict__ b1, const float* __restrict__ b2,
+                                                   const float* __restrict__ b3, __half* __restrict__ y, int H, int W)
+{
+    // buf0: the input features (FR0^2 x 16 channels), later layer 2's output
+    // ((FT + 4)^2 x 32); buf1: layer 1's output ((FT + 6)^2 x 32), later layer 3's
+    __shared__ __align__(16) __half buf0[(FT + 4) * (FT + 4) * 32];
+    __shared__ __align__(16) __half buf1[(FT + 6) * (FT + 6) * 32];
+    static_assert(FR0 * FR0 * 16 <= (FT + 4) * (FT + 4) * 32, "the features fit buf0");
+    const int tx_n = (W + FT - 1) / FT, ty_n = (H + FT - 1) / FT;
+    const int tile = (int)xcd_block(blockIdx.x, gridDim.x);
+    const int f = tile / (tx_n * ty_n), tr = tile % (tx_n * ty_n);
+    const int Y0 = (tr / tx_n) * FT, X0 = (tr % tx_n) * FT;
+    const long long fbase = (long long)f * H * W;
+    for (int v = threadIdx.x; v < FR0 * FR0 * 2; v += blockDim.x) {
+        const int p = v >> 1, q = v & 1;
+        const int gy = Y0 - 4 + p / FR0, gx = X0 - 4 + p % FR0;
+        uint4 val = make_uint4(0, 0, 0, 0);
+        if (gy >= 0 && gy < H && gx >= 0 && gx < W)
+            val = reinterpret_cast<const uint4*>(x + (fbase + (long long)gy * W + gx) * 16)[q];
+        *reinterpret_cast<uint4*>(buf0 + chunk_at<16>(p, q)) = val;
+    }
+    __syncthreads();
+    fused_layer<16, 2, false>(buf0, buf1, FT + 6, w0, b0, Y0 - 3, X0 - 3, H, W, fbase, nullptr);
+    __syncthreads();
+    fused_layer<32, 2, false>(buf1, buf0, FT + 4, w1, b1, Y0 - 2, X0 - 2, H, W, fbase, nullptr);
+    __syncthreads();
+    fused_layer<32, 2, false>(buf0, buf1, FT + 2, w2, b2, Y0 - 1, X0 - 1, H, W, fbase, nullptr);
+    __syncthreads();
+    fused_layer<32, 1, true>(buf1, nullptr, FT, w3, b3, Y0, X0, H, W, fbase, y);
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 
 static inline unsigned nb256(long long n) { return (unsigned)((n + 255) / 256); }
@@ -519,6 +672,18 @@ hipError_t launch_cnn_forward(const Shape& sh, DevState s, float sigma_h, const 
                        b.act[3], sh.F, sh.rows, sh.cols);
     hipLaunchKernelGGL((k_conv3x3<32, 16, 1>), dim3(g), dim3(64 * CR), 0, st, b.act[3], w.wt[3], w.bias[3], nullptr,
                        b.act[4], sh.F, sh.rows, sh.cols);
+    return hipGetLastError();
+}
+
+hipError_t launch_cnn_infer(const Shape& sh, DevState s, float sigma_h, const CnnWeights& w, const CnnBuffers& b,
+                            hipStream_t st)
+{
+    if (sh.P == 0) return hipSuccess;
+    const unsigned tiles = (unsigned)(sh.F * ((sh.rows + PKT - 1) / PKT) * ((sh.cols + PKT - 1) / PKT));
+    hipLaunchKernelGGL(k_cnn_pack, dim3(tiles), dim3(PKT * PKT), 0, st, sh, s, sigma_h, b.act[0]);
+    const unsigned ft = (unsigned)(sh.F * ((sh.rows + FT - 1) / FT) * ((sh.cols + FT - 1) / FT));
+    hipLaunchKernelGGL(k_cnn_fused, dim3(ft), dim3(256), 0, st, b.act[0], w.wt[0], w.wt[1], w.wt[2], w.wt[3],
+                       w.bias[0], w.bias[1], w.bias[2], w.bias[3], b.act[4], sh.rows, sh.cols);
     return hipGetLastError();
 }
 

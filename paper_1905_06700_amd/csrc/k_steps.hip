@@ -53,9 +53,9 @@ constexpr int STEP_LIST = STEP_BATCH * LPP;
 // entries ascend in bin, so the batch's support entries are one contiguous
 // run: the lanes count the entries below lo and up to hi, and then evaluate
 // the run from LDS, its entries shared out over the lanes in turn.
-__device__ __forceinline__ void accumulate(const DevModel& m, const PixPoints& q, float bb, float G,
-                                           const uint32_t* __restrict__ ent, uint32_t e0p, uint32_t e1, int sub,
-                                           uint32_t* list, float& sz, float (&sh)[KM], float (&shp)[KM])
+__device__ __forceinline__ void accumulate(const DevModel& m, const float4* cr, const PixPoints& q, float bb,
+                                           float G, const uint32_t* __restrict__ ent, uint32_t e0p, uint32_t e1,
+                                           int sub, uint32_t* list, float& sz, float (&sh)[KM], float (&shp)[KM])
 {
     sz = 0.f;
 #pragma unroll
@@ -104,7 +104,7 @@ __device__ __forceinline__ void accumulate(const DevModel& m, const PixPoints& q
                 h[k] = 0.f;
                 hp[k] = 0.f;
                 if (k < q.c) {
-                    irf_eval(m, tb, q.a[k], q.f[k], h[k], hp[k]);
+                    irf_eval_t(cr, m.L, m.o, tb, q.a[k], q.f[k], h[k], hp[k]);
                     lam = fmaf(q.r[k], h[k], lam);
                 }
             }
@@ -156,6 +156,19 @@ __device__ __forceinline__ void s_eval_points(const DevModel& m, const PixPoints
     }
 }
 
+// The IRF's Catmull-Rom segments for the entry loop: staged in the
+// workgroup's LDS when they fit (TLDS), else read from global memory.
+constexpr int STEP_CR_LDS = 256;
+
+template <bool TLDS>
+__device__ __forceinline__ const float4* stage_segments(const DevModel& m, float4* crl)
+{
+    if (!TLDS) return m.cr;
+    for (int i = threadIdx.x; i <= m.L; i += blockDim.x) crl[i] = m.cr[i];
+    __syncthreads();
+    return crl;
+}
+
 // Common prologue: the pixel of this lane, its points and its entry range.
 struct Lane {
     long long pix;
@@ -196,20 +209,24 @@ __device__ __forceinline__ Lane lane_setup(const DevModel& m, const DevState& s,
     return L;
 }
 
+template <bool TLDS>
 __global__ __launch_bounds__(256) void k_depth_step(DevModel m, DevParams p, Shape sh,
                                                     const uint32_t* __restrict__ off,
                                                     const uint32_t* __restrict__ ent,
                                                     const float* __restrict__ gain, DevState s)
 {
     __shared__ uint32_t lists[256 / LPP * STEP_LIST];
+    __shared__ float4 crl[TLDS ? STEP_CR_LDS : 1];
+    const float4* cr = stage_segments<TLDS>(m, crl);
     uint32_t* list = lists + (threadIdx.x / LPP) * STEP_LIST;
     const long long P = sh.P;
     const Lane L = lane_setup(m, s, P, off, gain, true);
     float sz, shh[KM], shp[KM];
-    accumulate(m, L.q, L.live ? s.b[L.pix] : 1.f, L.live ? L.G : 1.f, ent, L.e0, L.e1, L.sub, list, sz, shh, shp);
-    reduce_lanes(sz, shh, shp);
+    // S' first: its table reads do not wait for the entries
     float Sv[KM], Spv[KM];
     s_eval_points(m, L.q, L.sub, Sv, Spv);
+    accumulate(m, cr, L.q, L.live ? s.b[L.pix] : 1.f, L.live ? L.G : 1.f, ent, L.e0, L.e1, L.sub, list, sz, shh, shp);
+    reduce_lanes(sz, shh, shp);
     if (!L.live || L.sub != 0) return;
 #pragma unroll
     for (int k = 0; k < KM; ++k)
@@ -257,19 +274,21 @@ __device__ __forceinline__ void merge_lane(const DevState& s, long long P, const
 
 // MERGE: the in-pixel merge runs first (the loop's order: merge, then the
 // intensity step on the merged points).
-template <bool MERGE>
+template <bool MERGE, bool TLDS>
 __global__ __launch_bounds__(256) void k_intensity_step(DevModel m, DevParams p, Shape sh,
                                                         const uint32_t* __restrict__ off,
                                                         const uint32_t* __restrict__ ent,
                                                         const float* __restrict__ gain, DevState s)
 {
     __shared__ uint32_t lists[256 / LPP * STEP_LIST];
+    __shared__ float4 crl[TLDS ? STEP_CR_LDS : 1];
+    const float4* cr = stage_segments<TLDS>(m, crl);
     uint32_t* list = lists + (threadIdx.x / LPP) * STEP_LIST;
     const long long P = sh.P;
     Lane L = lane_setup(m, s, P, off, gain, true);
     if (MERGE && L.member) merge_lane(s, P, p, L.pix, L.sub, L.q);
     float sz, shh[KM], shp[KM];
-    accumulate(m, L.q, L.live ? s.b[L.pix] : 1.f, L.live ? L.G : 1.f, ent, L.e0, L.e1, L.sub, list, sz, shh, shp);
+    accumulate(m, cr, L.q, L.live ? s.b[L.pix] : 1.f, L.live ? L.G : 1.f, ent, L.e0, L.e1, L.sub, list, sz, shh, shp);
     reduce_lanes(sz, shh, shp);
     float Sv[KM], Spv[KM];
     s_eval_points(m, L.q, L.sub, Sv, Spv);
@@ -281,19 +300,22 @@ __global__ __launch_bounds__(256) void k_intensity_step(DevModel m, DevParams p,
 
 // The background step writes the new b to bdst (the state's own b, or a
 // second buffer the background filter reads); dead pixels keep their b.
+template <bool TLDS>
 __global__ __launch_bounds__(256) void k_bg_step(DevModel m, DevParams p, Shape sh,
                                                  const uint32_t* __restrict__ off,
                                                  const uint32_t* __restrict__ ent,
                                                  const float* __restrict__ gain, DevState s, float* bdst)
 {
     __shared__ uint32_t lists[256 / LPP * STEP_LIST];
+    __shared__ float4 crl[TLDS ? STEP_CR_LDS : 1];
+    const float4* cr = stage_segments<TLDS>(m, crl);
     uint32_t* list = lists + (threadIdx.x / LPP) * STEP_LIST;
     const long long P = sh.P;
     const Lane L = lane_setup(m, s, P, off, gain, false);
     const float braw = L.pix < P ? s.b[L.pix] : 1.f;
     const float bb = L.live ? braw : 1.f;
     float sz, shh[KM], shp[KM];
-    accumulate(m, L.q, bb, L.live ? L.G : 1.f, ent, L.e0, L.e1, L.sub, list, sz, shh, shp);
+    accumulate(m, cr, L.q, bb, L.live ? L.G : 1.f, ent, L.e0, L.e1, L.sub, list, sz, shh, shp);
     reduce_lanes(sz, shh, shp);
     if (!L.member || L.sub != 0) return;
     if (!L.live) {
@@ -303,6 +325,7 @@ __global__ __launch_bounds__(256) void k_bg_step(DevModel m, DevParams p, Shape 
     bdst[L.pix] = background_next(m, p, bb, sz);
 }
 
+template <bool TLDS>
 __global__ __launch_bounds__(256) void k_gradients(DevModel m, Shape sh, const uint32_t* __restrict__ off,
                                                    const uint32_t* __restrict__ ent,
                                                    const float* __restrict__ gain, DevState s,
@@ -310,11 +333,13 @@ __global__ __launch_bounds__(256) void k_gradients(DevModel m, Shape sh, const u
                                                    float* __restrict__ gb)
 {
     __shared__ uint32_t lists[256 / LPP * STEP_LIST];
+    __shared__ float4 crl[TLDS ? STEP_CR_LDS : 1];
+    const float4* cr = stage_segments<TLDS>(m, crl);
     uint32_t* list = lists + (threadIdx.x / LPP) * STEP_LIST;
     const long long P = sh.P;
     const Lane L = lane_setup(m, s, P, off, gain, false);
     float sz, shh[KM], shp[KM];
-    accumulate(m, L.q, L.live ? s.b[L.pix] : 1.f, L.live ? L.G : 1.f, ent, L.e0, L.e1, L.sub, list, sz, shh, shp);
+    accumulate(m, cr, L.q, L.live ? s.b[L.pix] : 1.f, L.live ? L.G : 1.f, ent, L.e0, L.e1, L.sub, list, sz, shh, shp);
     reduce_lanes(sz, shh, shp);
     float Sv[KM], Spv[KM];
     s_eval_points(m, L.q, L.sub, Sv, Spv);
@@ -407,12 +432,15 @@ hipError_t launch_class_lists(const uint8_t* cls, long long P, int n, uint32_t* 
     return hipGetLastError();
 }
 
+static inline bool segments_fit(const DevModel& m) { return m.L + 1 <= STEP_CR_LDS; }
+
 hipError_t launch_depth_step(const DevModel& m, const DevParams& p, const Shape& sh, const uint32_t* off,
                              const uint32_t* ent, const float* gain, DevState s, hipStream_t st)
 {
     if (sh.P == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_depth_step, dim3(blocks_for(sh.P * LPP, 256)), dim3(256), 0, st, m, p, sh, off, ent, gain,
-                       s);
+    const dim3 g(blocks_for(sh.P * LPP, 256)), b(256);
+    if (segments_fit(m)) hipLaunchKernelGGL(k_depth_step<true>, g, b, 0, st, m, p, sh, off, ent, gain, s);
+    else hipLaunchKernelGGL(k_depth_step<false>, g, b, 0, st, m, p, sh, off, ent, gain, s);
     return hipGetLastError();
 }
 
@@ -420,12 +448,12 @@ hipError_t launch_intensity_step(const DevModel& m, const DevParams& p, const Sh
                                  const uint32_t* ent, const float* gain, DevState s, bool merge, hipStream_t st)
 {
     if (sh.P == 0) return hipSuccess;
-    if (merge)
-        hipLaunchKernelGGL(k_intensity_step<true>, dim3(blocks_for(sh.P * LPP, 256)), dim3(256), 0, st, m, p, sh,
-                           off, ent, gain, s);
-    else
-        hipLaunchKernelGGL(k_intensity_step<false>, dim3(blocks_for(sh.P * LPP, 256)), dim3(256), 0, st, m, p, sh,
-                           off, ent, gain, s);
+    const dim3 g(blocks_for(sh.P * LPP, 256)), b(256);
+    const bool tl = segments_fit(m);
+    if (merge && tl) hipLaunchKernelGGL((k_intensity_step<true, true>), g, b, 0, st, m, p, sh, off, ent, gain, s);
+    else if (merge) hipLaunchKernelGGL((k_intensity_step<true, false>), g, b, 0, st, m, p, sh, off, ent, gain, s);
+    else if (tl) hipLaunchKernelGGL((k_intensity_step<false, true>), g, b, 0, st, m, p, sh, off, ent, gain, s);
+    else hipLaunchKernelGGL((k_intensity_step<false, false>), g, b, 0, st, m, p, sh, off, ent, gain, s);
     return hipGetLastError();
 }
 
@@ -433,8 +461,10 @@ hipError_t launch_bg_step(const DevModel& m, const DevParams& p, const Shape& sh
                           const uint32_t* ent, const float* gain, DevState s, float* bdst, hipStream_t st)
 {
     if (sh.P == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bg_step, dim3(blocks_for(sh.P * LPP, 256)), dim3(256), 0, st, m, p, sh, off, ent, gain, s,
-                       bdst ? bdst : s.b);
+    const dim3 g(blocks_for(sh.P * LPP, 256)), b(256);
+    float* dst = bdst ? bdst : s.b;
+    if (segments_fit(m)) hipLaunchKernelGGL(k_bg_step<true>, g, b, 0, st, m, p, sh, off, ent, gain, s, dst);
+    else hipLaunchKernelGGL(k_bg_step<false>, g, b, 0, st, m, p, sh, off, ent, gain, s, dst);
     return hipGetLastError();
 }
 
@@ -444,8 +474,9 @@ hipError_t launch_gradients(const DevModel& m, const DevParams& p, const Shape& 
 {
     (void)p;
     if (sh.P == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gradients, dim3(blocks_for(sh.P * LPP, 256)), dim3(256), 0, st, m, sh, off, ent, gain, s,
-                       gt, gr, gb);
+    const dim3 g(blocks_for(sh.P * LPP, 256)), b(256);
+    if (segments_fit(m)) hipLaunchKernelGGL(k_gradients<true>, g, b, 0, st, m, sh, off, ent, gain, s, gt, gr, gb);
+    else hipLaunchKernelGGL(k_gradients<false>, g, b, 0, st, m, sh, off, ent, gain, s, gt, gr, gb);
     return hipGetLastError();
 }
 

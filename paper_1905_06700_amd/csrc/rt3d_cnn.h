@@ -51,6 +51,10 @@ unsigned cnn_wgrad_groups(const Shape& sh);
 hipError_t launch_cnn_prepare(const CnnWeights& w, hipStream_t st);
 hipError_t launch_cnn_forward(const Shape& sh, DevState s, float sigma_h, const CnnWeights& w, const CnnBuffers& b,
                               hipStream_t st);
+// The same network output as launch_cnn_forward, by the fused kernel (no
+// stored activations: inference only).
+hipError_t launch_cnn_infer(const Shape& sh, DevState s, float sigma_h, const CnnWeights& w, const CnnBuffers& b,
+                            hipStream_t st);
 hipError_t launch_cnn_apply(const Shape& sh, const CnnBuffers& b, float sigma_h, double tmax, DevState s,
                             hipStream_t st);
 hipError_t launch_cnn_unpack(const Shape& sh, const CnnBuffers& b, float* out, hipStream_t st);

@@ -182,15 +182,21 @@ __device__ __forceinline__ void cr_segment(const float4 c, float s, float& h, fl
 // h(tb - t) and dh/dtau for an integer bin tb and a point at depth t held as
 // integer anchor a = floor(t) plus fraction f = t - a.  h is the Catmull-Rom
 // interpolant of the IRF samples (continuous value and slope).
-__device__ __forceinline__ void irf_eval(const DevModel& m, int tb, int a, float f, float& h, float& hp)
+__device__ __forceinline__ void irf_eval_t(const float4* __restrict__ cr, int L, int o, int tb, int a, float f,
+                                           float& h, float& hp)
 {
-    const float x = (float)(tb - a + m.o) - f;   // sample position of the lag
+    const float x = (float)(tb - a + o) - f;   // sample position of the lag
     h = 0.f;
     hp = 0.f;
-    if (x > -1.f && x < (float)m.L) {
+    if (x > -1.f && x < (float)L) {
         const float fk = floorf(x);
-        cr_segment(m.cr[(int)fk + 1], x - fk, h, hp);
+        cr_segment(cr[(int)fk + 1], x - fk, h, hp);
     }
+}
+
+__device__ __forceinline__ void irf_eval(const DevModel& m, int tb, int a, float f, float& h, float& hp)
+{
+    irf_eval_t(m.cr, m.L, m.o, tb, a, f, h, hp);
 }
 
 // S(t) = sum over bins of h(tb - t) and dS/dt = -sum h'(tb - t) (every lag

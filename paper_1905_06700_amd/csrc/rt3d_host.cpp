@@ -588,6 +588,15 @@ int n_classes(const rt3d_ctx* c, const uint8_t* cls) { return cls ? (int)c->irf.
 // Per-pixel steps run once over the batch (sh), once per IRF class with a
 // class map cls; steps that read neighbouring pixels run once per group of
 // equally sized frames.
+// The inference buffers of the learned denoiser for the pixels from `base` on.
+CnnBuffers cnn_at(const CnnBuffers& b, long long base)
+{
+    CnnBuffers r = b;
+    r.act[0] += base * 16;
+    r.act[4] += base * 16;
+    return r;
+}
+
 // One iteration on the state whose planes `cur` points at; `alt` holds the
 // other buffer of each plane.  Kernels that read neighbours' values write the
 // planes they change to the other buffer (APSS: depths and normals; the
@@ -622,11 +631,17 @@ rt3d_status iterate(rt3d_ctx* c, const Shape& sh, const std::vector<Group>& grou
         std::swap(cur.t, alt.t);
         std::swap(cur.n, alt.n);
     } else if (c->p.denoiser == RT3D_DENOISE_CNN) {
-        // APSS only for pixels holding more points than the network's three slots
-        RT3D_LAUNCH(c, RT3D_KERNEL_APSS, st, launch_apss(m, p, sh, cur, alt, 3, st));
-        RT3D_LAUNCH(c, RT3D_KERNEL_CNN, st,
-                    launch_cnn_forward(sh, alt, (float)std::sqrt(c->irf[0].sigma2), c->cnn, *cnn, st));
-        RT3D_HIP(c, launch_cnn_apply(sh, *cnn, (float)std::sqrt(c->irf[0].sigma2), (double)(c->T - 1), alt, st));
+        // APSS only for pixels holding more points than the network's three
+        // slots, then the network on each group of equal-size frames
+        for (const Tiles& tg : tiles)
+            RT3D_LAUNCH(c, RT3D_KERNEL_APSS, st, launch_apss_tiles(m, p, tg, cur, alt, 3, true, st));
+        const float sig = (float)std::sqrt(c->irf[0].sigma2);
+        for (const Group& g : groups) {
+            const CnnBuffers b = cnn_at(*cnn, g.base);
+            const DevState ga = state_at(alt, g.base);
+            RT3D_LAUNCH(c, RT3D_KERNEL_CNN, st, launch_cnn_infer(g.sh, ga, sig, c->cnn, b, st));
+            RT3D_HIP(c, launch_cnn_apply(g.sh, b, sig, (double)(c->T - 1), ga, st));
+        }
         std::swap(cur, alt);
     } else {
         RT3D_HIP(c, launch_copy_state(sh, cur, alt, st));
@@ -961,8 +976,6 @@ rt3d_status rt3d_reconstruct(rt3d_ctx* c, const rt3d_input* in, rt3d_output* out
         }
         for (Group& g : groups) g.sh.S = P;
         sh = shape_of(1, 1, (uint32_t)P);
-        if (groups.size() > 1 && c->p.denoiser == RT3D_DENOISE_CNN)
-            return fail(c, RT3D_E_UNSUPPORTED, "the learned denoiser needs frames of one size");
         if (c->p.sr > 1) return fail(c, RT3D_E_UNSUPPORTED, "super-resolution needs frames of one size");
     } else {
         if (!shape_ok(in->frames, in->rows, in->cols))
@@ -1587,7 +1600,7 @@ rt3d_status rt3d_cnn_forward(rt3d_ctx* c, const rt3d_state* st, float* y, void* 
     if (s != RT3D_OK) return s;
     const Shape sh = shape_of(st->frames, st->rows, st->cols);
     hipStream_t hs = (hipStream_t)hip_stream;
-    RT3D_HIP(c, launch_cnn_forward(sh, dev_state(st), (float)std::sqrt(c->irf[0].sigma2), c->cnn, w.cnn, hs));
+    RT3D_HIP(c, launch_cnn_infer(sh, dev_state(st), (float)std::sqrt(c->irf[0].sigma2), c->cnn, w.cnn, hs));
     RT3D_HIP(c, launch_cnn_unpack(sh, w.cnn, y, hs));
     return RT3D_OK;
 }

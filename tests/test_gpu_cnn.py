@@ -243,25 +243,21 @@ def _scores(scenes, res, sig, R, C):
 
 
 def test_trained_network_beats_no_denoiser():
-    """Train on the GPU (the library's own kernels) on depth-block inputs
-    recorded from plain-APSS runs of multi-layer scenes (6 signal photons per
-    pixel, SBR 0.2), then reconstruct held-out scenes: the network's depth
-    error over the surfaces found is lower than with no depth denoiser, at the
-    same detection rate."""
-    R, C_, F, T_ = 96, 96, 6, 1024
-    trn = [synth.layers_scene(s, rows=R, cols=C_, T=T_, signal=6.0, sbr=0.2) for s in range(F)]
-    p = params(trn[0])
-    apss = rt3d.Context(trn[0].irf.probs, T_, **p)
-    net = rt3d.Context(trn[0].irf.probs, T_, denoiser=rt3d.DENOISE_CNN, **p)
-    none = rt3d.Context(trn[0].irf.probs, T_, denoiser=rt3d.DENOISE_NONE, **p)
-    Z = torch.cat([to_dev_hist(s.Z)[None] for s in trn])
-    recorded = train.record_depth_inputs(apss, Z, iters=(0, 1, 2, 4, 7, 11), n_iter=12)
-    truth = torch.from_numpy(np.concatenate([s.depth.reshape(3, -1) for s in trn], axis=1)
-                             .astype(np.float32)).cuda()
-    net.workspace(F, R, C_, F * R * C_ * 200)
-    hist = train.train(net, [(recorded, truth)], steps=600, lr=2e-3, seed=7, log_every=100,
-                       log=lambda m: print("[gpu-cnn]", m, flush=True))
-    del recorded
+    """Train on the GPU (the library's own kernels) by the training recipe --
+    depth-block inputs recorded at iterations 1, 2, 5, 10 and 20 of plain-APSS
+    runs of multi-layer scenes (6 signal photons per pixel, SBR 0.2), random
+    crops -- then reconstruct held-out scenes: the network's depth error over
+    the surfaces found is lower than with no depth denoiser, at the same
+    detection rate."""
+    R, C_, T_, n_scenes = 96, 96, 1024, 24
+    sc0 = synth.layers_scene(0, rows=8, cols=8, T=T_)
+    p = params(sc0)
+    apss = rt3d.Context(sc0.irf.probs, T_, **p)
+    net = rt3d.Context(sc0.irf.probs, T_, denoiser=rt3d.DENOISE_CNN, **p)
+    none = rt3d.Context(sc0.irf.probs, T_, denoiser=rt3d.DENOISE_NONE, **p)
+    lists = (train.scene_lists((s, R, C_, T_, 6.0, 0.2)) for s in range(n_scenes))
+    hist = train.train_recipe(net, apss, lists, n_scenes, steps=600, rows=R, cols=C_, frames_per_batch=8,
+                              crop=64, batch=16, seed=7, log=lambda m: print("[gpu-cnn]", m, flush=True))
     test = [synth.layers_scene(100 + s, rows=R, cols=C_, T=T_, signal=6.0, sbr=0.2) for s in range(2)]
     sig = float(np.sqrt(net.sigma2))
     Zt = torch.cat([to_dev_hist(s.Z)[None] for s in test])
@@ -271,6 +267,6 @@ def test_trained_network_beats_no_denoiser():
         res = ctx.make_output(2 * R * C_)
         ctx.reconstruct_into(res, 2, R, C_, hist=Zt)
         r[name] = _scores(test, res, sig, R, C_)
-    print(f"[gpu-cnn] held-out (matched RMSE bins, found fraction): {r}; training loss {hist}", flush=True)
+    print(f"[gpu-cnn] held-out (RMSE over found surfaces, found fraction): {r}; training loss {hist}", flush=True)
     assert r["cnn"][0] < 0.95 * r["none"][0]
     assert r["cnn"][1] >= r["none"][1] - 0.02

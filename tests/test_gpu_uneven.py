@@ -65,7 +65,7 @@ def test_uneven_batch_equals_frames_alone():
     assert int(out.pt_off[-1].item()) == sum(int(r[0][-1]) for r in ref)
 
 
-def test_uneven_batch_graph_replay_and_learned_denoiser_refused():
+def test_uneven_batch_graph_replay():
     scs = scenes()[:3]
     shapes = SHAPES[:3]
     ctx = rt3d.Context(scs[0].irf.probs, T, **params_for(scs[0]))
@@ -86,8 +86,31 @@ def test_uneven_batch_graph_replay_and_learned_denoiser_refused():
     for name in ("depth", "intensity", "normal"):
         assert torch.equal(getattr(direct, name)[:n], getattr(replayed, name)[:n]), name
     del g
-    cnn = rt3d.Context(scs[0].irf.probs, T, **dict(params_for(scs[0]), denoiser=rt3d.DENOISE_CNN))
-    cnn.workspace(1, 1, P, P * 64)
-    with pytest.raises(rt3d.Rt3dError) as e:
-        cnn.reconstruct_into(cnn.make_output(P), len(shapes), 1, 1, hist=Z, frame_shapes=shapes)
-    assert e.value.status == rt3d.E_UNSUPPORTED
+
+
+def test_uneven_batch_with_learned_denoiser_equals_frames_alone():
+    """The learned denoiser runs once per group of equal-size frames; each
+    frame of the batch equals the frame reconstructed alone, to the bit."""
+    from oracle import cnn
+    scs = scenes()
+    w = cnn.he_init(3).astype(np.float32)
+    rng = np.random.default_rng(4)
+    w += rng.normal(0, 0.02, w.shape).astype(np.float32)
+    prm = dict(params_for(scs[0]), denoiser=rt3d.DENOISE_CNN, fused_loop=0, n_iter=4)
+    ctx = rt3d.Context(scs[0].irf.probs, T, **prm)
+    ctx.cnn_set_weights(w)
+    sizes = [r * c for r, c in SHAPES]
+    bases = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+    P = int(sum(sizes))
+    ref = [frame_slices(alone(ctx, sc), [0], [sc.rows * sc.cols])[0] for sc in scs]
+    Z = torch.cat([to_dev_hist(sc.Z).reshape(-1, T) for sc in scs]).contiguous()
+    ctx.workspace(1, 1, P, P * 64)
+    out = ctx.make_output(P)
+    print(f"[gpu-uneven] learned denoiser, {len(SHAPES)} frames {SHAPES} in one call", flush=True)
+    ctx.reconstruct_into(out, len(SHAPES), 1, 1, hist=Z, frame_shapes=SHAPES)
+    assert ctx.query().device_error == 0
+    got = frame_slices(out, bases, sizes)
+    for f, (a, b) in enumerate(zip(got, ref)):
+        np.testing.assert_array_equal(a[0], b[0], err_msg=f"frame {f} point offsets")
+        for name, x, y in zip(("depth", "intensity", "normal", "background"), a[1:], b[1:]):
+            assert torch.equal(x, y), f"frame {f} {name}"
