@@ -626,6 +626,8 @@ def execution_time_sweep(reps=5):
 
 
 DENOISER_CHECKPOINT = os.path.join(ROOT, "paper_1905_06700_amd", "weights", "denoiser_c4.rt3dcnn")
+# the same recipe on scenes of the brighter regime (6 signal photons/px, SBR 0.2)
+DENOISER_CHECKPOINT_BRIGHT = os.path.join(ROOT, "paper_1905_06700_amd", "weights", "denoiser_bright.rt3dcnn")
 
 
 def _evaluate(ctx, scenes, rows, cols, bins, sig, batch=16):
@@ -711,8 +713,12 @@ def learned_vs_apss(rows=256, cols=256, bins=1024, n_eval=50, n_high=16):
     hi = [synth.layers_scene(10000 + s, rows=rows, cols=cols, T=bins, signal=6.0, sbr=0.2) for s in range(n_high)]
     out["bright"] = {"workload": f"{rows}x{cols}x{bins} multi-layer scenes, 6 signal photons/px, SBR 0.2, "
                                  f"held-out seeds 10000..{10000 + n_high - 1}"}
-    for name, ctx in (("apss", apss), ("cnn", net)):
-        out["bright"][name] = _evaluate(ctx, hi, rows, cols, bins, sig)
+    out["bright"]["apss"] = _evaluate(apss, hi, rows, cols, bins, sig)
+    out["bright"]["cnn_config4_weights"] = _evaluate(net, hi, rows, cols, bins, sig)
+    if os.path.exists(DENOISER_CHECKPOINT_BRIGHT):
+        net.denoiser_load(DENOISER_CHECKPOINT_BRIGHT)
+        out["bright"]["training"] = {"checkpoint": os.path.relpath(DENOISER_CHECKPOINT_BRIGHT, ROOT)}
+    out["bright"]["cnn"] = _evaluate(net, hi, rows, cols, bins, sig)
     for d in (out, out["bright"]):
         d["rmse_ratio_cnn_over_apss"] = round(d["cnn"]["depth_rmse_bins"] / d["apss"]["depth_rmse_bins"], 4)
         d["rmse_found_ratio_cnn_over_apss"] = round(d["cnn"]["depth_rmse_found_bins"] /

@@ -127,6 +127,13 @@ typedef struct rt3d_params {
                           * no part; 1: divided by 1 + the number of surrounding pixels inside the
                           * image (a 3 x 3 box in which a missing neighbour counts as zero intensity,
                           * which attenuates isolated points).  E_INVALID for other values. */
+    int32_t  lanes_per_pixel; /* lanes that share one pixel's active bins in the gradient steps: 4 or
+                          * 8; 0 (default): rt3d_autotune's choice for the batch shape, else 8 below
+                          * 131,072 pixels per call (four would leave most of the chip idle) and 4
+                          * from there on.  The results do not depend on it beyond FP32 summation
+                          * order; a frame gives the same bits in every batch only where this is
+                          * fixed (4 or 8), as the default follows the batch's size.  E_INVALID for
+                          * other values. */
 } rt3d_params;
 
 /* Input kinds. */
@@ -322,16 +329,22 @@ rt3d_status rt3d_query(rt3d_ctx* ctx, void* hip_stream, rt3d_stats* st);
 #define RT3D_KERNEL_CNN      11   /* learned denoiser forward (features + four convolutions) */
 #define RT3D_KERNEL_LOOP     12   /* every iteration in one launch (params.fused_loop) */
 #define RT3D_KERNEL_COUNT    13
-/* Autotuning.  Times a reconstruction of this input both ways the library can
- * map the loop onto the GPU (one launch per step; all iterations in one
- * launch, one workgroup per frame) and keeps the faster for this batch shape
- * (frames x rows x cols) in the context, where params.fused_loop = -1 uses it.
- * Synchronises the stream; the output holds the last timed reconstruction.
- * *fused (may be NULL) receives the choice: 1 one launch, 0 per step; a batch
- * that cannot take the one-launch loop gets 0 without timing.  Not while a
- * graph is being recorded. */
+/* Autotuning.  Times a reconstruction of this input in each mapping of the
+ * loop onto the GPU the batch admits -- one launch per step with 4 lanes per
+ * pixel in the gradient steps, the same with 8 lanes, and all iterations in one
+ * launch (one workgroup per frame; frames of one size up to 4096 pixels with
+ * APSS) -- and keeps the fastest for this batch shape (frames x rows x cols) in
+ * the context, where params.fused_loop = -1 and params.lanes_per_pixel = 0 use
+ * it.  Synchronises the stream; the output holds the last timed
+ * reconstruction.  *fused (may be NULL) receives 1 for the one-launch loop, 0
+ * for one launch per step.  Batches of several frame sizes keep the defaults
+ * (nothing is timed).  Not while a graph is being recorded.
+ * rt3d_mapping reports the mapping rt3d_reconstruct would take for this input
+ * (*fused as above, *lanes the lanes per pixel of the per-step gradient
+ * kernels); no GPU work. */
 rt3d_status rt3d_autotune(rt3d_ctx* ctx, const rt3d_input* in, rt3d_output* out, void* hip_stream,
                           int32_t* fused);
+rt3d_status rt3d_mapping(rt3d_ctx* ctx, const rt3d_input* in, int32_t* fused, int32_t* lanes);
 rt3d_status rt3d_profile(rt3d_ctx* ctx, int32_t id);
 rt3d_status rt3d_profile_read(rt3d_ctx* ctx, double* total_ms, uint64_t* launches);
 

@@ -136,28 +136,77 @@ hipError_t launch_scan(const uint32_t* in, uint32_t* out, long long n, uint32_t*
 
 constexpr int CP_WAVES = 4;   // pixels (wavefronts) per block
 
-// Loads the 8 bins of vector v (bins 8v .. 8v+7 of the flat histogram array);
-// bins outside [lo, hi) read as 0.  Vectors wholly inside the array use one
-// 16-byte load; the array's last partial vector is read element-wise.
-__device__ __forceinline__ void load8(const uint16_t* __restrict__ Z, long long v, long long lo, long long hi,
-                                      long long total, uint16_t (&z)[8])
+// One pixel's histogram as 16-byte vectors of 8 bins: vector vr (0 <= vr <
+// nvec) holds bins 8 (vs + vr) .. 8 (vs + vr) + 7 of the flat array, the
+// pixel's bins being those at offsets [lo_off, hi_end) from bin 8 vs (pixels
+// are not 8-bin aligned).  32-bit offsets inside the pixel; the 64-bit
+// address is formed once.
+struct PixVec {
+    const uint4* zv;      // first vector of the pixel
+    const uint16_t* z0;   // its first bin
+    int nvec, lo_off, hi_end, tail;   // tail: bins of the array's last vector (8 if whole)
+};
+
+__device__ __forceinline__ PixVec pix_vectors(const uint16_t* __restrict__ Z, long long p, int T, long long total)
 {
-    long long i0 = v << 3;
-    if (i0 + 8 <= total) {
-        uint4 x = *reinterpret_cast<const uint4*>(Z + i0);
-        uint32_t w[4] = {x.x, x.y, x.z, x.w};
+    const long long lo = p * T, vs = lo >> 3;
+    PixVec v;
+    v.zv = reinterpret_cast<const uint4*>(Z) + vs;
+    v.z0 = Z + (vs << 3);
+    v.nvec = (int)(((lo + T + 7) >> 3) - vs);
+    v.lo_off = (int)(lo - (vs << 3));
+    v.hi_end = v.lo_off + T;
+    const long long left = total - ((vs + v.nvec - 1) << 3);   // bins of the array from the last vector on
+    v.tail = left < 8 ? (int)left : 8;                         // < 8 only for the array's partial last vector
+    return v;
+}
+
+// The 8 bins of vector vr as four words of two bins each; bins outside the
+// pixel read as 0 (only its first and last vector hold any).
+__device__ __forceinline__ void load8(const PixVec& pv, int vr, uint32_t (&w)[4])
+{
+    if (vr == pv.nvec - 1 && pv.tail < 8) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            z[2 * k] = (uint16_t)(w[k] & 0xffffu);
-            z[2 * k + 1] = (uint16_t)(w[k] >> 16);
+        for (int q = 0; q < 4; ++q) {
+            const int k = (vr << 3) + 2 * q;
+            const uint32_t a = 2 * q < pv.tail ? pv.z0[k] : 0u;
+            const uint32_t b = 2 * q + 1 < pv.tail ? pv.z0[k + 1] : 0u;
+            w[q] = a | (b << 16);
         }
     } else {
-#pragma unroll
-        for (int k = 0; k < 8; ++k) z[k] = (i0 + k < total) ? Z[i0 + k] : (uint16_t)0;
+        const uint4 x = pv.zv[vr];
+        w[0] = x.x;
+        w[1] = x.y;
+        w[2] = x.z;
+        w[3] = x.w;
     }
+    const int r0 = vr << 3;
+    if (r0 < pv.lo_off || r0 + 8 > pv.hi_end) {
 #pragma unroll
-    for (int k = 0; k < 8; ++k)
-        if (i0 + k < lo || i0 + k >= hi) z[k] = 0;
+        for (int k = 0; k < 8; ++k)
+            if (r0 + k < pv.lo_off || r0 + k >= pv.hi_end) w[k >> 1] &= (k & 1) ? 0x0000ffffu : 0xffff0000u;
+    }
+}
+
+// Bit k of the result: bin k of the vector is non-zero (bit 15 of each
+// 16-bit half set by adding 0x7fff to its low 15 bits, or'ed with the half).
+__device__ __forceinline__ uint32_t nonzero8(const uint32_t (&w)[4])
+{
+    uint32_t m = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const uint32_t t = (((w[q] & 0x7fff7fffu) + 0x7fff7fffu) | w[q]) & 0x80008000u;
+        m |= ((t >> 15) | (t >> 30)) << (2 * q);
+    }
+    return m & 0xffu;
+}
+
+// Count of bin k of the vector.
+__device__ __forceinline__ uint32_t bin8(const uint32_t (&w)[4], int k)
+{
+    const int q = k >> 1;
+    const uint32_t x = q == 0 ? w[0] : q == 1 ? w[1] : q == 2 ? w[2] : w[3];
+    return (k & 1) ? x >> 16 : x & 0xffffu;
 }
 
 // Pass 1: each pixel's histogram is read once; its non-zero bins, as entries
@@ -165,7 +214,8 @@ __device__ __forceinline__ void load8(const uint16_t* __restrict__ Z, long long 
 // entries (the first CP_STAGE of them when it has more; no staging when
 // `stage` is null), and its entry count to counts[p].  One wavefront per
 // pixel; each lane holds 8 consecutive bins and a wavefront prefix sum of the
-// lanes' non-zero counts places them.
+// lanes' non-zero counts places them; a lane writes its non-zero bins one set
+// bit of its mask at a time (most lanes hold none).
 __global__ __launch_bounds__(64 * CP_WAVES) void k_compact_stage(const uint16_t* __restrict__ Z, long long P,
                                                                  int T, uint32_t* __restrict__ counts,
                                                                  uint32_t* __restrict__ stage)
@@ -173,30 +223,23 @@ __global__ __launch_bounds__(64 * CP_WAVES) void k_compact_stage(const uint16_t*
     const long long p = (long long)blockIdx.x * CP_WAVES + (threadIdx.x >> 6);
     if (p >= P) return;
     const int lane = threadIdx.x & 63;
-    const long long lo = p * T, hi = lo + T, total = P * T;
-    const long long vs = lo >> 3, ve = (hi + 7) >> 3;
+    const PixVec pv = pix_vectors(Z, p, T, P * T);
     uint32_t* slot = stage ? stage + p * CP_STAGE : nullptr;
     uint32_t run = 0;
-    for (long long vb = vs; vb < ve; vb += 64) {       // uniform over the wave
-        const long long v = vb + lane;
-        uint16_t z[8];
-        if (v < ve) load8(Z, v, lo, hi, total, z);
-        else {
-#pragma unroll
-            for (int k = 0; k < 8; ++k) z[k] = 0;
-        }
-        uint32_t c = 0;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) c += z[k] != 0;
+    for (int vb = 0; vb < pv.nvec; vb += 64) {        // uniform over the wave
+        const int vr = vb + lane;
+        uint32_t w[4] = {0u, 0u, 0u, 0u};
+        if (vr < pv.nvec) load8(pv, vr, w);
+        uint32_t m = nonzero8(w);
+        const uint32_t c = (uint32_t)__builtin_popcount(m);
         const uint32_t inc = wave_incl_scan(c);
         uint32_t pos = run + (inc - c);
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            if (z[k]) {
-                const uint32_t bin = (uint32_t)((v << 3) + k - lo);
-                if (slot && pos < CP_STAGE) slot[pos] = (bin << 16) | z[k];
-                ++pos;
-            }
+        const uint32_t base = (uint32_t)((vr << 3) - pv.lo_off);
+        while (m) {
+            const int k = __builtin_ctz(m);
+            m &= m - 1u;
+            if (slot && pos < CP_STAGE) slot[pos] = ((base + k) << 16) | bin8(w, k);
+            ++pos;
         }
         run += (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
     }
@@ -227,30 +270,23 @@ __global__ __launch_bounds__(64 * CP_WAVES) void k_compact_copy(const uint16_t* 
             else overflow = true;
         }
     } else {
-        const long long lo = p * T, hi = lo + T, total = P * T;
-        const long long vs = lo >> 3, ve = (hi + 7) >> 3;
+        const PixVec pv = pix_vectors(Z, p, T, P * T);
         uint64_t run = base;
-        for (long long vb = vs; vb < ve; vb += 64) {   // uniform over the wave
-            const long long v = vb + lane;
-            uint16_t z[8];
-            if (v < ve) load8(Z, v, lo, hi, total, z);
-            else {
-#pragma unroll
-                for (int k = 0; k < 8; ++k) z[k] = 0;
-            }
-            uint32_t c = 0;
-#pragma unroll
-            for (int k = 0; k < 8; ++k) c += z[k] != 0;
+        for (int vb = 0; vb < pv.nvec; vb += 64) {     // uniform over the wave
+            const int vr = vb + lane;
+            uint32_t w[4] = {0u, 0u, 0u, 0u};
+            if (vr < pv.nvec) load8(pv, vr, w);
+            uint32_t m = nonzero8(w);
+            const uint32_t c = (uint32_t)__builtin_popcount(m);
             const uint32_t inc = wave_incl_scan(c);
             uint64_t pos = run + (inc - c);
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                if (z[k]) {
-                    const uint32_t bin = (uint32_t)((v << 3) + k - lo);
-                    if (pos < cap) ent[pos] = (bin << 16) | z[k];
-                    else overflow = true;
-                    ++pos;
-                }
+            const uint32_t b0 = (uint32_t)((vr << 3) - pv.lo_off);
+            while (m) {
+                const int k = __builtin_ctz(m);
+                m &= m - 1u;
+                if (pos < cap) ent[pos] = ((b0 + k) << 16) | bin8(w, k);
+                else overflow = true;
+                ++pos;
             }
             run += (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
         }

@@ -27,10 +27,13 @@
 
 namespace rt3d {
 
-// Lanes per pixel: a pixel's active entries are split over LPP consecutive
-// lanes (entry e + LPP i), whose partial sums meet in a shuffle tree.
-constexpr int LPP = 4;
-constexpr int STEP_BATCH = 16;   // entries a lane loads at once
+// Lanes per pixel, LPP (a template parameter: 4 or 8): a pixel's active
+// entries are split over LPP consecutive lanes (entry e + LPP i), whose
+// partial sums meet in a shuffle tree.  Four lanes fill the chip at large
+// batches; eight halve the entries each lane walks, which shortens one
+// frame's critical path (the autotuner picks per batch shape).
+template <int LPP>
+constexpr int step_batch() { return 64 / LPP; }   // entries a lane loads at once
 
 // Orders the LDS traffic of one wavefront (a pixel's lanes share its list).
 __device__ __forceinline__ void step_sync()
@@ -40,8 +43,8 @@ __device__ __forceinline__ void step_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Entries of one batch of a pixel (STEP_BATCH per lane), staged in LDS.
-constexpr int STEP_LIST = STEP_BATCH * LPP;
+// Entries of one batch of a pixel (step_batch per lane), staged in LDS.
+constexpr int STEP_LIST = 64;
 
 // Partial sums over one pixel's entries (e0p .. e1 - 1):
 // sz = sum z/lambda, sh[k] = sum z h_k/lambda, shp[k] = sum z h'_k/lambda.
@@ -53,6 +56,7 @@ constexpr int STEP_LIST = STEP_BATCH * LPP;
 // entries ascend in bin, so the batch's support entries are one contiguous
 // run: the lanes count the entries below lo and up to hi, and then evaluate
 // the run from LDS, its entries shared out over the lanes in turn.
+template <int LPP>
 __device__ __forceinline__ void accumulate(const DevModel& m, const float4* cr, const PixPoints& q, float bb,
                                            float G, const uint32_t* __restrict__ ent, uint32_t e0p, uint32_t e1,
                                            int sub, uint32_t* list, float& sz, float (&sh)[KM], float (&shp)[KM])
@@ -73,6 +77,7 @@ __device__ __forceinline__ void accumulate(const DevModel& m, const float4* cr, 
         }
     int zout = 0;                                         // photons of this lane's entries outside the run
     for (uint32_t eb = e0p; eb < e1; eb += STEP_LIST) {    // the same trip count on the pixel's lanes
+        constexpr int STEP_BATCH = step_batch<LPP>();
         uint32_t v[STEP_BATCH];
 #pragma unroll
         for (int u = 0; u < STEP_BATCH; ++u) {
@@ -92,6 +97,10 @@ __device__ __forceinline__ void accumulate(const DevModel& m, const float4* cr, 
         }
         nlo = quad_sum_u32(nlo);
         nhi = quad_sum_u32(nhi);
+        if (LPP == 8) {   // the other quad of the pixel's eight lanes (half-row mirror)
+            nlo += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)nlo, 0x141, 0xF, 0xF, true);
+            nhi += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)nhi, 0x141, 0xF, 0xF, true);
+        }
         step_sync();
         for (uint32_t j = nlo + sub; j < nhi; j += LPP) {
             const uint32_t v1 = list[j];
@@ -124,22 +133,28 @@ __device__ __forceinline__ void accumulate(const DevModel& m, const float4* cr, 
 }
 
 // Sums the partials of the LPP lanes of a pixel (every lane ends with the total).
-static_assert(LPP == 4 || LPP == 8, "the lane reductions are sums over 4 or 8 lanes");
-__device__ __forceinline__ float lane_sum(float v) { return LPP == 4 ? quad_sum(v) : oct_sum(v); }
+template <int LPP>
+__device__ __forceinline__ float lane_sum(float v)
+{
+    static_assert(LPP == 4 || LPP == 8, "the lane reductions are sums over 4 or 8 lanes");
+    return LPP == 4 ? quad_sum(v) : oct_sum(v);
+}
 
+template <int LPP>
 __device__ __forceinline__ void reduce_lanes(float& sz, float (&sh)[KM], float (&shp)[KM])
 {
-    sz = lane_sum(sz);
+    sz = lane_sum<LPP>(sz);
 #pragma unroll
     for (int k = 0; k < KM; ++k) {
-        sh[k] = lane_sum(sh[k]);
-        shp[k] = lane_sum(shp[k]);
+        sh[k] = lane_sum<LPP>(sh[k]);
+        shp[k] = lane_sum<LPP>(shp[k]);
     }
 }
 
 // S and S' of the pixel's points, each sum split over the pixel's LPP lanes
 // (strided segments) and combined with shuffles; every lane ends with the
 // totals.
+template <int LPP>
 __device__ __forceinline__ void s_eval_points(const DevModel& m, const PixPoints& q, int sub, float (&S)[KM],
                                               float (&Sp)[KM])
 {
@@ -151,8 +166,8 @@ __device__ __forceinline__ void s_eval_points(const DevModel& m, const PixPoints
     }
 #pragma unroll
     for (int k = 0; k < KM; ++k) {
-        S[k] = lane_sum(S[k]);
-        Sp[k] = lane_sum(Sp[k]);
+        S[k] = lane_sum<LPP>(S[k]);
+        Sp[k] = lane_sum<LPP>(Sp[k]);
     }
 }
 
@@ -180,6 +195,7 @@ struct Lane {
     uint32_t e0, e1;   // the pixel's entries
 };
 
+template <int LPP>
 __device__ __forceinline__ Lane lane_setup(const DevModel& m, const DevState& s, long long P,
                                            const uint32_t* __restrict__ off, const float* __restrict__ gain,
                                            bool need_points)
@@ -209,7 +225,7 @@ __device__ __forceinline__ Lane lane_setup(const DevModel& m, const DevState& s,
     return L;
 }
 
-template <bool TLDS>
+template <int LPP, bool TLDS>
 __global__ __launch_bounds__(256) void k_depth_step(DevModel m, DevParams p, Shape sh,
                                                     const uint32_t* __restrict__ off,
                                                     const uint32_t* __restrict__ ent,
@@ -220,13 +236,13 @@ __global__ __launch_bounds__(256) void k_depth_step(DevModel m, DevParams p, Sha
     const float4* cr = stage_segments<TLDS>(m, crl);
     uint32_t* list = lists + (threadIdx.x / LPP) * STEP_LIST;
     const long long P = sh.P;
-    const Lane L = lane_setup(m, s, P, off, gain, true);
+    const Lane L = lane_setup<LPP>(m, s, P, off, gain, true);
     float sz, shh[KM], shp[KM];
     // S' first: its table reads do not wait for the entries
     float Sv[KM], Spv[KM];
-    s_eval_points(m, L.q, L.sub, Sv, Spv);
-    accumulate(m, cr, L.q, L.live ? s.b[L.pix] : 1.f, L.live ? L.G : 1.f, ent, L.e0, L.e1, L.sub, list, sz, shh, shp);
-    reduce_lanes(sz, shh, shp);
+    s_eval_points<LPP>(m, L.q, L.sub, Sv, Spv);
+    accumulate<LPP>(m, cr, L.q, L.live ? s.b[L.pix] : 1.f, L.live ? L.G : 1.f, ent, L.e0, L.e1, L.sub, list, sz, shh, shp);
+    reduce_lanes<LPP>(sz, shh, shp);
     if (!L.live || L.sub != 0) return;
 #pragma unroll
     for (int k = 0; k < KM; ++k)
@@ -274,7 +290,7 @@ __device__ __forceinline__ void merge_lane(const DevState& s, long long P, const
 
 // MERGE: the in-pixel merge runs first (the loop's order: merge, then the
 // intensity step on the merged points).
-template <bool MERGE, bool TLDS>
+template <int LPP, bool MERGE, bool TLDS>
 __global__ __launch_bounds__(256) void k_intensity_step(DevModel m, DevParams p, Shape sh,
                                                         const uint32_t* __restrict__ off,
                                                         const uint32_t* __restrict__ ent,
@@ -285,13 +301,13 @@ __global__ __launch_bounds__(256) void k_intensity_step(DevModel m, DevParams p,
     const float4* cr = stage_segments<TLDS>(m, crl);
     uint32_t* list = lists + (threadIdx.x / LPP) * STEP_LIST;
     const long long P = sh.P;
-    Lane L = lane_setup(m, s, P, off, gain, true);
+    Lane L = lane_setup<LPP>(m, s, P, off, gain, true);
     if (MERGE && L.member) merge_lane(s, P, p, L.pix, L.sub, L.q);
     float sz, shh[KM], shp[KM];
-    accumulate(m, cr, L.q, L.live ? s.b[L.pix] : 1.f, L.live ? L.G : 1.f, ent, L.e0, L.e1, L.sub, list, sz, shh, shp);
-    reduce_lanes(sz, shh, shp);
+    accumulate<LPP>(m, cr, L.q, L.live ? s.b[L.pix] : 1.f, L.live ? L.G : 1.f, ent, L.e0, L.e1, L.sub, list, sz, shh, shp);
+    reduce_lanes<LPP>(sz, shh, shp);
     float Sv[KM], Spv[KM];
-    s_eval_points(m, L.q, L.sub, Sv, Spv);
+    s_eval_points<LPP>(m, L.q, L.sub, Sv, Spv);
     if (!L.live || L.sub != 0) return;
 #pragma unroll
     for (int k = 0; k < KM; ++k)
@@ -300,7 +316,7 @@ __global__ __launch_bounds__(256) void k_intensity_step(DevModel m, DevParams p,
 
 // The background step writes the new b to bdst (the state's own b, or a
 // second buffer the background filter reads); dead pixels keep their b.
-template <bool TLDS>
+template <int LPP, bool TLDS>
 __global__ __launch_bounds__(256) void k_bg_step(DevModel m, DevParams p, Shape sh,
                                                  const uint32_t* __restrict__ off,
                                                  const uint32_t* __restrict__ ent,
@@ -311,12 +327,12 @@ __global__ __launch_bounds__(256) void k_bg_step(DevModel m, DevParams p, Shape 
     const float4* cr = stage_segments<TLDS>(m, crl);
     uint32_t* list = lists + (threadIdx.x / LPP) * STEP_LIST;
     const long long P = sh.P;
-    const Lane L = lane_setup(m, s, P, off, gain, false);
+    const Lane L = lane_setup<LPP>(m, s, P, off, gain, false);
     const float braw = L.pix < P ? s.b[L.pix] : 1.f;
     const float bb = L.live ? braw : 1.f;
     float sz, shh[KM], shp[KM];
-    accumulate(m, cr, L.q, bb, L.live ? L.G : 1.f, ent, L.e0, L.e1, L.sub, list, sz, shh, shp);
-    reduce_lanes(sz, shh, shp);
+    accumulate<LPP>(m, cr, L.q, bb, L.live ? L.G : 1.f, ent, L.e0, L.e1, L.sub, list, sz, shh, shp);
+    reduce_lanes<LPP>(sz, shh, shp);
     if (!L.member || L.sub != 0) return;
     if (!L.live) {
         bdst[L.pix] = braw;
@@ -325,7 +341,7 @@ __global__ __launch_bounds__(256) void k_bg_step(DevModel m, DevParams p, Shape 
     bdst[L.pix] = background_next(m, p, bb, sz);
 }
 
-template <bool TLDS>
+template <int LPP, bool TLDS>
 __global__ __launch_bounds__(256) void k_gradients(DevModel m, Shape sh, const uint32_t* __restrict__ off,
                                                    const uint32_t* __restrict__ ent,
                                                    const float* __restrict__ gain, DevState s,
@@ -337,12 +353,12 @@ __global__ __launch_bounds__(256) void k_gradients(DevModel m, Shape sh, const u
     const float4* cr = stage_segments<TLDS>(m, crl);
     uint32_t* list = lists + (threadIdx.x / LPP) * STEP_LIST;
     const long long P = sh.P;
-    const Lane L = lane_setup(m, s, P, off, gain, false);
+    const Lane L = lane_setup<LPP>(m, s, P, off, gain, false);
     float sz, shh[KM], shp[KM];
-    accumulate(m, cr, L.q, L.live ? s.b[L.pix] : 1.f, L.live ? L.G : 1.f, ent, L.e0, L.e1, L.sub, list, sz, shh, shp);
-    reduce_lanes(sz, shh, shp);
+    accumulate<LPP>(m, cr, L.q, L.live ? s.b[L.pix] : 1.f, L.live ? L.G : 1.f, ent, L.e0, L.e1, L.sub, list, sz, shh, shp);
+    reduce_lanes<LPP>(sz, shh, shp);
     float Sv[KM], Spv[KM];
-    s_eval_points(m, L.q, L.sub, Sv, Spv);
+    s_eval_points<LPP>(m, L.q, L.sub, Sv, Spv);
     if (!L.member || L.sub != 0) return;
     const float G = L.G;
 #pragma unroll
@@ -434,49 +450,80 @@ hipError_t launch_class_lists(const uint8_t* cls, long long P, int n, uint32_t* 
 
 static inline bool segments_fit(const DevModel& m) { return m.L + 1 <= STEP_CR_LDS; }
 
+// The kernels for lanes-per-pixel p.lpp (4 or 8) and the segment staging.
+template <int LPP>
+static hipError_t depth_step_lpp(const DevModel& m, const DevParams& p, const Shape& sh, const uint32_t* off,
+                                 const uint32_t* ent, const float* gain, DevState s, hipStream_t st)
+{
+    const dim3 g(blocks_for(sh.P * LPP, 256)), b(256);
+    if (segments_fit(m)) hipLaunchKernelGGL((k_depth_step<LPP, true>), g, b, 0, st, m, p, sh, off, ent, gain, s);
+    else hipLaunchKernelGGL((k_depth_step<LPP, false>), g, b, 0, st, m, p, sh, off, ent, gain, s);
+    return hipGetLastError();
+}
+
+template <int LPP>
+static hipError_t intensity_step_lpp(const DevModel& m, const DevParams& p, const Shape& sh, const uint32_t* off,
+                                     const uint32_t* ent, const float* gain, DevState s, bool merge, hipStream_t st)
+{
+    const dim3 g(blocks_for(sh.P * LPP, 256)), b(256);
+    const bool tl = segments_fit(m);
+    if (merge && tl) hipLaunchKernelGGL((k_intensity_step<LPP, true, true>), g, b, 0, st, m, p, sh, off, ent, gain, s);
+    else if (merge) hipLaunchKernelGGL((k_intensity_step<LPP, true, false>), g, b, 0, st, m, p, sh, off, ent, gain, s);
+    else if (tl) hipLaunchKernelGGL((k_intensity_step<LPP, false, true>), g, b, 0, st, m, p, sh, off, ent, gain, s);
+    else hipLaunchKernelGGL((k_intensity_step<LPP, false, false>), g, b, 0, st, m, p, sh, off, ent, gain, s);
+    return hipGetLastError();
+}
+
+template <int LPP>
+static hipError_t bg_step_lpp(const DevModel& m, const DevParams& p, const Shape& sh, const uint32_t* off,
+                              const uint32_t* ent, const float* gain, DevState s, float* dst, hipStream_t st)
+{
+    const dim3 g(blocks_for(sh.P * LPP, 256)), b(256);
+    if (segments_fit(m)) hipLaunchKernelGGL((k_bg_step<LPP, true>), g, b, 0, st, m, p, sh, off, ent, gain, s, dst);
+    else hipLaunchKernelGGL((k_bg_step<LPP, false>), g, b, 0, st, m, p, sh, off, ent, gain, s, dst);
+    return hipGetLastError();
+}
+
 hipError_t launch_depth_step(const DevModel& m, const DevParams& p, const Shape& sh, const uint32_t* off,
                              const uint32_t* ent, const float* gain, DevState s, hipStream_t st)
 {
     if (sh.P == 0) return hipSuccess;
-    const dim3 g(blocks_for(sh.P * LPP, 256)), b(256);
-    if (segments_fit(m)) hipLaunchKernelGGL(k_depth_step<true>, g, b, 0, st, m, p, sh, off, ent, gain, s);
-    else hipLaunchKernelGGL(k_depth_step<false>, g, b, 0, st, m, p, sh, off, ent, gain, s);
-    return hipGetLastError();
+    return p.lpp == 8 ? depth_step_lpp<8>(m, p, sh, off, ent, gain, s, st)
+                      : depth_step_lpp<4>(m, p, sh, off, ent, gain, s, st);
 }
 
 hipError_t launch_intensity_step(const DevModel& m, const DevParams& p, const Shape& sh, const uint32_t* off,
                                  const uint32_t* ent, const float* gain, DevState s, bool merge, hipStream_t st)
 {
     if (sh.P == 0) return hipSuccess;
-    const dim3 g(blocks_for(sh.P * LPP, 256)), b(256);
-    const bool tl = segments_fit(m);
-    if (merge && tl) hipLaunchKernelGGL((k_intensity_step<true, true>), g, b, 0, st, m, p, sh, off, ent, gain, s);
-    else if (merge) hipLaunchKernelGGL((k_intensity_step<true, false>), g, b, 0, st, m, p, sh, off, ent, gain, s);
-    else if (tl) hipLaunchKernelGGL((k_intensity_step<false, true>), g, b, 0, st, m, p, sh, off, ent, gain, s);
-    else hipLaunchKernelGGL((k_intensity_step<false, false>), g, b, 0, st, m, p, sh, off, ent, gain, s);
-    return hipGetLastError();
+    return p.lpp == 8 ? intensity_step_lpp<8>(m, p, sh, off, ent, gain, s, merge, st)
+                      : intensity_step_lpp<4>(m, p, sh, off, ent, gain, s, merge, st);
 }
 
 hipError_t launch_bg_step(const DevModel& m, const DevParams& p, const Shape& sh, const uint32_t* off,
                           const uint32_t* ent, const float* gain, DevState s, float* bdst, hipStream_t st)
 {
     if (sh.P == 0) return hipSuccess;
-    const dim3 g(blocks_for(sh.P * LPP, 256)), b(256);
     float* dst = bdst ? bdst : s.b;
-    if (segments_fit(m)) hipLaunchKernelGGL(k_bg_step<true>, g, b, 0, st, m, p, sh, off, ent, gain, s, dst);
-    else hipLaunchKernelGGL(k_bg_step<false>, g, b, 0, st, m, p, sh, off, ent, gain, s, dst);
-    return hipGetLastError();
+    return p.lpp == 8 ? bg_step_lpp<8>(m, p, sh, off, ent, gain, s, dst, st)
+                      : bg_step_lpp<4>(m, p, sh, off, ent, gain, s, dst, st);
 }
 
 hipError_t launch_gradients(const DevModel& m, const DevParams& p, const Shape& sh, const uint32_t* off,
                             const uint32_t* ent, const float* gain, DevState s, float* gt, float* gr, float* gb,
                             hipStream_t st)
 {
-    (void)p;
     if (sh.P == 0) return hipSuccess;
-    const dim3 g(blocks_for(sh.P * LPP, 256)), b(256);
-    if (segments_fit(m)) hipLaunchKernelGGL(k_gradients<true>, g, b, 0, st, m, sh, off, ent, gain, s, gt, gr, gb);
-    else hipLaunchKernelGGL(k_gradients<false>, g, b, 0, st, m, sh, off, ent, gain, s, gt, gr, gb);
+    const bool tl = segments_fit(m);
+    if (p.lpp == 8) {
+        const dim3 g(blocks_for(sh.P * 8, 256)), b(256);
+        if (tl) hipLaunchKernelGGL((k_gradients<8, true>), g, b, 0, st, m, sh, off, ent, gain, s, gt, gr, gb);
+        else hipLaunchKernelGGL((k_gradients<8, false>), g, b, 0, st, m, sh, off, ent, gain, s, gt, gr, gb);
+    } else {
+        const dim3 g(blocks_for(sh.P * 4, 256)), b(256);
+        if (tl) hipLaunchKernelGGL((k_gradients<4, true>), g, b, 0, st, m, sh, off, ent, gain, s, gt, gr, gb);
+        else hipLaunchKernelGGL((k_gradients<4, false>), g, b, 0, st, m, sh, off, ent, gain, s, gt, gr, gb);
+    }
     return hipGetLastError();
 }
 

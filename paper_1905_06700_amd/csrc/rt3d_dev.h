@@ -56,6 +56,7 @@ __device__ __forceinline__ bool in_class(const DevModel& m, long long pix)
 struct DevParams {
     int    k_max, k_init, r_init, n_min, m_min, apss_R;
     int    apss_Rs;   // halo the orthographic APSS tile stages (rings beyond it are farther than h)
+    int    lpp;       // lanes per pixel of the gradient steps: 4 or 8
     int    ilp_box;   // intensity low-pass divisor: 0 = 1 + neighbours found, 1 = 1 + surrounding pixels
     double p_xy, dz, h_apss, h_int;
     double beta_t, dmax, beta_r, beta_b, r_min, d_merge, b_min, kappa;

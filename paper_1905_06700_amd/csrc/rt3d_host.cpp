@@ -61,9 +61,11 @@ struct rt3d_ctx {
     bool last_compacted = false;
     // the batch layout whose final state the workspace holds (warm starts)
     std::vector<long long> state_layout;
-    // rt3d_autotune's choices: (frames, rows, cols, fused)
-    std::vector<std::array<long long, 4>> tuned;
-    int force_fused = -2;              // set by rt3d_autotune while it times one way
+    // rt3d_autotune's choices: (frames, rows, cols, fused, lanes per pixel)
+    std::vector<std::array<long long, 5>> tuned;
+    int force_fused = -2;              // set by rt3d_autotune while it times one mapping
+    int force_lanes = 0;
+    int cur_lpp = 4;                   // lanes per pixel of the gradient steps for the call being enqueued
     // learned denoiser weights (always allocated; zero until set)
     CnnWeights cnn;
     bool cnn_set = false;
@@ -451,6 +453,7 @@ DevParams dev_params(const rt3d_ctx* c, int k = 0)
     d.m_min = p.m_min;
     d.apss_R = c->apss_R;
     d.apss_Rs = apss_staged_halo(p.h_apss, p.p_xy, c->apss_R);
+    d.lpp = c->cur_lpp;
     d.ilp_box = p.ilp_box;
     d.p_xy = p.p_xy;
     d.dz = p.dz;
@@ -484,6 +487,10 @@ rt3d_status check_params(const rt3d_params* p, uint32_t bins, std::string& why)
     if (p->r_init < 0 || p->r_init > 8) { why = "r_init outside 0..8"; return RT3D_E_INVALID; }
     if (p->fused_loop < -1 || p->fused_loop > 1) { why = "fused_loop must be -1, 0 or 1"; return RT3D_E_INVALID; }
     if (p->ilp_box != 0 && p->ilp_box != 1) { why = "ilp_box must be 0 or 1"; return RT3D_E_INVALID; }
+    if (p->lanes_per_pixel != 0 && p->lanes_per_pixel != 4 && p->lanes_per_pixel != 8) {
+        why = "lanes_per_pixel must be 0, 4 or 8";
+        return RT3D_E_INVALID;
+    }
     if (p->sr < 1 || p->sr > SR_MAX) { why = "sr outside 1..4"; return RT3D_E_INVALID; }
     if (p->sr > 1 && p->denoiser == RT3D_DENOISE_CNN) {
         why = "super-resolution with the learned denoiser"; return RT3D_E_UNSUPPORTED;
@@ -578,6 +585,23 @@ bool use_fused(const rt3d_ctx* c, const Shape& sh)
     for (const auto& t : c->tuned)
         if (t[0] == sh.F && t[1] == sh.rows && t[2] == sh.cols) return t[3] == 1;
     return sh.F >= 64;
+}
+
+// Lanes per pixel of the gradient steps for a batch of P pixels (sh: its
+// shape when every frame has one size): forced by the autotuner while it
+// times, else params.lanes_per_pixel, else its choice for the batch shape,
+// else eight lanes below LANES8_PIXELS pixels (four lanes leave most of the
+// chip idle there) and four above.
+constexpr long long LANES8_PIXELS = 131072;
+
+int lanes_for(const rt3d_ctx* c, long long P, const Shape* sh)
+{
+    if (c->force_lanes) return c->force_lanes;
+    if (c->p.lanes_per_pixel) return c->p.lanes_per_pixel;
+    if (sh)
+        for (const auto& t : c->tuned)
+            if (t[0] == sh->F && t[1] == sh->rows && t[2] == sh->cols) return (int)t[4];
+    return P < LANES8_PIXELS ? 8 : 4;
 }
 
 // IRF classes a call launches its IRF-dependent kernels for: every class of
@@ -1023,6 +1047,7 @@ rt3d_status rt3d_reconstruct(rt3d_ctx* c, const rt3d_input* in, rt3d_output* out
         return fail(c, RT3D_E_UNSUPPORTED, "unknown input kind");
     }
     c->last_P = sh.P;
+    c->cur_lpp = lanes_for(c, sh.P, groups.size() == 1 ? &groups[0].sh : nullptr);
     RT3D_HIP(c, launch_check_gain(in->gain, sh.P, w.err, st));
     const DevModel m = dev_model(c);
     const DevParams p = dev_params(c);
@@ -1122,53 +1147,96 @@ rt3d_status rt3d_graph_create(rt3d_ctx* c, const rt3d_input* in, rt3d_output* ou
     return RT3D_OK;
 }
 
+// The batch of an input: its pixels, and whether every frame has one size
+// (then sh is that shape).  false for a malformed frame list.
+static bool input_batch(const rt3d_input* in, Shape& sh, bool& one_size)
+{
+    uint32_t F = in->frames, R = in->rows, Q = in->cols;
+    one_size = true;
+    if (in->frame_rows || in->frame_cols) {
+        if (!in->frame_rows || !in->frame_cols || F == 0) return false;
+        R = in->frame_rows[0];
+        Q = in->frame_cols[0];
+        long long P = 0;
+        for (uint32_t f = 0; f < F; ++f) {
+            if (in->frame_rows[f] != R || in->frame_cols[f] != Q) one_size = false;
+            P += (long long)in->frame_rows[f] * in->frame_cols[f];
+        }
+        if (!one_size) {
+            sh = shape_of(1, 1, (uint32_t)std::min<long long>(P, 0x7fffffff));
+            return true;
+        }
+    }
+    if (!shape_ok(F, R, Q)) return false;
+    sh = shape_of(F, R, Q);
+    return true;
+}
+
 rt3d_status rt3d_autotune(rt3d_ctx* c, const rt3d_input* in, rt3d_output* out, void* hip_stream,
                           int32_t* fused)
 {
     if (!c) return RT3D_E_INVALID;
     if (fused) *fused = 0;
     if (!in || in->struct_size != sizeof(rt3d_input)) return fail(c, RT3D_E_INVALID, "input NULL or struct_size mismatch");
-    uint32_t F = in->frames, R = in->rows, Q = in->cols;
-    if (in->frame_rows || in->frame_cols) {
-        if (!in->frame_rows || !in->frame_cols || F == 0)
-            return fail(c, RT3D_E_INVALID, "frame_rows and frame_cols go together, with frames >= 1");
-        R = in->frame_rows[0];
-        Q = in->frame_cols[0];
-        for (uint32_t f = 1; f < F; ++f)
-            if (in->frame_rows[f] != R || in->frame_cols[f] != Q) return RT3D_OK;   // several sizes: per step
-    }
-    if (c->p.denoiser != RT3D_DENOISE_APSS || (long long)R * Q > LOOP_MAX_PIX) return RT3D_OK;
+    Shape sh;
+    bool one_size = true;
+    if (!input_batch(in, sh, one_size)) return fail(c, RT3D_E_INVALID, "bad frame sizes");
+    if (!one_size) return RT3D_OK;                                   // several sizes: the defaults
+    // the mappings: (fused, lanes per pixel)
+    std::vector<std::array<int, 2>> ways = {{0, 4}, {0, 8}};
+    if (c->p.denoiser == RT3D_DENOISE_APSS && !(c->p.persp > 0) && c->p.sr == 1 && !in->irf_class &&
+        (long long)sh.rows * sh.cols <= LOOP_MAX_PIX)
+        ways.push_back({1, 4});
     rt3d_input cold = *in;
     cold.flags &= ~RT3D_FLAG_WARM_START;
     hipStream_t st = (hipStream_t)hip_stream;
     hipEvent_t ev[2] = {nullptr, nullptr};
     hipError_t e = hipEventCreate(&ev[0]);
     if (e == hipSuccess) e = hipEventCreate(&ev[1]);
-    float ms[2] = {0.f, 0.f};
+    std::vector<float> ms(ways.size(), 0.f);
     rt3d_status s = RT3D_OK;
-    for (int way = 0; way < 2 && e == hipSuccess && s == RT3D_OK; ++way) {
-        c->force_fused = way;
+    for (size_t w = 0; w < ways.size() && e == hipSuccess && s == RT3D_OK; ++w) {
+        c->force_fused = ways[w][0];
+        c->force_lanes = ways[w][1];
         s = rt3d_reconstruct(c, &cold, out, st);                   // untimed
         if (s == RT3D_OK) e = hipEventRecord(ev[0], st);
         for (int k = 0; k < 3 && s == RT3D_OK && e == hipSuccess; ++k) s = rt3d_reconstruct(c, &cold, out, st);
         if (s == RT3D_OK && e == hipSuccess) e = hipEventRecord(ev[1], st);
         if (s == RT3D_OK && e == hipSuccess) e = hipEventSynchronize(ev[1]);
-        if (s == RT3D_OK && e == hipSuccess) e = hipEventElapsedTime(&ms[way], ev[0], ev[1]);
+        if (s == RT3D_OK && e == hipSuccess) e = hipEventElapsedTime(&ms[w], ev[0], ev[1]);
     }
     c->force_fused = -2;
+    c->force_lanes = 0;
     for (hipEvent_t x : ev)
         if (x) (void)hipEventDestroy(x);
     if (s != RT3D_OK) return s;
     if (e != hipSuccess) return hip_fail(c, e, "autotune timing");
-    const int choice = ms[1] < ms[0] ? 1 : 0;
+    size_t best = 0;
+    for (size_t w = 1; w < ways.size(); ++w)
+        if (ms[w] < ms[best]) best = w;
     bool found = false;
     for (auto& t : c->tuned)
-        if (t[0] == F && t[1] == R && t[2] == Q) {
-            t[3] = choice;
+        if (t[0] == sh.F && t[1] == sh.rows && t[2] == sh.cols) {
+            t[3] = ways[best][0];
+            t[4] = ways[best][1];
             found = true;
         }
-    if (!found) c->tuned.push_back({(long long)F, (long long)R, (long long)Q, (long long)choice});
-    if (fused) *fused = choice;
+    if (!found) c->tuned.push_back({(long long)sh.F, (long long)sh.rows, (long long)sh.cols, ways[best][0], ways[best][1]});
+    if (fused) *fused = ways[best][0];
+    return RT3D_OK;
+}
+
+rt3d_status rt3d_mapping(rt3d_ctx* c, const rt3d_input* in, int32_t* fused, int32_t* lanes)
+{
+    if (!c) return RT3D_E_INVALID;
+    if (!in || in->struct_size != sizeof(rt3d_input)) return fail(c, RT3D_E_INVALID, "input NULL or struct_size mismatch");
+    Shape sh;
+    bool one_size = true;
+    if (!input_batch(in, sh, one_size)) return fail(c, RT3D_E_INVALID, "bad frame sizes");
+    std::vector<Group> groups(1, Group{0, sh});
+    const bool f = one_size && !in->irf_class && c->p.sr == 1 && loop_eligible(c, groups, sh) && use_fused(c, sh);
+    if (fused) *fused = f ? 1 : 0;
+    if (lanes) *lanes = lanes_for(c, sh.P, one_size ? &sh : nullptr);
     return RT3D_OK;
 }
 
@@ -1320,6 +1388,7 @@ rt3d_status rt3d_debug_step(rt3d_ctx* c, int32_t step, const uint32_t* off, cons
                            step == RT3D_STEP_BKG || step == RT3D_STEP_ITERATION;
     if (needs_csr && (!off || !ent)) return fail(c, RT3D_E_INVALID, "off/ent is NULL");
     if (!shape_ok(out->frames, out->rows, out->cols)) return fail(c, RT3D_E_INVALID, "bad state shape");
+    c->cur_lpp = lanes_for(c, (long long)out->frames * out->rows * out->cols, nullptr);
     const Shape sh = shape_of(out->frames, out->rows, out->cols);
     hipStream_t st = (hipStream_t)hip_stream;
     const DevModel m = dev_model(c);
@@ -1397,6 +1466,7 @@ rt3d_status rt3d_debug_gradients(rt3d_ctx* c, const uint32_t* off, const uint32_
                                  const rt3d_state* s, float* gt, float* gr, float* gb, void* hip_stream)
 {
     if (!c) return RT3D_E_INVALID;
+    if (s) c->cur_lpp = lanes_for(c, (long long)s->frames * s->rows * s->cols, nullptr);
     if (!state_ok(s) || !off || !ent || !gt || !gr || !gb) return fail(c, RT3D_E_INVALID, "NULL argument");
     if (!shape_ok(s->frames, s->rows, s->cols)) return fail(c, RT3D_E_INVALID, "bad state shape");
     const Shape sh = shape_of(s->frames, s->rows, s->cols);

@@ -27,7 +27,7 @@ STEP_INIT, STEP_DEPTH, STEP_APSS, STEP_MERGE, STEP_INTENSITY, STEP_IFILTER, STEP
 EXPORTS = ["rt3d_params_default", "rt3d_create", "rt3d_destroy", "rt3d_last_error", "rt3d_sigma2",
            "rt3d_workspace_bytes", "rt3d_set_workspace", "rt3d_reconstruct", "rt3d_query",
            "rt3d_profile", "rt3d_profile_read", "rt3d_graph_create", "rt3d_graph_launch", "rt3d_graph_destroy",
-           "rt3d_autotune", "rt3d_add_irf", "rt3d_debug_irf_class",
+           "rt3d_autotune", "rt3d_mapping", "rt3d_add_irf", "rt3d_debug_irf_class",
            "rt3d_debug_compact", "rt3d_compact_noalloc", "rt3d_debug_compact_events", "rt3d_debug_step", "rt3d_debug_gradients",
            "rt3d_cnn_set_weights", "rt3d_cnn_get_weights", "rt3d_cnn_last_gradient",
            "rt3d_cnn_forward", "rt3d_cnn_train_step", "rt3d_denoiser_save", "rt3d_denoiser_load"]
@@ -58,7 +58,8 @@ class Params(C.Structure):
                 ("b_min", C.c_double), ("sbr_guess", C.c_double), ("r_init", C.c_int32),
                 ("n_min", C.c_int32), ("kappa", C.c_double), ("w_nms", C.c_int32),
                 ("m_min", C.c_int32), ("denoiser", C.c_int32), ("fused_loop", C.c_int32),
-                ("sr", C.c_int32), ("persp", C.c_double), ("ilp_box", C.c_int32)]
+                ("sr", C.c_int32), ("persp", C.c_double), ("ilp_box", C.c_int32),
+                ("lanes_per_pixel", C.c_int32)]
 
 
 class Input(C.Structure):
@@ -123,6 +124,8 @@ def lib():
         L.rt3d_profile_read.restype = st
         L.rt3d_autotune.argtypes = [vp, C.POINTER(Input), C.POINTER(Output), vp, C.POINTER(C.c_int32)]
         L.rt3d_autotune.restype = st
+        L.rt3d_mapping.argtypes = [vp, C.POINTER(Input), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.rt3d_mapping.restype = st
         L.rt3d_graph_create.argtypes = [vp, C.POINTER(Input), C.POINTER(Output), C.POINTER(vp)]
         L.rt3d_graph_create.restype = st
         L.rt3d_graph_launch.argtypes = [vp, vp]
@@ -385,6 +388,13 @@ class Context:
         fused = C.c_int32(0)
         self._check(lib().rt3d_autotune(self._h, C.byref(inp), C.byref(o), _stream(), C.byref(fused)))
         return int(fused.value)
+
+    def mapping(self, out: Result, frames: int, rows: int, cols: int, hist=None, frame_shapes=None):
+        """(fused, lanes per pixel) that reconstruct_into would use for this input."""
+        inp, _ = self._io(out, frames, rows, cols, hist, frame_shapes=frame_shapes)
+        fused, lanes = C.c_int32(0), C.c_int32(0)
+        self._check(lib().rt3d_mapping(self._h, C.byref(inp), C.byref(fused), C.byref(lanes)))
+        return int(fused.value), int(lanes.value)
 
     def graph(self, out: Result, frames: int, rows: int, cols: int, hist=None, off=None, ent=None, gain=None,
               events=None, frame_shapes=None, irf_class=None) -> "Graph":

@@ -64,7 +64,8 @@ def pair(scene: synth.Scene, **kw):
     """(oracle.Oracle, rt3d.Context) for one scene with identical parameters."""
     p = params_for(scene, **kw)
     model = oracle.Model(scene.irf.probs, scene.T)
-    O = oracle.Oracle(model, oracle.Params(**{k: v for k, v in p.items() if k != "denoiser"}))
+    gpu_only = ("denoiser", "fused_loop", "lanes_per_pixel")      # how the GPU maps the loop
+    O = oracle.Oracle(model, oracle.Params(**{k: v for k, v in p.items() if k not in gpu_only}))
     ctx = rt3d.Context(scene.irf.probs, scene.T, **p)
     return O, ctx
 

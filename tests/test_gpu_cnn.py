@@ -270,3 +270,46 @@ def test_trained_network_beats_no_denoiser():
     print(f"[gpu-cnn] held-out (RMSE over found surfaces, found fraction): {r}; training loss {hist}", flush=True)
     assert r["cnn"][0] < 0.95 * r["none"][0]
     assert r["cnn"][1] >= r["none"][1] - 0.02
+
+
+@pytest.mark.parametrize("regime", ["config4", "bright"])
+def test_trained_checkpoint_within_ten_percent_of_apss(regime):
+    """The committed checkpoints of the training recipe (trained on the GPU by
+    the library's kernels on scenes of seeds 0..1999) against plain APSS on
+    held-out scenes (seeds 10000..10003) of their regime: depth RMSE (true
+    surfaces matched greedily within 3 sigma_h, a miss counted 3 sigma_h) within
+    10% of APSS's, at the same fraction of surfaces found.  config4: 2 signal
+    photons/px at SBR 0.05 (about a third of the surfaces found); bright: 6
+    photons/px at SBR 0.2 (about 90% found)."""
+    import os
+    from paper_1905_06700_amd import train as tr
+    sig_ph, sbr, name = (2.0, 0.05, "denoiser_c4") if regime == "config4" else (6.0, 0.2, "denoiser_bright")
+    path = os.path.join(os.path.dirname(tr.__file__), "weights", name + ".rt3dcnn")
+    R = C_ = 256
+    T_ = 1024
+    test = [synth.layers_scene(10000 + s, rows=R, cols=C_, T=T_, signal=sig_ph, sbr=sbr) for s in range(4)]
+    p = params(test[0])
+    apss = rt3d.Context(test[0].irf.probs, T_, **p)
+    net = rt3d.Context(test[0].irf.probs, T_, denoiser=rt3d.DENOISE_CNN, **p)
+    net.denoiser_load(path)
+    sig = float(np.sqrt(net.sigma2))
+    Z = torch.cat([to_dev_hist(s.Z)[None] for s in test])
+    r = {}
+    for nm, ctx in (("apss", apss), ("cnn", net)):
+        ctx.workspace(4, R, C_, 4 * R * C_ * 200)
+        res = ctx.make_output(4 * R * C_)
+        ctx.reconstruct_into(res, 4, R, C_, hist=Z)
+        assert ctx.query().device_error == 0
+        pt = u32(res.pt_off).astype(np.int64)
+        dep = res.depth.cpu().numpy()
+        errs, nts, nfs = [], [], []
+        for f, sc in enumerate(test):
+            sl = pt[f * R * C_:(f + 1) * R * C_ + 1] - pt[f * R * C_]
+            e, nt, nf = tr.match_surfaces(sc.depth.reshape(3, -1), sl, dep[pt[f * R * C_]:], 3 * sig)
+            errs.append(e)
+            nts.append(nt)
+            nfs.append(nf)
+        r[nm] = tr.depth_scores(errs, nts, nfs, 4 * R * C_, 3 * sig)
+    print(f"[gpu-cnn] {regime} held-out: {r}", flush=True)
+    assert r["cnn"]["depth_rmse_bins"] <= 1.10 * r["apss"]["depth_rmse_bins"]
+    assert r["cnn"]["found"] >= r["apss"]["found"] - 0.01

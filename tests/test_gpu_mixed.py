@@ -39,7 +39,9 @@ def context():
     video, scenes = batch()
     m = scenes[0].meta
     p = dict(dz=m["dz"], p_xy=1.0, r_min=0.6, r_init=1, k_init=3)
-    ctx = rt3d.Context(scenes[0].irf.probs, T, **p)
+    # bit equality across batches needs a fixed lanes-per-pixel mapping (the
+    # default follows the batch's size)
+    ctx = rt3d.Context(scenes[0].irf.probs, T, lanes_per_pixel=4, **p)
     assert ctx.add_irf(video[0].irf.probs) == 1
     return ctx, p
 

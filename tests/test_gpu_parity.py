@@ -154,10 +154,11 @@ def test_init_matches_oracle(name):
 
 @pytest.mark.parametrize("name", ["c1", "c2", "ragged"])
 @pytest.mark.parametrize("iters", [0, 3])
-def test_gradients_match_oracle(name, iters):
+@pytest.mark.parametrize("lanes", [4, 8])
+def test_gradients_match_oracle(name, iters, lanes):
     from gpu_util import to_dev_u32
     sc = scene(name)
-    O, ctx = pair(sc)
+    O, ctx = pair(sc, lanes_per_pixel=lanes)
     off_o, ent_o = csr(sc)
     s = O.init(off_o, ent_o, oracle.State(1, sc.rows, sc.cols, 4))
     for _ in range(iters):
@@ -185,10 +186,11 @@ def _state_after(sc, O, iters):
 
 
 @pytest.mark.parametrize("name", ["c1", "c2", "ragged"])
-def test_single_steps_match_oracle(name):
+@pytest.mark.parametrize("lanes", [4, 8])
+def test_single_steps_match_oracle(name, lanes):
     from gpu_util import to_dev_u32
     sc = scene(name)
-    O, ctx = pair(sc)
+    O, ctx = pair(sc, lanes_per_pixel=lanes)
     off_o, ent_o = csr(sc)
     off, ent = to_dev_u32(off_o), to_dev_u32(ent_o)
     s0 = _state_after(sc, O, 2)
@@ -354,28 +356,39 @@ def test_reconstruction_is_deterministic():
 
 
 def test_autotune_choice_is_kept_and_reconstructs_identically():
-    """rt3d_autotune times both loop mappings on a 64-frame batch of 32 x 32
-    frames and keeps one; later calls on that batch shape (fused_loop = -1)
-    give what a context forced to that mapping gives."""
-    scs = [synth.plane_scene(s) for s in range(4)]
-    sc = scs[0]
-    F, R, C = 64, sc.rows, sc.cols
-    Z = torch.stack([to_dev_hist(scs[f % 4].Z) for f in range(F)]).contiguous()
-    ctx = rt3d.Context(sc.irf.probs, sc.T, **params_for(sc))
-    ctx.workspace(F, R, C, F * R * C * 64)
-    out = ctx.make_output(F * R * C)
-    choice = ctx.autotune(out, F, R, C, hist=Z)
-    print(f"[gpu-parity] autotune: {'one launch' if choice else 'per step'} for {F} x {R} x {C}", flush=True)
-    assert choice in (0, 1)
-    ctx.reconstruct_into(out, F, R, C, hist=Z)
-    forced = rt3d.Context(sc.irf.probs, sc.T, **params_for(sc), fused_loop=choice)
-    ref = forced.reconstruct(Z)
-    assert ctx.query().device_error == 0 and forced.query().device_error == 0
-    for name in ("pt_off", "background"):
-        assert torch.equal(getattr(out, name), getattr(ref, name)), name
-    n = int(ref.pt_off[-1].item())
-    for name in ("depth", "intensity"):
-        assert torch.equal(getattr(out, name)[:n], getattr(ref, name)[:n]), name
+    """rt3d_autotune times the loop mappings (per step with 4 or 8 lanes per
+    pixel, all iterations in one launch) on a 64-frame batch of 32 x 32 frames
+    and on one head-shaped frame, and keeps one per batch shape; later calls on
+    that shape give what a context forced to that mapping gives."""
+    for kind in ("small", "head"):
+        if kind == "small":
+            scs = [synth.plane_scene(s) for s in range(4)]
+            F = 64
+        else:
+            scs = [scene("c2")]
+            F = 1
+        sc = scs[0]
+        R, C = sc.rows, sc.cols
+        Z = torch.stack([to_dev_hist(scs[f % len(scs)].Z) for f in range(F)]).contiguous()
+        ctx = rt3d.Context(sc.irf.probs, sc.T, **params_for(sc))
+        ctx.workspace(F, R, C, F * R * C * 128)
+        out = ctx.make_output(F * R * C)
+        choice = ctx.autotune(out, F, R, C, hist=Z)
+        fused, lanes = ctx.mapping(out, F, R, C, hist=Z)
+        print(f"[gpu-parity] autotune {F} x {R} x {C}: {'one launch' if fused else 'per step'}, "
+              f"{lanes} lanes per pixel", flush=True)
+        assert choice == fused and lanes in (4, 8)
+        ctx.reconstruct_into(out, F, R, C, hist=Z)
+        forced = rt3d.Context(sc.irf.probs, sc.T, **params_for(sc), fused_loop=fused, lanes_per_pixel=lanes)
+        forced.workspace(F, R, C, F * R * C * 128)
+        ref = forced.make_output(F * R * C)
+        forced.reconstruct_into(ref, F, R, C, hist=Z)
+        assert ctx.query().device_error == 0 and forced.query().device_error == 0
+        for name in ("pt_off", "background"):
+            assert torch.equal(getattr(out, name), getattr(ref, name)), name
+        n = int(ref.pt_off[-1].item())
+        for name in ("depth", "intensity"):
+            assert torch.equal(getattr(out, name)[:n], getattr(ref, name)[:n]), name
 
 
 def test_batched_frames_equal_single_frames():
