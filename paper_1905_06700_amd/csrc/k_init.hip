@@ -65,8 +65,23 @@ struct Peaks {
         return sup;
     }
 
+    // any accepted peak's suppression reaching tau in [lo, hi] (wave-uniform)
+    __device__ __forceinline__ bool suppresses_any(int lo, int hi, int wnms) const
+    {
+        bool any = false;
+#pragma unroll
+        for (int j = 0; j < KM; ++j)
+            if (j < n && t[j] - wnms <= hi && t[j] + wnms >= lo) any = true;
+        return any;
+    }
+
+    // (wave-uniform values: kept in scalar registers)
     __device__ __forceinline__ void push(int tt, int aa, int cc, int ww)
     {
+        tt = __builtin_amdgcn_readfirstlane(tt);
+        aa = __builtin_amdgcn_readfirstlane(aa);
+        cc = __builtin_amdgcn_readfirstlane(cc);
+        ww = __builtin_amdgcn_readfirstlane(ww);
 #pragma unroll
         for (int j = 0; j < KM; ++j)
             if (j == n) {
@@ -100,41 +115,111 @@ __device__ __forceinline__ int q_range_max(const int* qst, int L, int lo, int hi
 __device__ __forceinline__ int popc_ballot(bool x) { return __popcll(__ballot(x)); }
 
 constexpr int INIT_WAVES = 4;
-constexpr int INIT_ELDS = 640;    // pooled entries a wavefront scores from LDS (held in registers)
-constexpr int INIT_EPL = INIT_ELDS / 64;   // pooled entries per lane
+constexpr int INIT_ELDS = 560;    // pooled entries a wavefront scores from LDS (held in registers)
+constexpr int INIT_EPL = (INIT_ELDS + 63) / 64;   // pooled entries per lane
 // Pixels whose pool is larger, up to INIT_WIDE_ELDS entries, are listed and
 // scored from LDS by a second kernel that stages their photons in passes over
 // HBM; larger pools take the HBM path.
 constexpr int INIT_WIDE_ELDS = 1536;
 constexpr unsigned INIT_WIDE_GRID = 1024;
 constexpr int INIT_QLDS = 4096;   // IRF weight tables (ints) up to this size are staged in LDS
-constexpr int INIT_QPAD = 128;    // zero weights on either side of the staged IRF weights
+constexpr int INIT_QPAD = 96;     // zero weights on either side of the staged IRF weights (at least 94)
 constexpr int INIT_BWS = 5;       // the LDS path buckets photons by 2^INIT_BWS bins
 constexpr int NO_TAU = 0x7fffffff;
 
 // Width (tau) of the sub-blocks the LDS path bounds, and the number of
 // sub-blocks up to which it keeps their tables (at most two 64-tau blocks per
-// lane).
-constexpr int INIT_SB = 16;
-constexpr int INIT_NB_LDS = 512;
+// lane).  Narrow sub-blocks give tight bounds (the largest weight over 8
+// lags rather than 16 roughly halves the blocks scored on head-shaped
+// scenes) at the price of more bound terms per photon.
+constexpr int INIT_SB = 8;
+constexpr int INIT_SB2 = 2 * INIT_SB;   // the bins of one pair of sub-blocks
+constexpr int INIT_NB_LDS = 1024;
 static_assert(INIT_NB_LDS * INIT_SB <= 128 * 64, "two blocks per lane");
+static_assert((INIT_SB & (INIT_SB - 1)) == 0 && 64 % INIT_SB == 0, "sub-blocks tile a block");
 
-// 8-byte LDS words of one wavefront: the HBM path's per-pixel photon ranges,
-// then either the LDS path's sub-block bounds, bucketed photons and bucket
-// ends, or the HBM path's block bounds.
-inline __host__ __device__ size_t init_wave_words(int T, int r_init, size_t elds = INIT_ELDS)
+// The LDS path adds a photon to the bounds of the sub-blocks in pairs (one
+// 64-bit LDS atomic per two sub-blocks): for a photon at bin t, with
+// t + o = 2 SB h + r (0 <= r < 2 SB, SB = INIT_SB), the pairs cover
+// sub-blocks 2h - 2 np + 2 .. 2h + 1, which hold every sub-block whose tau
+// can see t.  The pair count np = ceil((ceil((L - 1) / SB) + 2) / 2); the
+// bounds carry 2 np - 2 guard entries in front (indices below 0) and reach
+// index 2 floor((T - 1 + o) / (2 SB)) + 1 at the back.
+inline __host__ __device__ int init_np(int L) { return ((((L - 1) + INIT_SB - 1) / INIT_SB) + 3) >> 1; }
+inline __host__ __device__ size_t init_bound_words(int T, int L, int o)
+{
+    return (size_t)init_np(L) + (size_t)(T - 1 + o) / INIT_SB2;
+}
+
+// 8-byte LDS words of one wavefront: either the LDS path's sub-block bounds
+// (with their guards), bucketed photons and bucket ends, or the HBM path's
+// per-pixel photon ranges and block bounds.  (The areas are sized so that
+// seven four-wavefront workgroups of the head-shaped scenes' init, 4613 bins
+// and a 137-bin IRF, fit one compute unit's LDS.)
+inline __host__ __device__ size_t init_wave_words(int T, int L, int o, int r_init, size_t elds = INIT_ELDS)
 {
     const size_t nb = (size_t)(T + 63) / 64, nbs = (size_t)(T + INIT_SB - 1) / INIT_SB;
     const size_t side = 2 * (size_t)r_init + 1;
     const size_t nk = ((size_t)T + (1u << INIT_BWS) - 1) >> INIT_BWS;
-    const size_t staged = nbs <= INIT_NB_LDS ? (nbs + 1) / 2 + elds / 2 + (nk + 2) / 2 : 0;
-    return side * side + (nb > staged ? nb : staged);
+    const size_t staged = nbs <= INIT_NB_LDS ? init_bound_words(T, L, o) + (elds + 1) / 2 + (nk + 1) / 2 : 0;
+    const size_t hbm = side * side + nb;
+    return hbm > staged ? hbm : staged;
 }
 
 // Ints of the staged weights (with their zero padding), and of the sliding
-// maximum table: M[x] = max q[x - INIT_SB + 1 .. x] (q = 0 outside [0, L)).
+// maximum table: Mz[SB + x] = M[x] = max q[x - SB + 1 .. x] (q = 0 outside
+// [0, L)), with SB zeros in front and zeros past x = L + SB - 2 up to the
+// last entry a photon's pairs read.
 inline __host__ __device__ size_t q_staged_ints(int L) { return (size_t)L + 2 * INIT_QPAD; }
-inline __host__ __device__ size_t q_window_ints(int L) { return (size_t)L + INIT_SB - 1; }
+inline __host__ __device__ size_t q_window_ints(int L) { return INIT_SB2 * (size_t)init_np(L) + INIT_SB; }
+
+// Largest sub-block bound of block b.
+__device__ __forceinline__ uint32_t block_bound(const uint32_t* bnd, int nbs, int b)
+{
+    uint32_t mx = 0;
+#pragma unroll
+    for (int c = 0; c < 64 / INIT_SB; ++c) {
+        const int sb = b * (64 / INIT_SB) + c;
+        if (sb < nbs) mx = max(mx, bnd[sb]);
+    }
+    return mx;
+}
+
+// Adds to the sub-block bounds (or, with SUB, takes away) the terms of a
+// photon of count z at bin t, x = t + o: sub-block sb gains z x M[x - SB sb].
+// Pair j of the photon's pairs (counted from the back) holds sub-blocks
+// 2h - 2j and 2h - 2j + 1 (x = 2 SB h + r) and gains z x M[r + 2 SB j] and
+// z x M[r + 2 SB j - SB] in its low and high words; every other sub-block of
+// the pairs gets a zero weight (its lag lies outside M).  bnd2: the bounds as
+// 64-bit words from the first guard entry.  A bound is an exact sum below
+// 2^32, and a photon's term is part of it while it is taken away, so the low
+// word never carries into (or borrows from) the high one.
+template <bool SUB>
+__device__ __forceinline__ void bound_photon(unsigned long long* bnd2, const int* Mz, int np, int x, uint32_t z)
+{
+    const int h = x / INIT_SB2, r = x % INIT_SB2;           // x >= 0
+    const int* Mb = Mz + r;
+    unsigned long long* bp = bnd2 + h + np - 1;
+    auto term = [z](int hiw, int low) {
+        const unsigned long long v = ((unsigned long long)(uint32_t)__umul24(z, (uint32_t)hiw) << 32) |
+                                     (uint32_t)__umul24(z, (uint32_t)low);
+        return SUB ? 0ull - v : v;
+    };
+    // four pairs at a time: their weight reads in flight together
+    int j = 0;
+    for (; j + 4 <= np; j += 4, Mb += 4 * INIT_SB2, bp -= 4) {
+        int w0[4], w1[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            w0[k] = Mb[k * INIT_SB2];
+            w1[k] = Mb[k * INIT_SB2 + INIT_SB];
+        }
+        unsigned long long* b3 = bp - 3;          // (ascending offsets from the lowest word)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) atomicAdd(b3 + (3 - k), term(w0[k], w1[k]));
+    }
+    for (; j < np; ++j, Mb += INIT_SB2, --bp) atomicAdd(bp, term(Mb[0], Mb[INIT_SB]));
+}
 
 // Whole-wavefront maximum / minimum on the VALU: DPP quad permutations, row
 // shifts by 4 and 8, then row broadcasts of lanes 15 and 31; lane 63 ends with
@@ -268,8 +353,8 @@ __device__ __forceinline__ uint32_t score_block(const uint32_t* E, const int* be
 template <bool STAGED>
 __device__ __forceinline__ void lds_search(const DevModel& m, const DevParams& p, int T, int L, int o, int nb,
                                            int nbs, int nk, const uint32_t (&pe)[INIT_EPL], int total, long long ntot,
-                                           const int* qs, const int* M, uint32_t* bnd, uint32_t* E, int* bend,
-                                           Peaks& pk)
+                                           const int* qs, const int* Mz, unsigned long long* bnd2, int np,
+                                           uint32_t* bnd, uint32_t* E, int* bend, Peaks& pk)
 {
     const int lane = threadIdx.x & 63;
     // stage the photons bucketed by 2^INIT_BWS bins; bins >= T become zero
@@ -288,44 +373,31 @@ __device__ __forceinline__ void lds_search(const DevModel& m, const DevParams& p
 #pragma unroll
     for (int u = 0; u < INIT_EPL; ++u) {
         if (STAGED || lane + 64 * u >= total) break;
-        const int t = ent_bin(pe[u]), z = ent_cnt(pe[u]);
-        if (t >= T) continue;
-        const int blo = max(0, t + o - L + 1) / INIT_SB, bhi = min(T - 1, t + o) / INIT_SB;
-        const int* Mx = M + (t + o - INIT_SB * bhi);
-#pragma unroll 2
-        for (int b = bhi; b >= blo; --b, Mx += INIT_SB) atomicAdd(&bnd[b], __umul24((unsigned)z, (unsigned)*Mx));
+        const int t = ent_bin(pe[u]);
+        if (t < T) bound_photon<false>(bnd2, Mz, np, t + o, (uint32_t)ent_cnt(pe[u]));
     }
     wave_sync();
-    // blocks lane and lane + 64: the largest sub-block bound and the first
-    // tau of the first sub-block holding it; the cached exact best
+    // blocks lane and lane + 64: the largest sub-block bound; the cached
+    // exact best
     uint32_t bmx[2], bsc[2];
-    int bsub[2], btau[2];
+    int btau[2];
     bool cached[2], has[2];
 #pragma unroll
     for (int s2 = 0; s2 < 2; ++s2) {
         const int b = lane + 64 * s2;
-        uint32_t mx = 0;
-        int sub = NO_TAU;
-        if (b < nb) {
-#pragma unroll
-            for (int c = 0; c < 64 / INIT_SB; ++c) {
-                const int sb = b * (64 / INIT_SB) + c;
-                if (sb < nbs) {
-                    const uint32_t u = bnd[sb];
-                    if (sub == NO_TAU || u > mx) {
-                        mx = u;
-                        sub = sb * INIT_SB;
-                    }
-                }
-            }
-        }
-        bmx[s2] = mx;
-        bsub[s2] = sub;
+        bmx[s2] = b < nb ? block_bound(bnd, nbs, b) : 0u;
         cached[s2] = b >= nb;     // blocks past the end are never picked
         has[s2] = false;
         bsc[s2] = 0;
         btau[s2] = NO_TAU;
     }
+    // Blocks are picked by one wave maximum of a key: the block's bound
+    // rounded up to 24 significant bits (shift sh; bounds only fall later),
+    // plus one, above 127 - the block's index (smallest index on ties).  Any
+    // unscored block's bound is at most the largest key's rounded bound.
+    const uint32_t ball = wave_max_u32(max(bmx[0], bmx[1]));
+    const int sh = max(0, 32 - (int)__clz(ball) - 24);
+    const uint32_t rmask = (1u << sh) - 1u;
     const double k2 = p.kappa * p.kappa;
     for (int it = 0; it < p.k_init; ++it) {
         // best over the blocks whose exact best is known
@@ -349,26 +421,25 @@ __device__ __forceinline__ void lds_search(const DevModel& m, const DevParams& p
             }
         }
         while (true) {
-            // the unscored block with the largest bound (smallest index on ties)
+            // the unscored block with the largest rounded bound
             uint32_t key = 0;
 #pragma unroll
             for (int s2 = 0; s2 < 2; ++s2)
-                if (!cached[s2] && bmx[s2] + 1 > key) key = bmx[s2] + 1;
+                if (!cached[s2]) {
+                    const uint32_t k = (bmx[s2] >> sh) + ((bmx[s2] & rmask) != 0u) + 1u;
+                    key = max(key, (k << 7) | (uint32_t)(127 - (lane + 64 * s2)));
+                }
             const uint32_t mx = wave_max_u32(key);
             if (mx == 0) break;                                   // every block scored
-            unsigned cand = 0xffffffffu;
-#pragma unroll
-            for (int s2 = 1; s2 >= 0; --s2)
-                if (!cached[s2] && bmx[s2] + 1 == mx) cand = (unsigned)(lane + 64 * s2);
-            const int bb = (int)wave_min_u32(cand);
-            const uint32_t bu = mx - 1;
+            const int bb = 127 - (int)(mx & 127u);
+            const unsigned long long bu = (unsigned long long)((mx >> 7) - 1u) << sh;
+            if (hb && bu < best) break;                           // no unscored tau can reach best
             const int hi = bb >> 6;                               // wave-uniform
-            const int subt = __builtin_amdgcn_readlane(hi ? bsub[1] : bsub[0], bb & 63);
-            if (hb && (bu < best || (bu == best && subt > bestt))) break;
             // exact scores of its 64 tau, and their best (tau rises with the lane)
             const int tau = (bb << 6) + lane;
             const uint32_t sc = score_block(E, bend, nk, bb, qs, L, o);
-            const bool valid = tau < T && !pk.suppressed(tau, m.wnms);
+            const bool valid = tau < T && !(pk.suppresses_any(bb << 6, (bb << 6) + 63, m.wnms) &&
+                                            pk.suppressed(tau, m.wnms));
             const uint32_t sk = valid ? sc + 1 : 0;
             const uint32_t smx = wave_max_u32(sk);
             int st = NO_TAU;
@@ -419,12 +490,7 @@ __device__ __forceinline__ void lds_search(const DevModel& m, const DevParams& p
             const int tb = ent_bin(v), z = ent_cnt(v);
             if (tb >= a && tb <= c) {
                 E[x] = v & 0xffff0000u;
-                if (z > 0) {
-                    const int blo = max(0, tb + o - L + 1) / INIT_SB, bhi = min(T - 1, tb + o) / INIT_SB;
-                    const int* Mx = M + (tb + o - INIT_SB * bhi);
-                    for (int b = bhi; b >= blo; --b, Mx += INIT_SB)
-                        atomicSub(&bnd[b], __umul24((unsigned)z, (unsigned)*Mx));
-                }
+                if (z > 0) bound_photon<true>(bnd2, Mz, np, tb + o, (uint32_t)z);
             }
         }
         wave_sync();
@@ -438,33 +504,17 @@ __device__ __forceinline__ void lds_search(const DevModel& m, const DevParams& p
             const int ta = b << 6, tb = (b << 6) + 63;
             const bool seen = ta <= A1 && tb >= A0;
             if (b < nb && (seen || (ta <= S1 && tb >= S0))) cached[s2] = false;
-            if (b < nb && seen) {
-                uint32_t mx = 0;
-                int sub = NO_TAU;
-#pragma unroll
-                for (int q = 0; q < 64 / INIT_SB; ++q) {
-                    const int sb = b * (64 / INIT_SB) + q;
-                    if (sb < nbs) {
-                        const uint32_t u = bnd[sb];
-                        if (sub == NO_TAU || u > mx) {
-                            mx = u;
-                            sub = sb * INIT_SB;
-                        }
-                    }
-                }
-                bmx[s2] = mx;
-                bsub[s2] = sub;
-            }
+            if (b < nb && seen) bmx[s2] = block_bound(bnd, nbs, b);
         }
     }
 }
 
 // Stages the IRF weights (INIT_QPAD zeros, the L weights, INIT_QPAD zeros)
-// and their sliding maximum over INIT_SB lags in LDS, with the whole
-// workgroup; returns the largest weight (wave-uniform).  Without QL the
-// weights stay in HBM and the result is 0.
+// and their sliding maximum over INIT_SB lags (Mz, zero-padded) in LDS, with
+// the whole workgroup; returns the largest weight (wave-uniform).  Without QL
+// the weights stay in HBM and the result is 0.
 template <bool QL>
-__device__ __forceinline__ int stage_weights(const DevModel& m, int* qs, int* M)
+__device__ __forceinline__ int stage_weights(const DevModel& m, int* qs, int* Mz)
 {
     const int L = m.L, lane = threadIdx.x & 63;
     if (QL) {
@@ -473,11 +523,15 @@ __device__ __forceinline__ int stage_weights(const DevModel& m, int* qs, int* M)
             qs[k] = (lag >= 0 && lag < L) ? m.q[lag] : 0;
         }
         __syncthreads();
-        for (int x = threadIdx.x; x < L + INIT_SB - 1; x += blockDim.x) {
+        const int nz = (int)q_window_ints(L);
+        for (int k = threadIdx.x; k < nz; k += blockDim.x) {
+            const int x = k - INIT_SB;
             int mx = 0;
+            if (x >= 0 && x <= L + INIT_SB - 2) {
 #pragma unroll
-            for (int d = 0; d < INIT_SB; ++d) mx = max(mx, qs[INIT_QPAD + x - d]);
-            M[x] = mx;
+                for (int d = 0; d < INIT_SB; ++d) mx = max(mx, qs[INIT_QPAD + x - d]);
+            }
+            Mz[k] = mx;
         }
     }
     __syncthreads();
@@ -512,7 +566,7 @@ template <bool QL, bool WIDE>
 __device__ __forceinline__ void init_pixel(const DevModel& m, const DevParams& p, const Shape& sh,
                                            const uint32_t* __restrict__ off, const uint32_t* __restrict__ ent,
                                            const float* __restrict__ gain, DevState& s, long long pix,
-                                           unsigned long long* wbase, const int* qs, const int* M, int qmax,
+                                           unsigned long long* wbase, const int* qs, const int* Mz, int qmax,
                                            uint32_t* wide)
 {
     const int lane = threadIdx.x & 63;
@@ -523,7 +577,8 @@ __device__ __forceinline__ void init_pixel(const DevModel& m, const DevParams& p
     const long long S = sh.S;
     const int nb = (T + 63) >> 6;
     uint2* lists = reinterpret_cast<uint2*>(wbase);
-    unsigned long long* ub = wbase + side * side;
+    unsigned long long* ub = wbase + side * side;                    // the HBM path's block bounds
+    unsigned long long* lb = wbase;                                  // the LDS path's area
     (void)qt;
 
     if (lane < KM) {
@@ -578,12 +633,14 @@ __device__ __forceinline__ void init_pixel(const DevModel& m, const DevParams& p
     uint32_t pe[INIT_EPL];
     long long ntot = 0;
     const int nk = (T + (1 << INIT_BWS) - 1) >> INIT_BWS;
-    uint32_t* bnd = reinterpret_cast<uint32_t*>(ub);                 // [nbs] sub-block bounds
-    uint32_t* E = reinterpret_cast<uint32_t*>(ub + (nbs + 1) / 2);   // [ELDS] bucketed photons
+    const int np = init_np(L);
+    const int bw2 = (int)init_bound_words(T, L, o);
+    uint32_t* bnd = reinterpret_cast<uint32_t*>(lb) + 2 * np - 2;    // [nbs] sub-block bounds, after their guards
+    uint32_t* E = reinterpret_cast<uint32_t*>(lb + bw2);             // [ELDS] bucketed photons
     int* bend = reinterpret_cast<int*>(E + ELDS);                   // [nk] bucket ends
     if (lds && WIDE) {
         // count the photons per bucket while totalling them (a first pass over HBM)
-        for (int b = lane; b < nbs; b += 64) bnd[b] = 0u;
+        for (int b = lane; b < bw2; b += 64) lb[b] = 0ull;
         for (int b = lane; b < nk; b += 64) bend[b] = 0;
         wave_sync();
         uint32_t nt = 0;                        // at most INIT_WIDE_ELDS x 65535
@@ -609,24 +666,35 @@ __device__ __forceinline__ void init_pixel(const DevModel& m, const DevParams& p
     if (lds && !WIDE) {
         // read the pooled photons once: entry k of the pool is lane k % 64's
         // pe[k / 64]
+        // (chunks past the pool's last one are skipped as a whole)
+        const int nch = (total + 63) >> 6;
         uint32_t src[INIT_EPL];
 #pragma unroll
-        for (int u = 0; u < INIT_EPL; ++u) src[u] = 0;
+        for (int u = 0; u < INIT_EPL; ++u) {
+            src[u] = 0;
+            pe[u] = 0u;
+        }
         for (int r = 0; r < side; ++r) {
             const uint32_t r0 = (uint32_t)__builtin_amdgcn_readlane((int)(rend - rlen), r);
             const uint32_t rb = (uint32_t)__builtin_amdgcn_readlane((int)rs, r);
 #pragma unroll
             for (int u = 0; u < INIT_EPL; ++u) {
+                if (u >= nch) break;
                 const uint32_t k = (uint32_t)(lane + 64 * u);
                 if (k >= r0) src[u] = rb + (k - r0);
             }
         }
 #pragma unroll
-        for (int u = 0; u < INIT_EPL; ++u) pe[u] = lane + 64 * u < total ? ent[src[u]] : 0u;
+        for (int u = 0; u < INIT_EPL; ++u) {
+            if (u >= nch) break;
+            if (lane + 64 * u < total) pe[u] = ent[src[u]];
+        }
         uint32_t nt = 0;                        // at most INIT_ELDS x 65535
 #pragma unroll
-        for (int u = 0; u < INIT_EPL; ++u)
+        for (int u = 0; u < INIT_EPL; ++u) {
+            if (u >= nch) break;
             if (lane + 64 * u < total && ent_bin(pe[u]) < T) nt += ent_cnt(pe[u]);
+        }
         ntot = wave_sum_u32(nt);
         lds = (unsigned long long)ntot * (unsigned long long)qmax <= 0xfffffffeull;
     }
@@ -634,7 +702,7 @@ __device__ __forceinline__ void init_pixel(const DevModel& m, const DevParams& p
         // Count the photons per 2^INIT_BWS-bin bucket, scan the counts into
         // bucket starts, then stage, bound and search them.
         if (!WIDE) {
-            for (int b = lane; b < nbs; b += 64) bnd[b] = 0u;
+            for (int b = lane; b < bw2; b += 64) lb[b] = 0ull;
             for (int b = lane; b < nk; b += 64) bend[b] = 0;
             wave_sync();
 #pragma unroll
@@ -674,17 +742,12 @@ __device__ __forceinline__ void init_pixel(const DevModel& m, const DevParams& p
                     const int t = ent_bin(v), z = ent_cnt(v);
                     const int pos = atomicAdd(&bend[min(t >> INIT_BWS, nk - 1)], 1);
                     E[pos] = t < T ? v : ((uint32_t)((nk << INIT_BWS) - 1) << 16);
-                    if (t < T) {
-                        const int blo = max(0, t + o - L + 1) / INIT_SB, bhi = min(T - 1, t + o) / INIT_SB;
-                        const int* Mx = M + (t + o - INIT_SB * bhi);
-                        for (int b = bhi; b >= blo; --b, Mx += INIT_SB)
-                            atomicAdd(&bnd[b], __umul24((unsigned)z, (unsigned)*Mx));
-                    }
+                    if (t < T) bound_photon<false>(lb, Mz, np, t + o, (uint32_t)z);
                 }
             }
             wave_sync();
         }
-        lds_search<WIDE>(m, p, T, L, o, nb, nbs, nk, pe, total, ntot, qs, M, bnd, E, bend, pk);
+        lds_search<WIDE>(m, p, T, L, o, nb, nbs, nk, pe, total, ntot, qs, Mz, lb, np, bnd, E, bend, pk);
     } else {
         // the window's pixels' photon lists (each ascending in t)
         const int npl = side * side;
@@ -892,7 +955,7 @@ __device__ __forceinline__ void init_pixel(const DevModel& m, const DevParams& p
 // QL: the IRF weight tables are staged in LDS (they fit INIT_QLDS ints).
 // wide: list of pixels left for k_init_wide (count first), or null.
 template <bool QL>
-__global__ __launch_bounds__(64 * INIT_WAVES) void k_init(DevModel m, DevParams p, Shape sh,
+__global__ __launch_bounds__(64 * INIT_WAVES, 7) void k_init(DevModel m, DevParams p, Shape sh,
                                                           const uint32_t* __restrict__ off,
                                                           const uint32_t* __restrict__ ent,
                                                           const float* __restrict__ gain, DevState s,
@@ -900,14 +963,14 @@ __global__ __launch_bounds__(64 * INIT_WAVES) void k_init(DevModel m, DevParams 
 {
     extern __shared__ unsigned long long smem64[];
     const int wv = threadIdx.x >> 6;
-    const size_t ww = init_wave_words(m.T, p.r_init);
+    const size_t ww = init_wave_words(m.T, m.L, m.o, p.r_init);
     int* qs = reinterpret_cast<int*>(smem64 + INIT_WAVES * ww);
-    int* M = qs + q_staged_ints(m.L);
-    const int qmax = stage_weights<QL>(m, qs, M);
+    int* Mz = qs + q_staged_ints(m.L);
+    const int qmax = stage_weights<QL>(m, qs, Mz);
     const long long pix = (long long)xcd_block(blockIdx.x, gridDim.x) * INIT_WAVES + wv;
     // whole wavefront (pixels of other IRF classes: their own launch); no workgroup barriers below
     if (pix >= sh.P || !in_class(m, pix)) return;
-    init_pixel<QL, false>(m, p, sh, off, ent, gain, s, pix, smem64 + (size_t)wv * ww, qs, M, qmax, wide);
+    init_pixel<QL, false>(m, p, sh, off, ent, gain, s, pix, smem64 + (size_t)wv * ww, qs, Mz, qmax, wide);
 }
 
 // The pixels k_init listed (pools of INIT_ELDS to INIT_WIDE_ELDS photons),
@@ -922,13 +985,13 @@ __global__ __launch_bounds__(64 * INIT_WAVES) void k_init_wide(DevModel m, DevPa
     const uint32_t n = wide[0];
     if ((size_t)blockIdx.x * INIT_WAVES >= n) return;                 // whole workgroup
     const int wv = threadIdx.x >> 6;
-    const size_t ww = init_wave_words(m.T, p.r_init, INIT_WIDE_ELDS);
+    const size_t ww = init_wave_words(m.T, m.L, m.o, p.r_init, INIT_WIDE_ELDS);
     int* qs = reinterpret_cast<int*>(smem64 + INIT_WAVES * ww);
-    int* M = qs + q_staged_ints(m.L);
-    const int qmax = stage_weights<true>(m, qs, M);
+    int* Mz = qs + q_staged_ints(m.L);
+    const int qmax = stage_weights<true>(m, qs, Mz);
     for (size_t k = (size_t)blockIdx.x * INIT_WAVES + wv; k < n; k += (size_t)gridDim.x * INIT_WAVES)
         init_pixel<true, true>(m, p, sh, off, ent, gain, s, (long long)wide[1 + k], smem64 + (size_t)wv * ww, qs,
-                               M, qmax, nullptr);
+                               Mz, qmax, nullptr);
 }
 
 __global__ void k_init_reset(uint32_t* wide)
@@ -1023,12 +1086,12 @@ __global__ __launch_bounds__(256) void k_init_normals(DevParams p, Shape sh, Dev
 }
 
 // LDS bytes of one init workgroup (wide: of the wide kernel): the
-// wavefronts' areas and the IRF weights.
-size_t init_lds_bytes(int T, int L, int r_init, bool wide)
+// wavefronts' areas and the IRF weights (o: the IRF's origin, 0 <= o < L).
+size_t init_lds_bytes(int T, int L, int o, int r_init, bool wide)
 {
     const size_t nq = q_staged_ints(L);
     const size_t qwords = nq <= INIT_QLDS ? (nq + q_window_ints(L) + 1) / 2 : 0;
-    return (INIT_WAVES * init_wave_words(T, r_init, wide ? INIT_WIDE_ELDS : INIT_ELDS) + qwords) *
+    return (INIT_WAVES * init_wave_words(T, L, o, r_init, wide ? INIT_WIDE_ELDS : INIT_ELDS) + qwords) *
            sizeof(unsigned long long);
 }
 
@@ -1036,14 +1099,14 @@ hipError_t launch_init(const DevModel& m, const DevParams& p, const Shape& sh, c
                        const uint32_t* ent, const float* gain, DevState s, uint32_t* wide, hipStream_t st)
 {
     if (sh.P == 0) return hipSuccess;
-    const size_t lds = init_lds_bytes(m.T, m.L, p.r_init, false);
+    const size_t lds = init_lds_bytes(m.T, m.L, m.o, p.r_init, false);
     const unsigned nblk = (unsigned)((sh.P + INIT_WAVES - 1) / INIT_WAVES);
     if (q_staged_ints(m.L) > (size_t)INIT_QLDS) {
         hipLaunchKernelGGL(k_init<false>, dim3(nblk), dim3(64 * INIT_WAVES), lds, st, m, p, sh, off, ent, gain, s,
                            nullptr);
         return hipGetLastError();
     }
-    const size_t wlds = init_lds_bytes(m.T, m.L, p.r_init, true);
+    const size_t wlds = init_lds_bytes(m.T, m.L, m.o, p.r_init, true);
     if (wlds > 65536 || sh.P >= (1ll << 32)) wide = nullptr;
     if (wide) hipLaunchKernelGGL(k_init_reset, dim3(1), dim3(64), 0, st, wide);
     hipLaunchKernelGGL(k_init<true>, dim3(nblk), dim3(64 * INIT_WAVES), lds, st, m, p, sh, off, ent, gain, s, wide);

@@ -446,13 +446,6 @@ __device__ __forceinline__ void store_points(const DevState& s, long long P, lon
 // Wave-level helpers (wave64).
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
 
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v)
-{
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-    return v;
-}
 
 // Cross-lane moves inside small aligned lane groups on the VALU (DPP), with
 // no LDS traffic.  Every lane of the wavefront must be active.
@@ -520,12 +513,55 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
     return v;
 }
 
-// Sum over the 64 lanes (every lane gets it), by a butterfly of lane swaps.
+// Sums over the 64 lanes (every lane gets the total, read from lane 63 of
+// the inclusive scan), on the VALU with no LDS traffic.  Every lane must be
+// active.
 __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
 {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-    return v;
+    return (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan(v), 63);
+}
+
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ unsigned long long dpp_or_zero_u64(unsigned long long v)
+{
+    const uint32_t lo = dpp_or_zero<CTRL, ROW_MASK>((uint32_t)v), hi = dpp_or_zero<CTRL, ROW_MASK>((uint32_t)(v >> 32));
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+__device__ __forceinline__ unsigned long long readlane63_u64(unsigned long long v)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+// The same scan on 64-bit integers (exact) and on doubles (a DPP move with no
+// source lane gives the bits of +0.0).
+__device__ __forceinline__ long long wave_sum(long long v)
+{
+    unsigned long long u = (unsigned long long)v;
+    u += dpp_or_zero_u64<0x111>(u);
+    u += dpp_or_zero_u64<0x112>(u);
+    u += dpp_or_zero_u64<0x114>(u);
+    u += dpp_or_zero_u64<0x118>(u);
+    u += dpp_or_zero_u64<0x142, 0xA>(u);
+    u += dpp_or_zero_u64<0x143, 0xC>(u);
+    return (long long)readlane63_u64(u);
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) { return wave_sum_u32(v); }
+__device__ __forceinline__ int wave_sum(int v) { return (int)wave_sum_u32((uint32_t)v); }
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+    auto step = [](double x, unsigned long long bits) { return x + __longlong_as_double((long long)bits); };
+    v = step(v, dpp_or_zero_u64<0x111>((unsigned long long)__double_as_longlong(v)));
+    v = step(v, dpp_or_zero_u64<0x112>((unsigned long long)__double_as_longlong(v)));
+    v = step(v, dpp_or_zero_u64<0x114>((unsigned long long)__double_as_longlong(v)));
+    v = step(v, dpp_or_zero_u64<0x118>((unsigned long long)__double_as_longlong(v)));
+    v = step(v, dpp_or_zero_u64<0x142, 0xA>((unsigned long long)__double_as_longlong(v)));
+    v = step(v, dpp_or_zero_u64<0x143, 0xC>((unsigned long long)__double_as_longlong(v)));
+    return __longlong_as_double((long long)readlane63_u64((unsigned long long)__double_as_longlong(v)));
 }
 
 // ---------------------------------------------------------------------------

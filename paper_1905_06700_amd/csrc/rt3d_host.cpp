@@ -17,7 +17,7 @@
 #include "rt3d_cnn.h"
 
 namespace rt3d {
-size_t init_lds_bytes(int T, int L, int r_init, bool wide = false);
+size_t init_lds_bytes(int T, int L, int o, int r_init, bool wide = false);
 }
 
 using namespace rt3d;
@@ -166,7 +166,8 @@ rt3d_status check_irf(const double* irf, uint32_t irf_len, int32_t irf_origin, i
     }
     if (!(sum > 0.0)) return RT3D_E_INVALID;
     if (irf_origin >= (int32_t)irf_len) return RT3D_E_INVALID;
-    if (init_lds_bytes(T, (int)irf_len, p->r_init) > 65536) return RT3D_E_UNSUPPORTED;
+    // the origin is not known before the IRF is normalised: its largest value
+    if (init_lds_bytes(T, (int)irf_len, (int)irf_len - 1, p->r_init) > 65536) return RT3D_E_UNSUPPORTED;
     return RT3D_OK;
 }
 
