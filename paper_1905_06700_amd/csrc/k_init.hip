@@ -666,35 +666,24 @@ __device__ __forceinline__ void init_pixel(const DevModel& m, const DevParams& p
     if (lds && !WIDE) {
         // read the pooled photons once: entry k of the pool is lane k % 64's
         // pe[k / 64]
-        // (chunks past the pool's last one are skipped as a whole)
-        const int nch = (total + 63) >> 6;
         uint32_t src[INIT_EPL];
 #pragma unroll
-        for (int u = 0; u < INIT_EPL; ++u) {
-            src[u] = 0;
-            pe[u] = 0u;
-        }
+        for (int u = 0; u < INIT_EPL; ++u) src[u] = 0;
         for (int r = 0; r < side; ++r) {
             const uint32_t r0 = (uint32_t)__builtin_amdgcn_readlane((int)(rend - rlen), r);
             const uint32_t rb = (uint32_t)__builtin_amdgcn_readlane((int)rs, r);
 #pragma unroll
             for (int u = 0; u < INIT_EPL; ++u) {
-                if (u >= nch) break;
                 const uint32_t k = (uint32_t)(lane + 64 * u);
                 if (k >= r0) src[u] = rb + (k - r0);
             }
         }
 #pragma unroll
-        for (int u = 0; u < INIT_EPL; ++u) {
-            if (u >= nch) break;
-            if (lane + 64 * u < total) pe[u] = ent[src[u]];
-        }
+        for (int u = 0; u < INIT_EPL; ++u) pe[u] = lane + 64 * u < total ? ent[src[u]] : 0u;
         uint32_t nt = 0;                        // at most INIT_ELDS x 65535
 #pragma unroll
-        for (int u = 0; u < INIT_EPL; ++u) {
-            if (u >= nch) break;
+        for (int u = 0; u < INIT_EPL; ++u)
             if (lane + 64 * u < total && ent_bin(pe[u]) < T) nt += ent_cnt(pe[u]);
-        }
         ntot = wave_sum_u32(nt);
         lds = (unsigned long long)ntot * (unsigned long long)qmax <= 0xfffffffeull;
     }
@@ -877,24 +866,26 @@ __device__ __forceinline__ void init_pixel(const DevModel& m, const DevParams& p
     const int npk = pk.n;
 
     // own photons: total and per claimed window
+    // (a pixel holds at most 65535 entries, each count below 65536: the sums
+    // fit 32 bits)
     const uint32_t e0 = off[pix], e1 = off[pix + 1];
-    long long zp = 0;
-    long long nown[KM] = {0, 0, 0, 0};
+    uint32_t zp = 0;
+    uint32_t nown[KM] = {0, 0, 0, 0};
     for (uint32_t e = e0 + lane; e < e1; e += 64) {
         const uint32_t v = ent[e];
-        const int z = ent_cnt(v);
+        const uint32_t z = (uint32_t)ent_cnt(v);
         zp += z;
         const int ow = pk.owner(ent_bin(v));
 #pragma unroll
         for (int k = 0; k < KM; ++k)
             if (ow == k) nown[k] += z;
     }
-    zp = wave_sum(zp);
+    zp = wave_sum_u32(zp);
     double H[KM] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int k = 0; k < KM; ++k) {
-        nown[k] = wave_sum(nown[k]);
         if (k < npk) {
+            nown[k] = wave_sum_u32(nown[k]);
             double hs = 0.0;
             for (int tb = pk.a[k] + lane; tb <= pk.c[k]; tb += 64) {
                 const int idx = tb - pk.t[k] + o;
@@ -911,7 +902,7 @@ __device__ __forceinline__ void init_pixel(const DevModel& m, const DevParams& p
             sum_n += nown[k];
             sum_w += pk.w[k];
         }
-    long long num = zp - sum_n;
+    long long num = (long long)zp - sum_n;
     if (num < 0) num = 0;
     const long long den = (long long)T - sum_w;
     // kept peaks, then ascending depth (distinct depths; a fixed sorting network)
