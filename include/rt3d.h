@@ -399,7 +399,7 @@ rt3d_status rt3d_debug_compact_events(rt3d_ctx* ctx, const uint32_t* ev_pixel, c
  * lidar grid before its points spread over the point grid (it needs a
  * workspace for the lidar frames).  Without super-resolution the
  * initialisation uses a bound workspace that covers the frames for its list
- * of pixels whose pooled window holds more than 560 active bins, which are
+ * of pixels whose pooled window holds more than 608 active bins, which are
  * then scored from LDS; without one they take a slower search from HBM with
  * the same result. */
 #define RT3D_STEP_INIT       0  /* log-matched-filter initialisation + initial normals (reads no state) */

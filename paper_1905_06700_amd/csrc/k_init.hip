@@ -115,7 +115,7 @@ __device__ __forceinline__ int q_range_max(const int* qst, int L, int lo, int hi
 __device__ __forceinline__ int popc_ballot(bool x) { return __popcll(__ballot(x)); }
 
 constexpr int INIT_WAVES = 4;
-constexpr int INIT_ELDS = 560;    // pooled entries a wavefront scores from LDS (held in registers)
+constexpr int INIT_ELDS = 608;    // pooled entries a wavefront scores from LDS (held in registers)
 constexpr int INIT_EPL = (INIT_ELDS + 63) / 64;   // pooled entries per lane
 // Pixels whose pool is larger, up to INIT_WIDE_ELDS entries, are listed and
 // scored from LDS by a second kernel that stages their photons in passes over
@@ -161,7 +161,7 @@ inline __host__ __device__ size_t init_wave_words(int T, int L, int o, int r_ini
     const size_t nb = (size_t)(T + 63) / 64, nbs = (size_t)(T + INIT_SB - 1) / INIT_SB;
     const size_t side = 2 * (size_t)r_init + 1;
     const size_t nk = ((size_t)T + (1u << INIT_BWS) - 1) >> INIT_BWS;
-    const size_t staged = nbs <= INIT_NB_LDS ? init_bound_words(T, L, o) + (elds + 1) / 2 + (nk + 1) / 2 : 0;
+    const size_t staged = nbs <= INIT_NB_LDS ? init_bound_words(T, L, o) + (elds + 1) / 2 + (nk + 3) / 4 : 0;
     const size_t hbm = side * side + nb;
     return hbm > staged ? hbm : staged;
 }
@@ -297,10 +297,22 @@ __device__ __forceinline__ uint32_t mad_u24(uint32_t z, uint32_t q, uint32_t acc
     return acc;
 }
 
+// Bucket cursors (then ends), two 16-bit values per 32-bit LDS word: a bucket
+// holds at most INIT_WIDE_ELDS photons, so no half carries into the other.
+struct Bend16 {
+    uint32_t* w;
+    __device__ __forceinline__ int get(int b) const { return (int)((w[b >> 1] >> ((b & 1) << 4)) & 0xffffu); }
+    __device__ __forceinline__ void add1(int b) const { atomicAdd(&w[b >> 1], 1u << ((b & 1) << 4)); }
+    __device__ __forceinline__ int fetch_inc(int b) const
+    {
+        return (int)((atomicAdd(&w[b >> 1], 1u << ((b & 1) << 4)) >> ((b & 1) << 4)) & 0xffffu);
+    }
+};
+
 // Exact scores of block bb's 64 tau (one per lane): L(tau) = sum of
 // z q[t - tau + o] over the pooled photons in the window [wlo, whi] the block
 // can see (photons in claimed bins have had their count set to zero).  The
-// photons are bucketed by 2^INIT_BWS bins in LDS (bucket b ends at bend[b],
+// photons are bucketed by 2^INIT_BWS bins in LDS (bucket b ends at bend.get(b),
 // nk buckets); the window's buckets are read 64 photons at a time and each
 // photon is broadcast from the lane that loaded it, four at a time so that
 // their weight lookups overlap.  qs holds the weights with INIT_QPAD zeros on
@@ -308,7 +320,7 @@ __device__ __forceinline__ uint32_t mad_u24(uint32_t z, uint32_t q, uint32_t acc
 // (photons with bins >= T were staged as zero counts at the last bucket's
 // last bin), so every lag lies in [-63 - 31, L + 62 + 31] and indexes the
 // padded table without a clamp.
-__device__ __forceinline__ uint32_t score_block(const uint32_t* E, const int* bend, int nk, int bb, const int* qs,
+__device__ __forceinline__ uint32_t score_block(const uint32_t* E, const Bend16 bend, int nk, int bb, const int* qs,
                                                 int L, int o)
 {
     const int lane = threadIdx.x & 63;
@@ -317,8 +329,8 @@ __device__ __forceinline__ uint32_t score_block(const uint32_t* E, const int* be
     uint32_t sc = 0;
     if (whi < 0) return sc;
     const int b0 = max(0, wlo) >> INIT_BWS, b1 = min(nk - 1, whi >> INIT_BWS);
-    const int x0 = __builtin_amdgcn_readfirstlane(b0 > 0 ? bend[b0 - 1] : 0);
-    const int x1 = __builtin_amdgcn_readfirstlane(bend[b1]);
+    const int x0 = __builtin_amdgcn_readfirstlane(b0 > 0 ? bend.get(b0 - 1) : 0);
+    const int x1 = __builtin_amdgcn_readfirstlane(bend.get(b1));
     for (int c0 = x0; c0 < x1; c0 += 64) {
         const int x = c0 + lane;
         const int vv = x < x1 ? (int)E[x] : 0;
@@ -354,7 +366,7 @@ template <bool STAGED>
 __device__ __forceinline__ void lds_search(const DevModel& m, const DevParams& p, int T, int L, int o, int nb,
                                            int nbs, int nk, const uint32_t (&pe)[INIT_EPL], int total, long long ntot,
                                            const int* qs, const int* Mz, unsigned long long* bnd2, int np,
-                                           uint32_t* bnd, uint32_t* E, int* bend, Peaks& pk)
+                                           uint32_t* bnd, uint32_t* E, const Bend16 bend, Peaks& pk)
 {
     const int lane = threadIdx.x & 63;
     // stage the photons bucketed by 2^INIT_BWS bins; bins >= T become zero
@@ -364,7 +376,7 @@ __device__ __forceinline__ void lds_search(const DevModel& m, const DevParams& p
         if (STAGED || lane + 64 * u >= total) break;
         const uint32_t v = pe[u];
         const int t = ent_bin(v);
-        const int pos = atomicAdd(&bend[min(t >> INIT_BWS, nk - 1)], 1);
+        const int pos = bend.fetch_inc(min(t >> INIT_BWS, nk - 1));
         E[pos] = t < T ? v : ((uint32_t)((nk << INIT_BWS) - 1) << 16);
     }
     // each photon raises the bound of every sub-block whose tau can see it by
@@ -470,7 +482,7 @@ __device__ __forceinline__ void lds_search(const DevModel& m, const DevParams& p
         win = wave_sum_u32(win);
         uint32_t nwin = 0;                                      // at most ntot
         const int b0 = a >> INIT_BWS, b1 = min(nk - 1, c >> INIT_BWS);
-        const int x0 = b0 > 0 ? bend[b0 - 1] : 0, x1 = bend[b1];
+        const int x0 = b0 > 0 ? bend.get(b0 - 1) : 0, x1 = bend.get(b1);
         for (int x = x0 + lane; x < x1; x += 64) {
             const uint32_t v = E[x];
             const int tb = ent_bin(v);
@@ -637,11 +649,12 @@ __device__ __forceinline__ void init_pixel(const DevModel& m, const DevParams& p
     const int bw2 = (int)init_bound_words(T, L, o);
     uint32_t* bnd = reinterpret_cast<uint32_t*>(lb) + 2 * np - 2;    // [nbs] sub-block bounds, after their guards
     uint32_t* E = reinterpret_cast<uint32_t*>(lb + bw2);             // [ELDS] bucketed photons
-    int* bend = reinterpret_cast<int*>(E + ELDS);                   // [nk] bucket ends
+    const Bend16 bend{E + ELDS};                                    // [nk] bucket ends, 16 bits each
+    const int nkw = (nk + 1) >> 1;                                  // their words
     if (lds && WIDE) {
         // count the photons per bucket while totalling them (a first pass over HBM)
         for (int b = lane; b < bw2; b += 64) lb[b] = 0ull;
-        for (int b = lane; b < nk; b += 64) bend[b] = 0;
+        for (int b = lane; b < nkw; b += 64) bend.w[b] = 0u;
         wave_sync();
         uint32_t nt = 0;                        // at most INIT_WIDE_ELDS x 65535
         // four 64-entry chunks per round, their loads in flight together
@@ -657,7 +670,7 @@ __device__ __forceinline__ void init_pixel(const DevModel& m, const DevParams& p
             for (int u = 0; u < 4; ++u)
                 if (c0 + 64 * u + lane < total) {
                     if (ent_bin(v[u]) < T) nt += ent_cnt(v[u]);
-                    atomicAdd(&bend[min(ent_bin(v[u]) >> INIT_BWS, nk - 1)], 1);
+                    bend.add1(min(ent_bin(v[u]) >> INIT_BWS, nk - 1));
                 }
         }
         ntot = wave_sum_u32(nt);
@@ -692,23 +705,26 @@ __device__ __forceinline__ void init_pixel(const DevModel& m, const DevParams& p
         // bucket starts, then stage, bound and search them.
         if (!WIDE) {
             for (int b = lane; b < bw2; b += 64) lb[b] = 0ull;
-            for (int b = lane; b < nk; b += 64) bend[b] = 0;
+            for (int b = lane; b < nkw; b += 64) bend.w[b] = 0u;
             wave_sync();
 #pragma unroll
             for (int u = 0; u < INIT_EPL; ++u) {
                 if (lane + 64 * u >= total) break;
-                atomicAdd(&bend[min(ent_bin(pe[u]) >> INIT_BWS, nk - 1)], 1);
+                bend.add1(min(ent_bin(pe[u]) >> INIT_BWS, nk - 1));
             }
         }
         wave_sync();
         // bucket starts (exclusive prefix of the counts); each bucket's cursor
         // ends at the bucket's end once the photons are staged
+        // (a word's two buckets at a time; a padding bucket past nk counts 0)
         uint32_t carry = 0;
-        for (int c0 = 0; c0 < nk; c0 += 64) {
+        for (int c0 = 0; c0 < nkw; c0 += 64) {
             const int b = c0 + lane;
-            const uint32_t cnt = b < nk ? (uint32_t)bend[b] : 0u;
+            const uint32_t wd = b < nkw ? bend.w[b] : 0u;
+            const uint32_t lo = wd & 0xffffu, cnt = lo + (wd >> 16);
             const uint32_t inc = wave_incl_scan(cnt);
-            if (b < nk) bend[b] = (int)(carry + inc - cnt);
+            const uint32_t s0 = carry + inc - cnt;
+            if (b < nkw) bend.w[b] = s0 | ((s0 + lo) << 16);
             carry += (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
         }
         wave_sync();
@@ -729,7 +745,7 @@ __device__ __forceinline__ void init_pixel(const DevModel& m, const DevParams& p
                     if (c0 + 64 * u + lane >= total) continue;
                     const uint32_t v = vv[u];
                     const int t = ent_bin(v), z = ent_cnt(v);
-                    const int pos = atomicAdd(&bend[min(t >> INIT_BWS, nk - 1)], 1);
+                    const int pos = bend.fetch_inc(min(t >> INIT_BWS, nk - 1));
                     E[pos] = t < T ? v : ((uint32_t)((nk << INIT_BWS) - 1) << 16);
                     if (t < T) bound_photon<false>(lb, Mz, np, t + o, (uint32_t)z);
                 }

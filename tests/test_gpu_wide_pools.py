@@ -2,7 +2,7 @@
 (Methods, initialisation: the log-matched filter over the pooled photons of
 the window around each pixel).  One frame whose background rises across the
 columns from 20 to 330 photons per pixel at T = 4613 puts pools of every size
-in one launch: up to 560 photons (scored from registers and LDS), 561 to
+in one launch: up to 608 photons (scored from registers and LDS), 609 to
 1536 (listed and scored from LDS by the second kernel, which stages them in
 passes over HBM), and more (the HBM path).  Through the C ABI against the
 oracle: the initial state exactly (counts and depths) or within rounding
@@ -43,7 +43,7 @@ def pools(sc):
 def test_scene_spans_every_pool_regime():
     sc = scene()
     pl = pools(sc).reshape(-1)
-    assert (pl <= 560).sum() >= 100 and ((pl > 560) & (pl <= 1536)).sum() >= 100 and (pl > 1536).sum() >= 100
+    assert (pl <= 608).sum() >= 100 and ((pl > 608) & (pl <= 1536)).sum() >= 100 and (pl > 1536).sum() >= 100
 
 
 def test_wide_pools_init_matches_oracle():
