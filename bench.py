@@ -175,10 +175,11 @@ def roofline_of(kernel, F, N, T, E, pooled, L, pts, avg_ms):
             "algorithmic_bytes_per_launch": int(abytes)}
 
 
-def stored_traffic(kernel):
+def stored_traffic(kernel, frames):
     """HBM bytes per launch measured with FETCH_SIZE / WRITE_SIZE counters
     (profiles/traffic_<kernel>_head141x141x4613.md), or None when the
-    kernel's sources changed since the counters were taken."""
+    kernel's sources changed since the counters were taken or the counters
+    were taken at another number of frames per launch."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_head141x141x4613.md")
     if not os.path.exists(path):
@@ -192,7 +193,7 @@ def stored_traffic(kernel):
     h = hashlib.sha256()
     for f in GROUP_SOURCES[kernel] + ["rt3d_dev.h"]:
         h.update(open(os.path.join(ROOT, "paper_1905_06700_amd", "csrc", f), "rb").read())
-    if rec.get("sources_sha256") != h.hexdigest():
+    if rec.get("sources_sha256") != h.hexdigest() or int(rec.get("frames", 0)) != frames:
         return None
     return int(float(rec["bytes_per_launch"]))
 
@@ -732,7 +733,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--frames", type=int, default=16, help="frames per reconstruction call")
+    ap.add_argument("--frames", type=int, default=32,
+                    help="frames per reconstruction call (32: where frames/s levels off)")
     ap.add_argument("--kernel", default="", help="kernel group for the roofline object (default: the one "
                                                   "taking the most time per call)")
     ap.add_argument("--cpu-frames", type=int, default=2, help="frames the oracle times (0 = skip)")
@@ -865,7 +867,7 @@ def main():
     avg_ms = kms / max(klaunch, 1)
     roofline = roofline_of(kernel, F, ROWS * COLS, BINS, E, pooled, len(sc0.irf.probs), pts, avg_ms)
     roofline["launches"] = int(klaunch)
-    traffic = stored_traffic(kernel)
+    traffic = stored_traffic(kernel, F)
     if traffic is not None:
         roofline["traffic"] = traffic
     kernels = {g: {"ms_per_call": round(group[g][0], 4), "launches_per_call": group[g][1],
