@@ -188,17 +188,24 @@ __device__ __forceinline__ void load8(const PixVec& pv, int vr, uint32_t (&w)[4]
     }
 }
 
-// Bit k of the result: bin k of the vector is non-zero (bit 15 of each
-// 16-bit half set by adding 0x7fff to its low 15 bits, or'ed with the half).
+// Bit k of the result: bin k of the vector is non-zero.  Each word's two
+// 16-bit counts become 0 or 1 with one packed 16-bit minimum against 1;
+// words 1 and 3 shift by two bits onto words 0 and 2, word 2 by four onto
+// word 0, so bins 0, 2, 4, 6 land on bits 0, 2, 4, 6 and bins 1, 3, 5, 7 on
+// bits 16, 18, 20, 22, which a shift by 15 brings to bits 1, 3, 5, 7.
+__device__ __forceinline__ uint32_t nonzero_halves(uint32_t w)
+{
+    uint32_t r;
+    asm("v_pk_min_u16 %0, %1, %2" : "=v"(r) : "v"(w), "s"(0x00010001u));   // (the compiler otherwise
+    return r;                                                             // compares each half)
+}
+
 __device__ __forceinline__ uint32_t nonzero8(const uint32_t (&w)[4])
 {
-    uint32_t m = 0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const uint32_t t = (((w[q] & 0x7fff7fffu) + 0x7fff7fffu) | w[q]) & 0x80008000u;
-        m |= ((t >> 15) | (t >> 30)) << (2 * q);
-    }
-    return m & 0xffu;
+    const uint32_t a = nonzero_halves(w[0]) | (nonzero_halves(w[1]) << 2);
+    const uint32_t b = nonzero_halves(w[2]) | (nonzero_halves(w[3]) << 2);
+    const uint32_t c = a | (b << 4);
+    return (c | (c >> 15)) & 0xffu;
 }
 
 // Count of bin k of the vector.
@@ -209,13 +216,19 @@ __device__ __forceinline__ uint32_t bin8(const uint32_t (&w)[4], int k)
     return (k & 1) ? x >> 16 : x & 0xffffu;
 }
 
+// Count of bin k of two consecutive vectors (k < 16).
+__device__ __forceinline__ uint32_t bin16(const uint32_t (&w0)[4], const uint32_t (&w1)[4], int k)
+{
+    return k < 8 ? bin8(w0, k) : bin8(w1, k - 8);
+}
+
 // Pass 1: each pixel's histogram is read once; its non-zero bins, as entries
 // (t << 16 | z) in ascending t, go to the pixel's staging slot of CP_STAGE
 // entries (the first CP_STAGE of them when it has more; no staging when
 // `stage` is null), and its entry count to counts[p].  One wavefront per
-// pixel; each lane holds 8 consecutive bins and a wavefront prefix sum of the
-// lanes' non-zero counts places them; a lane writes its non-zero bins one set
-// bit of its mask at a time (most lanes hold none).
+// pixel; each lane holds 16 consecutive bins (two vectors) and a wavefront
+// prefix sum of the lanes' non-zero counts places them; a lane writes its
+// non-zero bins one set bit of its mask at a time (most lanes hold none).
 __global__ __launch_bounds__(64 * CP_WAVES) void k_compact_stage(const uint16_t* __restrict__ Z, long long P,
                                                                  int T, uint32_t* __restrict__ counts,
                                                                  uint32_t* __restrict__ stage)
@@ -226,19 +239,20 @@ __global__ __launch_bounds__(64 * CP_WAVES) void k_compact_stage(const uint16_t*
     const PixVec pv = pix_vectors(Z, p, T, P * T);
     uint32_t* slot = stage ? stage + p * CP_STAGE : nullptr;
     uint32_t run = 0;
-    for (int vb = 0; vb < pv.nvec; vb += 64) {        // uniform over the wave
-        const int vr = vb + lane;
-        uint32_t w[4] = {0u, 0u, 0u, 0u};
-        if (vr < pv.nvec) load8(pv, vr, w);
-        uint32_t m = nonzero8(w);
+    for (int vb = 0; vb < pv.nvec; vb += 128) {       // uniform over the wave
+        const int vr = vb + 2 * lane;
+        uint32_t w0[4] = {0u, 0u, 0u, 0u}, w1[4] = {0u, 0u, 0u, 0u};
+        if (vr < pv.nvec) load8(pv, vr, w0);
+        if (vr + 1 < pv.nvec) load8(pv, vr + 1, w1);
+        uint32_t m = nonzero8(w0) | (nonzero8(w1) << 8);
         const uint32_t c = (uint32_t)__builtin_popcount(m);
         const uint32_t inc = wave_incl_scan(c);
         uint32_t pos = run + (inc - c);
-        const uint32_t base = (uint32_t)((vr << 3) - pv.lo_off);
+        const uint32_t base = (uint32_t)((vr << 3) - pv.lo_off);   // bin of bit 0 (bit k: base + k)
         while (m) {
             const int k = __builtin_ctz(m);
             m &= m - 1u;
-            if (slot && pos < CP_STAGE) slot[pos] = ((base + k) << 16) | bin8(w, k);
+            if (slot && pos < CP_STAGE) slot[pos] = ((base + k) << 16) | bin16(w0, w1, k);
             ++pos;
         }
         run += (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
