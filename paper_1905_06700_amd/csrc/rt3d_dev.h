@@ -183,16 +183,21 @@ __device__ __forceinline__ void cr_segment(const float4 c, float s, float& h, fl
 // h(tb - t) and dh/dtau for an integer bin tb and a point at depth t held as
 // integer anchor a = floor(t) plus fraction f = t - a.  h is the Catmull-Rom
 // interpolant of the IRF samples (continuous value and slope).
+// The lag's sample position x = tb - a + o - f falls in segment
+// idx = floor(x) + 1 at local parameter s = x - floor(x): with f > 0 that is
+// idx = tb - a + o and s = 1 - f, with f = 0 idx = tb - a + o + 1 and s = 0.
+// Only idx depends on the bin, so a loop over bins for one point keeps s and
+// the offset; segments exist for -1 < x < L, i.e. idx in [1 - sh, L].
 __device__ __forceinline__ void irf_eval_t(const float4* __restrict__ cr, int L, int o, int tb, int a, float f,
                                            float& h, float& hp)
 {
-    const float x = (float)(tb - a + o) - f;   // sample position of the lag
+    const int sh = f > 0.f ? 1 : 0;
+    const float s = sh ? 1.f - f : 0.f;
+    const int lo = 1 - sh;
+    const int idx = tb - a + o + lo;
     h = 0.f;
     hp = 0.f;
-    if (x > -1.f && x < (float)L) {
-        const float fk = floorf(x);
-        cr_segment(cr[(int)fk + 1], x - fk, h, hp);
-    }
+    if ((unsigned)(idx - lo) <= (unsigned)(L - lo)) cr_segment(cr[idx], s, h, hp);
 }
 
 __device__ __forceinline__ void irf_eval(const DevModel& m, int tb, int a, float f, float& h, float& hp)
