@@ -872,6 +872,19 @@ def main():
         roofline["traffic"] = traffic
     kernels = {g: {"ms_per_call": round(group[g][0], 4), "launches_per_call": group[g][1],
                    "share": round(group[g][0] / gtotal, 4)} for g in GROUPS}
+    # the whole call against HBM: histogram bins at 2 bytes each read once
+    # (the compaction's floor), and every HBM-bound group's algorithmic bytes
+    # (the init, bound by its integer arithmetic, counts its pooled reads of
+    # L2-resident entries as 4 bytes per own entry)
+    call_bytes = sum(algorithmic_bytes(g, F, ROWS * COLS, BINS, E, pts) * group[g][1]
+                     for g in GROUPS if g != "init") + 4 * E
+    call_roofline = {
+        "histogram_bins_per_s": round(gbin * 1e9, 1),
+        "bins_per_s_at_hbm_peak": HBM_PEAK_GBS * 1e9 / 2,
+        "frac_bins": round(gbin * 1e9 / (HBM_PEAK_GBS * 1e9 / 2), 4),
+        "algorithmic_bytes_per_call": int(call_bytes),
+        "achieved_GBs": round(call_bytes / (ms_per_step / 1e3) / 1e9, 1),
+        "frac_hbm": round(call_bytes / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
 
     cpu = None
     if args.cpu_frames > 0:
@@ -919,7 +932,7 @@ def main():
         "execution_time_sweep": None if args.no_sweep else execution_time_sweep(),
         "stress_batch": None if args.no_stress else stress_batch(),
         "wall_s": round(wall, 3),
-        "roofline": roofline, "kernels": kernels, "cpu_baseline": cpu,
+        "roofline": roofline, "call_roofline": call_roofline, "kernels": kernels, "cpu_baseline": cpu,
         "learned_vs_apss": None if args.no_learned else learned_vs_apss(),
         "paper_context": {"frames_per_s": 76.9, "ms_per_frame": 13, "hardware": "NVIDIA Titan Xp",
                           "data": "real head scan, ~3 photons/px, SBR 13"},
