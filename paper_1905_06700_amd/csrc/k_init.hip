@@ -910,8 +910,7 @@ __device__ __forceinline__ void init_pixel(const DevModel& m, const DevParams& p
             H[k] = wave_sum(hs);
         }
     }
-    if (lane != 0) return;
-    long long sum_n = 0, sum_w = 0;
+    long long sum_n = 0, sum_w = 0;                          // (wave-uniform)
 #pragma unroll
     for (int k = 0; k < KM; ++k)
         if (k < npk) {
@@ -921,38 +920,35 @@ __device__ __forceinline__ void init_pixel(const DevModel& m, const DevParams& p
     long long num = (long long)zp - sum_n;
     if (num < 0) num = 0;
     const long long den = (long long)T - sum_w;
-    // kept peaks, then ascending depth (distinct depths; a fixed sorting network)
-    int kt[KM];
-    float kr[KM];
-    bool kk[KM];
-#pragma unroll
-    for (int k = 0; k < KM; ++k) {
-        const long long w = pk.w[k];
-        const bool keep = k < npk && (den > 0 ? (nown[k] * den > num * w) : (nown[k] > 0)) && H[k] > 0.0;
-        const double excess = den > 0 ? (double)nown[k] - (double)num * (double)w / (double)den
-                                      : (double)nown[k];
-        kk[k] = keep;
-        kt[k] = keep ? pk.t[k] : 0x7fffffff;
-        kr[k] = keep ? (float)(excess / ((double)G * H[k])) : 0.f;
-    }
-#pragma unroll
-    for (int x = 0; x < KM; ++x)
-#pragma unroll
-        for (int y = 0; y + 1 < KM - x; ++y)
-            if (kt[y + 1] < kt[y]) {
-                const int tt = kt[y]; kt[y] = kt[y + 1]; kt[y + 1] = tt;
-                const float rr = kr[y]; kr[y] = kr[y + 1]; kr[y + 1] = rr;
-            }
-    int nkeep = 0;
-#pragma unroll
-    for (int k = 0; k < KM; ++k) nkeep += kk[k] ? 1 : 0;
-    if (nkeep > p.k_max) nkeep = p.k_max;
+    // lane k < KM decides peak k (keep, depth, intensity); the kept peaks
+    // take the slots in ascending depth (depths are distinct): a peak's slot
+    // is the number of kept peaks above it
+    long long w = 0;
+    long long nwk = 0;
+    double hk = 0.0;
+    int tk = 0;
 #pragma unroll
     for (int k = 0; k < KM; ++k)
-        if (k < nkeep) {
-            s.t[k * S + pix] = (double)kt[k];
-            s.r[k * S + pix] = kr[k];
+        if (lane == k) {
+            w = pk.w[k];
+            nwk = nown[k];
+            hk = H[k];
+            tk = pk.t[k];
         }
+    const bool keep = lane < npk && (den > 0 ? (nwk * den > num * w) : (nwk > 0)) && hk > 0.0;
+    const int kt = keep ? tk : 0x7fffffff;
+    const uint32_t kept = (uint32_t)__ballot(keep) & ((1u << KM) - 1u);
+    int rank = 0;
+#pragma unroll
+    for (int j = 0; j < KM; ++j) rank += __builtin_amdgcn_readlane(kt, j) < kt ? 1 : 0;
+    int nkeep = __builtin_popcount(kept);
+    if (nkeep > p.k_max) nkeep = p.k_max;
+    if (keep && rank < nkeep) {
+        const double excess = den > 0 ? (double)nwk - (double)num * (double)w / (double)den : (double)nwk;
+        s.t[rank * S + pix] = (double)kt;
+        s.r[rank * S + pix] = (float)(excess / ((double)G * hk));
+    }
+    if (lane != 0) return;
     s.cnt[pix] = (uint8_t)nkeep;
     const double bown = den > 0 ? (double)num / (double)den : 0.0;
     const double b0 = bown / (double)G;
