@@ -35,31 +35,102 @@ namespace rt3d {
 template <int LPP>
 constexpr int step_batch() { return 64 / LPP; }   // entries a lane loads at once
 
-// Orders the LDS traffic of one wavefront (a pixel's lanes share its list).
-__device__ __forceinline__ void step_sync()
+// Entries of one batch of a pixel: step_batch per lane, STEP_LIST per pixel.
+constexpr int STEP_LIST = 64;
+
+// LDS words per workgroup for the lanes' staged entries.
+template <int LPP>
+constexpr int step_stage_words() { return 256 * step_batch<LPP>(); }
+
+// A lane's staging segment: slot n of lane l of a wavefront at n * 64 + l, so
+// that the wavefront's writes and reads of one slot each fall on distinct banks
+// whatever slot each lane is at.
+template <int LPP>
+__device__ __forceinline__ uint32_t* stage_segment(uint32_t* stage)
 {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    return stage + (threadIdx.x / 64) * (64 * step_batch<LPP>()) + (threadIdx.x % 64);
 }
 
-// Entries of one batch of a pixel (step_batch per lane), staged in LDS.
-constexpr int STEP_LIST = 64;
+// Largest point count over the wavefront (uniform).
+__device__ __forceinline__ int wave_max_count(int c)
+{
+    if (__builtin_amdgcn_ballot_w64(c > 3)) return 4;
+    if (__builtin_amdgcn_ballot_w64(c > 2)) return 3;
+    if (__builtin_amdgcn_ballot_w64(c > 1)) return 2;
+    if (__builtin_amdgcn_ballot_w64(c > 0)) return 1;
+    return 0;
+}
 
 // Partial sums over one pixel's entries (e0p .. e1 - 1):
 // sz = sum z/lambda, sh[k] = sum z h_k/lambda, shp[k] = sum z h'_k/lambda.
-// h_k vanishes outside bins [floor(t_k) - o - 1, floor(t_k) - o + L], so only
-// entries inside the union [lo, hi] of these ranges (the points' support) are
-// evaluated; every other entry has lambda = g b and only adds z / (g b) to
-// sz.  The pixel's LPP lanes load its entries STEP_BATCH per lane at a time
-// (entry e0p + sub + LPP u) and stage the batch in the pixel's LDS list.  The
-// entries ascend in bin, so the batch's support entries are one contiguous
-// run: the lanes count the entries below lo and up to hi, and then evaluate
-// the run from LDS, its entries shared out over the lanes in turn.
+// h_k is zero outside bins floor(t_k) - o .. floor(t_k) - o + L (the
+// segments' domain), so an entry in none of these ranges has lambda = g b and
+// only adds z / (g b) to sz; those photons are summed as integers and added
+// once.  The
+// pixel's LPP lanes load its entries STEP_LIST at a time, entry
+// e0p + sub + LPP u to lane sub; each lane writes the entries of its batch
+// that lie in some point's support to its own LDS segment and evaluates them
+// itself, so the work of a wavefront is the largest count of such entries on
+// one lane, whatever the spread of the points of its pixels.  NPT is the
+// largest point count of the wavefront; points at or beyond a lane's count
+// have r = 0 and an anchor no entry's bin reaches, so they neither select
+// entries nor change lambda, and a lane's sums do not depend on the other
+// pixels of its wavefront.
+template <int LPP, int NPT>
+__device__ __forceinline__ void accumulate_n(const DevModel& m, const float4* cr, const PixPoints& q, float bb,
+                                             float invG, const uint32_t* __restrict__ ent, uint32_t e0p,
+                                             uint32_t e1, int sub, uint32_t* seg, float& sz, float (&sh)[KM],
+                                             float (&shp)[KM])
+{
+    constexpr int STEP_BATCH = step_batch<LPP>();
+    uint32_t zout = 0;                                    // photons of this lane's entries outside every support
+    for (uint32_t eb = e0p; eb < e1; eb += STEP_LIST) {    // the same trip count on the pixel's lanes
+        uint32_t v[STEP_BATCH];
+#pragma unroll
+        for (int u = 0; u < STEP_BATCH; ++u) {
+            const uint32_t x = eb + sub + u * LPP;
+            v[u] = x < e1 ? ent[x] : 0u;
+        }
+        int n = 0;
+#pragma unroll
+        for (int u = 0; u < STEP_BATCH; ++u) {
+            const int tbo = ent_bin(v[u]) + m.o;
+            bool in = false;
+#pragma unroll
+            for (int k = 0; k < NPT; ++k) in = in || (uint32_t)(tbo - q.a[k]) <= (uint32_t)m.L;
+            in = in && eb + sub + u * LPP < e1;
+            seg[n * 64] = v[u];                           // kept only when it lies in a support
+            n += in ? 1 : 0;
+            zout += in ? 0u : (uint32_t)ent_cnt(v[u]);    // zero where not valid
+        }
+        if (NPT == 0) continue;
+        for (int j = 0; j < n; ++j) {
+            const uint32_t v1 = seg[j * 64];
+            const int tb = ent_bin(v1);
+            const float z = (float)ent_cnt(v1);
+            float h[KM], hp[KM];
+            float lam = bb;
+#pragma unroll
+            for (int k = 0; k < NPT; ++k) {
+                irf_eval_t(cr, m.L, m.o, tb, q.a[k], q.f[k], h[k], hp[k]);
+                lam = fmaf(q.r[k], h[k], lam);
+            }
+            const float zl = z * invG * __builtin_amdgcn_rcpf(lam);
+            sz += zl;
+#pragma unroll
+            for (int k = 0; k < NPT; ++k) {
+                sh[k] = fmaf(zl, h[k], sh[k]);
+                shp[k] = fmaf(zl, hp[k], shp[k]);
+            }
+        }
+    }
+    sz += (float)zout * invG * __builtin_amdgcn_rcpf(bb);
+}
+
 template <int LPP>
 __device__ __forceinline__ void accumulate(const DevModel& m, const float4* cr, const PixPoints& q, float bb,
                                            float G, const uint32_t* __restrict__ ent, uint32_t e0p, uint32_t e1,
-                                           int sub, uint32_t* list, float& sz, float (&sh)[KM], float (&shp)[KM])
+                                           int sub, uint32_t* seg, float& sz, float (&sh)[KM], float (&shp)[KM])
 {
     sz = 0.f;
 #pragma unroll
@@ -68,68 +139,13 @@ __device__ __forceinline__ void accumulate(const DevModel& m, const float4* cr, 
         shp[k] = 0.f;
     }
     const float invG = 1.f / G;
-    int lo = 0x7fffffff, hi = -0x7fffffff;
-#pragma unroll
-    for (int k = 0; k < KM; ++k)
-        if (k < q.c) {
-            lo = min(lo, q.a[k] - m.o - 1);
-            hi = max(hi, q.a[k] - m.o + m.L);
-        }
-    int zout = 0;                                         // photons of this lane's entries outside the run
-    for (uint32_t eb = e0p; eb < e1; eb += STEP_LIST) {    // the same trip count on the pixel's lanes
-        constexpr int STEP_BATCH = step_batch<LPP>();
-        uint32_t v[STEP_BATCH];
-#pragma unroll
-        for (int u = 0; u < STEP_BATCH; ++u) {
-            const uint32_t x = eb + sub + u * LPP;
-            v[u] = x < e1 ? ent[x] : 0u;
-        }
-        uint32_t nlo = 0, nhi = 0;
-#pragma unroll
-        for (int u = 0; u < STEP_BATCH; ++u) {
-            const int tb = ent_bin(v[u]);
-            const bool valid = eb + sub + u * LPP < e1;
-            const bool below = valid && tb < lo, upto = valid && tb <= hi;
-            nlo += below ? 1u : 0u;
-            nhi += upto ? 1u : 0u;
-            zout += upto && !below ? 0 : ent_cnt(v[u]);     // zero where not valid
-            list[sub + u * LPP] = v[u];
-        }
-        nlo = quad_sum_u32(nlo);
-        nhi = quad_sum_u32(nhi);
-        if (LPP == 8) {   // the other quad of the pixel's eight lanes (half-row mirror)
-            nlo += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)nlo, 0x141, 0xF, 0xF, true);
-            nhi += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)nhi, 0x141, 0xF, 0xF, true);
-        }
-        step_sync();
-        for (uint32_t j = nlo + sub; j < nhi; j += LPP) {
-            const uint32_t v1 = list[j];
-            const int tb = ent_bin(v1);
-            const float z = (float)ent_cnt(v1);
-            float h[KM], hp[KM];
-            float lam = bb;
-#pragma unroll
-            for (int k = 0; k < KM; ++k) {
-                h[k] = 0.f;
-                hp[k] = 0.f;
-                if (k < q.c) {
-                    irf_eval_t(cr, m.L, m.o, tb, q.a[k], q.f[k], h[k], hp[k]);
-                    lam = fmaf(q.r[k], h[k], lam);
-                }
-            }
-            const float zl = z * invG * __builtin_amdgcn_rcpf(lam);
-            sz += zl;
-#pragma unroll
-            for (int k = 0; k < KM; ++k) {
-                if (k < q.c) {
-                    sh[k] = fmaf(zl, h[k], sh[k]);
-                    shp[k] = fmaf(zl, hp[k], shp[k]);
-                }
-            }
-        }
-        step_sync();
+    switch (wave_max_count(q.c)) {
+    case 0: accumulate_n<LPP, 0>(m, cr, q, bb, invG, ent, e0p, e1, sub, seg, sz, sh, shp); break;
+    case 1: accumulate_n<LPP, 1>(m, cr, q, bb, invG, ent, e0p, e1, sub, seg, sz, sh, shp); break;
+    case 2: accumulate_n<LPP, 2>(m, cr, q, bb, invG, ent, e0p, e1, sub, seg, sz, sh, shp); break;
+    case 3: accumulate_n<LPP, 3>(m, cr, q, bb, invG, ent, e0p, e1, sub, seg, sz, sh, shp); break;
+    default: accumulate_n<LPP, KM>(m, cr, q, bb, invG, ent, e0p, e1, sub, seg, sz, sh, shp); break;
     }
-    sz += (float)zout * invG * __builtin_amdgcn_rcpf(bb);
 }
 
 // Sums the partials of the LPP lanes of a pixel (every lane ends with the total).
@@ -231,17 +247,17 @@ __global__ __launch_bounds__(256) void k_depth_step(DevModel m, DevParams p, Sha
                                                     const uint32_t* __restrict__ ent,
                                                     const float* __restrict__ gain, DevState s)
 {
-    __shared__ uint32_t lists[256 / LPP * STEP_LIST];
+    __shared__ uint32_t stage[step_stage_words<LPP>()];
     __shared__ float4 crl[TLDS ? STEP_CR_LDS : 1];
     const float4* cr = stage_segments<TLDS>(m, crl);
-    uint32_t* list = lists + (threadIdx.x / LPP) * STEP_LIST;
+    uint32_t* seg = stage_segment<LPP>(stage);
     const long long P = sh.P;
     const Lane L = lane_setup<LPP>(m, s, P, off, gain, true);
     float sz, shh[KM], shp[KM];
     // S' first: its table reads do not wait for the entries
     float Sv[KM], Spv[KM];
     s_eval_points<LPP>(m, L.q, L.sub, Sv, Spv);
-    accumulate<LPP>(m, cr, L.q, L.live ? s.b[L.pix] : 1.f, L.live ? L.G : 1.f, ent, L.e0, L.e1, L.sub, list, sz, shh, shp);
+    accumulate<LPP>(m, cr, L.q, L.live ? s.b[L.pix] : 1.f, L.live ? L.G : 1.f, ent, L.e0, L.e1, L.sub, seg, sz, shh, shp);
     reduce_lanes<LPP>(sz, shh, shp);
     if (!L.live || L.sub != 0) return;
 #pragma unroll
@@ -282,7 +298,7 @@ __device__ __forceinline__ void merge_lane(const DevState& s, long long P, const
         const double tk = on ? t[k] : 0.0;
         const double fl = floor(tk);
         q.t[k] = tk;
-        q.a[k] = (int)fl;
+        q.a[k] = on ? (int)fl : PT_ABSENT;
         q.f[k] = (float)(tk - fl);
         q.r[k] = on ? r[k] : 0.f;
     }
@@ -296,15 +312,15 @@ __global__ __launch_bounds__(256) void k_intensity_step(DevModel m, DevParams p,
                                                         const uint32_t* __restrict__ ent,
                                                         const float* __restrict__ gain, DevState s)
 {
-    __shared__ uint32_t lists[256 / LPP * STEP_LIST];
+    __shared__ uint32_t stage[step_stage_words<LPP>()];
     __shared__ float4 crl[TLDS ? STEP_CR_LDS : 1];
     const float4* cr = stage_segments<TLDS>(m, crl);
-    uint32_t* list = lists + (threadIdx.x / LPP) * STEP_LIST;
+    uint32_t* seg = stage_segment<LPP>(stage);
     const long long P = sh.P;
     Lane L = lane_setup<LPP>(m, s, P, off, gain, true);
     if (MERGE && L.member) merge_lane(s, P, p, L.pix, L.sub, L.q);
     float sz, shh[KM], shp[KM];
-    accumulate<LPP>(m, cr, L.q, L.live ? s.b[L.pix] : 1.f, L.live ? L.G : 1.f, ent, L.e0, L.e1, L.sub, list, sz, shh, shp);
+    accumulate<LPP>(m, cr, L.q, L.live ? s.b[L.pix] : 1.f, L.live ? L.G : 1.f, ent, L.e0, L.e1, L.sub, seg, sz, shh, shp);
     reduce_lanes<LPP>(sz, shh, shp);
     float Sv[KM], Spv[KM];
     s_eval_points<LPP>(m, L.q, L.sub, Sv, Spv);
@@ -322,16 +338,16 @@ __global__ __launch_bounds__(256) void k_bg_step(DevModel m, DevParams p, Shape 
                                                  const uint32_t* __restrict__ ent,
                                                  const float* __restrict__ gain, DevState s, float* bdst)
 {
-    __shared__ uint32_t lists[256 / LPP * STEP_LIST];
+    __shared__ uint32_t stage[step_stage_words<LPP>()];
     __shared__ float4 crl[TLDS ? STEP_CR_LDS : 1];
     const float4* cr = stage_segments<TLDS>(m, crl);
-    uint32_t* list = lists + (threadIdx.x / LPP) * STEP_LIST;
+    uint32_t* seg = stage_segment<LPP>(stage);
     const long long P = sh.P;
     const Lane L = lane_setup<LPP>(m, s, P, off, gain, false);
     const float braw = L.pix < P ? s.b[L.pix] : 1.f;
     const float bb = L.live ? braw : 1.f;
     float sz, shh[KM], shp[KM];
-    accumulate<LPP>(m, cr, L.q, bb, L.live ? L.G : 1.f, ent, L.e0, L.e1, L.sub, list, sz, shh, shp);
+    accumulate<LPP>(m, cr, L.q, bb, L.live ? L.G : 1.f, ent, L.e0, L.e1, L.sub, seg, sz, shh, shp);
     reduce_lanes<LPP>(sz, shh, shp);
     if (!L.member || L.sub != 0) return;
     if (!L.live) {
@@ -348,14 +364,14 @@ __global__ __launch_bounds__(256) void k_gradients(DevModel m, Shape sh, const u
                                                    float* __restrict__ gt, float* __restrict__ gr,
                                                    float* __restrict__ gb)
 {
-    __shared__ uint32_t lists[256 / LPP * STEP_LIST];
+    __shared__ uint32_t stage[step_stage_words<LPP>()];
     __shared__ float4 crl[TLDS ? STEP_CR_LDS : 1];
     const float4* cr = stage_segments<TLDS>(m, crl);
-    uint32_t* list = lists + (threadIdx.x / LPP) * STEP_LIST;
+    uint32_t* seg = stage_segment<LPP>(stage);
     const long long P = sh.P;
     const Lane L = lane_setup<LPP>(m, s, P, off, gain, false);
     float sz, shh[KM], shp[KM];
-    accumulate<LPP>(m, cr, L.q, L.live ? s.b[L.pix] : 1.f, L.live ? L.G : 1.f, ent, L.e0, L.e1, L.sub, list, sz, shh, shp);
+    accumulate<LPP>(m, cr, L.q, L.live ? s.b[L.pix] : 1.f, L.live ? L.G : 1.f, ent, L.e0, L.e1, L.sub, seg, sz, shh, shp);
     reduce_lanes<LPP>(sz, shh, shp);
     float Sv[KM], Spv[KM];
     s_eval_points<LPP>(m, L.q, L.sub, Sv, Spv);

@@ -377,8 +377,13 @@ struct PixPoints {
     double t[KM];
 };
 
+// Anchor of a slot at or beyond the count: far below every bin, so that no
+// IRF support reaches any entry.
+constexpr int PT_ABSENT = -(1 << 28);
+
 // Every slot is read whatever the count (the state holds KM slots per pixel),
-// so that no load waits on another; slots at or beyond the count are zeroed.
+// so that no load waits on another; slots at or beyond the count hold t = 0,
+// r = 0 and the anchor PT_ABSENT.
 __device__ __forceinline__ void load_points(const DevState& s, long long P, long long pix, PixPoints& q)
 {
     double tv[KM];
@@ -395,7 +400,7 @@ __device__ __forceinline__ void load_points(const DevState& s, long long P, long
         const double t = on ? tv[k] : 0.0;
         const double fl = floor(t);
         q.t[k] = t;
-        q.a[k] = (int)fl;
+        q.a[k] = on ? (int)fl : PT_ABSENT;
         q.f[k] = (float)(t - fl);
         q.r[k] = on ? rv[k] : 0.f;
     }
