@@ -66,8 +66,7 @@ __device__ __forceinline__ int wave_max_count(int c)
 // h_k is zero outside bins floor(t_k) - o .. floor(t_k) - o + L (the
 // segments' domain), so an entry in none of these ranges has lambda = g b and
 // only adds z / (g b) to sz; those photons are summed as integers and added
-// once.  The
-// pixel's LPP lanes load its entries STEP_LIST at a time, entry
+// once.  The pixel's LPP lanes load its entries STEP_LIST at a time, entry
 // e0p + sub + LPP u to lane sub; each lane writes the entries of its batch
 // that lie in some point's support to its own LDS segment and evaluates them
 // itself, so the work of a wavefront is the largest count of such entries on
@@ -91,7 +90,7 @@ __device__ __forceinline__ void accumulate_n(const DevModel& m, const float4* cr
             const uint32_t x = eb + sub + u * LPP;
             v[u] = x < e1 ? ent[x] : 0u;
         }
-        int n = 0;
+        uint32_t* wp = seg;
 #pragma unroll
         for (int u = 0; u < STEP_BATCH; ++u) {
             const int tbo = ent_bin(v[u]) + m.o;
@@ -99,13 +98,13 @@ __device__ __forceinline__ void accumulate_n(const DevModel& m, const float4* cr
 #pragma unroll
             for (int k = 0; k < NPT; ++k) in = in || (uint32_t)(tbo - q.a[k]) <= (uint32_t)m.L;
             in = in && eb + sub + u * LPP < e1;
-            seg[n * 64] = v[u];                           // kept only when it lies in a support
-            n += in ? 1 : 0;
+            *wp = v[u];                                   // kept only when it lies in a support
+            wp += in ? 64 : 0;
             zout += in ? 0u : (uint32_t)ent_cnt(v[u]);    // zero where not valid
         }
         if (NPT == 0) continue;
-        for (int j = 0; j < n; ++j) {
-            const uint32_t v1 = seg[j * 64];
+        for (const uint32_t* rp = seg; rp < wp; rp += 64) {
+            const uint32_t v1 = *rp;
             const int tb = ent_bin(v1);
             const float z = (float)ent_cnt(v1);
             float h[KM], hp[KM];
@@ -241,8 +240,10 @@ __device__ __forceinline__ Lane lane_setup(const DevModel& m, const DevState& s,
     return L;
 }
 
+// Seven workgroups per CU (at most 72 VGPRs; the few values the compiler then
+// keeps in scratch are written before the entry loop and read after it).
 template <int LPP, bool TLDS>
-__global__ __launch_bounds__(256) void k_depth_step(DevModel m, DevParams p, Shape sh,
+__global__ __launch_bounds__(256, 7) void k_depth_step(DevModel m, DevParams p, Shape sh,
                                                     const uint32_t* __restrict__ off,
                                                     const uint32_t* __restrict__ ent,
                                                     const float* __restrict__ gain, DevState s)
@@ -254,11 +255,11 @@ __global__ __launch_bounds__(256) void k_depth_step(DevModel m, DevParams p, Sha
     const long long P = sh.P;
     const Lane L = lane_setup<LPP>(m, s, P, off, gain, true);
     float sz, shh[KM], shp[KM];
-    // S' first: its table reads do not wait for the entries
-    float Sv[KM], Spv[KM];
-    s_eval_points<LPP>(m, L.q, L.sub, Sv, Spv);
     accumulate<LPP>(m, cr, L.q, L.live ? s.b[L.pix] : 1.f, L.live ? L.G : 1.f, ent, L.e0, L.e1, L.sub, seg, sz, shh, shp);
     reduce_lanes<LPP>(sz, shh, shp);
+    // S' after the entries: nothing of it stays live across the entry loop
+    float Sv[KM], Spv[KM];
+    s_eval_points<LPP>(m, L.q, L.sub, Sv, Spv);
     if (!L.live || L.sub != 0) return;
 #pragma unroll
     for (int k = 0; k < KM; ++k)
