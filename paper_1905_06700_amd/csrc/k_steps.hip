@@ -75,61 +75,114 @@ __device__ __forceinline__ int wave_max_count(int c)
 // have r = 0 and an anchor no entry's bin reaches, so they neither select
 // entries nor change lambda, and a lane's sums do not depend on the other
 // pixels of its wavefront.
-template <int LPP, int NPT>
-__device__ __forceinline__ void accumulate_n(const DevModel& m, const float4* cr, const PixPoints& q, float bb,
-                                             float invG, const uint32_t* __restrict__ ent, uint32_t e0p,
-                                             uint32_t e1, int sub, uint32_t* seg, float& sz, float (&sh)[KM],
+// Entries the buffer loads address (byte offsets below 2^31, so that an entry
+// past a pixel's end can be given an offset past every record).
+constexpr uint32_t STEP_BUF_ENTRIES = 1u << 29;
+
+// One batch of SB entries per lane from eb: load, select the entries inside
+// some point's support into the lane's LDS segment, evaluate them.  BUF: the
+// loads are buffer loads (an entry past the pixel's end reads 0 from an
+// out-of-range offset), else global loads under the same condition.
+template <int LPP, int NPT, int SB, bool BUF>
+__device__ __forceinline__ void step_batch_n(const DevModel& m, const float4* cr, const PixPoints& q, float bb,
+                                             float invG, const uint32_t* __restrict__ ent,
+                                             __amdgpu_buffer_rsrc_t rsrc, uint32_t eb, uint32_t e1, int sub,
+                                             uint32_t* seg, uint32_t& zout, float& sz, float (&sh)[KM],
                                              float (&shp)[KM])
 {
-    constexpr int STEP_BATCH = step_batch<LPP>();
-    uint32_t zout = 0;                                    // photons of this lane's entries outside every support
-    for (uint32_t eb = e0p; eb < e1; eb += STEP_LIST) {    // the same trip count on the pixel's lanes
-        uint32_t v[STEP_BATCH];
+    const uint32_t rem = e1 - eb;
+    // this lane's entries of the batch: u < nv
+    const int nv = (uint32_t)sub < rem ? (int)min((rem - (uint32_t)sub + LPP - 1) / LPP, (uint32_t)SB) : 0;
+    uint32_t v[SB];
+    if (BUF) {
+        const uint32_t b4 = (eb + (uint32_t)sub) * 4u;
 #pragma unroll
-        for (int u = 0; u < STEP_BATCH; ++u) {
+        for (int u = 0; u < SB; ++u) {
+            const uint32_t o4 = u < nv ? b4 : 0x80000000u;
+            v[u] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rsrc, o4, u * LPP * 4, 0);
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
             const uint32_t x = eb + sub + u * LPP;
             v[u] = x < e1 ? ent[x] : 0u;
         }
-        uint32_t* wp = seg;
+    }
+    uint32_t* wp = seg;
 #pragma unroll
-        for (int u = 0; u < STEP_BATCH; ++u) {
-            const int tbo = ent_bin(v[u]) + m.o;
-            bool in = false;
+    for (int u = 0; u < SB; ++u) {
+        const int tbo = ent_bin(v[u]) + m.o;
+        bool in = false;
 #pragma unroll
-            for (int k = 0; k < NPT; ++k) in = in || (uint32_t)(tbo - q.a[k]) <= (uint32_t)m.L;
-            in = in && eb + sub + u * LPP < e1;
-            *wp = v[u];                                   // kept only when it lies in a support
-            wp += in ? 64 : 0;
-            zout += in ? 0u : (uint32_t)ent_cnt(v[u]);    // zero where not valid
+        for (int k = 0; k < NPT; ++k) in = in || (uint32_t)(tbo - q.a[k]) <= (uint32_t)m.L;
+        in = in && u < nv;
+        *wp = v[u];                                       // kept only when it lies in a support
+        wp += in ? 64 : 0;
+        zout += in ? 0u : (uint32_t)ent_cnt(v[u]);        // zero where not valid
+    }
+    if (NPT == 0) return;
+    for (const uint32_t* rp = seg; rp < wp; rp += 64) {
+        const uint32_t v1 = *rp;
+        const int tb = ent_bin(v1);
+        const float z = (float)ent_cnt(v1);
+        float h[KM], hp[KM];
+        float lam = bb;
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            irf_eval_t(cr, m.L, m.o, tb, q.a[k], q.f[k], h[k], hp[k]);
+            lam = fmaf(q.r[k], h[k], lam);
         }
-        if (NPT == 0) continue;
-        for (const uint32_t* rp = seg; rp < wp; rp += 64) {
-            const uint32_t v1 = *rp;
-            const int tb = ent_bin(v1);
-            const float z = (float)ent_cnt(v1);
-            float h[KM], hp[KM];
-            float lam = bb;
+        const float zl = z * invG * __builtin_amdgcn_rcpf(lam);
+        sz += zl;
 #pragma unroll
-            for (int k = 0; k < NPT; ++k) {
-                irf_eval_t(cr, m.L, m.o, tb, q.a[k], q.f[k], h[k], hp[k]);
-                lam = fmaf(q.r[k], h[k], lam);
-            }
-            const float zl = z * invG * __builtin_amdgcn_rcpf(lam);
-            sz += zl;
-#pragma unroll
-            for (int k = 0; k < NPT; ++k) {
-                sh[k] = fmaf(zl, h[k], sh[k]);
-                shp[k] = fmaf(zl, hp[k], shp[k]);
-            }
+        for (int k = 0; k < NPT; ++k) {
+            sh[k] = fmaf(zl, h[k], sh[k]);
+            shp[k] = fmaf(zl, hp[k], shp[k]);
         }
     }
+}
+
+// The first STEP_LIST entries of a pixel form one batch, later ones batches
+// of STEP_LIST / 2 (a wavefront's later batches are short, and a batch costs
+// its full width on every lane).
+template <int LPP, int NPT, bool BUF>
+__device__ __forceinline__ void accumulate_n(const DevModel& m, const float4* cr, const PixPoints& q, float bb,
+                                             float invG, const uint32_t* __restrict__ ent, uint32_t etot,
+                                             uint32_t e0p, uint32_t e1, int sub, uint32_t* seg, float& sz,
+                                             float (&sh)[KM], float (&shp)[KM])
+{
+    constexpr int SB = step_batch<LPP>();
+    const __amdgpu_buffer_rsrc_t rsrc =
+        __builtin_amdgcn_make_buffer_rsrc((void*)ent, (short)0, BUF ? (int)(etot * 4u) : 0, 0x00020000);
+    uint32_t zout = 0;                                    // photons of this lane's entries outside every support
+    if (e0p < e1)
+        step_batch_n<LPP, NPT, SB, BUF>(m, cr, q, bb, invG, ent, rsrc, e0p, e1, sub, seg, zout, sz, sh, shp);
+    for (uint32_t eb = e0p + STEP_LIST; eb < e1; eb += STEP_LIST / 2)
+        step_batch_n<LPP, NPT, SB / 2, BUF>(m, cr, q, bb, invG, ent, rsrc, eb, e1, sub, seg, zout, sz, sh, shp);
     sz += (float)zout * invG * __builtin_amdgcn_rcpf(bb);
 }
 
+template <int LPP, bool BUF>
+__device__ __forceinline__ void accumulate_b(const DevModel& m, const float4* cr, const PixPoints& q, float bb,
+                                             float invG, const uint32_t* __restrict__ ent, uint32_t etot,
+                                             uint32_t e0p, uint32_t e1, int sub, uint32_t* seg, float& sz,
+                                             float (&sh)[KM], float (&shp)[KM])
+{
+    switch (wave_max_count(q.c)) {
+    case 0: accumulate_n<LPP, 0, BUF>(m, cr, q, bb, invG, ent, etot, e0p, e1, sub, seg, sz, sh, shp); break;
+    case 1: accumulate_n<LPP, 1, BUF>(m, cr, q, bb, invG, ent, etot, e0p, e1, sub, seg, sz, sh, shp); break;
+    case 2: accumulate_n<LPP, 2, BUF>(m, cr, q, bb, invG, ent, etot, e0p, e1, sub, seg, sz, sh, shp); break;
+    case 3: accumulate_n<LPP, 3, BUF>(m, cr, q, bb, invG, ent, etot, e0p, e1, sub, seg, sz, sh, shp); break;
+    default: accumulate_n<LPP, KM, BUF>(m, cr, q, bb, invG, ent, etot, e0p, e1, sub, seg, sz, sh, shp); break;
+    }
+}
+
+// etot: the entry count of all pixels (off[P], the same on every lane).
 template <int LPP>
 __device__ __forceinline__ void accumulate(const DevModel& m, const float4* cr, const PixPoints& q, float bb,
-                                           float G, const uint32_t* __restrict__ ent, uint32_t e0p, uint32_t e1,
-                                           int sub, uint32_t* seg, float& sz, float (&sh)[KM], float (&shp)[KM])
+                                           float G, const uint32_t* __restrict__ ent, uint32_t etot, uint32_t e0p,
+                                           uint32_t e1, int sub, uint32_t* seg, float& sz, float (&sh)[KM],
+                                           float (&shp)[KM])
 {
     sz = 0.f;
 #pragma unroll
@@ -138,13 +191,10 @@ __device__ __forceinline__ void accumulate(const DevModel& m, const float4* cr, 
         shp[k] = 0.f;
     }
     const float invG = 1.f / G;
-    switch (wave_max_count(q.c)) {
-    case 0: accumulate_n<LPP, 0>(m, cr, q, bb, invG, ent, e0p, e1, sub, seg, sz, sh, shp); break;
-    case 1: accumulate_n<LPP, 1>(m, cr, q, bb, invG, ent, e0p, e1, sub, seg, sz, sh, shp); break;
-    case 2: accumulate_n<LPP, 2>(m, cr, q, bb, invG, ent, e0p, e1, sub, seg, sz, sh, shp); break;
-    case 3: accumulate_n<LPP, 3>(m, cr, q, bb, invG, ent, e0p, e1, sub, seg, sz, sh, shp); break;
-    default: accumulate_n<LPP, KM>(m, cr, q, bb, invG, ent, e0p, e1, sub, seg, sz, sh, shp); break;
-    }
+    if (etot <= STEP_BUF_ENTRIES)
+        accumulate_b<LPP, true>(m, cr, q, bb, invG, ent, etot, e0p, e1, sub, seg, sz, sh, shp);
+    else
+        accumulate_b<LPP, false>(m, cr, q, bb, invG, ent, etot, e0p, e1, sub, seg, sz, sh, shp);
 }
 
 // Sums the partials of the LPP lanes of a pixel (every lane ends with the total).
@@ -208,6 +258,7 @@ struct Lane {
     float G;
     PixPoints q;
     uint32_t e0, e1;   // the pixel's entries
+    uint32_t etot;     // entries of all pixels (the same on every lane)
 };
 
 template <int LPP>
@@ -230,6 +281,7 @@ __device__ __forceinline__ Lane lane_setup(const DevModel& m, const DevState& s,
     L.live = L.member;
     const long long pp = L.live ? L.pix : 0;
     const uint32_t e0 = off[pp], e1 = off[pp + 1];
+    L.etot = __builtin_amdgcn_readfirstlane(off[P]);
     L.G = L.live ? gain_at(gain, pp) : 0.f;
     load_points(s, P, pp, L.q);
     if (!L.live) L.q.c = 0;
@@ -255,7 +307,7 @@ __global__ __launch_bounds__(256, 7) void k_depth_step(DevModel m, DevParams p, 
     const long long P = sh.P;
     const Lane L = lane_setup<LPP>(m, s, P, off, gain, true);
     float sz, shh[KM], shp[KM];
-    accumulate<LPP>(m, cr, L.q, L.live ? s.b[L.pix] : 1.f, L.live ? L.G : 1.f, ent, L.e0, L.e1, L.sub, seg, sz, shh, shp);
+    accumulate<LPP>(m, cr, L.q, L.live ? s.b[L.pix] : 1.f, L.live ? L.G : 1.f, ent, L.etot, L.e0, L.e1, L.sub, seg, sz, shh, shp);
     reduce_lanes<LPP>(sz, shh, shp);
     // S' after the entries: nothing of it stays live across the entry loop
     float Sv[KM], Spv[KM];
@@ -308,7 +360,7 @@ __device__ __forceinline__ void merge_lane(const DevState& s, long long P, const
 // MERGE: the in-pixel merge runs first (the loop's order: merge, then the
 // intensity step on the merged points).
 template <int LPP, bool MERGE, bool TLDS>
-__global__ __launch_bounds__(256) void k_intensity_step(DevModel m, DevParams p, Shape sh,
+__global__ __launch_bounds__(256, 7) void k_intensity_step(DevModel m, DevParams p, Shape sh,
                                                         const uint32_t* __restrict__ off,
                                                         const uint32_t* __restrict__ ent,
                                                         const float* __restrict__ gain, DevState s)
@@ -321,7 +373,7 @@ __global__ __launch_bounds__(256) void k_intensity_step(DevModel m, DevParams p,
     Lane L = lane_setup<LPP>(m, s, P, off, gain, true);
     if (MERGE && L.member) merge_lane(s, P, p, L.pix, L.sub, L.q);
     float sz, shh[KM], shp[KM];
-    accumulate<LPP>(m, cr, L.q, L.live ? s.b[L.pix] : 1.f, L.live ? L.G : 1.f, ent, L.e0, L.e1, L.sub, seg, sz, shh, shp);
+    accumulate<LPP>(m, cr, L.q, L.live ? s.b[L.pix] : 1.f, L.live ? L.G : 1.f, ent, L.etot, L.e0, L.e1, L.sub, seg, sz, shh, shp);
     reduce_lanes<LPP>(sz, shh, shp);
     float Sv[KM], Spv[KM];
     s_eval_points<LPP>(m, L.q, L.sub, Sv, Spv);
@@ -348,7 +400,7 @@ __global__ __launch_bounds__(256) void k_bg_step(DevModel m, DevParams p, Shape 
     const float braw = L.pix < P ? s.b[L.pix] : 1.f;
     const float bb = L.live ? braw : 1.f;
     float sz, shh[KM], shp[KM];
-    accumulate<LPP>(m, cr, L.q, bb, L.live ? L.G : 1.f, ent, L.e0, L.e1, L.sub, seg, sz, shh, shp);
+    accumulate<LPP>(m, cr, L.q, bb, L.live ? L.G : 1.f, ent, L.etot, L.e0, L.e1, L.sub, seg, sz, shh, shp);
     reduce_lanes<LPP>(sz, shh, shp);
     if (!L.member || L.sub != 0) return;
     if (!L.live) {
@@ -372,7 +424,7 @@ __global__ __launch_bounds__(256) void k_gradients(DevModel m, Shape sh, const u
     const long long P = sh.P;
     const Lane L = lane_setup<LPP>(m, s, P, off, gain, false);
     float sz, shh[KM], shp[KM];
-    accumulate<LPP>(m, cr, L.q, L.live ? s.b[L.pix] : 1.f, L.live ? L.G : 1.f, ent, L.e0, L.e1, L.sub, seg, sz, shh, shp);
+    accumulate<LPP>(m, cr, L.q, L.live ? s.b[L.pix] : 1.f, L.live ? L.G : 1.f, ent, L.etot, L.e0, L.e1, L.sub, seg, sz, shh, shp);
     reduce_lanes<LPP>(sz, shh, shp);
     float Sv[KM], Spv[KM];
     s_eval_points<LPP>(m, L.q, L.sub, Sv, Spv);
