@@ -122,6 +122,21 @@ constexpr int INIT_EPL = (INIT_ELDS + 63) / 64;   // pooled entries per lane
 // HBM; larger pools take the HBM path.
 constexpr int INIT_WIDE_ELDS = 1536;
 constexpr unsigned INIT_WIDE_GRID = 1024;
+
+// The list of those pixels: INIT_LIST_SEGS counters INIT_LIST_STRIDE words
+// apart (separate cache lines, so that appends from many wavefronts do not
+// queue on one address), then one segment of init_list_cap(P) pixels per
+// counter; workgroup b of the main kernel appends to segment b mod
+// INIT_LIST_SEGS, which holds at most init_list_cap(P) of its pixels.
+constexpr int INIT_LIST_SEGS = 64;      // one per lane of the wide kernel's segment scan
+constexpr int INIT_LIST_STRIDE = 64;
+constexpr size_t INIT_LIST_HDR = (size_t)INIT_LIST_SEGS * INIT_LIST_STRIDE;
+
+__host__ __device__ inline size_t init_list_cap(long long P)
+{
+    const long long nblk = (P + INIT_WAVES - 1) / INIT_WAVES;
+    return (size_t)((nblk + INIT_LIST_SEGS - 1) / INIT_LIST_SEGS) * INIT_WAVES;
+}
 constexpr int INIT_QLDS = 4096;   // IRF weight tables (ints) up to this size are staged in LDS
 constexpr int INIT_QPAD = 96;     // zero weights on either side of the staged IRF weights (at least 94)
 constexpr int INIT_BWS = 5;       // the LDS path buckets photons by 2^INIT_BWS bins
@@ -637,7 +652,11 @@ __device__ __forceinline__ void init_pixel(const DevModel& m, const DevParams& p
     const int nbs = (T + INIT_SB - 1) / INIT_SB;
     const bool ldsok = QL && nbs <= INIT_NB_LDS && qmax < (1 << 24);
     if (!WIDE && wide && ldsok && total > INIT_ELDS && total <= INIT_WIDE_ELDS) {
-        if (lane == 0) wide[1 + atomicAdd(&wide[0], 1u)] = (uint32_t)pix;
+        if (lane == 0) {
+            const unsigned sg = blockIdx.x % INIT_LIST_SEGS;
+            wide[INIT_LIST_HDR + sg * init_list_cap(sh.P) + atomicAdd(&wide[sg * INIT_LIST_STRIDE], 1u)] =
+                (uint32_t)pix;
+        }
         return;
     }
     constexpr int ELDS = WIDE ? INIT_WIDE_ELDS : INIT_ELDS;
@@ -956,7 +975,7 @@ __device__ __forceinline__ void init_pixel(const DevModel& m, const DevParams& p
 }
 
 // QL: the IRF weight tables are staged in LDS (they fit INIT_QLDS ints).
-// wide: list of pixels left for k_init_wide (count first), or null.
+// wide: list of pixels left for k_init_wide (segment counters first), or null.
 template <bool QL>
 __global__ __launch_bounds__(64 * INIT_WAVES, 7) void k_init(DevModel m, DevParams p, Shape sh,
                                                           const uint32_t* __restrict__ off,
@@ -985,22 +1004,34 @@ __global__ __launch_bounds__(64 * INIT_WAVES) void k_init_wide(DevModel m, DevPa
                                                                const uint32_t* __restrict__ wide)
 {
     extern __shared__ unsigned long long smem64[];
-    const uint32_t n = wide[0];
+    // listed pixel k lies in the segment whose inclusive count prefix (lane
+    // s: segment s) first exceeds k
+    const int lane = threadIdx.x & 63;
+    const uint32_t cs = wide[lane * INIT_LIST_STRIDE];
+    const uint32_t incl = wave_incl_scan(cs);
+    const uint32_t n = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
     if ((size_t)blockIdx.x * INIT_WAVES >= n) return;                 // whole workgroup
+    const size_t cap = init_list_cap(sh.P);
     const int wv = threadIdx.x >> 6;
     const size_t ww = init_wave_words(m.T, m.L, m.o, p.r_init, INIT_WIDE_ELDS);
     int* qs = reinterpret_cast<int*>(smem64 + INIT_WAVES * ww);
     int* Mz = qs + q_staged_ints(m.L);
     const int qmax = stage_weights<true>(m, qs, Mz);
-    for (size_t k = (size_t)blockIdx.x * INIT_WAVES + wv; k < n; k += (size_t)gridDim.x * INIT_WAVES)
-        init_pixel<true, true>(m, p, sh, off, ent, gain, s, (long long)wide[1 + k], smem64 + (size_t)wv * ww, qs,
-                               Mz, qmax, nullptr);
+    for (uint32_t k = blockIdx.x * INIT_WAVES + wv; k < n; k += gridDim.x * INIT_WAVES) {
+        const int sg = __popcll(__builtin_amdgcn_ballot_w64(incl <= k));
+        const uint32_t at = k - (uint32_t)__builtin_amdgcn_readlane((int)(incl - cs), sg);
+        init_pixel<true, true>(m, p, sh, off, ent, gain, s, (long long)wide[INIT_LIST_HDR + sg * cap + at],
+                               smem64 + (size_t)wv * ww, qs, Mz, qmax, nullptr);
+    }
 }
 
 __global__ void k_init_reset(uint32_t* wide)
 {
-    if (threadIdx.x == 0) wide[0] = 0u;
+    if (threadIdx.x < INIT_LIST_SEGS) wide[threadIdx.x * INIT_LIST_STRIDE] = 0u;
 }
+
+// Words of the list for P pixels.
+size_t init_list_words(long long P) { return INIT_LIST_HDR + INIT_LIST_SEGS * init_list_cap(P); }
 
 // Initial normals (reading): weighted least-squares plane Z = a + c1 X + c2 Y
 // over the APSS neighbourhood in FP64, local coordinates; n = (c1, c2, -1)/|.|,

@@ -18,6 +18,7 @@
 
 namespace rt3d {
 size_t init_lds_bytes(int T, int L, int o, int r_init, bool wide = false);
+size_t init_list_words(long long P);
 }
 
 using namespace rt3d;
@@ -93,7 +94,7 @@ struct Workspace {
     uint32_t* stage;
     uint32_t* cls_list;                // per-class pixel lists (per-pixel IRFs)
     uint32_t* cls_meta;
-    uint32_t* wide;                    // the init's list of pixels with large pools (count first)
+    uint32_t* wide;                    // the init's list of pixels with large pools (segment counters first)
     DevState A, B;
     float* btmp;
     CnnBuffers cnn;
@@ -122,7 +123,7 @@ Workspace carve(uint8_t* base, long long P, long long Ps, uint64_t E, bool with_
     w.stage = (uint32_t*)take(sizeof(uint32_t) * CP_STAGE * std::max<long long>(P, 1));
     w.cls_list = (uint32_t*)take(sizeof(uint32_t) * std::max<long long>(P, 1));
     w.cls_meta = (uint32_t*)take(sizeof(uint32_t) * CLASS_META);
-    w.wide = (uint32_t*)take(sizeof(uint32_t) * (P + 1));
+    w.wide = (uint32_t*)take(sizeof(uint32_t) * init_list_words(P));
     for (DevState* s : {&w.A, &w.B}) {
         s->t = (double*)take(sizeof(double) * KM * Ps);
         s->r = (float*)take(sizeof(float) * KM * Ps);
