@@ -121,7 +121,7 @@ constexpr int INIT_EPL = (INIT_ELDS + 63) / 64;   // pooled entries per lane
 // scored from LDS by a second kernel that stages their photons in passes over
 // HBM; larger pools take the HBM path.
 constexpr int INIT_WIDE_ELDS = 1536;
-constexpr unsigned INIT_WIDE_GRID = 1024;
+constexpr unsigned INIT_WIDE_GRID = 2048;
 
 // The list of those pixels: INIT_LIST_SEGS counters INIT_LIST_STRIDE words
 // apart (separate cache lines, so that appends from many wavefronts do not
