@@ -27,8 +27,9 @@ constexpr int IFT = TILE;
 constexpr int IFS = IFT + 2;
 
 // PERSP: world distances of the pinhole camera (t dz along each pixel's ray).
+// The orthographic variant fits 72 VGPRs: seven workgroups per CU.
 template <bool PERSP>
-__global__ __launch_bounds__(IFT * IFT) void k_ifilter_tile(DevParams p, Tiles tg, DevState in, DevState out)
+__global__ __launch_bounds__(IFT * IFT, PERSP ? 1 : 6) void k_ifilter_tile(DevParams p, Tiles tg, DevState in, DevState out)
 {
     __shared__ double tl[KM][IFS * IFS];
     __shared__ float rl[KM][IFS * IFS];
@@ -59,11 +60,21 @@ __global__ __launch_bounds__(IFT * IFT) void k_ifilter_tile(DevParams p, Tiles t
         }
         cl[x] = c;
     }
-    __syncthreads();
+    // the pixel's normals and background, loaded with the tile (the output
+    // loop would otherwise wait on them once per kept point; the pinhole
+    // variant, short of registers, reads the normals there)
     const int ty = threadIdx.x / IFT, tx = threadIdx.x % IFT;
     const int i = i0 + ty, j = j0 + tx;
-    if (i >= sh.rows || j >= sh.cols) return;
-    const long long pix = fbase + (long long)i * sh.cols + j;
+    const bool inside = i < sh.rows && j < sh.cols;
+    const long long pix = fbase + (long long)(inside ? i : 0) * sh.cols + (inside ? j : 0);
+    float nq[3][KM];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int k = 0; k < KM; ++k) nq[a][k] = !PERSP && inside ? in.n[(a * KM + k) * S + pix] : 0.f;
+    const float bq = inside ? in.b[pix] : 0.f;
+    __syncthreads();
+    if (!inside) return;
     const int xc = (ty + 1) * IFS + tx + 1;
     const int c = cl[xc];
     const float hi2 = (float)(p.h_int * p.h_int);
@@ -120,7 +131,12 @@ __global__ __launch_bounds__(IFT * IFT) void k_ifilter_tile(DevParams p, Tiles t
         out.t[nk * S + pix] = tq;
         out.r[nk * S + pix] = rn;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) out.n[(a * KM + nk) * S + pix] = in.n[(a * KM + k) * S + pix];
+        for (int a = 0; a < 3; ++a) {
+            float v = nq[a][0];
+#pragma unroll
+            for (int k2 = 1; k2 < KM; ++k2) v = k == k2 ? nq[a][k2] : v;
+            out.n[(a * KM + nk) * S + pix] = PERSP ? in.n[(a * KM + k) * S + pix] : v;
+        }
         ++nk;
     }
     for (int k = nk; k < KM; ++k) {
@@ -131,7 +147,7 @@ __global__ __launch_bounds__(IFT * IFT) void k_ifilter_tile(DevParams p, Tiles t
         out.n[(2 * KM + k) * S + pix] = -1.f;
     }
     out.cnt[pix] = (uint8_t)nk;
-    out.b[pix] = in.b[pix];
+    out.b[pix] = bq;
 }
 
 // Row pass: tmp[f][i][j] = sum_d w[d] b[f][i][(j + d) mod cols].
