@@ -27,7 +27,7 @@ constexpr int IFT = TILE;
 constexpr int IFS = IFT + 2;
 
 // PERSP: world distances of the pinhole camera (t dz along each pixel's ray).
-// The orthographic variant fits 72 VGPRs: seven workgroups per CU.
+// The orthographic variant fits 74 VGPRs: six workgroups per CU.
 template <bool PERSP>
 __global__ __launch_bounds__(IFT * IFT, PERSP ? 1 : 6) void k_ifilter_tile(DevParams p, Tiles tg, DevState in, DevState out)
 {
@@ -60,9 +60,13 @@ __global__ __launch_bounds__(IFT * IFT, PERSP ? 1 : 6) void k_ifilter_tile(DevPa
         }
         cl[x] = c;
     }
-    // the pixel's normals and background, loaded with the tile (the output
-    // loop would otherwise wait on them once per kept point; the pinhole
-    // variant, short of registers, reads the normals there)
+    // Normals and background move with their own pixel only.  In place (the
+    // iteration's planes) a kept point's normal moves only when an earlier
+    // point of the pixel was dropped, and the background stays; into another
+    // state they are copied, loaded here with the tile (the output loop would
+    // otherwise wait on them once per kept point; the pinhole variant, short
+    // of registers, reads the normals there).
+    const bool n_inplace = in.n == out.n, b_inplace = in.b == out.b;
     const int ty = threadIdx.x / IFT, tx = threadIdx.x % IFT;
     const int i = i0 + ty, j = j0 + tx;
     const bool inside = i < sh.rows && j < sh.cols;
@@ -71,8 +75,9 @@ __global__ __launch_bounds__(IFT * IFT, PERSP ? 1 : 6) void k_ifilter_tile(DevPa
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int k = 0; k < KM; ++k) nq[a][k] = !PERSP && inside ? in.n[(a * KM + k) * S + pix] : 0.f;
-    const float bq = inside ? in.b[pix] : 0.f;
+        for (int k = 0; k < KM; ++k)
+            nq[a][k] = !PERSP && !n_inplace && inside ? in.n[(a * KM + k) * S + pix] : 0.f;
+    const float bq = !b_inplace && inside ? in.b[pix] : 0.f;
     __syncthreads();
     if (!inside) return;
     const int xc = (ty + 1) * IFS + tx + 1;
@@ -130,24 +135,33 @@ __global__ __launch_bounds__(IFT * IFT, PERSP ? 1 : 6) void k_ifilter_tile(DevPa
         if (rn < rmin) continue;
         out.t[nk * S + pix] = tq;
         out.r[nk * S + pix] = rn;
+        if (n_inplace) {
+            // slot k moves down to nk < k: its reads come before any write to it
+            if (nk != k)
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            float v = nq[a][0];
+                for (int a = 0; a < 3; ++a) out.n[(a * KM + nk) * S + pix] = in.n[(a * KM + k) * S + pix];
+        } else {
 #pragma unroll
-            for (int k2 = 1; k2 < KM; ++k2) v = k == k2 ? nq[a][k2] : v;
-            out.n[(a * KM + nk) * S + pix] = PERSP ? in.n[(a * KM + k) * S + pix] : v;
+            for (int a = 0; a < 3; ++a) {
+                float v = nq[a][0];
+#pragma unroll
+                for (int k2 = 1; k2 < KM; ++k2) v = k == k2 ? nq[a][k2] : v;
+                out.n[(a * KM + nk) * S + pix] = PERSP ? in.n[(a * KM + k) * S + pix] : v;
+            }
         }
         ++nk;
     }
     for (int k = nk; k < KM; ++k) {
         out.t[k * S + pix] = 0.0;
         out.r[k * S + pix] = 0.f;
-        out.n[(0 * KM + k) * S + pix] = 0.f;
-        out.n[(1 * KM + k) * S + pix] = 0.f;
-        out.n[(2 * KM + k) * S + pix] = -1.f;
+        if (!n_inplace || k < c) {   // in place, slots past the count stay as they are
+            out.n[(0 * KM + k) * S + pix] = 0.f;
+            out.n[(1 * KM + k) * S + pix] = 0.f;
+            out.n[(2 * KM + k) * S + pix] = -1.f;
+        }
     }
     out.cnt[pix] = (uint8_t)nk;
-    out.b[pix] = bq;
+    if (!b_inplace) out.b[pix] = bq;
 }
 
 // Row pass: tmp[f][i][j] = sum_d w[d] b[f][i][(j + d) mod cols].
