@@ -151,14 +151,16 @@ __global__ __launch_bounds__(IFT * IFT, PERSP ? 1 : 6) void k_ifilter_tile(DevPa
         }
         ++nk;
     }
+    // slots past the new count: cleared where they held a point; in the
+    // iteration (normals in place) slots past the old count keep what they
+    // hold, as every reader of a slot checks the count
     for (int k = nk; k < KM; ++k) {
+        if (n_inplace && k >= c) break;
         out.t[k * S + pix] = 0.0;
         out.r[k * S + pix] = 0.f;
-        if (!n_inplace || k < c) {   // in place, slots past the count stay as they are
-            out.n[(0 * KM + k) * S + pix] = 0.f;
-            out.n[(1 * KM + k) * S + pix] = 0.f;
-            out.n[(2 * KM + k) * S + pix] = -1.f;
-        }
+        out.n[(0 * KM + k) * S + pix] = 0.f;
+        out.n[(1 * KM + k) * S + pix] = 0.f;
+        out.n[(2 * KM + k) * S + pix] = -1.f;
     }
     out.cnt[pix] = (uint8_t)nk;
     if (!b_inplace) out.b[pix] = bq;
