@@ -60,9 +60,11 @@ int apss_staged_halo(double h_apss, double p_xy, int R)
 // differences formed in FP64), no lateral pre-test, projection along the
 // query's ray; else the orthographic map, staged halo p.apss_Rs.
 // carry: also copy the count, background and intensities to `out` (else
-// `out` receives only the depths and normals of the live slots).
+// `out` receives only the depths and normals of the live slots).  The
+// orthographic variant runs five workgroups per CU (96 VGPRs; a few values
+// wait in scratch).
 template <bool PERSP>
-__global__ __launch_bounds__(ATX * ATY) void k_apss_tile(DevModel m, DevParams p, Tiles tg, DevState in,
+__global__ __launch_bounds__(ATX * ATY, PERSP ? 1 : 5) void k_apss_tile(DevModel m, DevParams p, Tiles tg, DevState in,
                                                        DevState out, int only_above, int carry)
 {
     extern __shared__ double apss_lds[];
