@@ -1045,7 +1045,7 @@ __global__ __launch_bounds__(256) void k_init_normals(DevParams p, Shape sh, Dev
     const int per_frame = sh.rows * sh.cols;
     const long long fr = pix / per_frame;
     const int i = (int)((pix / sh.cols) % sh.rows), j = (int)(pix % sh.cols);
-    const double h2 = p.h_apss * p.h_apss;
+    const double h2 = p.h_apss * p.h_apss, inv_h2 = 1.0 / h2;
     const int R = p.apss_R;
     const bool persp = p.persp > 0.0;   // pinhole camera: t dz along each pixel's ray
     double vq[3] = {0.0, 0.0, 1.0};
@@ -1074,7 +1074,7 @@ __global__ __launch_bounds__(256) void k_init_normals(DevParams p, Shape sh, Dev
                     }
                     const double d2 = x * x + y * y + z * z;
                     if (!(d2 < h2)) continue;
-                    double a = 1.0 - d2 / h2;
+                    double a = 1.0 - d2 * inv_h2;
                     a = a * a;
                     const double w = a * a;
                     M00 += w; M01 += w * x; M02 += w * y;
