@@ -135,6 +135,7 @@ hipError_t launch_scan(const uint32_t* in, uint32_t* out, long long n, uint32_t*
 // compaction
 
 constexpr int CP_WAVES = 4;   // pixels (wavefronts) per block
+constexpr int CP_VPL = 2;     // 8-bin vectors per lane per pass of the stage kernel
 
 // One pixel's histogram as 16-byte vectors of 8 bins: vector vr (0 <= vr <
 // nvec) holds bins 8 (vs + vr) .. 8 (vs + vr) + 7 of the flat array, the
@@ -216,19 +217,15 @@ __device__ __forceinline__ uint32_t bin8(const uint32_t (&w)[4], int k)
     return (k & 1) ? x >> 16 : x & 0xffffu;
 }
 
-// Count of bin k of two consecutive vectors (k < 16).
-__device__ __forceinline__ uint32_t bin16(const uint32_t (&w0)[4], const uint32_t (&w1)[4], int k)
-{
-    return k < 8 ? bin8(w0, k) : bin8(w1, k - 8);
-}
-
 // Pass 1: each pixel's histogram is read once; its non-zero bins, as entries
 // (t << 16 | z) in ascending t, go to the pixel's staging slot of CP_STAGE
 // entries (the first CP_STAGE of them when it has more; no staging when
 // `stage` is null), and its entry count to counts[p].  One wavefront per
-// pixel; each lane holds 16 consecutive bins (two vectors) and a wavefront
-// prefix sum of the lanes' non-zero counts places them; a lane writes its
-// non-zero bins one set bit of its mask at a time (most lanes hold none).
+// pixel; a pass loads CP_VPL runs of 64 consecutive 8-bin vectors (one per
+// lane each, so that every load instruction reads 1 KB in one piece), then
+// for each run a wavefront prefix sum of the lanes' non-zero counts places
+// them; a lane writes its non-zero bins one set bit of its mask at a time
+// (most lanes hold none).
 __global__ __launch_bounds__(64 * CP_WAVES) void k_compact_stage(const uint16_t* __restrict__ Z, long long P,
                                                                  int T, uint32_t* __restrict__ counts,
                                                                  uint32_t* __restrict__ stage)
@@ -239,23 +236,32 @@ __global__ __launch_bounds__(64 * CP_WAVES) void k_compact_stage(const uint16_t*
     const PixVec pv = pix_vectors(Z, p, T, P * T);
     uint32_t* slot = stage ? stage + p * CP_STAGE : nullptr;
     uint32_t run = 0;
-    for (int vb = 0; vb < pv.nvec; vb += 128) {       // uniform over the wave
-        const int vr = vb + 2 * lane;
-        uint32_t w0[4] = {0u, 0u, 0u, 0u}, w1[4] = {0u, 0u, 0u, 0u};
-        if (vr < pv.nvec) load8(pv, vr, w0);
-        if (vr + 1 < pv.nvec) load8(pv, vr + 1, w1);
-        uint32_t m = nonzero8(w0) | (nonzero8(w1) << 8);
-        const uint32_t c = (uint32_t)__builtin_popcount(m);
-        const uint32_t inc = wave_incl_scan(c);
-        uint32_t pos = run + (inc - c);
-        const uint32_t base = (uint32_t)((vr << 3) - pv.lo_off);   // bin of bit 0 (bit k: base + k)
-        while (m) {
-            const int k = __builtin_ctz(m);
-            m &= m - 1u;
-            if (slot && pos < CP_STAGE) slot[pos] = ((base + k) << 16) | bin16(w0, w1, k);
-            ++pos;
+    for (int vb = 0; vb < pv.nvec; vb += 64 * CP_VPL) {   // uniform over the wave
+        // CP_VPL vectors per lane, each load instruction 64 consecutive ones
+        uint32_t w[CP_VPL][4];
+#pragma unroll
+        for (int q = 0; q < CP_VPL; ++q) {
+            const int vr = vb + 64 * q + lane;
+            w[q][0] = w[q][1] = w[q][2] = w[q][3] = 0u;
+            if (vr < pv.nvec) load8(pv, vr, w[q]);
         }
-        run += (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
+#pragma unroll
+        for (int q = 0; q < CP_VPL; ++q) {
+            if (vb + 64 * q >= pv.nvec) break;                   // uniform
+            const int vr = vb + 64 * q + lane;
+            uint32_t m = nonzero8(w[q]);
+            const uint32_t c = (uint32_t)__builtin_popcount(m);
+            const uint32_t inc = wave_incl_scan(c);
+            uint32_t pos = run + (inc - c);
+            const uint32_t base = (uint32_t)((vr << 3) - pv.lo_off);   // bin of bit 0 (bit k: base + k)
+            while (m) {
+                const int k = __builtin_ctz(m);
+                m &= m - 1u;
+                if (slot && pos < CP_STAGE) slot[pos] = ((base + k) << 16) | bin8(w[q], k);
+                ++pos;
+            }
+            run += (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
+        }
     }
     if (lane == 0) counts[p] = run;
 }
