@@ -190,7 +190,7 @@ __device__ __forceinline__ void accumulate(const DevModel& m, const float4* cr, 
         sh[k] = 0.f;
         shp[k] = 0.f;
     }
-    const float invG = 1.f / G;
+    const float invG = __builtin_amdgcn_rcpf(G);   // 1 / g (exact for g = 1)
     if (etot <= STEP_BUF_ENTRIES)
         accumulate_b<LPP, true>(m, cr, q, bb, invG, ent, etot, e0p, e1, sub, seg, sz, sh, shp);
     else
