@@ -15,8 +15,9 @@
 // Jacobi: every query reads the state before the step.
 //
 // Mapping: a workgroup takes a tile of ATY x ATX pixels of one frame; it stages
-// the counts and the live slots of the tile with a halo in LDS (depths in
-// FP64, normals), then one thread per pixel fits and projects the pixel's
+// the counts and every slot of the tile with a halo in LDS in one round of
+// loads (depths in FP64, normals; a second round for the live slots only,
+// after the counts, cost more time than the bytes it saved), then one thread per pixel fits and projects the pixel's
 // points, accumulating the sphere moments over the window from LDS in FP32,
 // in coordinates local to the query (depth differences formed in FP64); under
 // the orthographic map the halo covers only the pixels whose lateral offset
@@ -84,30 +85,22 @@ __global__ __launch_bounds__(ATX * ATY, PERSP ? 1 : 5) void k_apss_tile(DevModel
     const int fr = tile / tpf, tr = tile % tpf;
     const int i0 = (tr / tiles_x) * ATY, j0 = (tr % tiles_x) * ATX;
     const long long fbase = (long long)fr * sh.rows * sh.cols;
-    // stage the counts and slot 0 of the tile and its halo (slot 0 without
-    // waiting for the count: almost every pixel holds a point) ...
+    // stage the counts and every slot of the tile and its halo (without
+    // waiting for the counts)
     for (int x = threadIdx.x; x < NS; x += ATX * ATY) {
         const int i2 = i0 - R + x / SX, j2 = j0 - R + x % SX;
         int c = 0;
         if (i2 >= 0 && i2 < sh.rows && j2 >= 0 && j2 < sh.cols) {
             const long long pp = fbase + (long long)i2 * sh.cols + j2;
             c = load_cnt(in.cnt, pp);
-            tl[x] = in.t[pp];
 #pragma unroll
-            for (int a = 0; a < 3; ++a) nl[a * KM * NS + x] = in.n[a * KM * S + pp];
+            for (int k = 0; k < KM; ++k) {
+                tl[k * NS + x] = in.t[k * S + pp];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) nl[(a * KM + k) * NS + x] = in.n[(a * KM + k) * S + pp];
+            }
         }
         cl[x] = c;
-    }
-    __syncthreads();
-    // ... then the other live slots only
-    for (int y = threadIdx.x; y < (KM - 1) * NS; y += ATX * ATY) {
-        const int k = 1 + y / NS, x = y - (k - 1) * NS;
-        if (k < cl[x]) {
-            const long long pp = fbase + (long long)(i0 - R + x / SX) * sh.cols + (j0 - R + x % SX);
-            tl[k * NS + x] = in.t[k * S + pp];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) nl[(a * KM + k) * NS + x] = in.n[(a * KM + k) * S + pp];
-        }
     }
     __syncthreads();
     const int ty = threadIdx.x / ATX, tx = threadIdx.x % ATX;
