@@ -1061,13 +1061,19 @@ __global__ __launch_bounds__(256) void k_init_normals(DevParams p, Shape sh, Dev
                 if (j2 < 0 || j2 >= sh.cols) continue;
                 const long long pp = (fr * sh.rows + i2) * sh.cols + j2;
                 const int cc = load_cnt(s.cnt, pp);
+                // every slot's depth without waiting for the count
+                double tn[KM];
+#pragma unroll
+                for (int k2 = 0; k2 < KM; ++k2) tn[k2] = s.t[k2 * S + pp];
                 double vn[3] = {0.0, 0.0, 1.0};
                 if (persp && cc > 0) ray_dir(p.persp, sh.rows, sh.cols, i2, j2, vn);
-                for (int k2 = 0; k2 < cc; ++k2) {
+#pragma unroll
+                for (int k2 = 0; k2 < KM; ++k2) {
+                    if (k2 >= cc) break;
                     double x = (j2 - j) * p.p_xy, y = (i2 - i) * p.p_xy;
-                    double z = (s.t[k2 * S + pp] - tq) * p.dz;
+                    double z = (tn[k2] - tq) * p.dz;
                     if (persp) {
-                        const double t2 = s.t[k2 * S + pp];
+                        const double t2 = tn[k2];
                         x = (t2 * vn[0] - tq * vq[0]) * p.dz;
                         y = (t2 * vn[1] - tq * vq[1]) * p.dz;
                         z = (t2 * vn[2] - tq * vq[2]) * p.dz;
