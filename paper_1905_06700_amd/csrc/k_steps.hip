@@ -219,15 +219,27 @@ __device__ __forceinline__ void reduce_lanes(float& sz, float (&sh)[KM], float (
 // S and S' of the pixel's points, each sum split over the pixel's LPP lanes
 // (strided segments) and combined with shuffles; every lane ends with the
 // totals.
+// The piecewise cubic's table, staged in LDS by the workgroup when it has at
+// most STEP_STAB_PIECES pieces (its reads come at the end of a wavefront's
+// work, where nothing else waits with them).
+constexpr int STEP_STAB_PIECES = 8;
+constexpr int STEP_STAB_LDS = STEP_STAB_PIECES + 1 + 4 * STEP_STAB_PIECES;
+
+__device__ __forceinline__ bool stab_staged(const DevModel& m) { return m.s_np > 0 && m.s_np <= STEP_STAB_PIECES; }
+
 template <int LPP>
-__device__ __forceinline__ void s_eval_points(const DevModel& m, const PixPoints& q, int sub, float (&S)[KM],
-                                              float (&Sp)[KM])
+__device__ __forceinline__ void s_eval_points(const DevModel& m, const PixPoints& q, int sub, const double* stl,
+                                              float (&S)[KM], float (&Sp)[KM])
 {
+    const bool staged = stab_staged(m);
 #pragma unroll
     for (int k = 0; k < KM; ++k) {
         S[k] = 0.f;
         Sp[k] = 0.f;
-        if (k < q.c) s_eval(m, q.t[k], S[k], Sp[k], sub, LPP);
+        if (k < q.c) {
+            if (staged) s_eval_tab(m, stl, q.t[k], S[k], Sp[k], sub, LPP);
+            else s_eval_tab(m, m.s_tab, q.t[k], S[k], Sp[k], sub, LPP);
+        }
     }
 #pragma unroll
     for (int k = 0; k < KM; ++k) {
@@ -240,13 +252,16 @@ __device__ __forceinline__ void s_eval_points(const DevModel& m, const PixPoints
 // workgroup's LDS when they fit (TLDS), else read from global memory.
 constexpr int STEP_CR_LDS = 256;
 
-template <bool TLDS>
-__device__ __forceinline__ const float4* stage_segments(const DevModel& m, float4* crl)
+// STAB: the kernel evaluates S and S' (the table of the piecewise cubic too).
+template <bool TLDS, bool STAB = true>
+__device__ __forceinline__ const float4* stage_segments(const DevModel& m, float4* crl, double* stl)
 {
-    if (!TLDS) return m.cr;
-    for (int i = threadIdx.x; i <= m.L; i += blockDim.x) crl[i] = m.cr[i];
+    if (STAB && stab_staged(m))
+        for (int i = threadIdx.x; i < 5 * m.s_np + 1; i += blockDim.x) stl[i] = m.s_tab[i];
+    if (TLDS)
+        for (int i = threadIdx.x; i <= m.L; i += blockDim.x) crl[i] = m.cr[i];
     __syncthreads();
-    return crl;
+    return TLDS ? crl : m.cr;
 }
 
 // Common prologue: the pixel of this lane, its points and its entry range.
@@ -302,7 +317,8 @@ __global__ __launch_bounds__(256, 7) void k_depth_step(DevModel m, DevParams p, 
 {
     __shared__ uint32_t stage[step_stage_words<LPP>()];
     __shared__ float4 crl[TLDS ? STEP_CR_LDS : 1];
-    const float4* cr = stage_segments<TLDS>(m, crl);
+    __shared__ double stl[STEP_STAB_LDS];
+    const float4* cr = stage_segments<TLDS>(m, crl, stl);
     uint32_t* seg = stage_segment<LPP>(stage);
     const long long P = sh.P;
     const Lane L = lane_setup<LPP>(m, s, P, off, gain, true);
@@ -311,7 +327,7 @@ __global__ __launch_bounds__(256, 7) void k_depth_step(DevModel m, DevParams p, 
     reduce_lanes<LPP>(sz, shh, shp);
     // S' after the entries: nothing of it stays live across the entry loop
     float Sv[KM], Spv[KM];
-    s_eval_points<LPP>(m, L.q, L.sub, Sv, Spv);
+    s_eval_points<LPP>(m, L.q, L.sub, stl, Sv, Spv);
     if (!L.live || L.sub != 0) return;
 #pragma unroll
     for (int k = 0; k < KM; ++k)
@@ -367,7 +383,8 @@ __global__ __launch_bounds__(256, 7) void k_intensity_step(DevModel m, DevParams
 {
     __shared__ uint32_t stage[step_stage_words<LPP>()];
     __shared__ float4 crl[TLDS ? STEP_CR_LDS : 1];
-    const float4* cr = stage_segments<TLDS>(m, crl);
+    __shared__ double stl[STEP_STAB_LDS];
+    const float4* cr = stage_segments<TLDS>(m, crl, stl);
     uint32_t* seg = stage_segment<LPP>(stage);
     const long long P = sh.P;
     Lane L = lane_setup<LPP>(m, s, P, off, gain, true);
@@ -376,7 +393,7 @@ __global__ __launch_bounds__(256, 7) void k_intensity_step(DevModel m, DevParams
     accumulate<LPP>(m, cr, L.q, L.live ? s.b[L.pix] : 1.f, L.live ? L.G : 1.f, ent, L.etot, L.e0, L.e1, L.sub, seg, sz, shh, shp);
     reduce_lanes<LPP>(sz, shh, shp);
     float Sv[KM], Spv[KM];
-    s_eval_points<LPP>(m, L.q, L.sub, Sv, Spv);
+    s_eval_points<LPP>(m, L.q, L.sub, stl, Sv, Spv);
     if (!L.live || L.sub != 0) return;
 #pragma unroll
     for (int k = 0; k < KM; ++k)
@@ -393,7 +410,8 @@ __global__ __launch_bounds__(256) void k_bg_step(DevModel m, DevParams p, Shape 
 {
     __shared__ uint32_t stage[step_stage_words<LPP>()];
     __shared__ float4 crl[TLDS ? STEP_CR_LDS : 1];
-    const float4* cr = stage_segments<TLDS>(m, crl);
+    __shared__ double stl[STEP_STAB_LDS];
+    const float4* cr = stage_segments<TLDS, false>(m, crl, stl);
     uint32_t* seg = stage_segment<LPP>(stage);
     const long long P = sh.P;
     const Lane L = lane_setup<LPP>(m, s, P, off, gain, false);
@@ -419,7 +437,8 @@ __global__ __launch_bounds__(256) void k_gradients(DevModel m, Shape sh, const u
 {
     __shared__ uint32_t stage[step_stage_words<LPP>()];
     __shared__ float4 crl[TLDS ? STEP_CR_LDS : 1];
-    const float4* cr = stage_segments<TLDS>(m, crl);
+    __shared__ double stl[STEP_STAB_LDS];
+    const float4* cr = stage_segments<TLDS>(m, crl, stl);
     uint32_t* seg = stage_segment<LPP>(stage);
     const long long P = sh.P;
     const Lane L = lane_setup<LPP>(m, s, P, off, gain, false);
@@ -427,7 +446,7 @@ __global__ __launch_bounds__(256) void k_gradients(DevModel m, Shape sh, const u
     accumulate<LPP>(m, cr, L.q, L.live ? s.b[L.pix] : 1.f, L.live ? L.G : 1.f, ent, L.etot, L.e0, L.e1, L.sub, seg, sz, shh, shp);
     reduce_lanes<LPP>(sz, shh, shp);
     float Sv[KM], Spv[KM];
-    s_eval_points<LPP>(m, L.q, L.sub, Sv, Spv);
+    s_eval_points<LPP>(m, L.q, L.sub, stl, Sv, Spv);
     if (!L.member || L.sub != 0) return;
     const float G = L.G;
 #pragma unroll

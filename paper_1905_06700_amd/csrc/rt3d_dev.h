@@ -211,8 +211,9 @@ __device__ __forceinline__ void irf_eval(const DevModel& m, int tb, int a, float
 // summation over the segments that fall inside [0, T).
 // Lane `part` of `parts` sums the segments k0 + part, k0 + part + parts, ...
 // (parts = 1: the whole sum).
-__device__ __forceinline__ void s_eval(const DevModel& m, double t, float& S, float& Sp, int part = 0,
-                                       int parts = 1)
+// tab: the piecewise cubic's table (m.s_tab, or a copy of it in LDS).
+__device__ __forceinline__ void s_eval_tab(const DevModel& m, const double* tab, double t, float& S, float& Sp,
+                                           int part = 0, int parts = 1)
 {
     const double fl = floor(t);
     const int a = (int)fl;
@@ -234,8 +235,8 @@ __device__ __forceinline__ void s_eval(const DevModel& m, double t, float& S, fl
             } else {
                 const double sd = (double)s;
                 int i = 0;
-                while (i + 1 < m.s_np && sd >= m.s_tab[i + 1]) ++i;
-                const double* c = m.s_tab + (m.s_np + 1) + 4 * i;
+                while (i + 1 < m.s_np && sd >= tab[i + 1]) ++i;
+                const double* c = tab + (m.s_np + 1) + 4 * i;
                 S = (float)(((c[3] * sd + c[2]) * sd + c[1]) * sd + c[0]);
                 Sp = (float)(-((3.0 * c[3] * sd + 2.0 * c[2]) * sd + c[1]));
             }
@@ -252,6 +253,12 @@ __device__ __forceinline__ void s_eval(const DevModel& m, double t, float& S, fl
     }
     S = acc;
     Sp = accp;
+}
+
+__device__ __forceinline__ void s_eval(const DevModel& m, double t, float& S, float& Sp, int part = 0,
+                                       int parts = 1)
+{
+    s_eval_tab(m, m.s_tab, t, S, Sp, part, parts);
 }
 
 __device__ __forceinline__ int ent_bin(uint32_t e) { return (int)(e >> 16); }
