@@ -61,20 +61,6 @@ __device__ __forceinline__ int wave_max_count(int c)
     return 0;
 }
 
-// Partial sums over one pixel's entries (e0p .. e1 - 1):
-// sz = sum z/lambda, sh[k] = sum z h_k/lambda, shp[k] = sum z h'_k/lambda.
-// h_k is zero outside bins floor(t_k) - o .. floor(t_k) - o + L (the
-// segments' domain), so an entry in none of these ranges has lambda = g b and
-// only adds z / (g b) to sz; those photons are summed as integers and added
-// once.  The pixel's LPP lanes load its entries STEP_LIST at a time, entry
-// e0p + sub + LPP u to lane sub; each lane writes the entries of its batch
-// that lie in some point's support to its own LDS segment and evaluates them
-// itself, so the work of a wavefront is the largest count of such entries on
-// one lane, whatever the spread of the points of its pixels.  NPT is the
-// largest point count of the wavefront; points at or beyond a lane's count
-// have r = 0 and an anchor no entry's bin reaches, so they neither select
-// entries nor change lambda, and a lane's sums do not depend on the other
-// pixels of its wavefront.
 // Entries the buffer loads address (byte offsets below 2^31, so that an entry
 // past a pixel's end can be given an offset past every record).
 constexpr uint32_t STEP_BUF_ENTRIES = 1u << 29;
@@ -142,9 +128,25 @@ __device__ __forceinline__ void step_batch_n(const DevModel& m, const float4* cr
     }
 }
 
-// The first STEP_LIST entries of a pixel form one batch, later ones batches
-// of STEP_LIST / 2 (a wavefront's later batches are short, and a batch costs
-// its full width on every lane).
+// Partial sums over one pixel's entries (e0p .. e1 - 1):
+// sz = sum z/lambda, sh[k] = sum z h_k/lambda, shp[k] = sum z h'_k/lambda.
+// h_k is zero outside bins floor(t_k) - o .. floor(t_k) - o + L (the
+// segments' domain), so an entry in none of these ranges has lambda = g b and
+// only adds z / (g b) to sz; those photons are summed as integers and added
+// once.  The pixel's LPP lanes load its entries in batches, entry
+// eb + sub + LPP u to lane sub: the first STEP_LIST entries form one batch,
+// later ones batches of STEP_LIST / 2 (a wavefront's later batches are short,
+// and a batch costs its full width on every lane).  Each lane writes the
+// entries of its batch that lie in some point's support to its own LDS
+// segment and evaluates them itself, so the work of a wavefront is the
+// largest count of such entries on one lane, whatever the spread of the
+// points of its pixels.  NPT is the largest point count of the wavefront;
+// points at or beyond a lane's count have r = 0 and an anchor no entry's bin
+// reaches, so they neither select entries nor change lambda, and a lane's
+// sums do not depend on the other pixels of its wavefront.  BUF: the entries
+// are read through a buffer resource over the whole entry array (etot
+// entries; 0x00020000 is the resource word of a raw 32-bit buffer on this
+// architecture).
 template <int LPP, int NPT, bool BUF>
 __device__ __forceinline__ void accumulate_n(const DevModel& m, const float4* cr, const PixPoints& q, float bb,
                                              float invG, const uint32_t* __restrict__ ent, uint32_t etot,
