@@ -284,9 +284,17 @@ __global__ __launch_bounds__(64 * CP_WAVES) void k_compact_copy(const uint16_t* 
     const uint32_t n = off[p + 1] - off[p];
     bool overflow = false;
     if (stage && n <= (uint32_t)CP_STAGE) {
+        // the slot's entries load with the offsets (the slot holds CP_STAGE
+        // entries whatever the count)
         const uint32_t* slot = stage + p * CP_STAGE;
-        for (uint32_t k = lane; k < n; k += 64) {
-            if (base + k < cap) ent[base + k] = slot[k];
+        static_assert(CP_STAGE == 128, "two entries of the slot per lane");
+        const uint32_t s0 = slot[lane], s1 = slot[lane + 64];
+        if ((uint32_t)lane < n) {
+            if (base + lane < cap) ent[base + lane] = s0;
+            else overflow = true;
+        }
+        if ((uint32_t)lane + 64 < n) {
+            if (base + lane + 64 < cap) ent[base + lane + 64] = s1;
             else overflow = true;
         }
     } else {
