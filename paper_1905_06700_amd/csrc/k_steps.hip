@@ -320,10 +320,10 @@ __global__ __launch_bounds__(256, 7) void k_depth_step(DevModel m, DevParams p, 
     __shared__ uint32_t stage[step_stage_words<LPP>()];
     __shared__ float4 crl[TLDS ? STEP_CR_LDS : 1];
     __shared__ double stl[STEP_STAB_LDS];
+    const long long P = sh.P;
+    const Lane L = lane_setup<LPP>(m, s, P, off, gain, true);    // its loads stay in flight across the staging
     const float4* cr = stage_segments<TLDS>(m, crl, stl);
     uint32_t* seg = stage_segment<LPP>(stage);
-    const long long P = sh.P;
-    const Lane L = lane_setup<LPP>(m, s, P, off, gain, true);
     float sz, shh[KM], shp[KM];
     accumulate<LPP>(m, cr, L.q, L.live ? s.b[L.pix] : 1.f, L.live ? L.G : 1.f, ent, L.etot, L.e0, L.e1, L.sub, seg, sz, shh, shp);
     reduce_lanes<LPP>(sz, shh, shp);
@@ -386,10 +386,10 @@ __global__ __launch_bounds__(256, 7) void k_intensity_step(DevModel m, DevParams
     __shared__ uint32_t stage[step_stage_words<LPP>()];
     __shared__ float4 crl[TLDS ? STEP_CR_LDS : 1];
     __shared__ double stl[STEP_STAB_LDS];
+    const long long P = sh.P;
+    Lane L = lane_setup<LPP>(m, s, P, off, gain, true);          // its loads stay in flight across the staging
     const float4* cr = stage_segments<TLDS>(m, crl, stl);
     uint32_t* seg = stage_segment<LPP>(stage);
-    const long long P = sh.P;
-    Lane L = lane_setup<LPP>(m, s, P, off, gain, true);
     if (MERGE && L.member) merge_lane(s, P, p, L.pix, L.sub, L.q);
     float sz, shh[KM], shp[KM];
     accumulate<LPP>(m, cr, L.q, L.live ? s.b[L.pix] : 1.f, L.live ? L.G : 1.f, ent, L.etot, L.e0, L.e1, L.sub, seg, sz, shh, shp);
@@ -413,10 +413,10 @@ __global__ __launch_bounds__(256) void k_bg_step(DevModel m, DevParams p, Shape 
     __shared__ uint32_t stage[step_stage_words<LPP>()];
     __shared__ float4 crl[TLDS ? STEP_CR_LDS : 1];
     __shared__ double stl[STEP_STAB_LDS];
+    const long long P = sh.P;
+    const Lane L = lane_setup<LPP>(m, s, P, off, gain, false);   // its loads stay in flight across the staging
     const float4* cr = stage_segments<TLDS, false>(m, crl, stl);
     uint32_t* seg = stage_segment<LPP>(stage);
-    const long long P = sh.P;
-    const Lane L = lane_setup<LPP>(m, s, P, off, gain, false);
     const float braw = L.pix < P ? s.b[L.pix] : 1.f;
     const float bb = L.live ? braw : 1.f;
     float sz, shh[KM], shp[KM];
@@ -440,10 +440,10 @@ __global__ __launch_bounds__(256) void k_gradients(DevModel m, Shape sh, const u
     __shared__ uint32_t stage[step_stage_words<LPP>()];
     __shared__ float4 crl[TLDS ? STEP_CR_LDS : 1];
     __shared__ double stl[STEP_STAB_LDS];
+    const long long P = sh.P;
+    const Lane L = lane_setup<LPP>(m, s, P, off, gain, false);   // its loads stay in flight across the staging
     const float4* cr = stage_segments<TLDS>(m, crl, stl);
     uint32_t* seg = stage_segment<LPP>(stage);
-    const long long P = sh.P;
-    const Lane L = lane_setup<LPP>(m, s, P, off, gain, false);
     float sz, shh[KM], shp[KM];
     accumulate<LPP>(m, cr, L.q, L.live ? s.b[L.pix] : 1.f, L.live ? L.G : 1.f, ent, L.etot, L.e0, L.e1, L.sub, seg, sz, shh, shp);
     reduce_lanes<LPP>(sz, shh, shp);
