@@ -249,9 +249,14 @@ __global__ __launch_bounds__(BFT * BFT) void k_bfilter_tile(const float* __restr
     const int i0 = (tr / tiles_x) * BFT, j0 = (tr % tiles_x) * BFT;
     const long long fbase = (long long)fr * sh.rows * sh.cols;
     for (int k = threadIdx.x; k < 2 * rb + 1; k += BFT * BFT) wl[k] = w[k];
-    for (int x = threadIdx.x; x < S * S; x += BFT * BFT) {
-        const int ii = wrap_index(i0 - rb + x / S, sh.rows), jj = wrap_index(j0 - rb + x % S, sh.cols);
-        reg[x] = src[fbase + (long long)ii * sh.cols + jj];
+    // the region by rows and columns of the thread's place in the tile (one
+    // wrap per row and per column, no division by S)
+    {
+        const int ry = threadIdx.x / BFT, rx = threadIdx.x % BFT;
+        for (int r = ry; r < S; r += BFT) {
+            const long long row = fbase + (long long)wrap_index(i0 - rb + r, sh.rows) * sh.cols;
+            for (int c = rx; c < S; c += BFT) reg[r * S + c] = src[row + wrap_index(j0 - rb + c, sh.cols)];
+        }
     }
     __syncthreads();
     for (int x = threadIdx.x; x < S * BFT; x += BFT * BFT) {
